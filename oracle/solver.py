@@ -1,0 +1,124 @@
+"""Jacobi-preconditioned CG and Gauss-Newton with Armijo search (oracle).
+
+Test infrastructure only (see ``oracle/__init__.py``).
+
+The paper minimises eq. (1) with L-BFGS (Sec. 2) and states that any
+numerical optimisation scheme can be used.  The non-parametric instance here
+uses Gauss-Newton: each iteration solves H delta = -g approximately by
+Jacobi-preconditioned conjugate gradients started at 0, then takes the first
+step t in {1, 1/2, ..., 2^-ls_max} that meets the Armijo condition
+J(u + t delta) <= J(u) + c1 t g.delta.
+
+``fixed=True`` (parity mode) runs exactly ``gn_max`` Gauss-Newton and
+``cg_max`` CG iterations with no convergence exits; only the exact-zero and
+breakdown guards below stop early, and they are the same on the HIP path.
+"""
+
+from dataclasses import dataclass, field
+
+import numpy as np
+
+from .objective import objective, objective_value, hessvec, jacobi_diag
+
+
+def pcg(apply_H, diag, b, cg_max, rtol=0.1, fixed=False):
+    """Solve H x = b from x = 0 with the Jacobi preconditioner ``diag``.
+
+    Returns (x, iterations, status); status is "ok" or "breakdown"
+    (p.Hp <= 0, the last iterate is kept).  Stops early when r.z becomes
+    exactly 0, and, unless ``fixed``, when ||r|| <= rtol ||r_0||.
+    """
+    x = np.zeros_like(b)
+    r = b.copy()
+    z = r / diag
+    p = z.copy()
+    rz = float(np.sum(r * z))
+    r0 = float(np.sqrt(np.sum(r * r)))
+    iters = 0
+    if rz == 0.0:
+        return x, iters, "ok"
+    for _ in range(cg_max):
+        q = apply_H(p)
+        pq = float(np.sum(p * q))
+        if not pq > 0.0:
+            return x, iters, "breakdown"
+        a = rz / pq
+        x = x + a * p
+        r = r - a * q
+        iters += 1
+        z = r / diag
+        rz_new = float(np.sum(r * z))
+        if not fixed and float(np.sqrt(np.sum(r * r))) <= rtol * r0:
+            break
+        if rz_new == 0.0:
+            break
+        beta = rz_new / rz
+        p = z + beta * p
+        rz = rz_new
+    return x, iters, "ok"
+
+
+@dataclass
+class GNResult:
+    u: np.ndarray
+    J0: float
+    J: float
+    iterations: int
+    cg_iterations: list = field(default_factory=list)
+    steps: list = field(default_factory=list)      # accepted t per iteration
+    J_history: list = field(default_factory=list)
+    status: str = "ok"
+
+
+def gauss_newton(frames, u0, K, h, params, gn_max=10, cg_max=20,
+                 cg_rtol=0.1, ls_max=10, c1=1e-4, fixed=False,
+                 tol_J=1e-3, tol_u=1e-2):
+    """Minimise J over the frames in K, starting from u0 (all n frames).
+
+    Frames outside K keep their displacement.  Unless ``fixed``, stop once
+    an accepted step lowers J by at most tol_J * |J| and moves no
+    displacement by more than tol_u (finest pixels).
+    """
+    K = list(K)
+    u = np.array(u0, dtype=np.float64, copy=True)
+    res = GNResult(u=u, J0=float("nan"), J=float("nan"), iterations=0)
+    for it in range(gn_max):
+        o = objective(frames, u, K, h, params, with_grad=True)
+        J, g, dW = o["J"], o["g"], o["dW"]
+        if it == 0:
+            res.J0 = J
+            res.J = J
+        diag = jacobi_diag(dW, h, params)
+        delta, cgi, st = pcg(lambda v: hessvec(dW, v, h, params), diag, -g,
+                             cg_max, cg_rtol, fixed)
+        res.cg_iterations.append(cgi)
+        if st != "ok":
+            res.status = st
+        slope = float(np.sum(g * delta))
+        t = 1.0
+        accepted = False
+        Jt = J
+        for _ in range(ls_max + 1):
+            ut = u.copy()
+            ut[K] = u[K] + t * delta
+            Jt = objective_value(frames, ut, K, h, params)[0]
+            if Jt <= J + c1 * t * slope:
+                accepted = True
+                break
+            t *= 0.5
+        if not accepted:
+            res.status = "linesearch"
+            break
+        u[K] = u[K] + t * delta
+        res.iterations += 1
+        res.steps.append(t)
+        res.J_history.append(Jt)
+        res.J = Jt
+        if st == "breakdown":
+            break
+        if not fixed:
+            if (J - Jt) <= tol_J * abs(J) and \
+                    t * float(np.max(np.abs(delta))) <= tol_u:
+                break
+    res.u = u
+    return res
