@@ -1,0 +1,195 @@
+#!/usr/bin/env python
+"""Throughput benchmark of the STML registration path on one MI355X.
+
+One step = one whole spatio-temporal multilevel solve of a 64-frame
+256x256 synthetic OCT-like sequence (4 spatial x 3 temporal levels,
+curvature regulariser, fixed 5 Gauss-Newton x 10 CG iterations per
+registration): restriction, prolongation, the temporal predictors and every
+Gauss-Newton / PCG / Armijo step, all in libstml.so.  The frames are in HBM
+before the timed region starts.
+
+value = voxel-frames pushed through the warp+distance+gradient kernel and
+the Hessian-product kernel per second, over the whole step: every
+evaluation and every Hessian product over a subset K on a level with N
+voxels counts |K| N voxel-frames.  The Armijo trial sweeps, CG vector
+updates, predictors and host synchronisation are inside the timed region
+but not counted as units.
+
+Prints one JSON line.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+# algorithmic bytes per voxel-frame of one Hessian-product launch:
+# read v (D floats) and dW/du (D floats), write Hv (D floats)
+HV_BYTES_PER_VF = {2: 24, 3: 36}
+
+WORKLOAD = dict(n=64, extent=(256, 256), n_spatial=4, n_temporal=3,
+                reg="curvature", alpha=0.1, lam=1e-2, beta=1e-5, gn_max=5,
+                cg_max=10, parity_mode=True)
+
+
+def _units(logs, extents):
+    total = 0.0
+    for lg in logs:
+        N = float(np.prod(extents[lg["level"]]))
+        for cg in lg["cg"]:
+            total += lg["nK"] * N * (1 + cg)
+    return total
+
+
+def _traffic_record(dim):
+    """HBM bytes per Hessian-product launch from the committed rocprofv3
+    counter summary, if it was taken on the current kernel source."""
+    path = os.path.join(ROOT, "profiles", "hessvec_traffic.json")
+    src = os.path.join(ROOT, "paper_2001_06613_amd", "csrc", "kernels.hip")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    with open(src, "rb") as f:
+        sha = hashlib.sha256(f.read()).hexdigest()
+    if rec.get("kernels_hip_sha256") != sha:
+        return None
+    return rec.get("hbm_bytes_per_launch")
+
+
+def cpu_baseline(frames, budget_s=30.0):
+    """Oracle timed on the host: one Gauss-Newton iteration (evaluation,
+    10 CG Hessian products, Armijo search) over all 64 frames at the
+    finest level, from zero displacement."""
+    import oracle
+
+    w = WORKLOAD
+    par = oracle.ModelParams(alpha=w["alpha"], lam=w["lam"], reg=w["reg"])
+    n = frames.shape[0]
+    u0 = np.zeros((n, 2) + frames.shape[1:])
+    t0 = time.perf_counter()
+    res = oracle.gauss_newton(frames, u0, list(range(n)), 1.0, par, gn_max=1,
+                              cg_max=w["cg_max"], fixed=True)
+    dt = time.perf_counter() - t0
+    units = n * float(np.prod(frames.shape[1:])) * (1 + res.cg_iterations[0])
+    return {"value": units / dt / 1e9, "unit": "Gvoxel-frames/s", "cores": 1,
+            "kind": "oracle",
+            "sample": "one Gauss-Newton iteration (1 evaluation + 10 Hessian "
+                      "products + CG + Armijo) over 64 frames x 256x256 at "
+                      f"the finest level, NumPy float64, {dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: --gpus {args.gpus} is not supported: this build "
+              "runs the registration path on one GPU only", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2001_06613_amd import synth
+    from paper_2001_06613_amd.binding import STML, default_opts
+
+    torch.cuda.set_device(0)
+    w = WORKLOAD
+    frames, _ = synth.config_large(1)
+    opts = default_opts(n_spatial=w["n_spatial"], n_temporal=w["n_temporal"],
+                        reg=w["reg"], alpha=w["alpha"], lam=w["lam"],
+                        beta=w["beta"], gn_max=w["gn_max"],
+                        cg_max=w["cg_max"], parity_mode=w["parity_mode"])
+    st = STML(w["n"], w["extent"], opts=opts)
+    fr = torch.from_numpy(frames).cuda()
+    extents = [st.level_extent(l) for l in range(w["n_spatial"])]
+
+    def step():
+        st.set_sequence(fr)
+        st.run()
+
+    for i in range(args.warmup):
+        step()
+        print(f"warmup {i + 1}/{args.warmup} done", file=sys.stderr,
+              flush=True)
+    units_per_step = _units(st.logs(), extents)
+    st.timing(1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step()
+        print(f"step {i + 1}/{args.steps} done", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    st.timing(0)
+    dt = t1 - t0
+    ms_per_step = dt / args.steps * 1e3
+    value = units_per_step * args.steps / dt / 1e9
+
+    hv = st.timing_get("hessvec")
+    dim = len(w["extent"])
+    bytes_total = hv["voxel_frames"] * HV_BYTES_PER_VF[dim]
+    avg_ms = hv["ms"] / max(hv["launches"], 1)
+    achieved = bytes_total / (hv["ms"] * 1e-3) / 1e9 if hv["ms"] > 0 else 0.0
+    fin = st.timing_get("hessvec", w["n_spatial"] - 1)
+    fin_gbs = fin["voxel_frames"] * HV_BYTES_PER_VF[dim] / \
+        (fin["ms"] * 1e-3) / 1e9 if fin["ms"] > 0 else 0.0
+    traffic = _traffic_record(dim)
+    kernels = {}
+    for k in ("eval", "hessvec", "cg_update", "cg_pupdate", "trial",
+              "cg_init", "accept", "predict", "restrict"):
+        t = st.timing_get(k)
+        kernels[k] = {"ms_per_step": round(t["ms"] / args.steps, 4),
+                      "launches_per_step": t["launches"] // args.steps}
+
+    out = {
+        "metric": "warp+dist+grad+Hv Gvoxel-frames/s",
+        "value": round(value, 3),
+        "unit": "Gvoxel-frames/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "STML solve, 64 frames x 256x256 OCT-like phantom, "
+                        "4 spatial x 3 temporal levels (|K| 17/33/64), "
+                        "curvature alpha 0.1, fixed 5 GN x 10 CG",
+            "frames": w["n"], "extent": list(w["extent"]),
+            "units_per_step": units_per_step,
+        },
+        "roofline": {
+            "kernel": "pcg_hv_kernel<2> (all levels)",
+            "bound": "hbm",
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+            "avg_launch_ms": round(avg_ms, 5),
+            "algorithmic_bytes_per_launch": bytes_total / max(hv["launches"], 1),
+            "finest_level_GBs": round(fin_gbs, 1),
+        },
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(frames)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,224 @@
+/*
+ * stml.h -- C-ABI of the MI355X (gfx950) spatio-temporal multilevel (STML)
+ * registration library, libstml.so.
+ *
+ * Method: Aggrawal & Modersitzki, "Accelerating the Registration of Image
+ * Sequences by Spatio-temporal Multilevel Strategies" (arXiv 2001.06613).
+ *   Sec. 2, eq. (1)  groupwise objective over a frame subset K,
+ *                    J = sum_ij D(R_i o y_i, R_j o y_j) + S(Y) + P(Y),
+ *                    with the penalty P on the mean transformation.
+ *   Sec. 3, Fig. 1   temporal binary tree K_0 ... K_T.
+ *   Sec. 3           coarse-level linear (midpoint) predictor, correction by
+ *                    registering K_{q+1} from the prediction.
+ *   Sec. 3, eq. (2)  least-squares temporal predictor on finer levels,
+ *                    solved by the Thomas algorithm.
+ *   Sec. 3, eq. (3)  optional stopping rule on the change of D.
+ *   Sec. 4           spatial multilevel data, smoothed in space only.
+ *
+ * Instance computed here (the paper leaves the inner model open): every
+ * frame k has a displacement u_k on a cell-centred grid, y_k = x + u_k;
+ * D is the groupwise sum of squared differences normalised by 1/(2|K|)
+ * (= h^d sum_k ||W_k - mean W||^2 with W_k the frame warped by bi/trilinear
+ * interpolation, edge clamp); S = (alpha/2) h^d sum ||B u||^2 with B the
+ * forward differences (diffusion) or the Neumann Laplacian (curvature);
+ * P = lambda h^d ||mean_k u_k||^2.  The minimiser is Gauss-Newton with a
+ * matrix-free Hessian, Jacobi-preconditioned CG, and an Armijo search.
+ *
+ * Conventions for every entry point
+ *   - Pointers named *_dev are device pointers (HIP global memory on the
+ *     context's device); all others are host pointers.
+ *   - Images are float32, [n][extent...] with the last axis fastest
+ *     (extent[0] slowest).  Displacements are float32 [n][dim][extent...]:
+ *     component c is the displacement along axis c, in finest-level pixels.
+ *   - The caller owns every buffer.  The context never allocates device
+ *     memory: all device state lives in the caller's workspace, sized by
+ *     stml_workspace_bytes().  Inputs are copied; outputs are written into
+ *     caller buffers.
+ *   - All work is enqueued on the stream given to stml_create(); every
+ *     entry point returns with that stream synchronised.
+ *   - Return value: 0 success, < 0 error (nothing further is valid for that
+ *     call), > 0 warning (the call completed).  stml_last_error() gives a
+ *     message.  One context must not be used by two threads at once.
+ */
+#ifndef STML_H
+#define STML_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define STML_OK            0
+#define STML_EINVAL       -1  /* bad argument, shape, or non-finite input   */
+#define STML_ENOMEM       -2  /* workspace too small                        */
+#define STML_EDEVICE      -3  /* a HIP call failed                          */
+#define STML_ESTATE       -4  /* call out of order (e.g. no sequence yet)   */
+#define STML_EBREAKDOWN   -5  /* CG met p.Hp <= 0 (operator not SPD)        */
+#define STML_WLINESEARCH   2  /* Armijo search found no step; u unchanged   */
+
+#define STML_REG_DIFFUSION 0
+#define STML_REG_CURVATURE 1
+
+#define STML_MAX_FRAMES  256  /* frames per sequence supported by kernels   */
+
+typedef struct stml_ctx stml_ctx;
+
+/* Parameters.  stml_default_opts() fills the defaults listed here. */
+typedef struct stml_opts {
+  int dim;            /* 2 or 3                                     (2)      */
+  int n_spatial;      /* number of spatial levels L >= 1            (2)      */
+  int n_temporal;     /* number of temporal levels T + 1 >= 1       (2)      */
+  int regulariser;    /* STML_REG_DIFFUSION or STML_REG_CURVATURE   (0)      */
+  double alpha;       /* regulariser weight                         (1e-2)   */
+  double lambda;      /* penalty weight of Sec. 2                   (1e-2)   */
+  double beta;        /* eq. (2) weight                             (1e-5)   */
+  double eps_stop;    /* eq. (3) relative tolerance; 0 = off        (0)      */
+  int gn_max;         /* Gauss-Newton iterations per registration   (10)     */
+  int cg_max;         /* CG iterations per Gauss-Newton step        (20)     */
+  double cg_rtol;     /* CG stops at ||r|| <= cg_rtol ||r_0||       (0.1)    */
+  int ls_max;         /* Armijo tries t = 1, 1/2, ..., 2^-ls_max    (10)     */
+  double c1;          /* Armijo constant                            (1e-4)   */
+  double tol_J;       /* GN stops when the relative decrease of J   (1e-3)   */
+  double tol_u;       /*   and max |t delta| (pixels) are below both (1e-2)  */
+  int predictor;      /* 0 = the paper's interpolation predictors   (0)      */
+  int parity_mode;    /* 1: exactly gn_max GN and cg_max CG iterations,
+                         no convergence exits, eq. (3) off          (0)      */
+} stml_opts;
+
+/* Statistics of one registration call (GIR on one subset). */
+typedef struct stml_gir_log {
+  int level, q, n_frames;
+  int gn_iterations;
+  int status;             /* STML_OK, STML_WLINESEARCH or STML_EBREAKDOWN   */
+  double J0, J;           /* objective before the first and after the last
+                             accepted step                                   */
+  double D, S, P;         /* parts of J at the last evaluation              */
+  int cg_iterations[64];  /* per GN iteration (first 64)                    */
+  double step[64];        /* accepted Armijo step t per GN iteration        */
+} stml_gir_log;
+
+void stml_default_opts(stml_opts* opts);
+
+/* Bytes of device workspace a context for n frames of the given finest
+ * extent (dim entries, slowest first) needs.  0 if the arguments are
+ * invalid. */
+size_t stml_workspace_bytes(const stml_opts* opts, int n, const int* extent);
+
+/* Create a context.  workspace_dev must stay valid, untouched by the caller,
+ * until stml_destroy().  hip_stream is a hipStream_t (NULL = default).
+ * Errors: EINVAL (opts or shape), ENOMEM (ws_bytes too small), EDEVICE. */
+int stml_create(const stml_opts* opts, int n, const int* extent,
+                void* hip_stream, void* workspace_dev, size_t ws_bytes,
+                stml_ctx** out);
+
+void stml_destroy(stml_ctx* ctx);
+
+const char* stml_last_error(const stml_ctx* ctx);
+
+/* Load the sequence R_1..R_n (Sec. 2) and build the spatial pyramid by
+ * restriction in space only (Sec. 4): each coarser cell is the mean of the
+ * 2^dim finer cells that exist (extents halve rounding up, as in Table 1).
+ * frames_dev: [n][extent...] float32.  Resets every level's displacements
+ * to 0.  Errors: EINVAL if any value is not finite. */
+int stml_set_sequence(stml_ctx* ctx, const float* frames_dev);
+
+/* Copy the pyramid image of `level` (0 = coarsest) into out_dev,
+ * [n][extent_level...]. */
+int stml_get_level_frames(const stml_ctx* ctx, int level, float* out_dev);
+
+/* Extent of `level` (dim ints into out_extent). */
+int stml_level_extent(const stml_ctx* ctx, int level, int* out_extent);
+
+/* Frames of K_q (Sec. 3, Fig. 1), 0-based, ascending; returns |K_q| (or an
+ * error) and writes at most `cap` indices to out_frames. */
+int stml_temporal_set(const stml_ctx* ctx, int q, int* out_frames, int cap);
+
+/* Predictor step (Sec. 3).  Sets the start guess z(level, q_next, all) of
+ * every frame and makes it the current estimate y:
+ *   q_next = 0, level = 0 : identity (u = 0);
+ *   q_next = 0, level > 0 : prolongation of level-1's estimate;
+ *   q_next > 0, level = 0 : linear interpolation from K_{q_next-1};
+ *   q_next > 0, level > 0 : eq. (2), eta = current estimate on K_{q_next-1},
+ *                           omega = the previous start guess, Thomas solve.
+ * Errors: ESTATE (no sequence, or level-1 not registered), EINVAL. */
+int stml_predict(stml_ctx* ctx, int level, int q_next);
+
+/* Groupwise registration GIR(level, K_q) of eq. (1) from the current
+ * estimate; frames outside K_q are unchanged.  Returns OK, or
+ * STML_WLINESEARCH / STML_EBREAKDOWN (last good iterate kept). */
+int stml_register_level(stml_ctx* ctx, int level, int q);
+
+/* Correction step of Sec. 3: GIR(level, K_{q_next}) started from the
+ * prediction; identical to stml_register_level(ctx, level, q_next). */
+int stml_correct(stml_ctx* ctx, int level, int q_next);
+
+/* Whole schedule of Sec. 3: levels coarse to fine, predictor-corrector over
+ * K_0..K_T, eq. (3) when eps_stop > 0 and not in parity mode. */
+int stml_run(stml_ctx* ctx);
+
+/* Current estimate (y) of `level` into u_dev [n][dim][extent_level...]. */
+int stml_get_displacements(const stml_ctx* ctx, int level, float* u_dev);
+/* Overwrite the current estimate of `level` (resume or test). */
+int stml_set_displacements(stml_ctx* ctx, int level, const float* u_dev);
+/* Last start guess z of `level` (the omega reference of eq. (2)). */
+int stml_get_prediction(const stml_ctx* ctx, int level, float* z_dev);
+int stml_set_prediction(stml_ctx* ctx, int level, const float* z_dev);
+
+/* Registration statistics: number of logged GIR calls since
+ * stml_set_sequence, and entry i. */
+int stml_log_count(const stml_ctx* ctx);
+int stml_get_log(const stml_ctx* ctx, int i, stml_gir_log* out);
+
+/* --- kernel-level entry points (same conventions) ------------------------
+ * frames: host array of nk frame indices (distinct, ascending), the subset K.
+ * u_dev : [n][dim][extent_level] displacement of all frames.
+ * Compact outputs are [nk][dim][extent_level], in the order of frames.  */
+
+/* Objective (eq. (1) instance) at u: out_JDSP = {J, D, S, P}; gradient
+ * into grad_dev and dW/du into dW_dev (either may be NULL). */
+int stml_eval(stml_ctx* ctx, int level, const int* frames, int nk,
+              const float* u_dev, double* out_JDSP, float* grad_dev,
+              float* dW_dev);
+
+/* Gauss-Newton Hessian at u applied to v_dev (compact) into hv_dev
+ * (compact); out_vHv (may be NULL) receives v.Hv. */
+int stml_hessvec(stml_ctx* ctx, int level, const int* frames, int nk,
+                 const float* u_dev, const float* v_dev, float* hv_dev,
+                 double* out_vHv);
+
+/* One Gauss-Newton direction at u: Jacobi-PCG on H delta = -g with the
+ * context's cg_max / cg_rtol / parity_mode; delta into delta_dev
+ * (compact), CG iterations into *out_cg.  Returns EBREAKDOWN on p.Hp <= 0
+ * (delta = last iterate). */
+int stml_gn_direction(stml_ctx* ctx, int level, const int* frames, int nk,
+                      const float* u_dev, float* delta_dev, int* out_cg);
+
+/* --- kernel timing (measurement only) -----------------------------------
+ * With timing on, each launch of the kernel classes below on the context's
+ * stream is bracketed by two HIP events; durations, launch counts and the
+ * voxel-frames each launch covers (|K| x voxels of the level, or n x voxels
+ * for whole-sequence kernels) accumulate per (class, level) until the next
+ * stml_timing(ctx, 1).  Timing adds two event records per launch. */
+#define STML_K_EVAL        0  /* warp + distance + gradient                 */
+#define STML_K_HESSVEC     1  /* Gauss-Newton Hessian product (CG and test)  */
+#define STML_K_CG_UPDATE   2  /* x, r, z update and r.z                      */
+#define STML_K_CG_PUPDATE  3  /* p = z + beta p                              */
+#define STML_K_TRIAL       4  /* objective at the Armijo trial steps         */
+#define STML_K_CG_INIT     5  /* CG start                                    */
+#define STML_K_ACCEPT      6  /* u += t delta                                */
+#define STML_K_PREDICT     7  /* prolongation and temporal predictors        */
+#define STML_K_RESTRICT    8  /* spatial restriction                         */
+#define STML_K_COUNT       9
+
+/* on = 1: clear the accumulators and start timing; on = 0: stop. */
+int stml_timing(stml_ctx* ctx, int on);
+/* Totals of one kernel class at one level (level = -1: all levels). */
+int stml_timing_get(stml_ctx* ctx, int kernel, int level, double* total_ms,
+                    long long* launches, double* voxel_frames);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* STML_H */

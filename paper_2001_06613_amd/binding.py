@@ -1,0 +1,365 @@
+"""ctypes binding of libstml.so (C-ABI declared in include/stml.h).
+
+Argument marshalling only: every step of the registration path runs in the
+HIP library.  PyTorch supplies device memory (the workspace and the caller's
+buffers) and the HIP stream.  If the library is missing or cannot load, every
+call raises; there is no fallback.
+"""
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libstml.so")
+
+STML_OK = 0
+STML_EINVAL = -1
+STML_ENOMEM = -2
+STML_EDEVICE = -3
+STML_ESTATE = -4
+STML_EBREAKDOWN = -5
+STML_WLINESEARCH = 2
+MAX_FRAMES = 256
+
+REG = {"diffusion": 0, "curvature": 1}
+
+
+class stml_opts(ctypes.Structure):
+    _fields_ = [
+        ("dim", ctypes.c_int),
+        ("n_spatial", ctypes.c_int),
+        ("n_temporal", ctypes.c_int),
+        ("regulariser", ctypes.c_int),
+        ("alpha", ctypes.c_double),
+        ("lambda_", ctypes.c_double),
+        ("beta", ctypes.c_double),
+        ("eps_stop", ctypes.c_double),
+        ("gn_max", ctypes.c_int),
+        ("cg_max", ctypes.c_int),
+        ("cg_rtol", ctypes.c_double),
+        ("ls_max", ctypes.c_int),
+        ("c1", ctypes.c_double),
+        ("tol_J", ctypes.c_double),
+        ("tol_u", ctypes.c_double),
+        ("predictor", ctypes.c_int),
+        ("parity_mode", ctypes.c_int),
+    ]
+
+
+class stml_gir_log(ctypes.Structure):
+    _fields_ = [
+        ("level", ctypes.c_int),
+        ("q", ctypes.c_int),
+        ("n_frames", ctypes.c_int),
+        ("gn_iterations", ctypes.c_int),
+        ("status", ctypes.c_int),
+        ("J0", ctypes.c_double),
+        ("J", ctypes.c_double),
+        ("D", ctypes.c_double),
+        ("S", ctypes.c_double),
+        ("P", ctypes.c_double),
+        ("cg_iterations", ctypes.c_int * 64),
+        ("step", ctypes.c_double * 64),
+    ]
+
+
+# every symbol include/stml.h declares, with (restype, argtypes)
+_P = ctypes.c_void_p
+_I = ctypes.c_int
+_IP = ctypes.POINTER(ctypes.c_int)
+_DP = ctypes.POINTER(ctypes.c_double)
+SIGNATURES = {
+    "stml_default_opts": (None, [ctypes.POINTER(stml_opts)]),
+    "stml_workspace_bytes": (ctypes.c_size_t,
+                             [ctypes.POINTER(stml_opts), _I, _IP]),
+    "stml_create": (_I, [ctypes.POINTER(stml_opts), _I, _IP, _P, _P,
+                         ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "stml_destroy": (None, [_P]),
+    "stml_last_error": (ctypes.c_char_p, [_P]),
+    "stml_set_sequence": (_I, [_P, _P]),
+    "stml_get_level_frames": (_I, [_P, _I, _P]),
+    "stml_level_extent": (_I, [_P, _I, _IP]),
+    "stml_temporal_set": (_I, [_P, _I, _IP, _I]),
+    "stml_predict": (_I, [_P, _I, _I]),
+    "stml_register_level": (_I, [_P, _I, _I]),
+    "stml_correct": (_I, [_P, _I, _I]),
+    "stml_run": (_I, [_P]),
+    "stml_get_displacements": (_I, [_P, _I, _P]),
+    "stml_set_displacements": (_I, [_P, _I, _P]),
+    "stml_get_prediction": (_I, [_P, _I, _P]),
+    "stml_set_prediction": (_I, [_P, _I, _P]),
+    "stml_log_count": (_I, [_P]),
+    "stml_get_log": (_I, [_P, _I, ctypes.POINTER(stml_gir_log)]),
+    "stml_eval": (_I, [_P, _I, _IP, _I, _P, _DP, _P, _P]),
+    "stml_hessvec": (_I, [_P, _I, _IP, _I, _P, _P, _P, _DP]),
+    "stml_gn_direction": (_I, [_P, _I, _IP, _I, _P, _P, _IP]),
+    "stml_timing": (_I, [_P, _I]),
+    "stml_timing_get": (_I, [_P, _I, _I, _DP, ctypes.POINTER(ctypes.c_longlong),
+                             _DP]),
+}
+
+KERNELS = {"eval": 0, "hessvec": 1, "cg_update": 2, "cg_pupdate": 3,
+           "trial": 4, "cg_init": 5, "accept": 6, "predict": 7,
+           "restrict": 8}
+
+_lib = None
+
+
+class STMLError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"stml error {code}: {msg}")
+        self.code = code
+
+
+def load(path=LIB_PATH):
+    """Load libstml.so and declare every exported entry point."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise STMLError(STML_EDEVICE,
+                        f"{path} is missing: build it with "
+                        "`python -c 'import __graft_entry__ as g; g.build()'`")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def default_opts(**kw):
+    lib = load()
+    o = stml_opts()
+    lib.stml_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if k == "lam" or k == "lambda":
+            k = "lambda_"
+        if k == "reg":
+            k, v = "regulariser", REG[v]
+        if k == "parity_mode":
+            v = int(bool(v))
+        if not hasattr(o, k):
+            raise KeyError(k)
+        setattr(o, k, v)
+    return o
+
+
+def _int_array(vals):
+    arr = (ctypes.c_int * len(vals))(*[int(v) for v in vals])
+    return arr
+
+
+def _ptr(t):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class STML:
+    """One registration context on the current torch device and stream.
+
+    Mirrors the C-ABI one to one: set_sequence, predict, register_level,
+    correct, run, get/set_displacements, eval, hessvec, gn_direction.
+    """
+
+    def __init__(self, n, extent, opts=None, stream=None, **kw):
+        import torch
+
+        self.torch = torch
+        self.lib = load()
+        self.opts = opts if opts is not None else default_opts(**kw)
+        self.n = int(n)
+        self.extent = tuple(int(m) for m in extent)
+        self.dim = len(self.extent)
+        if self.dim != self.opts.dim:
+            raise STMLError(STML_EINVAL, "extent does not match opts.dim")
+        ext = _int_array(self.extent)
+        nbytes = self.lib.stml_workspace_bytes(ctypes.byref(self.opts),
+                                               self.n, ext)
+        if nbytes == 0:
+            raise STMLError(STML_EINVAL, "invalid options or shape")
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8,
+                                     device=self.device)
+        self.stream = stream if stream is not None else \
+            torch.cuda.current_stream(self.device)
+        ctx = ctypes.c_void_p()
+        rc = self.lib.stml_create(ctypes.byref(self.opts), self.n, ext,
+                                  ctypes.c_void_p(self.stream.cuda_stream),
+                                  _ptr(self.workspace), nbytes,
+                                  ctypes.byref(ctx))
+        if rc != STML_OK:
+            raise STMLError(rc, "stml_create failed")
+        self.ctx = ctx
+        self.levels = self.opts.n_spatial
+
+    # -- helpers
+    def _check(self, rc, allow_warn=True):
+        if rc < 0 or (rc > 0 and not allow_warn):
+            msg = self.lib.stml_last_error(self.ctx).decode()
+            raise STMLError(rc, msg)
+        return rc
+
+    def _sync_in(self):
+        # the library works on self.stream; order it after torch's work
+        cur = self.torch.cuda.current_stream(self.device)
+        if cur.cuda_stream != self.stream.cuda_stream:
+            self.stream.wait_stream(cur)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            self.lib.stml_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def level_extent(self, level):
+        out = (ctypes.c_int * self.dim)()
+        self._check(self.lib.stml_level_extent(self.ctx, level, out))
+        return tuple(out)
+
+    def temporal_set(self, q):
+        out = (ctypes.c_int * MAX_FRAMES)()
+        cnt = self._check(self.lib.stml_temporal_set(self.ctx, q, out,
+                                                     MAX_FRAMES))
+        return list(out[:cnt])
+
+    def _field(self, level, frames=None):
+        ext = self.level_extent(level)
+        nf = self.n if frames is None else frames
+        return self.torch.empty((nf, self.dim) + ext, dtype=self.torch.float32,
+                                device=self.device)
+
+    def _dev(self, t, shape=None):
+        t = t.to(self.device, self.torch.float32).contiguous()
+        if shape is not None and tuple(t.shape) != tuple(shape):
+            raise STMLError(STML_EINVAL, f"shape {tuple(t.shape)} != {shape}")
+        return t
+
+    # -- C-ABI entry points
+    def set_sequence(self, frames):
+        f = self._dev(frames, (self.n,) + self.extent)
+        self._sync_in()
+        return self._check(self.lib.stml_set_sequence(self.ctx, _ptr(f)))
+
+    def get_level_frames(self, level):
+        out = self.torch.empty((self.n,) + self.level_extent(level),
+                               dtype=self.torch.float32, device=self.device)
+        self._check(self.lib.stml_get_level_frames(self.ctx, level, _ptr(out)))
+        return out
+
+    def predict(self, level, q_next):
+        return self._check(self.lib.stml_predict(self.ctx, level, q_next))
+
+    def register_level(self, level, q):
+        return self._check(self.lib.stml_register_level(self.ctx, level, q))
+
+    def correct(self, level, q_next):
+        return self._check(self.lib.stml_correct(self.ctx, level, q_next))
+
+    def run(self):
+        return self._check(self.lib.stml_run(self.ctx))
+
+    def get_displacements(self, level=None):
+        level = self.levels - 1 if level is None else level
+        out = self._field(level)
+        self._check(self.lib.stml_get_displacements(self.ctx, level,
+                                                    _ptr(out)))
+        return out
+
+    def set_displacements(self, level, u):
+        u = self._dev(u, (self.n, self.dim) + self.level_extent(level))
+        self._sync_in()
+        return self._check(self.lib.stml_set_displacements(self.ctx, level,
+                                                           _ptr(u)))
+
+    def get_prediction(self, level):
+        out = self._field(level)
+        self._check(self.lib.stml_get_prediction(self.ctx, level, _ptr(out)))
+        return out
+
+    def set_prediction(self, level, z):
+        z = self._dev(z, (self.n, self.dim) + self.level_extent(level))
+        self._sync_in()
+        return self._check(self.lib.stml_set_prediction(self.ctx, level,
+                                                        _ptr(z)))
+
+    def logs(self):
+        out = []
+        for i in range(self.lib.stml_log_count(self.ctx)):
+            lg = stml_gir_log()
+            self._check(self.lib.stml_get_log(self.ctx, i, ctypes.byref(lg)))
+            it = lg.gn_iterations
+            out.append({"level": lg.level, "q": lg.q, "nK": lg.n_frames,
+                        "gn": it, "status": lg.status, "J0": lg.J0,
+                        "J": lg.J, "D": lg.D, "S": lg.S, "P": lg.P,
+                        "cg": list(lg.cg_iterations[:max(it, 0)]),
+                        "steps": list(lg.step[:max(it, 0)])})
+        return out
+
+    def timing(self, on):
+        return self._check(self.lib.stml_timing(self.ctx, int(bool(on))))
+
+    def timing_get(self, kernel, level=-1):
+        ms = ctypes.c_double()
+        n = ctypes.c_longlong()
+        vf = ctypes.c_double()
+        self._check(self.lib.stml_timing_get(self.ctx, KERNELS[kernel], level,
+                                             ctypes.byref(ms), ctypes.byref(n),
+                                             ctypes.byref(vf)))
+        return {"ms": ms.value, "launches": n.value, "voxel_frames": vf.value}
+
+    def eval(self, level, frames, u, want_grad=True):
+        """Objective {J, D, S, P}, gradient and dW/du at u (all frames)."""
+        u = self._dev(u, (self.n, self.dim) + self.level_extent(level))
+        fr = _int_array(frames)
+        out = (ctypes.c_double * 4)()
+        g = self._field(level, len(frames)) if want_grad else None
+        dW = self._field(level, len(frames)) if want_grad else None
+        self._sync_in()
+        self._check(self.lib.stml_eval(
+            self.ctx, level, fr, len(frames), _ptr(u), out,
+            _ptr(g) if g is not None else None,
+            _ptr(dW) if dW is not None else None))
+        return {"J": out[0], "D": out[1], "S": out[2], "P": out[3],
+                "g": g, "dW": dW}
+
+    def hessvec(self, level, frames, u, v):
+        ext = self.level_extent(level)
+        u = self._dev(u, (self.n, self.dim) + ext)
+        v = self._dev(v, (len(frames), self.dim) + ext)
+        hv = self._field(level, len(frames))
+        vhv = ctypes.c_double()
+        self._sync_in()
+        self._check(self.lib.stml_hessvec(self.ctx, level,
+                                          _int_array(frames), len(frames),
+                                          _ptr(u), _ptr(v), _ptr(hv),
+                                          ctypes.byref(vhv)))
+        return hv, vhv.value
+
+    def gn_direction(self, level, frames, u):
+        u = self._dev(u, (self.n, self.dim) + self.level_extent(level))
+        delta = self._field(level, len(frames))
+        cg = ctypes.c_int()
+        self._sync_in()
+        self._check(self.lib.stml_gn_direction(self.ctx, level,
+                                               _int_array(frames), len(frames),
+                                               _ptr(u), _ptr(delta),
+                                               ctypes.byref(cg)))
+        return delta, cg.value
+
+
+def exported_symbols(path=LIB_PATH):
+    """Names of the C-ABI functions that libstml.so exports (no GPU call)."""
+    lib = ctypes.CDLL(path)
+    return [n for n in SIGNATURES if hasattr(lib, n)]
+
+
+def as_numpy(t):
+    return t.detach().cpu().numpy().astype(np.float64)

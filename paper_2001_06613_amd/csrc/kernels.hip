@@ -1,0 +1,858 @@
+// HIP kernels of the STML registration path for gfx950 (CDNA4, wave64).
+//
+// Tile kernels (evaluation, Hessian product, trial steps) give every block
+// one or more 64-voxel tiles; the waves of a block split the frames of the
+// subset K between them, so each voxel's cross-frame means (mean warped
+// image, mean displacement) are combined through LDS without a second HBM
+// pass.  Frames a thread owns stay in registers between the two sweeps.
+// All warp and residual arithmetic is float64 from float32 loads; every
+// reduction is float64 and deterministic.
+#include <math.h>
+
+#include "launch.h"
+#include "reduce.h"
+
+namespace stml {
+
+// ------------------------------------------------------------------ setup
+
+Geom make_geom(int dim, const int* ext, double h) {
+  Geom g;
+  g.m[0] = ext[0];
+  g.m[1] = ext[1];
+  g.m[2] = dim == 3 ? ext[2] : 1;
+  if (dim == 2) {
+    g.s[1] = 1;
+    g.s[0] = g.m[1];
+    g.s[2] = 0;
+    g.N = (long long)g.m[0] * g.m[1];
+  } else {
+    g.s[2] = 1;
+    g.s[1] = g.m[2];
+    g.s[0] = (long long)g.m[1] * g.m[2];
+    g.N = (long long)g.m[0] * g.m[1] * g.m[2];
+  }
+  g.inv_h = 1.0 / h;
+  return g;
+}
+
+Model make_model(int dim, double h, int nK, double alpha, double lambda,
+                 int reg) {
+  Model md;
+  double hd = dim == 3 ? h * h * h : h * h;
+  md.hd = hd;
+  md.data_c = 2.0 * hd;
+  md.mdiag_c = 2.0 * hd * (1.0 - 1.0 / nK);
+  md.alpha_hd = alpha * hd;
+  md.half_alpha_hd = 0.5 * alpha * hd;
+  md.lam_hd = lambda * hd;
+  md.lam_c = 2.0 * lambda * hd / nK;
+  md.pen_diag = 2.0 * lambda * hd / ((double)nK * nK);
+  md.reg_scale = reg == 0 ? 1.0 / (h * h) : 1.0 / (h * h * h * h);
+  md.inv_nK = 1.0 / nK;
+  md.reg = reg;
+  md.nK = nK;
+  return md;
+}
+
+static int round_up(long long v, int m) { return (int)((v + m - 1) / m * m); }
+
+int tile_blocks(const Geom& g) {
+  long long ntiles = (g.N + kWave - 1) / kWave;
+  long long nb = ntiles < kMaxTileBlocks ? ntiles : kMaxTileBlocks;
+  return round_up(nb, kXCD);
+}
+
+// Four waves per block split the frames of K (fewer if |K| < 4).
+int tile_threads(int nK) {
+  int G = nK < 4 ? nK : 4;
+  if (G < 1) G = 1;
+  return G * kWave;
+}
+
+#define STML_DIM_DISPATCH(dim, KERNEL, GRID, BLOCK, STREAM, ...)          \
+  do {                                                                    \
+    if ((dim) == 2)                                                       \
+      KERNEL<2><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);                 \
+    else                                                                  \
+      KERNEL<3><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);                 \
+  } while (0)
+
+static int elem_blocks(size_t count, int per_thread = 4) {
+  size_t nb = (count + 256 * per_thread - 1) / (256 * per_thread);
+  if (nb < 1) nb = 1;
+  if (nb > kMaxElemBlocks) nb = kMaxElemBlocks;
+  return (int)nb;
+}
+
+// --------------------------------------------------------- simple kernels
+
+__global__ void fill_kernel(float* __restrict__ p, size_t count, float v) {
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += stride)
+    p[i] = v;
+}
+
+__global__ void check_finite_kernel(const float* __restrict__ p, size_t count,
+                                    Scal* sc) {
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  int bad = 0;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += stride)
+    bad += !isfinite(p[i]);
+  if (bad) atomicAdd(&sc->bad, bad);
+}
+
+// One spatial restriction step: coarse cell = mean of the existing fine
+// cells 2I + {0,1}^D (extents halve rounding up).
+template <int D>
+__global__ void restrict_kernel(const float* __restrict__ fine,
+                                float* __restrict__ coarse, int n, Geom gf,
+                                Geom gc) {
+  long long total = (long long)n * gc.N;
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+       e < total; e += stride) {
+    int k = (int)(e / gc.N);
+    long long xc = e - (long long)k * gc.N;
+    Pos<D> pc = make_pos<D>(gc, xc);
+    const float* f = fine + (size_t)k * gf.N;
+    double sum = 0.0;
+    int cnt = 0;
+#pragma unroll
+    for (int o = 0; o < (1 << D); ++o) {
+      long long idx = 0;
+      bool ok = true;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        int c = 2 * pc.c[a] + ((o >> (D - 1 - a)) & 1);
+        ok = ok && (c < gf.m[a]);
+        idx += (long long)c * gf.s[a];
+      }
+      if (ok) {
+        sum += (double)f[idx];
+        ++cnt;
+      }
+    }
+    coarse[e] = (float)(sum / cnt);
+  }
+}
+
+// Prolongation: the coarse cell-centred linear interpolant (edge clamp)
+// sampled at fine cell centres; fine index i sits at coarse coordinate
+// i/2 - 1/4.
+template <int D>
+__global__ void prolong_kernel(const float* __restrict__ coarse,
+                               float* __restrict__ fine, int fields, Geom gc,
+                               Geom gf) {
+  long long stride = (long long)gridDim.x * blockDim.x;
+  for (long long x = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+       x < gf.N; x += stride) {
+    Pos<D> pf = make_pos<D>(gf, x);
+    int i0[D], i1[D];
+    double f[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      int M = gc.m[a];
+      double q = 0.5 * (double)pf.c[a] - 0.25;
+      q = fmin(fmax(q, 0.0), (double)(M - 1));
+      if (M >= 2) {
+        int fl = (int)floor(q);
+        i0[a] = fl < M - 2 ? fl : M - 2;
+        f[a] = q - i0[a];
+        i1[a] = i0[a] + 1;
+      } else {
+        i0[a] = i1[a] = 0;
+        f[a] = 0.0;
+      }
+    }
+    for (int fi = 0; fi < fields; ++fi) {
+      const float* c = coarse + (size_t)fi * gc.N;
+      double v = 0.0;
+#pragma unroll
+      for (int o = 0; o < (1 << D); ++o) {
+        double w = 1.0;
+        long long idx = 0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          int bit = (o >> (D - 1 - a)) & 1;
+          w *= bit ? f[a] : 1.0 - f[a];
+          idx += (long long)(bit ? i1[a] : i0[a]) * gc.s[a];
+        }
+        v += w * (double)c[idx];
+      }
+      fine[(size_t)fi * gf.N + x] = (float)v;
+    }
+  }
+}
+
+// ---------------------------------------------------------- tile kernels
+
+// Split of the frames 0..nK-1 between the waves of a block.
+struct Chunk {
+  int j0, j1;
+};
+__device__ __forceinline__ Chunk frame_chunk(int nK) {
+  int G = blockDim.x / kWave;
+  int w = threadIdx.x / kWave;
+  int per = (nK + G - 1) / G;
+  int j0 = w * per;
+  int j1 = j0 + per < nK ? j0 + per : nK;
+  return {j0, j1};
+}
+
+// Objective (D, S, P), gradient and dW/du at u for the frames K.
+// Sweep 1 over the wave's frames warps every frame, stores dW/du and sums
+// W and u per voxel; after the LDS combine, sweep 2 warps again (the loads
+// hit the caches), forms r = W - mean W and writes the gradient.
+template <int D>
+__global__ __launch_bounds__(256) void eval_kernel(
+    const float* __restrict__ T, const float* __restrict__ u,
+    const int* __restrict__ K, Geom g, Model md, float* __restrict__ grad,
+    float* __restrict__ dWo, double* __restrict__ part,
+    unsigned* __restrict__ counter, Scal* __restrict__ sc) {
+  __shared__ double xs[4][kWave][1 + D];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int G = blockDim.x / kWave;
+  const Chunk ch = frame_chunk(md.nK);
+  const long long N = g.N;
+  const long long ntiles = (N + kWave - 1) / kWave;
+  double accD = 0.0, accS = 0.0, accP = 0.0;
+  for (int it = 0;; ++it) {
+    long long tile = xcd_tile(ntiles, it);
+    if (tile < 0) break;
+    long long x = tile * kWave + lane;
+    bool valid = x < N;
+    Pos<D> p = make_pos<D>(g, valid ? x : N - 1);
+    double sW = 0.0, sU[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) sU[a] = 0.0;
+    for (int j = ch.j0; j < ch.j1; ++j) {
+      int k = K[j];
+      const float* uk = u + (size_t)k * D * N;
+      double uv[D], dw[D], W;
+#pragma unroll
+      for (int a = 0; a < D; ++a) uv[a] = (double)uk[(size_t)a * N + p.idx];
+      warp_sample<D>(T + (size_t)k * N, g, p, uv, W, dw);
+      sW += W;
+      float* dj = dWo ? dWo + (size_t)j * D * N : nullptr;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        sU[a] += uv[a];
+        if (valid && dj) dj[(size_t)a * N + p.idx] = (float)dw[a];
+      }
+    }
+    xs[w][lane][0] = sW;
+#pragma unroll
+    for (int a = 0; a < D; ++a) xs[w][lane][1 + a] = sU[a];
+    __syncthreads();
+    double Wb = 0.0, ub[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) ub[a] = 0.0;
+    for (int c = 0; c < G; ++c) {
+      Wb += xs[c][lane][0];
+#pragma unroll
+      for (int a = 0; a < D; ++a) ub[a] += xs[c][lane][1 + a];
+    }
+    __syncthreads();
+    Wb *= md.inv_nK;
+#pragma unroll
+    for (int a = 0; a < D; ++a) ub[a] *= md.inv_nK;
+    if (valid) {
+      for (int j = ch.j0; j < ch.j1; ++j) {
+        int k = K[j];
+        const float* uk = u + (size_t)k * D * N;
+        double uv[D], dw[D], W;
+#pragma unroll
+        for (int a = 0; a < D; ++a) uv[a] = (double)uk[(size_t)a * N + p.idx];
+        warp_sample<D>(T + (size_t)k * N, g, p, uv, W, dw);
+        double r = W - Wb;
+        accD += r * r;
+        float* gj = grad ? grad + (size_t)j * D * N : nullptr;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double btb, e;
+          reg_terms<D>(uk + (size_t)a * N, p, g, md.reg, btb, e);
+          accS += e;
+          if (gj) {
+            double gv = md.data_c * r * dw[a] +
+                        md.alpha_hd * md.reg_scale * btb + md.lam_c * ub[a];
+            gj[(size_t)a * N + p.idx] = (float)gv;
+          }
+        }
+      }
+      if (w == 0) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) accP += ub[a] * ub[a];
+      }
+    }
+  }
+  double vals[3] = {accD, accS, accP};
+  double out[3];
+  if (grid_reduce<3>(vals, 0u, part, counter, out) && threadIdx.x == 0) {
+    double Dv = md.hd * out[0];
+    double Sv = md.half_alpha_hd * md.reg_scale * out[1];
+    double Pv = md.lam_hd * out[2];
+    sc->D = Dv;
+    sc->S = Sv;
+    sc->P = Pv;
+    sc->J = Dv + Sv + Pv;
+  }
+}
+
+// Gauss-Newton Hessian product on the tiles of this block; returns this
+// thread's share of v.Hv.  Sweep 1 sums s_k = dW_k . v_k and v_k per voxel;
+// sweep 2 re-reads dW_k and v_k (cache hits) and writes
+// (Hv)_k = 2h^D dW_k (s_k - mean s) + alpha h^D B^T B v_k + 2 lambda h^D / |K| mean v.
+template <int D>
+__device__ double hv_tiles(const float* __restrict__ v,
+                           const float* __restrict__ dW, const Geom& g,
+                           const Model& md, float* __restrict__ hv) {
+  __shared__ double xs[4][kWave][1 + D];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int G = blockDim.x / kWave;
+  const Chunk ch = frame_chunk(md.nK);
+  const long long N = g.N;
+  const long long ntiles = (N + kWave - 1) / kWave;
+  double acc = 0.0;
+  for (int it = 0;; ++it) {
+    long long tile = xcd_tile(ntiles, it);
+    if (tile < 0) break;
+    long long x = tile * kWave + lane;
+    bool valid = x < N;
+    Pos<D> p = make_pos<D>(g, valid ? x : N - 1);
+    double sS = 0.0, sV[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) sV[a] = 0.0;
+    for (int j = ch.j0; j < ch.j1; ++j) {
+      const float* vj = v + (size_t)j * D * N;
+      const float* dj = dW + (size_t)j * D * N;
+      double s = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        double vv = (double)vj[(size_t)a * N + p.idx];
+        s += (double)dj[(size_t)a * N + p.idx] * vv;
+        sV[a] += vv;
+      }
+      sS += s;
+    }
+    xs[w][lane][0] = sS;
+#pragma unroll
+    for (int a = 0; a < D; ++a) xs[w][lane][1 + a] = sV[a];
+    __syncthreads();
+    double sb = 0.0, vb[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) vb[a] = 0.0;
+    for (int c = 0; c < G; ++c) {
+      sb += xs[c][lane][0];
+#pragma unroll
+      for (int a = 0; a < D; ++a) vb[a] += xs[c][lane][1 + a];
+    }
+    __syncthreads();
+    sb *= md.inv_nK;
+#pragma unroll
+    for (int a = 0; a < D; ++a) vb[a] *= md.inv_nK;
+    if (valid) {
+      for (int j = ch.j0; j < ch.j1; ++j) {
+        const float* vj = v + (size_t)j * D * N;
+        const float* dj = dW + (size_t)j * D * N;
+        float* hj = hv + (size_t)j * D * N;
+        double s = 0.0;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          s += (double)dj[(size_t)a * N + p.idx] *
+               (double)vj[(size_t)a * N + p.idx];
+        double ds = md.data_c * (s - sb);
+#pragma unroll 1
+        for (int a = 0; a < D; ++a) {
+          const float* vja = vj + (size_t)a * N;
+          double btb, e;
+          reg_terms<D>(vja, p, g, md.reg, btb, e);
+          double vba = a == 0 ? vb[0] : (a == 1 ? vb[1] : vb[D - 1]);
+          double h = ds * (double)dj[(size_t)a * N + p.idx] +
+                     md.alpha_hd * md.reg_scale * btb + md.lam_c * vba;
+          float hf = (float)h;
+          hj[(size_t)a * N + p.idx] = hf;
+          acc += (double)vja[p.idx] * (double)hf;
+        }
+      }
+    }
+  }
+  return acc;
+}
+
+template <int D>
+__global__ __launch_bounds__(256) void hessvec_kernel(
+    const float* __restrict__ v, const float* __restrict__ dW, Geom g,
+    Model md, float* __restrict__ hv, double* __restrict__ part,
+    unsigned* __restrict__ counter, Scal* __restrict__ sc) {
+  double vals[1] = {hv_tiles<D>(v, dW, g, md, hv)};
+  double out[1];
+  if (grid_reduce<1>(vals, 0u, part, counter, out) && threadIdx.x == 0)
+    sc->vHv = out[0];
+}
+
+// CG step, part 1: q = H p and a = rz / p.q (breakdown if p.q <= 0).
+template <int D>
+__global__ __launch_bounds__(256) void pcg_hv_kernel(
+    const float* __restrict__ p, const float* __restrict__ dW, Geom g,
+    Model md, float* __restrict__ q, double* __restrict__ part,
+    unsigned* __restrict__ counter, Scal* __restrict__ sc) {
+  if (sc->done) return;
+  double vals[1] = {hv_tiles<D>(p, dW, g, md, q)};
+  double out[1];
+  if (grid_reduce<1>(vals, 0u, part, counter, out) && threadIdx.x == 0) {
+    double pq = out[0];
+    sc->pq = pq;
+    if (pq > 0.0) {
+      sc->a = sc->rz / pq;
+    } else {
+      sc->done = 2;
+    }
+  }
+}
+
+// Jacobi preconditioner entry of element e = (j, a, x).
+template <int D>
+__device__ __forceinline__ double jacobi_at(const float* __restrict__ dW,
+                                            size_t e, long long N,
+                                            const Geom& g, const Model& md) {
+  long long x = (long long)(e % (size_t)N);
+  Pos<D> p = make_pos<D>(g, x);
+  double d = (double)dW[e];
+  return md.mdiag_c * d * d +
+         md.alpha_hd * md.reg_scale * reg_diag_at<D>(p, g, md.reg) +
+         md.pen_diag;
+}
+
+// CG start: x = 0, r = -g, z = M^-1 r, p = z.
+template <int D>
+__global__ __launch_bounds__(256) void pcg_init_kernel(
+    const float* __restrict__ grad, const float* __restrict__ dW, Geom g,
+    Model md, size_t count, float* __restrict__ x, float* __restrict__ r,
+    float* __restrict__ z, float* __restrict__ p, double* __restrict__ part,
+    unsigned* __restrict__ counter, Scal* __restrict__ sc) {
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  double rz = 0.0, rr = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += stride) {
+    float rv = -grad[e];
+    float zv = (float)((double)rv / jacobi_at<D>(dW, e, g.N, g, md));
+    x[e] = 0.0f;
+    r[e] = rv;
+    z[e] = zv;
+    p[e] = zv;
+    rz += (double)rv * (double)zv;
+    rr += (double)rv * (double)rv;
+  }
+  double vals[2] = {rz, rr};
+  double out[2];
+  if (grid_reduce<2>(vals, 0u, part, counter, out) && threadIdx.x == 0) {
+    sc->rz = out[0];
+    sc->r0 = sqrt(out[1]);
+    sc->rr = out[1];
+    sc->iters = 0;
+    sc->done = out[0] == 0.0 ? 1 : 0;
+  }
+}
+
+// CG step, part 2: x += a p, r -= a q, z = M^-1 r; convergence and beta.
+template <int D>
+__global__ __launch_bounds__(256) void pcg_update_kernel(
+    const float* __restrict__ p, const float* __restrict__ q,
+    const float* __restrict__ dW, Geom g, Model md, size_t count,
+    float* __restrict__ x, float* __restrict__ r, float* __restrict__ z,
+    int fixed, double rtol, double* __restrict__ part,
+    unsigned* __restrict__ counter, Scal* __restrict__ sc) {
+  if (sc->done) return;
+  const double a = sc->a;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  double rz = 0.0, rr = 0.0;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += stride) {
+    double pe = (double)p[e];
+    x[e] = (float)((double)x[e] + a * pe);
+    float rv = (float)((double)r[e] - a * (double)q[e]);
+    float zv = (float)((double)rv / jacobi_at<D>(dW, e, g.N, g, md));
+    r[e] = rv;
+    z[e] = zv;
+    rz += (double)rv * (double)zv;
+    rr += (double)rv * (double)rv;
+  }
+  double vals[2] = {rz, rr};
+  double out[2];
+  if (grid_reduce<2>(vals, 0u, part, counter, out) && threadIdx.x == 0) {
+    sc->iters += 1;
+    sc->rr = out[1];
+    bool conv = (!fixed && sqrt(out[1]) <= rtol * sc->r0) || out[0] == 0.0;
+    if (conv) {
+      sc->done = 1;
+    } else {
+      sc->beta = out[0] / sc->rz;
+      sc->rz = out[0];
+    }
+  }
+}
+
+// CG step, part 3: p = z + beta p.
+__global__ __launch_bounds__(256) void pcg_pupdate_kernel(
+    const float* __restrict__ z, float* __restrict__ p, size_t count,
+    const Scal* __restrict__ sc) {
+  if (sc->done) return;
+  const double b = sc->beta;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += stride)
+    p[e] = (float)((double)z[e] + b * (double)p[e]);
+}
+
+struct Steps {
+  double t[kTrialSteps];
+};
+
+// Objective at u + t delta for kTrialSteps values of t in one sweep.  The
+// data term per voxel is sum (W - c)^2 - (sum (W - c))^2 / |K| with c the
+// voxel's value in the first frame of K (a shift against cancellation);
+// S and P are quadratic in t and are expanded exactly.  The per-step sums
+// live in LDS (one slot row per thread), which keeps register use low.
+template <int D>
+__global__ __launch_bounds__(256) void trial_kernel(
+    const float* __restrict__ T, const float* __restrict__ u,
+    const float* __restrict__ dl, const float* __restrict__ gr,
+    const int* __restrict__ K, Geom g, Model md, Steps st,
+    double* __restrict__ part, unsigned* __restrict__ counter,
+    Scal* __restrict__ sc) {
+  constexpr int NT = kTrialSteps;
+  constexpr int NV = 2 * NT + 2 * D;
+  __shared__ double xs[4][kWave][NV];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = threadIdx.x / kWave;
+  const int G = blockDim.x / kWave;
+  const Chunk ch = frame_chunk(md.nK);
+  const long long N = g.N;
+  const long long ntiles = (N + kWave - 1) / kWave;
+  double* my = xs[w][lane];
+  double accD[NT];
+#pragma unroll
+  for (int s = 0; s < NT; ++s) accD[s] = 0.0;
+  double rA = 0, rB = 0, rC = 0, pA = 0, pB = 0, pC = 0, slope = 0, mx = 0;
+  for (int it = 0;; ++it) {
+    long long tile = xcd_tile(ntiles, it);
+    if (tile < 0) break;
+    long long x = tile * kWave + lane;
+    bool valid = x < N;
+    Pos<D> p = make_pos<D>(g, valid ? x : N - 1);
+    const double c = (double)T[(size_t)K[0] * N + p.idx];
+    for (int v = 0; v < NV; ++v) my[v] = 0.0;
+    for (int j = ch.j0; j < ch.j1; ++j) {
+      int k = K[j];
+      double uv[D], dv[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        uv[a] = (double)u[((size_t)k * D + a) * N + p.idx];
+        size_t o = ((size_t)j * D + a) * N + p.idx;
+        dv[a] = (double)dl[o];
+        my[2 * NT + a] += uv[a];
+        my[2 * NT + D + a] += dv[a];
+        if (valid) {
+          slope += (double)gr[o] * dv[a];
+          mx = fmax(mx, fabs(dv[a]));
+          double uu, uw, ww;
+          reg_cross<D>(u + ((size_t)k * D + a) * N,
+                       dl + ((size_t)j * D + a) * N, p, g, md.reg, uu, uw, ww);
+          rA += uu;
+          rB += uw;
+          rC += ww;
+        }
+      }
+      const float* Tk = T + (size_t)k * N;
+#pragma unroll 1
+      for (int s = 0; s < NT; ++s) {
+        double ut[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) ut[a] = uv[a] + st.t[s] * dv[a];
+        double wv = warp_value<D>(Tk, g, p, ut) - c;
+        my[s] += wv;
+        my[NT + s] += wv * wv;
+      }
+    }
+    __syncthreads();
+    if (w == 0 && valid) {
+      double t1[NT], t2[NT], tu[D], tl[D];
+#pragma unroll
+      for (int s = 0; s < NT; ++s) t1[s] = t2[s] = 0.0;
+#pragma unroll
+      for (int a = 0; a < D; ++a) tu[a] = tl[a] = 0.0;
+      for (int cw = 0; cw < G; ++cw) {
+#pragma unroll
+        for (int s = 0; s < NT; ++s) {
+          t1[s] += xs[cw][lane][s];
+          t2[s] += xs[cw][lane][NT + s];
+        }
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          tu[a] += xs[cw][lane][2 * NT + a];
+          tl[a] += xs[cw][lane][2 * NT + D + a];
+        }
+      }
+#pragma unroll
+      for (int s = 0; s < NT; ++s) accD[s] += t2[s] - t1[s] * t1[s] * md.inv_nK;
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        double ub = tu[a] * md.inv_nK, lb = tl[a] * md.inv_nK;
+        pA += ub * ub;
+        pB += ub * lb;
+        pC += lb * lb;
+      }
+    }
+    __syncthreads();
+  }
+  double vals[NT + 8];
+#pragma unroll
+  for (int s = 0; s < NT; ++s) vals[s] = accD[s];
+  vals[NT + 0] = rA;
+  vals[NT + 1] = rB;
+  vals[NT + 2] = rC;
+  vals[NT + 3] = pA;
+  vals[NT + 4] = pB;
+  vals[NT + 5] = pC;
+  vals[NT + 6] = slope;
+  vals[NT + 7] = mx;
+  double out[NT + 8];
+  if (grid_reduce<NT + 8>(vals, 1u << (NT + 7), part, counter, out) &&
+      threadIdx.x == 0) {
+    double sA = md.half_alpha_hd * md.reg_scale;
+    for (int s = 0; s < NT; ++s) {
+      double t = st.t[s];
+      double Dv = md.hd * out[s];
+      double Sv = sA * (out[NT] + 2.0 * t * out[NT + 1] + t * t * out[NT + 2]);
+      double Pv = md.lam_hd *
+                  (out[NT + 3] + 2.0 * t * out[NT + 4] + t * t * out[NT + 5]);
+      sc->Jt[s] = Dv + Sv + Pv;
+    }
+    sc->slope = out[NT + 6];
+    sc->maxd = out[NT + 7];
+  }
+}
+
+__global__ void accept_kernel(float* __restrict__ u,
+                              const float* __restrict__ dl,
+                              const int* __restrict__ K, int nK, int dim,
+                              long long N, double t) {
+  size_t count = (size_t)nK * dim * N;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += stride) {
+    size_t row = e / (size_t)N;
+    size_t x = e - row * (size_t)N;
+    int j = (int)(row / dim);
+    int a = (int)(row - (size_t)j * dim);
+    size_t o = ((size_t)K[j] * dim + a) * N + x;
+    u[o] = (float)((double)u[o] + t * (double)dl[e]);
+  }
+}
+
+// Linear temporal interpolation of all frames from the frames of K_q.
+__global__ void linear_predict_kernel(const float* Y, float* __restrict__ Z,
+                                      float* Yout, LinTab tab,
+                                      int n, int dim, long long N) {
+  size_t per = (size_t)dim * N;
+  size_t count = (size_t)n * per;
+  size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+       e += stride) {
+    int k = (int)(e / per);
+    size_t off = e - (size_t)k * per;
+    int l = tab.left[k], r = tab.right[k];
+    double v = tab.wl[k] * (double)Y[(size_t)l * per + off] +
+               tab.wr[k] * (double)Y[(size_t)r * per + off];
+    float fv = (float)v;
+    Z[e] = fv;
+    if (l != k || r != k) Yout[e] = fv;
+  }
+}
+
+// Eq. (2) for every (component, voxel): zeta = omega + xi with
+// (M + beta D^T D) xi = M (eta - omega); Thomas sweep with the shared
+// factorisation, d' kept in LDS (64 systems per block).
+__global__ __launch_bounds__(64) void ls_predict_kernel(
+    float* __restrict__ Y, float* __restrict__ Z, ThomasTab tab, int n,
+    int dim, long long N, double beta) {
+  extern __shared__ double dp[];   // [n][blockDim.x]
+  const int B = blockDim.x;
+  const size_t per = (size_t)dim * N;
+  const size_t sys = (size_t)blockIdx.x * B + threadIdx.x;
+  const bool valid = sys < per;
+  double prev = 0.0;
+  for (int k = 0; k < n; ++k) {
+    double rhs = 0.0;
+    if (valid && tab.mask[k]) {
+      size_t o = (size_t)k * per + sys;
+      rhs = (double)Y[o] - (double)Z[o];
+    }
+    prev = (rhs + beta * prev) * tab.invp[k];
+    dp[k * B + threadIdx.x] = prev;
+  }
+  double xi = 0.0;
+  for (int k = n - 1; k >= 0; --k) {
+    xi = (k == n - 1) ? dp[k * B + threadIdx.x]
+                      : dp[k * B + threadIdx.x] - tab.cp[k] * xi;
+    if (valid) {
+      size_t o = (size_t)k * per + sys;
+      float zv = (float)((double)Z[o] + xi);
+      Z[o] = zv;
+      Y[o] = zv;
+    }
+  }
+}
+
+// ------------------------------------------------------------- launchers
+
+hipError_t launch_fill(float* p, size_t count, float v, hipStream_t s) {
+  if (count == 0) return hipSuccess;
+  fill_kernel<<<elem_blocks(count), 256, 0, s>>>(p, count, v);
+  return hipGetLastError();
+}
+
+hipError_t launch_check_finite(const float* p, size_t count, Scal* sc,
+                               hipStream_t s) {
+  check_finite_kernel<<<elem_blocks(count), 256, 0, s>>>(p, count, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_restrict(int dim, const float* fine, float* coarse, int n,
+                           const Geom& gf, const Geom& gc, hipStream_t s) {
+  int nb = elem_blocks((size_t)n * gc.N, 1);
+  if (dim == 2)
+    restrict_kernel<2><<<nb, 256, 0, s>>>(fine, coarse, n, gf, gc);
+  else
+    restrict_kernel<3><<<nb, 256, 0, s>>>(fine, coarse, n, gf, gc);
+  return hipGetLastError();
+}
+
+hipError_t launch_prolong(int dim, const float* coarse, float* fine,
+                          int fields, const Geom& gc, const Geom& gf,
+                          hipStream_t s) {
+  int nb = elem_blocks((size_t)gf.N, 1);
+  if (dim == 2)
+    prolong_kernel<2><<<nb, 256, 0, s>>>(coarse, fine, fields, gc, gf);
+  else
+    prolong_kernel<3><<<nb, 256, 0, s>>>(coarse, fine, fields, gc, gf);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(int dim, const float* T, const float* u, const int* K,
+                       const Geom& g, const Model& md, float* grad,
+                       float* dW, RedBuf rb, Scal* sc, hipStream_t s) {
+  int nb = tile_blocks(g), nt = tile_threads(md.nK);
+  STML_DIM_DISPATCH(dim, eval_kernel, nb, nt, s, T, u, K, g, md,
+                     grad, dW, rb.part, rb.counter, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_hessvec(int dim, const float* v, const float* dW,
+                          const Geom& g, const Model& md, float* hv,
+                          RedBuf rb, Scal* sc, hipStream_t s) {
+  int nb = tile_blocks(g), nt = tile_threads(md.nK);
+  STML_DIM_DISPATCH(dim, hessvec_kernel, nb, nt, s, v, dW, g, md, hv,
+                     rb.part, rb.counter, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_init(int dim, const float* grad, const float* dW,
+                           const Geom& g, const Model& md, float* x, float* r,
+                           float* z, float* p, RedBuf rb, Scal* sc,
+                           hipStream_t s) {
+  size_t count = (size_t)md.nK * dim * g.N;
+  int nb = elem_blocks(count);
+  if (dim == 2)
+    pcg_init_kernel<2><<<nb, 256, 0, s>>>(grad, dW, g, md, count, x, r, z, p,
+                                          rb.part, rb.counter, sc);
+  else
+    pcg_init_kernel<3><<<nb, 256, 0, s>>>(grad, dW, g, md, count, x, r, z, p,
+                                          rb.part, rb.counter, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_hv(int dim, const float* p, const float* dW,
+                         const Geom& g, const Model& md, float* q, RedBuf rb,
+                         Scal* sc, hipStream_t s) {
+  int nb = tile_blocks(g), nt = tile_threads(md.nK);
+  STML_DIM_DISPATCH(dim, pcg_hv_kernel, nb, nt, s, p, dW, g, md, q,
+                     rb.part, rb.counter, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_update(int dim, const float* p, const float* q,
+                             const float* dW, const Geom& g, const Model& md,
+                             float* x, float* r, float* z, int fixed,
+                             double rtol, RedBuf rb, Scal* sc, hipStream_t s) {
+  size_t count = (size_t)md.nK * dim * g.N;
+  int nb = elem_blocks(count);
+  if (dim == 2)
+    pcg_update_kernel<2><<<nb, 256, 0, s>>>(p, q, dW, g, md, count, x, r, z,
+                                            fixed, rtol, rb.part, rb.counter,
+                                            sc);
+  else
+    pcg_update_kernel<3><<<nb, 256, 0, s>>>(p, q, dW, g, md, count, x, r, z,
+                                            fixed, rtol, rb.part, rb.counter,
+                                            sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_pupdate(const float* z, float* p, size_t count,
+                              Scal* sc, hipStream_t s) {
+  pcg_pupdate_kernel<<<elem_blocks(count), 256, 0, s>>>(z, p, count, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_trial(int dim, const float* T, const float* u,
+                        const float* delta, const float* grad, const int* K,
+                        const Geom& g, const Model& md, const double* t,
+                        RedBuf rb, Scal* sc, hipStream_t s) {
+  Steps st;
+  for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
+  int nb = tile_blocks(g);
+  int nt = tile_threads(md.nK);
+  if (dim == 2)
+    trial_kernel<2><<<nb, nt, 0, s>>>(T, u, delta, grad, K, g, md, st,
+                                      rb.part, rb.counter, sc);
+  else
+    trial_kernel<3><<<nb, nt, 0, s>>>(T, u, delta, grad, K, g, md, st,
+                                      rb.part, rb.counter, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_accept(float* u, const float* delta, const int* K, int nK,
+                         int dim, long long N, double t, hipStream_t s) {
+  size_t count = (size_t)nK * dim * N;
+  accept_kernel<<<elem_blocks(count), 256, 0, s>>>(u, delta, K, nK, dim, N,
+                                                   t);
+  return hipGetLastError();
+}
+
+hipError_t launch_linear_predict(const float* Y, float* Z, float* Yout,
+                                 LinTab tab, int n, int dim, long long N,
+                                 hipStream_t s) {
+  size_t count = (size_t)n * dim * N;
+  linear_predict_kernel<<<elem_blocks(count), 256, 0, s>>>(Y, Z, Yout, tab, n,
+                                                           dim, N);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_predict(float* Y, float* Z, ThomasTab tab, int n,
+                             int dim, long long N, double beta,
+                             hipStream_t s) {
+  // d' of every system stays in LDS: n * B doubles <= 64 KiB.
+  size_t systems = (size_t)dim * N;
+  int B = n <= 128 ? 64 : 32;
+  int nb = (int)((systems + B - 1) / B);
+  size_t lds = (size_t)n * B * sizeof(double);
+  ls_predict_kernel<<<nb, B, lds, s>>>(Y, Z, tab, n, dim, N, beta);
+  return hipGetLastError();
+}
+
+}  // namespace stml

@@ -1,0 +1,894 @@
+// Host side of libstml: context, workspace layout, the Gauss-Newton / PCG
+// driver, the spatio-temporal multilevel schedule and the C-ABI of stml.h.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/stml.h"
+#include "launch.h"
+
+using namespace stml;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+struct LevelBufs {
+  float* T;      // [n][N]
+  float* Y;      // [n][D][N] current estimate
+  float* Z;      // [n][D][N] last start guess (omega of eq. (2))
+};
+
+struct QTabs {
+  int* K;            // device: frames of K_q
+  LinTab lin;
+  ThomasTab thomas;
+};
+
+// Workspace carve-up; the same walk sizes and assigns it.
+struct Layout {
+  size_t off = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    size_t o = off;
+    off = align_up(off + count * sizeof(T));
+    return base ? reinterpret_cast<T*>(base + o) : nullptr;
+  }
+};
+
+}  // namespace
+
+struct stml_ctx {
+  stml_opts o;
+  int n = 0, d = 2, L = 1, T1 = 1;
+  std::vector<std::vector<int>> ext;    // per level, coarse first
+  std::vector<long long> N;
+  std::vector<double> h;
+  hipStream_t stream = nullptr;
+  std::vector<LevelBufs> lv;
+  std::vector<QTabs> qt;
+  std::vector<std::vector<int>> K;      // host copies of K_q
+  // solver scratch, compact [nK][D][N_finest]
+  float *g = nullptr, *dW = nullptr, *x = nullptr, *r = nullptr,
+        *p = nullptr, *z = nullptr, *q = nullptr;
+  RedBuf rb{};
+  Scal* sc = nullptr;
+  int* kbuf = nullptr;                  // device frame list for test calls
+  Scal* hsc = nullptr;                  // pinned host mirror of sc
+  int* hk = nullptr;                    // pinned host staging of frame lists
+  bool have_seq = false;
+  std::vector<stml_gir_log> logs;
+  std::string err;
+  // kernel timing
+  struct Rec {
+    int kernel, level;
+    double vf;
+    hipEvent_t a, b;
+  };
+  struct KStat {
+    double ms = 0.0, vf = 0.0;
+    long long n = 0;
+  };
+  bool timing = false;
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::pair<int, int>, KStat> kstats;
+};
+
+namespace {
+
+int fail(stml_ctx* c, int code, const char* fmt, ...) {
+  if (c) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    c->err = buf;
+  }
+  return code;
+}
+
+#define HIP_OK(call)                                                       \
+  do {                                                                     \
+    hipError_t e_ = (call);                                                \
+    if (e_ != hipSuccess)                                                  \
+      return fail(c, STML_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+bool opts_valid(const stml_opts* o) {
+  return o && (o->dim == 2 || o->dim == 3) && o->n_spatial >= 1 &&
+         o->n_spatial <= 16 && o->n_temporal >= 1 && o->n_temporal <= 16 &&
+         (o->regulariser == STML_REG_DIFFUSION ||
+          o->regulariser == STML_REG_CURVATURE) &&
+         o->alpha >= 0 && o->lambda >= 0 && o->beta >= 0 &&
+         o->eps_stop >= 0 && o->gn_max >= 0 && o->cg_max >= 0 &&
+         o->ls_max >= 0 && o->ls_max <= 60;
+}
+
+std::vector<std::vector<int>> level_extents(int dim, const int* extent,
+                                            int L) {
+  std::vector<std::vector<int>> e(L);
+  e[L - 1].assign(extent, extent + dim);
+  for (int l = L - 2; l >= 0; --l) {
+    e[l].resize(dim);
+    for (int a = 0; a < dim; ++a) e[l][a] = (e[l + 1][a] + 1) / 2;
+  }
+  return e;
+}
+
+// K_q = {k : k mod 2^(T-q) = 0} u {n-1} (Sec. 3, Fig. 1).
+std::vector<std::vector<int>> temporal_sets(int n, int T1) {
+  std::vector<std::vector<int>> K(T1);
+  int T = T1 - 1;
+  for (int q = 0; q < T1; ++q) {
+    long long step = 1LL << (T - q);
+    for (int k = 0; k < n; ++k)
+      if (k % step == 0 || k == n - 1) K[q].push_back(k);
+  }
+  return K;
+}
+
+long long voxels(const std::vector<int>& e) {
+  long long v = 1;
+  for (int m : e) v *= m;
+  return v;
+}
+
+// Walk the workspace: returns the byte size; assigns pointers if base.
+size_t layout(stml_ctx* c, char* base) {
+  Layout lo;
+  lo.base = base;
+  const int n = c->n, D = c->d;
+  c->lv.resize(c->L);
+  for (int l = 0; l < c->L; ++l) {
+    size_t NL = (size_t)c->N[l];
+    c->lv[l].T = lo.take<float>((size_t)n * NL);
+    c->lv[l].Y = lo.take<float>((size_t)n * D * NL);
+    c->lv[l].Z = lo.take<float>((size_t)n * D * NL);
+  }
+  size_t vec = (size_t)n * D * (size_t)c->N[c->L - 1];
+  c->g = lo.take<float>(vec);
+  c->dW = lo.take<float>(vec);
+  c->x = lo.take<float>(vec);
+  c->r = lo.take<float>(vec);
+  c->p = lo.take<float>(vec);
+  c->z = lo.take<float>(vec);
+  c->q = lo.take<float>(vec);
+  c->rb.part = lo.take<double>(kRedSlots);
+  c->rb.counter = lo.take<unsigned>(64);
+  c->sc = lo.take<Scal>(1);
+  c->kbuf = lo.take<int>(STML_MAX_FRAMES);
+  c->qt.resize(c->T1);
+  for (int q = 0; q < c->T1; ++q) {
+    c->qt[q].K = lo.take<int>(n);
+    c->qt[q].lin.left = lo.take<int>(n);
+    c->qt[q].lin.right = lo.take<int>(n);
+    c->qt[q].lin.wl = lo.take<double>(n);
+    c->qt[q].lin.wr = lo.take<double>(n);
+    c->qt[q].thomas.invp = lo.take<double>(n);
+    c->qt[q].thomas.cp = lo.take<double>(n);
+    c->qt[q].thomas.mask = lo.take<int>(n);
+  }
+  return lo.off;
+}
+
+bool setup_dims(stml_ctx* c, const stml_opts* o, int n, const int* extent) {
+  if (!opts_valid(o) || n < 1 || n > STML_MAX_FRAMES || !extent) return false;
+  for (int a = 0; a < o->dim; ++a)
+    if (extent[a] < 1) return false;
+  c->o = *o;
+  c->n = n;
+  c->d = o->dim;
+  c->L = o->n_spatial;
+  c->T1 = o->n_temporal;
+  c->ext = level_extents(o->dim, extent, c->L);
+  c->N.resize(c->L);
+  c->h.resize(c->L);
+  for (int l = 0; l < c->L; ++l) {
+    c->N[l] = voxels(c->ext[l]);
+    c->h[l] = std::ldexp(1.0, c->L - 1 - l);
+  }
+  // compact vectors index elements with 64-bit offsets, but the element
+  // kernels decode the frame index from 32-bit rows
+  if ((double)n * o->dim * (double)c->N[c->L - 1] > 2.0e9) return false;
+  c->K = temporal_sets(n, c->T1);
+  return true;
+}
+
+Geom geom_of(const stml_ctx* c, int level) {
+  return make_geom(c->d, c->ext[level].data(), c->h[level]);
+}
+
+Model model_of(const stml_ctx* c, int level, int nK) {
+  return make_model(c->d, c->h[level], nK, c->o.alpha, c->o.lambda,
+                    c->o.regulariser);
+}
+
+// --- kernel timing: event pairs around launches, resolved at sync points
+hipEvent_t pooled_event(stml_ctx* c) {
+  if (!c->pool.empty()) {
+    hipEvent_t e = c->pool.back();
+    c->pool.pop_back();
+    return e;
+  }
+  hipEvent_t e = nullptr;
+  if (hipEventCreate(&e) != hipSuccess) return nullptr;
+  return e;
+}
+
+void tbegin(stml_ctx* c, int kernel, int level, double vf) {
+  if (!c->timing) return;
+  stml_ctx::Rec r{kernel, level, vf, pooled_event(c), pooled_event(c)};
+  if (!r.a || !r.b) return;
+  (void)hipEventRecord(r.a, c->stream);
+  c->pending.push_back(r);
+}
+
+void tend(stml_ctx* c) {
+  if (!c->timing || c->pending.empty()) return;
+  (void)hipEventRecord(c->pending.back().b, c->stream);
+}
+
+void tresolve(stml_ctx* c) {
+  for (auto& r : c->pending) {
+    float ms = 0.0f;
+    if (hipEventSynchronize(r.b) == hipSuccess &&
+        hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+      auto& st = c->kstats[{r.kernel, r.level}];
+      st.ms += ms;
+      st.vf += r.vf;
+      st.n += 1;
+    }
+    c->pool.push_back(r.a);
+    c->pool.push_back(r.b);
+  }
+  c->pending.clear();
+}
+
+int read_scal(stml_ctx* c) {
+  HIP_OK(hipMemcpyAsync(c->hsc, c->sc, sizeof(Scal), hipMemcpyDeviceToHost,
+                        c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  tresolve(c);
+  return STML_OK;
+}
+
+#define TIMED(KERNEL, LEVEL, VF, CALL) \
+  do {                                 \
+    tbegin(c, KERNEL, LEVEL, VF);      \
+    hipError_t te_ = (CALL);           \
+    tend(c);                           \
+    HIP_OK(te_);                       \
+  } while (0)
+
+int upload_tables(stml_ctx* c) {
+  const int n = c->n;
+  const double beta = c->o.beta;
+  for (int q = 0; q < c->T1; ++q) {
+    const std::vector<int>& Kq = c->K[q];
+    std::vector<int> left(n), right(n), mask(n, 0);
+    std::vector<double> wl(n), wr(n), invp(n), cp(n);
+    for (int k : Kq) mask[k] = 1;
+    for (int k = 0; k < n; ++k) {
+      if (mask[k]) {
+        left[k] = right[k] = k;
+        wl[k] = 1.0;
+        wr[k] = 0.0;
+        continue;
+      }
+      int l = 0, r = n - 1;
+      for (int z : Kq) {
+        if (z < k) l = z;
+        if (z > k) {
+          r = z;
+          break;
+        }
+      }
+      left[k] = l;
+      right[k] = r;
+      wl[k] = (double)(r - k) / (r - l);
+      wr[k] = (double)(k - l) / (r - l);
+    }
+    // Thomas factorisation of M + beta D^T D (shared by every component)
+    double prev_cp = 0.0;
+    for (int k = 0; k < n; ++k) {
+      int ndiff = (n == 1) ? 0 : ((k == 0 || k == n - 1) ? 1 : 2);
+      double diag = mask[k] + beta * ndiff;
+      double den = (k == 0) ? diag : diag + beta * prev_cp;  // -sub*cp, sub=-beta
+      invp[k] = 1.0 / den;
+      cp[k] = (k == n - 1) ? 0.0 : -beta / den;
+      prev_cp = cp[k];
+    }
+    QTabs& t = c->qt[q];
+    HIP_OK(hipMemcpyAsync(t.K, Kq.data(), Kq.size() * sizeof(int),
+                          hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(t.lin.left, left.data(), n * sizeof(int),
+                          hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(t.lin.right, right.data(), n * sizeof(int),
+                          hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(t.lin.wl, wl.data(), n * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(t.lin.wr, wr.data(), n * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(t.thomas.invp, invp.data(), n * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(t.thomas.cp, cp.data(), n * sizeof(double),
+                          hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(t.thomas.mask, mask.data(), n * sizeof(int),
+                          hipMemcpyHostToDevice, c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+  }
+  return STML_OK;
+}
+
+int check_level(stml_ctx* c, int level) {
+  if (level < 0 || level >= c->L)
+    return fail(c, STML_EINVAL, "level %d outside [0, %d)", level, c->L);
+  return STML_OK;
+}
+
+// Frames list from the caller into the device staging buffer.
+int stage_frames(stml_ctx* c, const int* frames, int nk) {
+  if (!frames || nk < 1 || nk > c->n)
+    return fail(c, STML_EINVAL, "frame list: need 1..%d frames", c->n);
+  for (int i = 0; i < nk; ++i) {
+    if (frames[i] < 0 || frames[i] >= c->n || (i && frames[i] <= frames[i - 1]))
+      return fail(c, STML_EINVAL, "frame list must be ascending in [0,%d)",
+                  c->n);
+    c->hk[i] = frames[i];
+  }
+  HIP_OK(hipMemcpyAsync(c->kbuf, c->hk, nk * sizeof(int),
+                        hipMemcpyHostToDevice, c->stream));
+  return STML_OK;
+}
+
+// Jacobi-PCG for H delta = -g at the evaluation just made (g, dW in
+// scratch).  Enqueued only; scalars stay on the device.
+int enqueue_pcg(stml_ctx* c, int level, const Geom& g, const Model& md) {
+  const int D = c->d;
+  const size_t count = (size_t)md.nK * D * g.N;
+  const double vf = (double)md.nK * g.N;
+  TIMED(STML_K_CG_INIT, level, vf,
+        launch_pcg_init(D, c->g, c->dW, g, md, c->x, c->r, c->z, c->p, c->rb,
+                        c->sc, c->stream));
+  for (int it = 0; it < c->o.cg_max; ++it) {
+    TIMED(STML_K_HESSVEC, level, vf,
+          launch_pcg_hv(D, c->p, c->dW, g, md, c->q, c->rb, c->sc,
+                        c->stream));
+    TIMED(STML_K_CG_UPDATE, level, vf,
+          launch_pcg_update(D, c->p, c->q, c->dW, g, md, c->x, c->r, c->z,
+                            c->o.parity_mode, c->o.cg_rtol, c->rb, c->sc,
+                            c->stream));
+    if (it + 1 < c->o.cg_max)
+      TIMED(STML_K_CG_PUPDATE, level, vf,
+            launch_pcg_pupdate(c->z, c->p, count, c->sc, c->stream));
+  }
+  return STML_OK;
+}
+
+// Gauss-Newton on the frames Kdev (nK of them) of `level`, updating u in
+// place.  Mirrors the oracle's gauss_newton step for step.
+int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
+                 stml_gir_log* log) {
+  const stml_opts& o = c->o;
+  const int D = c->d;
+  const Geom g = geom_of(c, level);
+  const Model md = model_of(c, level, nK);
+  const float* T = c->lv[level].T;
+  int status = STML_OK;
+  std::memset(log, 0, sizeof *log);
+  log->n_frames = nK;
+  log->J0 = log->J = NAN;
+  const double vf = (double)nK * g.N;
+  for (int it = 0; it < o.gn_max; ++it) {
+    TIMED(STML_K_EVAL, level, vf,
+          launch_eval(D, T, u, Kdev, g, md, c->g, c->dW, c->rb, c->sc,
+                      c->stream));
+    int rc = enqueue_pcg(c, level, g, md);
+    if (rc) return rc;
+    // Armijo: t = 1, 1/2, ..., 2^-ls_max, kTrialSteps per sweep; the first
+    // sweep also evaluates t = 0 so the comparison uses one formula.
+    double J0t = 0.0, J = 0.0, slope = 0.0, maxd = 0.0, tacc = -1.0, Jacc = 0;
+    int next = 0;           // exponent of the next step to try
+    bool first = true;
+    int cg_iters = 0, done = 0;
+    while (next <= o.ls_max && tacc < 0) {
+      double ts[kTrialSteps];
+      int cnt = 0, base = 0;
+      if (first) ts[cnt++] = 0.0, base = 1;
+      int e0 = next;
+      while (cnt < kTrialSteps) {
+        int e = next <= o.ls_max ? next : o.ls_max;
+        ts[cnt++] = std::ldexp(1.0, -e);
+        if (next <= o.ls_max) ++next;
+      }
+      TIMED(STML_K_TRIAL, level, vf,
+            launch_trial(D, T, u, c->x, c->g, Kdev, g, md, ts, c->rb, c->sc,
+                         c->stream));
+      rc = read_scal(c);
+      if (rc) return rc;
+      if (first) {
+        J0t = c->hsc->Jt[0];
+        J = c->hsc->J;
+        slope = c->hsc->slope;
+        maxd = c->hsc->maxd;
+        cg_iters = c->hsc->iters;
+        done = c->hsc->done;
+        first = false;
+      }
+      for (int s = base; s < kTrialSteps && tacc < 0; ++s) {
+        int e = e0 + (s - base);
+        if (e > o.ls_max) break;
+        double t = ts[s];
+        if (c->hsc->Jt[s] <= J0t + o.c1 * t * slope) {
+          tacc = t;
+          Jacc = c->hsc->Jt[s];
+        }
+      }
+    }
+    if (it == 0) {
+      log->J0 = J;
+      log->J = J;
+    }
+    log->D = c->hsc->D;
+    log->S = c->hsc->S;
+    log->P = c->hsc->P;
+    if (it < 64) log->cg_iterations[it] = cg_iters;
+    if (tacc < 0) {
+      status = STML_WLINESEARCH;
+      break;
+    }
+    TIMED(STML_K_ACCEPT, level, vf,
+          launch_accept(u, c->x, Kdev, nK, D, g.N, tacc, c->stream));
+    if (it < 64) log->step[it] = tacc;
+    log->gn_iterations += 1;
+    log->J = Jacc;
+    if (done == 2) {
+      status = STML_EBREAKDOWN;
+      break;
+    }
+    if (!o.parity_mode && (J - Jacc) <= o.tol_J * std::fabs(J) &&
+        tacc * maxd <= o.tol_u)
+      break;
+  }
+  HIP_OK(hipStreamSynchronize(c->stream));
+  tresolve(c);
+  log->status = status;
+  return status;
+}
+
+int do_predict(stml_ctx* c, int level, int q_next) {
+  const int n = c->n, D = c->d;
+  LevelBufs& b = c->lv[level];
+  const size_t cnt = (size_t)n * D * c->N[level];
+  const double vf = (double)n * c->N[level];
+  if (q_next == 0) {
+    if (level == 0) {
+      HIP_OK(launch_fill(b.Z, cnt, 0.0f, c->stream));
+    } else {
+      Geom gc = geom_of(c, level - 1), gf = geom_of(c, level);
+      TIMED(STML_K_PREDICT, level, vf,
+            launch_prolong(D, c->lv[level - 1].Y, b.Z, n * D, gc, gf,
+                           c->stream));
+    }
+    HIP_OK(hipMemcpyAsync(b.Y, b.Z, cnt * sizeof(float),
+                          hipMemcpyDeviceToDevice, c->stream));
+  } else if (level == 0) {
+    TIMED(STML_K_PREDICT, level, vf,
+          launch_linear_predict(b.Y, b.Z, b.Y, c->qt[q_next - 1].lin, n, D,
+                                c->N[level], c->stream));
+  } else {
+    TIMED(STML_K_PREDICT, level, vf,
+          launch_ls_predict(b.Y, b.Z, c->qt[q_next - 1].thomas, n, D,
+                            c->N[level], c->o.beta, c->stream));
+  }
+  HIP_OK(hipStreamSynchronize(c->stream));
+  tresolve(c);
+  return STML_OK;
+}
+
+int do_register(stml_ctx* c, int level, int q) {
+  stml_gir_log log;
+  int rc = gauss_newton(c, level, c->qt[q].K, (int)c->K[q].size(),
+                        c->lv[level].Y, &log);
+  if (rc < 0 && rc != STML_EBREAKDOWN) return rc;
+  log.level = level;
+  log.q = q;
+  c->logs.push_back(log);
+  if (rc == STML_EBREAKDOWN) return fail(c, rc, "CG breakdown (p.Hp <= 0)");
+  if (rc == STML_WLINESEARCH)
+    return fail(c, rc, "Armijo search found no step at level %d q %d", level,
+                q);
+  return STML_OK;
+}
+
+// D over all frames at an all-frame estimate U (eq. (3) test).
+int all_frame_D(stml_ctx* c, int level, const float* U, double* out) {
+  const int T = c->T1 - 1;
+  const Geom g = geom_of(c, level);
+  const Model md = model_of(c, level, c->n);
+  HIP_OK(launch_eval(c->d, c->lv[level].T, U, c->qt[T].K, g, md, nullptr,
+                     nullptr, c->rb, c->sc, c->stream));
+  int rc = read_scal(c);
+  if (rc) return rc;
+  *out = c->hsc->D;
+  return STML_OK;
+}
+
+}  // namespace
+
+// ================================================================= C-ABI
+
+extern "C" {
+
+void stml_default_opts(stml_opts* o) {
+  if (!o) return;
+  std::memset(o, 0, sizeof *o);
+  o->dim = 2;
+  o->n_spatial = 2;
+  o->n_temporal = 2;
+  o->regulariser = STML_REG_DIFFUSION;
+  o->alpha = 1e-2;
+  o->lambda = 1e-2;
+  o->beta = 1e-5;
+  o->eps_stop = 0.0;
+  o->gn_max = 10;
+  o->cg_max = 20;
+  o->cg_rtol = 0.1;
+  o->ls_max = 10;
+  o->c1 = 1e-4;
+  o->tol_J = 1e-3;
+  o->tol_u = 1e-2;
+  o->predictor = 0;
+  o->parity_mode = 0;
+}
+
+size_t stml_workspace_bytes(const stml_opts* o, int n, const int* extent) {
+  stml_ctx tmp;
+  if (!setup_dims(&tmp, o, n, extent)) return 0;
+  return layout(&tmp, nullptr);
+}
+
+int stml_create(const stml_opts* o, int n, const int* extent, void* stream,
+                void* ws, size_t ws_bytes, stml_ctx** out) {
+  if (!out) return STML_EINVAL;
+  *out = nullptr;
+  stml_ctx* c = new stml_ctx();
+  if (!setup_dims(c, o, n, extent)) {
+    delete c;
+    return STML_EINVAL;
+  }
+  size_t need = layout(c, nullptr);
+  if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign)) {
+    delete c;
+    return ws && ws_bytes < need ? STML_ENOMEM : STML_EINVAL;
+  }
+  layout(c, static_cast<char*>(ws));
+  c->stream = static_cast<hipStream_t>(stream);
+  if (hipHostMalloc((void**)&c->hsc, sizeof(Scal), hipHostMallocDefault) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&c->hk, STML_MAX_FRAMES * sizeof(int),
+                    hipHostMallocDefault) != hipSuccess) {
+    stml_destroy(c);
+    return STML_EDEVICE;
+  }
+  if (hipMemsetAsync(c->rb.counter, 0, 64 * sizeof(unsigned), c->stream) !=
+          hipSuccess ||
+      hipMemsetAsync(c->sc, 0, sizeof(Scal), c->stream) != hipSuccess ||
+      upload_tables(c) != STML_OK) {
+    stml_destroy(c);
+    return STML_EDEVICE;
+  }
+  *out = c;
+  return STML_OK;
+}
+
+void stml_destroy(stml_ctx* c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  tresolve(c);
+  for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
+  if (c->hsc) (void)hipHostFree(c->hsc);
+  if (c->hk) (void)hipHostFree(c->hk);
+  delete c;
+}
+
+const char* stml_last_error(const stml_ctx* c) {
+  return c ? c->err.c_str() : "null context";
+}
+
+int stml_set_sequence(stml_ctx* c, const float* frames_dev) {
+  if (!c) return STML_EINVAL;
+  if (!frames_dev) return fail(c, STML_EINVAL, "null frames");
+  const int n = c->n, D = c->d, L = c->L;
+  size_t cnt = (size_t)n * c->N[L - 1];
+  HIP_OK(hipMemsetAsync(&c->sc->bad, 0, sizeof(int), c->stream));
+  HIP_OK(launch_check_finite(frames_dev, cnt, c->sc, c->stream));
+  HIP_OK(hipMemcpyAsync(c->lv[L - 1].T, frames_dev, cnt * sizeof(float),
+                        hipMemcpyDeviceToDevice, c->stream));
+  for (int l = L - 1; l > 0; --l) {
+    Geom gf = geom_of(c, l), gc = geom_of(c, l - 1);
+    TIMED(STML_K_RESTRICT, l - 1, (double)n * gc.N,
+          launch_restrict(D, c->lv[l].T, c->lv[l - 1].T, n, gf, gc,
+                          c->stream));
+  }
+  for (int l = 0; l < L; ++l) {
+    size_t vc = (size_t)n * D * c->N[l];
+    HIP_OK(launch_fill(c->lv[l].Y, vc, 0.0f, c->stream));
+    HIP_OK(launch_fill(c->lv[l].Z, vc, 0.0f, c->stream));
+  }
+  int rc = read_scal(c);
+  if (rc) return rc;
+  if (c->hsc->bad) {
+    c->have_seq = false;
+    return fail(c, STML_EINVAL, "%d non-finite frame values", c->hsc->bad);
+  }
+  c->have_seq = true;
+  c->logs.clear();
+  return STML_OK;
+}
+
+int stml_get_level_frames(const stml_ctx* cc, int level, float* out) {
+  stml_ctx* c = const_cast<stml_ctx*>(cc);
+  if (!c) return STML_EINVAL;
+  int rc = check_level(c, level);
+  if (rc) return rc;
+  if (!c->have_seq) return fail(c, STML_ESTATE, "no sequence");
+  HIP_OK(hipMemcpyAsync(out, c->lv[level].T,
+                        (size_t)c->n * c->N[level] * sizeof(float),
+                        hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  return STML_OK;
+}
+
+int stml_level_extent(const stml_ctx* cc, int level, int* out_extent) {
+  stml_ctx* c = const_cast<stml_ctx*>(cc);
+  if (!c || !out_extent) return STML_EINVAL;
+  int rc = check_level(c, level);
+  if (rc) return rc;
+  for (int a = 0; a < c->d; ++a) out_extent[a] = c->ext[level][a];
+  return STML_OK;
+}
+
+int stml_temporal_set(const stml_ctx* cc, int q, int* out, int cap) {
+  stml_ctx* c = const_cast<stml_ctx*>(cc);
+  if (!c) return STML_EINVAL;
+  if (q < 0 || q >= c->T1) return fail(c, STML_EINVAL, "q %d out of range", q);
+  const std::vector<int>& Kq = c->K[q];
+  for (int i = 0; i < (int)Kq.size() && i < cap; ++i) out[i] = Kq[i];
+  return (int)Kq.size();
+}
+
+int stml_predict(stml_ctx* c, int level, int q_next) {
+  if (!c) return STML_EINVAL;
+  int rc = check_level(c, level);
+  if (rc) return rc;
+  if (q_next < 0 || q_next >= c->T1)
+    return fail(c, STML_EINVAL, "q_next %d out of range", q_next);
+  if (!c->have_seq) return fail(c, STML_ESTATE, "no sequence");
+  return do_predict(c, level, q_next);
+}
+
+int stml_register_level(stml_ctx* c, int level, int q) {
+  if (!c) return STML_EINVAL;
+  int rc = check_level(c, level);
+  if (rc) return rc;
+  if (q < 0 || q >= c->T1) return fail(c, STML_EINVAL, "q %d out of range", q);
+  if (!c->have_seq) return fail(c, STML_ESTATE, "no sequence");
+  return do_register(c, level, q);
+}
+
+int stml_correct(stml_ctx* c, int level, int q_next) {
+  return stml_register_level(c, level, q_next);
+}
+
+int stml_run(stml_ctx* c) {
+  if (!c) return STML_EINVAL;
+  if (!c->have_seq) return fail(c, STML_ESTATE, "no sequence");
+  const int T = c->T1 - 1;
+  const bool eq3 = c->o.eps_stop > 0 && !c->o.parity_mode;
+  int warn = STML_OK;
+  for (int level = 0; level < c->L; ++level) {
+    int rc = do_predict(c, level, 0);
+    if (rc < 0) return rc;
+    rc = do_register(c, level, 0);
+    if (rc < 0) return rc;
+    if (rc > 0) warn = rc;
+    bool have_prev = false;
+    double D_prev = 0.0;
+    const size_t cnt = (size_t)c->n * c->d * c->N[level];
+    for (int q = 0; q < T; ++q) {
+      LevelBufs& b = c->lv[level];
+      if (eq3) {
+        // keep the registered frames of K_q for the all-frame estimate
+        HIP_OK(hipMemcpyAsync(c->x, b.Y, cnt * sizeof(float),
+                              hipMemcpyDeviceToDevice, c->stream));
+      }
+      rc = do_predict(c, level, q + 1);
+      if (rc < 0) return rc;
+      if (eq3) {
+        // estimate = prediction, with the frames of K_q as registered
+        HIP_OK(hipMemcpyAsync(c->r, b.Y, cnt * sizeof(float),
+                              hipMemcpyDeviceToDevice, c->stream));
+        size_t fr = (size_t)c->d * c->N[level];
+        for (int k : c->K[q])
+          HIP_OK(hipMemcpyAsync(c->r + k * fr, c->x + k * fr,
+                                fr * sizeof(float), hipMemcpyDeviceToDevice,
+                                c->stream));
+        double Dq;
+        rc = all_frame_D(c, level, c->r, &Dq);
+        if (rc) return rc;
+        if (have_prev && std::fabs(Dq - D_prev) <= c->o.eps_stop * std::fabs(Dq)) {
+          HIP_OK(hipMemcpyAsync(b.Y, c->r, cnt * sizeof(float),
+                                hipMemcpyDeviceToDevice, c->stream));
+          HIP_OK(hipStreamSynchronize(c->stream));
+          break;
+        }
+        D_prev = Dq;
+        have_prev = true;
+      }
+      rc = do_register(c, level, q + 1);
+      if (rc < 0) return rc;
+      if (rc > 0) warn = rc;
+    }
+  }
+  return warn;
+}
+
+static int copy_field(stml_ctx* c, int level, float* dst, const float* src) {
+  int rc = check_level(c, level);
+  if (rc) return rc;
+  if (!dst || !src) return fail(c, STML_EINVAL, "null pointer");
+  HIP_OK(hipMemcpyAsync(dst, src, (size_t)c->n * c->d * c->N[level] *
+                                      sizeof(float),
+                        hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  return STML_OK;
+}
+
+int stml_get_displacements(const stml_ctx* cc, int level, float* u) {
+  stml_ctx* c = const_cast<stml_ctx*>(cc);
+  if (!c) return STML_EINVAL;
+  if (check_level(c, level)) return STML_EINVAL;
+  return copy_field(c, level, u, c->lv[level].Y);
+}
+
+int stml_set_displacements(stml_ctx* c, int level, const float* u) {
+  if (!c) return STML_EINVAL;
+  if (check_level(c, level)) return STML_EINVAL;
+  return copy_field(c, level, c->lv[level].Y, u);
+}
+
+int stml_get_prediction(const stml_ctx* cc, int level, float* z) {
+  stml_ctx* c = const_cast<stml_ctx*>(cc);
+  if (!c) return STML_EINVAL;
+  if (check_level(c, level)) return STML_EINVAL;
+  return copy_field(c, level, z, c->lv[level].Z);
+}
+
+int stml_set_prediction(stml_ctx* c, int level, const float* z) {
+  if (!c) return STML_EINVAL;
+  if (check_level(c, level)) return STML_EINVAL;
+  return copy_field(c, level, c->lv[level].Z, z);
+}
+
+int stml_log_count(const stml_ctx* c) {
+  return c ? (int)c->logs.size() : STML_EINVAL;
+}
+
+int stml_get_log(const stml_ctx* c, int i, stml_gir_log* out) {
+  if (!c || !out || i < 0 || i >= (int)c->logs.size()) return STML_EINVAL;
+  *out = c->logs[i];
+  return STML_OK;
+}
+
+int stml_eval(stml_ctx* c, int level, const int* frames, int nk,
+              const float* u, double* out, float* grad, float* dW) {
+  if (!c) return STML_EINVAL;
+  int rc = check_level(c, level);
+  if (rc) return rc;
+  if (!c->have_seq) return fail(c, STML_ESTATE, "no sequence");
+  if (!u || !out) return fail(c, STML_EINVAL, "null pointer");
+  rc = stage_frames(c, frames, nk);
+  if (rc) return rc;
+  Geom g = geom_of(c, level);
+  Model md = model_of(c, level, nk);
+  HIP_OK(launch_eval(c->d, c->lv[level].T, u, c->kbuf, g, md,
+                     grad ? grad : c->g, dW ? dW : c->dW, c->rb, c->sc,
+                     c->stream));
+  rc = read_scal(c);
+  if (rc) return rc;
+  out[0] = c->hsc->J;
+  out[1] = c->hsc->D;
+  out[2] = c->hsc->S;
+  out[3] = c->hsc->P;
+  return STML_OK;
+}
+
+int stml_hessvec(stml_ctx* c, int level, const int* frames, int nk,
+                 const float* u, const float* v, float* hv, double* vHv) {
+  if (!c) return STML_EINVAL;
+  int rc = check_level(c, level);
+  if (rc) return rc;
+  if (!c->have_seq) return fail(c, STML_ESTATE, "no sequence");
+  if (!u || !v || !hv) return fail(c, STML_EINVAL, "null pointer");
+  rc = stage_frames(c, frames, nk);
+  if (rc) return rc;
+  Geom g = geom_of(c, level);
+  Model md = model_of(c, level, nk);
+  HIP_OK(launch_eval(c->d, c->lv[level].T, u, c->kbuf, g, md, c->g, c->dW,
+                     c->rb, c->sc, c->stream));
+  TIMED(STML_K_HESSVEC, level, (double)nk * g.N,
+        launch_hessvec(c->d, v, c->dW, g, md, hv, c->rb, c->sc, c->stream));
+  rc = read_scal(c);
+  if (rc) return rc;
+  if (vHv) *vHv = c->hsc->vHv;
+  return STML_OK;
+}
+
+int stml_gn_direction(stml_ctx* c, int level, const int* frames, int nk,
+                      const float* u, float* delta, int* out_cg) {
+  if (!c) return STML_EINVAL;
+  int rc = check_level(c, level);
+  if (rc) return rc;
+  if (!c->have_seq) return fail(c, STML_ESTATE, "no sequence");
+  if (!u || !delta) return fail(c, STML_EINVAL, "null pointer");
+  rc = stage_frames(c, frames, nk);
+  if (rc) return rc;
+  Geom g = geom_of(c, level);
+  Model md = model_of(c, level, nk);
+  HIP_OK(launch_eval(c->d, c->lv[level].T, u, c->kbuf, g, md, c->g, c->dW,
+                     c->rb, c->sc, c->stream));
+  rc = enqueue_pcg(c, level, g, md);
+  if (rc) return rc;
+  HIP_OK(hipMemcpyAsync(delta, c->x, (size_t)nk * c->d * g.N * sizeof(float),
+                        hipMemcpyDeviceToDevice, c->stream));
+  rc = read_scal(c);
+  if (rc) return rc;
+  if (out_cg) *out_cg = c->hsc->iters;
+  if (c->hsc->done == 2) return fail(c, STML_EBREAKDOWN, "CG breakdown");
+  return STML_OK;
+}
+
+int stml_timing(stml_ctx* c, int on) {
+  if (!c) return STML_EINVAL;
+  HIP_OK(hipStreamSynchronize(c->stream));
+  tresolve(c);
+  if (on) c->kstats.clear();
+  c->timing = on != 0;
+  return STML_OK;
+}
+
+int stml_timing_get(stml_ctx* c, int kernel, int level, double* ms,
+                    long long* n, double* vf) {
+  if (!c || kernel < 0 || kernel >= STML_K_COUNT) return STML_EINVAL;
+  HIP_OK(hipStreamSynchronize(c->stream));
+  tresolve(c);
+  double tms = 0.0, tvf = 0.0;
+  long long tn = 0;
+  for (auto& kv : c->kstats) {
+    if (kv.first.first != kernel) continue;
+    if (level >= 0 && kv.first.second != level) continue;
+    tms += kv.second.ms;
+    tvf += kv.second.vf;
+    tn += kv.second.n;
+  }
+  if (ms) *ms = tms;
+  if (n) *n = tn;
+  if (vf) *vf = tvf;
+  return STML_OK;
+}
+
+}  // extern "C"

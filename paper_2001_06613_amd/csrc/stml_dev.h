@@ -1,0 +1,351 @@
+// Device-side shared definitions for the STML kernels (gfx950, wave64).
+//
+// Layout in HBM: images [n][N], displacement-like fields [frames][D][N],
+// N = voxels of one level, last axis fastest.  Compact solver vectors hold
+// the |K| frames of the subset being registered, in the order of K.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace stml {
+
+constexpr int kWave = 64;          // CDNA wavefront
+constexpr int kMaxFPT = 16;        // max frames one thread keeps in registers
+constexpr int kMaxChunks = 16;     // waves per block -> |K| <= 256
+constexpr int kTrialSteps = 5;     // Armijo steps evaluated per pass
+constexpr int kXCD = 8;            // MI355X: 8 accelerator complex dies
+constexpr int kMaxTileBlocks = 2048;
+constexpr int kMaxElemBlocks = 2048;
+
+// Level geometry.  D = 2 uses m[0] (slow) and m[1] (fast); D = 3 uses all.
+struct Geom {
+  int m[3];
+  long long s[3];      // strides (elements) of each axis
+  long long N;         // voxels
+  double inv_h;        // 1 / cell width (finest-pixel units)
+};
+
+// Constants of the model on one level and subset.
+struct Model {
+  double hd;           // h^D
+  double data_c;       // 2 h^D
+  double mdiag_c;      // 2 h^D (1 - 1/|K|)
+  double alpha_hd;     // alpha h^D
+  double half_alpha_hd;
+  double lam_hd;       // lambda h^D
+  double lam_c;        // 2 lambda h^D / |K|
+  double pen_diag;     // 2 lambda h^D / |K|^2
+  double reg_scale;    // 1/h^2 (diffusion) or 1/h^4 (curvature)
+  double inv_nK;
+  int reg;             // 0 diffusion, 1 curvature
+  int nK;
+};
+
+// Device-resident scalars of one Gauss-Newton step.  Written only by the
+// last block of a kernel, read by later kernels.
+struct Scal {
+  double J, D, S, P;          // objective at the evaluation point
+  double rz, r0, a, beta;     // CG scalars
+  double pq, rr;
+  double Jt[8];               // objective at the trial steps
+  double slope;               // g . delta
+  double maxd;                // max |delta|
+  double vHv;
+  int done;                   // 0 running, 1 converged, 2 breakdown
+  int iters;                  // CG iterations taken
+  int bad;                    // non-finite input count
+  int pad;
+};
+
+// ---------------------------------------------------------------- helpers
+
+// Voxel coordinates and its index inside one [N] plane.  Planes hold at
+// most 2^30 voxels, so in-plane offsets are 32-bit: loads then use a
+// wave-uniform plane base (scalar registers) plus a 32-bit lane offset.
+template <int D>
+struct Pos {
+  int c[D];
+  unsigned idx;
+};
+
+template <int D>
+__device__ __forceinline__ Pos<D> make_pos(const Geom& g, long long x) {
+  Pos<D> p;
+  p.idx = (unsigned)x;
+  if (D == 2) {
+    int c0 = (int)(x / g.m[1]);
+    p.c[0] = c0;
+    p.c[1] = (int)(x - (long long)c0 * g.m[1]);
+  } else {
+    long long plane = (long long)g.m[1] * g.m[2];
+    int c0 = (int)(x / plane);
+    long long rem = x - (long long)c0 * plane;
+    int c1 = (int)(rem / g.m[2]);
+    p.c[0] = c0;
+    p.c[1] = c1;
+    p.c[D - 1] = (int)(rem - (long long)c1 * g.m[2]);
+  }
+  return p;
+}
+
+// Regulariser stencils.  Neighbours outside the grid are replaced by the
+// voxel itself (replicate padding), which turns the plain Laplacian into the
+// Neumann graph Laplacian L.  All arithmetic is float64 on float32 loads.
+
+// Offsets (in elements) of the clamped neighbours at -2, -1, +1, +2 along
+// every axis, and whether the -1 / +1 neighbour exists.
+template <int D>
+struct Nbr {
+  int m1[D], p1[D], m2[D], p2[D];
+  bool hm[D], hp[D];
+};
+
+template <int D>
+__device__ __forceinline__ Nbr<D> neighbours(const Pos<D>& p, const Geom& g) {
+  Nbr<D> n;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int c = p.c[a], m = g.m[a];
+    int s = (int)g.s[a];
+    n.hm[a] = c > 0;
+    n.hp[a] = c < m - 1;
+    n.m1[a] = n.hm[a] ? -s : 0;
+    n.p1[a] = n.hp[a] ? s : 0;
+    n.m2[a] = c >= 2 ? -2 * s : n.m1[a];
+    n.p2[a] = c <= m - 3 ? 2 * s : n.p1[a];
+  }
+  return n;
+}
+
+// (L v)(x) from the 2D face neighbours.
+template <int D>
+__device__ __forceinline__ double lap_c(const float* __restrict__ v,
+                                        unsigned idx, const Nbr<D>& nb) {
+  double c = (double)v[idx];
+  double s = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+    s += ((double)v[idx + nb.m1[a]] - c) + ((double)v[idx + nb.p1[a]] - c);
+  return s;
+}
+
+// B^T B v at p (without the 1/h^2 or 1/h^4 factor) and this voxel's share
+// of ||B v||^2: diffusion -> (-L v, forward-face differences squared);
+// curvature -> (L (L v), (L v)^2), L(Lv) from 1 + 4D + 2D(D-1) loads.
+template <int D>
+__device__ __forceinline__ void reg_terms(const float* __restrict__ v,
+                                          const Pos<D>& p, const Geom& g,
+                                          int reg, double& btb,
+                                          double& energy) {
+  const Nbr<D> nb = neighbours<D>(p, g);
+  const unsigned i = p.idx;
+  const double c = (double)v[i];
+  double vm[D], vp[D], Lc = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    vm[a] = (double)v[i + nb.m1[a]];
+    vp[a] = (double)v[i + nb.p1[a]];
+    Lc += (vm[a] - c) + (vp[a] - c);
+  }
+  if (reg == 0) {
+    double e = 0.0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) e += (vp[a] - c) * (vp[a] - c);
+    btb = -Lc;
+    energy = e;
+    return;
+  }
+  // diagonal neighbours c + sa e_a + sb e_b (a < b), clamped per axis
+  double dg[D][2][D][2];
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int b = a + 1; b < D; ++b)
+#pragma unroll
+      for (int sa = 0; sa < 2; ++sa)
+#pragma unroll
+        for (int sb = 0; sb < 2; ++sb) {
+          int o = (sa ? nb.p1[a] : nb.m1[a]) + (sb ? nb.p1[b] : nb.m1[b]);
+          double val = (double)v[i + o];
+          dg[a][sa][b][sb] = val;
+          dg[b][sb][a][sa] = val;
+        }
+  double LL = 0.0;
+#pragma unroll
+  for (int a = 0; a < D; ++a)
+#pragma unroll
+    for (int sa = 0; sa < 2; ++sa) {
+      bool has = sa ? nb.hp[a] : nb.hm[a];
+      double vn = sa ? vp[a] : vm[a];
+      double far = (double)v[i + (sa ? nb.p2[a] : nb.m2[a])];
+      double Ln = (far - vn) + (c - vn);
+#pragma unroll
+      for (int b = 0; b < D; ++b) {
+        if (b == a) continue;
+        Ln += (dg[a][sa][b][0] - vn) + (dg[a][sa][b][1] - vn);
+      }
+      LL += has ? (Ln - Lc) : 0.0;
+    }
+  btb = LL;
+  energy = Lc * Lc;
+}
+
+// Shares of ||B u||^2, <B u, B w>, ||B w||^2 at p (quadratic expansion of S).
+template <int D>
+__device__ __forceinline__ void reg_cross(const float* __restrict__ u,
+                                          const float* __restrict__ w,
+                                          const Pos<D>& p, const Geom& g,
+                                          int reg, double& uu, double& uw,
+                                          double& ww) {
+  const Nbr<D> nb = neighbours<D>(p, g);
+  const unsigned i = p.idx;
+  if (reg == 0) {
+    double cu = (double)u[i], cw = (double)w[i];
+    double a_uu = 0, a_uw = 0, a_ww = 0;
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      double du = (double)u[i + nb.p1[a]] - cu;
+      double dw = (double)w[i + nb.p1[a]] - cw;
+      a_uu += du * du;
+      a_uw += du * dw;
+      a_ww += dw * dw;
+    }
+    uu = a_uu;
+    uw = a_uw;
+    ww = a_ww;
+  } else {
+    double lu = lap_c<D>(u, i, nb);
+    double lw = lap_c<D>(w, i, nb);
+    uu = lu * lu;
+    uw = lu * lw;
+    ww = lw * lw;
+  }
+}
+
+// diag(B^T B) at p (unscaled).
+template <int D>
+__device__ __forceinline__ double reg_diag_at(const Pos<D>& p, const Geom& g,
+                                              int reg) {
+  int deg = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    deg += (p.c[a] > 0) + (p.c[a] < g.m[a] - 1);
+  }
+  double dd = (double)deg;
+  return reg == 0 ? dd : dd * dd + dd;
+}
+
+// Bi/trilinear sample of one frame at x + u(x) with d/du, float64.
+template <int D>
+__device__ __forceinline__ void warp_sample(const float* __restrict__ T,
+                                            const Geom& g, const Pos<D>& p,
+                                            const double* uv, double& W,
+                                            double* dW) {
+  int i0[D], i1[D];
+  double f[D];
+  bool inside[D];
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    int m = g.m[a];
+    double q = (double)p.c[a] + uv[a] * g.inv_h;
+    inside[a] = (q >= 0.0) && (q <= (double)(m - 1));
+    double qc = fmin(fmax(q, 0.0), (double)(m - 1));
+    if (m >= 2) {
+      int fl = (int)floor(qc);
+      i0[a] = fl < m - 2 ? fl : m - 2;
+      f[a] = qc - (double)i0[a];
+      i1[a] = i0[a] + 1;
+    } else {
+      i0[a] = 0;
+      i1[a] = 0;
+      f[a] = 0.0;
+    }
+  }
+  if (D == 2) {
+    unsigned r0 = (unsigned)i0[0] * (unsigned)g.s[0];
+    unsigned r1 = (unsigned)i1[0] * (unsigned)g.s[0];
+    double t00 = T[r0 + i0[1]], t01 = T[r0 + i1[1]];
+    double t10 = T[r1 + i0[1]], t11 = T[r1 + i1[1]];
+    double a0 = (1.0 - f[1]) * t00 + f[1] * t01;   // row i0
+    double a1 = (1.0 - f[1]) * t10 + f[1] * t11;   // row i1
+    double b0 = (1.0 - f[0]) * t00 + f[0] * t10;   // column i0
+    double b1 = (1.0 - f[0]) * t01 + f[0] * t11;   // column i1
+    W = (1.0 - f[0]) * a0 + f[0] * a1;
+    dW[0] = inside[0] ? (a1 - a0) * g.inv_h : 0.0;
+    dW[1] = inside[1] ? (b1 - b0) * g.inv_h : 0.0;
+  } else {
+    double t[2][2][2];
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          unsigned o = (unsigned)(z ? i1[0] : i0[0]) * (unsigned)g.s[0] +
+                       (unsigned)(y ? i1[1] : i0[1]) * (unsigned)g.s[1] +
+                       (unsigned)(x ? i1[2] : i0[2]);
+          t[z][y][x] = T[o];
+        }
+    double w0[2] = {1.0 - f[0], f[0]};
+    double w1[2] = {1.0 - f[1], f[1]};
+    double w2[2] = {1.0 - f[2], f[2]};
+    double val = 0.0, d0 = 0.0, d1 = 0.0, d2 = 0.0;
+#pragma unroll
+    for (int z = 0; z < 2; ++z)
+#pragma unroll
+      for (int y = 0; y < 2; ++y)
+#pragma unroll
+        for (int x = 0; x < 2; ++x) {
+          double tv = t[z][y][x];
+          val += w0[z] * w1[y] * w2[x] * tv;
+          d0 += (z ? 1.0 : -1.0) * w1[y] * w2[x] * tv;
+          d1 += (y ? 1.0 : -1.0) * w0[z] * w2[x] * tv;
+          d2 += (x ? 1.0 : -1.0) * w0[z] * w1[y] * tv;
+        }
+    W = val;
+    dW[0] = inside[0] ? d0 * g.inv_h : 0.0;
+    dW[1] = inside[1] ? d1 * g.inv_h : 0.0;
+    dW[2] = inside[2] ? d2 * g.inv_h : 0.0;
+  }
+}
+
+// Value only (trial evaluations).
+template <int D>
+__device__ __forceinline__ double warp_value(const float* __restrict__ T,
+                                             const Geom& g, const Pos<D>& p,
+                                             const double* uv) {
+  double W, dW[D];
+  warp_sample<D>(T, g, p, uv, W, dW);
+  return W;
+}
+
+// Wave-level sum (butterfly, fixed order -> deterministic).
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
+  return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
+  return v;
+}
+
+// Tile index of the i-th tile a block processes.  Blocks are dealt to the 8
+// XCDs round-robin by the hardware; this gives every XCD one contiguous
+// range of tiles so that stencil neighbours share that XCD's L2.
+__device__ __forceinline__ long long xcd_tile(long long ntiles, int i) {
+  int b = blockIdx.x;
+  int nb = gridDim.x;            // a multiple of kXCD
+  int xcd = b % kXCD;
+  int local = b / kXCD;
+  int per_xcd_blocks = nb / kXCD;
+  long long lo = ntiles * xcd / kXCD;
+  long long hi = ntiles * (xcd + 1) / kXCD;
+  long long t = lo + local + (long long)i * per_xcd_blocks;
+  return t < hi ? t : -1;
+}
+
+}  // namespace stml
