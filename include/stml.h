@@ -195,11 +195,11 @@ int stml_gn_direction(stml_ctx* ctx, int level, const int* frames, int nk,
                       const float* u_dev, float* delta_dev, int* out_cg);
 
 /* --- kernel timing (measurement only) -----------------------------------
- * With timing on, each launch of the kernel classes below on the context's
- * stream is bracketed by two HIP events; durations, launch counts and the
- * voxel-frames each launch covers (|K| x voxels of the level, or n x voxels
- * for whole-sequence kernels) accumulate per (class, level) until the next
- * stml_timing(ctx, 1).  Timing adds two event records per launch. */
+ * Each launch of a timed kernel class on the context's stream is bracketed
+ * by two HIP events; durations, launch counts and the voxel-frames each
+ * launch covers (|K| x voxels of the level, or n x voxels for
+ * whole-sequence kernels) accumulate per (class, level).  Timing adds two
+ * event records per timed launch. */
 #define STML_K_EVAL        0  /* warp + distance + gradient                 */
 #define STML_K_HESSVEC     1  /* Gauss-Newton Hessian product (CG and test)  */
 #define STML_K_CG_UPDATE   2  /* x, r, z update and r.z                      */
@@ -210,12 +210,17 @@ int stml_gn_direction(stml_ctx* ctx, int level, const int* frames, int nk,
 #define STML_K_PREDICT     7  /* prolongation and temporal predictors        */
 #define STML_K_RESTRICT    8  /* spatial restriction                         */
 #define STML_K_COUNT       9
+#define STML_K_ALL       0x1ff  /* mask of every class                     */
 
-/* on = 1: clear the accumulators and start timing; on = 0: stop. */
-int stml_timing(stml_ctx* ctx, int on);
-/* Totals of one kernel class at one level (level = -1: all levels). */
+/* mask != 0: clear the accumulators and time the classes whose bit
+ * (1 << STML_K_...) is set; mask = 0: stop timing. */
+int stml_timing(stml_ctx* ctx, int mask);
+/* Totals of one kernel class at one level (level = -1: all levels):
+ * time, launches, voxel-frames, and algorithmic HBM bytes (every input
+ * field read once, every output field written once, float32). */
 int stml_timing_get(stml_ctx* ctx, int kernel, int level, double* total_ms,
-                    long long* launches, double* voxel_frames);
+                    long long* launches, double* voxel_frames,
+                    double* bytes);
 
 #ifdef __cplusplus
 }

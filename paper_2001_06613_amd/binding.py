@@ -96,8 +96,8 @@ SIGNATURES = {
     "stml_hessvec": (_I, [_P, _I, _IP, _I, _P, _P, _P, _DP]),
     "stml_gn_direction": (_I, [_P, _I, _IP, _I, _P, _P, _IP]),
     "stml_timing": (_I, [_P, _I]),
-    "stml_timing_get": (_I, [_P, _I, _I, _DP, ctypes.POINTER(ctypes.c_longlong),
-                             _DP]),
+    "stml_timing_get": (_I, [_P, _I, _I, _DP,
+                             ctypes.POINTER(ctypes.c_longlong), _DP, _DP]),
 }
 
 KERNELS = {"eval": 0, "hessvec": 1, "cg_update": 2, "cg_pupdate": 3,
@@ -303,17 +303,30 @@ class STML:
                         "steps": list(lg.step[:max(it, 0)])})
         return out
 
-    def timing(self, on):
-        return self._check(self.lib.stml_timing(self.ctx, int(bool(on))))
+    def timing(self, kernels):
+        """Start timing the named kernel classes (True: all), or stop (None,
+        False or an empty list)."""
+        if kernels is True:
+            mask = (1 << len(KERNELS)) - 1
+        elif not kernels:
+            mask = 0
+        else:
+            mask = 0
+            for k in kernels:
+                mask |= 1 << KERNELS[k]
+        return self._check(self.lib.stml_timing(self.ctx, mask))
 
     def timing_get(self, kernel, level=-1):
         ms = ctypes.c_double()
         n = ctypes.c_longlong()
         vf = ctypes.c_double()
+        nbytes = ctypes.c_double()
         self._check(self.lib.stml_timing_get(self.ctx, KERNELS[kernel], level,
                                              ctypes.byref(ms), ctypes.byref(n),
-                                             ctypes.byref(vf)))
-        return {"ms": ms.value, "launches": n.value, "voxel_frames": vf.value}
+                                             ctypes.byref(vf),
+                                             ctypes.byref(nbytes)))
+        return {"ms": ms.value, "launches": n.value, "voxel_frames": vf.value,
+                "bytes": nbytes.value}
 
     def eval(self, level, frames, u, want_grad=True):
         """Objective {J, D, S, P}, gradient and dW/du at u (all frames)."""

@@ -1,0 +1,472 @@
+// Conjugate-gradient kernels of the Gauss-Newton step for 2-D sequences.
+//
+// The Gauss-Newton Hessian couples the frames of a voxel only through two
+// per-voxel sums, S = sum_k dW_k . v_k and V = sum_k v_k.  The CG direction
+// is p = z + beta p_old, so S and V of p follow from those of z (summed
+// by the kernel that writes z) and of p_old (kept from the previous
+// product): S_p = S_z + beta S_pold.  The Hessian product therefore needs
+// no sweep over frames and runs as a plain stencil kernel, parallel over
+// (frame, spatial tile): each block stages p = z + beta p_old of a 64 x 4
+// tile with a 2-cell halo in LDS, forms L p once per point and L (L p) from
+// LDS.  The vector updates are voxel-major (the waves of a block split the
+// frames of a 64-voxel tile) so that they can sum S_z and V_z per voxel; the
+// Jacobi diagonal is recomputed there from dW/du instead of being stored.
+#include <math.h>
+
+#include "launch.h"
+#include "reduce.h"
+
+namespace stml {
+
+constexpr int kTX = 64;            // tile width (x, fastest axis)
+constexpr int kTY = 4;             // tile height (y)
+constexpr int kHX = kTX + 4;       // with a 2-cell halo
+constexpr int kHY = kTY + 4;
+constexpr int kLX = kTX + 2;       // L p on a 1-cell halo
+constexpr int kLY = kTY + 2;
+constexpr int kCgMaxBlocks = 2048;
+
+// Frames of a voxel-major tile handled by this wave.
+__device__ __forceinline__ void wave_frames(int nK, int& j0, int& j1) {
+  int G = blockDim.x / kWave;
+  int w = wave_id();
+  int per = (nK + G - 1) / G;
+  j0 = w * per;
+  j1 = j0 + per < nK ? j0 + per : nK;
+}
+
+// Jacobi diagonal factor of voxel p without the data term.
+template <int D>
+__device__ __forceinline__ double jacobi_rest(const Pos<D>& p, const Geom& g,
+                                              const Model& md) {
+  return md.alpha_hd * md.reg_scale * reg_diag_at<D>(p, g, md.reg) +
+         md.pen_diag;
+}
+
+// Combine the per-wave sums of S (1) and V (D) of every voxel of the tile
+// and store them (float64).
+template <int D>
+__device__ __forceinline__ void store_voxel_sums(double s, const double* v,
+                                                 long long x, bool valid,
+                                                 long long N,
+                                                 double* __restrict__ S,
+                                                 double* __restrict__ V) {
+  __shared__ double xs[kMaxChunks][kWave][1 + D];
+  const int lane = threadIdx.x & (kWave - 1);
+  const int w = wave_id();
+  const int G = blockDim.x / kWave;
+  xs[w][lane][0] = s;
+#pragma unroll
+  for (int a = 0; a < D; ++a) xs[w][lane][1 + a] = v[a];
+  __syncthreads();
+  if (w == 0 && valid) {
+    double ts = 0.0, tv[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) tv[a] = 0.0;
+    for (int c = 0; c < G; ++c) {
+      ts += xs[c][lane][0];
+#pragma unroll
+      for (int a = 0; a < D; ++a) tv[a] += xs[c][lane][1 + a];
+    }
+    S[x] = ts;
+#pragma unroll
+    for (int a = 0; a < D; ++a) V[(size_t)a * N + x] = tv[a];
+  }
+  __syncthreads();
+}
+
+// CG start: r = -g, z = M^-1 r; per-voxel S_z, V_z; partials of r.z, r.r.
+template <int D>
+__global__ __launch_bounds__(1024) void cgv_init_kernel(
+    const float* __restrict__ grad, const float* __restrict__ dW, Geom g,
+    Model md, float* __restrict__ r, float* __restrict__ z,
+    double* __restrict__ Sz, double* __restrict__ Vz,
+    double* __restrict__ part, int gn_it, const Scal* __restrict__ sc) {
+  if (gn_it >= sc->gn_stop) return;
+  int j0, j1;
+  wave_frames(md.nK, j0, j1);
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long N = g.N;
+  const long long ntiles = (N + kWave - 1) / kWave;
+  double rz = 0.0, rr = 0.0;
+  for (int it = 0;; ++it) {
+    long long tile = xcd_tile(ntiles, it);
+    if (tile < 0) break;
+    long long x = tile * kWave + lane;
+    bool valid = x < N;
+    Pos<D> pos = make_pos<D>(g, valid ? x : N - 1);
+    const double rest = jacobi_rest<D>(pos, g, md);
+    double s = 0.0, v[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] = 0.0;
+    if (valid) {
+      for (int j = j0; j < j1; ++j) {
+        const size_t base = (size_t)j * D * N + pos.idx;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          size_t o = base + (size_t)a * N;
+          double d = (double)dW[o];
+          float rv = -grad[o];
+          float zv = (float)((double)rv / (md.mdiag_c * d * d + rest));
+          r[o] = rv;
+          z[o] = zv;
+          rz += (double)rv * (double)zv;
+          rr += (double)rv * (double)rv;
+          s += d * (double)zv;
+          v[a] += (double)zv;
+        }
+      }
+    }
+    store_voxel_sums<D>(s, v, x, valid, N, Sz, Vz);
+  }
+  double vals[2] = {rz, rr};
+  block_partials<2>(vals, 0u, part);
+}
+
+// CG step, part 2: a = rz / p.q (stop on p.q <= 0); x += a p (x = a p at
+// it = 0), r -= a q, z = M^-1 r; per-voxel S_z, V_z; partials r.z, r.r.
+template <int D>
+__global__ __launch_bounds__(1024) void cgv_update_kernel(
+    int it, const float* __restrict__ p, const float* __restrict__ q,
+    const float* __restrict__ dW, Geom g, Model md, float* __restrict__ x,
+    float* __restrict__ r, float* __restrict__ z, double* __restrict__ Sz,
+    double* __restrict__ Vz, const double* __restrict__ hv_part, int hv_nb,
+    double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
+  if (sc->done || gn_it >= sc->gn_stop) return;
+  double t[1];
+  reduce_partials<1>(hv_part, hv_nb, 0u, t);
+  const double pq = t[0];
+  if (!(pq > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->pq = pq;
+      sc->done = 2;
+    }
+    return;
+  }
+  const double alpha = sc->rzh[it & 1] / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->pq = pq;
+    sc->a = alpha;
+    sc->iters = it + 1;
+  }
+  int j0, j1;
+  wave_frames(md.nK, j0, j1);
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long N = g.N;
+  const long long ntiles = (N + kWave - 1) / kWave;
+  double rz = 0.0, rr = 0.0;
+  for (int tt = 0;; ++tt) {
+    long long tile = xcd_tile(ntiles, tt);
+    if (tile < 0) break;
+    long long xv = tile * kWave + lane;
+    bool valid = xv < N;
+    Pos<D> pos = make_pos<D>(g, valid ? xv : N - 1);
+    const double rest = jacobi_rest<D>(pos, g, md);
+    double s = 0.0, v[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) v[a] = 0.0;
+    if (valid) {
+#pragma unroll 2
+      for (int j = j0; j < j1; ++j) {
+        const size_t base = (size_t)j * D * N + pos.idx;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          size_t o = base + (size_t)a * N;
+          double pe = (double)p[o];
+          double d = (double)dW[o];
+          float xn = it == 0 ? (float)(alpha * pe)
+                             : (float)((double)x[o] + alpha * pe);
+          float rv = (float)((double)r[o] - alpha * (double)q[o]);
+          float zv = (float)((double)rv / (md.mdiag_c * d * d + rest));
+          x[o] = xn;
+          r[o] = rv;
+          z[o] = zv;
+          rz += (double)rv * (double)zv;
+          rr += (double)rv * (double)rv;
+          s += d * (double)zv;
+          v[a] += (double)zv;
+        }
+      }
+    }
+    store_voxel_sums<D>(s, v, xv, valid, N, Sz, Vz);
+  }
+  double vals[2] = {rz, rr};
+  block_partials<2>(vals, 0u, part);
+}
+
+// Per-voxel S and V of a stored field v (Hessian product test entry).
+template <int D>
+__global__ __launch_bounds__(1024) void cgv_sums_kernel(
+    const float* __restrict__ v, const float* __restrict__ dW, Geom g,
+    Model md, double* __restrict__ S, double* __restrict__ V) {
+  int j0, j1;
+  wave_frames(md.nK, j0, j1);
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long N = g.N;
+  const long long ntiles = (N + kWave - 1) / kWave;
+  for (int it = 0;; ++it) {
+    long long tile = xcd_tile(ntiles, it);
+    if (tile < 0) break;
+    long long x = tile * kWave + lane;
+    bool valid = x < N;
+    double s = 0.0, vs[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) vs[a] = 0.0;
+    if (valid) {
+      for (int j = j0; j < j1; ++j) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          size_t o = ((size_t)j * D + a) * N + x;
+          double vv = (double)v[o];
+          s += (double)dW[o] * vv;
+          vs[a] += vv;
+        }
+      }
+    }
+    store_voxel_sums<D>(s, vs, x, valid, N, S, V);
+  }
+}
+
+// Hessian product on p = z + beta p_old (it > 0) or p = z (it = 0) for one
+// 64 x 4 tile of a group of frames; stores p and q = H p, partial p.q.
+// For it > 0 it first finishes the previous update: beta and the
+// convergence test from the update's partials.
+template <int REG>
+__global__ __launch_bounds__(256) void cgt_hvp2_kernel(
+    int it, const float* __restrict__ zv, const float* __restrict__ p_old,
+    float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
+    Model md, float* __restrict__ q, const double* __restrict__ Sz,
+    const double* __restrict__ Vz, const double* __restrict__ Sp_old,
+    const double* __restrict__ Vp_old, double* __restrict__ Sp_new,
+    double* __restrict__ Vp_new, int nreal, int nfg, int fpg,
+    const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
+    double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
+  constexpr int D = 2;
+  __shared__ double P[D][kHY][kHX];
+  __shared__ double L[REG ? D : 1][REG ? kLY : 1][REG ? kLX : 1];
+  if (sc->done || gn_it >= sc->gn_stop) return;
+  double beta = 0.0;
+  if (it > 0) {
+    double t[2];
+    reduce_partials<2>(up_part, up_nb, 0u, t);
+    const double rz_old = sc->rzh[(it - 1) & 1];
+    bool conv = (!fixed && sqrt(t[1]) <= rtol * sc->r0) || t[0] == 0.0;
+    if (conv) {
+      if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 1;
+      return;
+    }
+    beta = t[0] / rz_old;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->rzh[it & 1] = t[0];
+      sc->rr = t[1];
+      sc->beta = beta;
+    }
+  }
+  const float bf = (float)beta;
+  // block -> (tile, frame group), XCD-chunked
+  const int per_xcd = gridDim.x / kXCD;
+  const int bb = (blockIdx.x % kXCD) * per_xcd + blockIdx.x / kXCD;
+  double acc = 0.0;
+  if (bb < nreal) {
+    const int m0 = g.m[0], m1 = g.m[1];
+    const long long N = g.N;
+    const int tile = bb / nfg, fg = bb - (bb / nfg) * nfg;
+    const int ntx = (m1 + kTX - 1) / kTX;
+    const int y0 = (tile / ntx) * kTY, x0 = (tile % ntx) * kTX;
+    const int ty = threadIdx.x / kTX, tx = threadIdx.x % kTX;
+    const int y = y0 + ty, xx = x0 + tx;
+    const bool valid = y < m0 && xx < m1;
+    const unsigned vox = valid ? (unsigned)(y * m1 + xx) : 0u;
+    double sbar = 0.0, vbar[D] = {0.0, 0.0};
+    if (valid) {
+      double S = Sz[vox], V0 = Vz[vox], V1 = Vz[N + vox];
+      if (it > 0) {
+        S += beta * Sp_old[vox];
+        V0 += beta * Vp_old[vox];
+        V1 += beta * Vp_old[N + vox];
+      }
+      if (fg == 0) {
+        Sp_new[vox] = S;
+        Vp_new[vox] = V0;
+        Vp_new[N + vox] = V1;
+      }
+      sbar = S * md.inv_nK;
+      vbar[0] = V0 * md.inv_nK;
+      vbar[1] = V1 * md.inv_nK;
+    }
+    const int jbeg = fg * fpg;
+    const int jend = jbeg + fpg < md.nK ? jbeg + fpg : md.nK;
+    for (int j = jbeg; j < jend; ++j) {
+      // stage p (replicate padding at the grid edge = clamped loads)
+      for (int i = threadIdx.x; i < kHY * kHX; i += blockDim.x) {
+        int hy = i / kHX, hx = i - (i / kHX) * kHX;
+        int gy = min(max(y0 - 2 + hy, 0), m0 - 1);
+        int gx = min(max(x0 - 2 + hx, 0), m1 - 1);
+        unsigned o = (unsigned)(gy * m1 + gx);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          size_t plane = ((size_t)j * D + a) * N;
+          float pv = it > 0 ? __builtin_fmaf(bf, p_old[plane + o], zv[plane + o])
+                            : zv[plane + o];
+          P[a][hy][hx] = (double)pv;
+        }
+      }
+      __syncthreads();
+      if (REG) {
+        // L p on the 1-cell halo; outside the grid it replicates the edge
+        for (int i = threadIdx.x; i < kLY * kLX; i += blockDim.x) {
+          int ly = i / kLX, lx = i - (i / kLX) * kLX;
+          int gy = min(max(y0 - 1 + ly, 0), m0 - 1);
+          int gx = min(max(x0 - 1 + lx, 0), m1 - 1);
+          int cy = gy - y0 + 2, cx = gx - x0 + 2;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            double c = P[a][cy][cx];
+            L[a][ly][lx] = (P[a][cy - 1][cx] - c) + (P[a][cy + 1][cx] - c) +
+                           (P[a][cy][cx - 1] - c) + (P[a][cy][cx + 1] - c);
+          }
+        }
+        __syncthreads();
+      }
+      if (valid) {
+        const int py = ty + 2, px = tx + 2;
+        double pc[D], d[D], s = 0.0;
+        const size_t jb = (size_t)j * D * N + vox;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          pc[a] = P[a][py][px];
+          d[a] = (double)dW[jb + (size_t)a * N];
+          s += d[a] * pc[a];
+        }
+        const double ds = md.data_c * (s - sbar);
+        // neighbours that leave the grid replicate this voxel: zero terms
+        const bool hn = y > 0, hs = y < m0 - 1, hw = xx > 0, he = xx < m1 - 1;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double btb;
+          if (REG) {
+            const int ly = ty + 1, lx = tx + 1;
+            double c = L[a][ly][lx];
+            btb = (hn ? L[a][ly - 1][lx] - c : 0.0) +
+                  (hs ? L[a][ly + 1][lx] - c : 0.0) +
+                  (hw ? L[a][ly][lx - 1] - c : 0.0) +
+                  (he ? L[a][ly][lx + 1] - c : 0.0);
+          } else {
+            double c = pc[a];
+            btb = -((P[a][py - 1][px] - c) + (P[a][py + 1][px] - c) +
+                    (P[a][py][px - 1] - c) + (P[a][py][px + 1] - c));
+          }
+          double h = ds * d[a] + md.alpha_hd * md.reg_scale * btb +
+                     md.lam_c * vbar[a];
+          float hf = (float)h;
+          q[jb + (size_t)a * N] = hf;
+          p_new[jb + (size_t)a * N] = (float)pc[a];
+          acc += pc[a] * (double)hf;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  double vals[1] = {acc};
+  block_partials<1>(vals, 0u, part);
+}
+
+// ------------------------------------------------------------ launchers
+
+static int cgv_blocks(const Geom& g) {
+  long long ntiles = (g.N + kWave - 1) / kWave;
+  long long nb = ntiles < kMaxTileBlocks ? ntiles : kMaxTileBlocks;
+  return (int)((nb + kXCD - 1) / kXCD * kXCD);
+}
+
+static int cgv_threads(int nK) {
+  int G = nK < kMaxChunks ? nK : kMaxChunks;
+  return (G < 1 ? 1 : G) * kWave;
+}
+
+CgTiles cg_tiles_2d(const Geom& g, int nK) {
+  CgTiles t;
+  int ntx = (g.m[1] + kTX - 1) / kTX, nty = (g.m[0] + kTY - 1) / kTY;
+  int ntiles = ntx * nty;
+  int nfg = (kCgMaxBlocks + ntiles - 1) / ntiles;
+  if (nfg > nK) nfg = nK;
+  if (nfg < 1) nfg = 1;
+  t.fpg = (nK + nfg - 1) / nfg;
+  t.nfg = (nK + t.fpg - 1) / t.fpg;
+  t.nreal = ntiles * t.nfg;
+  t.grid = (t.nreal + kXCD - 1) / kXCD * kXCD;
+  t.vox_grid = cgv_blocks(g);
+  return t;
+}
+
+hipError_t launch_cgv_init(int dim, const float* grad, const float* dW,
+                           const Geom& g, const Model& md, float* r, float* z,
+                           CgSums sums, RedBuf rb, Scal* sc, hipStream_t s,
+                           int gn_it, GNLog* log) {
+  int nb = cgv_blocks(g), nt = cgv_threads(md.nK);
+  double* part = rb.region(kRegInit);
+  if (dim == 2)
+    cgv_init_kernel<2><<<nb, nt, 0, s>>>(grad, dW, g, md, r, z, sums.Sz,
+                                         sums.Vz, part, gn_it, sc);
+  else
+    cgv_init_kernel<3><<<nb, nt, 0, s>>>(grad, dW, g, md, r, z, sums.Sz,
+                                         sums.Vz, part, gn_it, sc);
+  return launch_finalize_start(rb, tile_blocks(g), nb, md, sc, gn_it, log, s);
+}
+
+hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
+                          float* p_new, const float* dW, const Geom& g,
+                          const Model& md, float* q, CgSums sums, int fixed,
+                          double rtol, RedBuf rb, Scal* sc, hipStream_t s,
+                          int gn_it) {
+  CgTiles t = cg_tiles_2d(g, md.nK);
+  const double* Sp_old = sums.Sp[(it + 1) & 1];
+  const double* Vp_old = sums.Vp[(it + 1) & 1];
+  double* Sp_new = sums.Sp[it & 1];
+  double* Vp_new = sums.Vp[it & 1];
+  if (md.reg == 0)
+    cgt_hvp2_kernel<0><<<t.grid, kTX * kTY, 0, s>>>(
+        it, z, p_old, p_new, dW, g, md, q, sums.Sz, sums.Vz, Sp_old, Vp_old,
+        Sp_new, Vp_new, t.nreal, t.nfg, t.fpg, rb.region(kRegUpdate),
+        t.vox_grid, fixed, rtol, rb.region(kRegHv), sc, gn_it);
+  else
+    cgt_hvp2_kernel<1><<<t.grid, kTX * kTY, 0, s>>>(
+        it, z, p_old, p_new, dW, g, md, q, sums.Sz, sums.Vz, Sp_old, Vp_old,
+        Sp_new, Vp_new, t.nreal, t.nfg, t.fpg, rb.region(kRegUpdate),
+        t.vox_grid, fixed, rtol, rb.region(kRegHv), sc, gn_it);
+  return hipGetLastError();
+}
+
+hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
+                             const float* dW, const Geom& g, const Model& md,
+                             float* x, float* r, float* z, CgSums sums,
+                             RedBuf rb, Scal* sc, hipStream_t s, int gn_it) {
+  int nb = cgv_blocks(g), nt = cgv_threads(md.nK);
+  int hv_nb = cg_tiles_2d(g, md.nK).grid;
+  if (dim == 2)
+    cgv_update_kernel<2><<<nb, nt, 0, s>>>(
+        it, p, q, dW, g, md, x, r, z, sums.Sz, sums.Vz, rb.region(kRegHv),
+        hv_nb, rb.region(kRegUpdate), sc, gn_it);
+  else
+    cgv_update_kernel<3><<<nb, nt, 0, s>>>(
+        it, p, q, dW, g, md, x, r, z, sums.Sz, sums.Vz, rb.region(kRegHv),
+        hv_nb, rb.region(kRegUpdate), sc, gn_it);
+  return hipGetLastError();
+}
+
+hipError_t launch_hessvec_2d(const float* v, const float* dW, const Geom& g,
+                             const Model& md, float* hv, float* vcopy,
+                             CgSums sums, RedBuf rb, Scal* sc,
+                             hipStream_t s) {
+  int nb = cgv_blocks(g), nt = cgv_threads(md.nK);
+  cgv_sums_kernel<2><<<nb, nt, 0, s>>>(v, dW, g, md, sums.Sz, sums.Vz);
+  hipError_t e = launch_gn_reset(sc, nullptr, 0, s);
+  if (e != hipSuccess) return e;
+  e = launch_cgt_hvp(0, v, nullptr, vcopy, dW, g, md, hv, sums, 1, 0.0, rb,
+                     sc, s, 0);
+  if (e != hipSuccess) return e;
+  return launch_finalize_vhv(rb.region(kRegHv), cg_tiles_2d(g, md.nK).grid,
+                             sc, s);
+}
+
+}  // namespace stml

@@ -63,11 +63,19 @@ int tile_blocks(const Geom& g) {
   return round_up(nb, kXCD);
 }
 
-// Four waves per block split the frames of K (fewer if |K| < 4).
-int tile_threads(int nK) {
-  int G = nK < 4 ? nK : 4;
-  if (G < 1) G = 1;
-  return G * kWave;
+// Waves per block split the frames of K; more waves shorten the per-wave
+// frame loops (latency) at the cost of registers: up to 16 (2D Hessian
+// product), 8 (2D evaluation) or 4.
+static int waves_for(int nK, int maxg) {
+  int G = nK < maxg ? nK : maxg;
+  return G < 1 ? 1 : G;
+}
+int tile_threads(int nK) { return waves_for(nK, 4) * kWave; }
+int eval_threads(int dim, int nK) {
+  return waves_for(nK, dim == 2 ? 8 : 4) * kWave;
+}
+int hv_threads(int dim, int nK) {
+  return waves_for(nK, dim == 2 ? 16 : 4) * kWave;
 }
 
 #define STML_DIM_DISPATCH(dim, KERNEL, GRID, BLOCK, STREAM, ...)          \
@@ -76,6 +84,19 @@ int tile_threads(int nK) {
       KERNEL<2><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);                 \
     else                                                                  \
       KERNEL<3><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);                 \
+  } while (0)
+
+// (dimension, regulariser) specialisations of the tile kernels.
+#define STML_TILE_DISPATCH(dim, reg, KERNEL, GRID, BLOCK, STREAM, ...)     \
+  do {                                                                    \
+    if ((dim) == 2 && (reg) == 0)                                         \
+      KERNEL<2, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);              \
+    else if ((dim) == 2)                                                  \
+      KERNEL<2, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);              \
+    else if ((reg) == 0)                                                  \
+      KERNEL<3, 0><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);              \
+    else                                                                  \
+      KERNEL<3, 1><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);              \
   } while (0)
 
 static int elem_blocks(size_t count, int per_thread = 4) {
@@ -195,7 +216,7 @@ struct Chunk {
 };
 __device__ __forceinline__ Chunk frame_chunk(int nK) {
   int G = blockDim.x / kWave;
-  int w = threadIdx.x / kWave;
+  int w = wave_id();
   int per = (nK + G - 1) / G;
   int j0 = w * per;
   int j1 = j0 + per < nK ? j0 + per : nK;
@@ -205,16 +226,18 @@ __device__ __forceinline__ Chunk frame_chunk(int nK) {
 // Objective (D, S, P), gradient and dW/du at u for the frames K.
 // Sweep 1 over the wave's frames warps every frame, stores dW/du and sums
 // W and u per voxel; after the LDS combine, sweep 2 warps again (the loads
-// hit the caches), forms r = W - mean W and writes the gradient.
-template <int D>
-__global__ __launch_bounds__(256) void eval_kernel(
+// hit the caches), forms r = W - mean W and writes the gradient.  Block
+// partials of D, S, P go to `part` (3 x gridDim slots).
+template <int D, int REG>
+__global__ __launch_bounds__(D == 2 ? 512 : 256) void eval_kernel(
     const float* __restrict__ T, const float* __restrict__ u,
     const int* __restrict__ K, Geom g, Model md, float* __restrict__ grad,
-    float* __restrict__ dWo, double* __restrict__ part,
-    unsigned* __restrict__ counter, Scal* __restrict__ sc) {
-  __shared__ double xs[4][kWave][1 + D];
+    float* __restrict__ dWo, double* __restrict__ part, int gn_it,
+    const Scal* __restrict__ sc) {
+  if (sc && gn_it >= sc->gn_stop) return;
+  __shared__ double xs[kMaxChunks][kWave][1 + D];
   const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
+  const int w = wave_id();
   const int G = blockDim.x / kWave;
   const Chunk ch = frame_chunk(md.nK);
   const long long N = g.N;
@@ -273,8 +296,8 @@ __global__ __launch_bounds__(256) void eval_kernel(
         float* gj = grad ? grad + (size_t)j * D * N : nullptr;
 #pragma unroll
         for (int a = 0; a < D; ++a) {
-          double btb, e;
-          reg_terms<D>(uk + (size_t)a * N, p, g, md.reg, btb, e);
+          double btb, e, cen;
+          reg_terms<D, REG>(Src1{uk + (size_t)a * N}, p, g, btb, e, cen);
           accS += e;
           if (gj) {
             double gv = md.data_c * r * dw[a] +
@@ -290,29 +313,36 @@ __global__ __launch_bounds__(256) void eval_kernel(
     }
   }
   double vals[3] = {accD, accS, accP};
-  double out[3];
-  if (grid_reduce<3>(vals, 0u, part, counter, out) && threadIdx.x == 0) {
-    double Dv = md.hd * out[0];
-    double Sv = md.half_alpha_hd * md.reg_scale * out[1];
-    double Pv = md.lam_hd * out[2];
-    sc->D = Dv;
-    sc->S = Sv;
-    sc->P = Pv;
-    sc->J = Dv + Sv + Pv;
-  }
+  block_partials<3>(vals, 0u, part);
 }
 
-// Gauss-Newton Hessian product on the tiles of this block; returns this
-// thread's share of v.Hv.  Sweep 1 sums s_k = dW_k . v_k and v_k per voxel;
-// sweep 2 re-reads dW_k and v_k (cache hits) and writes
-// (Hv)_k = 2h^D dW_k (s_k - mean s) + alpha h^D B^T B v_k + 2 lambda h^D / |K| mean v.
-template <int D>
-__device__ double hv_tiles(const float* __restrict__ v,
-                           const float* __restrict__ dW, const Geom& g,
-                           const Model& md, float* __restrict__ hv) {
-  __shared__ double xs[4][kWave][1 + D];
+// Plane-offset views of the accessors used by hv_tiles.
+struct Plane1 : Src1 {
+  __device__ __forceinline__ Plane1 plane(size_t off) const {
+    return Plane1{{a + off}};
+  }
+};
+struct PlaneLin : SrcLin {
+  __device__ __forceinline__ PlaneLin plane(size_t off) const {
+    return PlaneLin{{z + off, p + off, b}};
+  }
+};
+
+// Gauss-Newton Hessian product over this block's tiles, on the field f
+// (a stored vector, or the CG direction formed on the fly).  Sweep 1 sums
+// s_k = dW_k . v_k and v_k per voxel; sweep 2 re-reads dW_k and v_k (cache
+// hits) and writes
+//   (Hv)_k = 2h^D dW_k (s_k - mean s) + alpha h^D B^T B v_k
+//            + (2 lambda h^D / |K|) mean v.
+// If vout is set, the float32 value of v is stored there too.  Returns this
+// thread's share of v.Hv.
+template <int D, int REG, class F>
+__device__ double hv_tiles(const F& f, const float* dWp,
+                           const Geom& g, const Model& md,
+                           float* __restrict__ hv, float* __restrict__ vout) {
+  __shared__ double xs[kMaxChunks][kWave][1 + D];
   const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
+  const int w = wave_id();
   const int G = blockDim.x / kWave;
   const Chunk ch = frame_chunk(md.nK);
   const long long N = g.N;
@@ -328,12 +358,12 @@ __device__ double hv_tiles(const float* __restrict__ v,
 #pragma unroll
     for (int a = 0; a < D; ++a) sV[a] = 0.0;
     for (int j = ch.j0; j < ch.j1; ++j) {
-      const float* vj = v + (size_t)j * D * N;
-      const float* dj = dW + (size_t)j * D * N;
+      const F fj = f.plane((size_t)j * D * N);
+      const float* dj = dWp + (size_t)j * D * N;
       double s = 0.0;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
-        double vv = (double)vj[(size_t)a * N + p.idx];
+        double vv = fj((unsigned)(a * N) + p.idx);
         s += (double)dj[(size_t)a * N + p.idx] * vv;
         sV[a] += vv;
       }
@@ -357,26 +387,28 @@ __device__ double hv_tiles(const float* __restrict__ v,
     for (int a = 0; a < D; ++a) vb[a] *= md.inv_nK;
     if (valid) {
       for (int j = ch.j0; j < ch.j1; ++j) {
-        const float* vj = v + (size_t)j * D * N;
-        const float* dj = dW + (size_t)j * D * N;
+        const F fj = f.plane((size_t)j * D * N);
+        const float* dj = dWp + (size_t)j * D * N;
         float* hj = hv + (size_t)j * D * N;
         double s = 0.0;
 #pragma unroll
         for (int a = 0; a < D; ++a)
           s += (double)dj[(size_t)a * N + p.idx] *
-               (double)vj[(size_t)a * N + p.idx];
+               fj((unsigned)(a * N) + p.idx);
         double ds = md.data_c * (s - sb);
 #pragma unroll 1
         for (int a = 0; a < D; ++a) {
-          const float* vja = vj + (size_t)a * N;
-          double btb, e;
-          reg_terms<D>(vja, p, g, md.reg, btb, e);
+          const F fja = fj.plane((size_t)a * N);
+          double btb, e, cen;
+          reg_terms<D, REG>(fja, p, g, btb, e, cen);
           double vba = a == 0 ? vb[0] : (a == 1 ? vb[1] : vb[D - 1]);
           double h = ds * (double)dj[(size_t)a * N + p.idx] +
                      md.alpha_hd * md.reg_scale * btb + md.lam_c * vba;
           float hf = (float)h;
-          hj[(size_t)a * N + p.idx] = hf;
-          acc += (double)vja[p.idx] * (double)hf;
+          size_t o = ((size_t)j * D + a) * N + p.idx;
+          hv[o] = hf;
+          if (vout) vout[o] = (float)cen;
+          acc += cen * (double)hf;
         }
       }
     }
@@ -384,129 +416,186 @@ __device__ double hv_tiles(const float* __restrict__ v,
   return acc;
 }
 
-template <int D>
-__global__ __launch_bounds__(256) void hessvec_kernel(
+// Test entry: Hv for a stored v; block partials of v.Hv.
+template <int D, int REG>
+__global__ __launch_bounds__(D == 2 ? 1024 : 256) void hessvec_kernel(
     const float* __restrict__ v, const float* __restrict__ dW, Geom g,
-    Model md, float* __restrict__ hv, double* __restrict__ part,
-    unsigned* __restrict__ counter, Scal* __restrict__ sc) {
-  double vals[1] = {hv_tiles<D>(v, dW, g, md, hv)};
-  double out[1];
-  if (grid_reduce<1>(vals, 0u, part, counter, out) && threadIdx.x == 0)
-    sc->vHv = out[0];
+    Model md, float* __restrict__ hv, double* __restrict__ part) {
+  double vals[1] = {hv_tiles<D, REG>(Plane1{{v}}, dW, g, md, hv, nullptr)};
+  block_partials<1>(vals, 0u, part);
 }
 
-// CG step, part 1: q = H p and a = rz / p.q (breakdown if p.q <= 0).
-template <int D>
-__global__ __launch_bounds__(256) void pcg_hv_kernel(
-    const float* __restrict__ p, const float* __restrict__ dW, Geom g,
-    Model md, float* __restrict__ q, double* __restrict__ part,
-    unsigned* __restrict__ counter, Scal* __restrict__ sc) {
-  if (sc->done) return;
-  double vals[1] = {hv_tiles<D>(p, dW, g, md, q)};
-  double out[1];
-  if (grid_reduce<1>(vals, 0u, part, counter, out) && threadIdx.x == 0) {
-    double pq = out[0];
-    sc->pq = pq;
-    if (pq > 0.0) {
-      sc->a = sc->rz / pq;
-    } else {
-      sc->done = 2;
-    }
-  }
-}
+// ------------------------------------------------------------------ PCG
+//
+// Two kernels per CG iteration it (scalars stay on the device):
+//   pcg_hvp(it):   [it > 0] reduce r.z and r.r of update(it-1); stop if
+//                  converged; beta = rz_new / rz_old;
+//                  p_it = z + beta p_{it-1} (formed on the fly, stored),
+//                  q = H p_it, partial p.q
+//   pcg_update(it): reduce p.q; a = rz / p.q (stop on p.q <= 0);
+//                  x += a p, r -= a q, z = M^-1 r, partial r.z and r.r
+// r.z of iteration it lives in sc->rzh[it & 1]; a kernel reads one slot and
+// writes the other.  Every block of a consumer reduces the producer's
+// partial slots in the same order, so all blocks take the same decision.
 
-// Jacobi preconditioner entry of element e = (j, a, x).
-template <int D>
-__device__ __forceinline__ double jacobi_at(const float* __restrict__ dW,
-                                            size_t e, long long N,
-                                            const Geom& g, const Model& md) {
-  long long x = (long long)(e % (size_t)N);
-  Pos<D> p = make_pos<D>(g, x);
-  double d = (double)dW[e];
-  return md.mdiag_c * d * d +
-         md.alpha_hd * md.reg_scale * reg_diag_at<D>(p, g, md.reg) +
-         md.pen_diag;
-}
-
-// CG start: x = 0, r = -g, z = M^-1 r, p = z.
+// CG start: M = diag(H) (Jacobi), x = 0, r = -g, z = M^-1 r.
 template <int D>
 __global__ __launch_bounds__(256) void pcg_init_kernel(
     const float* __restrict__ grad, const float* __restrict__ dW, Geom g,
-    Model md, size_t count, float* __restrict__ x, float* __restrict__ r,
-    float* __restrict__ z, float* __restrict__ p, double* __restrict__ part,
-    unsigned* __restrict__ counter, Scal* __restrict__ sc) {
-  size_t stride = (size_t)gridDim.x * blockDim.x;
+    Model md, unsigned count, float* __restrict__ Mo, float* __restrict__ x,
+    float* __restrict__ r, float* __restrict__ z,
+    double* __restrict__ part, int gn_it, const Scal* __restrict__ sc) {
+  if (gn_it >= sc->gn_stop) return;
+  const unsigned N = (unsigned)g.N;
+  const unsigned stride = gridDim.x * blockDim.x;
   double rz = 0.0, rr = 0.0;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+  for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < count;
        e += stride) {
+    unsigned row = e / N;
+    Pos<D> pos = make_pos<D>(g, (long long)(e - row * N));
+    double d = (double)dW[e];
+    double M = md.mdiag_c * d * d +
+               md.alpha_hd * md.reg_scale * reg_diag_at<D>(pos, g, md.reg) +
+               md.pen_diag;
     float rv = -grad[e];
-    float zv = (float)((double)rv / jacobi_at<D>(dW, e, g.N, g, md));
+    float zv = (float)((double)rv / M);
+    Mo[e] = (float)M;
     x[e] = 0.0f;
     r[e] = rv;
     z[e] = zv;
-    p[e] = zv;
     rz += (double)rv * (double)zv;
     rr += (double)rv * (double)rv;
   }
   double vals[2] = {rz, rr};
-  double out[2];
-  if (grid_reduce<2>(vals, 0u, part, counter, out) && threadIdx.x == 0) {
-    sc->rz = out[0];
-    sc->r0 = sqrt(out[1]);
-    sc->rr = out[1];
+  block_partials<2>(vals, 0u, part);
+}
+
+// One block: the objective of the evaluation and the CG start scalars.
+__global__ __launch_bounds__(256) void finalize_start_kernel(
+    const double* __restrict__ ev_part, int ev_nb,
+    const double* __restrict__ in_part, int in_nb, Model md,
+    Scal* __restrict__ sc, int gn_it, GNLog* __restrict__ log) {
+  if (gn_it >= sc->gn_stop) return;
+  double e[3], i2[2];
+  reduce_partials<3>(ev_part, ev_nb, 0u, e);
+  reduce_partials<2>(in_part, in_nb, 0u, i2);
+  if (threadIdx.x == 0) {
+    double Dv = md.hd * e[0];
+    double Sv = md.half_alpha_hd * md.reg_scale * e[1];
+    double Pv = md.lam_hd * e[2];
+    sc->D = Dv;
+    sc->S = Sv;
+    sc->P = Pv;
+    sc->J = Dv + Sv + Pv;
+    sc->rzh[0] = i2[0];
+    sc->r0 = sqrt(i2[1]);
+    sc->rr = i2[1];
     sc->iters = 0;
-    sc->done = out[0] == 0.0 ? 1 : 0;
+    sc->done = i2[0] == 0.0 ? 1 : 0;
+    if (log) log[gn_it].J = Dv + Sv + Pv;
   }
 }
 
-// CG step, part 2: x += a p, r -= a q, z = M^-1 r; convergence and beta.
-template <int D>
-__global__ __launch_bounds__(256) void pcg_update_kernel(
-    const float* __restrict__ p, const float* __restrict__ q,
-    const float* __restrict__ dW, Geom g, Model md, size_t count,
-    float* __restrict__ x, float* __restrict__ r, float* __restrict__ z,
-    int fixed, double rtol, double* __restrict__ part,
-    unsigned* __restrict__ counter, Scal* __restrict__ sc) {
-  if (sc->done) return;
-  const double a = sc->a;
-  size_t stride = (size_t)gridDim.x * blockDim.x;
-  double rz = 0.0, rr = 0.0;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
-       e += stride) {
-    double pe = (double)p[e];
-    x[e] = (float)((double)x[e] + a * pe);
-    float rv = (float)((double)r[e] - a * (double)q[e]);
-    float zv = (float)((double)rv / jacobi_at<D>(dW, e, g.N, g, md));
-    r[e] = rv;
-    z[e] = zv;
-    rz += (double)rv * (double)zv;
-    rr += (double)rv * (double)rv;
-  }
-  double vals[2] = {rz, rr};
-  double out[2];
-  if (grid_reduce<2>(vals, 0u, part, counter, out) && threadIdx.x == 0) {
-    sc->iters += 1;
-    sc->rr = out[1];
-    bool conv = (!fixed && sqrt(out[1]) <= rtol * sc->r0) || out[0] == 0.0;
+template <int D, int REG>
+__global__ __launch_bounds__(D == 2 ? 1024 : 256) void pcg_hvp_kernel(
+    int it, const float* __restrict__ z, const float* __restrict__ p_old,
+    float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
+    Model md, float* __restrict__ q, const double* __restrict__ up_part,
+    int up_nb, int fixed, double rtol, double* __restrict__ part,
+    Scal* __restrict__ sc, int gn_it) {
+  if (sc->done || gn_it >= sc->gn_stop) return;
+  double beta = 0.0;
+  if (it > 0) {
+    double t[2];
+    reduce_partials<2>(up_part, up_nb, 0u, t);
+    const double rz_old = sc->rzh[(it - 1) & 1];
+    bool conv = (!fixed && sqrt(t[1]) <= rtol * sc->r0) || t[0] == 0.0;
     if (conv) {
-      sc->done = 1;
-    } else {
-      sc->beta = out[0] / sc->rz;
-      sc->rz = out[0];
+      if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 1;
+      return;
+    }
+    beta = t[0] / rz_old;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->rzh[it & 1] = t[0];
+      sc->rr = t[1];
+      sc->beta = beta;
     }
   }
+  double acc;
+  if (it > 0)
+    acc = hv_tiles<D, REG>(PlaneLin{{z, p_old, (float)beta}}, dW, g, md, q, p_new);
+  else
+    acc = hv_tiles<D, REG>(Plane1{{z}}, dW, g, md, q, p_new);
+  double vals[1] = {acc};
+  block_partials<1>(vals, 0u, part);
 }
 
-// CG step, part 3: p = z + beta p.
-__global__ __launch_bounds__(256) void pcg_pupdate_kernel(
-    const float* __restrict__ z, float* __restrict__ p, size_t count,
-    const Scal* __restrict__ sc) {
-  if (sc->done) return;
-  const double b = sc->beta;
-  size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
-       e += stride)
-    p[e] = (float)((double)z[e] + b * (double)p[e]);
+__device__ __forceinline__ void cg_upd1(float& xv, float& rv, float& zv,
+                                        float pv, float qv, float Mv,
+                                        double a, double& rz, double& rr) {
+  xv = (float)((double)xv + a * (double)pv);
+  rv = (float)((double)rv - a * (double)qv);
+  zv = (float)((double)rv / (double)Mv);
+  rz += (double)rv * (double)zv;
+  rr += (double)rv * (double)rv;
+}
+
+template <bool V4>
+__global__ __launch_bounds__(256) void pcg_update_kernel(
+    int it, const float* __restrict__ p, const float* __restrict__ q,
+    const float* __restrict__ M, unsigned count, float* __restrict__ x,
+    float* __restrict__ r, float* __restrict__ z,
+    const double* __restrict__ hv_part, int hv_nb,
+    double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
+  if (sc->done || gn_it >= sc->gn_stop) return;
+  double t[1];
+  reduce_partials<1>(hv_part, hv_nb, 0u, t);
+  const double pq = t[0];
+  if (!(pq > 0.0)) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      sc->pq = pq;
+      sc->done = 2;
+    }
+    return;
+  }
+  const double a = sc->rzh[it & 1] / pq;
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    sc->pq = pq;
+    sc->a = a;
+    sc->iters = it + 1;
+  }
+  const unsigned stride = gridDim.x * blockDim.x;
+  double rz = 0.0, rr = 0.0;
+  if (V4) {
+    const unsigned c4 = count / 4;
+    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < c4;
+         i += stride) {
+      float4 pv = reinterpret_cast<const float4*>(p)[i];
+      float4 qv = reinterpret_cast<const float4*>(q)[i];
+      float4 Mv = reinterpret_cast<const float4*>(M)[i];
+      float4 xv = reinterpret_cast<float4*>(x)[i];
+      float4 rv = reinterpret_cast<float4*>(r)[i];
+      float4 zv;
+      cg_upd1(xv.x, rv.x, zv.x, pv.x, qv.x, Mv.x, a, rz, rr);
+      cg_upd1(xv.y, rv.y, zv.y, pv.y, qv.y, Mv.y, a, rz, rr);
+      cg_upd1(xv.z, rv.z, zv.z, pv.z, qv.z, Mv.z, a, rz, rr);
+      cg_upd1(xv.w, rv.w, zv.w, pv.w, qv.w, Mv.w, a, rz, rr);
+      reinterpret_cast<float4*>(x)[i] = xv;
+      reinterpret_cast<float4*>(r)[i] = rv;
+      reinterpret_cast<float4*>(z)[i] = zv;
+    }
+  } else {
+    for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < count;
+         e += stride) {
+      float xv = x[e], rv = r[e], zv;
+      cg_upd1(xv, rv, zv, p[e], q[e], M[e], a, rz, rr);
+      x[e] = xv;
+      r[e] = rv;
+      z[e] = zv;
+    }
+  }
+  double vals[2] = {rz, rr};
+  block_partials<2>(vals, 0u, part);
 }
 
 struct Steps {
@@ -518,18 +607,20 @@ struct Steps {
 // voxel's value in the first frame of K (a shift against cancellation);
 // S and P are quadratic in t and are expanded exactly.  The per-step sums
 // live in LDS (one slot row per thread), which keeps register use low.
-template <int D>
+template <int D, int REG>
 __global__ __launch_bounds__(256) void trial_kernel(
     const float* __restrict__ T, const float* __restrict__ u,
     const float* __restrict__ dl, const float* __restrict__ gr,
     const int* __restrict__ K, Geom g, Model md, Steps st,
-    double* __restrict__ part, unsigned* __restrict__ counter,
-    Scal* __restrict__ sc) {
+    double* __restrict__ part, int gn_it, LSPass ls,
+    const Scal* __restrict__ sc, const GNLog* __restrict__ log) {
+  if (gn_it >= sc->gn_stop) return;
+  if (ls.p > 0 && log[gn_it].next_pass != ls.p) return;
   constexpr int NT = kTrialSteps;
   constexpr int NV = 2 * NT + 2 * D;
   __shared__ double xs[4][kWave][NV];
   const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
+  const int w = wave_id();
   const int G = blockDim.x / kWave;
   const Chunk ch = frame_chunk(md.nK);
   const long long N = g.N;
@@ -561,8 +652,8 @@ __global__ __launch_bounds__(256) void trial_kernel(
           slope += (double)gr[o] * dv[a];
           mx = fmax(mx, fabs(dv[a]));
           double uu, uw, ww;
-          reg_cross<D>(u + ((size_t)k * D + a) * N,
-                       dl + ((size_t)j * D + a) * N, p, g, md.reg, uu, uw, ww);
+          reg_cross<D, REG>(u + ((size_t)k * D + a) * N,
+                            dl + ((size_t)j * D + a) * N, p, g, uu, uw, ww);
           rA += uu;
           rB += uw;
           rC += ww;
@@ -621,9 +712,19 @@ __global__ __launch_bounds__(256) void trial_kernel(
   vals[NT + 5] = pC;
   vals[NT + 6] = slope;
   vals[NT + 7] = mx;
+  block_partials<NT + 8>(vals, 1u << (NT + 7), part);
+}
+
+// One block: objective at the trial steps, g.delta and max |delta|.
+__global__ __launch_bounds__(256) void finalize_trial_kernel(
+    const double* __restrict__ part, int nb, Model md, Steps st,
+    Scal* __restrict__ sc, int gn_it, LSPass ls, GNLog* __restrict__ log) {
+  if (gn_it >= sc->gn_stop) return;
+  if (ls.p > 0 && log[gn_it].next_pass != ls.p) return;
+  constexpr int NT = kTrialSteps;
   double out[NT + 8];
-  if (grid_reduce<NT + 8>(vals, 1u << (NT + 7), part, counter, out) &&
-      threadIdx.x == 0) {
+  reduce_partials<NT + 8>(part, nb, 1u << (NT + 7), out);
+  if (threadIdx.x == 0) {
     double sA = md.half_alpha_hd * md.reg_scale;
     for (int s = 0; s < NT; ++s) {
       double t = st.t[s];
@@ -635,13 +736,51 @@ __global__ __launch_bounds__(256) void trial_kernel(
     }
     sc->slope = out[NT + 6];
     sc->maxd = out[NT + 7];
+    if (ls.p == 0) {
+      GNLog& L = log[gn_it];
+      L.J0t = sc->Jt[0];
+      L.slope = out[NT + 6];
+      L.maxd = out[NT + 7];
+    }
   }
 }
 
-__global__ void accept_kernel(float* __restrict__ u,
-                              const float* __restrict__ dl,
-                              const int* __restrict__ K, int nK, int dim,
-                              long long N, double t) {
+// Armijo decision of sweep ls and, if a step passes, u[K[j]] += t delta_j.
+// Every block takes the same decision from the same values.  Flags a later
+// block of this kernel might read (next_pass, gn_stop) are only written in
+// ways that leave such a block's work unchanged.
+__global__ __launch_bounds__(256) void ls_accept_kernel(
+    float* __restrict__ u, const float* __restrict__ dl,
+    const int* __restrict__ K, int nK, int dim, long long N, Steps st,
+    LSPass ls, int ls_max, double c1, int fixed, double tol_J, double tol_u,
+    int gn_it, Scal* __restrict__ sc, GNLog* __restrict__ log) {
+  if (gn_it >= sc->gn_stop) return;
+  GNLog* L = log + gn_it;
+  if (ls.p > 0 && L->next_pass != ls.p) return;
+  const double J0t = L->J0t, slope = L->slope;
+  double tacc = -1.0, Jacc = 0.0;
+  for (int s = ls.base; s < kTrialSteps; ++s) {
+    int e = ls.e0 + (s - ls.base);
+    if (e > ls_max) break;
+    if (sc->Jt[s] <= J0t + c1 * st.t[s] * slope) {
+      tacc = st.t[s];
+      Jacc = sc->Jt[s];
+      break;
+    }
+  }
+  if (tacc < 0.0) {
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      if (ls.last) {
+        L->status = 1;
+        L->t = 0.0;
+        L->cg = sc->iters;
+        sc->gn_stop = gn_it;
+      } else {
+        L->next_pass = ls.p + 1;
+      }
+    }
+    return;
+  }
   size_t count = (size_t)nK * dim * N;
   size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
@@ -651,8 +790,60 @@ __global__ void accept_kernel(float* __restrict__ u,
     int j = (int)(row / dim);
     int a = (int)(row - (size_t)j * dim);
     size_t o = ((size_t)K[j] * dim + a) * N + x;
-    u[o] = (float)((double)u[o] + t * (double)dl[e]);
+    u[o] = (float)((double)u[o] + tacc * (double)dl[e]);
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    bool breakdown = sc->done == 2;
+    L->t = tacc;
+    L->Jacc = Jacc;
+    L->cg = sc->iters;
+    L->status = breakdown ? 2 : 0;
+    bool stop = breakdown ||
+                (!fixed && (L->J - Jacc) <= tol_J * fabs(L->J) &&
+                 tacc * L->maxd <= tol_u);
+    if (stop) sc->gn_stop = gn_it + 1;
+  }
+}
+
+// Start of a registration: every Gauss-Newton iteration enabled, logs
+// cleared.
+__global__ void gn_reset_kernel(Scal* __restrict__ sc,
+                                GNLog* __restrict__ log, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    GNLog L = {};
+    L.status = -1;
+    L.next_pass = 0;
+    log[i] = L;
+  }
+  if (i == 0) {
+    sc->gn_stop = 0x7fffffff;
+    sc->done = 0;
+  }
+}
+
+// One block: objective only (no CG start) and v.Hv of the test entry.
+__global__ __launch_bounds__(256) void finalize_eval_kernel(
+    const double* __restrict__ ev_part, int ev_nb, Model md,
+    Scal* __restrict__ sc) {
+  double e[3];
+  reduce_partials<3>(ev_part, ev_nb, 0u, e);
+  if (threadIdx.x == 0) {
+    double Dv = md.hd * e[0];
+    double Sv = md.half_alpha_hd * md.reg_scale * e[1];
+    double Pv = md.lam_hd * e[2];
+    sc->D = Dv;
+    sc->S = Sv;
+    sc->P = Pv;
+    sc->J = Dv + Sv + Pv;
+  }
+}
+
+__global__ __launch_bounds__(256) void finalize_vhv_kernel(
+    const double* __restrict__ part, int nb, Scal* __restrict__ sc) {
+  double t[1];
+  reduce_partials<1>(part, nb, 0u, t);
+  if (threadIdx.x == 0) sc->vHv = t[0];
 }
 
 // Linear temporal interpolation of all frames from the frames of K_q.
@@ -744,95 +935,6 @@ hipError_t launch_prolong(int dim, const float* coarse, float* fine,
   return hipGetLastError();
 }
 
-hipError_t launch_eval(int dim, const float* T, const float* u, const int* K,
-                       const Geom& g, const Model& md, float* grad,
-                       float* dW, RedBuf rb, Scal* sc, hipStream_t s) {
-  int nb = tile_blocks(g), nt = tile_threads(md.nK);
-  STML_DIM_DISPATCH(dim, eval_kernel, nb, nt, s, T, u, K, g, md,
-                     grad, dW, rb.part, rb.counter, sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_hessvec(int dim, const float* v, const float* dW,
-                          const Geom& g, const Model& md, float* hv,
-                          RedBuf rb, Scal* sc, hipStream_t s) {
-  int nb = tile_blocks(g), nt = tile_threads(md.nK);
-  STML_DIM_DISPATCH(dim, hessvec_kernel, nb, nt, s, v, dW, g, md, hv,
-                     rb.part, rb.counter, sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_init(int dim, const float* grad, const float* dW,
-                           const Geom& g, const Model& md, float* x, float* r,
-                           float* z, float* p, RedBuf rb, Scal* sc,
-                           hipStream_t s) {
-  size_t count = (size_t)md.nK * dim * g.N;
-  int nb = elem_blocks(count);
-  if (dim == 2)
-    pcg_init_kernel<2><<<nb, 256, 0, s>>>(grad, dW, g, md, count, x, r, z, p,
-                                          rb.part, rb.counter, sc);
-  else
-    pcg_init_kernel<3><<<nb, 256, 0, s>>>(grad, dW, g, md, count, x, r, z, p,
-                                          rb.part, rb.counter, sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_hv(int dim, const float* p, const float* dW,
-                         const Geom& g, const Model& md, float* q, RedBuf rb,
-                         Scal* sc, hipStream_t s) {
-  int nb = tile_blocks(g), nt = tile_threads(md.nK);
-  STML_DIM_DISPATCH(dim, pcg_hv_kernel, nb, nt, s, p, dW, g, md, q,
-                     rb.part, rb.counter, sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_update(int dim, const float* p, const float* q,
-                             const float* dW, const Geom& g, const Model& md,
-                             float* x, float* r, float* z, int fixed,
-                             double rtol, RedBuf rb, Scal* sc, hipStream_t s) {
-  size_t count = (size_t)md.nK * dim * g.N;
-  int nb = elem_blocks(count);
-  if (dim == 2)
-    pcg_update_kernel<2><<<nb, 256, 0, s>>>(p, q, dW, g, md, count, x, r, z,
-                                            fixed, rtol, rb.part, rb.counter,
-                                            sc);
-  else
-    pcg_update_kernel<3><<<nb, 256, 0, s>>>(p, q, dW, g, md, count, x, r, z,
-                                            fixed, rtol, rb.part, rb.counter,
-                                            sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_pupdate(const float* z, float* p, size_t count,
-                              Scal* sc, hipStream_t s) {
-  pcg_pupdate_kernel<<<elem_blocks(count), 256, 0, s>>>(z, p, count, sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_trial(int dim, const float* T, const float* u,
-                        const float* delta, const float* grad, const int* K,
-                        const Geom& g, const Model& md, const double* t,
-                        RedBuf rb, Scal* sc, hipStream_t s) {
-  Steps st;
-  for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
-  int nb = tile_blocks(g);
-  int nt = tile_threads(md.nK);
-  if (dim == 2)
-    trial_kernel<2><<<nb, nt, 0, s>>>(T, u, delta, grad, K, g, md, st,
-                                      rb.part, rb.counter, sc);
-  else
-    trial_kernel<3><<<nb, nt, 0, s>>>(T, u, delta, grad, K, g, md, st,
-                                      rb.part, rb.counter, sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_accept(float* u, const float* delta, const int* K, int nK,
-                         int dim, long long N, double t, hipStream_t s) {
-  size_t count = (size_t)nK * dim * N;
-  accept_kernel<<<elem_blocks(count), 256, 0, s>>>(u, delta, K, nK, dim, N,
-                                                   t);
-  return hipGetLastError();
-}
 
 hipError_t launch_linear_predict(const float* Y, float* Z, float* Yout,
                                  LinTab tab, int n, int dim, long long N,
@@ -852,6 +954,131 @@ hipError_t launch_ls_predict(float* Y, float* Z, ThomasTab tab, int n,
   int nb = (int)((systems + B - 1) / B);
   size_t lds = (size_t)n * B * sizeof(double);
   ls_predict_kernel<<<nb, B, lds, s>>>(Y, Z, tab, n, dim, N, beta);
+  return hipGetLastError();
+}
+
+hipError_t launch_eval(int dim, const float* T, const float* u, const int* K,
+                       const Geom& g, const Model& md, float* grad,
+                       float* dW, RedBuf rb, Scal* sc, hipStream_t s,
+                       bool finalize, int gn_it) {
+  int nb = tile_blocks(g), nt = eval_threads(dim, md.nK);
+  double* part = rb.region(kRegEval);
+  const Scal* gate = finalize ? nullptr : sc;
+  STML_TILE_DISPATCH(dim, md.reg, eval_kernel, nb, nt, s, T, u, K, g, md,
+                     grad, dW, part, gn_it, gate);
+  if (finalize)
+    finalize_eval_kernel<<<1, 256, 0, s>>>(part, nb, md, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_hessvec(int dim, const float* v, const float* dW,
+                          const Geom& g, const Model& md, float* hv,
+                          RedBuf rb, Scal* sc, hipStream_t s) {
+  int nb = tile_blocks(g), nt = hv_threads(dim, md.nK);
+  double* part = rb.region(kRegTest);
+  STML_TILE_DISPATCH(dim, md.reg, hessvec_kernel, nb, nt, s, v, dW, g, md, hv, part);
+  finalize_vhv_kernel<<<1, 256, 0, s>>>(part, nb, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_init(int dim, const float* grad, const float* dW,
+                           const Geom& g, const Model& md, float* M, float* x,
+                           float* r, float* z, RedBuf rb, Scal* sc,
+                           hipStream_t s, int gn_it, GNLog* log) {
+  unsigned count = (unsigned)((size_t)md.nK * dim * g.N);
+  int nb = elem_blocks(count);
+  double* part = rb.region(kRegInit);
+  if (dim == 2)
+    pcg_init_kernel<2><<<nb, 256, 0, s>>>(grad, dW, g, md, count, M, x, r, z,
+                                          part, gn_it, sc);
+  else
+    pcg_init_kernel<3><<<nb, 256, 0, s>>>(grad, dW, g, md, count, M, x, r, z,
+                                          part, gn_it, sc);
+  finalize_start_kernel<<<1, 256, 0, s>>>(rb.region(kRegEval), tile_blocks(g),
+                                          part, nb, md, sc, gn_it, log);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_hvp(int dim, int it, const float* z, const float* p_old,
+                          float* p_new, const float* dW, const Geom& g,
+                          const Model& md, float* q, int fixed, double rtol,
+                          RedBuf rb, Scal* sc, hipStream_t s, int gn_it) {
+  int nb = tile_blocks(g), nt = hv_threads(dim, md.nK);
+  size_t count = (size_t)md.nK * dim * g.N;
+  int up_nb = elem_blocks(count, (g.N % 4) == 0 ? 4 : 1);
+  STML_TILE_DISPATCH(dim, md.reg, pcg_hvp_kernel, nb, nt, s, it, z, p_old, p_new, dW,
+                    g, md, q, rb.region(kRegUpdate), up_nb, fixed, rtol,
+                    rb.region(kRegHv), sc, gn_it);
+  return hipGetLastError();
+}
+
+hipError_t launch_pcg_update(int it, const float* p, const float* q,
+                             const float* M, size_t count, const Geom& g,
+                             float* x, float* r, float* z, RedBuf rb,
+                             Scal* sc, hipStream_t s, int gn_it) {
+  bool v4 = (g.N % 4) == 0;
+  int nb = elem_blocks(count, v4 ? 4 : 1);
+  int hv_nb = tile_blocks(g);
+  if (v4)
+    pcg_update_kernel<true><<<nb, 256, 0, s>>>(
+        it, p, q, M, (unsigned)count, x, r, z, rb.region(kRegHv), hv_nb,
+        rb.region(kRegUpdate), sc, gn_it);
+  else
+    pcg_update_kernel<false><<<nb, 256, 0, s>>>(
+        it, p, q, M, (unsigned)count, x, r, z, rb.region(kRegHv), hv_nb,
+        rb.region(kRegUpdate), sc, gn_it);
+  return hipGetLastError();
+}
+
+hipError_t launch_trial(int dim, const float* T, const float* u,
+                        const float* delta, const float* grad, const int* K,
+                        const Geom& g, const Model& md, const double* t,
+                        RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
+                        LSPass ls, GNLog* log) {
+  Steps st;
+  for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
+  int nb = tile_blocks(g);
+  int nt = tile_threads(md.nK);
+  double* part = rb.region(kRegTrial);
+  STML_TILE_DISPATCH(dim, md.reg, trial_kernel, nb, nt, s, T, u, delta, grad,
+                     K, g, md, st, part, gn_it, ls, sc, log);
+  finalize_trial_kernel<<<1, 256, 0, s>>>(part, nb, md, st, sc, gn_it, ls,
+                                          log);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_accept(float* u, const float* delta, const int* K,
+                            int nK, int dim, long long N, const double* t,
+                            LSPass ls, int ls_max, double c1, int fixed,
+                            double tol_J, double tol_u, int gn_it, Scal* sc,
+                            GNLog* log, hipStream_t s) {
+  Steps st;
+  for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
+  size_t count = (size_t)nK * dim * N;
+  ls_accept_kernel<<<elem_blocks(count), 256, 0, s>>>(
+      u, delta, K, nK, dim, N, st, ls, ls_max, c1, fixed, tol_J, tol_u, gn_it,
+      sc, log);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_start(RedBuf rb, int ev_nb, int in_nb,
+                                 const Model& md, Scal* sc, int gn_it,
+                                 GNLog* log, hipStream_t s) {
+  finalize_start_kernel<<<1, 256, 0, s>>>(rb.region(kRegEval), ev_nb,
+                                          rb.region(kRegInit), in_nb, md, sc,
+                                          gn_it, log);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_vhv(const double* part, int nb, Scal* sc,
+                               hipStream_t s) {
+  finalize_vhv_kernel<<<1, 256, 0, s>>>(part, nb, sc);
+  return hipGetLastError();
+}
+
+hipError_t launch_gn_reset(Scal* sc, GNLog* log, int n, hipStream_t s) {
+  int nb = (n + 255) / 256;
+  gn_reset_kernel<<<nb < 1 ? 1 : nb, 256, 0, s>>>(sc, log, n);
   return hipGetLastError();
 }
 

@@ -7,12 +7,16 @@
 
 namespace stml {
 
-// Scratch the reductions use: partial slots and the last-block counter.
+// Partial-sum slots of the reductions: one region per producing kernel, so
+// a consumer can read its producer's slots after the next kernel wrote its
+// own.  A region holds up to 16 values x 1024 blocks.
+constexpr size_t kRegionSlots = (size_t)16 * 1024;
+enum { kRegEval, kRegInit, kRegHv, kRegUpdate, kRegTrial, kRegTest, kRegCount };
+constexpr size_t kRedSlots = kRegionSlots * kRegCount;
 struct RedBuf {
-  double* part;         // capacity: kRedSlots doubles
-  unsigned* counter;    // one zero-initialised counter per kernel in flight
+  double* part;         // kRedSlots doubles
+  double* region(int r) const { return part + (size_t)r * kRegionSlots; }
 };
-constexpr size_t kRedSlots = (size_t)16 * 65536;
 
 // Temporal-predictor tables of one subset K_q (device pointers).
 struct LinTab {            // per frame k: z_k = wl y_left + wr y_right
@@ -33,6 +37,8 @@ Model make_model(int dim, double h, int nK, double alpha, double lambda,
 
 int tile_blocks(const Geom& g);
 int tile_threads(int nK);
+int eval_threads(int dim, int nK);
+int hv_threads(int dim, int nK);
 
 hipError_t launch_fill(float* p, size_t count, float v, hipStream_t s);
 hipError_t launch_check_finite(const float* p, size_t count, Scal* sc,
@@ -43,37 +49,87 @@ hipError_t launch_prolong(int dim, const float* coarse, float* fine,
                           int fields, const Geom& gc, const Geom& gf,
                           hipStream_t s);
 
+// finalize = false leaves the partials for launch_pcg_init to reduce.
+// gn_it: Gauss-Newton iteration this launch belongs to (ignored when
+// finalize is set); the kernel does nothing if gn_it >= sc->gn_stop.
 hipError_t launch_eval(int dim, const float* T, const float* u, const int* K,
                        const Geom& g, const Model& md, float* grad,
-                       float* dW, RedBuf rb, Scal* sc, hipStream_t s);
+                       float* dW, RedBuf rb, Scal* sc, hipStream_t s,
+                       bool finalize, int gn_it);
 hipError_t launch_hessvec(int dim, const float* v, const float* dW,
                           const Geom& g, const Model& md, float* hv,
                           RedBuf rb, Scal* sc, hipStream_t s);
 
 // PCG on H delta = -g (device-resident scalars in sc).
+// Also reduces the evaluation's partials (J, D, S, P into sc).
 hipError_t launch_pcg_init(int dim, const float* grad, const float* dW,
-                           const Geom& g, const Model& md, float* x, float* r,
-                           float* z, float* p, RedBuf rb, Scal* sc,
-                           hipStream_t s);
-hipError_t launch_pcg_hv(int dim, const float* p, const float* dW,
-                         const Geom& g, const Model& md, float* q, RedBuf rb,
-                         Scal* sc, hipStream_t s);
-hipError_t launch_pcg_update(int dim, const float* p, const float* q,
-                             const float* dW, const Geom& g, const Model& md,
-                             float* x, float* r, float* z, int fixed,
-                             double rtol, RedBuf rb, Scal* sc, hipStream_t s);
-hipError_t launch_pcg_pupdate(const float* z, float* p, size_t count,
-                              Scal* sc, hipStream_t s);
+                           const Geom& g, const Model& md, float* M, float* x,
+                           float* r, float* z, RedBuf rb, Scal* sc,
+                           hipStream_t s, int gn_it, GNLog* log);
+// CG iteration it: p_new = z + beta p_old (it > 0; p_new = z at it = 0),
+// q = H p_new; then x, r, z updates.
+hipError_t launch_pcg_hvp(int dim, int it, const float* z, const float* p_old,
+                          float* p_new, const float* dW, const Geom& g,
+                          const Model& md, float* q, int fixed, double rtol,
+                          RedBuf rb, Scal* sc, hipStream_t s, int gn_it);
+hipError_t launch_pcg_update(int it, const float* p, const float* q,
+                             const float* M, size_t count, const Geom& g,
+                             float* x, float* r, float* z, RedBuf rb,
+                             Scal* sc, hipStream_t s, int gn_it);
 
-// Objective at u + t_i delta for kTrialSteps values of t (t = 0 allowed);
-// also g.delta and max |delta|.  Results in sc->Jt, sc->slope, sc->maxd.
+// Objective at u + t_i delta for kTrialSteps values of t (t = 0 allowed),
+// g.delta and max |delta|, for line-search sweep ls of iteration gn_it.
 hipError_t launch_trial(int dim, const float* T, const float* u,
                         const float* delta, const float* grad, const int* K,
                         const Geom& g, const Model& md, const double* t,
-                        RedBuf rb, Scal* sc, hipStream_t s);
-// u[K[j]] += t delta_j
-hipError_t launch_accept(float* u, const float* delta, const int* K, int nK,
-                         int dim, long long N, double t, hipStream_t s);
+                        RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
+                        LSPass ls, GNLog* log);
+// Armijo decision of sweep ls; u[K[j]] += t delta_j for the accepted t.
+hipError_t launch_ls_accept(float* u, const float* delta, const int* K,
+                            int nK, int dim, long long N, const double* t,
+                            LSPass ls, int ls_max, double c1, int fixed,
+                            double tol_J, double tol_u, int gn_it, Scal* sc,
+                            GNLog* log, hipStream_t s);
+hipError_t launch_gn_reset(Scal* sc, GNLog* log, int n, hipStream_t s);
+// One block: objective of the evaluation (ev_nb partials) and the CG start
+// scalars (in_nb partials of the CG start kernel).
+hipError_t launch_finalize_start(RedBuf rb, int ev_nb, int in_nb,
+                                 const Model& md, Scal* sc, int gn_it,
+                                 GNLog* log, hipStream_t s);
+hipError_t launch_finalize_vhv(const double* part, int nb, Scal* sc,
+                               hipStream_t s);
+
+// --- CG with per-voxel cross-frame sums (cg_tiles.hip) -------------------
+// Float64 per-voxel sums: S = sum_k dW_k . v_k ([N]) and V = sum_k v_k
+// ([D][N]) of z, and of the CG directions (ping-pong by CG iteration).
+struct CgSums {
+  double* Sz;
+  double* Vz;
+  double* Sp[2];
+  double* Vp[2];
+};
+struct CgTiles {             // launch shape of the 2-D Hessian product
+  int nreal, nfg, fpg, grid, vox_grid;
+};
+CgTiles cg_tiles_2d(const Geom& g, int nK);
+hipError_t launch_cgv_init(int dim, const float* grad, const float* dW,
+                           const Geom& g, const Model& md, float* r, float* z,
+                           CgSums sums, RedBuf rb, Scal* sc, hipStream_t s,
+                           int gn_it, GNLog* log);
+hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
+                          float* p_new, const float* dW, const Geom& g,
+                          const Model& md, float* q, CgSums sums, int fixed,
+                          double rtol, RedBuf rb, Scal* sc, hipStream_t s,
+                          int gn_it);
+hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
+                             const float* dW, const Geom& g, const Model& md,
+                             float* x, float* r, float* z, CgSums sums,
+                             RedBuf rb, Scal* sc, hipStream_t s, int gn_it);
+// Test entry: H v for a stored v (2-D); v is copied to vcopy on the way.
+hipError_t launch_hessvec_2d(const float* v, const float* dW, const Geom& g,
+                             const Model& md, float* hv, float* vcopy,
+                             CgSums sums, RedBuf rb, Scal* sc,
+                             hipStream_t s);
 
 hipError_t launch_linear_predict(const float* Y, float* Z, float* Yout,
                                  LinTab tab, int n, int dim, long long N,

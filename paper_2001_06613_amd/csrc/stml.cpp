@@ -61,11 +61,15 @@ struct stml_ctx {
   std::vector<std::vector<int>> K;      // host copies of K_q
   // solver scratch, compact [nK][D][N_finest]
   float *g = nullptr, *dW = nullptr, *x = nullptr, *r = nullptr,
-        *p = nullptr, *z = nullptr, *q = nullptr;
+        *z = nullptr, *q = nullptr, *M = nullptr;
+  float* P[2] = {nullptr, nullptr};      // CG directions, ping-pong
+  CgSums sums{};                         // per-voxel cross-frame sums
   RedBuf rb{};
   Scal* sc = nullptr;
   int* kbuf = nullptr;                  // device frame list for test calls
   Scal* hsc = nullptr;                  // pinned host mirror of sc
+  GNLog* gnlog = nullptr;               // device: one entry per GN iteration
+  GNLog* hlog = nullptr;                // pinned host mirror
   int* hk = nullptr;                    // pinned host staging of frame lists
   bool have_seq = false;
   std::vector<stml_gir_log> logs;
@@ -73,14 +77,14 @@ struct stml_ctx {
   // kernel timing
   struct Rec {
     int kernel, level;
-    double vf;
+    double vf, bytes;
     hipEvent_t a, b;
   };
   struct KStat {
-    double ms = 0.0, vf = 0.0;
+    double ms = 0.0, vf = 0.0, bytes = 0.0;
     long long n = 0;
   };
-  bool timing = false;
+  unsigned timing = 0;                  // bit k: time kernel class k
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::pair<int, int>, KStat> kstats;
@@ -163,12 +167,23 @@ size_t layout(stml_ctx* c, char* base) {
   c->dW = lo.take<float>(vec);
   c->x = lo.take<float>(vec);
   c->r = lo.take<float>(vec);
-  c->p = lo.take<float>(vec);
+  c->P[0] = lo.take<float>(vec);
+  c->P[1] = lo.take<float>(vec);
   c->z = lo.take<float>(vec);
   c->q = lo.take<float>(vec);
+  c->M = lo.take<float>(vec);
+  {
+    size_t NF = (size_t)c->N[c->L - 1];
+    c->sums.Sz = lo.take<double>(NF);
+    c->sums.Vz = lo.take<double>(NF * D);
+    for (int i = 0; i < 2; ++i) {
+      c->sums.Sp[i] = lo.take<double>(NF);
+      c->sums.Vp[i] = lo.take<double>(NF * D);
+    }
+  }
   c->rb.part = lo.take<double>(kRedSlots);
-  c->rb.counter = lo.take<unsigned>(64);
   c->sc = lo.take<Scal>(1);
+  c->gnlog = lo.take<GNLog>(c->o.gn_max > 0 ? c->o.gn_max : 1);
   c->kbuf = lo.take<int>(STML_MAX_FRAMES);
   c->qt.resize(c->T1);
   for (int q = 0; q < c->T1; ++q) {
@@ -228,16 +243,17 @@ hipEvent_t pooled_event(stml_ctx* c) {
   return e;
 }
 
-void tbegin(stml_ctx* c, int kernel, int level, double vf) {
-  if (!c->timing) return;
-  stml_ctx::Rec r{kernel, level, vf, pooled_event(c), pooled_event(c)};
+void tbegin(stml_ctx* c, int kernel, int level, double vf, double bytes) {
+  if (!((c->timing >> kernel) & 1u)) return;
+  stml_ctx::Rec r{kernel, level, vf, bytes, pooled_event(c),
+                  pooled_event(c)};
   if (!r.a || !r.b) return;
   (void)hipEventRecord(r.a, c->stream);
   c->pending.push_back(r);
 }
 
-void tend(stml_ctx* c) {
-  if (!c->timing || c->pending.empty()) return;
+void tend(stml_ctx* c, int kernel) {
+  if (!((c->timing >> kernel) & 1u) || c->pending.empty()) return;
   (void)hipEventRecord(c->pending.back().b, c->stream);
 }
 
@@ -249,6 +265,7 @@ void tresolve(stml_ctx* c) {
       auto& st = c->kstats[{r.kernel, r.level}];
       st.ms += ms;
       st.vf += r.vf;
+      st.bytes += r.bytes;
       st.n += 1;
     }
     c->pool.push_back(r.a);
@@ -265,11 +282,30 @@ int read_scal(stml_ctx* c) {
   return STML_OK;
 }
 
-#define TIMED(KERNEL, LEVEL, VF, CALL) \
-  do {                                 \
-    tbegin(c, KERNEL, LEVEL, VF);      \
+// Algorithmic HBM bytes per voxel-frame of each kernel class (float32
+// fields of D components): what the kernel must read and write once.
+double alg_bytes(int kernel, int D, int cg_it) {
+  switch (kernel) {
+    case STML_K_EVAL: return 4.0 + 12.0 * D;      // T; u; dW, g
+    case STML_K_HESSVEC:                          // z (+p_old), dW; p, q
+      return cg_it > 0 ? 20.0 * D : 16.0 * D;
+    case STML_K_CG_UPDATE:                        // p, q, dW, r (+x); x, r, z
+      return cg_it > 0 ? 32.0 * D : 28.0 * D;
+    case STML_K_CG_INIT: return 16.0 * D;         // g, dW; r, z
+    case STML_K_TRIAL: return 4.0 + 12.0 * D;     // T; u, delta, g
+    case STML_K_ACCEPT: return 12.0 * D;          // u, delta; u
+    case STML_K_PREDICT: return 16.0 * D;         // read y, z; write z, y
+    case STML_K_RESTRICT: return 4.0 * (1 << D) + 4.0;  // per coarse voxel
+    default: return 0.0;
+  }
+}
+
+#define TIMED(KERNEL, LEVEL, VF, CALL) TIMED_IT(KERNEL, LEVEL, VF, 0, CALL)
+#define TIMED_IT(KERNEL, LEVEL, VF, CGIT, CALL)                        \
+  do {                                                                 \
+    tbegin(c, KERNEL, LEVEL, VF, (VF) * alg_bytes(KERNEL, c->d, CGIT)); \
     hipError_t te_ = (CALL);           \
-    tend(c);                           \
+    tend(c, KERNEL);                   \
     HIP_OK(te_);                       \
   } while (0)
 
@@ -355,31 +391,77 @@ int stage_frames(stml_ctx* c, const int* frames, int nk) {
 }
 
 // Jacobi-PCG for H delta = -g at the evaluation just made (g, dW in
-// scratch).  Enqueued only; scalars stay on the device.
-int enqueue_pcg(stml_ctx* c, int level, const Geom& g, const Model& md) {
+// scratch), as part of Gauss-Newton iteration gn_it.  Enqueued only; the
+// scalars stay on the device.
+int enqueue_pcg(stml_ctx* c, int level, const Geom& g, const Model& md,
+                int gn_it) {
   const int D = c->d;
   const size_t count = (size_t)md.nK * D * g.N;
   const double vf = (double)md.nK * g.N;
+  if (D == 2) {
+    TIMED(STML_K_CG_INIT, level, vf,
+          launch_cgv_init(D, c->g, c->dW, g, md, c->r, c->z, c->sums, c->rb,
+                          c->sc, c->stream, gn_it, c->gnlog));
+    for (int it = 0; it < c->o.cg_max; ++it) {
+      float* pn = c->P[it & 1];
+      const float* po = c->P[(it + 1) & 1];
+      TIMED_IT(STML_K_HESSVEC, level, vf, it,
+               launch_cgt_hvp(it, c->z, po, pn, c->dW, g, md, c->q, c->sums,
+                              c->o.parity_mode, c->o.cg_rtol, c->rb, c->sc,
+                              c->stream, gn_it));
+      TIMED_IT(STML_K_CG_UPDATE, level, vf, it,
+               launch_cgv_update(D, it, pn, c->q, c->dW, g, md, c->x, c->r,
+                                 c->z, c->sums, c->rb, c->sc, c->stream,
+                                 gn_it));
+    }
+    return STML_OK;
+  }
   TIMED(STML_K_CG_INIT, level, vf,
-        launch_pcg_init(D, c->g, c->dW, g, md, c->x, c->r, c->z, c->p, c->rb,
-                        c->sc, c->stream));
+        launch_pcg_init(D, c->g, c->dW, g, md, c->M, c->x, c->r, c->z, c->rb,
+                        c->sc, c->stream, gn_it, c->gnlog));
   for (int it = 0; it < c->o.cg_max; ++it) {
+    float* pn = c->P[it & 1];
+    const float* po = c->P[(it + 1) & 1];
     TIMED(STML_K_HESSVEC, level, vf,
-          launch_pcg_hv(D, c->p, c->dW, g, md, c->q, c->rb, c->sc,
-                        c->stream));
+          launch_pcg_hvp(D, it, c->z, po, pn, c->dW, g, md, c->q,
+                         c->o.parity_mode, c->o.cg_rtol, c->rb, c->sc,
+                         c->stream, gn_it));
     TIMED(STML_K_CG_UPDATE, level, vf,
-          launch_pcg_update(D, c->p, c->q, c->dW, g, md, c->x, c->r, c->z,
-                            c->o.parity_mode, c->o.cg_rtol, c->rb, c->sc,
-                            c->stream));
-    if (it + 1 < c->o.cg_max)
-      TIMED(STML_K_CG_PUPDATE, level, vf,
-            launch_pcg_pupdate(c->z, c->p, count, c->sc, c->stream));
+          launch_pcg_update(it, pn, c->q, c->M, count, g, c->x, c->r, c->z,
+                            c->rb, c->sc, c->stream, gn_it));
   }
   return STML_OK;
 }
 
+// Armijo sweeps of one Gauss-Newton iteration: t = 1, 1/2, ..., 2^-ls_max,
+// kTrialSteps per sweep; the first sweep also evaluates t = 0 so that the
+// comparison uses one formula on both sides.
+int ls_passes(int ls_max, std::vector<LSPass>* passes,
+              std::vector<std::vector<double>>* steps) {
+  int next = 0;
+  for (int p = 0; next <= ls_max; ++p) {
+    LSPass ls{p, p == 0 ? 1 : 0, next, 0};
+    std::vector<double> ts(kTrialSteps);
+    int cnt = 0;
+    if (p == 0) ts[cnt++] = 0.0;
+    while (cnt < kTrialSteps) {
+      int e = next <= ls_max ? next : ls_max;
+      ts[cnt++] = std::ldexp(1.0, -e);
+      if (next <= ls_max) ++next;
+    }
+    ls.last = next > ls_max;
+    passes->push_back(ls);
+    steps->push_back(ts);
+  }
+  return (int)passes->size();
+}
+
 // Gauss-Newton on the frames Kdev (nK of them) of `level`, updating u in
-// place.  Mirrors the oracle's gauss_newton step for step.
+// place; mirrors the oracle's gauss_newton step for step.  Every decision
+// (CG stop, Armijo step, Gauss-Newton stop) is taken on the device, so the
+// iterations are enqueued without host round trips; in parity mode the
+// host synchronises once at the end, otherwise after every iteration so
+// that no launches are spent after the stopping rule fired.
 int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
                  stml_gir_log* log) {
   const stml_opts& o = c->o;
@@ -387,84 +469,62 @@ int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
   const Geom g = geom_of(c, level);
   const Model md = model_of(c, level, nK);
   const float* T = c->lv[level].T;
+  const double vf = (double)nK * g.N;
+  std::vector<LSPass> passes;
+  std::vector<std::vector<double>> steps;
+  ls_passes(o.ls_max, &passes, &steps);
+  HIP_OK(launch_gn_reset(c->sc, c->gnlog, o.gn_max, c->stream));
+  for (int it = 0; it < o.gn_max; ++it) {
+    TIMED(STML_K_EVAL, level, vf,
+          launch_eval(D, T, u, Kdev, g, md, c->g, c->dW, c->rb, c->sc,
+                      c->stream, false, it));
+    int rc = enqueue_pcg(c, level, g, md, it);
+    if (rc) return rc;
+    for (size_t pi = 0; pi < passes.size(); ++pi) {
+      TIMED(STML_K_TRIAL, level, vf,
+            launch_trial(D, T, u, c->x, c->g, Kdev, g, md, steps[pi].data(),
+                         c->rb, c->sc, c->stream, it, passes[pi], c->gnlog));
+      TIMED(STML_K_ACCEPT, level, vf,
+            launch_ls_accept(u, c->x, Kdev, nK, D, g.N, steps[pi].data(),
+                             passes[pi], o.ls_max, o.c1, o.parity_mode,
+                             o.tol_J, o.tol_u, it, c->sc, c->gnlog,
+                             c->stream));
+    }
+    if (!o.parity_mode) {
+      rc = read_scal(c);
+      if (rc) return rc;
+      if (c->hsc->gn_stop <= it + 1) break;
+    }
+  }
+  // logs of every iteration that ran
+  HIP_OK(hipMemcpyAsync(c->hlog, c->gnlog, o.gn_max * sizeof(GNLog),
+                        hipMemcpyDeviceToHost, c->stream));
+  int rc = read_scal(c);
+  if (rc) return rc;
   int status = STML_OK;
   std::memset(log, 0, sizeof *log);
   log->n_frames = nK;
   log->J0 = log->J = NAN;
-  const double vf = (double)nK * g.N;
   for (int it = 0; it < o.gn_max; ++it) {
-    TIMED(STML_K_EVAL, level, vf,
-          launch_eval(D, T, u, Kdev, g, md, c->g, c->dW, c->rb, c->sc,
-                      c->stream));
-    int rc = enqueue_pcg(c, level, g, md);
-    if (rc) return rc;
-    // Armijo: t = 1, 1/2, ..., 2^-ls_max, kTrialSteps per sweep; the first
-    // sweep also evaluates t = 0 so the comparison uses one formula.
-    double J0t = 0.0, J = 0.0, slope = 0.0, maxd = 0.0, tacc = -1.0, Jacc = 0;
-    int next = 0;           // exponent of the next step to try
-    bool first = true;
-    int cg_iters = 0, done = 0;
-    while (next <= o.ls_max && tacc < 0) {
-      double ts[kTrialSteps];
-      int cnt = 0, base = 0;
-      if (first) ts[cnt++] = 0.0, base = 1;
-      int e0 = next;
-      while (cnt < kTrialSteps) {
-        int e = next <= o.ls_max ? next : o.ls_max;
-        ts[cnt++] = std::ldexp(1.0, -e);
-        if (next <= o.ls_max) ++next;
-      }
-      TIMED(STML_K_TRIAL, level, vf,
-            launch_trial(D, T, u, c->x, c->g, Kdev, g, md, ts, c->rb, c->sc,
-                         c->stream));
-      rc = read_scal(c);
-      if (rc) return rc;
-      if (first) {
-        J0t = c->hsc->Jt[0];
-        J = c->hsc->J;
-        slope = c->hsc->slope;
-        maxd = c->hsc->maxd;
-        cg_iters = c->hsc->iters;
-        done = c->hsc->done;
-        first = false;
-      }
-      for (int s = base; s < kTrialSteps && tacc < 0; ++s) {
-        int e = e0 + (s - base);
-        if (e > o.ls_max) break;
-        double t = ts[s];
-        if (c->hsc->Jt[s] <= J0t + o.c1 * t * slope) {
-          tacc = t;
-          Jacc = c->hsc->Jt[s];
-        }
-      }
-    }
-    if (it == 0) {
-      log->J0 = J;
-      log->J = J;
-    }
-    log->D = c->hsc->D;
-    log->S = c->hsc->S;
-    log->P = c->hsc->P;
-    if (it < 64) log->cg_iterations[it] = cg_iters;
-    if (tacc < 0) {
+    const GNLog& L = c->hlog[it];
+    if (L.status < 0) break;
+    if (it == 0) log->J0 = log->J = L.J;
+    if (it < 64) log->cg_iterations[it] = L.cg;
+    if (L.status == 1) {
       status = STML_WLINESEARCH;
       break;
     }
-    TIMED(STML_K_ACCEPT, level, vf,
-          launch_accept(u, c->x, Kdev, nK, D, g.N, tacc, c->stream));
-    if (it < 64) log->step[it] = tacc;
+    if (it < 64) log->step[it] = L.t;
     log->gn_iterations += 1;
-    log->J = Jacc;
-    if (done == 2) {
+    log->J = L.Jacc;
+    if (L.status == 2) {
       status = STML_EBREAKDOWN;
       break;
     }
-    if (!o.parity_mode && (J - Jacc) <= o.tol_J * std::fabs(J) &&
-        tacc * maxd <= o.tol_u)
-      break;
   }
-  HIP_OK(hipStreamSynchronize(c->stream));
-  tresolve(c);
+  log->D = c->hsc->D;
+  log->S = c->hsc->S;
+  log->P = c->hsc->P;
   log->status = status;
   return status;
 }
@@ -520,7 +580,7 @@ int all_frame_D(stml_ctx* c, int level, const float* U, double* out) {
   const Geom g = geom_of(c, level);
   const Model md = model_of(c, level, c->n);
   HIP_OK(launch_eval(c->d, c->lv[level].T, U, c->qt[T].K, g, md, nullptr,
-                     nullptr, c->rb, c->sc, c->stream));
+                     nullptr, c->rb, c->sc, c->stream, true, 0));
   int rc = read_scal(c);
   if (rc) return rc;
   *out = c->hsc->D;
@@ -580,13 +640,14 @@ int stml_create(const stml_opts* o, int n, const int* extent, void* stream,
   if (hipHostMalloc((void**)&c->hsc, sizeof(Scal), hipHostMallocDefault) !=
           hipSuccess ||
       hipHostMalloc((void**)&c->hk, STML_MAX_FRAMES * sizeof(int),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&c->hlog,
+                    (o->gn_max > 0 ? o->gn_max : 1) * sizeof(GNLog),
                     hipHostMallocDefault) != hipSuccess) {
     stml_destroy(c);
     return STML_EDEVICE;
   }
-  if (hipMemsetAsync(c->rb.counter, 0, 64 * sizeof(unsigned), c->stream) !=
-          hipSuccess ||
-      hipMemsetAsync(c->sc, 0, sizeof(Scal), c->stream) != hipSuccess ||
+  if (hipMemsetAsync(c->sc, 0, sizeof(Scal), c->stream) != hipSuccess ||
       upload_tables(c) != STML_OK) {
     stml_destroy(c);
     return STML_EDEVICE;
@@ -602,6 +663,7 @@ void stml_destroy(stml_ctx* c) {
   for (hipEvent_t e : c->pool) (void)hipEventDestroy(e);
   if (c->hsc) (void)hipHostFree(c->hsc);
   if (c->hk) (void)hipHostFree(c->hk);
+  if (c->hlog) (void)hipHostFree(c->hlog);
   delete c;
 }
 
@@ -807,7 +869,7 @@ int stml_eval(stml_ctx* c, int level, const int* frames, int nk,
   Model md = model_of(c, level, nk);
   HIP_OK(launch_eval(c->d, c->lv[level].T, u, c->kbuf, g, md,
                      grad ? grad : c->g, dW ? dW : c->dW, c->rb, c->sc,
-                     c->stream));
+                     c->stream, true, 0));
   rc = read_scal(c);
   if (rc) return rc;
   out[0] = c->hsc->J;
@@ -829,9 +891,15 @@ int stml_hessvec(stml_ctx* c, int level, const int* frames, int nk,
   Geom g = geom_of(c, level);
   Model md = model_of(c, level, nk);
   HIP_OK(launch_eval(c->d, c->lv[level].T, u, c->kbuf, g, md, c->g, c->dW,
-                     c->rb, c->sc, c->stream));
-  TIMED(STML_K_HESSVEC, level, (double)nk * g.N,
-        launch_hessvec(c->d, v, c->dW, g, md, hv, c->rb, c->sc, c->stream));
+                     c->rb, c->sc, c->stream, true, 0));
+  if (c->d == 2)
+    TIMED(STML_K_HESSVEC, level, (double)nk * g.N,
+          launch_hessvec_2d(v, c->dW, g, md, hv, c->P[0], c->sums, c->rb,
+                            c->sc, c->stream));
+  else
+    TIMED(STML_K_HESSVEC, level, (double)nk * g.N,
+          launch_hessvec(c->d, v, c->dW, g, md, hv, c->rb, c->sc,
+                         c->stream));
   rc = read_scal(c);
   if (rc) return rc;
   if (vHv) *vHv = c->hsc->vHv;
@@ -849,9 +917,10 @@ int stml_gn_direction(stml_ctx* c, int level, const int* frames, int nk,
   if (rc) return rc;
   Geom g = geom_of(c, level);
   Model md = model_of(c, level, nk);
+  HIP_OK(launch_gn_reset(c->sc, c->gnlog, 1, c->stream));
   HIP_OK(launch_eval(c->d, c->lv[level].T, u, c->kbuf, g, md, c->g, c->dW,
-                     c->rb, c->sc, c->stream));
-  rc = enqueue_pcg(c, level, g, md);
+                     c->rb, c->sc, c->stream, false, 0));
+  rc = enqueue_pcg(c, level, g, md, 0);
   if (rc) return rc;
   HIP_OK(hipMemcpyAsync(delta, c->x, (size_t)nk * c->d * g.N * sizeof(float),
                         hipMemcpyDeviceToDevice, c->stream));
@@ -862,32 +931,34 @@ int stml_gn_direction(stml_ctx* c, int level, const int* frames, int nk,
   return STML_OK;
 }
 
-int stml_timing(stml_ctx* c, int on) {
-  if (!c) return STML_EINVAL;
+int stml_timing(stml_ctx* c, int mask) {
+  if (!c || mask < 0) return STML_EINVAL;
   HIP_OK(hipStreamSynchronize(c->stream));
   tresolve(c);
-  if (on) c->kstats.clear();
-  c->timing = on != 0;
+  if (mask) c->kstats.clear();
+  c->timing = (unsigned)mask & ((1u << STML_K_COUNT) - 1u);
   return STML_OK;
 }
 
 int stml_timing_get(stml_ctx* c, int kernel, int level, double* ms,
-                    long long* n, double* vf) {
+                    long long* n, double* vf, double* bytes) {
   if (!c || kernel < 0 || kernel >= STML_K_COUNT) return STML_EINVAL;
   HIP_OK(hipStreamSynchronize(c->stream));
   tresolve(c);
-  double tms = 0.0, tvf = 0.0;
+  double tms = 0.0, tvf = 0.0, tb = 0.0;
   long long tn = 0;
   for (auto& kv : c->kstats) {
     if (kv.first.first != kernel) continue;
     if (level >= 0 && kv.first.second != level) continue;
     tms += kv.second.ms;
     tvf += kv.second.vf;
+    tb += kv.second.bytes;
     tn += kv.second.n;
   }
   if (ms) *ms = tms;
   if (n) *n = tn;
   if (vf) *vf = tvf;
+  if (bytes) *bytes = tb;
   return STML_OK;
 }
 

@@ -15,8 +15,8 @@ constexpr int kMaxFPT = 16;        // max frames one thread keeps in registers
 constexpr int kMaxChunks = 16;     // waves per block -> |K| <= 256
 constexpr int kTrialSteps = 5;     // Armijo steps evaluated per pass
 constexpr int kXCD = 8;            // MI355X: 8 accelerator complex dies
-constexpr int kMaxTileBlocks = 2048;
-constexpr int kMaxElemBlocks = 2048;
+constexpr int kMaxTileBlocks = 512;
+constexpr int kMaxElemBlocks = 1024;
 
 // Level geometry.  D = 2 uses m[0] (slow) and m[1] (fast); D = 3 uses all.
 struct Geom {
@@ -46,7 +46,8 @@ struct Model {
 // last block of a kernel, read by later kernels.
 struct Scal {
   double J, D, S, P;          // objective at the evaluation point
-  double rz, r0, a, beta;     // CG scalars
+  double rzh[2];              // r.z of CG iteration it in slot it & 1
+  double r0, a, beta;         // CG scalars
   double pq, rr;
   double Jt[8];               // objective at the trial steps
   double slope;               // g . delta
@@ -55,7 +56,27 @@ struct Scal {
   int done;                   // 0 running, 1 converged, 2 breakdown
   int iters;                  // CG iterations taken
   int bad;                    // non-finite input count
+  int gn_stop;                // Gauss-Newton iterations >= gn_stop do nothing
+};
+
+// One Gauss-Newton iteration as decided on the device.
+struct GNLog {
+  double J;                   // objective at the evaluation
+  double J0t;                 // objective at t = 0 in the trial sweep
+  double Jacc;                // objective at the accepted step
+  double t;                   // accepted step
+  double slope, maxd;         // g . delta and max |delta|
+  int cg;                     // CG iterations
+  int status;                 // -1 not run, 0 accepted, 1 no step found,
+                              // 2 accepted after a CG breakdown
+  int next_pass;              // line-search pass that still has to run
   int pad;
+};
+
+// Armijo sweep p: steps t[0..kTrialSteps) with exponents e0 + (s - base)
+// for s >= base (slot 0 of the first sweep holds t = 0).
+struct LSPass {
+  int p, base, e0, last;      // last: no further sweep after this one
 };
 
 // ---------------------------------------------------------------- helpers
@@ -93,6 +114,28 @@ __device__ __forceinline__ Pos<D> make_pos(const Geom& g, long long x) {
 // voxel itself (replicate padding), which turns the plain Laplacian into the
 // Neumann graph Laplacian L.  All arithmetic is float64 on float32 loads.
 
+// Field accessors: a stored float32 plane, or the CG direction
+// p = z + beta p_old formed on the fly and rounded to float32 exactly as the
+// kernel that stores it rounds it.
+struct Src1 {
+  const float* __restrict__ a;
+  __device__ __forceinline__ float ld(unsigned i) const { return a[i]; }
+  __device__ __forceinline__ double operator()(unsigned i) const {
+    return (double)a[i];
+  }
+};
+struct SrcLin {
+  const float* __restrict__ z;
+  const float* __restrict__ p;
+  float b;
+  __device__ __forceinline__ float ld(unsigned i) const {
+    return __builtin_fmaf(b, p[i], z[i]);
+  }
+  __device__ __forceinline__ double operator()(unsigned i) const {
+    return (double)ld(i);
+  }
+};
+
 // Offsets (in elements) of the clamped neighbours at -2, -1, +1, +2 along
 // every axis, and whether the -1 / +1 neighbour exists.
 template <int D>
@@ -119,36 +162,90 @@ __device__ __forceinline__ Nbr<D> neighbours(const Pos<D>& p, const Geom& g) {
 }
 
 // (L v)(x) from the 2D face neighbours.
-template <int D>
-__device__ __forceinline__ double lap_c(const float* __restrict__ v,
-                                        unsigned idx, const Nbr<D>& nb) {
-  double c = (double)v[idx];
+template <int D, class F>
+__device__ __forceinline__ double lap_c(const F& v, unsigned idx,
+                                        const Nbr<D>& nb) {
+  double c = v(idx);
   double s = 0.0;
 #pragma unroll
   for (int a = 0; a < D; ++a)
-    s += ((double)v[idx + nb.m1[a]] - c) + ((double)v[idx + nb.p1[a]] - c);
+    s += (v(idx + nb.m1[a]) - c) + (v(idx + nb.p1[a]) - c);
   return s;
 }
 
-// B^T B v at p (without the 1/h^2 or 1/h^4 factor) and this voxel's share
-// of ||B v||^2: diffusion -> (-L v, forward-face differences squared);
-// curvature -> (L (L v), (L v)^2), L(Lv) from 1 + 4D + 2D(D-1) loads.
+// Stencil points: 0 = the voxel; 1 + 2a (+0 / +1) = its -1 / +1 neighbour
+// along axis a; 1 + 2D + 2a (+0 / +1) = the -2 / +2 neighbour; then for
+// every pair a < b the four diagonal neighbours (sa, sb) in {-1,+1}^2.
+// Offsets are clamped per axis (replicate padding).
 template <int D>
-__device__ __forceinline__ void reg_terms(const float* __restrict__ v,
-                                          const Pos<D>& p, const Geom& g,
-                                          int reg, double& btb,
-                                          double& energy) {
+struct StencilPts {
+  static constexpr int kFace = 1 + 2 * D;          // diffusion
+  static constexpr int kAll = 1 + 4 * D + 2 * D * (D - 1);  // curvature
+};
+
+template <int D, int NP>
+__device__ __forceinline__ void stencil_offsets(const Nbr<D>& nb, int* off) {
+  off[0] = 0;
+#pragma unroll
+  for (int a = 0; a < D; ++a) {
+    off[1 + 2 * a] = nb.m1[a];
+    off[2 + 2 * a] = nb.p1[a];
+  }
+  if (NP > 1 + 2 * D) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      off[1 + 2 * D + 2 * a] = nb.m2[a];
+      off[2 + 2 * D + 2 * a] = nb.p2[a];
+    }
+    int k = 1 + 4 * D;
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+#pragma unroll
+      for (int b = a + 1; b < D; ++b) {
+        off[k++] = nb.m1[a] + nb.m1[b];
+        off[k++] = nb.m1[a] + nb.p1[b];
+        off[k++] = nb.p1[a] + nb.m1[b];
+        off[k++] = nb.p1[a] + nb.p1[b];
+      }
+  }
+}
+
+// Index of the diagonal point (a, sa, b, sb) in the curvature stencil.
+template <int D>
+__device__ __forceinline__ constexpr int diag_index(int a, int sa, int b,
+                                                    int sb) {
+  // pairs (a < b) in order (0,1), (0,2), (1,2)
+  int lo = a < b ? a : b, hi = a < b ? b : a;
+  int slo = a < b ? sa : sb, shi = a < b ? sb : sa;
+  int pair = (D == 2) ? 0 : (lo == 0 ? hi - 1 : 2);
+  return 1 + 4 * D + 4 * pair + 2 * slo + shi;
+}
+
+// B^T B v at p (without the 1/h^2 or 1/h^4 factor), this voxel's share of
+// ||B v||^2 and v at p: diffusion (REG 0) -> (-L v, forward-face
+// differences squared); curvature (REG 1) -> (L (L v), (L v)^2).  All the
+// stencil's loads are issued first, then the float64 arithmetic.
+template <int D, int REG, class F>
+__device__ __forceinline__ void reg_terms(const F& f, const Pos<D>& p,
+                                          const Geom& g, double& btb,
+                                          double& energy, double& centre) {
+  constexpr int NP = REG ? StencilPts<D>::kAll : StencilPts<D>::kFace;
   const Nbr<D> nb = neighbours<D>(p, g);
-  const unsigned i = p.idx;
-  const double c = (double)v[i];
+  int off[NP];
+  stencil_offsets<D, NP>(nb, off);
+  float v[NP];
+#pragma unroll
+  for (int i = 0; i < NP; ++i) v[i] = f.ld(p.idx + off[i]);
+  const double c = (double)v[0];
+  centre = c;
   double vm[D], vp[D], Lc = 0.0;
 #pragma unroll
   for (int a = 0; a < D; ++a) {
-    vm[a] = (double)v[i + nb.m1[a]];
-    vp[a] = (double)v[i + nb.p1[a]];
+    vm[a] = (double)v[1 + 2 * a];
+    vp[a] = (double)v[2 + 2 * a];
     Lc += (vm[a] - c) + (vp[a] - c);
   }
-  if (reg == 0) {
+  if (REG == 0) {
     double e = 0.0;
 #pragma unroll
     for (int a = 0; a < D; ++a) e += (vp[a] - c) * (vp[a] - c);
@@ -156,21 +253,6 @@ __device__ __forceinline__ void reg_terms(const float* __restrict__ v,
     energy = e;
     return;
   }
-  // diagonal neighbours c + sa e_a + sb e_b (a < b), clamped per axis
-  double dg[D][2][D][2];
-#pragma unroll
-  for (int a = 0; a < D; ++a)
-#pragma unroll
-    for (int b = a + 1; b < D; ++b)
-#pragma unroll
-      for (int sa = 0; sa < 2; ++sa)
-#pragma unroll
-        for (int sb = 0; sb < 2; ++sb) {
-          int o = (sa ? nb.p1[a] : nb.m1[a]) + (sb ? nb.p1[b] : nb.m1[b]);
-          double val = (double)v[i + o];
-          dg[a][sa][b][sb] = val;
-          dg[b][sb][a][sa] = val;
-        }
   double LL = 0.0;
 #pragma unroll
   for (int a = 0; a < D; ++a)
@@ -178,12 +260,13 @@ __device__ __forceinline__ void reg_terms(const float* __restrict__ v,
     for (int sa = 0; sa < 2; ++sa) {
       bool has = sa ? nb.hp[a] : nb.hm[a];
       double vn = sa ? vp[a] : vm[a];
-      double far = (double)v[i + (sa ? nb.p2[a] : nb.m2[a])];
+      double far = (double)v[1 + 2 * D + 2 * a + sa];
       double Ln = (far - vn) + (c - vn);
 #pragma unroll
       for (int b = 0; b < D; ++b) {
         if (b == a) continue;
-        Ln += (dg[a][sa][b][0] - vn) + (dg[a][sa][b][1] - vn);
+        Ln += ((double)v[diag_index<D>(a, sa, b, 0)] - vn) +
+              ((double)v[diag_index<D>(a, sa, b, 1)] - vn);
       }
       LL += has ? (Ln - Lc) : 0.0;
     }
@@ -192,21 +275,22 @@ __device__ __forceinline__ void reg_terms(const float* __restrict__ v,
 }
 
 // Shares of ||B u||^2, <B u, B w>, ||B w||^2 at p (quadratic expansion of S).
-template <int D>
-__device__ __forceinline__ void reg_cross(const float* __restrict__ u,
-                                          const float* __restrict__ w,
+template <int D, int REG>
+__device__ __forceinline__ void reg_cross(const float* __restrict__ uptr,
+                                          const float* __restrict__ wptr,
                                           const Pos<D>& p, const Geom& g,
-                                          int reg, double& uu, double& uw,
+                                          double& uu, double& uw,
                                           double& ww) {
+  const Src1 u{uptr}, w{wptr};
   const Nbr<D> nb = neighbours<D>(p, g);
   const unsigned i = p.idx;
-  if (reg == 0) {
-    double cu = (double)u[i], cw = (double)w[i];
+  if (REG == 0) {
+    double cu = u(i), cw = w(i);
     double a_uu = 0, a_uw = 0, a_ww = 0;
 #pragma unroll
     for (int a = 0; a < D; ++a) {
-      double du = (double)u[i + nb.p1[a]] - cu;
-      double dw = (double)w[i + nb.p1[a]] - cw;
+      double du = u(i + nb.p1[a]) - cu;
+      double dw = w(i + nb.p1[a]) - cw;
       a_uu += du * du;
       a_uw += du * dw;
       a_ww += dw * dw;
@@ -318,6 +402,13 @@ __device__ __forceinline__ double warp_value(const float* __restrict__ T,
   double W, dW[D];
   warp_sample<D>(T, g, p, uv, W, dW);
   return W;
+}
+
+// Index of this thread's wave in the block, as a wave-uniform value (the
+// compiler cannot prove threadIdx.x / 64 uniform; readfirstlane lets loop
+// bounds and plane pointers that depend on it live in scalar registers).
+__device__ __forceinline__ int wave_id() {
+  return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
 }
 
 // Wave-level sum (butterfly, fixed order -> deterministic).
