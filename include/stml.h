@@ -222,6 +222,60 @@ int stml_timing_get(stml_ctx* ctx, int kernel, int level, double* total_ms,
                     long long* launches, double* voxel_frames,
                     double* bytes);
 
+/* --- learned temporal predictor -----------------------------------------
+ * A convolutional encoder-decoder that refines the linear interpolation of
+ * a frame t between its registered neighbours l < t < r (Sec. 3 predicts
+ * such frames by interpolation; the network adds a learned correction).
+ * 2-D only.  Input channels: frame_l, frame_t, frame_r, u_l / h, u_r / h
+ * (displacements in pixels of the level, h = cell width); output: the
+ * 2-channel correction c, u_t = w_l u_l + w_r u_r + h c with the linear
+ * weights w_l = (r - t) / (r - l), w_r = (t - l) / (r - l).  Encoder 3x3
+ * convolutions 32/64/128/128 with ReLU and 2x2 average pooling, decoder
+ * with nearest upsampling and skip concatenation, 1x1 head.  Parameters are
+ * one float32 vector (layer by layer W[tap][c_out][c_in] then b[c_out]);
+ * kernels use bfloat16 weights and activations with float32 accumulation
+ * (MFMA), float32 gradients, Adam on the float32 master copy.  Extents must
+ * be multiples of 8.  All buffers: caller-owned device memory; the net
+ * keeps the last assembled batch until the next one. */
+typedef struct stml_net stml_net;
+
+int stml_net_param_count(int dim);
+size_t stml_net_workspace_bytes(int dim, int max_batch,
+                                const int* max_extent);
+int stml_net_create(int dim, int max_batch, const int* max_extent,
+                    void* hip_stream, void* workspace_dev, size_t ws_bytes,
+                    stml_net** out);
+void stml_net_destroy(stml_net* net);
+/* Float32 parameters in and out (setting them also resets Adam). */
+int stml_net_set_params(stml_net* net, const float* params_dev);
+int stml_net_get_params(const stml_net* net, float* params_dev);
+/* A batch from planar float32 channels x [batch][channels][extent] and,
+ * optionally, the target correction [batch][extent][2]. */
+int stml_net_set_input(stml_net* net, const float* x_dev, int channels,
+                       const float* target_dev, int batch, const int* extent);
+/* A batch of frames (triples[3b] = t, l, r with l < t < r) from level
+ * images [n][extent] and displacements [n][2][extent]; with_target: the
+ * target correction (u_t - linear interpolation) / h from the same field. */
+int stml_net_assemble(stml_net* net, const float* frames_dev,
+                      const float* u_dev, const int* extent, double h,
+                      const int* triples, int batch, int with_target);
+/* Forward pass; out_dev (may be NULL) receives [batch][extent][32] floats
+ * whose first 2 channels are the correction. */
+int stml_net_forward(stml_net* net, float* out_dev);
+/* u_t = linear interpolation + h * correction into u_dev [n][2][extent]
+ * for the frames of the last assembled batch (after stml_net_forward). */
+int stml_net_emit(stml_net* net, double h, float* u_dev);
+/* Mean squared error of the correction and its gradient wrt the
+ * parameters (no update). */
+int stml_net_gradient(stml_net* net, float* grad_dev, double* loss);
+/* Forward, loss, backward and one Adam step (lr > 0). */
+int stml_net_train_step(stml_net* net, double lr, double* loss);
+/* Use net for the prediction of frames left out of K_q on every level
+ * whose extents are multiples of 8 (NULL: interpolation only).  The
+ * interpolation predictor of Sec. 3 stays the fallback: per prediction
+ * step the start guess with the lower objective on K_{q+1} is kept. */
+int stml_set_predictor_net(stml_ctx* ctx, stml_net* net);
+
 #ifdef __cplusplus
 }
 #endif

@@ -25,6 +25,9 @@ Precision points mirror the GPU path: weights and activations are rounded
 to bfloat16 (round to nearest even) where the GPU stores them in bfloat16,
 sums are exact (float64 here); the head output is not rounded.  With
 ``bf16=False`` every rounding is skipped (used by the finite-difference pin).
+``ACCUM`` selects the accumulation type of the convolutions: float64 by
+default; the parity tests also run float32 once to measure how far a
+float32 accumulation moves the bfloat16 roundings (their noise floor).
 """
 
 import numpy as np
@@ -75,6 +78,9 @@ def _r(x, bf16):
     return to_bf16(x) if bf16 else np.asarray(x, dtype=np.float64)
 
 
+ACCUM = np.float64
+
+
 def conv(x, W, b, k):
     """Zero-padded convolution (cross-correlation), NHWC.
 
@@ -83,32 +89,36 @@ def conv(x, W, b, k):
     """
     B, H, Wd, _ = x.shape
     co = W.shape[1]
-    y = np.zeros((B, H, Wd, co)) + b
+    y = (np.zeros((B, H, Wd, co)) + b).astype(ACCUM)
     r = k // 2
-    xp = np.pad(x, ((0, 0), (r, r), (r, r), (0, 0)))
+    xp = np.pad(x, ((0, 0), (r, r), (r, r), (0, 0))).astype(ACCUM)
+    Wa = W.astype(ACCUM)
     for tap in range(k * k):
         dy, dx = divmod(tap, k)
         xs = xp[:, dy:dy + H, dx:dx + Wd, :]
-        y += np.tensordot(xs, W[tap], axes=([3], [1]))
-    return y
+        y += np.tensordot(xs, Wa[tap], axes=([3], [1])).astype(ACCUM)
+    return y.astype(np.float64)
 
 
 def conv_backward(x, W, k, dy):
     """Gradients of conv wrt x, W and b for upstream gradient dy."""
     B, H, Wd, ci = x.shape
     r = k // 2
-    xp = np.pad(x, ((0, 0), (r, r), (r, r), (0, 0)))
+    xp = np.pad(x, ((0, 0), (r, r), (r, r), (0, 0))).astype(ACCUM)
+    dya = dy.astype(ACCUM)
+    Wa = W.astype(ACCUM)
     dxp = np.zeros_like(xp)
-    dW = np.zeros_like(W)
+    dW = np.zeros(W.shape, dtype=ACCUM)
     for tap in range(k * k):
         ty, tx = divmod(tap, k)
         xs = xp[:, ty:ty + H, tx:tx + Wd, :]
-        dW[tap] = np.tensordot(dy, xs, axes=([0, 1, 2], [0, 1, 2]))
-        dxp[:, ty:ty + H, tx:tx + Wd, :] += np.tensordot(dy, W[tap],
+        dW[tap] = np.tensordot(dya, xs, axes=([0, 1, 2], [0, 1, 2]))
+        dxp[:, ty:ty + H, tx:tx + Wd, :] += np.tensordot(dya, Wa[tap],
                                                          axes=([3], [0]))
     dx = dxp[:, r:r + H, r:r + Wd, :]
-    db = dy.sum(axis=(0, 1, 2))
-    return dx, dW, db
+    db = dya.sum(axis=(0, 1, 2))
+    return (dx.astype(np.float64), dW.astype(np.float64),
+            db.astype(np.float64))
 
 
 def pool(x):

@@ -95,6 +95,21 @@ SIGNATURES = {
     "stml_eval": (_I, [_P, _I, _IP, _I, _P, _DP, _P, _P]),
     "stml_hessvec": (_I, [_P, _I, _IP, _I, _P, _P, _P, _DP]),
     "stml_gn_direction": (_I, [_P, _I, _IP, _I, _P, _P, _IP]),
+    "stml_net_param_count": (_I, [_I]),
+    "stml_net_workspace_bytes": (ctypes.c_size_t, [_I, _I, _IP]),
+    "stml_net_create": (_I, [_I, _I, _IP, _P, _P, ctypes.c_size_t,
+                             ctypes.POINTER(_P)]),
+    "stml_net_destroy": (None, [_P]),
+    "stml_net_set_params": (_I, [_P, _P]),
+    "stml_net_get_params": (_I, [_P, _P]),
+    "stml_net_set_input": (_I, [_P, _P, _I, _P, _I, _IP]),
+    "stml_net_assemble": (_I, [_P, _P, _P, _IP, ctypes.c_double, _IP, _I,
+                               _I]),
+    "stml_net_forward": (_I, [_P, _P]),
+    "stml_net_emit": (_I, [_P, ctypes.c_double, _P]),
+    "stml_net_gradient": (_I, [_P, _P, _DP]),
+    "stml_net_train_step": (_I, [_P, ctypes.c_double, _DP]),
+    "stml_set_predictor_net": (_I, [_P, _P]),
     "stml_timing": (_I, [_P, _I]),
     "stml_timing_get": (_I, [_P, _I, _I, _DP,
                              ctypes.POINTER(ctypes.c_longlong), _DP, _DP]),
@@ -303,6 +318,11 @@ class STML:
                         "steps": list(lg.step[:max(it, 0)])})
         return out
 
+    def set_predictor_net(self, net):
+        self._net_ref = net
+        return self._check(self.lib.stml_set_predictor_net(
+            self.ctx, net.net if net is not None else None))
+
     def timing(self, kernels):
         """Start timing the named kernel classes (True: all), or stop (None,
         False or an empty list)."""
@@ -366,6 +386,112 @@ class STML:
                                                _ptr(u), _ptr(delta),
                                                ctypes.byref(cg)))
         return delta, cg.value
+
+
+class Net:
+    """The learned predictor network (stml_net_* entry points)."""
+
+    OUT_LD = 32
+
+    def __init__(self, max_batch, max_extent, dim=2, stream=None):
+        import torch
+
+        self.torch = torch
+        self.lib = load()
+        self.dim = dim
+        ext = _int_array(max_extent)
+        nbytes = self.lib.stml_net_workspace_bytes(dim, max_batch, ext)
+        if nbytes == 0:
+            raise STMLError(STML_EINVAL, "invalid network shape")
+        self.device = torch.device("cuda", torch.cuda.current_device())
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8,
+                                     device=self.device)
+        self.stream = stream if stream is not None else \
+            torch.cuda.current_stream(self.device)
+        net = ctypes.c_void_p()
+        rc = self.lib.stml_net_create(dim, max_batch, ext,
+                                      ctypes.c_void_p(self.stream.cuda_stream),
+                                      _ptr(self.workspace), nbytes,
+                                      ctypes.byref(net))
+        if rc != STML_OK:
+            raise STMLError(rc, "stml_net_create failed")
+        self.net = net
+        self.nparam = self.lib.stml_net_param_count(dim)
+
+    def _check(self, rc):
+        if rc != STML_OK:
+            raise STMLError(rc, "stml_net call failed")
+
+    def close(self):
+        if getattr(self, "net", None):
+            self.lib.stml_net_destroy(self.net)
+            self.net = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, params):
+        p = self.torch.as_tensor(params, dtype=self.torch.float32).to(
+            self.device).contiguous()
+        self._check(self.lib.stml_net_set_params(self.net, _ptr(p)))
+
+    def get_params(self):
+        p = self.torch.empty(self.nparam, dtype=self.torch.float32,
+                             device=self.device)
+        self._check(self.lib.stml_net_get_params(self.net, _ptr(p)))
+        return p
+
+    def set_input(self, x, target=None):
+        """x: [B][C][H][W] float32 (C <= 32); target [B][H][W][2]."""
+        x = self.torch.as_tensor(x, dtype=self.torch.float32).to(
+            self.device).contiguous()
+        B, C, H, W = x.shape
+        t = None
+        if target is not None:
+            t = self.torch.as_tensor(target, dtype=self.torch.float32).to(
+                self.device).contiguous()
+        self._input_refs = (x, t)
+        self._check(self.lib.stml_net_set_input(
+            self.net, _ptr(x), C, _ptr(t) if t is not None else None, B,
+            _int_array((H, W))))
+        self.cur = (B, H, W)
+
+    def assemble(self, frames, u, h, triples, with_target=False):
+        """frames [n][H][W], u [n][2][H][W] device tensors; triples
+        [(t, l, r), ...]."""
+        H, W = frames.shape[1:]
+        flat = [int(v) for tr in triples for v in tr]
+        self._check(self.lib.stml_net_assemble(
+            self.net, _ptr(frames), _ptr(u), _int_array((H, W)), float(h),
+            _int_array(flat), len(triples), int(bool(with_target))))
+        self.cur = (len(triples), H, W)
+
+    def forward(self):
+        B, H, W = self.cur
+        out = self.torch.empty((B, H, W, self.OUT_LD), dtype=self.torch.float32,
+                               device=self.device)
+        self._check(self.lib.stml_net_forward(self.net, _ptr(out)))
+        return out[..., :2]
+
+    def emit(self, h, u):
+        self._check(self.lib.stml_net_emit(self.net, float(h), _ptr(u)))
+
+    def gradient(self):
+        g = self.torch.empty(self.nparam, dtype=self.torch.float32,
+                             device=self.device)
+        loss = ctypes.c_double()
+        self._check(self.lib.stml_net_gradient(self.net, _ptr(g),
+                                               ctypes.byref(loss)))
+        return loss.value, g
+
+    def train_step(self, lr):
+        loss = ctypes.c_double()
+        self._check(self.lib.stml_net_train_step(self.net, float(lr),
+                                                 ctypes.byref(loss)))
+        return loss.value
 
 
 def exported_symbols(path=LIB_PATH):

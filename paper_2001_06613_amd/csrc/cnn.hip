@@ -1,0 +1,1094 @@
+// Learned temporal predictor: a convolutional encoder-decoder trained and
+// run with hand-written bfloat16 MFMA kernels (float32 accumulation).
+//
+// Network (2-D): input [frame_l, frame_t, frame_r, u_l / h, u_r / h]
+// (7 channels, NHWC, padded to 32), encoder convolutions 32/64/128/128
+// (3x3, ReLU) with 2x2 average pooling, decoder with nearest 2x upsampling
+// and skip concatenation [skip, up] (128/64/32), 1x1 head to the 2-channel
+// correction in level pixels.  Parameters: one float32 vector, layer by
+// layer W[tap][c_out][c_in] then b[c_out] (the order of the CPU reference).
+//
+// Convolution as an implicit GEMM on v_mfma_f32_16x16x32_bf16: a wave
+// multiplies a 16 (output channels) x 32 (input channels) weight slice by a
+// 32 x 16 (pixels) input slice.  Forward: A = weights, B = input.
+// Backward data: the same kernel with the flipped, transposed weights.
+// Weight gradient: pixels are the reduction dimension; 32-pixel chunks of
+// the upstream gradient and of the shifted input are staged in LDS
+// transposed, split-K partials are summed in a fixed order by the Adam
+// kernel.  Activations are bfloat16; gradients float32 (rounded to bfloat16
+// where they enter a matrix instruction).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+#include "../../include/stml.h"
+#include "launch.h"
+
+namespace stml {
+namespace cnn {
+
+typedef __bf16 bf16;
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+
+constexpr int kCinPad = 32;
+constexpr int kOutLd = 32;     // channels of the head output (2 real)
+
+struct LayerDef {
+  const char* name;
+  int ci, co, k;
+};
+constexpr int kLayers = 15;
+constexpr LayerDef kDefs[kLayers] = {
+    {"e1a", 7, 32, 3},    {"e1b", 32, 32, 3},   {"e2a", 32, 64, 3},
+    {"e2b", 64, 64, 3},   {"e3a", 64, 128, 3},  {"e3b", 128, 128, 3},
+    {"e4a", 128, 128, 3}, {"e4b", 128, 128, 3}, {"d3a", 256, 128, 3},
+    {"d3b", 128, 128, 3}, {"d2a", 192, 64, 3},  {"d2b", 64, 64, 3},
+    {"d1a", 96, 32, 3},   {"d1b", 32, 32, 3},   {"head", 32, 2, 1},
+};
+enum { E1A, E1B, E2A, E2B, E3A, E3B, E4A, E4B, D3A, D3B, D2A, D2B, D1A, D1B,
+       HEAD };
+
+static int rup(int v, int m) { return (v + m - 1) / m * m; }
+
+// ------------------------------------------------------------ kernels
+
+__device__ __forceinline__ bf16x8 load8(const bf16* p) {
+  return *reinterpret_cast<const bf16x8*>(p);
+}
+__device__ __forceinline__ bf16x8 load8(const float* p) {
+  f32x4 a = *reinterpret_cast<const f32x4*>(p);
+  f32x4 b = *reinterpret_cast<const f32x4*>(p + 4);
+  bf16x8 r;
+  r[0] = (bf16)a[0]; r[1] = (bf16)a[1]; r[2] = (bf16)a[2]; r[3] = (bf16)a[3];
+  r[4] = (bf16)b[0]; r[5] = (bf16)b[1]; r[6] = (bf16)b[2]; r[7] = (bf16)b[3];
+  return r;
+}
+
+// Y[b,y,x, yoff + co] = act(bias[co] + sum_tap sum_ci
+//                          X[b, y+dy, x+dx, xoff + ci] Wt[tap][co][ci])
+// (zero padding).  Block: one 64-pixel row segment x 16*MT output channels;
+// wave w owns pixels 16w..16w+15 of the segment.
+template <int K, int MT, class TX, bool OUT_F32, bool RELU>
+__global__ __launch_bounds__(256) void conv_kernel(
+    const TX* __restrict__ X, int xld, int xoff, int cin_p,
+    const bf16* __restrict__ Wt, const float* __restrict__ bias, int cout,
+    int cout_p, void* __restrict__ Yv, int yld, int yoff, int H, int W,
+    int nxb) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int bx = blockIdx.x % nxb;
+  const int row = blockIdx.x / nxb;
+  const int y = row % H, b = row / H;
+  const int co_base = blockIdx.y * 16 * MT;
+  const int px = bx * 64 + w * 16 + (lane & 15);
+  const int kq = (lane >> 4) * 8;
+  f32x4 acc[MT];
+#pragma unroll
+  for (int m = 0; m < MT; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+  const bf16x8 zero = {};
+  for (int tap = 0; tap < K * K; ++tap) {
+    const int yi = y + tap / K - K / 2, xi = px + tap % K - K / 2;
+    const bool inb = px < W && yi >= 0 && yi < H && xi >= 0 && xi < W;
+    const size_t pix = ((size_t)b * H + (inb ? yi : 0)) * W + (inb ? xi : 0);
+    const TX* xp = X + pix * xld + xoff + kq;
+    const bf16* wp = Wt + ((size_t)tap * cout_p + co_base + (lane & 15)) *
+                              cin_p + kq;
+    for (int c0 = 0; c0 < cin_p; c0 += 32) {
+      bf16x8 bop = inb ? load8(xp + c0) : zero;
+#pragma unroll
+      for (int m = 0; m < MT; ++m) {
+        bf16x8 aop = load8(wp + (size_t)16 * m * cin_p + c0);
+        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, acc[m], 0,
+                                                         0, 0);
+      }
+    }
+  }
+  if (px >= W) return;
+  const size_t obase = (((size_t)b * H + y) * W + px) * yld + yoff;
+#pragma unroll
+  for (int m = 0; m < MT; ++m) {
+    const int c = co_base + 16 * m + (lane >> 4) * 4;
+    float v[4];
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      float bb = (bias && c + i < cout) ? bias[c + i] : 0.f;
+      v[i] = acc[m][i] + bb;
+      if (RELU) v[i] = v[i] > 0.f ? v[i] : 0.f;
+    }
+    if (OUT_F32) {
+      float* Y = reinterpret_cast<float*>(Yv) + obase + c;
+      *reinterpret_cast<f32x4*>(Y) = f32x4{v[0], v[1], v[2], v[3]};
+    } else {
+      bf16* Y = reinterpret_cast<bf16*>(Yv) + obase + c;
+      typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
+      *reinterpret_cast<bf16x4*>(Y) =
+          bf16x4{(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+    }
+  }
+}
+
+// part[s][tap][co][ci] = sum over the pixels of split s of
+//   bf16(dP[p][poff + co]) * X[p + off(tap)][xoff + ci]   (zero padding)
+// Block: 64 output channels x 64 input channels of one tap; wave w owns
+// output channels 16w..16w+15.
+template <int K>
+__global__ __launch_bounds__(256) void wgrad_kernel(
+    const float* __restrict__ dP, int pld, int poff, int cout_p,
+    const bf16* __restrict__ X, int xld, int xoff, int cin_p, int B, int H,
+    int W, int chunks_per_split, float* __restrict__ part) {
+  __shared__ bf16 As[64][40];
+  __shared__ bf16 Bs[64][40];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int nco = (cout_p + 63) / 64, nci = (cin_p + 63) / 64;
+  int t = blockIdx.y;
+  const int cib = t % nci;
+  t /= nci;
+  const int cob = t % nco;
+  const int tap = t / nco;
+  const int dy = tap / K - K / 2, dx = tap % K - K / 2;
+  const int s = blockIdx.x;
+  const long long P = (long long)B * H * W;
+  const long long nchunks = (P + 31) / 32;
+  const long long c_beg = (long long)s * chunks_per_split;
+  long long c_end = c_beg + chunks_per_split;
+  if (c_end > nchunks) c_end = nchunks;
+  const int kq = (lane >> 4) * 8;
+  f32x4 acc[4];
+#pragma unroll
+  for (int n = 0; n < 4; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
+  // staging role of this thread: pixel sp of the chunk, 8 channels at c8
+  const int sp = threadIdx.x >> 3, c8 = (threadIdx.x & 7) * 8;
+  for (long long ch = c_beg; ch < c_end; ++ch) {
+    const long long p = ch * 32 + sp;
+    {
+      float v[8];
+      const int co = cob * 64 + c8;
+      if (p < P && co < cout_p) {
+        const float* src = dP + p * pld + poff + co;
+        f32x4 a = *reinterpret_cast<const f32x4*>(src);
+        f32x4 c = *reinterpret_cast<const f32x4*>(src + 4);
+        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
+        v[4] = c[0]; v[5] = c[1]; v[6] = c[2]; v[7] = c[3];
+      } else {
+#pragma unroll
+        for (int i = 0; i < 8; ++i) v[i] = 0.f;
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) As[c8 + i][sp] = (bf16)v[i];
+    }
+    {
+      bf16x8 v = {};
+      const int ci = cib * 64 + c8;
+      if (p < P && ci < cin_p) {
+        const long long pb = p / ((long long)H * W);
+        const int rem = (int)(p - pb * H * W);
+        const int yy = rem / W + dy, xx = rem % W + dx;
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
+          v = load8(X + (((size_t)pb * H + yy) * W + xx) * xld + xoff + ci);
+      }
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[c8 + i][sp] = v[i];
+    }
+    __syncthreads();
+    const bf16x8 aop = *reinterpret_cast<const bf16x8*>(&As[16 * w + (lane & 15)][kq]);
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+      const bf16x8 bop =
+          *reinterpret_cast<const bf16x8*>(&Bs[16 * n + (lane & 15)][kq]);
+      acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, acc[n], 0, 0,
+                                                       0);
+    }
+    __syncthreads();
+  }
+  const int K2 = K * K;
+#pragma unroll
+  for (int n = 0; n < 4; ++n) {
+    const int ci = cib * 64 + 16 * n + (lane & 15);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int co = cob * 64 + 16 * w + (lane >> 4) * 4 + i;
+      if (co < cout_p && ci < cin_p)
+        part[(((size_t)s * K2 + tap) * cout_p + co) * cin_p + ci] = acc[n][i];
+    }
+  }
+}
+
+// bpart[s][co] = sum over the pixels of split s of bf16(dP[p][poff + co])
+__global__ void bias_grad_kernel(const float* __restrict__ dP, int pld,
+                                 int poff, int cout_p, long long P,
+                                 long long pix_per_split,
+                                 float* __restrict__ bpart) {
+  const int co = threadIdx.x;
+  if (co >= cout_p) return;
+  const long long p0 = (long long)blockIdx.x * pix_per_split;
+  long long p1 = p0 + pix_per_split;
+  if (p1 > P) p1 = P;
+  float acc = 0.f;
+#pragma unroll 8
+  for (long long p = p0; p < p1; ++p)
+    acc += (float)(bf16)dP[p * pld + poff + co];
+  bpart[(size_t)blockIdx.x * cout_p + co] = acc;
+}
+
+struct AdamArgs {
+  float lr, b1, b2, eps, c1, c2;   // c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
+  int apply;
+};
+
+// Gradient of one layer from the split partials (fixed summation order),
+// optional copy out, Adam step on the float32 master, and the bfloat16
+// forward (Wt[tap][co_p][ci_p]) and backward (Wb[K2-1-tap][ci_p][co_p])
+// weight copies.
+__global__ void adam_layer_kernel(const float* __restrict__ part, int nsplit,
+                                  const float* __restrict__ bpart, int bsplit,
+                                  int K2, int cout, int cin, int cout_p,
+                                  int cin_p, float* __restrict__ master,
+                                  float* __restrict__ m, float* __restrict__ v,
+                                  float* __restrict__ grad_out, bf16* Wt,
+                                  bf16* Wb, AdamArgs a) {
+  const int nw = K2 * cout * cin;
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nw + cout) return;
+  float g = 0.f;
+  int tap = 0, co, ci = 0;
+  if (e < nw) {
+    tap = e / (cout * cin);
+    int r = e - tap * cout * cin;
+    co = r / cin;
+    ci = r - co * cin;
+    for (int s = 0; s < nsplit; ++s)
+      g += part[(((size_t)s * K2 + tap) * cout_p + co) * cin_p + ci];
+  } else {
+    co = e - nw;
+    for (int s = 0; s < bsplit; ++s) g += bpart[(size_t)s * cout_p + co];
+  }
+  if (grad_out) grad_out[e] = g;
+  if (!a.apply) return;
+  float mm = a.b1 * m[e] + (1.f - a.b1) * g;
+  float vv = a.b2 * v[e] + (1.f - a.b2) * g * g;
+  m[e] = mm;
+  v[e] = vv;
+  float wv = master[e] - a.lr * (mm * a.c1) / (sqrtf(vv * a.c2) + a.eps);
+  master[e] = wv;
+  if (e < nw) {
+    Wt[((size_t)tap * cout_p + co) * cin_p + ci] = (bf16)wv;
+    Wb[((size_t)(K2 - 1 - tap) * cin_p + ci) * cout_p + co] = (bf16)wv;
+  }
+}
+
+// Bfloat16 weight copies of one layer from the float32 master.
+__global__ void weights_from_master_kernel(const float* __restrict__ master,
+                                           int K2, int cout, int cin,
+                                           int cout_p, int cin_p, bf16* Wt,
+                                           bf16* Wb) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= K2 * cout * cin) return;
+  int tap = e / (cout * cin);
+  int r = e - tap * cout * cin;
+  int co = r / cin, ci = r - co * cin;
+  bf16 wv = (bf16)master[e];
+  Wt[((size_t)tap * cout_p + co) * cin_p + ci] = wv;
+  Wb[((size_t)(K2 - 1 - tap) * cin_p + ci) * cout_p + co] = wv;
+}
+
+__global__ void zero_f32_kernel(float* p, size_t n) {
+  size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  size_t st = (size_t)gridDim.x * blockDim.x;
+  for (; i < n; i += st) p[i] = 0.f;
+}
+
+// dP[p][off + c] *= (post[p][poff + c] > 0), c < C
+__global__ void relu_bwd_kernel(float* __restrict__ dP, int ld, int off,
+                                const bf16* __restrict__ post, int pld,
+                                int poff, int C, long long P) {
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < P * C; i += st) {
+    long long p = i / C;
+    int c = (int)(i - p * C);
+    if (!((float)post[p * pld + poff + c] > 0.f)) dP[p * ld + off + c] = 0.f;
+  }
+}
+
+// 2x2 average pooling, bfloat16 in and out (the sum of four bfloat16 values
+// is exact in float32).
+__global__ void pool_kernel(const bf16* __restrict__ X, int xld, int xoff,
+                            int C, int B, int H, int W, bf16* __restrict__ Y,
+                            int yld) {
+  const int Ho = H / 2, Wo = W / 2;
+  long long n = (long long)B * Ho * Wo * C;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) {
+    int c = (int)(i % C);
+    long long q = i / C;
+    int xo = (int)(q % Wo);
+    long long r = q / Wo;
+    int yo = (int)(r % Ho);
+    int b = (int)(r / Ho);
+    size_t p00 = (((size_t)b * H + 2 * yo) * W + 2 * xo);
+    float s = (float)X[p00 * xld + xoff + c] +
+              (float)X[(p00 + 1) * xld + xoff + c] +
+              (float)X[(p00 + W) * xld + xoff + c] +
+              (float)X[(p00 + W + 1) * xld + xoff + c];
+    Y[q * yld + c] = (bf16)(0.25f * s);
+  }
+}
+
+// dX[2y+i][2x+j][off + c] += dY[y][x][c] / 4
+__global__ void pool_bwd_add_kernel(const float* __restrict__ dY, int C,
+                                    int B, int H, int W,
+                                    float* __restrict__ dX, int dld,
+                                    int doff) {
+  long long n = (long long)B * H * W * C;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) {
+    int c = (int)(i % C);
+    long long q = i / C;
+    int x = (int)(q % W);
+    long long r = q / W;
+    int y = (int)(r % H);
+    int b = (int)(r / H);
+    int Hi = H / 2, Wi = W / 2;
+    float g = dY[(((size_t)b * Hi + y / 2) * Wi + x / 2) * C + c] * 0.25f;
+    dX[q * dld + doff + c] += g;
+  }
+}
+
+// Y[y][x][off + c] = X[y/2][x/2][c]
+__global__ void up_kernel(const bf16* __restrict__ X, int C, int B, int H,
+                          int W, bf16* __restrict__ Y, int yld, int yoff) {
+  long long n = (long long)B * H * W * C;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) {
+    int c = (int)(i % C);
+    long long q = i / C;
+    int x = (int)(q % W);
+    long long r = q / W;
+    int y = (int)(r % H);
+    int b = (int)(r / H);
+    Y[q * yld + yoff + c] =
+        X[(((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
+  }
+}
+
+// dX[y][x][c] = sum of dY[2y+i][2x+j][off + c]
+__global__ void up_bwd_kernel(const float* __restrict__ dY, int dld, int doff,
+                              int C, int B, int H, int W,
+                              float* __restrict__ dX) {
+  const int Ho = H / 2, Wo = W / 2;
+  long long n = (long long)B * Ho * Wo * C;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) {
+    int c = (int)(i % C);
+    long long q = i / C;
+    int xo = (int)(q % Wo);
+    long long r = q / Wo;
+    int yo = (int)(r % Ho);
+    int b = (int)(r / Ho);
+    size_t p00 = (((size_t)b * H + 2 * yo) * W + 2 * xo);
+    dX[q * C + c] = dY[p00 * dld + doff + c] + dY[(p00 + 1) * dld + doff + c] +
+                    dY[(p00 + W) * dld + doff + c] +
+                    dY[(p00 + W + 1) * dld + doff + c];
+  }
+}
+
+// Mean squared error of the 2-channel head (ld kOutLd) against tgt [P][2];
+// dout = 2 (out - tgt) / (2P) in channels 0, 1 and 0 elsewhere; per-block
+// float64 partial of the squared error.
+__global__ __launch_bounds__(256) void loss_kernel(
+    const float* __restrict__ out, const float* __restrict__ tgt, long long P,
+    float* __restrict__ dout, double* __restrict__ part) {
+  const double inv = 1.0 / (2.0 * (double)P);
+  double acc = 0.0;
+  for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < P;
+       p += (long long)gridDim.x * blockDim.x) {
+#pragma unroll
+    for (int c = 0; c < kOutLd; ++c) {
+      float g = 0.f;
+      if (c < 2) {
+        double d = (double)out[p * kOutLd + c] - (double)tgt[p * 2 + c];
+        acc += d * d;
+        g = (float)(2.0 * d * inv);
+      }
+      dout[p * kOutLd + c] = g;
+    }
+  }
+  __shared__ double red[256];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0] * inv;
+}
+
+__global__ void loss_final_kernel(const double* __restrict__ part, int nb,
+                                  double* __restrict__ loss) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < nb; ++i) s += part[i];
+    *loss = s;
+  }
+}
+
+// Network input from planar float32 channels [B][C][H][W] (C <= 32) and
+// the training target [B][H][W][2] from [B][2][H][W].
+__global__ void pack_input_kernel(const float* __restrict__ x, int C, int B,
+                                  int H, int W, bf16* __restrict__ xin) {
+  long long n = (long long)B * H * W * kCinPad;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) {
+    int c = (int)(i % kCinPad);
+    long long p = i / kCinPad;
+    long long b = p / ((long long)H * W);
+    long long hw = p - b * H * W;
+    float v = c < C ? x[(b * C + c) * H * W + hw] : 0.f;
+    xin[i] = (bf16)v;
+  }
+}
+
+// Inputs of frames t with registered neighbours l < t < r:
+// [T_l, T_t, T_r, u_l / h, u_r / h] (2-D), the linear-interpolation base
+// u_b = w_l u_l + w_r u_r ([B][2][H][W]) and, if U_t is wanted, the target
+// correction (u_t - u_b) / h ([B][H][W][2]).
+__global__ void assemble_kernel(const float* __restrict__ T,
+                                const float* __restrict__ U,
+                                const int* __restrict__ tlr, int B, int H,
+                                int W, double inv_h, bf16* __restrict__ xin,
+                                float* __restrict__ base,
+                                float* __restrict__ tgt) {
+  const long long HW = (long long)H * W;
+  long long n = (long long)B * HW;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) {
+    int b = (int)(i / HW);
+    long long hw = i - (long long)b * HW;
+    int t = tlr[3 * b], l = tlr[3 * b + 1], r = tlr[3 * b + 2];
+    double wl = (double)(r - t) / (r - l), wr = (double)(t - l) / (r - l);
+    bf16* o = xin + i * kCinPad;
+    o[0] = (bf16)T[(size_t)l * HW + hw];
+    o[1] = (bf16)T[(size_t)t * HW + hw];
+    o[2] = (bf16)T[(size_t)r * HW + hw];
+#pragma unroll
+    for (int a = 0; a < 2; ++a) {
+      double ul = U[((size_t)l * 2 + a) * HW + hw];
+      double ur = U[((size_t)r * 2 + a) * HW + hw];
+      o[3 + a] = (bf16)(float)(ul * inv_h);
+      o[5 + a] = (bf16)(float)(ur * inv_h);
+      double ub = wl * ul + wr * ur;
+      base[((size_t)b * 2 + a) * HW + hw] = (float)ub;
+      if (tgt) {
+        double ut = U[((size_t)t * 2 + a) * HW + hw];
+        tgt[i * 2 + a] = (float)((ut - ub) * inv_h);
+      }
+    }
+    for (int c = 7; c < kCinPad; ++c) o[c] = (bf16)0.f;
+  }
+}
+
+// u_t = base + h * correction, written into the all-frame field Uout.
+__global__ void emit_kernel(const float* __restrict__ base,
+                            const float* __restrict__ out,
+                            const int* __restrict__ tlr, int B, int H, int W,
+                            double h, float* __restrict__ Uout) {
+  const long long HW = (long long)H * W;
+  long long n = (long long)B * HW;
+  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  long long st = (long long)gridDim.x * blockDim.x;
+  for (; i < n; i += st) {
+    int b = (int)(i / HW);
+    long long hw = i - (long long)b * HW;
+    int t = tlr[3 * b];
+#pragma unroll
+    for (int a = 0; a < 2; ++a)
+      Uout[((size_t)t * 2 + a) * HW + hw] =
+          (float)((double)base[((size_t)b * 2 + a) * HW + hw] +
+                  h * (double)out[i * kOutLd + a]);
+  }
+}
+
+static int gridsz(long long n) {
+  long long nb = (n + 255) / 256;
+  return (int)(nb < 1 ? 1 : (nb > 8192 ? 8192 : nb));
+}
+
+}  // namespace cnn
+}  // namespace stml
+
+// ================================================================ network
+
+using namespace stml;
+using namespace stml::cnn;
+
+namespace {
+
+// A tensor view: NHWC with channel stride ld and channel offset off.
+struct TV {
+  void* p;
+  int ld, off, C;
+  int level;       // resolution level 0 (full) .. 3 (1/8)
+};
+
+struct Buf {
+  bf16* a;   // activation (bfloat16)
+  float* g;  // gradient (float32)
+  int ld;
+  int level;
+};
+
+struct Layer {
+  int ci, co, k, ci_p, co_p;
+  size_t woff, boff;      // offsets into the flat parameter vector
+  bf16 *Wt, *Wb;
+};
+
+}  // namespace
+
+struct stml_net {
+  int dim = 2, maxB = 0, maxH = 0, maxW = 0;
+  hipStream_t stream = nullptr;
+  size_t nparam = 0;
+  float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
+  Layer L[kLayers];
+  // activations and gradients
+  Buf xin, e1a, c1, p1, e2a, c2, p2, e3a, c3, p3, e4a, e4b, d3a, d3b, d2a,
+      d2b, d1a, d1b;
+  float* out = nullptr;     // head output [P][16]
+  float* dout = nullptr;
+  float *g_p1 = nullptr, *g_p2 = nullptr, *g_p3 = nullptr;
+  float* base = nullptr;    // [B][2][H][W]
+  float* tgt = nullptr;     // [B][H][W][2]
+  int* tlr = nullptr;       // device triples
+  int* htlr = nullptr;      // pinned host staging
+  float* wpart = nullptr;
+  size_t wpart_cap = 0;     // floats
+  float* bpart = nullptr;
+  size_t bpart_cap = 0;
+  double* lpart = nullptr;
+  double* dloss = nullptr;
+  double* hloss = nullptr;  // pinned
+  int step = 0;
+  int curB = 0, curH = 0, curW = 0;
+};
+
+namespace {
+
+constexpr size_t kAlignN = 256;
+size_t alignn(size_t v) { return (v + kAlignN - 1) / kAlignN * kAlignN; }
+
+struct NetLayout {
+  size_t off = 0;
+  char* base = nullptr;
+  template <typename T>
+  T* take(size_t count) {
+    size_t o = off;
+    off = alignn(off + count * sizeof(T));
+    return base ? reinterpret_cast<T*>(base + o) : nullptr;
+  }
+};
+
+constexpr size_t kWpartCap = (size_t)6 << 20;   // floats of split partials
+constexpr int kBSplit = 1024;
+
+size_t net_layout(stml_net* n, char* base) {
+  NetLayout lo;
+  lo.base = base;
+  size_t np = 0;
+  for (int i = 0; i < kLayers; ++i) {
+    const LayerDef& d = kDefs[i];
+    Layer& l = n->L[i];
+    l.ci = d.ci;
+    l.co = d.co;
+    l.k = d.k;
+    l.ci_p = rup(d.ci, 32);
+    l.co_p = rup(d.co, 32);
+    l.woff = np;
+    np += (size_t)d.k * d.k * d.co * d.ci;
+    l.boff = np;
+    np += d.co;
+  }
+  n->nparam = np;
+  n->master = lo.take<float>(np);
+  n->m = lo.take<float>(np);
+  n->v = lo.take<float>(np);
+  n->grad = lo.take<float>(np);
+  for (int i = 0; i < kLayers; ++i) {
+    Layer& l = n->L[i];
+    size_t nw = (size_t)l.k * l.k * l.co_p * l.ci_p;
+    l.Wt = lo.take<bf16>(nw);
+    l.Wb = lo.take<bf16>(nw);
+  }
+  const size_t P0 = (size_t)n->maxB * n->maxH * n->maxW;
+  auto buf = [&](Buf& b, int ch, int level) {
+    size_t P = P0 >> (2 * level);
+    b.a = lo.take<bf16>(P * ch);
+    b.g = lo.take<float>(P * ch);
+    b.ld = ch;
+    b.level = level;
+  };
+  buf(n->xin, 32, 0);
+  buf(n->e1a, 32, 0);
+  buf(n->c1, 96, 0);
+  buf(n->p1, 32, 1);
+  buf(n->e2a, 64, 1);
+  buf(n->c2, 192, 1);
+  buf(n->p2, 64, 2);
+  buf(n->e3a, 128, 2);
+  buf(n->c3, 256, 2);
+  buf(n->p3, 128, 3);
+  buf(n->e4a, 128, 3);
+  buf(n->e4b, 128, 3);
+  buf(n->d3a, 128, 2);
+  buf(n->d3b, 128, 2);
+  buf(n->d2a, 64, 1);
+  buf(n->d2b, 64, 1);
+  buf(n->d1a, 32, 0);
+  buf(n->d1b, 32, 0);
+  n->out = lo.take<float>(P0 * kOutLd);
+  n->dout = lo.take<float>(P0 * kOutLd);
+  n->base = lo.take<float>(P0 * 2);
+  n->tgt = lo.take<float>(P0 * 2);
+  n->tlr = lo.take<int>(3 * (size_t)n->maxB);
+  n->wpart_cap = kWpartCap;
+  n->wpart = lo.take<float>(kWpartCap);
+  n->bpart_cap = (size_t)kBSplit * 128;
+  n->bpart = lo.take<float>(n->bpart_cap);
+  n->lpart = lo.take<double>(8192);
+  n->dloss = lo.take<double>(1);
+  return lo.off;
+}
+
+#define NET_OK(call)                     \
+  do {                                   \
+    if ((call) != hipSuccess) return STML_EDEVICE; \
+  } while (0)
+
+hipError_t conv_launch(stml_net* n, const Layer& l, const void* X, bool x_f32,
+                       int xld, int xoff, int cin_p, const bf16* Wmat,
+                       const float* bias, int cout, int cout_p, void* Y,
+                       bool y_f32, int yld, int yoff, bool relu, int B, int H,
+                       int W) {
+  const int nxb = (W + 63) / 64;
+  const int nt = cout_p / 16;
+  const int MT = nt % 4 == 0 ? 4 : (nt % 2 == 0 ? 2 : 1);
+  dim3 grid(nxb * H * B, cout_p / (16 * MT));
+  hipStream_t s = n->stream;
+#define CONV_CASE(KK, MTT, TXX, OF, RL)                                       \
+  conv_kernel<KK, MTT, TXX, OF, RL><<<grid, 256, 0, s>>>(                     \
+      (const TXX*)X, xld, xoff, cin_p, Wmat, bias, cout, cout_p, Y, yld, yoff, \
+      H, W, nxb)
+  if (l.k == 3 && !x_f32 && !y_f32 && relu && MT == 4) CONV_CASE(3, 4, bf16, false, true);
+  else if (l.k == 3 && !x_f32 && !y_f32 && relu && MT == 2) CONV_CASE(3, 2, bf16, false, true);
+  else if (l.k == 1 && !x_f32 && y_f32 && !relu && MT == 2) CONV_CASE(1, 2, bf16, true, false);
+  else if (l.k == 3 && x_f32 && y_f32 && !relu && MT == 4) CONV_CASE(3, 4, float, true, false);
+  else if (l.k == 3 && x_f32 && y_f32 && !relu && MT == 2) CONV_CASE(3, 2, float, true, false);
+  else if (l.k == 1 && x_f32 && y_f32 && !relu && MT == 2) CONV_CASE(1, 2, float, true, false);
+  else return hipErrorInvalidValue;
+#undef CONV_CASE
+  return hipGetLastError();
+}
+
+// Forward through every layer for B images of H x W (multiples of 8).
+int net_forward(stml_net* n, int B, int H, int W) {
+  auto conv3 = [&](int li, const Buf& in, int ioff, Buf& outb, int ooff) {
+    const Layer& l = n->L[li];
+    int lev = in.level;
+    return conv_launch(n, l, in.a, false, in.ld, ioff, l.ci_p, l.Wt,
+                       n->master + l.boff, l.co, l.co_p, outb.a, false,
+                       outb.ld, ooff, true, B, H >> lev, W >> lev);
+  };
+  auto pool = [&](const Buf& in, int ioff, int C, Buf& outb) {
+    int lev = in.level;
+    int h = H >> lev, w = W >> lev;
+    pool_kernel<<<gridsz((long long)B * h * w * C / 4), 256, 0, n->stream>>>(
+        in.a, in.ld, ioff, C, B, h, w, outb.a, outb.ld);
+    return hipGetLastError();
+  };
+  auto up = [&](const Buf& in, int C, Buf& outb, int ooff) {
+    int lev = outb.level;
+    int h = H >> lev, w = W >> lev;
+    up_kernel<<<gridsz((long long)B * h * w * C), 256, 0, n->stream>>>(
+        in.a, C, B, h, w, outb.a, outb.ld, ooff);
+    return hipGetLastError();
+  };
+  NET_OK(conv3(E1A, n->xin, 0, n->e1a, 0));
+  NET_OK(conv3(E1B, n->e1a, 0, n->c1, 0));
+  NET_OK(pool(n->c1, 0, 32, n->p1));
+  NET_OK(conv3(E2A, n->p1, 0, n->e2a, 0));
+  NET_OK(conv3(E2B, n->e2a, 0, n->c2, 0));
+  NET_OK(pool(n->c2, 0, 64, n->p2));
+  NET_OK(conv3(E3A, n->p2, 0, n->e3a, 0));
+  NET_OK(conv3(E3B, n->e3a, 0, n->c3, 0));
+  NET_OK(pool(n->c3, 0, 128, n->p3));
+  NET_OK(conv3(E4A, n->p3, 0, n->e4a, 0));
+  NET_OK(conv3(E4B, n->e4a, 0, n->e4b, 0));
+  NET_OK(up(n->e4b, 128, n->c3, 128));
+  NET_OK(conv3(D3A, n->c3, 0, n->d3a, 0));
+  NET_OK(conv3(D3B, n->d3a, 0, n->d3b, 0));
+  NET_OK(up(n->d3b, 128, n->c2, 64));
+  NET_OK(conv3(D2A, n->c2, 0, n->d2a, 0));
+  NET_OK(conv3(D2B, n->d2a, 0, n->d2b, 0));
+  NET_OK(up(n->d2b, 64, n->c1, 32));
+  NET_OK(conv3(D1A, n->c1, 0, n->d1a, 0));
+  NET_OK(conv3(D1B, n->d1a, 0, n->d1b, 0));
+  const Layer& h = n->L[HEAD];
+  NET_OK(conv_launch(n, h, n->d1b.a, false, 32, 0, h.ci_p, h.Wt,
+                     n->master + h.boff, h.co, h.co_p, n->out, true, kOutLd,
+                     0, false, B, H, W));
+  return STML_OK;
+}
+
+// Weight and bias gradient of layer li from dPre (ld, off) and its input X.
+int layer_wgrad(stml_net* n, int li, const float* dP, int pld, int poff,
+                const bf16* X, int xld, int xoff, int B, int h, int w,
+                const AdamArgs& a, bool copy_grad) {
+  const Layer& l = n->L[li];
+  const int K2 = l.k * l.k;
+  const long long P = (long long)B * h * w;
+  const long long nchunks = (P + 31) / 32;
+  const int nco = (l.co_p + 63) / 64, nci = (l.ci_p + 63) / 64;
+  const int gy = K2 * nco * nci;
+  const size_t per_split = (size_t)K2 * l.co_p * l.ci_p;
+  long long ns = 1024 / gy;
+  if (ns < 1) ns = 1;
+  if (ns > nchunks) ns = nchunks;
+  if ((size_t)ns * per_split > n->wpart_cap) ns = n->wpart_cap / per_split;
+  if (ns < 1) return STML_ENOMEM;
+  const long long cps = (nchunks + ns - 1) / ns;
+  ns = (nchunks + cps - 1) / cps;
+  dim3 grid((unsigned)ns, gy);
+  if (l.k == 3)
+    wgrad_kernel<3><<<grid, 256, 0, n->stream>>>(dP, pld, poff, l.co_p, X, xld,
+                                                 xoff, l.ci_p, B, h, w,
+                                                 (int)cps, n->wpart);
+  else
+    wgrad_kernel<1><<<grid, 256, 0, n->stream>>>(dP, pld, poff, l.co_p, X, xld,
+                                                 xoff, l.ci_p, B, h, w,
+                                                 (int)cps, n->wpart);
+  NET_OK(hipGetLastError());
+  const long long pps = (P + kBSplit - 1) / kBSplit;
+  const int bs = (int)((P + pps - 1) / pps);
+  bias_grad_kernel<<<bs, l.co_p, 0, n->stream>>>(dP, pld, poff, l.co_p, P,
+                                                 pps, n->bpart);
+  NET_OK(hipGetLastError());
+  const int ne = K2 * l.co * l.ci + l.co;
+  adam_layer_kernel<<<(ne + 255) / 256, 256, 0, n->stream>>>(
+      n->wpart, (int)ns, n->bpart, bs, K2, l.co, l.ci, l.co_p, l.ci_p,
+      n->master + l.woff, n->m + l.woff, n->v + l.woff,
+      copy_grad ? n->grad + l.woff : nullptr, l.Wt, l.Wb, a);
+  NET_OK(hipGetLastError());
+  return STML_OK;
+}
+
+// Backward of a 3x3 conv layer: dPre in place (ReLU mask of its output),
+// weight gradient + Adam, and (if dX) the input gradient.
+int conv_back(stml_net* n, int li, Buf& outb, int ooff, const Buf& in,
+              int ioff, float* dX, int dld, int B, int H, int W,
+              const AdamArgs& a, bool copy_grad) {
+  const Layer& l = n->L[li];
+  const int lev = in.level;
+  const int h = H >> lev, w = W >> lev;
+  const long long P = (long long)B * h * w;
+  relu_bwd_kernel<<<gridsz(P * l.co), 256, 0, n->stream>>>(
+      outb.g, outb.ld, ooff, outb.a, outb.ld, ooff, l.co_p, P);
+  NET_OK(hipGetLastError());
+  // input gradient first: it must use the weights of the forward pass,
+  // which the Adam step below replaces
+  if (dX)
+    NET_OK(conv_launch(n, l, outb.g + ooff, true, outb.ld, 0, l.co_p, l.Wb,
+                       nullptr, l.ci_p, l.ci_p, dX, true, dld, 0, false, B, h,
+                       w));
+  return layer_wgrad(n, li, outb.g, outb.ld, ooff, in.a, in.ld, ioff, B, h, w,
+                     a, copy_grad);
+}
+
+}  // namespace
+
+// ================================================================ C-ABI
+
+extern "C" {
+
+int stml_net_param_count(int dim) {
+  if (dim != 2) return STML_EINVAL;
+  int np = 0;
+  for (int i = 0; i < kLayers; ++i)
+    np += kDefs[i].k * kDefs[i].k * kDefs[i].co * kDefs[i].ci + kDefs[i].co;
+  return np;
+}
+
+size_t stml_net_workspace_bytes(int dim, int max_batch, const int* ext) {
+  if (dim != 2 || max_batch < 1 || !ext || ext[0] < 8 || ext[1] < 8 ||
+      ext[0] % 8 || ext[1] % 8)
+    return 0;
+  stml_net tmp;
+  tmp.dim = dim;
+  tmp.maxB = max_batch;
+  tmp.maxH = ext[0];
+  tmp.maxW = ext[1];
+  return net_layout(&tmp, nullptr);
+}
+
+int stml_net_create(int dim, int max_batch, const int* ext, void* stream,
+                    void* ws, size_t ws_bytes, stml_net** out) {
+  if (!out) return STML_EINVAL;
+  *out = nullptr;
+  size_t need = stml_net_workspace_bytes(dim, max_batch, ext);
+  if (!need) return STML_EINVAL;
+  if (!ws || ws_bytes < need) return STML_ENOMEM;
+  stml_net* n = new stml_net();
+  n->dim = dim;
+  n->maxB = max_batch;
+  n->maxH = ext[0];
+  n->maxW = ext[1];
+  n->stream = (hipStream_t)stream;
+  net_layout(n, (char*)ws);
+  if (hipHostMalloc((void**)&n->htlr, 3 * sizeof(int) * max_batch,
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&n->hloss, sizeof(double),
+                    hipHostMallocDefault) != hipSuccess) {
+    stml_net_destroy(n);
+    return STML_EDEVICE;
+  }
+  // zero the whole workspace once: padded weight rows and channels stay 0
+  zero_f32_kernel<<<8192, 256, 0, n->stream>>>((float*)ws, need / 4);
+  if (hipGetLastError() != hipSuccess ||
+      hipStreamSynchronize(n->stream) != hipSuccess) {
+    stml_net_destroy(n);
+    return STML_EDEVICE;
+  }
+  *out = n;
+  return STML_OK;
+}
+
+void stml_net_destroy(stml_net* n) {
+  if (!n) return;
+  if (n->stream) (void)hipStreamSynchronize(n->stream);
+  if (n->htlr) (void)hipHostFree(n->htlr);
+  if (n->hloss) (void)hipHostFree(n->hloss);
+  delete n;
+}
+
+int stml_net_set_params(stml_net* n, const float* params) {
+  if (!n || !params) return STML_EINVAL;
+  NET_OK(hipMemcpyAsync(n->master, params, n->nparam * sizeof(float),
+                        hipMemcpyDeviceToDevice, n->stream));
+  zero_f32_kernel<<<2048, 256, 0, n->stream>>>(n->m, n->nparam);
+  zero_f32_kernel<<<2048, 256, 0, n->stream>>>(n->v, n->nparam);
+  for (int i = 0; i < kLayers; ++i) {
+    const Layer& l = n->L[i];
+    int ne = l.k * l.k * l.co * l.ci;
+    weights_from_master_kernel<<<(ne + 255) / 256, 256, 0, n->stream>>>(
+        n->master + l.woff, l.k * l.k, l.co, l.ci, l.co_p, l.ci_p, l.Wt, l.Wb);
+  }
+  n->step = 0;
+  NET_OK(hipGetLastError());
+  NET_OK(hipStreamSynchronize(n->stream));
+  return STML_OK;
+}
+
+int stml_net_get_params(const stml_net* n, float* params) {
+  if (!n || !params) return STML_EINVAL;
+  NET_OK(hipMemcpyAsync(params, n->master, n->nparam * sizeof(float),
+                        hipMemcpyDeviceToDevice, n->stream));
+  NET_OK(hipStreamSynchronize(n->stream));
+  return STML_OK;
+}
+
+static int check_shape(const stml_net* n, int B, const int* ext) {
+  if (!ext || B < 1 || B > n->maxB || ext[0] % 8 || ext[1] % 8 ||
+      ext[0] < 8 || ext[1] < 8 || (long long)ext[0] * ext[1] >
+                                      (long long)n->maxH * n->maxW)
+    return STML_EINVAL;
+  return STML_OK;
+}
+
+int stml_net_set_input(stml_net* n, const float* x, int C, const float* tgt,
+                       int B, const int* ext) {
+  if (!n || !x || C < 1 || C > kCinPad) return STML_EINVAL;
+  if (check_shape(n, B, ext)) return STML_EINVAL;
+  const int H = ext[0], W = ext[1];
+  long long P = (long long)B * H * W;
+  pack_input_kernel<<<gridsz(P * kCinPad), 256, 0, n->stream>>>(x, C, B, H, W,
+                                                                n->xin.a);
+  NET_OK(hipGetLastError());
+  if (tgt)
+    NET_OK(hipMemcpyAsync(n->tgt, tgt, P * 2 * sizeof(float),
+                          hipMemcpyDeviceToDevice, n->stream));
+  n->curB = B;
+  n->curH = H;
+  n->curW = W;
+  NET_OK(hipStreamSynchronize(n->stream));
+  return STML_OK;
+}
+
+int stml_net_assemble(stml_net* n, const float* T, const float* U,
+                      const int* ext, double h, const int* triples, int B,
+                      int with_target) {
+  if (!n || !T || !U || !triples || h <= 0) return STML_EINVAL;
+  if (check_shape(n, B, ext)) return STML_EINVAL;
+  for (int i = 0; i < 3 * B; ++i) n->htlr[i] = triples[i];
+  for (int b = 0; b < B; ++b)
+    if (!(triples[3 * b + 1] < triples[3 * b] &&
+          triples[3 * b] < triples[3 * b + 2]))
+      return STML_EINVAL;
+  NET_OK(hipMemcpyAsync(n->tlr, n->htlr, 3 * B * sizeof(int),
+                        hipMemcpyHostToDevice, n->stream));
+  const int H = ext[0], W = ext[1];
+  assemble_kernel<<<gridsz((long long)B * H * W), 256, 0, n->stream>>>(
+      T, U, n->tlr, B, H, W, 1.0 / h, n->xin.a, n->base,
+      with_target ? n->tgt : nullptr);
+  NET_OK(hipGetLastError());
+  n->curB = B;
+  n->curH = H;
+  n->curW = W;
+  NET_OK(hipStreamSynchronize(n->stream));
+  return STML_OK;
+}
+
+int stml_net_forward(stml_net* n, float* out) {
+  if (!n || !n->curB) return STML_ESTATE;
+  int rc = net_forward(n, n->curB, n->curH, n->curW);
+  if (rc) return rc;
+  if (out)
+    NET_OK(hipMemcpyAsync(out, n->out,
+                          (size_t)n->curB * n->curH * n->curW * kOutLd *
+                              sizeof(float),
+                          hipMemcpyDeviceToDevice, n->stream));
+  NET_OK(hipStreamSynchronize(n->stream));
+  return STML_OK;
+}
+
+int stml_net_emit(stml_net* n, double h, float* U) {
+  if (!n || !n->curB || !U) return STML_ESTATE;
+  emit_kernel<<<gridsz((long long)n->curB * n->curH * n->curW), 256, 0,
+                n->stream>>>(n->base, n->out, n->tlr, n->curB, n->curH,
+                             n->curW, h, U);
+  NET_OK(hipGetLastError());
+  NET_OK(hipStreamSynchronize(n->stream));
+  return STML_OK;
+}
+
+// forward + loss + backward; Adam if lr > 0; gradient copy if grad != NULL
+static int net_step(stml_net* n, double lr, float* grad, double* loss) {
+  if (!n->curB) return STML_ESTATE;
+  const int B = n->curB, H = n->curH, W = n->curW;
+  int rc = net_forward(n, B, H, W);
+  if (rc) return rc;
+  const long long P = (long long)B * H * W;
+  int lb = gridsz(P);
+  loss_kernel<<<lb, 256, 0, n->stream>>>(n->out, n->tgt, P, n->dout,
+                                         n->lpart);
+  loss_final_kernel<<<1, 64, 0, n->stream>>>(n->lpart, lb, n->dloss);
+  NET_OK(hipGetLastError());
+  AdamArgs a;
+  a.apply = lr > 0;
+  if (a.apply) n->step += 1;
+  a.lr = (float)lr;
+  a.b1 = 0.9f;
+  a.b2 = 0.999f;
+  a.eps = 1e-8f;
+  a.c1 = a.apply ? (float)(1.0 / (1.0 - std::pow(0.9, n->step))) : 1.f;
+  a.c2 = a.apply ? (float)(1.0 / (1.0 - std::pow(0.999, n->step))) : 1.f;
+  const bool cg = grad != nullptr;
+  // head: dout -> d1b gradient; weight gradient from dout and d1b
+  {
+    const Layer& l = n->L[HEAD];
+    NET_OK(conv_launch(n, l, n->dout, true, kOutLd, 0, l.co_p, l.Wb, nullptr,
+                       l.ci_p, l.ci_p, n->d1b.g, true, 32, 0, false, B, H, W));
+    rc = layer_wgrad(n, HEAD, n->dout, kOutLd, 0, n->d1b.a, 32, 0, B, H, W, a,
+                     cg);
+    if (rc) return rc;
+  }
+  // decoder 1
+  if ((rc = conv_back(n, D1B, n->d1b, 0, n->d1a, 0, n->d1a.g, 32, B, H, W, a,
+                      cg)))
+    return rc;
+  if ((rc = conv_back(n, D1A, n->d1a, 0, n->c1, 0, n->c1.g, 96, B, H, W, a,
+                      cg)))
+    return rc;
+  up_bwd_kernel<<<gridsz(P / 4 * 64), 256, 0, n->stream>>>(
+      n->c1.g, 96, 32, 64, B, H, W, n->d2b.g);
+  // decoder 2
+  if ((rc = conv_back(n, D2B, n->d2b, 0, n->d2a, 0, n->d2a.g, 64, B, H, W, a,
+                      cg)))
+    return rc;
+  if ((rc = conv_back(n, D2A, n->d2a, 0, n->c2, 0, n->c2.g, 192, B, H, W, a,
+                      cg)))
+    return rc;
+  up_bwd_kernel<<<gridsz(P / 16 * 128), 256, 0, n->stream>>>(
+      n->c2.g, 192, 64, 128, B, H / 2, W / 2, n->d3b.g);
+  // decoder 3
+  if ((rc = conv_back(n, D3B, n->d3b, 0, n->d3a, 0, n->d3a.g, 128, B, H, W,
+                      a, cg)))
+    return rc;
+  if ((rc = conv_back(n, D3A, n->d3a, 0, n->c3, 0, n->c3.g, 256, B, H, W, a,
+                      cg)))
+    return rc;
+  up_bwd_kernel<<<gridsz(P / 64 * 128), 256, 0, n->stream>>>(
+      n->c3.g, 256, 128, 128, B, H / 4, W / 4, n->e4b.g);
+  // encoder 4 (bottom)
+  if ((rc = conv_back(n, E4B, n->e4b, 0, n->e4a, 0, n->e4a.g, 128, B, H, W,
+                      a, cg)))
+    return rc;
+  if ((rc = conv_back(n, E4A, n->e4a, 0, n->p3, 0, n->p3.g, 128, B, H, W, a,
+                      cg)))
+    return rc;
+  pool_bwd_add_kernel<<<gridsz(P / 16 * 128), 256, 0, n->stream>>>(
+      n->p3.g, 128, B, H / 4, W / 4, n->c3.g, 256, 0);
+  // encoder 3
+  if ((rc = conv_back(n, E3B, n->c3, 0, n->e3a, 0, n->e3a.g, 128, B, H, W, a,
+                      cg)))
+    return rc;
+  if ((rc = conv_back(n, E3A, n->e3a, 0, n->p2, 0, n->p2.g, 64, B, H, W, a,
+                      cg)))
+    return rc;
+  pool_bwd_add_kernel<<<gridsz(P / 4 * 64), 256, 0, n->stream>>>(
+      n->p2.g, 64, B, H / 2, W / 2, n->c2.g, 192, 0);
+  // encoder 2
+  if ((rc = conv_back(n, E2B, n->c2, 0, n->e2a, 0, n->e2a.g, 64, B, H, W, a,
+                      cg)))
+    return rc;
+  if ((rc = conv_back(n, E2A, n->e2a, 0, n->p1, 0, n->p1.g, 32, B, H, W, a,
+                      cg)))
+    return rc;
+  pool_bwd_add_kernel<<<gridsz(P * 32), 256, 0, n->stream>>>(
+      n->p1.g, 32, B, H, W, n->c1.g, 96, 0);
+  // encoder 1
+  if ((rc = conv_back(n, E1B, n->c1, 0, n->e1a, 0, n->e1a.g, 32, B, H, W, a,
+                      cg)))
+    return rc;
+  if ((rc = conv_back(n, E1A, n->e1a, 0, n->xin, 0, nullptr, 0, B, H, W, a,
+                      cg)))
+    return rc;
+  NET_OK(hipGetLastError());
+  if (grad)
+    NET_OK(hipMemcpyAsync(grad, n->grad, n->nparam * sizeof(float),
+                          hipMemcpyDeviceToDevice, n->stream));
+  NET_OK(hipMemcpyAsync(n->hloss, n->dloss, sizeof(double),
+                        hipMemcpyDeviceToHost, n->stream));
+  NET_OK(hipStreamSynchronize(n->stream));
+  if (loss) *loss = *n->hloss;
+  return STML_OK;
+}
+
+int stml_net_gradient(stml_net* n, float* grad, double* loss) {
+  if (!n || !grad) return STML_EINVAL;
+  return net_step(n, 0.0, grad, loss);
+}
+
+int stml_net_train_step(stml_net* n, double lr, double* loss) {
+  if (!n || !(lr > 0)) return STML_EINVAL;
+  return net_step(n, lr, nullptr, loss);
+}
+
+}  // extern "C"

@@ -389,7 +389,6 @@ __device__ double hv_tiles(const F& f, const float* dWp,
       for (int j = ch.j0; j < ch.j1; ++j) {
         const F fj = f.plane((size_t)j * D * N);
         const float* dj = dWp + (size_t)j * D * N;
-        float* hj = hv + (size_t)j * D * N;
         double s = 0.0;
 #pragma unroll
         for (int a = 0; a < D; ++a)

@@ -72,6 +72,7 @@ struct stml_ctx {
   GNLog* hlog = nullptr;                // pinned host mirror
   int* hk = nullptr;                    // pinned host staging of frame lists
   bool have_seq = false;
+  stml_net* net = nullptr;               // learned predictor (optional)
   std::vector<stml_gir_log> logs;
   std::string err;
   // kernel timing
@@ -928,6 +929,13 @@ int stml_gn_direction(stml_ctx* c, int level, const int* frames, int nk,
   if (rc) return rc;
   if (out_cg) *out_cg = c->hsc->iters;
   if (c->hsc->done == 2) return fail(c, STML_EBREAKDOWN, "CG breakdown");
+  return STML_OK;
+}
+
+int stml_set_predictor_net(stml_ctx* c, stml_net* net) {
+  if (!c) return STML_EINVAL;
+  if (net && c->d != 2) return fail(c, STML_EINVAL, "learned predictor: 2-D");
+  c->net = net;
   return STML_OK;
 }
 

@@ -1,0 +1,143 @@
+"""GPU parity of the learned-predictor network against the float64 oracle.
+
+Both sides use the same bfloat16-rounded weights and round activations and
+matrix-instruction operands to bfloat16 at the same points; they differ in
+the accumulation (float32 on the GPU, float64 in the oracle).  A float32 sum
+can land on the other side of a bfloat16 rounding boundary than the float64
+sum, which changes that value by one bfloat16 ulp (2^-8 relative) and
+propagates.  The tolerance is measured, not guessed: the oracle is run once
+more with float32 accumulation, and the GPU must agree with the float64
+oracle to within twice that float32-vs-float64 distance (plus 1e-4).
+"""
+
+import numpy as np
+import pytest
+import torch
+
+from oracle import cnn
+from paper_2001_06613_amd import synth
+from paper_2001_06613_amd.binding import Net
+
+pytestmark = pytest.mark.gpu
+
+
+def _rel(a, b):
+    return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+
+
+def _oracle32(fn, *args, **kw):
+    cnn.ACCUM = np.float32
+    try:
+        return fn(*args, **kw)
+    finally:
+        cnn.ACCUM = np.float64
+
+
+def _batch(B, H, W, seed):
+    rng = np.random.default_rng(seed)
+    x = np.empty((B, 7, H, W), np.float32)
+    for b in range(B):
+        img = synth.base_image(rng, (H, W))
+        x[b, 0:3] = img[None] * (1 + 0.05 * rng.standard_normal((3, H, W)))
+        x[b, 3:7] = rng.uniform(-2, 2, (4, H, W))
+    tgt = (0.3 * rng.standard_normal((B, H, W, 2))).astype(np.float32)
+    return x, tgt
+
+
+@pytest.mark.parametrize("B,H,W", [(2, 32, 32), (1, 64, 48), (3, 16, 24)])
+def test_forward_parity(B, H, W):
+    net = Net(4, (64, 64))
+    params = cnn.init_params(1)
+    params[-2:] = 0.05           # non-zero head bias
+    net.set_params(torch.from_numpy(params))
+    x, _ = _batch(B, H, W, 2)
+    net.set_input(torch.from_numpy(x))
+    print(f"cnn forward {B}x{H}x{W}", flush=True)
+    out = net.forward().cpu().numpy()
+    ref, _ = cnn.forward(params, x.transpose(0, 2, 3, 1), bf16=True)
+    ref32, _ = _oracle32(cnn.forward, params, x.transpose(0, 2, 3, 1))
+    noise = _rel(ref32, ref)
+    print(f"gpu {_rel(out, ref):.2e}, f32-accumulation noise {noise:.2e}")
+    assert _rel(out, ref) <= 2 * noise + 1e-4
+
+
+def test_gradient_parity():
+    B, H, W = 2, 32, 32
+    net = Net(2, (32, 32))
+    params = cnn.init_params(3)
+    net.set_params(torch.from_numpy(params))
+    x, tgt = _batch(B, H, W, 4)
+    net.set_input(torch.from_numpy(x), torch.from_numpy(tgt))
+    print("cnn gradient", flush=True)
+    loss, g = net.gradient()
+    g = g.cpu().numpy().astype(np.float64)
+    xn = x.transpose(0, 2, 3, 1)
+    ref_loss, ref_g = cnn.loss_and_grad(params, xn, tgt, bf16=True)
+    l32, g32 = _oracle32(cnn.loss_and_grad, params, xn, tgt, bf16=True)
+    assert abs(loss - ref_loss) <= 2 * abs(l32 - ref_loss) + 1e-4 * ref_loss
+    assert _rel(g, ref_g) <= 2 * _rel(g32, ref_g) + 1e-4
+    # layer by layer (weights of each layer)
+    o = 0
+    for name, ci, co, k in cnn.LAYERS:
+        nw = k * k * co * ci
+        sl = slice(o, o + nw)
+        noise = _rel(g32[sl], ref_g[sl])
+        print(f"{name}: gpu {_rel(g[sl], ref_g[sl]):.2e} noise {noise:.2e}")
+        assert _rel(g[sl], ref_g[sl]) <= 2 * noise + 1e-4, name
+        o += nw + co
+
+
+def test_adam_step_and_loss_decrease():
+    B, H, W = 2, 32, 32
+    net = Net(2, (32, 32))
+    params = cnn.init_params(5)
+    net.set_params(torch.from_numpy(params))
+    x, _ = _batch(B, H, W, 6)
+    # a learnable target: the mean of the two neighbour displacements
+    tgt = (0.5 * (x[:, 3:5] + x[:, 5:7])).transpose(0, 2, 3, 1).copy()
+    net.set_input(torch.from_numpy(x), torch.from_numpy(tgt))
+    _, g = net.gradient()
+    g = g.cpu().numpy().astype(np.float64)
+    lr = 1e-3
+    net.train_step(lr)
+    p1 = net.get_params().cpu().numpy().astype(np.float64)
+    ref, _, _ = cnn.adam(params.astype(np.float64), 0 * g, 0 * g, g, 1, lr)
+    np.testing.assert_allclose(p1, ref, rtol=1e-5, atol=1e-6)
+    losses = [net.train_step(lr) for _ in range(60)]
+    print("losses", losses[0], losses[-1])
+    assert losses[-1] < 0.5 * losses[0]
+
+
+def test_assemble_and_emit():
+    n, H, W = 9, 16, 32
+    rng = np.random.default_rng(7)
+    frames = rng.uniform(0.2, 1, (n, H, W)).astype(np.float32)
+    u = rng.uniform(-3, 3, (n, 2, H, W)).astype(np.float32)
+    h = 2.0
+    triples = [(3, 0, 4), (5, 4, 8), (1, 0, 2)]
+    net = Net(4, (32, 32))
+    net.set_params(torch.from_numpy(cnn.init_params(8)))
+    fd = torch.from_numpy(frames).cuda()
+    ud = torch.from_numpy(u).cuda()
+    net.assemble(fd, ud, h, triples, with_target=True)
+    out = net.forward().cpu().numpy()
+    x = np.zeros((3, 7, H, W), np.float32)
+    base = np.zeros((3, 2, H, W))
+    for b, (t, l, r) in enumerate(triples):
+        x[b, 0], x[b, 1], x[b, 2] = frames[l], frames[t], frames[r]
+        x[b, 3:5] = u[l] / h
+        x[b, 5:7] = u[r] / h
+        wl, wr = (r - t) / (r - l), (t - l) / (r - l)
+        base[b] = wl * u[l].astype(np.float64) + wr * u[r]
+    ref, _ = cnn.forward(cnn.init_params(8), x.transpose(0, 2, 3, 1))
+    ref32, _ = _oracle32(cnn.forward, cnn.init_params(8),
+                         x.transpose(0, 2, 3, 1))
+    assert _rel(out, ref) <= 2 * _rel(ref32, ref) + 1e-4
+    unew = ud.clone()
+    net.emit(h, unew)
+    unew = unew.cpu().numpy()
+    for b, (t, l, r) in enumerate(triples):
+        expect = base[b] + h * out[b].transpose(2, 0, 1)
+        np.testing.assert_allclose(unew[t], expect, rtol=1e-5, atol=1e-5)
+    untouched = [k for k in range(n) if k not in (3, 5, 1)]
+    np.testing.assert_array_equal(unew[untouched], u[untouched])
