@@ -80,8 +80,11 @@ typedef struct stml_opts {
   int ls_max;         /* Armijo tries t = 1, 1/2, ..., 2^-ls_max    (10)     */
   double c1;          /* Armijo constant                            (1e-4)   */
   double tol_J;       /* GN stops when the relative decrease of J   (1e-3)   */
-  double tol_u;       /*   and max |t delta| (pixels) are below both (1e-2)  */
-  int predictor;      /* 0 = the paper's interpolation predictors   (0)      */
+  double tol_u;       /*   and the root mean square of the accepted
+                           step t delta (pixels) are below both     (1e-2)   */
+  int predictor;      /* 0 = the paper's interpolation predictors;
+                         1 = also reserve room for a learned predictor
+                         (stml_set_predictor_net)                  (0)      */
   int parity_mode;    /* 1: exactly gn_max GN and cg_max CG iterations,
                          no convergence exits, eq. (3) off          (0)      */
 } stml_opts;
@@ -96,6 +99,14 @@ typedef struct stml_gir_log {
   double D, S, P;         /* parts of J at the last evaluation              */
   int cg_iterations[64];  /* per GN iteration (first 64)                    */
   double step[64];        /* accepted Armijo step t per GN iteration        */
+  double J_iter[64];      /* objective after each accepted step             */
+  double du_max[64];      /* max |t delta| (pixels) of each accepted step    */
+  double du_rms[64];      /* root mean square of t delta (pixels)            */
+  int predictor;          /* start guess: -1 none (q = 0: the spatial
+                             prolongation), 0 the paper's temporal
+                             predictor, 1 the learned one                   */
+  double J_paper, J_learned;  /* objective on the subset at the two
+                             candidate start guesses (NaN if not compared) */
 } stml_gir_log;
 
 void stml_default_opts(stml_opts* opts);
@@ -235,8 +246,12 @@ int stml_timing_get(stml_ctx* ctx, int kernel, int level, double* total_ms,
  * one float32 vector (layer by layer W[tap][c_out][c_in] then b[c_out]);
  * kernels use bfloat16 weights and activations with float32 accumulation
  * (MFMA), float32 gradients, Adam on the float32 master copy.  Extents must
- * be multiples of 8.  All buffers: caller-owned device memory; the net
- * keeps the last assembled batch until the next one. */
+ * be multiples of 8.  The net is sized for max_batch frames of max_extent;
+ * a batch may hold any number B of frames of any extent H x W with
+ * B H W <= max_batch times the pixels of max_extent.  All buffers:
+ * caller-owned device memory; the net keeps the last assembled batch until
+ * the next one.  Errors: STML_EINVAL (shapes, null pointers, triples not
+ * l < t < r), STML_ESTATE (no batch yet), STML_EDEVICE. */
 typedef struct stml_net stml_net;
 
 int stml_net_param_count(int dim);
@@ -253,27 +268,35 @@ int stml_net_get_params(const stml_net* net, float* params_dev);
  * optionally, the target correction [batch][extent][2]. */
 int stml_net_set_input(stml_net* net, const float* x_dev, int channels,
                        const float* target_dev, int batch, const int* extent);
-/* A batch of frames (triples[3b] = t, l, r with l < t < r) from level
- * images [n][extent] and displacements [n][2][extent]; with_target: the
- * target correction (u_t - linear interpolation) / h from the same field. */
+/* A batch of frames (triples[3b] = t, l, r with 0 <= l < t < r < n_frames)
+ * from level images [n_frames][extent] and displacements
+ * [n_frames][2][extent]; with_target: the target correction
+ * (u_t - linear interpolation) / h from the same field. */
 int stml_net_assemble(stml_net* net, const float* frames_dev,
-                      const float* u_dev, const int* extent, double h,
-                      const int* triples, int batch, int with_target);
+                      const float* u_dev, int n_frames, const int* extent,
+                      double h, const int* triples, int batch,
+                      int with_target);
 /* Forward pass; out_dev (may be NULL) receives [batch][extent][32] floats
  * whose first 2 channels are the correction. */
 int stml_net_forward(stml_net* net, float* out_dev);
-/* u_t = linear interpolation + h * correction into u_dev [n][2][extent]
- * for the frames of the last assembled batch (after stml_net_forward). */
+/* u_t = linear interpolation + h * correction into u_dev
+ * [n_frames][2][extent] (n_frames and extent as last assembled) for the
+ * frames of the last assembled batch (after stml_net_forward). */
 int stml_net_emit(stml_net* net, double h, float* u_dev);
 /* Mean squared error of the correction and its gradient wrt the
  * parameters (no update). */
 int stml_net_gradient(stml_net* net, float* grad_dev, double* loss);
 /* Forward, loss, backward and one Adam step (lr > 0). */
 int stml_net_train_step(stml_net* net, double lr, double* loss);
-/* Use net for the prediction of frames left out of K_q on every level
- * whose extents are multiples of 8 (NULL: interpolation only).  The
- * interpolation predictor of Sec. 3 stays the fallback: per prediction
- * step the start guess with the lower objective on K_{q+1} is kept. */
+/* Use net for the prediction of the frames of K_{q+1} \ K_q (each from its
+ * nearest registered neighbours in K_q) on every level whose extents are
+ * multiples of 8 and fit the net (NULL: the paper's predictors only).  The
+ * predictor of Sec. 3 (linear interpolation, eq. (2) on finer levels) stays
+ * the fallback: per prediction step both start guesses are evaluated on
+ * K_{q+1} and the one with the lower objective is kept (a tie keeps the
+ * paper's); the log of the following registration records the choice.
+ * The context must have been created with opts.predictor = 1 (ESTATE
+ * otherwise); the net runs on its own stream and must outlive its use. */
 int stml_set_predictor_net(stml_ctx* ctx, stml_net* net);
 
 #ifdef __cplusplus

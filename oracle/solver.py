@@ -76,8 +76,11 @@ def gauss_newton(frames, u0, K, h, params, gn_max=10, cg_max=20,
     """Minimise J over the frames in K, starting from u0 (all n frames).
 
     Frames outside K keep their displacement.  Unless ``fixed``, stop once
-    an accepted step lowers J by at most tol_J * |J| and moves no
-    displacement by more than tol_u (finest pixels).
+    an accepted step lowers J by at most tol_J * |J| and its root mean
+    square over the moved displacements, t * rms(delta), is at most tol_u
+    (finest pixels).  The paper leaves the optimiser's tests to FAIR, whose
+    tests are relative and norm-based; a maximum over voxels is not used
+    because single voxels near interpolation kinks can keep moving.
     """
     K = list(K)
     u = np.array(u0, dtype=np.float64, copy=True)
@@ -118,7 +121,7 @@ def gauss_newton(frames, u0, K, h, params, gn_max=10, cg_max=20,
             break
         if not fixed:
             if (J - Jt) <= tol_J * abs(J) and \
-                    t * float(np.max(np.abs(delta))) <= tol_u:
+                    t * float(np.sqrt(np.mean(delta * delta))) <= tol_u:
                 break
     res.u = u
     return res

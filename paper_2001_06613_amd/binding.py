@@ -62,6 +62,12 @@ class stml_gir_log(ctypes.Structure):
         ("P", ctypes.c_double),
         ("cg_iterations", ctypes.c_int * 64),
         ("step", ctypes.c_double * 64),
+        ("J_iter", ctypes.c_double * 64),
+        ("du_max", ctypes.c_double * 64),
+        ("du_rms", ctypes.c_double * 64),
+        ("predictor", ctypes.c_int),
+        ("J_paper", ctypes.c_double),
+        ("J_learned", ctypes.c_double),
     ]
 
 
@@ -103,8 +109,8 @@ SIGNATURES = {
     "stml_net_set_params": (_I, [_P, _P]),
     "stml_net_get_params": (_I, [_P, _P]),
     "stml_net_set_input": (_I, [_P, _P, _I, _P, _I, _IP]),
-    "stml_net_assemble": (_I, [_P, _P, _P, _IP, ctypes.c_double, _IP, _I,
-                               _I]),
+    "stml_net_assemble": (_I, [_P, _P, _P, _I, _IP, ctypes.c_double, _IP,
+                               _I, _I]),
     "stml_net_forward": (_I, [_P, _P]),
     "stml_net_emit": (_I, [_P, ctypes.c_double, _P]),
     "stml_net_gradient": (_I, [_P, _P, _DP]),
@@ -252,7 +258,8 @@ class STML:
                                 device=self.device)
 
     def _dev(self, t, shape=None):
-        t = t.to(self.device, self.torch.float32).contiguous()
+        t = self.torch.as_tensor(t).to(self.device,
+                                        self.torch.float32).contiguous()
         if shape is not None and tuple(t.shape) != tuple(shape):
             raise STMLError(STML_EINVAL, f"shape {tuple(t.shape)} != {shape}")
         return t
@@ -315,7 +322,12 @@ class STML:
                         "gn": it, "status": lg.status, "J0": lg.J0,
                         "J": lg.J, "D": lg.D, "S": lg.S, "P": lg.P,
                         "cg": list(lg.cg_iterations[:max(it, 0)]),
-                        "steps": list(lg.step[:max(it, 0)])})
+                        "steps": list(lg.step[:max(it, 0)]),
+                        "J_iter": list(lg.J_iter[:max(it, 0)]),
+                        "du_max": list(lg.du_max[:max(it, 0)]),
+                        "du_rms": list(lg.du_rms[:max(it, 0)]),
+                        "predictor": lg.predictor, "J_paper": lg.J_paper,
+                        "J_learned": lg.J_learned})
         return out
 
     def set_predictor_net(self, net):
@@ -460,14 +472,22 @@ class Net:
         self.cur = (B, H, W)
 
     def assemble(self, frames, u, h, triples, with_target=False):
-        """frames [n][H][W], u [n][2][H][W] device tensors; triples
-        [(t, l, r), ...]."""
-        H, W = frames.shape[1:]
+        """frames [n][H][W], u [n][2][H][W] float32 device tensors; triples
+        [(t, l, r), ...] with 0 <= l < t < r < n."""
+        torch = self.torch
+        n, H, W = frames.shape
+        if (frames.dtype != torch.float32 or u.dtype != torch.float32 or
+                tuple(u.shape) != (n, 2, H, W) or not frames.is_cuda or
+                not u.is_cuda or not frames.is_contiguous() or
+                not u.is_contiguous()):
+            raise STMLError(STML_EINVAL, "frames [n][H][W] and u [n][2][H][W]"
+                            " contiguous float32 device tensors expected")
         flat = [int(v) for tr in triples for v in tr]
         self._check(self.lib.stml_net_assemble(
-            self.net, _ptr(frames), _ptr(u), _int_array((H, W)), float(h),
-            _int_array(flat), len(triples), int(bool(with_target))))
+            self.net, _ptr(frames), _ptr(u), int(n), _int_array((H, W)),
+            float(h), _int_array(flat), len(triples), int(bool(with_target))))
         self.cur = (len(triples), H, W)
+        self.cur_n = int(n)
 
     def forward(self):
         B, H, W = self.cur
@@ -477,6 +497,13 @@ class Net:
         return out[..., :2]
 
     def emit(self, h, u):
+        """u [n][2][H][W] (n, H, W as last assembled) receives the
+        predictions of the assembled frames."""
+        _, H, W = self.cur
+        if (u.dtype != self.torch.float32 or not u.is_cuda or
+                not u.is_contiguous() or
+                tuple(u.shape) != (getattr(self, "cur_n", -1), 2, H, W)):
+            raise STMLError(STML_EINVAL, "u must match the assembled frames")
         self._check(self.lib.stml_net_emit(self.net, float(h), _ptr(u)))
 
     def gradient(self):

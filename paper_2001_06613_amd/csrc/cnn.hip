@@ -600,6 +600,11 @@ struct NetLayout {
 constexpr size_t kWpartCap = (size_t)6 << 20;   // floats of split partials
 constexpr int kBSplit = 1024;
 
+// Frames a batch may hold: every frame has at least 8 x 8 pixels.
+size_t max_frames(const stml_net* n) {
+  return (size_t)n->maxB * n->maxH * n->maxW / 64;
+}
+
 size_t net_layout(stml_net* n, char* base) {
   NetLayout lo;
   lo.base = base;
@@ -658,7 +663,7 @@ size_t net_layout(stml_net* n, char* base) {
   n->dout = lo.take<float>(P0 * kOutLd);
   n->base = lo.take<float>(P0 * 2);
   n->tgt = lo.take<float>(P0 * 2);
-  n->tlr = lo.take<int>(3 * (size_t)n->maxB);
+  n->tlr = lo.take<int>(3 * max_frames(n));
   n->wpart_cap = kWpartCap;
   n->wpart = lo.take<float>(kWpartCap);
   n->bpart_cap = (size_t)kBSplit * 128;
@@ -814,6 +819,13 @@ int conv_back(stml_net* n, int li, Buf& outb, int ooff, const Buf& in,
 
 }  // namespace
 
+namespace stml {
+void net_capacity(const stml_net* n, int* max_batch, long long* max_pixels) {
+  *max_batch = n->maxB;
+  *max_pixels = (long long)n->maxB * n->maxH * n->maxW;
+}
+}  // namespace stml
+
 // ================================================================ C-ABI
 
 extern "C" {
@@ -852,7 +864,7 @@ int stml_net_create(int dim, int max_batch, const int* ext, void* stream,
   n->maxW = ext[1];
   n->stream = (hipStream_t)stream;
   net_layout(n, (char*)ws);
-  if (hipHostMalloc((void**)&n->htlr, 3 * sizeof(int) * max_batch,
+  if (hipHostMalloc((void**)&n->htlr, 3 * sizeof(int) * max_frames(n),
                     hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&n->hloss, sizeof(double),
                     hipHostMallocDefault) != hipSuccess) {
@@ -905,9 +917,9 @@ int stml_net_get_params(const stml_net* n, float* params) {
 }
 
 static int check_shape(const stml_net* n, int B, const int* ext) {
-  if (!ext || B < 1 || B > n->maxB || ext[0] % 8 || ext[1] % 8 ||
-      ext[0] < 8 || ext[1] < 8 || (long long)ext[0] * ext[1] >
-                                      (long long)n->maxH * n->maxW)
+  if (!ext || B < 1 || ext[0] % 8 || ext[1] % 8 || ext[0] < 8 ||
+      ext[1] < 8 ||
+      (long long)B * ext[0] * ext[1] > (long long)n->maxB * n->maxH * n->maxW)
     return STML_EINVAL;
   return STML_OK;
 }
@@ -932,15 +944,17 @@ int stml_net_set_input(stml_net* n, const float* x, int C, const float* tgt,
 }
 
 int stml_net_assemble(stml_net* n, const float* T, const float* U,
-                      const int* ext, double h, const int* triples, int B,
-                      int with_target) {
-  if (!n || !T || !U || !triples || h <= 0) return STML_EINVAL;
+                      int n_frames, const int* ext, double h,
+                      const int* triples, int B, int with_target) {
+  if (!n || !T || !U || !triples || !(h > 0) || n_frames < 3)
+    return STML_EINVAL;
   if (check_shape(n, B, ext)) return STML_EINVAL;
+  for (int b = 0; b < B; ++b) {
+    const int t = triples[3 * b], l = triples[3 * b + 1],
+              r = triples[3 * b + 2];
+    if (!(0 <= l && l < t && t < r && r < n_frames)) return STML_EINVAL;
+  }
   for (int i = 0; i < 3 * B; ++i) n->htlr[i] = triples[i];
-  for (int b = 0; b < B; ++b)
-    if (!(triples[3 * b + 1] < triples[3 * b] &&
-          triples[3 * b] < triples[3 * b + 2]))
-      return STML_EINVAL;
   NET_OK(hipMemcpyAsync(n->tlr, n->htlr, 3 * B * sizeof(int),
                         hipMemcpyHostToDevice, n->stream));
   const int H = ext[0], W = ext[1];

@@ -628,7 +628,8 @@ __global__ __launch_bounds__(256) void trial_kernel(
   double accD[NT];
 #pragma unroll
   for (int s = 0; s < NT; ++s) accD[s] = 0.0;
-  double rA = 0, rB = 0, rC = 0, pA = 0, pB = 0, pC = 0, slope = 0, mx = 0;
+  double rA = 0, rB = 0, rC = 0, pA = 0, pB = 0, pC = 0, slope = 0, mx = 0,
+         sq = 0;
   for (int it = 0;; ++it) {
     long long tile = xcd_tile(ntiles, it);
     if (tile < 0) break;
@@ -650,6 +651,7 @@ __global__ __launch_bounds__(256) void trial_kernel(
         if (valid) {
           slope += (double)gr[o] * dv[a];
           mx = fmax(mx, fabs(dv[a]));
+          sq += dv[a] * dv[a];
           double uu, uw, ww;
           reg_cross<D, REG>(u + ((size_t)k * D + a) * N,
                             dl + ((size_t)j * D + a) * N, p, g, uu, uw, ww);
@@ -700,7 +702,7 @@ __global__ __launch_bounds__(256) void trial_kernel(
     }
     __syncthreads();
   }
-  double vals[NT + 8];
+  double vals[NT + 9];
 #pragma unroll
   for (int s = 0; s < NT; ++s) vals[s] = accD[s];
   vals[NT + 0] = rA;
@@ -711,18 +713,20 @@ __global__ __launch_bounds__(256) void trial_kernel(
   vals[NT + 5] = pC;
   vals[NT + 6] = slope;
   vals[NT + 7] = mx;
-  block_partials<NT + 8>(vals, 1u << (NT + 7), part);
+  vals[NT + 8] = sq;
+  block_partials<NT + 9>(vals, 1u << (NT + 7), part);
 }
 
-// One block: objective at the trial steps, g.delta and max |delta|.
+// One block: objective at the trial steps, g.delta, max |delta| and
+// sum delta^2.
 __global__ __launch_bounds__(256) void finalize_trial_kernel(
     const double* __restrict__ part, int nb, Model md, Steps st,
     Scal* __restrict__ sc, int gn_it, LSPass ls, GNLog* __restrict__ log) {
   if (gn_it >= sc->gn_stop) return;
   if (ls.p > 0 && log[gn_it].next_pass != ls.p) return;
   constexpr int NT = kTrialSteps;
-  double out[NT + 8];
-  reduce_partials<NT + 8>(part, nb, 1u << (NT + 7), out);
+  double out[NT + 9];
+  reduce_partials<NT + 9>(part, nb, 1u << (NT + 7), out);
   if (threadIdx.x == 0) {
     double sA = md.half_alpha_hd * md.reg_scale;
     for (int s = 0; s < NT; ++s) {
@@ -740,6 +744,7 @@ __global__ __launch_bounds__(256) void finalize_trial_kernel(
       L.J0t = sc->Jt[0];
       L.slope = out[NT + 6];
       L.maxd = out[NT + 7];
+      L.ssqd = out[NT + 8];
     }
   }
 }
@@ -797,9 +802,10 @@ __global__ __launch_bounds__(256) void ls_accept_kernel(
     L->Jacc = Jacc;
     L->cg = sc->iters;
     L->status = breakdown ? 2 : 0;
+    const double rms = sqrt(L->ssqd / (double)count);
     bool stop = breakdown ||
                 (!fixed && (L->J - Jacc) <= tol_J * fabs(L->J) &&
-                 tacc * L->maxd <= tol_u);
+                 tacc * rms <= tol_u);
     if (stop) sc->gn_stop = gn_it + 1;
   }
 }

@@ -5,6 +5,8 @@
 
 #include "stml_dev.h"
 
+struct stml_net;
+
 namespace stml {
 
 // Partial-sum slots of the reductions: one region per producing kernel, so
@@ -137,5 +139,9 @@ hipError_t launch_linear_predict(const float* Y, float* Z, float* Yout,
 hipError_t launch_ls_predict(float* Y, float* Z, ThomasTab tab, int n,
                              int dim, long long N, double beta,
                              hipStream_t s);
+
+// Capacity of a learned-predictor net (cnn.hip): the batch it was created
+// for and the pixels a batch may hold in total (frames x pixels per frame).
+void net_capacity(const stml_net* n, int* max_batch, long long* max_pixels);
 
 }  // namespace stml

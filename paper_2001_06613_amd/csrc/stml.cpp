@@ -73,6 +73,11 @@ struct stml_ctx {
   int* hk = nullptr;                    // pinned host staging of frame lists
   bool have_seq = false;
   stml_net* net = nullptr;               // learned predictor (optional)
+  float* ureg = nullptr;                 // registered estimate kept for it
+  struct Pick {
+    int used = -1;
+    double Jp = NAN, Jl = NAN;
+  } pick;                                // start guess of the next GIR
   std::vector<stml_gir_log> logs;
   std::string err;
   // kernel timing
@@ -119,7 +124,8 @@ bool opts_valid(const stml_opts* o) {
           o->regulariser == STML_REG_CURVATURE) &&
          o->alpha >= 0 && o->lambda >= 0 && o->beta >= 0 &&
          o->eps_stop >= 0 && o->gn_max >= 0 && o->cg_max >= 0 &&
-         o->ls_max >= 0 && o->ls_max <= 60;
+         o->ls_max >= 0 && o->ls_max <= 60 &&
+         (o->predictor == 0 || o->predictor == 1);
 }
 
 std::vector<std::vector<int>> level_extents(int dim, const int* extent,
@@ -173,6 +179,7 @@ size_t layout(stml_ctx* c, char* base) {
   c->z = lo.take<float>(vec);
   c->q = lo.take<float>(vec);
   c->M = lo.take<float>(vec);
+  if (c->o.predictor == 1) c->ureg = lo.take<float>(vec);
   {
     size_t NF = (size_t)c->N[c->L - 1];
     c->sums.Sz = lo.take<double>(NF);
@@ -515,7 +522,12 @@ int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
       status = STML_WLINESEARCH;
       break;
     }
-    if (it < 64) log->step[it] = L.t;
+    if (it < 64) {
+      log->step[it] = L.t;
+      log->J_iter[it] = L.Jacc;
+      log->du_max[it] = L.t * L.maxd;
+      log->du_rms[it] = L.t * std::sqrt(L.ssqd / ((double)nK * D * g.N));
+    }
     log->gn_iterations += 1;
     log->J = L.Jacc;
     if (L.status == 2) {
@@ -530,11 +542,89 @@ int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
   return status;
 }
 
+// Objective of GIR(level, K_q) at the field U (no gradient).
+int objective_on(stml_ctx* c, int level, int q, const float* U, double* J) {
+  const Geom g = geom_of(c, level);
+  const Model md = model_of(c, level, (int)c->K[q].size());
+  HIP_OK(launch_eval(c->d, c->lv[level].T, U, c->qt[q].K, g, md, nullptr,
+                     nullptr, c->rb, c->sc, c->stream, true, 0));
+  int rc = read_scal(c);
+  if (rc) return rc;
+  *J = c->hsc->J;
+  return STML_OK;
+}
+
+bool net_fits(const stml_ctx* c, int level) {
+  if (!c->net || !c->ureg || c->d != 2) return false;
+  int maxB = 0;
+  long long maxpix = 0;
+  net_capacity(c->net, &maxB, &maxpix);
+  const std::vector<int>& e = c->ext[level];
+  return e[0] % 8 == 0 && e[1] % 8 == 0 && e[0] >= 8 && e[1] >= 8 &&
+         (long long)e[0] * e[1] <= maxpix;
+}
+
+// Learned start guess for the frames of K_{q_next} \ K_{q_next-1}: the
+// network refines the linear interpolation between each frame's nearest
+// registered neighbours (kept in ureg); the paper's prediction, already in
+// Y and Z, is kept unless the learned one has the lower objective on
+// K_{q_next}.  Both predictors leave Z equal to Y, so the candidate is
+// written into Z and the loser is overwritten by the winner.
+int learned_predict(stml_ctx* c, int level, int q_next) {
+  const std::vector<int>& Kq = c->K[q_next - 1];
+  const std::vector<int>& Kn = c->K[q_next];
+  LevelBufs& b = c->lv[level];
+  std::vector<int> tri;
+  for (int t : Kn) {
+    if (std::binary_search(Kq.begin(), Kq.end(), t)) continue;
+    auto it = std::upper_bound(Kq.begin(), Kq.end(), t);
+    if (it == Kq.begin() || it == Kq.end()) continue;   // K_q holds 0, n-1
+    tri.push_back(t);
+    tri.push_back(*(it - 1));
+    tri.push_back(*it);
+  }
+  const int nt = (int)tri.size() / 3;
+  if (nt == 0) return STML_OK;
+  double Jp = NAN, Jl = NAN;
+  int rc = objective_on(c, level, q_next, b.Y, &Jp);
+  if (rc) return rc;
+  int maxB = 0;
+  long long maxpix = 0;
+  net_capacity(c->net, &maxB, &maxpix);
+  const int* e = c->ext[level].data();
+  const double h = c->h[level];
+  const int per = (int)std::min<long long>(nt, maxpix / ((long long)e[0] * e[1]));
+  for (int s = 0; s < nt; s += per) {
+    int B = std::min(per, nt - s);
+    rc = stml_net_assemble(c->net, b.T, c->ureg, c->n, e, h,
+                           tri.data() + 3 * s, B, 0);
+    if (!rc) rc = stml_net_forward(c->net, nullptr);
+    if (!rc) rc = stml_net_emit(c->net, h, b.Z);
+    if (rc) return fail(c, rc, "learned predictor failed at level %d", level);
+  }
+  rc = objective_on(c, level, q_next, b.Z, &Jl);
+  if (rc) return rc;
+  const bool use = Jl < Jp;
+  const size_t cnt = (size_t)c->n * c->d * c->N[level];
+  HIP_OK(hipMemcpyAsync(use ? b.Y : b.Z, use ? b.Z : b.Y, cnt * sizeof(float),
+                        hipMemcpyDeviceToDevice, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  c->pick.used = use ? 1 : 0;
+  c->pick.Jp = Jp;
+  c->pick.Jl = Jl;
+  return STML_OK;
+}
+
 int do_predict(stml_ctx* c, int level, int q_next) {
   const int n = c->n, D = c->d;
   LevelBufs& b = c->lv[level];
   const size_t cnt = (size_t)n * D * c->N[level];
   const double vf = (double)n * c->N[level];
+  c->pick = stml_ctx::Pick{};
+  const bool learned = q_next > 0 && net_fits(c, level);
+  if (learned)
+    HIP_OK(hipMemcpyAsync(c->ureg, b.Y, cnt * sizeof(float),
+                          hipMemcpyDeviceToDevice, c->stream));
   if (q_next == 0) {
     if (level == 0) {
       HIP_OK(launch_fill(b.Z, cnt, 0.0f, c->stream));
@@ -557,6 +647,8 @@ int do_predict(stml_ctx* c, int level, int q_next) {
   }
   HIP_OK(hipStreamSynchronize(c->stream));
   tresolve(c);
+  if (q_next > 0) c->pick.used = 0;
+  if (learned) return learned_predict(c, level, q_next);
   return STML_OK;
 }
 
@@ -567,6 +659,10 @@ int do_register(stml_ctx* c, int level, int q) {
   if (rc < 0 && rc != STML_EBREAKDOWN) return rc;
   log.level = level;
   log.q = q;
+  log.predictor = c->pick.used;
+  log.J_paper = c->pick.Jp;
+  log.J_learned = c->pick.Jl;
+  c->pick = stml_ctx::Pick{};
   c->logs.push_back(log);
   if (rc == STML_EBREAKDOWN) return fail(c, rc, "CG breakdown (p.Hp <= 0)");
   if (rc == STML_WLINESEARCH)
@@ -935,6 +1031,8 @@ int stml_gn_direction(stml_ctx* c, int level, const int* frames, int nk,
 int stml_set_predictor_net(stml_ctx* c, stml_net* net) {
   if (!c) return STML_EINVAL;
   if (net && c->d != 2) return fail(c, STML_EINVAL, "learned predictor: 2-D");
+  if (net && !c->ureg)
+    return fail(c, STML_ESTATE, "create the context with predictor = 1");
   c->net = net;
   return STML_OK;
 }

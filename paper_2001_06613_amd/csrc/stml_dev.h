@@ -66,6 +66,7 @@ struct GNLog {
   double Jacc;                // objective at the accepted step
   double t;                   // accepted step
   double slope, maxd;         // g . delta and max |delta|
+  double ssqd;                // sum of delta^2
   int cg;                     // CG iterations
   int status;                 // -1 not run, 0 accepted, 1 no step found,
                               // 2 accepted after a CG breakdown

@@ -77,6 +77,31 @@ def test_register_level_parity(reg, nt):
 
 
 @pytest.mark.parametrize("reg", ["diffusion", "curvature"])
+def test_register_level_convergence_stop(reg):
+    """Outside parity mode CG stops at cg_rtol and Gauss-Newton at the
+    tol_J / tol_u test; the counts, steps and result match the oracle."""
+    frames = _small()
+    n, ext = 8, frames.shape[1:]
+    kw = dict(n_spatial=1, n_temporal=2, reg=reg, gn_max=40, cg_max=20,
+              tol_J=1e-3, tol_u=2e-2, parity_mode=False)
+    st = STML(n, ext, opts=default_opts(**kw))
+    st.set_sequence(torch.from_numpy(frames).cuda())
+    st.predict(0, 0)
+    st.register_level(0, 0)
+    ost = oracle.stml.STMLState(frames, oracle.STMLOptions(**kw))
+    ost.predict(0, 0)
+    ost.register_level(0, 0)
+    lg, olg = st.logs()[0], ost.log[0]
+    print("gn", lg["gn"], olg["gn"], "cg", lg["cg"], olg["cg"], flush=True)
+    assert lg["gn"] == olg["gn"] < kw["gn_max"]
+    assert lg["cg"] == olg["cg"]
+    assert lg["steps"] == olg["steps"]
+    assert lg["J"] == pytest.approx(olg["J"], rel=1e-5)
+    u = st.get_displacements(0).cpu().numpy()
+    assert np.abs(u - ost.Y[0]).max() <= 1e-3
+
+
+@pytest.mark.parametrize("reg", ["diffusion", "curvature"])
 def test_stml_run_parity_small(reg):
     """Whole schedule: 2 spatial x 2 temporal levels, 8 frames of 64x64."""
     frames = _small()
