@@ -246,7 +246,7 @@ int stml_timing_get(stml_ctx* ctx, int kernel, int level, double* total_ms,
  * one float32 vector (layer by layer W[tap][c_out][c_in] then b[c_out]);
  * kernels use bfloat16 weights and activations with float32 accumulation
  * (MFMA), float32 gradients, Adam on the float32 master copy.  Extents must
- * be multiples of 8.  The net is sized for max_batch frames of max_extent;
+ * be multiples of 8, widths at most 256.  The net is sized for max_batch frames of max_extent;
  * a batch may hold any number B of frames of any extent H x W with
  * B H W <= max_batch times the pixels of max_extent.  All buffers:
  * caller-owned device memory; the net keeps the last assembled batch until

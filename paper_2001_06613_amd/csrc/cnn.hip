@@ -8,20 +8,28 @@
 // correction in level pixels.  Parameters: one float32 vector, layer by
 // layer W[tap][c_out][c_in] then b[c_out] (the order of the CPU reference).
 //
-// Convolution as an implicit GEMM on v_mfma_f32_16x16x32_bf16: a wave
-// multiplies a 16 (output channels) x 32 (input channels) weight slice by a
-// 32 x 16 (pixels) input slice.  Forward: A = weights, B = input.
-// Backward data: the same kernel with the flipped, transposed weights.
-// Weight gradient: pixels are the reduction dimension; 32-pixel chunks of
-// the upstream gradient and of the shifted input are staged in LDS
-// transposed, split-K partials are summed in a fixed order by the Adam
-// kernel.  Activations are bfloat16; gradients float32 (rounded to bfloat16
-// where they enter a matrix instruction).
+// Convolution as an implicit GEMM on v_mfma_f32_32x32x16_bf16 (A = weights,
+// B = input, D = output channels x pixels): a block computes 256 or 512
+// consecutive output pixels (batch-flattened NHWC) by 32 or 64 output
+// channels.  Per 16-channel chunk of the input it stages in LDS the input
+// rows the taps reach (the pixel range widened by one image row and one
+// pixel on each side) and the weights of every tap; each wave then runs the
+// taps as MFMA steps with its operands reused across a 2 x 2 (or 4 x 1)
+// grid of 32 x 32 output tiles.  The decoder's upsampled channels are read
+// straight from the low-resolution tensor (nearest upsampling), so the
+// concatenation [skip, up] is never materialised.  Backward data: the same
+// kernel with the flipped, transposed weights.  Weight gradient: pixels
+// are the reduction dimension; 32-pixel chunks of the upstream gradient and
+// of the shifted input are staged in LDS transposed, split-K partials are
+// summed in a fixed order by the Adam kernel.  Activations are bfloat16;
+// gradients float32 (rounded to bfloat16 where they enter a matrix
+// instruction).
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstring>
 #include <random>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/stml.h"
@@ -33,9 +41,12 @@ namespace cnn {
 typedef __bf16 bf16;
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float f32x4;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
+typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 
 constexpr int kCinPad = 32;
 constexpr int kOutLd = 32;     // channels of the head output (2 real)
+constexpr int kMaxConvW = 256; // widest image row the 3x3 convolution stages
 
 struct LayerDef {
   const char* name;
@@ -68,79 +79,167 @@ __device__ __forceinline__ bf16x8 load8(const float* p) {
   return r;
 }
 
-// Y[b,y,x, yoff + co] = act(bias[co] + sum_tap sum_ci
-//                          X[b, y+dy, x+dx, xoff + ci] Wt[tap][co][ci])
-// (zero padding).  Block: one 64-pixel row segment x 16*MT output channels;
-// wave w owns pixels 16w..16w+15 of the segment.
-template <int K, int MT, class TX, bool OUT_F32, bool RELU>
+// Input channels of a convolution: [0, split) from a0 at the layer's
+// resolution, [split, cin_p) from a1 at half resolution (pixel (y, x) reads
+// a1's (y / 2, x / 2): nearest upsampling).  split is a multiple of 16.
+template <class TX>
+struct ConvSrc {
+  const TX* a0;
+  int ld0, off0;
+  const TX* a1;
+  int ld1, off1;
+  int split;
+};
+
+constexpr int kRowLd = 24;      // LDS row: 16 channels + 8 of padding
+
+// Y[p][yoff + co] = act(bias[co] + sum_tap sum_ci X[p + off(tap)][ci]
+//                   Wt[tap][co][ci]) with zero padding, p = (b, y, x)
+// flattened.  Block: 128 PS pixels x 32 CS output channels; wave w owns
+// pixel subtiles PS w .. PS w + PS - 1 (32 pixels each) and all CS channel
+// subtiles.  Requires W <= 256 (LDS rows of the halo), cin_p % 16 == 0.
+template <int K, int CS, int PS, class TX, bool OUT_F32, bool RELU>
 __global__ __launch_bounds__(256) void conv_kernel(
-    const TX* __restrict__ X, int xld, int xoff, int cin_p,
-    const bf16* __restrict__ Wt, const float* __restrict__ bias, int cout,
-    int cout_p, void* __restrict__ Yv, int yld, int yoff, int H, int W,
-    int nxb) {
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int bx = blockIdx.x % nxb;
-  const int row = blockIdx.x / nxb;
-  const int y = row % H, b = row / H;
-  const int co_base = blockIdx.y * 16 * MT;
-  const int px = bx * 64 + w * 16 + (lane & 15);
-  const int kq = (lane >> 4) * 8;
-  f32x4 acc[MT];
+    ConvSrc<TX> src, int cin_p, const bf16* __restrict__ Wt,
+    const float* __restrict__ bias, int cout, int cout_p,
+    void* __restrict__ Yv, int yld, int yoff, int B, int H, int W) {
+  constexpr int TP = 128 * PS;           // pixels per block
+  constexpr int COB = 32 * CS;           // output channels per block
+  extern __shared__ __align__(16) bf16 lds[];
+  const int R = K == 3 ? W + 1 : 0;      // halo of the flattened range
+  const int NR = TP + 2 * R;             // staged rows
+  bf16* act = lds;
+  bf16* wl = lds + (size_t)NR * kRowLd;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int ln = lane & 31, kh = lane >> 5;
+  const long long HW = (long long)H * W;
+  const long long P = (long long)B * HW;
+  const long long p0 = (long long)blockIdx.x * TP;
+  const int co_base = blockIdx.y * COB;
+  // this lane's pixels
+  int py[PS], pxx[PS];
+  bool pv[PS];
 #pragma unroll
-  for (int m = 0; m < MT; ++m) acc[m] = f32x4{0.f, 0.f, 0.f, 0.f};
+  for (int s = 0; s < PS; ++s) {
+    long long p = p0 + 32 * (PS * w + s) + ln;
+    pv[s] = p < P;
+    long long rem = pv[s] ? p % HW : 0;
+    py[s] = (int)(rem / W);
+    pxx[s] = (int)(rem - (long long)py[s] * W);
+  }
+  f32x16 acc[PS][CS];
+#pragma unroll
+  for (int s = 0; s < PS; ++s)
+#pragma unroll
+    for (int c = 0; c < CS; ++c)
+#pragma unroll
+      for (int i = 0; i < 16; ++i) acc[s][c][i] = 0.f;
   const bf16x8 zero = {};
-  for (int tap = 0; tap < K * K; ++tap) {
-    const int yi = y + tap / K - K / 2, xi = px + tap % K - K / 2;
-    const bool inb = px < W && yi >= 0 && yi < H && xi >= 0 && xi < W;
-    const size_t pix = ((size_t)b * H + (inb ? yi : 0)) * W + (inb ? xi : 0);
-    const TX* xp = X + pix * xld + xoff + kq;
-    const bf16* wp = Wt + ((size_t)tap * cout_p + co_base + (lane & 15)) *
-                              cin_p + kq;
-    for (int c0 = 0; c0 < cin_p; c0 += 32) {
-      bf16x8 bop = inb ? load8(xp + c0) : zero;
+  const int H1 = H >> 1, W1 = W >> 1;
+  for (int c0 = 0; c0 < cin_p; c0 += 16) {
+    // stage the input rows [p0 - R, p0 + TP + R) of this channel chunk
+    const bool hi = c0 >= src.split;
+    const TX* sp = hi ? src.a1 : src.a0;
+    const int sld = hi ? src.ld1 : src.ld0;
+    const int soff = hi ? src.off1 + c0 - src.split : src.off0 + c0;
+    for (int e = tid; e < 2 * NR; e += 256) {
+      const int row = e >> 1, hf = e & 1;
+      const long long q = p0 - R + row;
+      bf16x8 v = zero;
+      if (q >= 0 && q < P) {
+        long long idx = q;
+        if (hi) {
+          const long long b = q / HW;
+          const int rem = (int)(q - b * HW);
+          const int yy = rem / W, xx = rem - yy * W;
+          idx = (b * H1 + (yy >> 1)) * W1 + (xx >> 1);
+        }
+        v = load8(sp + idx * sld + soff + 8 * hf);
+      }
+      *reinterpret_cast<bf16x8*>(act + row * kRowLd + 8 * hf) = v;
+    }
+    // stage the weights of every tap for the block's output channels
+    for (int e = tid; e < 2 * K * K * COB; e += 256) {
+      const int row = e >> 1, hf = e & 1;
+      const int tap = row / COB, co = row - tap * COB;
+      *reinterpret_cast<bf16x8*>(wl + row * kRowLd + 8 * hf) =
+          load8(Wt + ((size_t)tap * cout_p + co_base + co) * cin_p + c0 +
+                8 * hf);
+    }
+    __syncthreads();
 #pragma unroll
-      for (int m = 0; m < MT; ++m) {
-        bf16x8 aop = load8(wp + (size_t)16 * m * cin_p + c0);
-        acc[m] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, acc[m], 0,
-                                                         0, 0);
+    for (int tap = 0; tap < K * K; ++tap) {
+      const int dy = tap / K - K / 2, dx = tap % K - K / 2;
+      bf16x8 bop[PS];
+#pragma unroll
+      for (int s = 0; s < PS; ++s) {
+        const int yy = py[s] + dy, xx = pxx[s] + dx;
+        const bool ok = pv[s] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+        const int row = 32 * (PS * w + s) + ln + R + dy * W + dx;
+        bop[s] = ok ? *reinterpret_cast<const bf16x8*>(act + row * kRowLd +
+                                                       8 * kh)
+                    : zero;
+      }
+#pragma unroll
+      for (int c = 0; c < CS; ++c) {
+        const bf16x8 aop = *reinterpret_cast<const bf16x8*>(
+            wl + (tap * COB + 32 * c + ln) * kRowLd + 8 * kh);
+#pragma unroll
+        for (int s = 0; s < PS; ++s)
+          acc[s][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop, bop[s],
+                                                              acc[s][c], 0, 0,
+                                                              0);
       }
     }
+    __syncthreads();
   }
-  if (px >= W) return;
-  const size_t obase = (((size_t)b * H + y) * W + px) * yld + yoff;
+  // D[co][pixel]: lane holds pixel ln, channels 8 g + 4 kh + (0..3)
 #pragma unroll
-  for (int m = 0; m < MT; ++m) {
-    const int c = co_base + 16 * m + (lane >> 4) * 4;
-    float v[4];
+  for (int s = 0; s < PS; ++s) {
+    if (!pv[s]) continue;
+    const long long p = p0 + 32 * (PS * w + s) + ln;
+    const size_t obase = (size_t)p * yld + yoff;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      float bb = (bias && c + i < cout) ? bias[c + i] : 0.f;
-      v[i] = acc[m][i] + bb;
-      if (RELU) v[i] = v[i] > 0.f ? v[i] : 0.f;
-    }
-    if (OUT_F32) {
-      float* Y = reinterpret_cast<float*>(Yv) + obase + c;
-      *reinterpret_cast<f32x4*>(Y) = f32x4{v[0], v[1], v[2], v[3]};
-    } else {
-      bf16* Y = reinterpret_cast<bf16*>(Yv) + obase + c;
-      typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
-      *reinterpret_cast<bf16x4*>(Y) =
-          bf16x4{(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
-    }
+    for (int c = 0; c < CS; ++c)
+#pragma unroll
+      for (int g = 0; g < 4; ++g) {
+        const int co = co_base + 32 * c + 8 * g + 4 * kh;
+        float v[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+          float bb = (bias && co + i < cout) ? bias[co + i] : 0.f;
+          v[i] = acc[s][c][4 * g + i] + bb;
+          if (RELU) v[i] = v[i] > 0.f ? v[i] : 0.f;
+        }
+        if (OUT_F32) {
+          *reinterpret_cast<f32x4*>(reinterpret_cast<float*>(Yv) + obase +
+                                    co) = f32x4{v[0], v[1], v[2], v[3]};
+        } else {
+          *reinterpret_cast<bf16x4*>(reinterpret_cast<bf16*>(Yv) + obase +
+                                     co) =
+              bf16x4{(bf16)v[0], (bf16)v[1], (bf16)v[2], (bf16)v[3]};
+        }
+      }
   }
 }
 
+constexpr int kWChunk = 128;    // pixels staged per step of the weight gradient
+constexpr int kWLd = kWChunk + 8;
+
 // part[s][tap][co][ci] = sum over the pixels of split s of
-//   bf16(dP[p][poff + co]) * X[p + off(tap)][xoff + ci]   (zero padding)
+//   bf16(dP[p][poff + co]) * X[p + off(tap)][ci]   (zero padding)
 // Block: 64 output channels x 64 input channels of one tap; wave w owns
-// output channels 16w..16w+15.
+// output channels 16w..16w+15 and all four 16-channel input subtiles.  Per
+// step 128 pixels of dP and of the shifted input are staged transposed
+// (channel-major) in LDS: thread t loads 32 contiguous channels of pixel
+// t % 128.
 template <int K>
 __global__ __launch_bounds__(256) void wgrad_kernel(
     const float* __restrict__ dP, int pld, int poff, int cout_p,
-    const bf16* __restrict__ X, int xld, int xoff, int cin_p, int B, int H,
-    int W, int chunks_per_split, float* __restrict__ part) {
-  __shared__ bf16 As[64][40];
-  __shared__ bf16 Bs[64][40];
+    ConvSrc<bf16> X, int cin_p, int B, int H, int W, int chunks_per_split,
+    float* __restrict__ part) {
+  __shared__ __align__(16) bf16 As[64][kWLd];
+  __shared__ __align__(16) bf16 Bs[64][kWLd];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   const int nco = (cout_p + 63) / 64, nci = (cin_p + 63) / 64;
   int t = blockIdx.y;
@@ -151,7 +250,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(
   const int dy = tap / K - K / 2, dx = tap % K - K / 2;
   const int s = blockIdx.x;
   const long long P = (long long)B * H * W;
-  const long long nchunks = (P + 31) / 32;
+  const long long nchunks = (P + kWChunk - 1) / kWChunk;
   const long long c_beg = (long long)s * chunks_per_split;
   long long c_end = c_beg + chunks_per_split;
   if (c_end > nchunks) c_end = nchunks;
@@ -159,47 +258,63 @@ __global__ __launch_bounds__(256) void wgrad_kernel(
   f32x4 acc[4];
 #pragma unroll
   for (int n = 0; n < 4; ++n) acc[n] = f32x4{0.f, 0.f, 0.f, 0.f};
-  // staging role of this thread: pixel sp of the chunk, 8 channels at c8
-  const int sp = threadIdx.x >> 3, c8 = (threadIdx.x & 7) * 8;
+  const int sp = threadIdx.x & (kWChunk - 1), c32 = (threadIdx.x >> 7) * 32;
+  const int co0 = cob * 64 + c32, ci0 = cib * 64 + c32;
   for (long long ch = c_beg; ch < c_end; ++ch) {
-    const long long p = ch * 32 + sp;
+    const long long p = ch * kWChunk + sp;
     {
-      float v[8];
-      const int co = cob * 64 + c8;
-      if (p < P && co < cout_p) {
-        const float* src = dP + p * pld + poff + co;
-        f32x4 a = *reinterpret_cast<const f32x4*>(src);
-        f32x4 c = *reinterpret_cast<const f32x4*>(src + 4);
-        v[0] = a[0]; v[1] = a[1]; v[2] = a[2]; v[3] = a[3];
-        v[4] = c[0]; v[5] = c[1]; v[6] = c[2]; v[7] = c[3];
-      } else {
+      float v[32];
 #pragma unroll
-        for (int i = 0; i < 8; ++i) v[i] = 0.f;
+      for (int i = 0; i < 32; ++i) v[i] = 0.f;
+      if (p < P && co0 < cout_p) {
+        const float* src = dP + p * pld + poff + co0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          f32x4 a = *reinterpret_cast<const f32x4*>(src + 4 * q);
+          v[4 * q] = a[0];
+          v[4 * q + 1] = a[1];
+          v[4 * q + 2] = a[2];
+          v[4 * q + 3] = a[3];
+        }
       }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) As[c8 + i][sp] = (bf16)v[i];
+      for (int i = 0; i < 32; ++i) As[c32 + i][sp] = (bf16)v[i];
     }
     {
-      bf16x8 v = {};
-      const int ci = cib * 64 + c8;
-      if (p < P && ci < cin_p) {
+      bf16x8 v[4] = {};
+      if (p < P && ci0 < cin_p) {
         const long long pb = p / ((long long)H * W);
         const int rem = (int)(p - pb * H * W);
         const int yy = rem / W + dy, xx = rem % W + dx;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W)
-          v = load8(X + (((size_t)pb * H + yy) * W + xx) * xld + xoff + ci);
+        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+          const bf16* src =
+              ci0 < X.split
+                  ? X.a0 + (((size_t)pb * H + yy) * W + xx) * X.ld0 + X.off0 +
+                        ci0
+                  : X.a1 +
+                        (((size_t)pb * (H >> 1) + (yy >> 1)) * (W >> 1) +
+                         (xx >> 1)) * X.ld1 + X.off1 + ci0 - X.split;
+#pragma unroll
+          for (int q = 0; q < 4; ++q) v[q] = load8(src + 8 * q);
+        }
       }
 #pragma unroll
-      for (int i = 0; i < 8; ++i) Bs[c8 + i][sp] = v[i];
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int i = 0; i < 8; ++i) Bs[c32 + 8 * q + i][sp] = v[q][i];
     }
     __syncthreads();
-    const bf16x8 aop = *reinterpret_cast<const bf16x8*>(&As[16 * w + (lane & 15)][kq]);
 #pragma unroll
-    for (int n = 0; n < 4; ++n) {
-      const bf16x8 bop =
-          *reinterpret_cast<const bf16x8*>(&Bs[16 * n + (lane & 15)][kq]);
-      acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, acc[n], 0, 0,
-                                                       0);
+    for (int k0 = 0; k0 < kWChunk; k0 += 32) {
+      const bf16x8 aop = *reinterpret_cast<const bf16x8*>(
+          &As[16 * w + (lane & 15)][k0 + kq]);
+#pragma unroll
+      for (int n = 0; n < 4; ++n) {
+        const bf16x8 bop = *reinterpret_cast<const bf16x8*>(
+            &Bs[16 * n + (lane & 15)][k0 + kq]);
+        acc[n] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aop, bop, acc[n], 0,
+                                                         0, 0);
+      }
     }
     __syncthreads();
   }
@@ -233,18 +348,31 @@ __global__ void bias_grad_kernel(const float* __restrict__ dP, int pld,
   bpart[(size_t)blockIdx.x * cout_p + co] = acc;
 }
 
+// gb[co] = sum_s bpart[s][co]: one wave per channel, lane i sums the
+// splits i, i + 64, ..., then a fixed butterfly (deterministic order).
+__global__ __launch_bounds__(64) void bias_reduce_kernel(
+    const float* __restrict__ bpart, int bsplit, int cout_p,
+    float* __restrict__ gb) {
+  const int co = blockIdx.x, lane = threadIdx.x;
+  float acc = 0.f;
+  for (int s = lane; s < bsplit; s += 64) acc += bpart[(size_t)s * cout_p + co];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+  if (lane == 0) gb[co] = acc;
+}
+
 struct AdamArgs {
   float lr, b1, b2, eps, c1, c2;   // c1 = 1/(1-b1^t), c2 = 1/(1-b2^t)
   int apply;
 };
 
-// Gradient of one layer from the split partials (fixed summation order),
+// Gradient of one layer from the split partials (fixed summation order) and
+// the reduced bias gradient gb,
 // optional copy out, Adam step on the float32 master, and the bfloat16
 // forward (Wt[tap][co_p][ci_p]) and backward (Wb[K2-1-tap][ci_p][co_p])
 // weight copies.
 __global__ void adam_layer_kernel(const float* __restrict__ part, int nsplit,
-                                  const float* __restrict__ bpart, int bsplit,
-                                  int K2, int cout, int cin, int cout_p,
+                                  const float* __restrict__ gb, int K2, int cout, int cin, int cout_p,
                                   int cin_p, float* __restrict__ master,
                                   float* __restrict__ m, float* __restrict__ v,
                                   float* __restrict__ grad_out, bf16* Wt,
@@ -259,11 +387,13 @@ __global__ void adam_layer_kernel(const float* __restrict__ part, int nsplit,
     int r = e - tap * cout * cin;
     co = r / cin;
     ci = r - co * cin;
-    for (int s = 0; s < nsplit; ++s)
-      g += part[(((size_t)s * K2 + tap) * cout_p + co) * cin_p + ci];
+    const size_t stride = (size_t)K2 * cout_p * cin_p;
+    const float* pp = part + ((size_t)tap * cout_p + co) * cin_p + ci;
+#pragma unroll 8
+    for (int s = 0; s < nsplit; ++s) g += pp[(size_t)s * stride];
   } else {
     co = e - nw;
-    for (int s = 0; s < bsplit; ++s) g += bpart[(size_t)s * cout_p + co];
+    g = gb[co];
   }
   if (grad_out) grad_out[e] = g;
   if (!a.apply) return;
@@ -356,24 +486,6 @@ __global__ void pool_bwd_add_kernel(const float* __restrict__ dY, int C,
     int Hi = H / 2, Wi = W / 2;
     float g = dY[(((size_t)b * Hi + y / 2) * Wi + x / 2) * C + c] * 0.25f;
     dX[q * dld + doff + c] += g;
-  }
-}
-
-// Y[y][x][off + c] = X[y/2][x/2][c]
-__global__ void up_kernel(const bf16* __restrict__ X, int C, int B, int H,
-                          int W, bf16* __restrict__ Y, int yld, int yoff) {
-  long long n = (long long)B * H * W * C;
-  long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-  long long st = (long long)gridDim.x * blockDim.x;
-  for (; i < n; i += st) {
-    int c = (int)(i % C);
-    long long q = i / C;
-    int x = (int)(q % W);
-    long long r = q / W;
-    int y = (int)(r % H);
-    int b = (int)(r / H);
-    Y[q * yld + yoff + c] =
-        X[(((size_t)b * (H / 2) + y / 2) * (W / 2) + x / 2) * C + c];
   }
 }
 
@@ -574,6 +686,7 @@ struct stml_net {
   size_t wpart_cap = 0;     // floats
   float* bpart = nullptr;
   size_t bpart_cap = 0;
+  float* gb = nullptr;      // reduced bias gradient of one layer
   double* lpart = nullptr;
   double* dloss = nullptr;
   double* hloss = nullptr;  // pinned
@@ -668,6 +781,7 @@ size_t net_layout(stml_net* n, char* base) {
   n->wpart = lo.take<float>(kWpartCap);
   n->bpart_cap = (size_t)kBSplit * 128;
   n->bpart = lo.take<float>(n->bpart_cap);
+  n->gb = lo.take<float>(256);
   n->lpart = lo.take<double>(8192);
   n->dloss = lo.take<double>(1);
   return lo.off;
@@ -678,39 +792,62 @@ size_t net_layout(stml_net* n, char* base) {
     if ((call) != hipSuccess) return STML_EDEVICE; \
   } while (0)
 
-hipError_t conv_launch(stml_net* n, const Layer& l, const void* X, bool x_f32,
-                       int xld, int xoff, int cin_p, const bf16* Wmat,
-                       const float* bias, int cout, int cout_p, void* Y,
-                       bool y_f32, int yld, int yoff, bool relu, int B, int H,
-                       int W) {
-  const int nxb = (W + 63) / 64;
-  const int nt = cout_p / 16;
-  const int MT = nt % 4 == 0 ? 4 : (nt % 2 == 0 ? 2 : 1);
-  dim3 grid(nxb * H * B, cout_p / (16 * MT));
+// One convolution: K x K taps, input src (cin_p channels), weights
+// Wmat[tap][cout_p][cin_p], output Y (yld, yoff) in float32 or bfloat16.
+// 64-channel blocks (2 x 2 tiles per wave) when cout_p allows, else
+// 32-channel blocks of 512 pixels (4 x 1 tiles per wave).
+template <class TX>
+hipError_t conv_launch(stml_net* n, int K, const ConvSrc<TX>& src, int cin_p,
+                       const bf16* Wmat, const float* bias, int cout,
+                       int cout_p, void* Y, bool y_f32, int yld, int yoff,
+                       bool relu, int B, int H, int W) {
+  if ((K != 1 && K != 3) || cin_p % 16 || cout_p % 32 || src.split % 16 ||
+      (K == 3 && W > kMaxConvW))
+    return hipErrorInvalidValue;
+  const bool wide = cout_p % 64 == 0;
+  const int TP = wide ? 256 : 512, COB = wide ? 64 : 32;
+  const int R = K == 3 ? W + 1 : 0;
+  const size_t lds = ((size_t)(TP + 2 * R) + (size_t)K * K * COB) * kRowLd *
+                     sizeof(bf16);
+  const long long P = (long long)B * H * W;
+  dim3 grid((unsigned)((P + TP - 1) / TP), cout_p / COB);
   hipStream_t s = n->stream;
-#define CONV_CASE(KK, MTT, TXX, OF, RL)                                       \
-  conv_kernel<KK, MTT, TXX, OF, RL><<<grid, 256, 0, s>>>(                     \
-      (const TXX*)X, xld, xoff, cin_p, Wmat, bias, cout, cout_p, Y, yld, yoff, \
-      H, W, nxb)
-  if (l.k == 3 && !x_f32 && !y_f32 && relu && MT == 4) CONV_CASE(3, 4, bf16, false, true);
-  else if (l.k == 3 && !x_f32 && !y_f32 && relu && MT == 2) CONV_CASE(3, 2, bf16, false, true);
-  else if (l.k == 1 && !x_f32 && y_f32 && !relu && MT == 2) CONV_CASE(1, 2, bf16, true, false);
-  else if (l.k == 3 && x_f32 && y_f32 && !relu && MT == 4) CONV_CASE(3, 4, float, true, false);
-  else if (l.k == 3 && x_f32 && y_f32 && !relu && MT == 2) CONV_CASE(3, 2, float, true, false);
-  else if (l.k == 1 && x_f32 && y_f32 && !relu && MT == 2) CONV_CASE(1, 2, float, true, false);
-  else return hipErrorInvalidValue;
+  constexpr bool F = std::is_same<TX, float>::value;
+#define CONV_CASE(KK, CSS, PSS, OF, RL)                                      \
+  conv_kernel<KK, CSS, PSS, TX, OF, RL><<<grid, 256, lds, s>>>(             \
+      src, cin_p, Wmat, bias, cout, cout_p, Y, yld, yoff, B, H, W)
+  if (!F && K == 3 && !y_f32 && relu) {
+    if (wide) CONV_CASE(3, 2, 2, false, true);
+    else CONV_CASE(3, 1, 4, false, true);
+  } else if (K == 3 && y_f32 && !relu) {
+    if (wide) CONV_CASE(3, 2, 2, true, false);
+    else CONV_CASE(3, 1, 4, true, false);
+  } else if (K == 1 && y_f32 && !relu && !wide) {
+    CONV_CASE(1, 1, 4, true, false);
+  } else {
+    return hipErrorInvalidValue;
+  }
 #undef CONV_CASE
   return hipGetLastError();
 }
 
+ConvSrc<bf16> one_src(const Buf& b, int off, int C) {
+  return ConvSrc<bf16>{b.a, b.ld, off, nullptr, 0, 0, C};
+}
+
+// [skip channels of b, upsampled channels of low]
+ConvSrc<bf16> cat_src(const Buf& b, int skipC, const Buf& low) {
+  return ConvSrc<bf16>{b.a, b.ld, 0, low.a, low.ld, 0, skipC};
+}
+
 // Forward through every layer for B images of H x W (multiples of 8).
 int net_forward(stml_net* n, int B, int H, int W) {
-  auto conv3 = [&](int li, const Buf& in, int ioff, Buf& outb, int ooff) {
+  auto conv3 = [&](int li, const ConvSrc<bf16>& in, int lev, Buf& outb,
+                   int ooff) {
     const Layer& l = n->L[li];
-    int lev = in.level;
-    return conv_launch(n, l, in.a, false, in.ld, ioff, l.ci_p, l.Wt,
-                       n->master + l.boff, l.co, l.co_p, outb.a, false,
-                       outb.ld, ooff, true, B, H >> lev, W >> lev);
+    return conv_launch(n, 3, in, l.ci_p, l.Wt, n->master + l.boff, l.co,
+                       l.co_p, outb.a, false, outb.ld, ooff, true, B, H >> lev,
+                       W >> lev);
   };
   auto pool = [&](const Buf& in, int ioff, int C, Buf& outb) {
     int lev = in.level;
@@ -719,35 +856,25 @@ int net_forward(stml_net* n, int B, int H, int W) {
         in.a, in.ld, ioff, C, B, h, w, outb.a, outb.ld);
     return hipGetLastError();
   };
-  auto up = [&](const Buf& in, int C, Buf& outb, int ooff) {
-    int lev = outb.level;
-    int h = H >> lev, w = W >> lev;
-    up_kernel<<<gridsz((long long)B * h * w * C), 256, 0, n->stream>>>(
-        in.a, C, B, h, w, outb.a, outb.ld, ooff);
-    return hipGetLastError();
-  };
-  NET_OK(conv3(E1A, n->xin, 0, n->e1a, 0));
-  NET_OK(conv3(E1B, n->e1a, 0, n->c1, 0));
+  NET_OK(conv3(E1A, one_src(n->xin, 0, 32), 0, n->e1a, 0));
+  NET_OK(conv3(E1B, one_src(n->e1a, 0, 32), 0, n->c1, 0));
   NET_OK(pool(n->c1, 0, 32, n->p1));
-  NET_OK(conv3(E2A, n->p1, 0, n->e2a, 0));
-  NET_OK(conv3(E2B, n->e2a, 0, n->c2, 0));
+  NET_OK(conv3(E2A, one_src(n->p1, 0, 32), 1, n->e2a, 0));
+  NET_OK(conv3(E2B, one_src(n->e2a, 0, 64), 1, n->c2, 0));
   NET_OK(pool(n->c2, 0, 64, n->p2));
-  NET_OK(conv3(E3A, n->p2, 0, n->e3a, 0));
-  NET_OK(conv3(E3B, n->e3a, 0, n->c3, 0));
+  NET_OK(conv3(E3A, one_src(n->p2, 0, 64), 2, n->e3a, 0));
+  NET_OK(conv3(E3B, one_src(n->e3a, 0, 128), 2, n->c3, 0));
   NET_OK(pool(n->c3, 0, 128, n->p3));
-  NET_OK(conv3(E4A, n->p3, 0, n->e4a, 0));
-  NET_OK(conv3(E4B, n->e4a, 0, n->e4b, 0));
-  NET_OK(up(n->e4b, 128, n->c3, 128));
-  NET_OK(conv3(D3A, n->c3, 0, n->d3a, 0));
-  NET_OK(conv3(D3B, n->d3a, 0, n->d3b, 0));
-  NET_OK(up(n->d3b, 128, n->c2, 64));
-  NET_OK(conv3(D2A, n->c2, 0, n->d2a, 0));
-  NET_OK(conv3(D2B, n->d2a, 0, n->d2b, 0));
-  NET_OK(up(n->d2b, 64, n->c1, 32));
-  NET_OK(conv3(D1A, n->c1, 0, n->d1a, 0));
-  NET_OK(conv3(D1B, n->d1a, 0, n->d1b, 0));
+  NET_OK(conv3(E4A, one_src(n->p3, 0, 128), 3, n->e4a, 0));
+  NET_OK(conv3(E4B, one_src(n->e4a, 0, 128), 3, n->e4b, 0));
+  NET_OK(conv3(D3A, cat_src(n->c3, 128, n->e4b), 2, n->d3a, 0));
+  NET_OK(conv3(D3B, one_src(n->d3a, 0, 128), 2, n->d3b, 0));
+  NET_OK(conv3(D2A, cat_src(n->c2, 64, n->d3b), 1, n->d2a, 0));
+  NET_OK(conv3(D2B, one_src(n->d2a, 0, 64), 1, n->d2b, 0));
+  NET_OK(conv3(D1A, cat_src(n->c1, 32, n->d2b), 0, n->d1a, 0));
+  NET_OK(conv3(D1B, one_src(n->d1a, 0, 32), 0, n->d1b, 0));
   const Layer& h = n->L[HEAD];
-  NET_OK(conv_launch(n, h, n->d1b.a, false, 32, 0, h.ci_p, h.Wt,
+  NET_OK(conv_launch(n, 1, one_src(n->d1b, 0, 32), h.ci_p, h.Wt,
                      n->master + h.boff, h.co, h.co_p, n->out, true, kOutLd,
                      0, false, B, H, W));
   return STML_OK;
@@ -755,12 +882,12 @@ int net_forward(stml_net* n, int B, int H, int W) {
 
 // Weight and bias gradient of layer li from dPre (ld, off) and its input X.
 int layer_wgrad(stml_net* n, int li, const float* dP, int pld, int poff,
-                const bf16* X, int xld, int xoff, int B, int h, int w,
+                const ConvSrc<bf16>& X, int B, int h, int w,
                 const AdamArgs& a, bool copy_grad) {
   const Layer& l = n->L[li];
   const int K2 = l.k * l.k;
   const long long P = (long long)B * h * w;
-  const long long nchunks = (P + 31) / 32;
+  const long long nchunks = (P + kWChunk - 1) / kWChunk;
   const int nco = (l.co_p + 63) / 64, nci = (l.ci_p + 63) / 64;
   const int gy = K2 * nco * nci;
   const size_t per_split = (size_t)K2 * l.co_p * l.ci_p;
@@ -773,22 +900,24 @@ int layer_wgrad(stml_net* n, int li, const float* dP, int pld, int poff,
   ns = (nchunks + cps - 1) / cps;
   dim3 grid((unsigned)ns, gy);
   if (l.k == 3)
-    wgrad_kernel<3><<<grid, 256, 0, n->stream>>>(dP, pld, poff, l.co_p, X, xld,
-                                                 xoff, l.ci_p, B, h, w,
-                                                 (int)cps, n->wpart);
+    wgrad_kernel<3><<<grid, 256, 0, n->stream>>>(dP, pld, poff, l.co_p, X,
+                                                 l.ci_p, B, h, w, (int)cps,
+                                                 n->wpart);
   else
-    wgrad_kernel<1><<<grid, 256, 0, n->stream>>>(dP, pld, poff, l.co_p, X, xld,
-                                                 xoff, l.ci_p, B, h, w,
-                                                 (int)cps, n->wpart);
+    wgrad_kernel<1><<<grid, 256, 0, n->stream>>>(dP, pld, poff, l.co_p, X,
+                                                 l.ci_p, B, h, w, (int)cps,
+                                                 n->wpart);
   NET_OK(hipGetLastError());
   const long long pps = (P + kBSplit - 1) / kBSplit;
   const int bs = (int)((P + pps - 1) / pps);
   bias_grad_kernel<<<bs, l.co_p, 0, n->stream>>>(dP, pld, poff, l.co_p, P,
                                                  pps, n->bpart);
   NET_OK(hipGetLastError());
+  bias_reduce_kernel<<<l.co, 64, 0, n->stream>>>(n->bpart, bs, l.co_p, n->gb);
+  NET_OK(hipGetLastError());
   const int ne = K2 * l.co * l.ci + l.co;
   adam_layer_kernel<<<(ne + 255) / 256, 256, 0, n->stream>>>(
-      n->wpart, (int)ns, n->bpart, bs, K2, l.co, l.ci, l.co_p, l.ci_p,
+      n->wpart, (int)ns, n->gb, K2, l.co, l.ci, l.co_p, l.ci_p,
       n->master + l.woff, n->m + l.woff, n->v + l.woff,
       copy_grad ? n->grad + l.woff : nullptr, l.Wt, l.Wb, a);
   NET_OK(hipGetLastError());
@@ -796,10 +925,12 @@ int layer_wgrad(stml_net* n, int li, const float* dP, int pld, int poff,
 }
 
 // Backward of a 3x3 conv layer: dPre in place (ReLU mask of its output),
-// weight gradient + Adam, and (if dX) the input gradient.
+// weight gradient + Adam, and (if dX) the input gradient.  The layer's
+// input is in (its first skipC channels) followed, when low is given, by
+// the upsampled channels of low.
 int conv_back(stml_net* n, int li, Buf& outb, int ooff, const Buf& in,
-              int ioff, float* dX, int dld, int B, int H, int W,
-              const AdamArgs& a, bool copy_grad) {
+              float* dX, int dld, int B, int H, int W, const AdamArgs& a,
+              bool copy_grad, const Buf* low = nullptr, int skipC = 0) {
   const Layer& l = n->L[li];
   const int lev = in.level;
   const int h = H >> lev, w = W >> lev;
@@ -810,11 +941,14 @@ int conv_back(stml_net* n, int li, Buf& outb, int ooff, const Buf& in,
   // input gradient first: it must use the weights of the forward pass,
   // which the Adam step below replaces
   if (dX)
-    NET_OK(conv_launch(n, l, outb.g + ooff, true, outb.ld, 0, l.co_p, l.Wb,
-                       nullptr, l.ci_p, l.ci_p, dX, true, dld, 0, false, B, h,
-                       w));
-  return layer_wgrad(n, li, outb.g, outb.ld, ooff, in.a, in.ld, ioff, B, h, w,
-                     a, copy_grad);
+    NET_OK(conv_launch(n, 3,
+                       ConvSrc<float>{outb.g + ooff, outb.ld, 0, nullptr, 0,
+                                      0, l.co_p},
+                       l.co_p, l.Wb, nullptr, l.ci_p, l.ci_p, dX, true, dld, 0,
+                       false, B, h, w));
+  const ConvSrc<bf16> X = low ? cat_src(in, skipC, *low)
+                              : one_src(in, 0, l.ci_p);
+  return layer_wgrad(n, li, outb.g, outb.ld, ooff, X, B, h, w, a, copy_grad);
 }
 
 }  // namespace
@@ -840,7 +974,7 @@ int stml_net_param_count(int dim) {
 
 size_t stml_net_workspace_bytes(int dim, int max_batch, const int* ext) {
   if (dim != 2 || max_batch < 1 || !ext || ext[0] < 8 || ext[1] < 8 ||
-      ext[0] % 8 || ext[1] % 8)
+      ext[0] % 8 || ext[1] % 8 || ext[1] > kMaxConvW)
     return 0;
   stml_net tmp;
   tmp.dim = dim;
@@ -918,7 +1052,7 @@ int stml_net_get_params(const stml_net* n, float* params) {
 
 static int check_shape(const stml_net* n, int B, const int* ext) {
   if (!ext || B < 1 || ext[0] % 8 || ext[1] % 8 || ext[0] < 8 ||
-      ext[1] < 8 ||
+      ext[1] < 8 || ext[1] > kMaxConvW ||
       (long long)B * ext[0] * ext[1] > (long long)n->maxB * n->maxH * n->maxW)
     return STML_EINVAL;
   return STML_OK;
@@ -1017,71 +1151,74 @@ static int net_step(stml_net* n, double lr, float* grad, double* loss) {
   // head: dout -> d1b gradient; weight gradient from dout and d1b
   {
     const Layer& l = n->L[HEAD];
-    NET_OK(conv_launch(n, l, n->dout, true, kOutLd, 0, l.co_p, l.Wb, nullptr,
-                       l.ci_p, l.ci_p, n->d1b.g, true, 32, 0, false, B, H, W));
-    rc = layer_wgrad(n, HEAD, n->dout, kOutLd, 0, n->d1b.a, 32, 0, B, H, W, a,
-                     cg);
+    NET_OK(conv_launch(n, 1,
+                       ConvSrc<float>{n->dout, kOutLd, 0, nullptr, 0, 0,
+                                      l.co_p},
+                       l.co_p, l.Wb, nullptr, l.ci_p, l.ci_p, n->d1b.g, true,
+                       32, 0, false, B, H, W));
+    rc = layer_wgrad(n, HEAD, n->dout, kOutLd, 0, one_src(n->d1b, 0, 32), B,
+                     H, W, a, cg);
     if (rc) return rc;
   }
   // decoder 1
-  if ((rc = conv_back(n, D1B, n->d1b, 0, n->d1a, 0, n->d1a.g, 32, B, H, W, a,
+  if ((rc = conv_back(n, D1B, n->d1b, 0, n->d1a, n->d1a.g, 32, B, H, W, a,
                       cg)))
     return rc;
-  if ((rc = conv_back(n, D1A, n->d1a, 0, n->c1, 0, n->c1.g, 96, B, H, W, a,
-                      cg)))
+  if ((rc = conv_back(n, D1A, n->d1a, 0, n->c1, n->c1.g, 96, B, H, W, a,
+                      cg, &n->d2b, 32)))
     return rc;
   up_bwd_kernel<<<gridsz(P / 4 * 64), 256, 0, n->stream>>>(
       n->c1.g, 96, 32, 64, B, H, W, n->d2b.g);
   // decoder 2
-  if ((rc = conv_back(n, D2B, n->d2b, 0, n->d2a, 0, n->d2a.g, 64, B, H, W, a,
+  if ((rc = conv_back(n, D2B, n->d2b, 0, n->d2a, n->d2a.g, 64, B, H, W, a,
                       cg)))
     return rc;
-  if ((rc = conv_back(n, D2A, n->d2a, 0, n->c2, 0, n->c2.g, 192, B, H, W, a,
-                      cg)))
+  if ((rc = conv_back(n, D2A, n->d2a, 0, n->c2, n->c2.g, 192, B, H, W, a,
+                      cg, &n->d3b, 64)))
     return rc;
   up_bwd_kernel<<<gridsz(P / 16 * 128), 256, 0, n->stream>>>(
       n->c2.g, 192, 64, 128, B, H / 2, W / 2, n->d3b.g);
   // decoder 3
-  if ((rc = conv_back(n, D3B, n->d3b, 0, n->d3a, 0, n->d3a.g, 128, B, H, W,
+  if ((rc = conv_back(n, D3B, n->d3b, 0, n->d3a, n->d3a.g, 128, B, H, W,
                       a, cg)))
     return rc;
-  if ((rc = conv_back(n, D3A, n->d3a, 0, n->c3, 0, n->c3.g, 256, B, H, W, a,
-                      cg)))
+  if ((rc = conv_back(n, D3A, n->d3a, 0, n->c3, n->c3.g, 256, B, H, W, a,
+                      cg, &n->e4b, 128)))
     return rc;
   up_bwd_kernel<<<gridsz(P / 64 * 128), 256, 0, n->stream>>>(
       n->c3.g, 256, 128, 128, B, H / 4, W / 4, n->e4b.g);
   // encoder 4 (bottom)
-  if ((rc = conv_back(n, E4B, n->e4b, 0, n->e4a, 0, n->e4a.g, 128, B, H, W,
+  if ((rc = conv_back(n, E4B, n->e4b, 0, n->e4a, n->e4a.g, 128, B, H, W,
                       a, cg)))
     return rc;
-  if ((rc = conv_back(n, E4A, n->e4a, 0, n->p3, 0, n->p3.g, 128, B, H, W, a,
+  if ((rc = conv_back(n, E4A, n->e4a, 0, n->p3, n->p3.g, 128, B, H, W, a,
                       cg)))
     return rc;
   pool_bwd_add_kernel<<<gridsz(P / 16 * 128), 256, 0, n->stream>>>(
       n->p3.g, 128, B, H / 4, W / 4, n->c3.g, 256, 0);
   // encoder 3
-  if ((rc = conv_back(n, E3B, n->c3, 0, n->e3a, 0, n->e3a.g, 128, B, H, W, a,
+  if ((rc = conv_back(n, E3B, n->c3, 0, n->e3a, n->e3a.g, 128, B, H, W, a,
                       cg)))
     return rc;
-  if ((rc = conv_back(n, E3A, n->e3a, 0, n->p2, 0, n->p2.g, 64, B, H, W, a,
+  if ((rc = conv_back(n, E3A, n->e3a, 0, n->p2, n->p2.g, 64, B, H, W, a,
                       cg)))
     return rc;
   pool_bwd_add_kernel<<<gridsz(P / 4 * 64), 256, 0, n->stream>>>(
       n->p2.g, 64, B, H / 2, W / 2, n->c2.g, 192, 0);
   // encoder 2
-  if ((rc = conv_back(n, E2B, n->c2, 0, n->e2a, 0, n->e2a.g, 64, B, H, W, a,
+  if ((rc = conv_back(n, E2B, n->c2, 0, n->e2a, n->e2a.g, 64, B, H, W, a,
                       cg)))
     return rc;
-  if ((rc = conv_back(n, E2A, n->e2a, 0, n->p1, 0, n->p1.g, 32, B, H, W, a,
+  if ((rc = conv_back(n, E2A, n->e2a, 0, n->p1, n->p1.g, 32, B, H, W, a,
                       cg)))
     return rc;
   pool_bwd_add_kernel<<<gridsz(P * 32), 256, 0, n->stream>>>(
       n->p1.g, 32, B, H, W, n->c1.g, 96, 0);
   // encoder 1
-  if ((rc = conv_back(n, E1B, n->c1, 0, n->e1a, 0, n->e1a.g, 32, B, H, W, a,
+  if ((rc = conv_back(n, E1B, n->c1, 0, n->e1a, n->e1a.g, 32, B, H, W, a,
                       cg)))
     return rc;
-  if ((rc = conv_back(n, E1A, n->e1a, 0, n->xin, 0, nullptr, 0, B, H, W, a,
+  if ((rc = conv_back(n, E1A, n->e1a, 0, n->xin, nullptr, 0, B, H, W, a,
                       cg)))
     return rc;
   NET_OK(hipGetLastError());
