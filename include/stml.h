@@ -299,6 +299,43 @@ int stml_net_train_step(stml_net* net, double lr, double* loss);
  * otherwise); the net runs on its own stream and must outlive its use. */
 int stml_set_predictor_net(stml_ctx* ctx, stml_net* net);
 
+/* --- batching: several 2-D sequences in shared launches ------------------
+ * A batch registers the sequences of several contexts together: each
+ * Gauss-Newton iteration of a stage (level, q) runs as one launch per
+ * kernel over the tiles of every sequence (a persistent grid whose blocks
+ * are dealt to the sequences in fixed shares, so every sequence gets the
+ * blocks, and hence the float64 sums, it gets alone: batched results equal
+ * per-sequence results bit for bit).  Per-sequence scalars and stop flags
+ * stay on the device; one iteration is captured in a HIP graph and
+ * replayed.  The contexts keep their own workspaces, sequences, logs and
+ * displacements (read them with stml_get_displacements / stml_get_log).
+ * All contexts: dim 2, the same numbers of levels, regulariser, gn_max,
+ * cg_max, cg_rtol, ls_max, c1, tol_J, tol_u and parity_mode; eq. (3) off
+ * (eps_stop = 0) unless in parity mode; at most one batch per context at a
+ * time.  The batch only borrows the contexts (they must outlive it).
+ * Workspace: caller-owned device memory of stml_batch_workspace_bytes().
+ * Errors: STML_EINVAL (mismatched contexts, bad level/q), STML_ESTATE (a
+ * context without a sequence), STML_ENOMEM, STML_EDEVICE; warnings as for
+ * the single-sequence calls (the worst over the sequences). */
+typedef struct stml_batch stml_batch;
+
+size_t stml_batch_workspace_bytes(int count);
+int stml_batch_create(stml_ctx* const* ctxs, int count, void* hip_stream,
+                      void* workspace_dev, size_t ws_bytes,
+                      stml_batch** out);
+void stml_batch_destroy(stml_batch* batch);
+const char* stml_batch_last_error(const stml_batch* batch);
+/* on = 0: enqueue every iteration's launches directly instead of replaying
+ * a captured graph (the default; same results). */
+int stml_batch_set_graph(stml_batch* batch, int on);
+/* stml_predict(level, q_next) of every sequence. */
+int stml_batch_predict(stml_batch* batch, int level, int q_next);
+/* stml_register_level(level, q) of every sequence, batched. */
+int stml_batch_register_level(stml_batch* batch, int level, int q);
+/* The schedule of Sec. 3 for every sequence (levels coarse to fine,
+ * predictor-corrector over K_0..K_T), each registration batched. */
+int stml_batch_run(stml_batch* batch);
+
 #ifdef __cplusplus
 }
 #endif

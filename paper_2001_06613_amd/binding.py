@@ -116,6 +116,15 @@ SIGNATURES = {
     "stml_net_gradient": (_I, [_P, _P, _DP]),
     "stml_net_train_step": (_I, [_P, ctypes.c_double, _DP]),
     "stml_set_predictor_net": (_I, [_P, _P]),
+    "stml_batch_workspace_bytes": (ctypes.c_size_t, [_I]),
+    "stml_batch_create": (_I, [ctypes.POINTER(_P), _I, _P, _P,
+                               ctypes.c_size_t, ctypes.POINTER(_P)]),
+    "stml_batch_destroy": (None, [_P]),
+    "stml_batch_last_error": (ctypes.c_char_p, [_P]),
+    "stml_batch_set_graph": (_I, [_P, _I]),
+    "stml_batch_predict": (_I, [_P, _I, _I]),
+    "stml_batch_register_level": (_I, [_P, _I, _I]),
+    "stml_batch_run": (_I, [_P]),
     "stml_timing": (_I, [_P, _I]),
     "stml_timing_get": (_I, [_P, _I, _I, _DP,
                              ctypes.POINTER(ctypes.c_longlong), _DP, _DP]),
@@ -398,6 +407,70 @@ class STML:
                                                _ptr(u), _ptr(delta),
                                                ctypes.byref(cg)))
         return delta, cg.value
+
+
+class Batch:
+    """Several STML contexts registered together (stml_batch_* entry
+    points): one launch per kernel per Gauss-Newton step over the tiles of
+    every sequence, the iteration replayed from a captured HIP graph."""
+
+    def __init__(self, stmls, stream=None, graph=True):
+        import torch
+
+        self.torch = torch
+        self.lib = load()
+        self.stmls = list(stmls)
+        n = len(self.stmls)
+        if n < 1:
+            raise STMLError(STML_EINVAL, "empty batch")
+        nbytes = self.lib.stml_batch_workspace_bytes(n)
+        dev = self.stmls[0].device
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=dev)
+        self.stream = stream if stream is not None else \
+            torch.cuda.current_stream(dev)
+        arr = (_P * n)(*[st.ctx.value for st in self.stmls])
+        b = ctypes.c_void_p()
+        rc = self.lib.stml_batch_create(arr, n,
+                                        ctypes.c_void_p(self.stream.cuda_stream),
+                                        _ptr(self.workspace), nbytes,
+                                        ctypes.byref(b))
+        if rc != STML_OK:
+            raise STMLError(rc, "stml_batch_create failed (contexts must "
+                            "agree in dim 2, levels and solver options)")
+        self.batch = b
+        self.set_graph(graph)
+
+    def _check(self, rc):
+        if rc < 0:
+            raise STMLError(rc, self.lib.stml_batch_last_error(
+                self.batch).decode())
+        return rc
+
+    def close(self):
+        if getattr(self, "batch", None):
+            self.lib.stml_batch_destroy(self.batch)
+            self.batch = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_graph(self, on):
+        return self._check(self.lib.stml_batch_set_graph(self.batch,
+                                                         int(bool(on))))
+
+    def predict(self, level, q_next):
+        return self._check(self.lib.stml_batch_predict(self.batch, level,
+                                                       q_next))
+
+    def register_level(self, level, q):
+        return self._check(self.lib.stml_batch_register_level(self.batch,
+                                                              level, q))
+
+    def run(self):
+        return self._check(self.lib.stml_batch_run(self.batch))
 
 
 class Net:

@@ -77,11 +77,12 @@ __device__ __forceinline__ void store_voxel_sums(double s, const double* v,
 
 // CG start: r = -g, z = M^-1 r; per-voxel S_z, V_z; partials of r.z, r.r.
 template <int D>
-__global__ __launch_bounds__(1024) void cgv_init_kernel(
-    const float* __restrict__ grad, const float* __restrict__ dW, Geom g,
-    Model md, float* __restrict__ r, float* __restrict__ z,
-    double* __restrict__ Sz, double* __restrict__ Vz,
-    double* __restrict__ part, int gn_it, const Scal* __restrict__ sc) {
+__device__ __forceinline__ void cgv_init_body(
+    const float* __restrict__ grad, const float* __restrict__ dW,
+    const Geom& g, const Model& md, float* __restrict__ r,
+    float* __restrict__ z, double* __restrict__ Sz, double* __restrict__ Vz,
+    double* __restrict__ part, int gn_it, const Scal* __restrict__ sc,
+    Blk blk) {
   if (gn_it >= sc->gn_stop) return;
   int j0, j1;
   wave_frames(md.nK, j0, j1);
@@ -90,7 +91,7 @@ __global__ __launch_bounds__(1024) void cgv_init_kernel(
   const long long ntiles = (N + kWave - 1) / kWave;
   double rz = 0.0, rr = 0.0;
   for (int it = 0;; ++it) {
-    long long tile = xcd_tile(ntiles, it);
+    long long tile = xcd_tile(ntiles, it, blk);
     if (tile < 0) break;
     long long x = tile * kWave + lane;
     bool valid = x < N;
@@ -120,31 +121,42 @@ __global__ __launch_bounds__(1024) void cgv_init_kernel(
     store_voxel_sums<D>(s, v, x, valid, N, Sz, Vz);
   }
   double vals[2] = {rz, rr};
-  block_partials<2>(vals, 0u, part);
+  block_partials<2>(vals, 0u, part, blk);
+}
+
+template <int D>
+__global__ __launch_bounds__(1024) void cgv_init_kernel(
+    const float* __restrict__ grad, const float* __restrict__ dW, Geom g,
+    Model md, float* __restrict__ r, float* __restrict__ z,
+    double* __restrict__ Sz, double* __restrict__ Vz,
+    double* __restrict__ part, int gn_it, const Scal* __restrict__ sc) {
+  cgv_init_body<D>(grad, dW, g, md, r, z, Sz, Vz, part, gn_it, sc,
+                   grid_blk());
 }
 
 // CG step, part 2: a = rz / p.q (stop on p.q <= 0); x += a p (x = a p at
 // it = 0), r -= a q, z = M^-1 r; per-voxel S_z, V_z; partials r.z, r.r.
 template <int D>
-__global__ __launch_bounds__(1024) void cgv_update_kernel(
+__device__ __forceinline__ void cgv_update_body(
     int it, const float* __restrict__ p, const float* __restrict__ q,
-    const float* __restrict__ dW, Geom g, Model md, float* __restrict__ x,
-    float* __restrict__ r, float* __restrict__ z, double* __restrict__ Sz,
-    double* __restrict__ Vz, const double* __restrict__ hv_part, int hv_nb,
-    double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
+    const float* __restrict__ dW, const Geom& g, const Model& md,
+    float* __restrict__ x, float* __restrict__ r, float* __restrict__ z,
+    double* __restrict__ Sz, double* __restrict__ Vz,
+    const double* __restrict__ hv_part, int hv_nb, double* __restrict__ part,
+    Scal* __restrict__ sc, int gn_it, Blk blk) {
   if (sc->done || gn_it >= sc->gn_stop) return;
   double t[1];
   reduce_partials<1>(hv_part, hv_nb, 0u, t);
   const double pq = t[0];
   if (!(pq > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk.id == 0 && threadIdx.x == 0) {
       sc->pq = pq;
       sc->done = 2;
     }
     return;
   }
   const double alpha = sc->rzh[it & 1] / pq;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blk.id == 0 && threadIdx.x == 0) {
     sc->pq = pq;
     sc->a = alpha;
     sc->iters = it + 1;
@@ -156,7 +168,7 @@ __global__ __launch_bounds__(1024) void cgv_update_kernel(
   const long long ntiles = (N + kWave - 1) / kWave;
   double rz = 0.0, rr = 0.0;
   for (int tt = 0;; ++tt) {
-    long long tile = xcd_tile(ntiles, tt);
+    long long tile = xcd_tile(ntiles, tt, blk);
     if (tile < 0) break;
     long long xv = tile * kWave + lane;
     bool valid = xv < N;
@@ -191,7 +203,18 @@ __global__ __launch_bounds__(1024) void cgv_update_kernel(
     store_voxel_sums<D>(s, v, xv, valid, N, Sz, Vz);
   }
   double vals[2] = {rz, rr};
-  block_partials<2>(vals, 0u, part);
+  block_partials<2>(vals, 0u, part, blk);
+}
+
+template <int D>
+__global__ __launch_bounds__(1024) void cgv_update_kernel(
+    int it, const float* __restrict__ p, const float* __restrict__ q,
+    const float* __restrict__ dW, Geom g, Model md, float* __restrict__ x,
+    float* __restrict__ r, float* __restrict__ z, double* __restrict__ Sz,
+    double* __restrict__ Vz, const double* __restrict__ hv_part, int hv_nb,
+    double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
+  cgv_update_body<D>(it, p, q, dW, g, md, x, r, z, Sz, Vz, hv_part, hv_nb,
+                     part, sc, gn_it, grid_blk());
 }
 
 // Per-voxel S and V of a stored field v (Hessian product test entry).
@@ -232,15 +255,15 @@ __global__ __launch_bounds__(1024) void cgv_sums_kernel(
 // For it > 0 it first finishes the previous update: beta and the
 // convergence test from the update's partials.
 template <int REG>
-__global__ __launch_bounds__(256) void cgt_hvp2_kernel(
+__device__ __forceinline__ void cgt_hvp2_body(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
-    float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
-    Model md, float* __restrict__ q, const double* __restrict__ Sz,
+    float* __restrict__ p_new, const float* __restrict__ dW, const Geom& g,
+    const Model& md, float* __restrict__ q, const double* __restrict__ Sz,
     const double* __restrict__ Vz, const double* __restrict__ Sp_old,
     const double* __restrict__ Vp_old, double* __restrict__ Sp_new,
     double* __restrict__ Vp_new, int nreal, int nfg, int fpg,
     const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
-    double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
+    double* __restrict__ part, Scal* __restrict__ sc, int gn_it, Blk blk) {
   constexpr int D = 2;
   __shared__ double P[D][kHY][kHX];
   __shared__ double L[REG ? D : 1][REG ? kLY : 1][REG ? kLX : 1];
@@ -252,11 +275,11 @@ __global__ __launch_bounds__(256) void cgt_hvp2_kernel(
     const double rz_old = sc->rzh[(it - 1) & 1];
     bool conv = (!fixed && sqrt(t[1]) <= rtol * sc->r0) || t[0] == 0.0;
     if (conv) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 1;
+      if (blk.id == 0 && threadIdx.x == 0) sc->done = 1;
       return;
     }
     beta = t[0] / rz_old;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk.id == 0 && threadIdx.x == 0) {
       sc->rzh[it & 1] = t[0];
       sc->rr = t[1];
       sc->beta = beta;
@@ -264,8 +287,8 @@ __global__ __launch_bounds__(256) void cgt_hvp2_kernel(
   }
   const float bf = (float)beta;
   // block -> (tile, frame group), XCD-chunked
-  const int per_xcd = gridDim.x / kXCD;
-  const int bb = (blockIdx.x % kXCD) * per_xcd + blockIdx.x / kXCD;
+  const int per_xcd = blk.n / kXCD;
+  const int bb = (blk.id % kXCD) * per_xcd + blk.id / kXCD;
   double acc = 0.0;
   if (bb < nreal) {
     const int m0 = g.m[0], m1 = g.m[1];
@@ -368,7 +391,22 @@ __global__ __launch_bounds__(256) void cgt_hvp2_kernel(
     }
   }
   double vals[1] = {acc};
-  block_partials<1>(vals, 0u, part);
+  block_partials<1>(vals, 0u, part, blk);
+}
+
+template <int REG>
+__global__ __launch_bounds__(256) void cgt_hvp2_kernel(
+    int it, const float* __restrict__ zv, const float* __restrict__ p_old,
+    float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
+    Model md, float* __restrict__ q, const double* __restrict__ Sz,
+    const double* __restrict__ Vz, const double* __restrict__ Sp_old,
+    const double* __restrict__ Vp_old, double* __restrict__ Sp_new,
+    double* __restrict__ Vp_new, int nreal, int nfg, int fpg,
+    const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
+    double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
+  cgt_hvp2_body<REG>(it, zv, p_old, p_new, dW, g, md, q, Sz, Vz, Sp_old,
+                     Vp_old, Sp_new, Vp_new, nreal, nfg, fpg, up_part, up_nb,
+                     fixed, rtol, part, sc, gn_it, grid_blk());
 }
 
 // ------------------------------------------------------------ launchers
@@ -379,7 +417,10 @@ static int cgv_blocks(const Geom& g) {
   return (int)((nb + kXCD - 1) / kXCD * kXCD);
 }
 
-static int cgv_threads(int nK) {
+// 2-D: a fixed block size (waves without frames idle), so that a problem
+// gets the same blocks, and the same rounding, alone and batched.
+static int cgv_threads(int dim, int nK) {
+  if (dim == 2) return kMaxChunks * kWave;
   int G = nK < kMaxChunks ? nK : kMaxChunks;
   return (G < 1 ? 1 : G) * kWave;
 }
@@ -403,7 +444,7 @@ hipError_t launch_cgv_init(int dim, const float* grad, const float* dW,
                            const Geom& g, const Model& md, float* r, float* z,
                            CgSums sums, RedBuf rb, Scal* sc, hipStream_t s,
                            int gn_it, GNLog* log) {
-  int nb = cgv_blocks(g), nt = cgv_threads(md.nK);
+  int nb = cgv_blocks(g), nt = cgv_threads(dim, md.nK);
   double* part = rb.region(kRegInit);
   if (dim == 2)
     cgv_init_kernel<2><<<nb, nt, 0, s>>>(grad, dW, g, md, r, z, sums.Sz,
@@ -441,7 +482,7 @@ hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
                              const float* dW, const Geom& g, const Model& md,
                              float* x, float* r, float* z, CgSums sums,
                              RedBuf rb, Scal* sc, hipStream_t s, int gn_it) {
-  int nb = cgv_blocks(g), nt = cgv_threads(md.nK);
+  int nb = cgv_blocks(g), nt = cgv_threads(dim, md.nK);
   int hv_nb = cg_tiles_2d(g, md.nK).grid;
   if (dim == 2)
     cgv_update_kernel<2><<<nb, nt, 0, s>>>(
@@ -454,11 +495,106 @@ hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
   return hipGetLastError();
 }
 
+// ------------------------------------------------- batched 2-D iteration
+
+__device__ __forceinline__ int cg_job_index(const int* __restrict__ f, int n,
+                                            int b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (f[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+__device__ __forceinline__ const Job& cg_job_of(const JobSet& js, int c,
+                                                Blk& blk) {
+  const int* f = js.first + (size_t)c * (js.n + 1);
+  const int b = blockIdx.x;
+  const int j = cg_job_index(f, js.n, b);
+  blk = Blk{b - f[j], f[j + 1] - f[j]};
+  return js.jobs[j];
+}
+
+__global__ __launch_bounds__(1024) void cg_init_batch_kernel(JobSet js) {
+  Blk blk;
+  const Job& J = cg_job_of(js, kClsVox, blk);
+  const Geom g = J.g;
+  const Model md = J.md;
+  Scal* sc = J.sc;
+  cgv_init_body<2>(J.grad, J.dW, g, md, J.r, J.z, J.sums.Sz, J.sums.Vz,
+                   J.rb.region(kRegInit), sc->gn_cur, sc, blk);
+}
+
+template <int REG>
+__global__ __launch_bounds__(256) void cg_hvp_batch_kernel(JobSet js, int it,
+                                                           int fixed,
+                                                           double rtol) {
+  Blk blk;
+  const Job& J = cg_job_of(js, kClsHv, blk);
+  const Geom g = J.g;
+  const Model md = J.md;
+  Scal* sc = J.sc;
+  float* pn = (it & 1) ? J.P1 : J.P0;
+  const float* po = (it & 1) ? J.P0 : J.P1;
+  cgt_hvp2_body<REG>(it, J.z, po, pn, J.dW, g, md, J.q, J.sums.Sz, J.sums.Vz,
+                     J.sums.Sp[(it + 1) & 1], J.sums.Vp[(it + 1) & 1],
+                     J.sums.Sp[it & 1], J.sums.Vp[it & 1], J.ct.nreal,
+                     J.ct.nfg, J.ct.fpg, J.rb.region(kRegUpdate), J.nb_vox,
+                     fixed, rtol, J.rb.region(kRegHv), sc, sc->gn_cur, blk);
+}
+
+__global__ __launch_bounds__(1024) void cg_update_batch_kernel(JobSet js,
+                                                               int it) {
+  Blk blk;
+  const Job& J = cg_job_of(js, kClsVox, blk);
+  const Geom g = J.g;
+  const Model md = J.md;
+  Scal* sc = J.sc;
+  const float* pn = (it & 1) ? J.P1 : J.P0;
+  cgv_update_body<2>(it, pn, J.q, J.dW, g, md, J.x, J.r, J.z, J.sums.Sz,
+                     J.sums.Vz, J.rb.region(kRegHv), J.ct.grid,
+                     J.rb.region(kRegUpdate), sc, sc->gn_cur, blk);
+}
+
+void job_shape(Job* job) {
+  job->ct = cg_tiles_2d(job->g, job->md.nK);
+  job->nb_tile = tile_blocks(job->g);
+  job->nb_vox = job->ct.vox_grid;
+  job->count = (long long)job->md.nK * 2 * job->g.N;
+  job->nb_elem = elem_grid(job->count);
+}
+
+hipError_t batch_finalize_start(const JobSet& js, hipStream_t s);
+
+hipError_t batch_cg_init(const JobSet& js, int nvox, hipStream_t s) {
+  cg_init_batch_kernel<<<nvox, cgv_threads(2, 0), 0, s>>>(js);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return batch_finalize_start(js, s);
+}
+
+hipError_t batch_cg_hvp(const JobSet& js, int nhv, int reg, int it,
+                        int fixed, double rtol, hipStream_t s) {
+  if (reg == 0)
+    cg_hvp_batch_kernel<0><<<nhv, kTX * kTY, 0, s>>>(js, it, fixed, rtol);
+  else
+    cg_hvp_batch_kernel<1><<<nhv, kTX * kTY, 0, s>>>(js, it, fixed, rtol);
+  return hipGetLastError();
+}
+
+hipError_t batch_cg_update(const JobSet& js, int nvox, int it,
+                           hipStream_t s) {
+  cg_update_batch_kernel<<<nvox, cgv_threads(2, 0), 0, s>>>(js, it);
+  return hipGetLastError();
+}
+
 hipError_t launch_hessvec_2d(const float* v, const float* dW, const Geom& g,
                              const Model& md, float* hv, float* vcopy,
                              CgSums sums, RedBuf rb, Scal* sc,
                              hipStream_t s) {
-  int nb = cgv_blocks(g), nt = cgv_threads(md.nK);
+  int nb = cgv_blocks(g), nt = cgv_threads(2, md.nK);
   cgv_sums_kernel<2><<<nb, nt, 0, s>>>(v, dW, g, md, sums.Sz, sums.Vz);
   hipError_t e = launch_gn_reset(sc, nullptr, 0, s);
   if (e != hipSuccess) return e;

@@ -70,9 +70,13 @@ static int waves_for(int nK, int maxg) {
   int G = nK < maxg ? nK : maxg;
   return G < 1 ? 1 : G;
 }
-int tile_threads(int nK) { return waves_for(nK, 4) * kWave; }
+// 2-D launches use a fixed block size (waves without frames idle), so that
+// a problem gets the same blocks, and the same rounding, alone and batched.
+int tile_threads(int dim, int nK) {
+  return (dim == 2 ? 4 : waves_for(nK, 4)) * kWave;
+}
 int eval_threads(int dim, int nK) {
-  return waves_for(nK, dim == 2 ? 8 : 4) * kWave;
+  return (dim == 2 ? 8 : waves_for(nK, 4)) * kWave;
 }
 int hv_threads(int dim, int nK) {
   return waves_for(nK, dim == 2 ? 16 : 4) * kWave;
@@ -229,11 +233,12 @@ __device__ __forceinline__ Chunk frame_chunk(int nK) {
 // hit the caches), forms r = W - mean W and writes the gradient.  Block
 // partials of D, S, P go to `part` (3 x gridDim slots).
 template <int D, int REG>
-__global__ __launch_bounds__(D == 2 ? 512 : 256) void eval_kernel(
+__device__ __forceinline__ void eval_body(
     const float* __restrict__ T, const float* __restrict__ u,
-    const int* __restrict__ K, Geom g, Model md, float* __restrict__ grad,
-    float* __restrict__ dWo, double* __restrict__ part, int gn_it,
-    const Scal* __restrict__ sc) {
+    const int* __restrict__ K, const Geom& g, const Model& md,
+    float* __restrict__ grad, float* __restrict__ dWo,
+    double* __restrict__ part, int gn_it, const Scal* __restrict__ sc,
+    Blk blk) {
   if (sc && gn_it >= sc->gn_stop) return;
   __shared__ double xs[kMaxChunks][kWave][1 + D];
   const int lane = threadIdx.x & (kWave - 1);
@@ -244,7 +249,7 @@ __global__ __launch_bounds__(D == 2 ? 512 : 256) void eval_kernel(
   const long long ntiles = (N + kWave - 1) / kWave;
   double accD = 0.0, accS = 0.0, accP = 0.0;
   for (int it = 0;; ++it) {
-    long long tile = xcd_tile(ntiles, it);
+    long long tile = xcd_tile(ntiles, it, blk);
     if (tile < 0) break;
     long long x = tile * kWave + lane;
     bool valid = x < N;
@@ -313,7 +318,16 @@ __global__ __launch_bounds__(D == 2 ? 512 : 256) void eval_kernel(
     }
   }
   double vals[3] = {accD, accS, accP};
-  block_partials<3>(vals, 0u, part);
+  block_partials<3>(vals, 0u, part, blk);
+}
+
+template <int D, int REG>
+__global__ __launch_bounds__(D == 2 ? 512 : 256) void eval_kernel(
+    const float* __restrict__ T, const float* __restrict__ u,
+    const int* __restrict__ K, Geom g, Model md, float* __restrict__ grad,
+    float* __restrict__ dWo, double* __restrict__ part, int gn_it,
+    const Scal* __restrict__ sc) {
+  eval_body<D, REG>(T, u, K, g, md, grad, dWo, part, gn_it, sc, grid_blk());
 }
 
 // Plane-offset views of the accessors used by hv_tiles.
@@ -470,9 +484,9 @@ __global__ __launch_bounds__(256) void pcg_init_kernel(
 }
 
 // One block: the objective of the evaluation and the CG start scalars.
-__global__ __launch_bounds__(256) void finalize_start_kernel(
+__device__ __forceinline__ void finalize_start_body(
     const double* __restrict__ ev_part, int ev_nb,
-    const double* __restrict__ in_part, int in_nb, Model md,
+    const double* __restrict__ in_part, int in_nb, const Model& md,
     Scal* __restrict__ sc, int gn_it, GNLog* __restrict__ log) {
   if (gn_it >= sc->gn_stop) return;
   double e[3], i2[2];
@@ -493,6 +507,13 @@ __global__ __launch_bounds__(256) void finalize_start_kernel(
     sc->done = i2[0] == 0.0 ? 1 : 0;
     if (log) log[gn_it].J = Dv + Sv + Pv;
   }
+}
+
+__global__ __launch_bounds__(256) void finalize_start_kernel(
+    const double* __restrict__ ev_part, int ev_nb,
+    const double* __restrict__ in_part, int in_nb, Model md,
+    Scal* __restrict__ sc, int gn_it, GNLog* __restrict__ log) {
+  finalize_start_body(ev_part, ev_nb, in_part, in_nb, md, sc, gn_it, log);
 }
 
 template <int D, int REG>
@@ -607,12 +628,12 @@ struct Steps {
 // S and P are quadratic in t and are expanded exactly.  The per-step sums
 // live in LDS (one slot row per thread), which keeps register use low.
 template <int D, int REG>
-__global__ __launch_bounds__(256) void trial_kernel(
+__device__ __forceinline__ void trial_body(
     const float* __restrict__ T, const float* __restrict__ u,
     const float* __restrict__ dl, const float* __restrict__ gr,
-    const int* __restrict__ K, Geom g, Model md, Steps st,
-    double* __restrict__ part, int gn_it, LSPass ls,
-    const Scal* __restrict__ sc, const GNLog* __restrict__ log) {
+    const int* __restrict__ K, const Geom& g, const Model& md,
+    const Steps& st, double* __restrict__ part, int gn_it, LSPass ls,
+    const Scal* __restrict__ sc, const GNLog* __restrict__ log, Blk blk) {
   if (gn_it >= sc->gn_stop) return;
   if (ls.p > 0 && log[gn_it].next_pass != ls.p) return;
   constexpr int NT = kTrialSteps;
@@ -631,7 +652,7 @@ __global__ __launch_bounds__(256) void trial_kernel(
   double rA = 0, rB = 0, rC = 0, pA = 0, pB = 0, pC = 0, slope = 0, mx = 0,
          sq = 0;
   for (int it = 0;; ++it) {
-    long long tile = xcd_tile(ntiles, it);
+    long long tile = xcd_tile(ntiles, it, blk);
     if (tile < 0) break;
     long long x = tile * kWave + lane;
     bool valid = x < N;
@@ -714,14 +735,26 @@ __global__ __launch_bounds__(256) void trial_kernel(
   vals[NT + 6] = slope;
   vals[NT + 7] = mx;
   vals[NT + 8] = sq;
-  block_partials<NT + 9>(vals, 1u << (NT + 7), part);
+  block_partials<NT + 9>(vals, 1u << (NT + 7), part, blk);
+}
+
+template <int D, int REG>
+__global__ __launch_bounds__(256) void trial_kernel(
+    const float* __restrict__ T, const float* __restrict__ u,
+    const float* __restrict__ dl, const float* __restrict__ gr,
+    const int* __restrict__ K, Geom g, Model md, Steps st,
+    double* __restrict__ part, int gn_it, LSPass ls,
+    const Scal* __restrict__ sc, const GNLog* __restrict__ log) {
+  trial_body<D, REG>(T, u, dl, gr, K, g, md, st, part, gn_it, ls, sc, log,
+                     grid_blk());
 }
 
 // One block: objective at the trial steps, g.delta, max |delta| and
 // sum delta^2.
-__global__ __launch_bounds__(256) void finalize_trial_kernel(
-    const double* __restrict__ part, int nb, Model md, Steps st,
-    Scal* __restrict__ sc, int gn_it, LSPass ls, GNLog* __restrict__ log) {
+__device__ __forceinline__ void finalize_trial_body(
+    const double* __restrict__ part, int nb, const Model& md,
+    const Steps& st, Scal* __restrict__ sc, int gn_it, LSPass ls,
+    GNLog* __restrict__ log) {
   if (gn_it >= sc->gn_stop) return;
   if (ls.p > 0 && log[gn_it].next_pass != ls.p) return;
   constexpr int NT = kTrialSteps;
@@ -749,15 +782,21 @@ __global__ __launch_bounds__(256) void finalize_trial_kernel(
   }
 }
 
+__global__ __launch_bounds__(256) void finalize_trial_kernel(
+    const double* __restrict__ part, int nb, Model md, Steps st,
+    Scal* __restrict__ sc, int gn_it, LSPass ls, GNLog* __restrict__ log) {
+  finalize_trial_body(part, nb, md, st, sc, gn_it, ls, log);
+}
+
 // Armijo decision of sweep ls and, if a step passes, u[K[j]] += t delta_j.
 // Every block takes the same decision from the same values.  Flags a later
 // block of this kernel might read (next_pass, gn_stop) are only written in
 // ways that leave such a block's work unchanged.
-__global__ __launch_bounds__(256) void ls_accept_kernel(
+__device__ __forceinline__ void ls_accept_body(
     float* __restrict__ u, const float* __restrict__ dl,
-    const int* __restrict__ K, int nK, int dim, long long N, Steps st,
+    const int* __restrict__ K, int nK, int dim, long long N, const Steps& st,
     LSPass ls, int ls_max, double c1, int fixed, double tol_J, double tol_u,
-    int gn_it, Scal* __restrict__ sc, GNLog* __restrict__ log) {
+    int gn_it, Scal* __restrict__ sc, GNLog* __restrict__ log, Blk blk) {
   if (gn_it >= sc->gn_stop) return;
   GNLog* L = log + gn_it;
   if (ls.p > 0 && L->next_pass != ls.p) return;
@@ -773,7 +812,7 @@ __global__ __launch_bounds__(256) void ls_accept_kernel(
     }
   }
   if (tacc < 0.0) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
+    if (blk.id == 0 && threadIdx.x == 0) {
       if (ls.last) {
         L->status = 1;
         L->t = 0.0;
@@ -786,8 +825,8 @@ __global__ __launch_bounds__(256) void ls_accept_kernel(
     return;
   }
   size_t count = (size_t)nK * dim * N;
-  size_t stride = (size_t)gridDim.x * blockDim.x;
-  for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < count;
+  size_t stride = (size_t)blk.n * blockDim.x;
+  for (size_t e = (size_t)blk.id * blockDim.x + threadIdx.x; e < count;
        e += stride) {
     size_t row = e / (size_t)N;
     size_t x = e - row * (size_t)N;
@@ -796,7 +835,7 @@ __global__ __launch_bounds__(256) void ls_accept_kernel(
     size_t o = ((size_t)K[j] * dim + a) * N + x;
     u[o] = (float)((double)u[o] + tacc * (double)dl[e]);
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
+  if (blk.id == 0 && threadIdx.x == 0) {
     bool breakdown = sc->done == 2;
     L->t = tacc;
     L->Jacc = Jacc;
@@ -808,6 +847,15 @@ __global__ __launch_bounds__(256) void ls_accept_kernel(
                  tacc * rms <= tol_u);
     if (stop) sc->gn_stop = gn_it + 1;
   }
+}
+
+__global__ __launch_bounds__(256) void ls_accept_kernel(
+    float* __restrict__ u, const float* __restrict__ dl,
+    const int* __restrict__ K, int nK, int dim, long long N, Steps st,
+    LSPass ls, int ls_max, double c1, int fixed, double tol_J, double tol_u,
+    int gn_it, Scal* __restrict__ sc, GNLog* __restrict__ log) {
+  ls_accept_body(u, dl, K, nK, dim, N, st, ls, ls_max, c1, fixed, tol_J,
+                 tol_u, gn_it, sc, log, grid_blk());
 }
 
 // Start of a registration: every Gauss-Newton iteration enabled, logs
@@ -824,6 +872,7 @@ __global__ void gn_reset_kernel(Scal* __restrict__ sc,
   if (i == 0) {
     sc->gn_stop = 0x7fffffff;
     sc->done = 0;
+    sc->gn_cur = 0;
   }
 }
 
@@ -903,6 +952,157 @@ __global__ __launch_bounds__(64) void ls_predict_kernel(
       Y[o] = zv;
     }
   }
+}
+
+// ------------------------------------------------- batched 2-D iteration
+
+// Problem of block b: the j with first[j] <= b < first[j + 1].
+__device__ __forceinline__ int job_index(const int* __restrict__ f, int n,
+                                         int b) {
+  int lo = 0, hi = n;
+  while (hi - lo > 1) {
+    int mid = (lo + hi) >> 1;
+    if (f[mid] <= b) lo = mid;
+    else hi = mid;
+  }
+  return __builtin_amdgcn_readfirstlane(lo);
+}
+
+// This block's problem in kernel class c and its block context there.
+__device__ __forceinline__ const Job& job_of(const JobSet& js, int c,
+                                             Blk& blk) {
+  const int* f = js.first + (size_t)c * (js.n + 1);
+  const int b = blockIdx.x;
+  const int j = job_index(f, js.n, b);
+  blk = Blk{b - f[j], f[j + 1] - f[j]};
+  return js.jobs[j];
+}
+
+template <int REG>
+__global__ __launch_bounds__(512) void eval_batch_kernel(JobSet js) {
+  Blk blk;
+  const Job& J = job_of(js, kClsTile, blk);
+  const Geom g = J.g;
+  const Model md = J.md;
+  Scal* sc = J.sc;
+  eval_body<2, REG>(J.T, J.u, J.K, g, md, J.grad, J.dW,
+                    J.rb.region(kRegEval), sc->gn_cur, sc, blk);
+}
+
+__global__ __launch_bounds__(256) void start_batch_kernel(JobSet js) {
+  const Job& J = js.jobs[blockIdx.x];
+  const Model md = J.md;
+  Scal* sc = J.sc;
+  finalize_start_body(J.rb.region(kRegEval), J.nb_tile,
+                      J.rb.region(kRegInit), J.nb_vox, md, sc, sc->gn_cur,
+                      J.log);
+}
+
+template <int REG>
+__global__ __launch_bounds__(256) void trial_batch_kernel(JobSet js, Steps st,
+                                                          LSPass ls) {
+  Blk blk;
+  const Job& J = job_of(js, kClsTile, blk);
+  const Geom g = J.g;
+  const Model md = J.md;
+  Scal* sc = J.sc;
+  trial_body<2, REG>(J.T, J.u, J.x, J.grad, J.K, g, md, st,
+                     J.rb.region(kRegTrial), sc->gn_cur, ls, sc, J.log, blk);
+}
+
+__global__ __launch_bounds__(256) void trial_final_batch_kernel(JobSet js,
+                                                                Steps st,
+                                                                LSPass ls) {
+  const Job& J = js.jobs[blockIdx.x];
+  const Model md = J.md;
+  Scal* sc = J.sc;
+  finalize_trial_body(J.rb.region(kRegTrial), J.nb_tile, md, st, sc,
+                      sc->gn_cur, ls, J.log);
+}
+
+__global__ __launch_bounds__(256) void accept_batch_kernel(
+    JobSet js, Steps st, LSPass ls, int ls_max, double c1, int fixed,
+    double tol_J, double tol_u) {
+  Blk blk;
+  const Job& J = job_of(js, kClsElem, blk);
+  Scal* sc = J.sc;
+  ls_accept_body(J.u, J.x, J.K, J.md.nK, 2, J.g.N, st, ls, ls_max, c1, fixed,
+                 tol_J, tol_u, sc->gn_cur, sc, J.log, blk);
+}
+
+// Start of a batched registration: per problem, every iteration enabled,
+// logs cleared, iteration counter 0.
+__global__ __launch_bounds__(256) void reset_batch_kernel(JobSet js,
+                                                          int gn_max) {
+  const Job& J = js.jobs[blockIdx.x];
+  for (int i = threadIdx.x; i < gn_max; i += blockDim.x) {
+    GNLog L = {};
+    L.status = -1;
+    L.next_pass = 0;
+    J.log[i] = L;
+  }
+  if (threadIdx.x == 0) {
+    J.sc->gn_stop = 0x7fffffff;
+    J.sc->done = 0;
+    J.sc->gn_cur = 0;
+  }
+}
+
+// End of a batched iteration: stop flag per problem, counter advanced.
+__global__ void advance_batch_kernel(JobSet js, int* __restrict__ stop) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  if (j >= js.n) return;
+  Scal* sc = js.jobs[j].sc;
+  const int it = sc->gn_cur;
+  stop[j] = sc->gn_stop <= it + 1 ? 1 : 0;
+  sc->gn_cur = it + 1;
+}
+
+int elem_grid(long long count) { return elem_blocks((size_t)count); }
+
+hipError_t batch_gn_reset(const JobSet& js, int gn_max, hipStream_t s) {
+  reset_batch_kernel<<<js.n, 256, 0, s>>>(js, gn_max);
+  return hipGetLastError();
+}
+
+hipError_t batch_eval(const JobSet& js, int nblocks, int reg, hipStream_t s) {
+  if (reg == 0)
+    eval_batch_kernel<0><<<nblocks, eval_threads(2, 0), 0, s>>>(js);
+  else
+    eval_batch_kernel<1><<<nblocks, eval_threads(2, 0), 0, s>>>(js);
+  return hipGetLastError();
+}
+
+hipError_t batch_finalize_start(const JobSet& js, hipStream_t s) {
+  start_batch_kernel<<<js.n, 256, 0, s>>>(js);
+  return hipGetLastError();
+}
+
+hipError_t batch_trial(const JobSet& js, int ntile, int reg, const double* t,
+                       LSPass ls, hipStream_t s) {
+  Steps st;
+  for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
+  if (reg == 0)
+    trial_batch_kernel<0><<<ntile, tile_threads(2, 0), 0, s>>>(js, st, ls);
+  else
+    trial_batch_kernel<1><<<ntile, tile_threads(2, 0), 0, s>>>(js, st, ls);
+  trial_final_batch_kernel<<<js.n, 256, 0, s>>>(js, st, ls);
+  return hipGetLastError();
+}
+
+hipError_t batch_accept(const JobSet& js, int nelem, const double* t,
+                        LSPass ls, int ls_max, double c1, int fixed,
+                        double tol_J, double tol_u, hipStream_t s) {
+  Steps st;
+  for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
+  accept_batch_kernel<<<nelem, 256, 0, s>>>(js, st, ls, ls_max, c1, fixed,
+                                            tol_J, tol_u);
+  return hipGetLastError();
+}
+
+hipError_t batch_advance(const JobSet& js, int* stop_out, hipStream_t s) {
+  advance_batch_kernel<<<(js.n + 63) / 64, 64, 0, s>>>(js, stop_out);
+  return hipGetLastError();
 }
 
 // ------------------------------------------------------------- launchers
@@ -1043,7 +1243,7 @@ hipError_t launch_trial(int dim, const float* T, const float* u,
   Steps st;
   for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
   int nb = tile_blocks(g);
-  int nt = tile_threads(md.nK);
+  int nt = tile_threads(dim, md.nK);
   double* part = rb.region(kRegTrial);
   STML_TILE_DISPATCH(dim, md.reg, trial_kernel, nb, nt, s, T, u, delta, grad,
                      K, g, md, st, part, gn_it, ls, sc, log);

@@ -17,7 +17,9 @@ enum { kRegEval, kRegInit, kRegHv, kRegUpdate, kRegTrial, kRegTest, kRegCount };
 constexpr size_t kRedSlots = kRegionSlots * kRegCount;
 struct RedBuf {
   double* part;         // kRedSlots doubles
-  double* region(int r) const { return part + (size_t)r * kRegionSlots; }
+  __host__ __device__ double* region(int r) const {
+    return part + (size_t)r * kRegionSlots;
+  }
 };
 
 // Temporal-predictor tables of one subset K_q (device pointers).
@@ -38,7 +40,7 @@ Model make_model(int dim, double h, int nK, double alpha, double lambda,
                  int reg);
 
 int tile_blocks(const Geom& g);
-int tile_threads(int nK);
+int tile_threads(int dim, int nK);
 int eval_threads(int dim, int nK);
 int hv_threads(int dim, int nK);
 
@@ -139,6 +141,54 @@ hipError_t launch_linear_predict(const float* Y, float* Z, float* Yout,
 hipError_t launch_ls_predict(float* Y, float* Z, ThomasTab tab, int n,
                              int dim, long long N, double beta,
                              hipStream_t s);
+
+// ------------------------------------------------------------- batching
+//
+// One problem of a batched launch: the subset K of one sequence at one
+// level, with that sequence's own solver vectors, reduction slots, scalars
+// and log.  Every kernel of a 2-D Gauss-Newton iteration has a batched
+// form that serves all problems in one launch: the blocks of a launch are
+// dealt to the problems in order (first[c][j] .. first[c][j+1] for kernel
+// class c), each problem getting exactly the blocks (and hence the sums) it
+// gets alone.  The iteration index is read from the problem's scalars
+// (gn_cur), so one captured iteration can be replayed.
+struct Job {
+  const float* T;        // level frames [n][N]
+  float* u;              // displacements [n][2][N]
+  const int* K;          // frames of the subset
+  Geom g;
+  Model md;
+  float *grad, *dW, *x, *r, *z, *q, *P0, *P1;
+  CgSums sums;
+  RedBuf rb;
+  Scal* sc;
+  GNLog* log;
+  long long count;       // |K| 2 N
+  int nb_tile, nb_vox, nb_elem;
+  CgTiles ct;
+};
+enum { kClsTile, kClsVox, kClsHv, kClsOne, kClsElem, kClsCount };
+struct JobSet {
+  const Job* jobs;
+  const int* first;      // [kClsCount][n + 1] block offsets
+  int n;
+};
+// Blocks of each kernel class for a problem (shares start at multiples of
+// kXCD); fills job.nb_* and job.ct.
+void job_shape(Job* job);
+int elem_grid(long long count);
+hipError_t batch_gn_reset(const JobSet& js, int gn_max, hipStream_t s);
+hipError_t batch_eval(const JobSet& js, int nblocks, int reg, hipStream_t s);
+hipError_t batch_cg_init(const JobSet& js, int nvox, hipStream_t s);
+hipError_t batch_cg_hvp(const JobSet& js, int nhv, int reg, int it,
+                        int fixed, double rtol, hipStream_t s);
+hipError_t batch_cg_update(const JobSet& js, int nvox, int it, hipStream_t s);
+hipError_t batch_trial(const JobSet& js, int ntile, int reg, const double* t,
+                       LSPass ls, hipStream_t s);
+hipError_t batch_accept(const JobSet& js, int nelem, const double* t,
+                        LSPass ls, int ls_max, double c1, int fixed,
+                        double tol_J, double tol_u, hipStream_t s);
+hipError_t batch_advance(const JobSet& js, int* stop_out, hipStream_t s);
 
 // Capacity of a learned-predictor net (cnn.hip): the batch it was created
 // for and the pixels a batch may hold in total (frames x pixels per frame).

@@ -15,10 +15,10 @@
 namespace stml {
 
 // vals[v]: this thread's contribution to value v; bit v of maxmask selects
-// max instead of sum.  Writes part[v * gridDim.x + blockIdx.x].
+// max instead of sum.  Writes part[v * blk.n + blk.id].
 template <int NV>
 __device__ void block_partials(const double (&vals)[NV], unsigned maxmask,
-                               double* __restrict__ part) {
+                               double* __restrict__ part, Blk blk) {
   __shared__ double red[kMaxChunks][NV];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = threadIdx.x / kWave;
@@ -34,45 +34,45 @@ __device__ void block_partials(const double (&vals)[NV], unsigned maxmask,
     bool mx = (maxmask >> v) & 1u;
     double s = red[0][v];
     for (int i = 1; i < nw; ++i) s = mx ? fmax(s, red[i][v]) : s + red[i][v];
-    part[(size_t)v * gridDim.x + blockIdx.x] = s;
+    part[(size_t)v * blk.n + blk.id] = s;
   }
+}
+template <int NV>
+__device__ void block_partials(const double (&vals)[NV], unsigned maxmask,
+                               double* __restrict__ part) {
+  block_partials<NV>(vals, maxmask, part, grid_blk());
 }
 
 // Totals of NV values from nb partial slots each; every thread of the block
-// receives them.
+// receives them.  The first wave sums slots lane, lane + 64, ... and then
+// across lanes, so the order depends on nb only, not on the block size.
 template <int NV>
 __device__ void reduce_partials(const double* __restrict__ part, int nb,
                                 unsigned maxmask, double (&out)[NV]) {
-  __shared__ double red[kMaxChunks][NV];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = threadIdx.x / kWave;
-  const int nw = blockDim.x / kWave;
-  double acc[NV];
-#pragma unroll
-  for (int v = 0; v < NV; ++v)
-    acc[v] = ((maxmask >> v) & 1u) ? -1.0e300 : 0.0;
-  for (int i = threadIdx.x; i < nb; i += blockDim.x) {
-    double x[NV];
-#pragma unroll
-    for (int v = 0; v < NV; ++v) x[v] = part[(size_t)v * nb + i];
+  __shared__ double red[NV];
+  if (threadIdx.x < kWave) {
+    double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
-      acc[v] = ((maxmask >> v) & 1u) ? fmax(acc[v], x[v]) : acc[v] + x[v];
-  }
+      acc[v] = ((maxmask >> v) & 1u) ? -1.0e300 : 0.0;
+    for (int i = threadIdx.x; i < nb; i += kWave) {
+      double x[NV];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    bool mx = (maxmask >> v) & 1u;
-    double s = mx ? wave_max(acc[v]) : wave_sum(acc[v]);
-    if (lane == 0) red[w][v] = s;
+      for (int v = 0; v < NV; ++v) x[v] = part[(size_t)v * nb + i];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        acc[v] = ((maxmask >> v) & 1u) ? fmax(acc[v], x[v]) : acc[v] + x[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      bool mx = (maxmask >> v) & 1u;
+      double s = mx ? wave_max(acc[v]) : wave_sum(acc[v]);
+      if (threadIdx.x == 0) red[v] = s;
+    }
   }
   __syncthreads();
 #pragma unroll
-  for (int v = 0; v < NV; ++v) {
-    bool mx = (maxmask >> v) & 1u;
-    double t = red[0][v];
-    for (int i = 1; i < nw; ++i) t = mx ? fmax(t, red[i][v]) : t + red[i][v];
-    out[v] = t;
-  }
+  for (int v = 0; v < NV; ++v) out[v] = red[v];
   __syncthreads();
 }
 

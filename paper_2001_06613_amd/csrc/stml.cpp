@@ -464,6 +464,8 @@ int ls_passes(int ls_max, std::vector<LSPass>* passes,
   return (int)passes->size();
 }
 
+int gn_log(stml_ctx* c, int nK, long long N, stml_gir_log* log);
+
 // Gauss-Newton on the frames Kdev (nK of them) of `level`, updating u in
 // place; mirrors the oracle's gauss_newton step for step.  Every decision
 // (CG stop, Armijo step, Gauss-Newton stop) is taken on the device, so the
@@ -504,7 +506,14 @@ int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
       if (c->hsc->gn_stop <= it + 1) break;
     }
   }
-  // logs of every iteration that ran
+  return gn_log(c, nK, g.N, log);
+}
+
+// Statistics of the registration that just ran on c (device log and
+// scalars) for nK frames of N voxels.
+int gn_log(stml_ctx* c, int nK, long long N, stml_gir_log* log) {
+  const stml_opts& o = c->o;
+  const int D = c->d;
   HIP_OK(hipMemcpyAsync(c->hlog, c->gnlog, o.gn_max * sizeof(GNLog),
                         hipMemcpyDeviceToHost, c->stream));
   int rc = read_scal(c);
@@ -526,7 +535,7 @@ int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
       log->step[it] = L.t;
       log->J_iter[it] = L.Jacc;
       log->du_max[it] = L.t * L.maxd;
-      log->du_rms[it] = L.t * std::sqrt(L.ssqd / ((double)nK * D * g.N));
+      log->du_rms[it] = L.t * std::sqrt(L.ssqd / ((double)nK * D * N));
     }
     log->gn_iterations += 1;
     log->J = L.Jacc;
@@ -652,10 +661,17 @@ int do_predict(stml_ctx* c, int level, int q_next) {
   return STML_OK;
 }
 
+int record_gir(stml_ctx* c, int level, int q, int rc, stml_gir_log& log);
+
 int do_register(stml_ctx* c, int level, int q) {
   stml_gir_log log;
   int rc = gauss_newton(c, level, c->qt[q].K, (int)c->K[q].size(),
                         c->lv[level].Y, &log);
+  return record_gir(c, level, q, rc, log);
+}
+
+// Keep the log of GIR(level, K_q) and turn its status into the return code.
+int record_gir(stml_ctx* c, int level, int q, int rc, stml_gir_log& log) {
   if (rc < 0 && rc != STML_EBREAKDOWN) return rc;
   log.level = level;
   log.q = q;
@@ -1066,6 +1082,303 @@ int stml_timing_get(stml_ctx* c, int kernel, int level, double* ms,
   if (vf) *vf = tvf;
   if (bytes) *bytes = tb;
   return STML_OK;
+}
+
+}  // extern "C"
+
+// ============================================================ batching
+
+struct stml_batch {
+  std::vector<stml_ctx*> c;
+  hipStream_t user = nullptr;     // caller's stream
+  hipStream_t stream = nullptr;   // internal (graphs are captured on it)
+  Job* djobs = nullptr;
+  int* dfirst = nullptr;
+  int* dstop = nullptr;
+  Job* hjobs = nullptr;           // pinned staging
+  int* hfirst = nullptr;
+  int* hstop = nullptr;
+  bool graph = true;               // replay a captured iteration
+  std::string err;
+};
+
+namespace {
+
+int bfail(stml_batch* b, int code, const char* fmt, ...) {
+  if (b) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    b->err = buf;
+  }
+  return code;
+}
+
+#define BHIP_OK(call)                                                       \
+  do {                                                                      \
+    hipError_t e_ = (call);                                                 \
+    if (e_ != hipSuccess)                                                   \
+      return bfail(b, STML_EDEVICE, "%s: %s", #call, hipGetErrorString(e_)); \
+  } while (0)
+
+size_t batch_layout(int count, char* base, stml_batch* b) {
+  Layout lo;
+  lo.base = base;
+  Job* j = lo.take<Job>(count);
+  int* f = lo.take<int>((size_t)kClsCount * (count + 1));
+  int* st = lo.take<int>(count);
+  if (b) {
+    b->djobs = j;
+    b->dfirst = f;
+    b->dstop = st;
+  }
+  return lo.off;
+}
+
+// One Gauss-Newton iteration of every problem of js.
+hipError_t batch_iteration(const JobSet& js, const int* tot, int reg,
+                           const stml_opts& o,
+                           const std::vector<LSPass>& passes,
+                           const std::vector<std::vector<double>>& steps,
+                           int* dstop, hipStream_t s) {
+  hipError_t e = batch_eval(js, tot[kClsTile], reg, s);
+  if (e == hipSuccess) e = batch_cg_init(js, tot[kClsVox], s);
+  for (int it = 0; e == hipSuccess && it < o.cg_max; ++it) {
+    e = batch_cg_hvp(js, tot[kClsHv], reg, it, o.parity_mode, o.cg_rtol, s);
+    if (e == hipSuccess) e = batch_cg_update(js, tot[kClsVox], it, s);
+  }
+  for (size_t pi = 0; e == hipSuccess && pi < passes.size(); ++pi) {
+    e = batch_trial(js, tot[kClsTile], reg, steps[pi].data(), passes[pi], s);
+    if (e == hipSuccess)
+      e = batch_accept(js, tot[kClsElem], steps[pi].data(), passes[pi],
+                       o.ls_max, o.c1, o.parity_mode, o.tol_J, o.tol_u, s);
+  }
+  if (e == hipSuccess) e = batch_advance(js, dstop, s);
+  return e;
+}
+
+// GIR(level, K_q) of every sequence of the batch, in shared launches.
+int batch_register(stml_batch* b, int level, int q) {
+  const int S = (int)b->c.size();
+  const stml_opts& o = b->c[0]->o;
+  int tot[kClsCount] = {};
+  for (int cl = 0; cl < kClsCount; ++cl) b->hfirst[cl * (S + 1)] = 0;
+  for (int j = 0; j < S; ++j) {
+    stml_ctx* c = b->c[j];
+    Job& J = b->hjobs[j];
+    J.T = c->lv[level].T;
+    J.u = c->lv[level].Y;
+    J.K = c->qt[q].K;
+    J.g = geom_of(c, level);
+    J.md = model_of(c, level, (int)c->K[q].size());
+    J.grad = c->g;
+    J.dW = c->dW;
+    J.x = c->x;
+    J.r = c->r;
+    J.z = c->z;
+    J.q = c->q;
+    J.P0 = c->P[0];
+    J.P1 = c->P[1];
+    J.sums = c->sums;
+    J.rb = c->rb;
+    J.sc = c->sc;
+    J.log = c->gnlog;
+    job_shape(&J);
+    const int nb[kClsCount] = {J.nb_tile, J.nb_vox, J.ct.grid, 1, J.nb_elem};
+    for (int cl = 0; cl < kClsCount; ++cl) {
+      tot[cl] += nb[cl];
+      b->hfirst[cl * (S + 1) + j + 1] = tot[cl];
+    }
+  }
+  BHIP_OK(hipMemcpyAsync(b->djobs, b->hjobs, S * sizeof(Job),
+                         hipMemcpyHostToDevice, b->stream));
+  BHIP_OK(hipMemcpyAsync(b->dfirst, b->hfirst,
+                         (size_t)kClsCount * (S + 1) * sizeof(int),
+                         hipMemcpyHostToDevice, b->stream));
+  const JobSet js{b->djobs, b->dfirst, S};
+  std::vector<LSPass> passes;
+  std::vector<std::vector<double>> steps;
+  ls_passes(o.ls_max, &passes, &steps);
+  const int reg = o.regulariser;
+  BHIP_OK(batch_gn_reset(js, o.gn_max, b->stream));
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (b->graph && o.gn_max > 0) {
+    BHIP_OK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
+    hipError_t e = batch_iteration(js, tot, reg, o, passes, steps, b->dstop,
+                                   b->stream);
+    hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
+    if (e == hipSuccess) e = e2;
+    if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return bfail(b, STML_EDEVICE, "graph capture: %s", hipGetErrorString(e));
+    }
+  }
+  hipError_t e = hipSuccess;
+  for (int it = 0; it < o.gn_max && e == hipSuccess; ++it) {
+    e = exec ? hipGraphLaunch(exec, b->stream)
+             : batch_iteration(js, tot, reg, o, passes, steps, b->dstop,
+                               b->stream);
+    if (e != hipSuccess || o.parity_mode) continue;
+    e = hipMemcpyAsync(b->hstop, b->dstop, S * sizeof(int),
+                       hipMemcpyDeviceToHost, b->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(b->stream);
+    bool all = true;
+    for (int j = 0; j < S && all; ++j) all = b->hstop[j] != 0;
+    if (all) break;
+  }
+  hipError_t es = hipStreamSynchronize(b->stream);
+  if (exec) (void)hipGraphExecDestroy(exec);
+  if (graph) (void)hipGraphDestroy(graph);
+  if (e == hipSuccess) e = es;
+  if (e != hipSuccess)
+    return bfail(b, STML_EDEVICE, "batched iteration: %s",
+                 hipGetErrorString(e));
+  int worst = STML_OK;
+  for (int j = 0; j < S; ++j) {
+    stml_ctx* c = b->c[j];
+    stml_gir_log log;
+    int rc = gn_log(c, (int)c->K[q].size(), c->N[level], &log);
+    rc = record_gir(c, level, q, rc, log);
+    if (rc < 0 && worst >= 0) {
+      worst = rc;
+      b->err = "sequence " + std::to_string(j) + ": " + c->err;
+    } else if (rc > 0 && worst == STML_OK) {
+      worst = rc;
+    }
+  }
+  return worst;
+}
+
+int batch_check(stml_batch* b, int level) {
+  for (size_t j = 0; j < b->c.size(); ++j) {
+    stml_ctx* c = b->c[j];
+    if (!c->have_seq)
+      return bfail(b, STML_ESTATE, "sequence %zu: no sequence set", j);
+    if (level < 0 || level >= c->L)
+      return bfail(b, STML_EINVAL, "level %d out of range", level);
+  }
+  if (b->user) BHIP_OK(hipStreamSynchronize(b->user));
+  return STML_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t stml_batch_workspace_bytes(int count) {
+  if (count < 1) return 0;
+  return batch_layout(count, nullptr, nullptr);
+}
+
+int stml_batch_create(stml_ctx* const* ctxs, int count, void* stream,
+                      void* ws, size_t ws_bytes, stml_batch** out) {
+  if (!out) return STML_EINVAL;
+  *out = nullptr;
+  if (!ctxs || count < 1) return STML_EINVAL;
+  const stml_ctx* a = ctxs[0];
+  if (!a) return STML_EINVAL;
+  for (int j = 0; j < count; ++j) {
+    const stml_ctx* c = ctxs[j];
+    if (!c || c->d != 2 || c->L != a->L || c->T1 != a->T1 ||
+        c->o.regulariser != a->o.regulariser || c->o.gn_max != a->o.gn_max ||
+        c->o.cg_max != a->o.cg_max || c->o.ls_max != a->o.ls_max ||
+        c->o.parity_mode != a->o.parity_mode || c->o.c1 != a->o.c1 ||
+        c->o.cg_rtol != a->o.cg_rtol || c->o.tol_J != a->o.tol_J ||
+        c->o.tol_u != a->o.tol_u ||
+        (c->o.eps_stop > 0 && !c->o.parity_mode))
+      return STML_EINVAL;
+    for (int i = 0; i < j; ++i)
+      if (ctxs[i] == c) return STML_EINVAL;
+  }
+  const size_t need = batch_layout(count, nullptr, nullptr);
+  if (!ws || ws_bytes < need || ((uintptr_t)ws % kAlign))
+    return ws && ws_bytes < need ? STML_ENOMEM : STML_EINVAL;
+  stml_batch* b = new stml_batch();
+  b->c.assign(ctxs, ctxs + count);
+  b->user = static_cast<hipStream_t>(stream);
+  batch_layout(count, static_cast<char*>(ws), b);
+  if (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) !=
+          hipSuccess ||
+      hipHostMalloc((void**)&b->hjobs, count * sizeof(Job),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&b->hfirst,
+                    (size_t)kClsCount * (count + 1) * sizeof(int),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&b->hstop, count * sizeof(int),
+                    hipHostMallocDefault) != hipSuccess) {
+    stml_batch_destroy(b);
+    return STML_EDEVICE;
+  }
+  *out = b;
+  return STML_OK;
+}
+
+void stml_batch_destroy(stml_batch* b) {
+  if (!b) return;
+  if (b->stream) {
+    (void)hipStreamSynchronize(b->stream);
+    (void)hipStreamDestroy(b->stream);
+  }
+  if (b->hjobs) (void)hipHostFree(b->hjobs);
+  if (b->hfirst) (void)hipHostFree(b->hfirst);
+  if (b->hstop) (void)hipHostFree(b->hstop);
+  delete b;
+}
+
+const char* stml_batch_last_error(const stml_batch* b) {
+  return b ? b->err.c_str() : "null batch";
+}
+
+int stml_batch_set_graph(stml_batch* b, int on) {
+  if (!b) return STML_EINVAL;
+  b->graph = on != 0;
+  return STML_OK;
+}
+
+int stml_batch_predict(stml_batch* b, int level, int q_next) {
+  if (!b) return STML_EINVAL;
+  int rc = batch_check(b, level);
+  if (rc) return rc;
+  for (size_t j = 0; j < b->c.size(); ++j) {
+    stml_ctx* c = b->c[j];
+    if (q_next < 0 || q_next >= c->T1)
+      return bfail(b, STML_EINVAL, "q_next %d out of range", q_next);
+    rc = do_predict(c, level, q_next);
+    if (rc < 0)
+      return bfail(b, rc, "sequence %zu: %s", j, c->err.c_str());
+  }
+  return STML_OK;
+}
+
+int stml_batch_register_level(stml_batch* b, int level, int q) {
+  if (!b) return STML_EINVAL;
+  int rc = batch_check(b, level);
+  if (rc) return rc;
+  if (q < 0 || q >= b->c[0]->T1)
+    return bfail(b, STML_EINVAL, "q %d out of range", q);
+  return batch_register(b, level, q);
+}
+
+int stml_batch_run(stml_batch* b) {
+  if (!b) return STML_EINVAL;
+  int rc = batch_check(b, 0);
+  if (rc) return rc;
+  const int L = b->c[0]->L, T = b->c[0]->T1 - 1;
+  int warn = STML_OK;
+  for (int level = 0; level < L; ++level) {
+    for (int q = 0; q <= T; ++q) {
+      rc = stml_batch_predict(b, level, q);
+      if (rc < 0) return rc;
+      rc = batch_register(b, level, q);
+      if (rc < 0) return rc;
+      if (rc > 0) warn = rc;
+    }
+  }
+  return warn;
 }
 
 }  // extern "C"

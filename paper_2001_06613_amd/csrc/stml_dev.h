@@ -57,6 +57,7 @@ struct Scal {
   int iters;                  // CG iterations taken
   int bad;                    // non-finite input count
   int gn_stop;                // Gauss-Newton iterations >= gn_stop do nothing
+  int gn_cur;                 // iteration of batched (graph) launches
 };
 
 // One Gauss-Newton iteration as decided on the device.
@@ -425,12 +426,23 @@ __device__ __forceinline__ double wave_max(double v) {
   return v;
 }
 
+// A block's index and the block count within its own problem: the grid of
+// a single-problem launch, or one problem's share of a batched launch
+// (whose shares start at multiples of kXCD, so b % kXCD is still the XCD).
+struct Blk {
+  int id, n;
+};
+__device__ __forceinline__ Blk grid_blk() {
+  return Blk{(int)blockIdx.x, (int)gridDim.x};
+}
+
 // Tile index of the i-th tile a block processes.  Blocks are dealt to the 8
 // XCDs round-robin by the hardware; this gives every XCD one contiguous
 // range of tiles so that stencil neighbours share that XCD's L2.
-__device__ __forceinline__ long long xcd_tile(long long ntiles, int i) {
-  int b = blockIdx.x;
-  int nb = gridDim.x;            // a multiple of kXCD
+__device__ __forceinline__ long long xcd_tile(long long ntiles, int i,
+                                              Blk blk) {
+  int b = blk.id;
+  int nb = blk.n;                // a multiple of kXCD
   int xcd = b % kXCD;
   int local = b / kXCD;
   int per_xcd_blocks = nb / kXCD;
@@ -438,6 +450,9 @@ __device__ __forceinline__ long long xcd_tile(long long ntiles, int i) {
   long long hi = ntiles * (xcd + 1) / kXCD;
   long long t = lo + local + (long long)i * per_xcd_blocks;
   return t < hi ? t : -1;
+}
+__device__ __forceinline__ long long xcd_tile(long long ntiles, int i) {
+  return xcd_tile(ntiles, i, grid_blk());
 }
 
 }  // namespace stml

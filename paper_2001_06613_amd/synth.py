@@ -31,15 +31,30 @@ def _rng(seed):
     return np.random.Generator(np.random.PCG64(seed))
 
 
+def band_edges(rng, H, n_bands=8, min_thick=3):
+    """Inner boundaries (n_bands - 1, sorted) of horizontal bands over [0, H):
+    uniform boundaries conditioned on every band being at least min_thick
+    thick (unconditioned when H < n_bands * min_thick)."""
+    slack = H - n_bands * min_thick
+    if slack >= 0 and (slack / H) ** (n_bands - 1) < 1e-3:
+        # the gaps are min_thick plus the slack split by uniform spacings;
+        # drawn directly because rejection would accept with probability
+        # (slack / H)^(n_bands - 1) only (0 at slack 0)
+        u = np.sort(rng.uniform(0, 1, n_bands - 1))
+        gaps = min_thick + slack * np.diff(np.concatenate([[0.0], u, [1.0]]))
+        return np.cumsum(gaps)[:-1]
+    while True:
+        b = np.sort(rng.uniform(0, H, n_bands - 1))
+        edges = np.concatenate([[0.0], b, [float(H)]])
+        if np.min(np.diff(edges)) >= min_thick or slack < 0:
+            return b
+
+
 def base_image(rng, shape, n_bands=8, min_thick=3, n_blobs=12,
                blob_sigma=3.0, speckle_std=0.3):
     """Layered phantom with blobs and speckle, float64, shape ``shape``."""
     H = shape[0]
-    while True:
-        b = np.sort(rng.uniform(0, H, n_bands - 1))
-        edges = np.concatenate([[0.0], b, [float(H)]])
-        if np.min(np.diff(edges)) >= min_thick or H < n_bands * min_thick:
-            break
+    b = band_edges(rng, H, n_bands, min_thick)
     inten = rng.uniform(0.2, 1.0, n_bands)
     y = np.arange(H) + 0.5
     band = np.searchsorted(b, y)
