@@ -113,7 +113,9 @@ void stml_default_opts(stml_opts* opts);
 
 /* Bytes of device workspace a context for n frames of the given finest
  * extent (dim entries, slowest first) needs.  0 if the arguments are
- * invalid. */
+ * invalid: n outside 1..STML_MAX_FRAMES, n dim N above 2e9 values, or (2-D)
+ * more than 8184 tiles of 64 x 4 pixels at the finest level (about 2 Mpx,
+ * e.g. 1448 x 1448). */
 size_t stml_workspace_bytes(const stml_opts* opts, int n, const int* extent);
 
 /* Create a context.  workspace_dev must stay valid, untouched by the caller,
@@ -222,6 +224,20 @@ int stml_gn_direction(stml_ctx* ctx, int level, const int* frames, int nk,
 #define STML_K_RESTRICT    8  /* spatial restriction                         */
 #define STML_K_COUNT       9
 #define STML_K_ALL       0x1ff  /* mask of every class                     */
+
+/* Launch shape of the 2-D kernels (autotuned by the caller; every value a
+ * multiple of 8): blocks per registration for the objective and trial
+ * kernels (8..1024, default 512) and for the voxel-major CG updates
+ * (8..1024, default 512), and the block target of the Hessian product
+ * (8..8192, default 2048).  Results depend on them only through the order
+ * of float64 sums.  EINVAL when out of range. */
+typedef struct stml_tuning {
+  int tile_blocks;
+  int vox_blocks;
+  int hv_blocks;
+} stml_tuning;
+int stml_set_tuning(stml_ctx* ctx, const stml_tuning* tuning);
+int stml_get_tuning(const stml_ctx* ctx, stml_tuning* tuning);
 
 /* mask != 0: clear the accumulators and time the classes whose bit
  * (1 << STML_K_...) is set; mask = 0: stop timing. */

@@ -71,6 +71,11 @@ class stml_gir_log(ctypes.Structure):
     ]
 
 
+class stml_tuning(ctypes.Structure):
+    _fields_ = [("tile_blocks", ctypes.c_int), ("vox_blocks", ctypes.c_int),
+                ("hv_blocks", ctypes.c_int)]
+
+
 # every symbol include/stml.h declares, with (restype, argtypes)
 _P = ctypes.c_void_p
 _I = ctypes.c_int
@@ -125,6 +130,8 @@ SIGNATURES = {
     "stml_batch_predict": (_I, [_P, _I, _I]),
     "stml_batch_register_level": (_I, [_P, _I, _I]),
     "stml_batch_run": (_I, [_P]),
+    "stml_set_tuning": (_I, [_P, ctypes.POINTER(stml_tuning)]),
+    "stml_get_tuning": (_I, [_P, ctypes.POINTER(stml_tuning)]),
     "stml_timing": (_I, [_P, _I]),
     "stml_timing_get": (_I, [_P, _I, _I, _DP,
                              ctypes.POINTER(ctypes.c_longlong), _DP, _DP]),
@@ -343,6 +350,16 @@ class STML:
         self._net_ref = net
         return self._check(self.lib.stml_set_predictor_net(
             self.ctx, net.net if net is not None else None))
+
+    def set_tuning(self, tile_blocks, vox_blocks, hv_blocks):
+        t = stml_tuning(int(tile_blocks), int(vox_blocks), int(hv_blocks))
+        return self._check(self.lib.stml_set_tuning(self.ctx, ctypes.byref(t)))
+
+    def get_tuning(self):
+        t = stml_tuning()
+        self._check(self.lib.stml_get_tuning(self.ctx, ctypes.byref(t)))
+        return {"tile_blocks": t.tile_blocks, "vox_blocks": t.vox_blocks,
+                "hv_blocks": t.hv_blocks}
 
     def timing(self, kernels):
         """Start timing the named kernel classes (True: all), or stop (None,

@@ -24,7 +24,6 @@ constexpr int kHX = kTX + 4;       // with a 2-cell halo
 constexpr int kHY = kTY + 4;
 constexpr int kLX = kTX + 2;       // L p on a 1-cell halo
 constexpr int kLY = kTY + 2;
-constexpr int kCgMaxBlocks = 2048;
 
 // Frames of a voxel-major tile handled by this wave.
 __device__ __forceinline__ void wave_frames(int nK, int& j0, int& j1) {
@@ -413,7 +412,7 @@ __global__ __launch_bounds__(256) void cgt_hvp2_kernel(
 
 static int cgv_blocks(const Geom& g) {
   long long ntiles = (g.N + kWave - 1) / kWave;
-  long long nb = ntiles < kMaxTileBlocks ? ntiles : kMaxTileBlocks;
+  long long nb = ntiles < g.vox_cap ? ntiles : g.vox_cap;
   return (int)((nb + kXCD - 1) / kXCD * kXCD);
 }
 
@@ -429,7 +428,7 @@ CgTiles cg_tiles_2d(const Geom& g, int nK) {
   CgTiles t;
   int ntx = (g.m[1] + kTX - 1) / kTX, nty = (g.m[0] + kTY - 1) / kTY;
   int ntiles = ntx * nty;
-  int nfg = (kCgMaxBlocks + ntiles - 1) / ntiles;
+  int nfg = (g.hv_target + ntiles - 1) / ntiles;
   if (nfg > nK) nfg = nK;
   if (nfg < 1) nfg = 1;
   t.fpg = (nK + nfg - 1) / nfg;

@@ -33,6 +33,9 @@ Geom make_geom(int dim, const int* ext, double h) {
     g.N = (long long)g.m[0] * g.m[1] * g.m[2];
   }
   g.inv_h = 1.0 / h;
+  g.tile_cap = kMaxTileBlocks;
+  g.vox_cap = kMaxTileBlocks;
+  g.hv_target = kHvBlocks;
   return g;
 }
 
@@ -59,7 +62,7 @@ static int round_up(long long v, int m) { return (int)((v + m - 1) / m * m); }
 
 int tile_blocks(const Geom& g) {
   long long ntiles = (g.N + kWave - 1) / kWave;
-  long long nb = ntiles < kMaxTileBlocks ? ntiles : kMaxTileBlocks;
+  long long nb = ntiles < g.tile_cap ? ntiles : g.tile_cap;
   return round_up(nb, kXCD);
 }
 

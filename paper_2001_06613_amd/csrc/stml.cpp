@@ -72,6 +72,7 @@ struct stml_ctx {
   GNLog* hlog = nullptr;                // pinned host mirror
   int* hk = nullptr;                    // pinned host staging of frame lists
   bool have_seq = false;
+  stml_tuning tune{kMaxTileBlocks, kMaxTileBlocks, kHvBlocks};
   stml_net* net = nullptr;               // learned predictor (optional)
   float* ureg = nullptr;                 // registered estimate kept for it
   struct Pick {
@@ -226,12 +227,23 @@ bool setup_dims(stml_ctx* c, const stml_opts* o, int n, const int* extent) {
   // compact vectors index elements with 64-bit offsets, but the element
   // kernels decode the frame index from 32-bit rows
   if ((double)n * o->dim * (double)c->N[c->L - 1] > 2.0e9) return false;
+  // the 2-D Hessian product runs one block per 64 x 4 tile at least, and
+  // its partials must fit one reduction region
+  if (o->dim == 2) {
+    const std::vector<int>& e = c->ext[c->L - 1];
+    long long tiles = (long long)((e[1] + 63) / 64) * ((e[0] + 3) / 4);
+    if (tiles > (long long)kRegionSlots - 8192 - 8) return false;
+  }
   c->K = temporal_sets(n, c->T1);
   return true;
 }
 
 Geom geom_of(const stml_ctx* c, int level) {
-  return make_geom(c->d, c->ext[level].data(), c->h[level]);
+  Geom g = make_geom(c->d, c->ext[level].data(), c->h[level]);
+  g.tile_cap = c->tune.tile_blocks;
+  g.vox_cap = c->tune.vox_blocks;
+  g.hv_target = c->tune.hv_blocks;
+  return g;
 }
 
 Model model_of(const stml_ctx* c, int level, int nK) {
@@ -1050,6 +1062,22 @@ int stml_set_predictor_net(stml_ctx* c, stml_net* net) {
   if (net && !c->ureg)
     return fail(c, STML_ESTATE, "create the context with predictor = 1");
   c->net = net;
+  return STML_OK;
+}
+
+int stml_set_tuning(stml_ctx* c, const stml_tuning* t) {
+  if (!c || !t) return STML_EINVAL;
+  auto ok = [](int v, int hi) { return v >= 8 && v <= hi && v % 8 == 0; };
+  if (!ok(t->tile_blocks, 1024) || !ok(t->vox_blocks, 1024) ||
+      !ok(t->hv_blocks, 8192))
+    return fail(c, STML_EINVAL, "tuning out of range");
+  c->tune = *t;
+  return STML_OK;
+}
+
+int stml_get_tuning(const stml_ctx* c, stml_tuning* t) {
+  if (!c || !t) return STML_EINVAL;
+  *t = c->tune;
   return STML_OK;
 }
 

@@ -15,7 +15,8 @@ constexpr int kMaxFPT = 16;        // max frames one thread keeps in registers
 constexpr int kMaxChunks = 16;     // waves per block -> |K| <= 256
 constexpr int kTrialSteps = 5;     // Armijo steps evaluated per pass
 constexpr int kXCD = 8;            // MI355X: 8 accelerator complex dies
-constexpr int kMaxTileBlocks = 512;
+constexpr int kMaxTileBlocks = 512;    // default block caps
+constexpr int kHvBlocks = 2048;
 constexpr int kMaxElemBlocks = 1024;
 
 // Level geometry.  D = 2 uses m[0] (slow) and m[1] (fast); D = 3 uses all.
@@ -24,6 +25,9 @@ struct Geom {
   long long s[3];      // strides (elements) of each axis
   long long N;         // voxels
   double inv_h;        // 1 / cell width (finest-pixel units)
+  // launch shape (host side only): block caps of the tile and voxel-major
+  // kernels, and the block target of the 2-D Hessian product
+  int tile_cap, vox_cap, hv_target;
 };
 
 // Constants of the model on one level and subset.

@@ -111,3 +111,66 @@ def test_batch_rejects_mismatched_contexts():
     with pytest.raises(STMLError):
         B.run()
 
+
+
+def test_tuning_changes_only_rounding_and_keeps_batch_identity(tmp_path):
+    from paper_2001_06613_amd import autotune
+
+    singles, batched = _pair(True)
+    tuned = (64, 128, 1024)
+    for a, b in zip(singles, batched):
+        a.set_tuning(*tuned)
+        b.set_tuning(*tuned)
+    print("tuned batch", flush=True)
+    for a in singles:
+        a.run()
+    Batch(batched).run()
+    for a, b in zip(singles, batched):
+        _assert_same(a, b)
+    # the default launch shape gives the same result up to float64 rounding
+    ref, _ = _pair(True)
+    for r in ref:
+        r.run()
+    for a, r in zip(singles, ref):
+        assert a.get_tuning() == {"tile_blocks": 64, "vox_blocks": 128,
+                                  "hv_blocks": 1024}
+        assert r.get_tuning() == autotune.DEFAULT
+        la, lr = a.logs(), r.logs()
+        for x, y in zip(la, lr):
+            assert x["steps"] == y["steps"]
+            assert x["J"] == pytest.approx(y["J"], rel=1e-9)
+        diff = (a.get_displacements() - r.get_displacements()).abs().max()
+        assert float(diff) <= 1e-4
+    with pytest.raises(STMLError):
+        singles[0].set_tuning(12, 512, 2048)
+    with pytest.raises(STMLError):
+        singles[0].set_tuning(512, 2048, 2048)
+
+
+def test_autotune_picks_a_valid_setting_and_caches_it(tmp_path):
+    from paper_2001_06613_amd import autotune
+
+    _, batched = _pair(True)
+    B = Batch(batched)
+    B.run()
+    before = [b.get_displacements().clone() for b in batched]
+    path = str(tmp_path / "tune.json")
+    print("autotune", flush=True)
+    cfg = autotune.tune(batched, batch=B, cache_path=path, repeats=1)
+    for name, values in autotune.CANDIDATES.items():
+        assert cfg[name] in values
+    # the timings restart from, and leave, the registered displacements
+    for b, u in zip(batched, before):
+        assert torch.equal(b.get_displacements(), u)
+        assert b.get_tuning() == {k: cfg[k] for k in autotune.DEFAULT}
+    import json
+    with open(path) as f:
+        cache = json.load(f)
+    key = autotune.cache_key(batched, True)
+    assert key in cache
+    # a second call reads the cache back
+    for b in batched:
+        b.set_tuning(512, 512, 2048)
+    cfg2 = autotune.tune(batched, batch=B, cache_path=path)
+    assert {k: cfg2[k] for k in autotune.DEFAULT} == \
+        {k: cfg[k] for k in autotune.DEFAULT}
