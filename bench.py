@@ -19,7 +19,6 @@ Prints one JSON line.
 """
 
 import argparse
-import hashlib
 import json
 import os
 import sys
@@ -31,6 +30,10 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E, vendor figure
+COPY_BYTES = 512 << 20         # plain copy that scales the HBM counters
+AUTOTUNE_CACHE = os.environ.get(
+    "STML_AUTOTUNE_CACHE",
+    os.path.join(ROOT, "paper_2001_06613_amd", "data", "autotune.json"))
 # The dominant kernel of the solve (largest share of GPU time in the
 # per-kernel breakdown) is timed live in the timed region.  Its algorithmic
 # bytes per launch come from the library: every field it must read and
@@ -53,18 +56,17 @@ def _units(logs, extents):
     return total
 
 
-def _traffic_record(dim):
+def _traffic_record():
     """HBM bytes per launch of the dominant kernel from the committed
-    rocprofv3 counter summary, if it was taken on the current source."""
+    rocprofv3 counter summary, if it was taken on the current sources."""
+    from paper_2001_06613_amd import pmc_traffic
+
     path = os.path.join(ROOT, "profiles", "cg_update_traffic.json")
-    src = os.path.join(ROOT, "paper_2001_06613_amd", "csrc", "cg_tiles.hip")
     if not os.path.exists(path):
         return None
     with open(path) as f:
         rec = json.load(f)
-    with open(src, "rb") as f:
-        sha = hashlib.sha256(f.read()).hexdigest()
-    if rec.get("kernels_hip_sha256") != sha:
+    if rec.get("source_sha256") != pmc_traffic.source_sha():
         return None
     return rec.get("hbm_bytes_per_launch")
 
@@ -91,20 +93,135 @@ def cpu_baseline(frames, budget_s=30.0):
                       f"the finest level, NumPy float64, {dt:.1f} s"}
 
 
+def _gen_batch_sequence(args):
+    from paper_2001_06613_amd import synth
+
+    n, side, seed = args
+    return synth.sinusoid_sequence(n, (side, side), 5.0, 3, seed)[0]
+
+
+def batched_comparison(seqs, log):
+    """The 32 uneven sequences (16..128 frames, 128..512 px squares, the
+    main workload's schedule and fixed iterations) solved one after the
+    other and as one batch (autotuned launch shapes); both must give
+    bit-identical displacements."""
+    import torch
+    from paper_2001_06613_amd import autotune
+    from paper_2001_06613_amd.binding import STML, Batch, default_opts
+
+    w = WORKLOAD
+    opts = default_opts(n_spatial=w["n_spatial"], n_temporal=w["n_temporal"],
+                        reg=w["reg"], alpha=w["alpha"], lam=w["lam"],
+                        beta=w["beta"], gn_max=w["gn_max"],
+                        cg_max=w["cg_max"], parity_mode=True)
+    sts = [STML(f.shape[0], f.shape[1:], opts=opts) for f in seqs]
+    dev = [torch.from_numpy(f).cuda() for f in seqs]
+    vf = float(sum(f.size for f in seqs))
+    B = Batch(sts)
+    _set_all(sts, dev)
+    cfg = autotune.tune(sts, batch=B, cache_path=AUTOTUNE_CACHE, repeats=1)
+    log("batch: launch shapes " + json.dumps(
+        {k: cfg[k] for k in autotune.DEFAULT}))
+
+    def timed(fn):
+        _set_all(sts, dev)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    timed(lambda: sts[0].run())           # warm-up
+    t_loop = timed(lambda: [s.run() for s in sts])
+    ref = [s.get_displacements().cpu() for s in sts]
+    log("batch: looped done")
+    t_batch = timed(B.run)
+    same = all(torch.equal(r, s.get_displacements().cpu())
+               for r, s in zip(ref, sts))
+    log("batch: batched done")
+    B.close()
+    for s in sts:
+        s.close()
+    return {"workload": "32 uneven sequences (16-128 frames, 128-512 px), "
+                        "same schedule and fixed iterations",
+            "voxel_frames": vf, "looped_ms": round(1e3 * t_loop, 1),
+            "batched_ms": round(1e3 * t_batch, 1),
+            "speedup": round(t_loop / t_batch, 3), "identical": same,
+            "tuning": {k: cfg[k] for k in autotune.DEFAULT}}
+
+
+def _set_all(sts, dev):
+    for s, f in zip(sts, dev):
+        s.set_sequence(f)
+    return True
+
+
+def learned_comparison(seqs, log):
+    """Paper's predictor vs the shipped learned one on held-out 64-frame
+    256x256 sequences (convergence-controlled Gauss-Newton)."""
+    from paper_2001_06613_amd import learned
+    from paper_2001_06613_amd.binding import Net
+
+    net = Net(8, WORKLOAD["extent"])
+    net.set_params(learned.load_params(learned.TRAINED_C2))
+    rows = learned.compare(net, seqs, opts=learned.schedule_opts(gn_max=40))
+    s = learned.summarise(rows)
+    log("learned: comparison done")
+    net.close()
+    return {"sequences": len(rows), "seeds": [r["seed"] for r in rows],
+            **{k: (round(v, 4) if isinstance(v, float) else v)
+               for k, v in s.items() if k != "sequences"}}
+
+
+def pmc_probe(st, fr):
+    """One solve and a plain copy of known size, for counter runs."""
+    import torch
+
+    st.set_sequence(fr)
+    st.run()
+    x = torch.ones(COPY_BYTES // 4, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"pmc_probe": True, "copy_bytes": COPY_BYTES}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--pmc-probe", action="store_true",
+                    help="one solve and a copy of known size (counter runs)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build "
               "runs the registration path on one GPU only", file=sys.stderr)
         sys.exit(2)
 
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    # synthetic inputs of the extra comparisons, generated by forked
+    # workers before the GPU is touched
+    from paper_2001_06613_amd import learned, synth
+
+    batch_seqs, learned_seqs = None, None
+    if not args.pmc_probe and not args.no_batch:
+        import multiprocessing as mp
+
+        with mp.get_context("fork").Pool(16) as pool:
+            batch_seqs = pool.map(_gen_batch_sequence, synth.config_batch(),
+                                  chunksize=1)
+        log("batch: sequences generated")
+    if not args.pmc_probe and not args.no_learned:
+        learned_seqs = list(learned.generate(range(20000, 20004), workers=4))
+
     import torch
-    from paper_2001_06613_amd import synth
     from paper_2001_06613_amd.binding import STML, default_opts
 
     torch.cuda.set_device(0)
@@ -121,6 +238,10 @@ def main():
     def step():
         st.set_sequence(fr)
         st.run()
+
+    if args.pmc_probe:
+        pmc_probe(st, fr)
+        return
 
     for i in range(args.warmup):
         step()
@@ -149,7 +270,7 @@ def main():
     achieved = bytes_total / (dk["ms"] * 1e-3) / 1e9 if dk["ms"] > 0 else 0.0
     fin = st.timing_get(DOMINANT, w["n_spatial"] - 1)
     fin_gbs = fin["bytes"] / (fin["ms"] * 1e-3) / 1e9 if fin["ms"] > 0 else 0.0
-    traffic = _traffic_record(dim)
+    traffic = _traffic_record()
     # per-kernel breakdown from one extra, separately timed solve (every
     # class bracketed), outside the timed region
     st.timing(True)
@@ -197,6 +318,11 @@ def main():
         },
         "kernels_one_solve": kernels,
     }
+    st.close()
+    if batch_seqs is not None:
+        out["batched"] = batched_comparison(batch_seqs, log)
+    if learned_seqs is not None:
+        out["learned"] = learned_comparison(learned_seqs, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frames)
     print(json.dumps(out))

@@ -44,18 +44,21 @@ __device__ void block_partials(const double (&vals)[NV], unsigned maxmask,
 }
 
 // Totals of NV values from nb partial slots each; every thread of the block
-// receives them.  The first wave sums slots lane, lane + 64, ... and then
-// across lanes, so the order depends on nb only, not on the block size.
+// receives them.  Slots are summed in 256 fixed strands (strand v: slots
+// v, v + 256, ...), whichever threads compute them, and the strands then in
+// a fixed tree, so the order depends on nb only, not on the block size.
 template <int NV>
 __device__ void reduce_partials(const double* __restrict__ part, int nb,
                                 unsigned maxmask, double (&out)[NV]) {
-  __shared__ double red[NV];
-  if (threadIdx.x < kWave) {
+  constexpr int kStrands = 4 * kWave;
+  __shared__ double red[NV][kStrands];
+  __shared__ double tot[NV];
+  for (int v0 = threadIdx.x; v0 < kStrands; v0 += blockDim.x) {
     double acc[NV];
 #pragma unroll
     for (int v = 0; v < NV; ++v)
       acc[v] = ((maxmask >> v) & 1u) ? -1.0e300 : 0.0;
-    for (int i = threadIdx.x; i < nb; i += kWave) {
+    for (int i = v0; i < nb; i += kStrands) {
       double x[NV];
 #pragma unroll
       for (int v = 0; v < NV; ++v) x[v] = part[(size_t)v * nb + i];
@@ -64,15 +67,24 @@ __device__ void reduce_partials(const double* __restrict__ part, int nb,
         acc[v] = ((maxmask >> v) & 1u) ? fmax(acc[v], x[v]) : acc[v] + x[v];
     }
 #pragma unroll
+    for (int v = 0; v < NV; ++v) red[v][v0] = acc[v];
+  }
+  __syncthreads();
+  if (threadIdx.x < kWave) {
+    const int l = threadIdx.x;
+#pragma unroll
     for (int v = 0; v < NV; ++v) {
       bool mx = (maxmask >> v) & 1u;
-      double s = mx ? wave_max(acc[v]) : wave_sum(acc[v]);
-      if (threadIdx.x == 0) red[v] = s;
+      double s = red[v][l];
+      for (int k = 1; k < 4; ++k)
+        s = mx ? fmax(s, red[v][l + k * kWave]) : s + red[v][l + k * kWave];
+      s = mx ? wave_max(s) : wave_sum(s);
+      if (l == 0) tot[v] = s;
     }
   }
   __syncthreads();
 #pragma unroll
-  for (int v = 0; v < NV; ++v) out[v] = red[v];
+  for (int v = 0; v < NV; ++v) out[v] = tot[v];
   __syncthreads();
 }
 
