@@ -11,6 +11,7 @@
 // LDS.  The vector updates are voxel-major (the waves of a block split the
 // frames of a 64-voxel tile) so that they can sum S_z and V_z per voxel; the
 // Jacobi diagonal is recomputed there from dW/du instead of being stored.
+#include <hip/hip_ext.h>
 #include <math.h>
 
 #include "launch.h"
@@ -458,35 +459,34 @@ hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
                           float* p_new, const float* dW, const Geom& g,
                           const Model& md, float* q, CgSums sums, int fixed,
                           double rtol, RedBuf rb, Scal* sc, hipStream_t s,
-                          int gn_it) {
+                          int gn_it, hipEvent_t ev0, hipEvent_t ev1) {
   CgTiles t = cg_tiles_2d(g, md.nK);
   const double* Sp_old = sums.Sp[(it + 1) & 1];
   const double* Vp_old = sums.Vp[(it + 1) & 1];
   double* Sp_new = sums.Sp[it & 1];
   double* Vp_new = sums.Vp[it & 1];
-  if (md.reg == 0)
-    cgt_hvp2_kernel<0><<<t.grid, kTX * kTY, 0, s>>>(
-        it, z, p_old, p_new, dW, g, md, q, sums.Sz, sums.Vz, Sp_old, Vp_old,
-        Sp_new, Vp_new, t.nreal, t.nfg, t.fpg, rb.region(kRegUpdate),
-        t.vox_grid, fixed, rtol, rb.region(kRegHv), sc, gn_it);
-  else
-    cgt_hvp2_kernel<1><<<t.grid, kTX * kTY, 0, s>>>(
-        it, z, p_old, p_new, dW, g, md, q, sums.Sz, sums.Vz, Sp_old, Vp_old,
-        Sp_new, Vp_new, t.nreal, t.nfg, t.fpg, rb.region(kRegUpdate),
-        t.vox_grid, fixed, rtol, rb.region(kRegHv), sc, gn_it);
+  // with events: the dispatch records its own start and end
+  hipExtLaunchKernelGGL(md.reg == 0 ? cgt_hvp2_kernel<0> : cgt_hvp2_kernel<1>,
+                        dim3(t.grid), dim3(kTX * kTY), 0, s, ev0, ev1, 0, it,
+                        z, p_old, p_new, dW, g, md, q, sums.Sz, sums.Vz,
+                        Sp_old, Vp_old, Sp_new, Vp_new, t.nreal, t.nfg, t.fpg,
+                        (const double*)rb.region(kRegUpdate), t.vox_grid,
+                        fixed, rtol, rb.region(kRegHv), sc, gn_it);
   return hipGetLastError();
 }
 
 hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
                              const float* dW, const Geom& g, const Model& md,
                              float* x, float* r, float* z, CgSums sums,
-                             RedBuf rb, Scal* sc, hipStream_t s, int gn_it) {
+                             RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
+                             hipEvent_t ev0, hipEvent_t ev1) {
   int nb = cgv_blocks(g), nt = cgv_threads(dim, md.nK);
   int hv_nb = cg_tiles_2d(g, md.nK).grid;
   if (dim == 2)
-    cgv_update_kernel<2><<<nb, nt, 0, s>>>(
-        it, p, q, dW, g, md, x, r, z, sums.Sz, sums.Vz, rb.region(kRegHv),
-        hv_nb, rb.region(kRegUpdate), sc, gn_it);
+    hipExtLaunchKernelGGL(cgv_update_kernel<2>, dim3(nb), dim3(nt), 0, s, ev0,
+                          ev1, 0, it, p, q, dW, g, md, x, r, z, sums.Sz,
+                          sums.Vz, (const double*)rb.region(kRegHv), hv_nb,
+                          rb.region(kRegUpdate), sc, gn_it);
   else
     cgv_update_kernel<3><<<nb, nt, 0, s>>>(
         it, p, q, dW, g, md, x, r, z, sums.Sz, sums.Vz, rb.region(kRegHv),

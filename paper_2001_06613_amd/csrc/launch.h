@@ -120,15 +120,19 @@ hipError_t launch_cgv_init(int dim, const float* grad, const float* dW,
                            const Geom& g, const Model& md, float* r, float* z,
                            CgSums sums, RedBuf rb, Scal* sc, hipStream_t s,
                            int gn_it, GNLog* log);
+// ev0/ev1 (optional): timed by the dispatch's own start/end timestamps
 hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
                           float* p_new, const float* dW, const Geom& g,
                           const Model& md, float* q, CgSums sums, int fixed,
                           double rtol, RedBuf rb, Scal* sc, hipStream_t s,
-                          int gn_it);
+                          int gn_it, hipEvent_t ev0 = nullptr,
+                          hipEvent_t ev1 = nullptr);
 hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
                              const float* dW, const Geom& g, const Model& md,
                              float* x, float* r, float* z, CgSums sums,
-                             RedBuf rb, Scal* sc, hipStream_t s, int gn_it);
+                             RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
+                             hipEvent_t ev0 = nullptr,
+                             hipEvent_t ev1 = nullptr);
 // Test entry: H v for a stored v (2-D); v is copied to vcopy on the way.
 hipError_t launch_hessvec_2d(const float* v, const float* dW, const Geom& g,
                              const Model& md, float* hv, float* vcopy,

@@ -272,6 +272,20 @@ void tbegin(stml_ctx* c, int kernel, int level, double vf, double bytes) {
   c->pending.push_back(r);
 }
 
+// Timing by the dispatch itself: a pending record whose events the
+// launcher passes to hipExtLaunchKernelGGL (no separate event packets).
+void tdispatch(stml_ctx* c, int kernel, int level, double vf, double bytes,
+               hipEvent_t* ev0, hipEvent_t* ev1) {
+  *ev0 = *ev1 = nullptr;
+  if (!((c->timing >> kernel) & 1u)) return;
+  stml_ctx::Rec r{kernel, level, vf, bytes, pooled_event(c),
+                  pooled_event(c)};
+  if (!r.a || !r.b) return;
+  *ev0 = r.a;
+  *ev1 = r.b;
+  c->pending.push_back(r);
+}
+
 void tend(stml_ctx* c, int kernel) {
   if (!((c->timing >> kernel) & 1u) || c->pending.empty()) return;
   (void)hipEventRecord(c->pending.back().b, c->stream);
@@ -321,6 +335,14 @@ double alg_bytes(int kernel, int D, int cg_it) {
 }
 
 #define TIMED(KERNEL, LEVEL, VF, CALL) TIMED_IT(KERNEL, LEVEL, VF, 0, CALL)
+// CALL names the events ev0_, ev1_ it passes to its launcher
+#define TIMED_DISPATCH(KERNEL, LEVEL, VF, CGIT, CALL)                   \
+  do {                                                                  \
+    hipEvent_t ev0_, ev1_;                                              \
+    tdispatch(c, KERNEL, LEVEL, VF,                                     \
+              (VF) * alg_bytes(KERNEL, c->d, CGIT), &ev0_, &ev1_);      \
+    HIP_OK(CALL);                                                       \
+  } while (0)
 #define TIMED_IT(KERNEL, LEVEL, VF, CGIT, CALL)                        \
   do {                                                                 \
     tbegin(c, KERNEL, LEVEL, VF, (VF) * alg_bytes(KERNEL, c->d, CGIT)); \
@@ -425,14 +447,15 @@ int enqueue_pcg(stml_ctx* c, int level, const Geom& g, const Model& md,
     for (int it = 0; it < c->o.cg_max; ++it) {
       float* pn = c->P[it & 1];
       const float* po = c->P[(it + 1) & 1];
-      TIMED_IT(STML_K_HESSVEC, level, vf, it,
-               launch_cgt_hvp(it, c->z, po, pn, c->dW, g, md, c->q, c->sums,
-                              c->o.parity_mode, c->o.cg_rtol, c->rb, c->sc,
-                              c->stream, gn_it));
-      TIMED_IT(STML_K_CG_UPDATE, level, vf, it,
-               launch_cgv_update(D, it, pn, c->q, c->dW, g, md, c->x, c->r,
-                                 c->z, c->sums, c->rb, c->sc, c->stream,
-                                 gn_it));
+      TIMED_DISPATCH(STML_K_HESSVEC, level, vf, it,
+                     launch_cgt_hvp(it, c->z, po, pn, c->dW, g, md, c->q,
+                                    c->sums, c->o.parity_mode, c->o.cg_rtol,
+                                    c->rb, c->sc, c->stream, gn_it, ev0_,
+                                    ev1_));
+      TIMED_DISPATCH(STML_K_CG_UPDATE, level, vf, it,
+                     launch_cgv_update(D, it, pn, c->q, c->dW, g, md, c->x,
+                                       c->r, c->z, c->sums, c->rb, c->sc,
+                                       c->stream, gn_it, ev0_, ev1_));
     }
     return STML_OK;
   }
