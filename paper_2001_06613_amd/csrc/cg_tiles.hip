@@ -25,6 +25,10 @@ constexpr int kHX = kTX + 4;       // with a 2-cell halo
 constexpr int kHY = kTY + 4;
 constexpr int kLX = kTX + 2;       // L p on a 1-cell halo
 constexpr int kLY = kTY + 2;
+// 3-D tiles: 16 (x) x 4 (y) x 4 (z) voxels, 2-cell halo for p, 1 for L p
+constexpr int kT3X = 16, kT3Y = 4, kT3Z = 4;
+constexpr int kH3X = kT3X + 4, kH3Y = kT3Y + 4, kH3Z = kT3Z + 4;
+constexpr int kL3X = kT3X + 2, kL3Y = kT3Y + 2, kL3Z = kT3Z + 2;
 
 // Frames of a voxel-major tile handled by this wave.
 __device__ __forceinline__ void wave_frames(int nK, int& j0, int& j1) {
@@ -409,6 +413,185 @@ __global__ __launch_bounds__(256) void cgt_hvp2_kernel(
                      fixed, rtol, part, sc, gn_it, grid_blk());
 }
 
+// 3-D Hessian product on p = z + beta p_old (it > 0) or p = z for one
+// 16 x 4 x 4 tile of a group of frames: the 2-D kernel's scheme with p
+// staged in LDS as float32 (exactly the values the kernel stores) and L p in
+// float64; the voxel sums S, V and the CG scalars as in 2-D.
+template <int REG>
+__device__ __forceinline__ void cgt_hvp3_body(
+    int it, const float* __restrict__ zv, const float* __restrict__ p_old,
+    float* __restrict__ p_new, const float* __restrict__ dW, const Geom& g,
+    const Model& md, float* __restrict__ q, const double* __restrict__ Sz,
+    const double* __restrict__ Vz, const double* __restrict__ Sp_old,
+    const double* __restrict__ Vp_old, double* __restrict__ Sp_new,
+    double* __restrict__ Vp_new, int nreal, int nfg, int fpg,
+    const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
+    double* __restrict__ part, Scal* __restrict__ sc, int gn_it, Blk blk) {
+  constexpr int D = 3;
+  __shared__ float P[D][kH3Z][kH3Y][kH3X];
+  __shared__ double L[REG ? D : 1][REG ? kL3Z : 1][REG ? kL3Y : 1]
+                     [REG ? kL3X : 1];
+  if (sc->done || gn_it >= sc->gn_stop) return;
+  double beta = 0.0;
+  if (it > 0) {
+    double t[2];
+    reduce_partials<2>(up_part, up_nb, 0u, t);
+    const double rz_old = sc->rzh[(it - 1) & 1];
+    bool conv = (!fixed && sqrt(t[1]) <= rtol * sc->r0) || t[0] == 0.0;
+    if (conv) {
+      if (blk.id == 0 && threadIdx.x == 0) sc->done = 1;
+      return;
+    }
+    beta = t[0] / rz_old;
+    if (blk.id == 0 && threadIdx.x == 0) {
+      sc->rzh[it & 1] = t[0];
+      sc->rr = t[1];
+      sc->beta = beta;
+    }
+  }
+  const float bf = (float)beta;
+  const int per_xcd = blk.n / kXCD;
+  const int bb = (blk.id % kXCD) * per_xcd + blk.id / kXCD;
+  double acc = 0.0;
+  if (bb < nreal) {
+    const int m0 = g.m[0], m1 = g.m[1], m2 = g.m[2];
+    const long long N = g.N;
+    const int tile = bb / nfg, fg = bb - (bb / nfg) * nfg;
+    const int ntx = (m2 + kT3X - 1) / kT3X, nty = (m1 + kT3Y - 1) / kT3Y;
+    const int x0 = (tile % ntx) * kT3X;
+    const int y0 = ((tile / ntx) % nty) * kT3Y;
+    const int z0 = (tile / ntx / nty) * kT3Z;
+    const int lx = threadIdx.x % kT3X, ly = (threadIdx.x / kT3X) % kT3Y,
+              lz = threadIdx.x / (kT3X * kT3Y);
+    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
+    const bool valid = x < m2 && y < m1 && z < m0;
+    const unsigned vox =
+        valid ? (unsigned)(((long long)z * m1 + y) * m2 + x) : 0u;
+    double sbar = 0.0, vbar[D] = {0.0, 0.0, 0.0};
+    if (valid) {
+      double S = Sz[vox], V[D];
+#pragma unroll
+      for (int a = 0; a < D; ++a) V[a] = Vz[(size_t)a * N + vox];
+      if (it > 0) {
+        S += beta * Sp_old[vox];
+#pragma unroll
+        for (int a = 0; a < D; ++a) V[a] += beta * Vp_old[(size_t)a * N + vox];
+      }
+      if (fg == 0) {
+        Sp_new[vox] = S;
+#pragma unroll
+        for (int a = 0; a < D; ++a) Vp_new[(size_t)a * N + vox] = V[a];
+      }
+      sbar = S * md.inv_nK;
+#pragma unroll
+      for (int a = 0; a < D; ++a) vbar[a] = V[a] * md.inv_nK;
+    }
+    const int jbeg = fg * fpg;
+    const int jend = jbeg + fpg < md.nK ? jbeg + fpg : md.nK;
+    for (int j = jbeg; j < jend; ++j) {
+      // stage p (replicate padding at the grid edge = clamped loads)
+      for (int i = threadIdx.x; i < kH3Z * kH3Y * kH3X; i += blockDim.x) {
+        int hz = i / (kH3Y * kH3X), r = i - hz * (kH3Y * kH3X);
+        int hy = r / kH3X, hx = r - hy * kH3X;
+        int gz = min(max(z0 - 2 + hz, 0), m0 - 1);
+        int gy = min(max(y0 - 2 + hy, 0), m1 - 1);
+        int gx = min(max(x0 - 2 + hx, 0), m2 - 1);
+        unsigned o = (unsigned)(((long long)gz * m1 + gy) * m2 + gx);
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          size_t plane = ((size_t)j * D + a) * N;
+          P[a][hz][hy][hx] =
+              it > 0 ? __builtin_fmaf(bf, p_old[plane + o], zv[plane + o])
+                     : zv[plane + o];
+        }
+      }
+      __syncthreads();
+      if (REG) {
+        // L p on the 1-cell halo; outside the grid it replicates the edge
+        for (int i = threadIdx.x; i < kL3Z * kL3Y * kL3X; i += blockDim.x) {
+          int qz = i / (kL3Y * kL3X), r = i - qz * (kL3Y * kL3X);
+          int qy = r / kL3X, qx = r - qy * kL3X;
+          int cz = min(max(z0 - 1 + qz, 0), m0 - 1) - z0 + 2;
+          int cy = min(max(y0 - 1 + qy, 0), m1 - 1) - y0 + 2;
+          int cx = min(max(x0 - 1 + qx, 0), m2 - 1) - x0 + 2;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            double c = P[a][cz][cy][cx];
+            L[a][qz][qy][qx] = ((double)P[a][cz - 1][cy][cx] - c) +
+                               ((double)P[a][cz + 1][cy][cx] - c) +
+                               ((double)P[a][cz][cy - 1][cx] - c) +
+                               ((double)P[a][cz][cy + 1][cx] - c) +
+                               ((double)P[a][cz][cy][cx - 1] - c) +
+                               ((double)P[a][cz][cy][cx + 1] - c);
+          }
+        }
+        __syncthreads();
+      }
+      if (valid) {
+        const int pz = lz + 2, py = ly + 2, px = lx + 2;
+        double pc[D], d[D], s = 0.0;
+        const size_t jb = (size_t)j * D * N + vox;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          pc[a] = P[a][pz][py][px];
+          d[a] = (double)dW[jb + (size_t)a * N];
+          s += d[a] * pc[a];
+        }
+        const double ds = md.data_c * (s - sbar);
+        // neighbours that leave the grid replicate this voxel: zero terms
+        const bool hd = z > 0, hu = z < m0 - 1, hn = y > 0, hs = y < m1 - 1,
+                   hw = x > 0, he = x < m2 - 1;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double btb;
+          if (REG) {
+            const int qz = lz + 1, qy = ly + 1, qx = lx + 1;
+            double c = L[a][qz][qy][qx];
+            btb = (hd ? L[a][qz - 1][qy][qx] - c : 0.0) +
+                  (hu ? L[a][qz + 1][qy][qx] - c : 0.0) +
+                  (hn ? L[a][qz][qy - 1][qx] - c : 0.0) +
+                  (hs ? L[a][qz][qy + 1][qx] - c : 0.0) +
+                  (hw ? L[a][qz][qy][qx - 1] - c : 0.0) +
+                  (he ? L[a][qz][qy][qx + 1] - c : 0.0);
+          } else {
+            double c = pc[a];
+            btb = -(((double)P[a][pz - 1][py][px] - c) +
+                    ((double)P[a][pz + 1][py][px] - c) +
+                    ((double)P[a][pz][py - 1][px] - c) +
+                    ((double)P[a][pz][py + 1][px] - c) +
+                    ((double)P[a][pz][py][px - 1] - c) +
+                    ((double)P[a][pz][py][px + 1] - c));
+          }
+          double h = ds * d[a] + md.alpha_hd * md.reg_scale * btb +
+                     md.lam_c * vbar[a];
+          float hf = (float)h;
+          q[jb + (size_t)a * N] = hf;
+          p_new[jb + (size_t)a * N] = (float)pc[a];
+          acc += pc[a] * (double)hf;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  double vals[1] = {acc};
+  block_partials<1>(vals, 0u, part, blk);
+}
+
+template <int REG>
+__global__ __launch_bounds__(256) void cgt_hvp3_kernel(
+    int it, const float* __restrict__ zv, const float* __restrict__ p_old,
+    float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
+    Model md, float* __restrict__ q, const double* __restrict__ Sz,
+    const double* __restrict__ Vz, const double* __restrict__ Sp_old,
+    const double* __restrict__ Vp_old, double* __restrict__ Sp_new,
+    double* __restrict__ Vp_new, int nreal, int nfg, int fpg,
+    const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
+    double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
+  cgt_hvp3_body<REG>(it, zv, p_old, p_new, dW, g, md, q, Sz, Vz, Sp_old,
+                     Vp_old, Sp_new, Vp_new, nreal, nfg, fpg, up_part, up_nb,
+                     fixed, rtol, part, sc, gn_it, grid_blk());
+}
+
 // ------------------------------------------------------------ launchers
 
 static int cgv_blocks(const Geom& g) {
@@ -425,10 +608,16 @@ static int cgv_threads(int dim, int nK) {
   return (G < 1 ? 1 : G) * kWave;
 }
 
-CgTiles cg_tiles_2d(const Geom& g, int nK) {
+int cg_tile_count(const Geom& g, int dim) {
+  if (dim == 2)
+    return ((g.m[1] + kTX - 1) / kTX) * ((g.m[0] + kTY - 1) / kTY);
+  return ((g.m[2] + kT3X - 1) / kT3X) * ((g.m[1] + kT3Y - 1) / kT3Y) *
+         ((g.m[0] + kT3Z - 1) / kT3Z);
+}
+
+CgTiles cg_tiles(const Geom& g, int nK, int dim) {
   CgTiles t;
-  int ntx = (g.m[1] + kTX - 1) / kTX, nty = (g.m[0] + kTY - 1) / kTY;
-  int ntiles = ntx * nty;
+  int ntiles = cg_tile_count(g, dim);
   int nfg = (g.hv_target + ntiles - 1) / ntiles;
   if (nfg > nK) nfg = nK;
   if (nfg < 1) nfg = 1;
@@ -460,18 +649,20 @@ hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
                           const Model& md, float* q, CgSums sums, int fixed,
                           double rtol, RedBuf rb, Scal* sc, hipStream_t s,
                           int gn_it, hipEvent_t ev0, hipEvent_t ev1) {
-  CgTiles t = cg_tiles_2d(g, md.nK);
+  const int dim = geom_dim(g);
+  CgTiles t = cg_tiles(g, md.nK, dim);
   const double* Sp_old = sums.Sp[(it + 1) & 1];
   const double* Vp_old = sums.Vp[(it + 1) & 1];
   double* Sp_new = sums.Sp[it & 1];
   double* Vp_new = sums.Vp[it & 1];
   // with events: the dispatch records its own start and end
-  hipExtLaunchKernelGGL(md.reg == 0 ? cgt_hvp2_kernel<0> : cgt_hvp2_kernel<1>,
-                        dim3(t.grid), dim3(kTX * kTY), 0, s, ev0, ev1, 0, it,
-                        z, p_old, p_new, dW, g, md, q, sums.Sz, sums.Vz,
-                        Sp_old, Vp_old, Sp_new, Vp_new, t.nreal, t.nfg, t.fpg,
-                        (const double*)rb.region(kRegUpdate), t.vox_grid,
-                        fixed, rtol, rb.region(kRegHv), sc, gn_it);
+  auto kern = dim == 2 ? (md.reg == 0 ? cgt_hvp2_kernel<0> : cgt_hvp2_kernel<1>)
+                       : (md.reg == 0 ? cgt_hvp3_kernel<0> : cgt_hvp3_kernel<1>);
+  hipExtLaunchKernelGGL(kern, dim3(t.grid), dim3(kTX * kTY), 0, s, ev0, ev1,
+                        0, it, z, p_old, p_new, dW, g, md, q, sums.Sz,
+                        sums.Vz, Sp_old, Vp_old, Sp_new, Vp_new, t.nreal,
+                        t.nfg, t.fpg, (const double*)rb.region(kRegUpdate),
+                        t.vox_grid, fixed, rtol, rb.region(kRegHv), sc, gn_it);
   return hipGetLastError();
 }
 
@@ -481,16 +672,12 @@ hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
                              RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
                              hipEvent_t ev0, hipEvent_t ev1) {
   int nb = cgv_blocks(g), nt = cgv_threads(dim, md.nK);
-  int hv_nb = cg_tiles_2d(g, md.nK).grid;
-  if (dim == 2)
-    hipExtLaunchKernelGGL(cgv_update_kernel<2>, dim3(nb), dim3(nt), 0, s, ev0,
-                          ev1, 0, it, p, q, dW, g, md, x, r, z, sums.Sz,
-                          sums.Vz, (const double*)rb.region(kRegHv), hv_nb,
-                          rb.region(kRegUpdate), sc, gn_it);
-  else
-    cgv_update_kernel<3><<<nb, nt, 0, s>>>(
-        it, p, q, dW, g, md, x, r, z, sums.Sz, sums.Vz, rb.region(kRegHv),
-        hv_nb, rb.region(kRegUpdate), sc, gn_it);
+  int hv_nb = cg_tiles(g, md.nK, dim).grid;
+  hipExtLaunchKernelGGL(dim == 2 ? cgv_update_kernel<2> : cgv_update_kernel<3>,
+                        dim3(nb), dim3(nt), 0, s, ev0, ev1, 0, it, p, q, dW, g,
+                        md, x, r, z, sums.Sz, sums.Vz,
+                        (const double*)rb.region(kRegHv), hv_nb,
+                        rb.region(kRegUpdate), sc, gn_it);
   return hipGetLastError();
 }
 
@@ -558,7 +745,7 @@ __global__ __launch_bounds__(1024) void cg_update_batch_kernel(JobSet js,
 }
 
 void job_shape(Job* job) {
-  job->ct = cg_tiles_2d(job->g, job->md.nK);
+  job->ct = cg_tiles(job->g, job->md.nK, 2);
   job->nb_tile = tile_blocks(job->g);
   job->nb_vox = job->ct.vox_grid;
   job->count = (long long)job->md.nK * 2 * job->g.N;
@@ -589,18 +776,22 @@ hipError_t batch_cg_update(const JobSet& js, int nvox, int it,
   return hipGetLastError();
 }
 
-hipError_t launch_hessvec_2d(const float* v, const float* dW, const Geom& g,
-                             const Model& md, float* hv, float* vcopy,
-                             CgSums sums, RedBuf rb, Scal* sc,
-                             hipStream_t s) {
-  int nb = cgv_blocks(g), nt = cgv_threads(2, md.nK);
-  cgv_sums_kernel<2><<<nb, nt, 0, s>>>(v, dW, g, md, sums.Sz, sums.Vz);
+hipError_t launch_hessvec_tiled(const float* v, const float* dW,
+                                const Geom& g, const Model& md, float* hv,
+                                float* vcopy, CgSums sums, RedBuf rb,
+                                Scal* sc, hipStream_t s) {
+  const int dim = geom_dim(g);
+  int nb = cgv_blocks(g), nt = cgv_threads(dim, md.nK);
+  if (dim == 2)
+    cgv_sums_kernel<2><<<nb, nt, 0, s>>>(v, dW, g, md, sums.Sz, sums.Vz);
+  else
+    cgv_sums_kernel<3><<<nb, nt, 0, s>>>(v, dW, g, md, sums.Sz, sums.Vz);
   hipError_t e = launch_gn_reset(sc, nullptr, 0, s);
   if (e != hipSuccess) return e;
   e = launch_cgt_hvp(0, v, nullptr, vcopy, dW, g, md, hv, sums, 1, 0.0, rb,
                      sc, s, 0);
   if (e != hipSuccess) return e;
-  return launch_finalize_vhv(rb.region(kRegHv), cg_tiles_2d(g, md.nK).grid,
+  return launch_finalize_vhv(rb.region(kRegHv), cg_tiles(g, md.nK, dim).grid,
                              sc, s);
 }
 

@@ -81,9 +81,6 @@ int tile_threads(int dim, int nK) {
 int eval_threads(int dim, int nK) {
   return (dim == 2 ? 8 : waves_for(nK, 4)) * kWave;
 }
-int hv_threads(int dim, int nK) {
-  return waves_for(nK, dim == 2 ? 16 : 4) * kWave;
-}
 
 #define STML_DIM_DISPATCH(dim, KERNEL, GRID, BLOCK, STREAM, ...)          \
   do {                                                                    \
@@ -333,159 +330,6 @@ __global__ __launch_bounds__(D == 2 ? 512 : 256) void eval_kernel(
   eval_body<D, REG>(T, u, K, g, md, grad, dWo, part, gn_it, sc, grid_blk());
 }
 
-// Plane-offset views of the accessors used by hv_tiles.
-struct Plane1 : Src1 {
-  __device__ __forceinline__ Plane1 plane(size_t off) const {
-    return Plane1{{a + off}};
-  }
-};
-struct PlaneLin : SrcLin {
-  __device__ __forceinline__ PlaneLin plane(size_t off) const {
-    return PlaneLin{{z + off, p + off, b}};
-  }
-};
-
-// Gauss-Newton Hessian product over this block's tiles, on the field f
-// (a stored vector, or the CG direction formed on the fly).  Sweep 1 sums
-// s_k = dW_k . v_k and v_k per voxel; sweep 2 re-reads dW_k and v_k (cache
-// hits) and writes
-//   (Hv)_k = 2h^D dW_k (s_k - mean s) + alpha h^D B^T B v_k
-//            + (2 lambda h^D / |K|) mean v.
-// If vout is set, the float32 value of v is stored there too.  Returns this
-// thread's share of v.Hv.
-template <int D, int REG, class F>
-__device__ double hv_tiles(const F& f, const float* dWp,
-                           const Geom& g, const Model& md,
-                           float* __restrict__ hv, float* __restrict__ vout) {
-  __shared__ double xs[kMaxChunks][kWave][1 + D];
-  const int lane = threadIdx.x & (kWave - 1);
-  const int w = wave_id();
-  const int G = blockDim.x / kWave;
-  const Chunk ch = frame_chunk(md.nK);
-  const long long N = g.N;
-  const long long ntiles = (N + kWave - 1) / kWave;
-  double acc = 0.0;
-  for (int it = 0;; ++it) {
-    long long tile = xcd_tile(ntiles, it);
-    if (tile < 0) break;
-    long long x = tile * kWave + lane;
-    bool valid = x < N;
-    Pos<D> p = make_pos<D>(g, valid ? x : N - 1);
-    double sS = 0.0, sV[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) sV[a] = 0.0;
-    for (int j = ch.j0; j < ch.j1; ++j) {
-      const F fj = f.plane((size_t)j * D * N);
-      const float* dj = dWp + (size_t)j * D * N;
-      double s = 0.0;
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        double vv = fj((unsigned)(a * N) + p.idx);
-        s += (double)dj[(size_t)a * N + p.idx] * vv;
-        sV[a] += vv;
-      }
-      sS += s;
-    }
-    xs[w][lane][0] = sS;
-#pragma unroll
-    for (int a = 0; a < D; ++a) xs[w][lane][1 + a] = sV[a];
-    __syncthreads();
-    double sb = 0.0, vb[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) vb[a] = 0.0;
-    for (int c = 0; c < G; ++c) {
-      sb += xs[c][lane][0];
-#pragma unroll
-      for (int a = 0; a < D; ++a) vb[a] += xs[c][lane][1 + a];
-    }
-    __syncthreads();
-    sb *= md.inv_nK;
-#pragma unroll
-    for (int a = 0; a < D; ++a) vb[a] *= md.inv_nK;
-    if (valid) {
-      for (int j = ch.j0; j < ch.j1; ++j) {
-        const F fj = f.plane((size_t)j * D * N);
-        const float* dj = dWp + (size_t)j * D * N;
-        double s = 0.0;
-#pragma unroll
-        for (int a = 0; a < D; ++a)
-          s += (double)dj[(size_t)a * N + p.idx] *
-               fj((unsigned)(a * N) + p.idx);
-        double ds = md.data_c * (s - sb);
-#pragma unroll 1
-        for (int a = 0; a < D; ++a) {
-          const F fja = fj.plane((size_t)a * N);
-          double btb, e, cen;
-          reg_terms<D, REG>(fja, p, g, btb, e, cen);
-          double vba = a == 0 ? vb[0] : (a == 1 ? vb[1] : vb[D - 1]);
-          double h = ds * (double)dj[(size_t)a * N + p.idx] +
-                     md.alpha_hd * md.reg_scale * btb + md.lam_c * vba;
-          float hf = (float)h;
-          size_t o = ((size_t)j * D + a) * N + p.idx;
-          hv[o] = hf;
-          if (vout) vout[o] = (float)cen;
-          acc += cen * (double)hf;
-        }
-      }
-    }
-  }
-  return acc;
-}
-
-// Test entry: Hv for a stored v; block partials of v.Hv.
-template <int D, int REG>
-__global__ __launch_bounds__(D == 2 ? 1024 : 256) void hessvec_kernel(
-    const float* __restrict__ v, const float* __restrict__ dW, Geom g,
-    Model md, float* __restrict__ hv, double* __restrict__ part) {
-  double vals[1] = {hv_tiles<D, REG>(Plane1{{v}}, dW, g, md, hv, nullptr)};
-  block_partials<1>(vals, 0u, part);
-}
-
-// ------------------------------------------------------------------ PCG
-//
-// Two kernels per CG iteration it (scalars stay on the device):
-//   pcg_hvp(it):   [it > 0] reduce r.z and r.r of update(it-1); stop if
-//                  converged; beta = rz_new / rz_old;
-//                  p_it = z + beta p_{it-1} (formed on the fly, stored),
-//                  q = H p_it, partial p.q
-//   pcg_update(it): reduce p.q; a = rz / p.q (stop on p.q <= 0);
-//                  x += a p, r -= a q, z = M^-1 r, partial r.z and r.r
-// r.z of iteration it lives in sc->rzh[it & 1]; a kernel reads one slot and
-// writes the other.  Every block of a consumer reduces the producer's
-// partial slots in the same order, so all blocks take the same decision.
-
-// CG start: M = diag(H) (Jacobi), x = 0, r = -g, z = M^-1 r.
-template <int D>
-__global__ __launch_bounds__(256) void pcg_init_kernel(
-    const float* __restrict__ grad, const float* __restrict__ dW, Geom g,
-    Model md, unsigned count, float* __restrict__ Mo, float* __restrict__ x,
-    float* __restrict__ r, float* __restrict__ z,
-    double* __restrict__ part, int gn_it, const Scal* __restrict__ sc) {
-  if (gn_it >= sc->gn_stop) return;
-  const unsigned N = (unsigned)g.N;
-  const unsigned stride = gridDim.x * blockDim.x;
-  double rz = 0.0, rr = 0.0;
-  for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < count;
-       e += stride) {
-    unsigned row = e / N;
-    Pos<D> pos = make_pos<D>(g, (long long)(e - row * N));
-    double d = (double)dW[e];
-    double M = md.mdiag_c * d * d +
-               md.alpha_hd * md.reg_scale * reg_diag_at<D>(pos, g, md.reg) +
-               md.pen_diag;
-    float rv = -grad[e];
-    float zv = (float)((double)rv / M);
-    Mo[e] = (float)M;
-    x[e] = 0.0f;
-    r[e] = rv;
-    z[e] = zv;
-    rz += (double)rv * (double)zv;
-    rr += (double)rv * (double)rv;
-  }
-  double vals[2] = {rz, rr};
-  block_partials<2>(vals, 0u, part);
-}
-
 // One block: the objective of the evaluation and the CG start scalars.
 __device__ __forceinline__ void finalize_start_body(
     const double* __restrict__ ev_part, int ev_nb,
@@ -517,108 +361,6 @@ __global__ __launch_bounds__(256) void finalize_start_kernel(
     const double* __restrict__ in_part, int in_nb, Model md,
     Scal* __restrict__ sc, int gn_it, GNLog* __restrict__ log) {
   finalize_start_body(ev_part, ev_nb, in_part, in_nb, md, sc, gn_it, log);
-}
-
-template <int D, int REG>
-__global__ __launch_bounds__(D == 2 ? 1024 : 256) void pcg_hvp_kernel(
-    int it, const float* __restrict__ z, const float* __restrict__ p_old,
-    float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
-    Model md, float* __restrict__ q, const double* __restrict__ up_part,
-    int up_nb, int fixed, double rtol, double* __restrict__ part,
-    Scal* __restrict__ sc, int gn_it) {
-  if (sc->done || gn_it >= sc->gn_stop) return;
-  double beta = 0.0;
-  if (it > 0) {
-    double t[2];
-    reduce_partials<2>(up_part, up_nb, 0u, t);
-    const double rz_old = sc->rzh[(it - 1) & 1];
-    bool conv = (!fixed && sqrt(t[1]) <= rtol * sc->r0) || t[0] == 0.0;
-    if (conv) {
-      if (blockIdx.x == 0 && threadIdx.x == 0) sc->done = 1;
-      return;
-    }
-    beta = t[0] / rz_old;
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc->rzh[it & 1] = t[0];
-      sc->rr = t[1];
-      sc->beta = beta;
-    }
-  }
-  double acc;
-  if (it > 0)
-    acc = hv_tiles<D, REG>(PlaneLin{{z, p_old, (float)beta}}, dW, g, md, q, p_new);
-  else
-    acc = hv_tiles<D, REG>(Plane1{{z}}, dW, g, md, q, p_new);
-  double vals[1] = {acc};
-  block_partials<1>(vals, 0u, part);
-}
-
-__device__ __forceinline__ void cg_upd1(float& xv, float& rv, float& zv,
-                                        float pv, float qv, float Mv,
-                                        double a, double& rz, double& rr) {
-  xv = (float)((double)xv + a * (double)pv);
-  rv = (float)((double)rv - a * (double)qv);
-  zv = (float)((double)rv / (double)Mv);
-  rz += (double)rv * (double)zv;
-  rr += (double)rv * (double)rv;
-}
-
-template <bool V4>
-__global__ __launch_bounds__(256) void pcg_update_kernel(
-    int it, const float* __restrict__ p, const float* __restrict__ q,
-    const float* __restrict__ M, unsigned count, float* __restrict__ x,
-    float* __restrict__ r, float* __restrict__ z,
-    const double* __restrict__ hv_part, int hv_nb,
-    double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
-  if (sc->done || gn_it >= sc->gn_stop) return;
-  double t[1];
-  reduce_partials<1>(hv_part, hv_nb, 0u, t);
-  const double pq = t[0];
-  if (!(pq > 0.0)) {
-    if (blockIdx.x == 0 && threadIdx.x == 0) {
-      sc->pq = pq;
-      sc->done = 2;
-    }
-    return;
-  }
-  const double a = sc->rzh[it & 1] / pq;
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    sc->pq = pq;
-    sc->a = a;
-    sc->iters = it + 1;
-  }
-  const unsigned stride = gridDim.x * blockDim.x;
-  double rz = 0.0, rr = 0.0;
-  if (V4) {
-    const unsigned c4 = count / 4;
-    for (unsigned i = blockIdx.x * blockDim.x + threadIdx.x; i < c4;
-         i += stride) {
-      float4 pv = reinterpret_cast<const float4*>(p)[i];
-      float4 qv = reinterpret_cast<const float4*>(q)[i];
-      float4 Mv = reinterpret_cast<const float4*>(M)[i];
-      float4 xv = reinterpret_cast<float4*>(x)[i];
-      float4 rv = reinterpret_cast<float4*>(r)[i];
-      float4 zv;
-      cg_upd1(xv.x, rv.x, zv.x, pv.x, qv.x, Mv.x, a, rz, rr);
-      cg_upd1(xv.y, rv.y, zv.y, pv.y, qv.y, Mv.y, a, rz, rr);
-      cg_upd1(xv.z, rv.z, zv.z, pv.z, qv.z, Mv.z, a, rz, rr);
-      cg_upd1(xv.w, rv.w, zv.w, pv.w, qv.w, Mv.w, a, rz, rr);
-      reinterpret_cast<float4*>(x)[i] = xv;
-      reinterpret_cast<float4*>(r)[i] = rv;
-      reinterpret_cast<float4*>(z)[i] = zv;
-    }
-  } else {
-    for (unsigned e = blockIdx.x * blockDim.x + threadIdx.x; e < count;
-         e += stride) {
-      float xv = x[e], rv = r[e], zv;
-      cg_upd1(xv, rv, zv, p[e], q[e], M[e], a, rz, rr);
-      x[e] = xv;
-      r[e] = rv;
-      z[e] = zv;
-    }
-  }
-  double vals[2] = {rz, rr};
-  block_partials<2>(vals, 0u, part);
 }
 
 struct Steps {
@@ -1176,65 +918,6 @@ hipError_t launch_eval(int dim, const float* T, const float* u, const int* K,
                      grad, dW, part, gn_it, gate);
   if (finalize)
     finalize_eval_kernel<<<1, 256, 0, s>>>(part, nb, md, sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_hessvec(int dim, const float* v, const float* dW,
-                          const Geom& g, const Model& md, float* hv,
-                          RedBuf rb, Scal* sc, hipStream_t s) {
-  int nb = tile_blocks(g), nt = hv_threads(dim, md.nK);
-  double* part = rb.region(kRegTest);
-  STML_TILE_DISPATCH(dim, md.reg, hessvec_kernel, nb, nt, s, v, dW, g, md, hv, part);
-  finalize_vhv_kernel<<<1, 256, 0, s>>>(part, nb, sc);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_init(int dim, const float* grad, const float* dW,
-                           const Geom& g, const Model& md, float* M, float* x,
-                           float* r, float* z, RedBuf rb, Scal* sc,
-                           hipStream_t s, int gn_it, GNLog* log) {
-  unsigned count = (unsigned)((size_t)md.nK * dim * g.N);
-  int nb = elem_blocks(count);
-  double* part = rb.region(kRegInit);
-  if (dim == 2)
-    pcg_init_kernel<2><<<nb, 256, 0, s>>>(grad, dW, g, md, count, M, x, r, z,
-                                          part, gn_it, sc);
-  else
-    pcg_init_kernel<3><<<nb, 256, 0, s>>>(grad, dW, g, md, count, M, x, r, z,
-                                          part, gn_it, sc);
-  finalize_start_kernel<<<1, 256, 0, s>>>(rb.region(kRegEval), tile_blocks(g),
-                                          part, nb, md, sc, gn_it, log);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_hvp(int dim, int it, const float* z, const float* p_old,
-                          float* p_new, const float* dW, const Geom& g,
-                          const Model& md, float* q, int fixed, double rtol,
-                          RedBuf rb, Scal* sc, hipStream_t s, int gn_it) {
-  int nb = tile_blocks(g), nt = hv_threads(dim, md.nK);
-  size_t count = (size_t)md.nK * dim * g.N;
-  int up_nb = elem_blocks(count, (g.N % 4) == 0 ? 4 : 1);
-  STML_TILE_DISPATCH(dim, md.reg, pcg_hvp_kernel, nb, nt, s, it, z, p_old, p_new, dW,
-                    g, md, q, rb.region(kRegUpdate), up_nb, fixed, rtol,
-                    rb.region(kRegHv), sc, gn_it);
-  return hipGetLastError();
-}
-
-hipError_t launch_pcg_update(int it, const float* p, const float* q,
-                             const float* M, size_t count, const Geom& g,
-                             float* x, float* r, float* z, RedBuf rb,
-                             Scal* sc, hipStream_t s, int gn_it) {
-  bool v4 = (g.N % 4) == 0;
-  int nb = elem_blocks(count, v4 ? 4 : 1);
-  int hv_nb = tile_blocks(g);
-  if (v4)
-    pcg_update_kernel<true><<<nb, 256, 0, s>>>(
-        it, p, q, M, (unsigned)count, x, r, z, rb.region(kRegHv), hv_nb,
-        rb.region(kRegUpdate), sc, gn_it);
-  else
-    pcg_update_kernel<false><<<nb, 256, 0, s>>>(
-        it, p, q, M, (unsigned)count, x, r, z, rb.region(kRegHv), hv_nb,
-        rb.region(kRegUpdate), sc, gn_it);
   return hipGetLastError();
 }
 

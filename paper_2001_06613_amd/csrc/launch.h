@@ -42,7 +42,6 @@ Model make_model(int dim, double h, int nK, double alpha, double lambda,
 int tile_blocks(const Geom& g);
 int tile_threads(int dim, int nK);
 int eval_threads(int dim, int nK);
-int hv_threads(int dim, int nK);
 
 hipError_t launch_fill(float* p, size_t count, float v, hipStream_t s);
 hipError_t launch_check_finite(const float* p, size_t count, Scal* sc,
@@ -53,33 +52,13 @@ hipError_t launch_prolong(int dim, const float* coarse, float* fine,
                           int fields, const Geom& gc, const Geom& gf,
                           hipStream_t s);
 
-// finalize = false leaves the partials for launch_pcg_init to reduce.
+// finalize = false leaves the partials for the CG start to reduce.
 // gn_it: Gauss-Newton iteration this launch belongs to (ignored when
 // finalize is set); the kernel does nothing if gn_it >= sc->gn_stop.
 hipError_t launch_eval(int dim, const float* T, const float* u, const int* K,
                        const Geom& g, const Model& md, float* grad,
                        float* dW, RedBuf rb, Scal* sc, hipStream_t s,
                        bool finalize, int gn_it);
-hipError_t launch_hessvec(int dim, const float* v, const float* dW,
-                          const Geom& g, const Model& md, float* hv,
-                          RedBuf rb, Scal* sc, hipStream_t s);
-
-// PCG on H delta = -g (device-resident scalars in sc).
-// Also reduces the evaluation's partials (J, D, S, P into sc).
-hipError_t launch_pcg_init(int dim, const float* grad, const float* dW,
-                           const Geom& g, const Model& md, float* M, float* x,
-                           float* r, float* z, RedBuf rb, Scal* sc,
-                           hipStream_t s, int gn_it, GNLog* log);
-// CG iteration it: p_new = z + beta p_old (it > 0; p_new = z at it = 0),
-// q = H p_new; then x, r, z updates.
-hipError_t launch_pcg_hvp(int dim, int it, const float* z, const float* p_old,
-                          float* p_new, const float* dW, const Geom& g,
-                          const Model& md, float* q, int fixed, double rtol,
-                          RedBuf rb, Scal* sc, hipStream_t s, int gn_it);
-hipError_t launch_pcg_update(int it, const float* p, const float* q,
-                             const float* M, size_t count, const Geom& g,
-                             float* x, float* r, float* z, RedBuf rb,
-                             Scal* sc, hipStream_t s, int gn_it);
 
 // Objective at u + t_i delta for kTrialSteps values of t (t = 0 allowed),
 // g.delta and max |delta|, for line-search sweep ls of iteration gn_it.
@@ -115,7 +94,9 @@ struct CgSums {
 struct CgTiles {             // launch shape of the 2-D Hessian product
   int nreal, nfg, fpg, grid, vox_grid;
 };
-CgTiles cg_tiles_2d(const Geom& g, int nK);
+// Launch shape of the Hessian product (2-D: 64 x 4 tiles, 3-D: 16 x 4 x 4)
+CgTiles cg_tiles(const Geom& g, int nK, int dim);
+int cg_tile_count(const Geom& g, int dim);
 hipError_t launch_cgv_init(int dim, const float* grad, const float* dW,
                            const Geom& g, const Model& md, float* r, float* z,
                            CgSums sums, RedBuf rb, Scal* sc, hipStream_t s,
@@ -133,11 +114,12 @@ hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
                              RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
                              hipEvent_t ev0 = nullptr,
                              hipEvent_t ev1 = nullptr);
-// Test entry: H v for a stored v (2-D); v is copied to vcopy on the way.
-hipError_t launch_hessvec_2d(const float* v, const float* dW, const Geom& g,
-                             const Model& md, float* hv, float* vcopy,
-                             CgSums sums, RedBuf rb, Scal* sc,
-                             hipStream_t s);
+// Test entry: H v for a stored v through the tiled Hessian product;
+// v is copied to vcopy on the way.
+hipError_t launch_hessvec_tiled(const float* v, const float* dW,
+                                const Geom& g, const Model& md, float* hv,
+                                float* vcopy, CgSums sums, RedBuf rb,
+                                Scal* sc, hipStream_t s);
 
 hipError_t launch_linear_predict(const float* Y, float* Z, float* Yout,
                                  LinTab tab, int n, int dim, long long N,

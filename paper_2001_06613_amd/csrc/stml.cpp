@@ -61,7 +61,7 @@ struct stml_ctx {
   std::vector<std::vector<int>> K;      // host copies of K_q
   // solver scratch, compact [nK][D][N_finest]
   float *g = nullptr, *dW = nullptr, *x = nullptr, *r = nullptr,
-        *z = nullptr, *q = nullptr, *M = nullptr;
+        *z = nullptr, *q = nullptr;
   float* P[2] = {nullptr, nullptr};      // CG directions, ping-pong
   CgSums sums{};                         // per-voxel cross-frame sums
   RedBuf rb{};
@@ -179,7 +179,6 @@ size_t layout(stml_ctx* c, char* base) {
   c->P[1] = lo.take<float>(vec);
   c->z = lo.take<float>(vec);
   c->q = lo.take<float>(vec);
-  c->M = lo.take<float>(vec);
   if (c->o.predictor == 1) c->ureg = lo.take<float>(vec);
   {
     size_t NF = (size_t)c->N[c->L - 1];
@@ -227,11 +226,14 @@ bool setup_dims(stml_ctx* c, const stml_opts* o, int n, const int* extent) {
   // compact vectors index elements with 64-bit offsets, but the element
   // kernels decode the frame index from 32-bit rows
   if ((double)n * o->dim * (double)c->N[c->L - 1] > 2.0e9) return false;
-  // the 2-D Hessian product runs one block per 64 x 4 tile at least, and
-  // its partials must fit one reduction region
-  if (o->dim == 2) {
+  // the Hessian product runs one block per 64 x 4 (3-D: 16 x 4 x 4) tile
+  // at least, and its partials must fit one reduction region
+  {
     const std::vector<int>& e = c->ext[c->L - 1];
-    long long tiles = (long long)((e[1] + 63) / 64) * ((e[0] + 3) / 4);
+    long long tiles =
+        o->dim == 2 ? (long long)((e[1] + 63) / 64) * ((e[0] + 3) / 4)
+                    : (long long)((e[2] + 15) / 16) * ((e[1] + 3) / 4) *
+                          ((e[0] + 3) / 4);
     if (tiles > (long long)kRegionSlots - 8192 - 8) return false;
   }
   c->K = temporal_sets(n, c->T1);
@@ -294,8 +296,10 @@ void tend(stml_ctx* c, int kernel) {
 void tresolve(stml_ctx* c) {
   for (auto& r : c->pending) {
     float ms = 0.0f;
-    if (hipEventSynchronize(r.b) == hipSuccess &&
-        hipEventElapsedTime(&ms, r.a, r.b) == hipSuccess) {
+    if (hipEventSynchronize(r.b) != hipSuccess ||
+        hipEventElapsedTime(&ms, r.a, r.b) != hipSuccess) {
+      (void)hipGetLastError();   // an unrecorded pair: not an error here
+    } else {
       auto& st = c->kstats[{r.kernel, r.level}];
       st.ms += ms;
       st.vf += r.vf;
@@ -438,40 +442,22 @@ int stage_frames(stml_ctx* c, const int* frames, int nk) {
 int enqueue_pcg(stml_ctx* c, int level, const Geom& g, const Model& md,
                 int gn_it) {
   const int D = c->d;
-  const size_t count = (size_t)md.nK * D * g.N;
   const double vf = (double)md.nK * g.N;
-  if (D == 2) {
-    TIMED(STML_K_CG_INIT, level, vf,
-          launch_cgv_init(D, c->g, c->dW, g, md, c->r, c->z, c->sums, c->rb,
-                          c->sc, c->stream, gn_it, c->gnlog));
-    for (int it = 0; it < c->o.cg_max; ++it) {
-      float* pn = c->P[it & 1];
-      const float* po = c->P[(it + 1) & 1];
-      TIMED_DISPATCH(STML_K_HESSVEC, level, vf, it,
-                     launch_cgt_hvp(it, c->z, po, pn, c->dW, g, md, c->q,
-                                    c->sums, c->o.parity_mode, c->o.cg_rtol,
-                                    c->rb, c->sc, c->stream, gn_it, ev0_,
-                                    ev1_));
-      TIMED_DISPATCH(STML_K_CG_UPDATE, level, vf, it,
-                     launch_cgv_update(D, it, pn, c->q, c->dW, g, md, c->x,
-                                       c->r, c->z, c->sums, c->rb, c->sc,
-                                       c->stream, gn_it, ev0_, ev1_));
-    }
-    return STML_OK;
-  }
   TIMED(STML_K_CG_INIT, level, vf,
-        launch_pcg_init(D, c->g, c->dW, g, md, c->M, c->x, c->r, c->z, c->rb,
+        launch_cgv_init(D, c->g, c->dW, g, md, c->r, c->z, c->sums, c->rb,
                         c->sc, c->stream, gn_it, c->gnlog));
   for (int it = 0; it < c->o.cg_max; ++it) {
     float* pn = c->P[it & 1];
     const float* po = c->P[(it + 1) & 1];
-    TIMED(STML_K_HESSVEC, level, vf,
-          launch_pcg_hvp(D, it, c->z, po, pn, c->dW, g, md, c->q,
-                         c->o.parity_mode, c->o.cg_rtol, c->rb, c->sc,
-                         c->stream, gn_it));
-    TIMED(STML_K_CG_UPDATE, level, vf,
-          launch_pcg_update(it, pn, c->q, c->M, count, g, c->x, c->r, c->z,
-                            c->rb, c->sc, c->stream, gn_it));
+    TIMED_DISPATCH(STML_K_HESSVEC, level, vf, it,
+                   launch_cgt_hvp(it, c->z, po, pn, c->dW, g, md, c->q,
+                                  c->sums, c->o.parity_mode, c->o.cg_rtol,
+                                  c->rb, c->sc, c->stream, gn_it, ev0_,
+                                  ev1_));
+    TIMED_DISPATCH(STML_K_CG_UPDATE, level, vf, it,
+                   launch_cgv_update(D, it, pn, c->q, c->dW, g, md, c->x,
+                                     c->r, c->z, c->sums, c->rb, c->sc,
+                                     c->stream, gn_it, ev0_, ev1_));
   }
   return STML_OK;
 }
@@ -1040,14 +1026,9 @@ int stml_hessvec(stml_ctx* c, int level, const int* frames, int nk,
   Model md = model_of(c, level, nk);
   HIP_OK(launch_eval(c->d, c->lv[level].T, u, c->kbuf, g, md, c->g, c->dW,
                      c->rb, c->sc, c->stream, true, 0));
-  if (c->d == 2)
-    TIMED(STML_K_HESSVEC, level, (double)nk * g.N,
-          launch_hessvec_2d(v, c->dW, g, md, hv, c->P[0], c->sums, c->rb,
-                            c->sc, c->stream));
-  else
-    TIMED(STML_K_HESSVEC, level, (double)nk * g.N,
-          launch_hessvec(c->d, v, c->dW, g, md, hv, c->rb, c->sc,
-                         c->stream));
+  TIMED(STML_K_HESSVEC, level, (double)nk * g.N,
+        launch_hessvec_tiled(v, c->dW, g, md, hv, c->P[0], c->sums, c->rb,
+                             c->sc, c->stream));
   rc = read_scal(c);
   if (rc) return rc;
   if (vHv) *vHv = c->hsc->vHv;

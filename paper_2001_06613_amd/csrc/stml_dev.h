@@ -30,6 +30,10 @@ struct Geom {
   int tile_cap, vox_cap, hv_target;
 };
 
+__host__ __device__ inline int geom_dim(const Geom& g) {
+  return g.s[2] == 1 ? 3 : 2;
+}
+
 // Constants of the model on one level and subset.
 struct Model {
   double hd;           // h^D
@@ -120,9 +124,7 @@ __device__ __forceinline__ Pos<D> make_pos(const Geom& g, long long x) {
 // voxel itself (replicate padding), which turns the plain Laplacian into the
 // Neumann graph Laplacian L.  All arithmetic is float64 on float32 loads.
 
-// Field accessors: a stored float32 plane, or the CG direction
-// p = z + beta p_old formed on the fly and rounded to float32 exactly as the
-// kernel that stores it rounds it.
+// Field accessor of a stored float32 plane.
 struct Src1 {
   const float* __restrict__ a;
   __device__ __forceinline__ float ld(unsigned i) const { return a[i]; }
@@ -130,18 +132,6 @@ struct Src1 {
     return (double)a[i];
   }
 };
-struct SrcLin {
-  const float* __restrict__ z;
-  const float* __restrict__ p;
-  float b;
-  __device__ __forceinline__ float ld(unsigned i) const {
-    return __builtin_fmaf(b, p[i], z[i]);
-  }
-  __device__ __forceinline__ double operator()(unsigned i) const {
-    return (double)ld(i);
-  }
-};
-
 // Offsets (in elements) of the clamped neighbours at -2, -1, +1, +2 along
 // every axis, and whether the -1 / +1 neighbour exists.
 template <int D>

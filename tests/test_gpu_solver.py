@@ -198,3 +198,56 @@ def test_large_level_parity():
     hv, _ = st.hessvec(3, K, torch.from_numpy(u), torch.from_numpy(v))
     Hv_ref = oracle.hessvec(ref["dW"].astype(np.float32), v, 1.0, par)
     assert _rel(hv.cpu().numpy(), Hv_ref) <= 1e-5
+
+
+def _volume(n, ext, seed):
+    return synth.sinusoid_sequence(n, ext, 1.5, 1, seed)[0]
+
+
+@pytest.mark.parametrize("reg", ["diffusion", "curvature"])
+def test_gn_direction_parity_3d(reg):
+    ext = (10, 12, 18)             # ragged against 16 x 4 x 4 tiles
+    n = 4
+    frames = _volume(n, ext, 21)
+    o = default_opts(dim=3, n_spatial=1, n_temporal=2, reg=reg, cg_max=8,
+                     parity_mode=True)
+    st = STML(n, ext, opts=o)
+    st.set_sequence(torch.from_numpy(frames).cuda())
+    u = synth.random_displacement(ext, n, 1.2, 4)
+    K = [0, 1, 3]
+    print(f"gn_direction 3d {reg}", flush=True)
+    delta, iters = st.gn_direction(0, K, torch.from_numpy(u))
+    par = oracle.ModelParams(reg=reg)
+    ref = oracle.objective(frames, u, K, 1.0, par)
+    diag = oracle.jacobi_diag(ref["dW"], 1.0, par)
+    d_ref, it_ref, _ = oracle.pcg(
+        lambda v: oracle.hessvec(ref["dW"], v, 1.0, par), diag, -ref["g"], 8,
+        fixed=True)
+    assert iters == it_ref == 8
+    d = delta.cpu().numpy()
+    assert _rel(d, d_ref) <= 1e-4
+    assert np.abs(d - d_ref).max() <= 1e-3
+
+
+@pytest.mark.parametrize("reg", ["diffusion", "curvature"])
+def test_register_level_parity_3d(reg):
+    ext = (10, 12, 18)
+    n = 4
+    frames = _volume(n, ext, 22)
+    kw = dict(dim=3, n_spatial=1, n_temporal=2, reg=reg, gn_max=3, cg_max=6,
+              parity_mode=True)
+    st = STML(n, ext, opts=default_opts(**kw))
+    st.set_sequence(torch.from_numpy(frames).cuda())
+    st.predict(0, 0)
+    st.register_level(0, 0)
+    ost = oracle.stml.STMLState(frames, oracle.STMLOptions(
+        **{k: v for k, v in kw.items() if k != "dim"}))
+    ost.predict(0, 0)
+    ost.register_level(0, 0)
+    lg, olg = st.logs()[0], ost.log[0]
+    print("3d steps", lg["steps"], olg["steps"], flush=True)
+    assert lg["steps"] == olg["steps"]
+    assert lg["cg"] == olg["cg"]
+    assert lg["J"] == pytest.approx(olg["J"], rel=1e-5)
+    u = st.get_displacements(0).cpu().numpy()
+    assert np.abs(u - ost.Y[0]).max() <= 1e-3
