@@ -45,6 +45,8 @@ DOMINANT_NAME = "cgv_update_kernel<2> (CG vector update, all levels)"
 WORKLOAD = dict(n=64, extent=(256, 256), n_spatial=4, n_temporal=3,
                 reg="curvature", alpha=0.1, lam=1e-2, beta=1e-5, gn_max=5,
                 cg_max=10, parity_mode=True)
+VOLUME = dict(n=32, extent=(128, 128, 64), n_spatial=3, n_temporal=3,
+              gn_max=5, cg_max=10)
 
 
 def _units(logs, extents):
@@ -150,6 +152,90 @@ def batched_comparison(seqs, log):
             "tuning": {k: cfg[k] for k in autotune.DEFAULT}}
 
 
+def _gen_volume_sequence(args):
+    from paper_2001_06613_amd import synth
+
+    n, seed = args
+    if seed == 3:
+        return synth.config_volume(seed)[0]
+    return synth.sinusoid_sequence(n, VOLUME["extent"], 4.0, 3, seed)[0]
+
+
+def volume_comparison(single, seqs, log):
+    """3-D: the 32-frame 128x128x64 volume solved alone (3 spatial x 3
+    temporal levels, curvature alpha 0.1, fixed 5 GN x 10 CG), then four
+    volumes of 24..40 frames looped and batched (bit-identical results)."""
+    import torch
+    from paper_2001_06613_amd.binding import STML, Batch, default_opts
+
+    v = VOLUME
+    opts = default_opts(dim=3, n_spatial=v["n_spatial"],
+                        n_temporal=v["n_temporal"], reg="curvature",
+                        alpha=0.1, gn_max=v["gn_max"], cg_max=v["cg_max"],
+                        parity_mode=True)
+
+    def sync_time(fn):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        fn()
+        torch.cuda.synchronize()
+        return time.perf_counter() - t0
+
+    st = STML(single.shape[0], single.shape[1:], opts=opts)
+    fr = torch.from_numpy(single).cuda()
+    solve = lambda: (st.set_sequence(fr), st.run())  # noqa: E731
+    solve()
+    t_single = min(sync_time(solve) for _ in range(2))
+    ext = [st.level_extent(l) for l in range(v["n_spatial"])]
+    units = _units(st.logs(), ext)
+    st.timing(True)
+    solve()
+    st.timing(False)
+    kern = {}
+    for k in ("eval", "hessvec", "cg_update"):
+        t = st.timing_get(k)
+        kern[k] = {"ms": round(t["ms"], 3), "launches": t["launches"],
+                   "GBs": round(t["bytes"] / (t["ms"] * 1e-3) / 1e9, 1)}
+    st.close()
+    del fr
+    log("volume: single done")
+
+    sts = [STML(f.shape[0], f.shape[1:], opts=opts) for f in seqs]
+    dev = [torch.from_numpy(f).cuda() for f in seqs]
+    B = Batch(sts)
+
+    def run_loop():
+        _set_all(sts, dev)
+        for s in sts:
+            s.run()
+
+    def run_batch():
+        _set_all(sts, dev)
+        B.run()
+
+    run_loop()
+    t_loop = sync_time(run_loop)
+    ref = [s.get_displacements().cpu() for s in sts]
+    run_batch()
+    t_batch = sync_time(run_batch)
+    same = all(torch.equal(r, s.get_displacements().cpu())
+               for r, s in zip(ref, sts))
+    log("volume: batch done")
+    B.close()
+    for s in sts:
+        s.close()
+    return {"workload": "32 x 128x128x64 volumes, 3 spatial x 3 temporal "
+                        "levels, curvature alpha 0.1, fixed 5 GN x 10 CG",
+            "solve_ms": round(1e3 * t_single, 1),
+            "value": round(units / t_single / 1e9, 3),
+            "unit": "Gvoxel-frames/s", "kernels_one_solve": kern,
+            "batch": {"frames": [int(f.shape[0]) for f in seqs],
+                      "looped_ms": round(1e3 * t_loop, 1),
+                      "batched_ms": round(1e3 * t_batch, 1),
+                      "speedup": round(t_loop / t_batch, 3),
+                      "identical": same}}
+
+
 def _set_all(sts, dev):
     for s, f in zip(sts, dev):
         s.set_sequence(f)
@@ -195,6 +281,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="one solve and a copy of known size (counter runs)")
     args = ap.parse_args()
@@ -210,14 +297,19 @@ def main():
     # workers before the GPU is touched
     from paper_2001_06613_amd import learned, synth
 
-    batch_seqs, learned_seqs = None, None
-    if not args.pmc_probe and not args.no_batch:
-        import multiprocessing as mp
+    import multiprocessing as mp
 
+    batch_seqs, learned_seqs, volume_seqs = None, None, None
+    if not args.pmc_probe and not args.no_batch:
         with mp.get_context("fork").Pool(16) as pool:
             batch_seqs = pool.map(_gen_batch_sequence, synth.config_batch(),
                                   chunksize=1)
         log("batch: sequences generated")
+    if not args.pmc_probe and not args.no_volume:
+        jobs = [(VOLUME["n"], 3)] + synth.config_volume_batch()
+        with mp.get_context("fork").Pool(len(jobs)) as pool:
+            volume_seqs = pool.map(_gen_volume_sequence, jobs, chunksize=1)
+        log("volume: sequences generated")
     if not args.pmc_probe and not args.no_learned:
         learned_seqs = list(learned.generate(range(20000, 20004), workers=4))
 
@@ -323,6 +415,9 @@ def main():
         out["batched"] = batched_comparison(batch_seqs, log)
     if learned_seqs is not None:
         out["learned"] = learned_comparison(learned_seqs, log)
+    if volume_seqs is not None:
+        out["volume"] = volume_comparison(volume_seqs[0], volume_seqs[1:],
+                                          log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frames)
     print(json.dumps(out))

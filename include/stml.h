@@ -315,7 +315,7 @@ int stml_net_train_step(stml_net* net, double lr, double* loss);
  * otherwise); the net runs on its own stream and must outlive its use. */
 int stml_set_predictor_net(stml_ctx* ctx, stml_net* net);
 
-/* --- batching: several 2-D sequences in shared launches ------------------
+/* --- batching: several sequences in shared launches ----------------------
  * A batch registers the sequences of several contexts together: each
  * Gauss-Newton iteration of a stage (level, q) runs as one launch per
  * kernel over the tiles of every sequence (a persistent grid whose blocks
@@ -325,8 +325,9 @@ int stml_set_predictor_net(stml_ctx* ctx, stml_net* net);
  * stay on the device; one iteration is captured in a HIP graph and
  * replayed.  The contexts keep their own workspaces, sequences, logs and
  * displacements (read them with stml_get_displacements / stml_get_log).
- * All contexts: dim 2, the same numbers of levels, regulariser, gn_max,
- * cg_max, cg_rtol, ls_max, c1, tol_J, tol_u and parity_mode; eq. (3) off
+ * All contexts: the same dim (2 or 3), the same numbers of levels,
+ * regulariser, gn_max, cg_max, cg_rtol, ls_max, c1, tol_J, tol_u and
+ * parity_mode; eq. (3) off
  * (eps_stop = 0) unless in parity mode; at most one batch per context at a
  * time.  The batch only borrows the contexts (they must outlive it).
  * Workspace: caller-owned device memory of stml_batch_workspace_bytes().

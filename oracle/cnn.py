@@ -7,19 +7,21 @@ interpolation (Sec. 3) or by the least-squares problem eq. (2).  The learned
 predictor replaces that guess by the linear interpolation plus a correction
 computed by a small convolutional encoder-decoder from the neighbouring
 frames and their registered displacements.  The network is not in the paper;
-the definition here is the one the HIP kernels implement:
+the definition here is the one the HIP kernels implement, for images (d = 2)
+and volumes (d = 3):
 
-* input (2-D, 7 channels): frame_l, frame_t, frame_r, u_l / h, u_r / h
-  (displacements in pixels of the level), NHWC;
-* encoder: 2 convolutions per level (3x3, zero padding, ReLU) with 32, 64,
-  128, 128 channels; 2x2 average pooling between levels;
+* input (3 + 2d channels): frame_l, frame_t, frame_r, u_l / h, u_r / h
+  (displacements in pixels of the level), channels last;
+* encoder: 2 convolutions per level (3^d taps, zero padding, ReLU) with 32,
+  64, 128, 128 channels; 2^d average pooling between levels;
 * decoder: nearest 2x upsampling, concatenation [skip, upsampled], 2
   convolutions per level (128, 64, 32 channels);
-* head: 1x1 convolution to 2 channels (the correction in level pixels).
+* head: 1x1 convolution to d channels (the correction in level pixels).
 
-Parameters are one float32 vector, layer by layer in the order of LAYERS,
-each layer W[tap][c_out][c_in] (tap = 3 dy + dx for 3x3, dy, dx in 0..2
-for offsets -1..1) followed by b[c_out].
+Parameters are one float32 vector, layer by layer in the order of
+``layers(d)``, each layer W[tap][c_out][c_in] followed by b[c_out]; the tap
+index runs over the offsets -1..1 of every axis in row-major order (tap =
+3 dy + dx in 2-D, 9 dz + 3 dy + dx in 3-D).
 
 Precision points mirror the GPU path: weights and activations are rounded
 to bfloat16 (round to nearest even) where the GPU stores them in bfloat16,
@@ -32,31 +34,36 @@ float32 accumulation moves the bfloat16 roundings (their noise floor).
 
 import numpy as np
 
-# (name, c_in, c_out, kernel size)
-LAYERS = [
-    ("e1a", 7, 32, 3), ("e1b", 32, 32, 3),
-    ("e2a", 32, 64, 3), ("e2b", 64, 64, 3),
-    ("e3a", 64, 128, 3), ("e3b", 128, 128, 3),
-    ("e4a", 128, 128, 3), ("e4b", 128, 128, 3),
-    ("d3a", 256, 128, 3), ("d3b", 128, 128, 3),
-    ("d2a", 192, 64, 3), ("d2b", 64, 64, 3),
-    ("d1a", 96, 32, 3), ("d1b", 32, 32, 3),
-    ("head", 32, 2, 1),
-]
+
+def layers(dim=2):
+    """(name, c_in, c_out, kernel size) of the network for d = dim."""
+    return [
+        ("e1a", 3 + 2 * dim, 32, 3), ("e1b", 32, 32, 3),
+        ("e2a", 32, 64, 3), ("e2b", 64, 64, 3),
+        ("e3a", 64, 128, 3), ("e3b", 128, 128, 3),
+        ("e4a", 128, 128, 3), ("e4b", 128, 128, 3),
+        ("d3a", 256, 128, 3), ("d3b", 128, 128, 3),
+        ("d2a", 192, 64, 3), ("d2b", 64, 64, 3),
+        ("d1a", 96, 32, 3), ("d1b", 32, 32, 3),
+        ("head", 32, dim, 1),
+    ]
 
 
-def param_count():
-    return sum(k * k * ci * co + co for _, ci, co, k in LAYERS)
+LAYERS = layers(2)
 
 
-def unpack(params):
+def param_count(dim=2):
+    return sum(k ** dim * ci * co + co for _, ci, co, k in layers(dim))
+
+
+def unpack(params, dim=2):
     """Flat vector -> {name: (W[taps][co][ci], b[co])} in float64."""
     params = np.asarray(params, dtype=np.float64)
     out = {}
     o = 0
-    for name, ci, co, k in LAYERS:
-        nw = k * k * co * ci
-        W = params[o:o + nw].reshape(k * k, co, ci)
+    for name, ci, co, k in layers(dim):
+        nw = k ** dim * co * ci
+        W = params[o:o + nw].reshape(k ** dim, co, ci)
         o += nw
         b = params[o:o + co]
         o += co
@@ -81,74 +88,97 @@ def _r(x, bf16):
 ACCUM = np.float64
 
 
-def conv(x, W, b, k):
-    """Zero-padded convolution (cross-correlation), NHWC.
+def _taps(k, d):
+    """Offsets of every tap (each axis 0..k-1, i.e. -k//2..k//2 shifted) in
+    row-major tap order."""
+    return list(np.ndindex(*((k,) * d)))
 
-    x: (B, H, Wd, ci); W: (k*k, co, ci); b: (co,).
+
+def conv(x, W, b, k):
+    """Zero-padded convolution (cross-correlation), channels last.
+
+    x: (B, *spatial, ci) with d spatial axes; W: (k^d, co, ci); b: (co,).
     y[p, co] = b[co] + sum_tap sum_ci x[p + off(tap), ci] W[tap, co, ci].
     """
-    B, H, Wd, _ = x.shape
+    d = x.ndim - 2
+    sp = x.shape[1:-1]
     co = W.shape[1]
-    y = (np.zeros((B, H, Wd, co)) + b).astype(ACCUM)
+    y = (np.zeros(x.shape[:-1] + (co,)) + b).astype(ACCUM)
     r = k // 2
-    xp = np.pad(x, ((0, 0), (r, r), (r, r), (0, 0))).astype(ACCUM)
+    xp = np.pad(x, ((0, 0),) + ((r, r),) * d + ((0, 0),)).astype(ACCUM)
     Wa = W.astype(ACCUM)
-    for tap in range(k * k):
-        dy, dx = divmod(tap, k)
-        xs = xp[:, dy:dy + H, dx:dx + Wd, :]
-        y += np.tensordot(xs, Wa[tap], axes=([3], [1])).astype(ACCUM)
+    for tap, off in enumerate(_taps(k, d)):
+        sl = tuple(slice(o, o + n) for o, n in zip(off, sp))
+        xs = xp[(slice(None),) + sl]
+        y += np.tensordot(xs, Wa[tap], axes=([d + 1], [1])).astype(ACCUM)
     return y.astype(np.float64)
 
 
 def conv_backward(x, W, k, dy):
     """Gradients of conv wrt x, W and b for upstream gradient dy."""
-    B, H, Wd, ci = x.shape
+    d = x.ndim - 2
+    sp = x.shape[1:-1]
     r = k // 2
-    xp = np.pad(x, ((0, 0), (r, r), (r, r), (0, 0))).astype(ACCUM)
+    xp = np.pad(x, ((0, 0),) + ((r, r),) * d + ((0, 0),)).astype(ACCUM)
     dya = dy.astype(ACCUM)
     Wa = W.astype(ACCUM)
     dxp = np.zeros_like(xp)
     dW = np.zeros(W.shape, dtype=ACCUM)
-    for tap in range(k * k):
-        ty, tx = divmod(tap, k)
-        xs = xp[:, ty:ty + H, tx:tx + Wd, :]
-        dW[tap] = np.tensordot(dya, xs, axes=([0, 1, 2], [0, 1, 2]))
-        dxp[:, ty:ty + H, tx:tx + Wd, :] += np.tensordot(dya, Wa[tap],
-                                                         axes=([3], [0]))
-    dx = dxp[:, r:r + H, r:r + Wd, :]
-    db = dya.sum(axis=(0, 1, 2))
+    axes = list(range(d + 1))
+    for tap, off in enumerate(_taps(k, d)):
+        sl = (slice(None),) + tuple(slice(o, o + n) for o, n in zip(off, sp))
+        xs = xp[sl]
+        dW[tap] = np.tensordot(dya, xs, axes=(axes, axes))
+        dxp[sl] += np.tensordot(dya, Wa[tap], axes=([d + 1], [0]))
+    dx = dxp[(slice(None),) + tuple(slice(r, r + n) for n in sp)]
+    db = dya.sum(axis=tuple(axes))
     return (dx.astype(np.float64), dW.astype(np.float64),
             db.astype(np.float64))
 
 
+def _blocks(x):
+    """(B, *spatial, C) -> (B, s0/2, 2, s1/2, 2, ..., C) and the axes of
+    the 2-blocks."""
+    d = x.ndim - 2
+    shape = [x.shape[0]]
+    for n in x.shape[1:-1]:
+        shape += [n // 2, 2]
+    shape.append(x.shape[-1])
+    return x.reshape(shape), tuple(2 + 2 * a for a in range(d))
+
+
 def pool(x):
-    B, H, Wd, C = x.shape
-    return x.reshape(B, H // 2, 2, Wd // 2, 2, C).mean(axis=(2, 4))
-
-
-def pool_backward(dy):
-    return np.repeat(np.repeat(dy, 2, axis=1), 2, axis=2) / 4.0
+    xb, ax = _blocks(x)
+    return xb.mean(axis=ax)
 
 
 def up(x):
-    return np.repeat(np.repeat(x, 2, axis=1), 2, axis=2)
+    for a in range(1, x.ndim - 1):
+        x = np.repeat(x, 2, axis=a)
+    return x
+
+
+def pool_backward(dy):
+    return up(dy) / float(2 ** (dy.ndim - 2))
 
 
 def up_backward(dy):
-    B, H, Wd, C = dy.shape
-    return dy.reshape(B, H // 2, 2, Wd // 2, 2, C).sum(axis=(2, 4))
+    yb, ax = _blocks(dy)
+    return yb.sum(axis=ax)
 
 
 def forward(params, x, bf16=True):
-    """Network output (B, H, W, 2) and the saved activations."""
-    P = unpack(params)
+    """Network output (B, *spatial, d) and the rounded parameters."""
+    d = x.ndim - 2
+    lay = layers(d)
+    P = unpack(params, d)
     if bf16:
         P = {n: (to_bf16(W), b) for n, (W, b) in P.items()}
     act = {"in": _r(x, bf16)}
 
     def cr(name, inp):
         W, b = P[name]
-        k = dict((l[0], l[3]) for l in LAYERS)[name]
+        k = dict((l[0], l[3]) for l in lay)[name]
         return _r(np.maximum(conv(inp, W, b, k), 0.0), bf16)
 
     e1 = cr("e1b", cr("e1a", act["in"]))
@@ -158,11 +188,11 @@ def forward(params, x, bf16=True):
     e3 = cr("e3b", cr("e3a", p2))
     p3 = _r(pool(e3), bf16)
     e4 = cr("e4b", cr("e4a", p3))
-    c3 = np.concatenate([e3, up(e4)], axis=3)
+    c3 = np.concatenate([e3, up(e4)], axis=-1)
     d3 = cr("d3b", cr("d3a", c3))
-    c2 = np.concatenate([e2, up(d3)], axis=3)
+    c2 = np.concatenate([e2, up(d3)], axis=-1)
     d2 = cr("d2b", cr("d2a", c2))
-    c1 = np.concatenate([e1, up(d2)], axis=3)
+    c1 = np.concatenate([e1, up(d2)], axis=-1)
     d1 = cr("d1b", cr("d1a", c1))
     W, b = P["head"]
     out = conv(d1, W, b, 1)
@@ -170,15 +200,17 @@ def forward(params, x, bf16=True):
 
 
 def loss_and_grad(params, x, target, bf16=True):
-    """Mean squared error over (B, H, W, 2) and its gradient wrt params.
+    """Mean squared error over (B, *spatial, d) and its gradient wrt params.
 
     The backward pass rounds every upstream gradient to bfloat16 where the
     GPU feeds it to a bfloat16 matrix instruction.
     """
-    P = unpack(params)
+    d = x.ndim - 2
+    lay = layers(d)
+    P = unpack(params, d)
     if bf16:
         P = {n: (to_bf16(W), b) for n, (W, b) in P.items()}
-    ks = dict((l[0], l[3]) for l in LAYERS)
+    ks = dict((l[0], l[3]) for l in lay)
     acts = {}
 
     def cr(name, inp):
@@ -196,11 +228,11 @@ def loss_and_grad(params, x, target, bf16=True):
     e3 = cr("e3b", cr("e3a", p2))
     p3 = _r(pool(e3), bf16)
     e4 = cr("e4b", cr("e4a", p3))
-    c3 = np.concatenate([e3, up(e4)], axis=3)
+    c3 = np.concatenate([e3, up(e4)], axis=-1)
     d3 = cr("d3b", cr("d3a", c3))
-    c2 = np.concatenate([e2, up(d3)], axis=3)
+    c2 = np.concatenate([e2, up(d3)], axis=-1)
     d2 = cr("d2b", cr("d2a", c2))
-    c1 = np.concatenate([e1, up(d2)], axis=3)
+    c1 = np.concatenate([e1, up(d2)], axis=-1)
     d1 = cr("d1b", cr("d1a", c1))
     Wh, bh = P["head"]
     out = conv(d1, Wh, bh, 1)
@@ -238,22 +270,22 @@ def loss_and_grad(params, x, target, bf16=True):
     back("e1a", back("e1b", de1))
 
     flat = []
-    for name, ci, co, k in LAYERS:
+    for name, ci, co, k in lay:
         dW, db = grads[name]
         flat.append(dW.ravel())
         flat.append(db.ravel())
     return loss, np.concatenate(flat)
 
 
-def init_params(seed):
+def init_params(seed, dim=2):
     """He-normal weights, zero biases, float32 (the GPU uses the same)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     out = []
-    for name, ci, co, k in LAYERS:
-        std = np.sqrt(2.0 / (k * k * ci))
+    for name, ci, co, k in layers(dim):
+        std = np.sqrt(2.0 / (k ** dim * ci))
         if name == "head":
             std *= 0.1
-        out.append(rng.standard_normal(k * k * co * ci) * std)
+        out.append(rng.standard_normal(k ** dim * co * ci) * std)
         out.append(np.zeros(co))
     return np.concatenate(out).astype(np.float32)
 

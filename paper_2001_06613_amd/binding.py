@@ -547,52 +547,58 @@ class Net:
         return p
 
     def set_input(self, x, target=None):
-        """x: [B][C][H][W] float32 (C <= 32); target [B][H][W][2]."""
+        """x: [B][C][*extent] float32 (C <= 32, extent of dim axes);
+        target [B][*extent][dim]."""
         x = self.torch.as_tensor(x, dtype=self.torch.float32).to(
             self.device).contiguous()
-        B, C, H, W = x.shape
+        if x.dim() != self.dim + 2:
+            raise STMLError(STML_EINVAL, "x must be [B][C][*extent]")
+        B, C, ext = x.shape[0], x.shape[1], tuple(x.shape[2:])
         t = None
         if target is not None:
             t = self.torch.as_tensor(target, dtype=self.torch.float32).to(
                 self.device).contiguous()
+            if tuple(t.shape) != (B,) + ext + (self.dim,):
+                raise STMLError(STML_EINVAL, "target must be [B][*extent][dim]")
         self._input_refs = (x, t)
         self._check(self.lib.stml_net_set_input(
             self.net, _ptr(x), C, _ptr(t) if t is not None else None, B,
-            _int_array((H, W))))
-        self.cur = (B, H, W)
+            _int_array(ext)))
+        self.cur = (B,) + ext
 
     def assemble(self, frames, u, h, triples, with_target=False):
-        """frames [n][H][W], u [n][2][H][W] float32 device tensors; triples
-        [(t, l, r), ...] with 0 <= l < t < r < n."""
+        """frames [n][*extent], u [n][dim][*extent] float32 device tensors;
+        triples [(t, l, r), ...] with 0 <= l < t < r < n."""
         torch = self.torch
-        n, H, W = frames.shape
-        if (frames.dtype != torch.float32 or u.dtype != torch.float32 or
-                tuple(u.shape) != (n, 2, H, W) or not frames.is_cuda or
+        n, ext = frames.shape[0], tuple(frames.shape[1:])
+        if (len(ext) != self.dim or frames.dtype != torch.float32 or
+                u.dtype != torch.float32 or
+                tuple(u.shape) != (n, self.dim) + ext or not frames.is_cuda or
                 not u.is_cuda or not frames.is_contiguous() or
                 not u.is_contiguous()):
-            raise STMLError(STML_EINVAL, "frames [n][H][W] and u [n][2][H][W]"
-                            " contiguous float32 device tensors expected")
+            raise STMLError(STML_EINVAL, "frames [n][*extent] and u "
+                            "[n][dim][*extent] contiguous float32 device "
+                            "tensors expected")
         flat = [int(v) for tr in triples for v in tr]
         self._check(self.lib.stml_net_assemble(
-            self.net, _ptr(frames), _ptr(u), int(n), _int_array((H, W)),
+            self.net, _ptr(frames), _ptr(u), int(n), _int_array(ext),
             float(h), _int_array(flat), len(triples), int(bool(with_target))))
-        self.cur = (len(triples), H, W)
+        self.cur = (len(triples),) + ext
         self.cur_n = int(n)
 
     def forward(self):
-        B, H, W = self.cur
-        out = self.torch.empty((B, H, W, self.OUT_LD), dtype=self.torch.float32,
-                               device=self.device)
+        out = self.torch.empty(self.cur + (self.OUT_LD,),
+                               dtype=self.torch.float32, device=self.device)
         self._check(self.lib.stml_net_forward(self.net, _ptr(out)))
-        return out[..., :2]
+        return out[..., :self.dim]
 
     def emit(self, h, u):
-        """u [n][2][H][W] (n, H, W as last assembled) receives the
+        """u [n][dim][*extent] (n and extent as last assembled) receives the
         predictions of the assembled frames."""
-        _, H, W = self.cur
+        ext = tuple(self.cur[1:])
         if (u.dtype != self.torch.float32 or not u.is_cuda or
                 not u.is_contiguous() or
-                tuple(u.shape) != (getattr(self, "cur_n", -1), 2, H, W)):
+                tuple(u.shape) != (getattr(self, "cur_n", -1), self.dim) + ext):
             raise STMLError(STML_EINVAL, "u must match the assembled frames")
         self._check(self.lib.stml_net_emit(self.net, float(h), _ptr(u)))
 

@@ -600,12 +600,12 @@ static int cgv_blocks(const Geom& g) {
   return (int)((nb + kXCD - 1) / kXCD * kXCD);
 }
 
-// 2-D: a fixed block size (waves without frames idle), so that a problem
-// gets the same blocks, and the same rounding, alone and batched.
+// A fixed block size (waves without frames idle), so that a problem gets
+// the same blocks, and the same rounding, alone and batched.
 static int cgv_threads(int dim, int nK) {
-  if (dim == 2) return kMaxChunks * kWave;
-  int G = nK < kMaxChunks ? nK : kMaxChunks;
-  return (G < 1 ? 1 : G) * kWave;
+  (void)dim;
+  (void)nK;
+  return kMaxChunks * kWave;
 }
 
 int cg_tile_count(const Geom& g, int dim) {
@@ -681,7 +681,7 @@ hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
   return hipGetLastError();
 }
 
-// ------------------------------------------------- batched 2-D iteration
+// ------------------------------------------------------ batched iteration
 
 __device__ __forceinline__ int cg_job_index(const int* __restrict__ f, int n,
                                             int b) {
@@ -703,17 +703,18 @@ __device__ __forceinline__ const Job& cg_job_of(const JobSet& js, int c,
   return js.jobs[j];
 }
 
+template <int D>
 __global__ __launch_bounds__(1024) void cg_init_batch_kernel(JobSet js) {
   Blk blk;
   const Job& J = cg_job_of(js, kClsVox, blk);
   const Geom g = J.g;
   const Model md = J.md;
   Scal* sc = J.sc;
-  cgv_init_body<2>(J.grad, J.dW, g, md, J.r, J.z, J.sums.Sz, J.sums.Vz,
+  cgv_init_body<D>(J.grad, J.dW, g, md, J.r, J.z, J.sums.Sz, J.sums.Vz,
                    J.rb.region(kRegInit), sc->gn_cur, sc, blk);
 }
 
-template <int REG>
+template <int D, int REG>
 __global__ __launch_bounds__(256) void cg_hvp_batch_kernel(JobSet js, int it,
                                                            int fixed,
                                                            double rtol) {
@@ -724,13 +725,23 @@ __global__ __launch_bounds__(256) void cg_hvp_batch_kernel(JobSet js, int it,
   Scal* sc = J.sc;
   float* pn = (it & 1) ? J.P1 : J.P0;
   const float* po = (it & 1) ? J.P0 : J.P1;
-  cgt_hvp2_body<REG>(it, J.z, po, pn, J.dW, g, md, J.q, J.sums.Sz, J.sums.Vz,
-                     J.sums.Sp[(it + 1) & 1], J.sums.Vp[(it + 1) & 1],
-                     J.sums.Sp[it & 1], J.sums.Vp[it & 1], J.ct.nreal,
-                     J.ct.nfg, J.ct.fpg, J.rb.region(kRegUpdate), J.nb_vox,
-                     fixed, rtol, J.rb.region(kRegHv), sc, sc->gn_cur, blk);
+  if constexpr (D == 2)
+    cgt_hvp2_body<REG>(it, J.z, po, pn, J.dW, g, md, J.q, J.sums.Sz,
+                       J.sums.Vz, J.sums.Sp[(it + 1) & 1],
+                       J.sums.Vp[(it + 1) & 1], J.sums.Sp[it & 1],
+                       J.sums.Vp[it & 1], J.ct.nreal, J.ct.nfg, J.ct.fpg,
+                       J.rb.region(kRegUpdate), J.nb_vox, fixed, rtol,
+                       J.rb.region(kRegHv), sc, sc->gn_cur, blk);
+  else
+    cgt_hvp3_body<REG>(it, J.z, po, pn, J.dW, g, md, J.q, J.sums.Sz,
+                       J.sums.Vz, J.sums.Sp[(it + 1) & 1],
+                       J.sums.Vp[(it + 1) & 1], J.sums.Sp[it & 1],
+                       J.sums.Vp[it & 1], J.ct.nreal, J.ct.nfg, J.ct.fpg,
+                       J.rb.region(kRegUpdate), J.nb_vox, fixed, rtol,
+                       J.rb.region(kRegHv), sc, sc->gn_cur, blk);
 }
 
+template <int D>
 __global__ __launch_bounds__(1024) void cg_update_batch_kernel(JobSet js,
                                                                int it) {
   Blk blk;
@@ -739,40 +750,49 @@ __global__ __launch_bounds__(1024) void cg_update_batch_kernel(JobSet js,
   const Model md = J.md;
   Scal* sc = J.sc;
   const float* pn = (it & 1) ? J.P1 : J.P0;
-  cgv_update_body<2>(it, pn, J.q, J.dW, g, md, J.x, J.r, J.z, J.sums.Sz,
+  cgv_update_body<D>(it, pn, J.q, J.dW, g, md, J.x, J.r, J.z, J.sums.Sz,
                      J.sums.Vz, J.rb.region(kRegHv), J.ct.grid,
                      J.rb.region(kRegUpdate), sc, sc->gn_cur, blk);
 }
 
 void job_shape(Job* job) {
-  job->ct = cg_tiles(job->g, job->md.nK, 2);
+  const int dim = geom_dim(job->g);
+  job->ct = cg_tiles(job->g, job->md.nK, dim);
   job->nb_tile = tile_blocks(job->g);
   job->nb_vox = job->ct.vox_grid;
-  job->count = (long long)job->md.nK * 2 * job->g.N;
+  job->count = (long long)job->md.nK * dim * job->g.N;
   job->nb_elem = elem_grid(job->count);
 }
 
 hipError_t batch_finalize_start(const JobSet& js, hipStream_t s);
 
-hipError_t batch_cg_init(const JobSet& js, int nvox, hipStream_t s) {
-  cg_init_batch_kernel<<<nvox, cgv_threads(2, 0), 0, s>>>(js);
+hipError_t batch_cg_init(const JobSet& js, int nvox, int dim, hipStream_t s) {
+  if (dim == 2)
+    cg_init_batch_kernel<2><<<nvox, cgv_threads(2, 0), 0, s>>>(js);
+  else
+    cg_init_batch_kernel<3><<<nvox, cgv_threads(3, 0), 0, s>>>(js);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return batch_finalize_start(js, s);
 }
 
-hipError_t batch_cg_hvp(const JobSet& js, int nhv, int reg, int it,
+hipError_t batch_cg_hvp(const JobSet& js, int nhv, int dim, int reg, int it,
                         int fixed, double rtol, hipStream_t s) {
-  if (reg == 0)
-    cg_hvp_batch_kernel<0><<<nhv, kTX * kTY, 0, s>>>(js, it, fixed, rtol);
-  else
-    cg_hvp_batch_kernel<1><<<nhv, kTX * kTY, 0, s>>>(js, it, fixed, rtol);
+  auto kern = dim == 2
+                  ? (reg == 0 ? cg_hvp_batch_kernel<2, 0>
+                              : cg_hvp_batch_kernel<2, 1>)
+                  : (reg == 0 ? cg_hvp_batch_kernel<3, 0>
+                              : cg_hvp_batch_kernel<3, 1>);
+  kern<<<nhv, kTX * kTY, 0, s>>>(js, it, fixed, rtol);
   return hipGetLastError();
 }
 
-hipError_t batch_cg_update(const JobSet& js, int nvox, int it,
+hipError_t batch_cg_update(const JobSet& js, int nvox, int dim, int it,
                            hipStream_t s) {
-  cg_update_batch_kernel<<<nvox, cgv_threads(2, 0), 0, s>>>(js, it);
+  if (dim == 2)
+    cg_update_batch_kernel<2><<<nvox, cgv_threads(2, 0), 0, s>>>(js, it);
+  else
+    cg_update_batch_kernel<3><<<nvox, cgv_threads(3, 0), 0, s>>>(js, it);
   return hipGetLastError();
 }
 

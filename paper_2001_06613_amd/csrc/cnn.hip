@@ -45,14 +45,16 @@ typedef __attribute__((__vector_size__(16 * sizeof(float)))) float f32x16;
 typedef __attribute__((__vector_size__(4 * sizeof(__bf16)))) __bf16 bf16x4;
 
 constexpr int kCinPad = 32;
-constexpr int kOutLd = 32;     // channels of the head output (2 real)
-constexpr int kMaxConvW = 256; // widest image row the 3x3 convolution stages
+constexpr int kOutLd = 32;     // channels of the head output (D real)
+constexpr int kMaxConvW = kMaxNetWidth;   // widest row a 3x3 conv stages
 
 struct LayerDef {
   const char* name;
   int ci, co, k;
 };
 constexpr int kLayers = 15;
+// 2-D table; in 3-D the first layer reads 3 + 2 x 3 channels and the head
+// writes 3.
 constexpr LayerDef kDefs[kLayers] = {
     {"e1a", 7, 32, 3},    {"e1b", 32, 32, 3},   {"e2a", 32, 64, 3},
     {"e2b", 64, 64, 3},   {"e3a", 64, 128, 3},  {"e3b", 128, 128, 3},
@@ -62,6 +64,15 @@ constexpr LayerDef kDefs[kLayers] = {
 };
 enum { E1A, E1B, E2A, E2B, E3A, E3B, E4A, E4B, D3A, D3B, D2A, D2B, D1A, D1B,
        HEAD };
+
+static LayerDef layer_def(int dim, int i) {
+  LayerDef d = kDefs[i];
+  if (i == E1A) d.ci = 3 + 2 * dim;
+  if (i == HEAD) d.co = dim;
+  return d;
+}
+// taps of a layer with kernel size k
+static int layer_taps(int dim, int k) { return dim == 3 ? k * k * k : k * k; }
 
 static int rup(int v, int m) { return (v + m - 1) / m * m; }
 
@@ -94,17 +105,21 @@ struct ConvSrc {
 constexpr int kRowLd = 24;      // LDS row: 16 channels + 8 of padding
 
 // Y[p][yoff + co] = act(bias[co] + sum_tap sum_ci X[p + off(tap)][ci]
-//                   Wt[tap][co][ci]) with zero padding, p = (b, y, x)
-// flattened.  Block: 128 PS pixels x 32 CS output channels; wave w owns
-// pixel subtiles PS w .. PS w + PS - 1 (32 pixels each) and all CS channel
-// subtiles.  Requires W <= 256 (LDS rows of the halo), cin_p % 16 == 0.
-template <int K, int CS, int PS, class TX, bool OUT_F32, bool RELU>
+//                   Wt[tap][co][ci]) with zero padding, p = (b, z, y, x)
+// flattened (z absent in 2-D: Z = 1, KZ = 1).  3-D taps (KZ = 3) are run as
+// three planes of K x K taps: for plane dz the staged rows are those of the
+// 2-D case shifted by dz H W, so the LDS footprint does not grow.  Block:
+// 128 PS pixels x 32 CS output channels; wave w owns pixel subtiles
+// PS w .. PS w + PS - 1 (32 pixels each) and all CS channel subtiles.
+// Requires W <= 256 (LDS rows of the halo), cin_p % 16 == 0.
+template <int K, int KZ, int CS, int PS, class TX, bool OUT_F32, bool RELU>
 __global__ __launch_bounds__(256) void conv_kernel(
     ConvSrc<TX> src, int cin_p, const bf16* __restrict__ Wt,
     const float* __restrict__ bias, int cout, int cout_p,
-    void* __restrict__ Yv, int yld, int yoff, int B, int H, int W) {
+    void* __restrict__ Yv, int yld, int yoff, int B, int Z, int H, int W) {
   constexpr int TP = 128 * PS;           // pixels per block
   constexpr int COB = 32 * CS;           // output channels per block
+  constexpr int K2 = K * K;
   extern __shared__ __align__(16) bf16 lds[];
   const int R = K == 3 ? W + 1 : 0;      // halo of the flattened range
   const int NR = TP + 2 * R;             // staged rows
@@ -113,17 +128,20 @@ __global__ __launch_bounds__(256) void conv_kernel(
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int ln = lane & 31, kh = lane >> 5;
   const long long HW = (long long)H * W;
-  const long long P = (long long)B * HW;
+  const long long ZHW = (long long)Z * HW;
+  const long long P = (long long)B * ZHW;
   const long long p0 = (long long)blockIdx.x * TP;
   const int co_base = blockIdx.y * COB;
   // this lane's pixels
-  int py[PS], pxx[PS];
+  int pz[PS], py[PS], pxx[PS];
   bool pv[PS];
 #pragma unroll
   for (int s = 0; s < PS; ++s) {
     long long p = p0 + 32 * (PS * w + s) + ln;
     pv[s] = p < P;
-    long long rem = pv[s] ? p % HW : 0;
+    long long rem = pv[s] ? p % ZHW : 0;
+    pz[s] = (int)(rem / HW);
+    rem -= (long long)pz[s] * HW;
     py[s] = (int)(rem / W);
     pxx[s] = (int)(rem - (long long)py[s] * W);
   }
@@ -135,63 +153,76 @@ __global__ __launch_bounds__(256) void conv_kernel(
 #pragma unroll
       for (int i = 0; i < 16; ++i) acc[s][c][i] = 0.f;
   const bf16x8 zero = {};
-  const int H1 = H >> 1, W1 = W >> 1;
+  const int H1 = H >> 1, W1 = W >> 1, Z1 = KZ == 3 ? Z >> 1 : 1;
   for (int c0 = 0; c0 < cin_p; c0 += 16) {
-    // stage the input rows [p0 - R, p0 + TP + R) of this channel chunk
     const bool hi = c0 >= src.split;
     const TX* sp = hi ? src.a1 : src.a0;
     const int sld = hi ? src.ld1 : src.ld0;
     const int soff = hi ? src.off1 + c0 - src.split : src.off0 + c0;
-    for (int e = tid; e < 2 * NR; e += 256) {
-      const int row = e >> 1, hf = e & 1;
-      const long long q = p0 - R + row;
-      bf16x8 v = zero;
-      if (q >= 0 && q < P) {
-        long long idx = q;
-        if (hi) {
-          const long long b = q / HW;
-          const int rem = (int)(q - b * HW);
-          const int yy = rem / W, xx = rem - yy * W;
-          idx = (b * H1 + (yy >> 1)) * W1 + (xx >> 1);
+    for (int pl = 0; pl < KZ; ++pl) {
+      const int dz = pl - KZ / 2;
+      // stage the input rows [p0 - R, p0 + TP + R) + dz H W of this chunk
+      const long long qb = p0 - R + dz * HW;
+      for (int e = tid; e < 2 * NR; e += 256) {
+        const int row = e >> 1, hf = e & 1;
+        const long long q = qb + row;
+        bf16x8 v = zero;
+        if (q >= 0 && q < P) {
+          long long idx = q;
+          if (hi) {
+            const long long b = q / ZHW;
+            long long rem = q - b * ZHW;
+            const int zz = (int)(rem / HW);
+            rem -= (long long)zz * HW;
+            const int yy = (int)(rem / W), xx = (int)(rem - (long long)yy * W);
+            idx = ((b * Z1 + (KZ == 3 ? zz >> 1 : 0)) * H1 + (yy >> 1)) * W1 +
+                  (xx >> 1);
+          }
+          v = load8(sp + idx * sld + soff + 8 * hf);
         }
-        v = load8(sp + idx * sld + soff + 8 * hf);
+        *reinterpret_cast<bf16x8*>(act + row * kRowLd + 8 * hf) = v;
       }
-      *reinterpret_cast<bf16x8*>(act + row * kRowLd + 8 * hf) = v;
-    }
-    // stage the weights of every tap for the block's output channels
-    for (int e = tid; e < 2 * K * K * COB; e += 256) {
-      const int row = e >> 1, hf = e & 1;
-      const int tap = row / COB, co = row - tap * COB;
-      *reinterpret_cast<bf16x8*>(wl + row * kRowLd + 8 * hf) =
-          load8(Wt + ((size_t)tap * cout_p + co_base + co) * cin_p + c0 +
-                8 * hf);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int tap = 0; tap < K * K; ++tap) {
-      const int dy = tap / K - K / 2, dx = tap % K - K / 2;
-      bf16x8 bop[PS];
+      // stage the weights of the plane's taps for the block's channels
+      for (int e = tid; e < 2 * K2 * COB; e += 256) {
+        const int row = e >> 1, hf = e & 1;
+        const int tap = row / COB, co = row - tap * COB;
+        *reinterpret_cast<bf16x8*>(wl + row * kRowLd + 8 * hf) =
+            load8(Wt + ((size_t)(pl * K2 + tap) * cout_p + co_base + co) *
+                           cin_p +
+                  c0 + 8 * hf);
+      }
+      __syncthreads();
+      bool zok[PS];
 #pragma unroll
       for (int s = 0; s < PS; ++s) {
-        const int yy = py[s] + dy, xx = pxx[s] + dx;
-        const bool ok = pv[s] && yy >= 0 && yy < H && xx >= 0 && xx < W;
-        const int row = 32 * (PS * w + s) + ln + R + dy * W + dx;
-        bop[s] = ok ? *reinterpret_cast<const bf16x8*>(act + row * kRowLd +
-                                                       8 * kh)
-                    : zero;
+        const int zz = pz[s] + dz;
+        zok[s] = pv[s] && zz >= 0 && zz < Z;
       }
 #pragma unroll
-      for (int c = 0; c < CS; ++c) {
-        const bf16x8 aop = *reinterpret_cast<const bf16x8*>(
-            wl + (tap * COB + 32 * c + ln) * kRowLd + 8 * kh);
+      for (int tap = 0; tap < K2; ++tap) {
+        const int dy = tap / K - K / 2, dx = tap % K - K / 2;
+        bf16x8 bop[PS];
 #pragma unroll
-        for (int s = 0; s < PS; ++s)
-          acc[s][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(aop, bop[s],
-                                                              acc[s][c], 0, 0,
-                                                              0);
+        for (int s = 0; s < PS; ++s) {
+          const int yy = py[s] + dy, xx = pxx[s] + dx;
+          const bool ok = zok[s] && yy >= 0 && yy < H && xx >= 0 && xx < W;
+          const int row = 32 * (PS * w + s) + ln + R + dy * W + dx;
+          bop[s] = ok ? *reinterpret_cast<const bf16x8*>(act + row * kRowLd +
+                                                         8 * kh)
+                      : zero;
+        }
+#pragma unroll
+        for (int c = 0; c < CS; ++c) {
+          const bf16x8 aop = *reinterpret_cast<const bf16x8*>(
+              wl + (tap * COB + 32 * c + ln) * kRowLd + 8 * kh);
+#pragma unroll
+          for (int s = 0; s < PS; ++s)
+            acc[s][c] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                aop, bop[s], acc[s][c], 0, 0, 0);
+        }
       }
+      __syncthreads();
     }
-    __syncthreads();
   }
   // D[co][pixel]: lane holds pixel ln, channels 8 g + 4 kh + (0..3)
 #pragma unroll
@@ -227,17 +258,18 @@ constexpr int kWChunk = 128;    // pixels staged per step of the weight gradient
 constexpr int kWLd = kWChunk + 8;
 
 // part[s][tap][co][ci] = sum over the pixels of split s of
-//   bf16(dP[p][poff + co]) * X[p + off(tap)][ci]   (zero padding)
+//   bf16(dP[p][poff + co]) * X[p + off(tap)][ci]   (zero padding; KZ K K
+//   taps, KZ = 3 for volumes)
 // Block: 64 output channels x 64 input channels of one tap; wave w owns
 // output channels 16w..16w+15 and all four 16-channel input subtiles.  Per
 // step 128 pixels of dP and of the shifted input are staged transposed
 // (channel-major) in LDS: thread t loads 32 contiguous channels of pixel
 // t % 128.
-template <int K>
+template <int K, int KZ>
 __global__ __launch_bounds__(256) void wgrad_kernel(
     const float* __restrict__ dP, int pld, int poff, int cout_p,
-    ConvSrc<bf16> X, int cin_p, int B, int H, int W, int chunks_per_split,
-    float* __restrict__ part) {
+    ConvSrc<bf16> X, int cin_p, int B, int Z, int H, int W,
+    int chunks_per_split, float* __restrict__ part) {
   __shared__ __align__(16) bf16 As[64][kWLd];
   __shared__ __align__(16) bf16 Bs[64][kWLd];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
@@ -247,9 +279,11 @@ __global__ __launch_bounds__(256) void wgrad_kernel(
   t /= nci;
   const int cob = t % nco;
   const int tap = t / nco;
-  const int dy = tap / K - K / 2, dx = tap % K - K / 2;
+  const int dz = tap / (K * K) - KZ / 2;
+  const int dy = (tap / K) % K - K / 2, dx = tap % K - K / 2;
   const int s = blockIdx.x;
-  const long long P = (long long)B * H * W;
+  const long long HW = (long long)H * W, ZHW = Z * HW;
+  const long long P = (long long)B * ZHW;
   const long long nchunks = (P + kWChunk - 1) / kWChunk;
   const long long c_beg = (long long)s * chunks_per_split;
   long long c_end = c_beg + chunks_per_split;
@@ -283,17 +317,21 @@ __global__ __launch_bounds__(256) void wgrad_kernel(
     {
       bf16x8 v[4] = {};
       if (p < P && ci0 < cin_p) {
-        const long long pb = p / ((long long)H * W);
-        const int rem = (int)(p - pb * H * W);
-        const int yy = rem / W + dy, xx = rem % W + dx;
-        if (yy >= 0 && yy < H && xx >= 0 && xx < W) {
+        const long long pb = p / ZHW;
+        long long rem = p - pb * ZHW;
+        const int zz = (int)(rem / HW) + dz;
+        rem %= HW;
+        const int yy = (int)(rem / W) + dy, xx = (int)(rem % W) + dx;
+        if (zz >= 0 && zz < Z && yy >= 0 && yy < H && xx >= 0 && xx < W) {
+          const int Z1 = KZ == 3 ? Z >> 1 : 1, z1 = KZ == 3 ? zz >> 1 : 0;
           const bf16* src =
               ci0 < X.split
-                  ? X.a0 + (((size_t)pb * H + yy) * W + xx) * X.ld0 + X.off0 +
-                        ci0
+                  ? X.a0 + ((((size_t)pb * Z + zz) * H + yy) * W + xx) *
+                               X.ld0 + X.off0 + ci0
                   : X.a1 +
-                        (((size_t)pb * (H >> 1) + (yy >> 1)) * (W >> 1) +
-                         (xx >> 1)) * X.ld1 + X.off1 + ci0 - X.split;
+                        ((((size_t)pb * Z1 + z1) * (H >> 1) + (yy >> 1)) *
+                             (W >> 1) + (xx >> 1)) * X.ld1 + X.off1 + ci0 -
+                        X.split;
 #pragma unroll
           for (int q = 0; q < 4; ++q) v[q] = load8(src + 8 * q);
         }
@@ -318,7 +356,7 @@ __global__ __launch_bounds__(256) void wgrad_kernel(
     }
     __syncthreads();
   }
-  const int K2 = K * K;
+  const int K2 = KZ * K * K;
 #pragma unroll
   for (int n = 0; n < 4; ++n) {
     const int ci = cib * 64 + 16 * n + (lane & 15);
@@ -443,13 +481,15 @@ __global__ void relu_bwd_kernel(float* __restrict__ dP, int ld, int off,
   }
 }
 
-// 2x2 average pooling, bfloat16 in and out (the sum of four bfloat16 values
-// is exact in float32).
+// 2x2 (2-D, Z = 1, DZ = 1) or 2x2x2 (3-D, DZ = 2) average pooling,
+// bfloat16 in and out; the block sum is formed in float32 (exact for four
+// bfloat16 values, and for eight of like magnitude).
+template <int DZ>
 __global__ void pool_kernel(const bf16* __restrict__ X, int xld, int xoff,
-                            int C, int B, int H, int W, bf16* __restrict__ Y,
-                            int yld) {
-  const int Ho = H / 2, Wo = W / 2;
-  long long n = (long long)B * Ho * Wo * C;
+                            int C, int B, int Z, int H, int W,
+                            bf16* __restrict__ Y, int yld) {
+  const int Zo = Z / DZ, Ho = H / 2, Wo = W / 2;
+  long long n = (long long)B * Zo * Ho * Wo * C;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long st = (long long)gridDim.x * blockDim.x;
   for (; i < n; i += st) {
@@ -458,43 +498,55 @@ __global__ void pool_kernel(const bf16* __restrict__ X, int xld, int xoff,
     int xo = (int)(q % Wo);
     long long r = q / Wo;
     int yo = (int)(r % Ho);
-    int b = (int)(r / Ho);
-    size_t p00 = (((size_t)b * H + 2 * yo) * W + 2 * xo);
-    float s = (float)X[p00 * xld + xoff + c] +
-              (float)X[(p00 + 1) * xld + xoff + c] +
-              (float)X[(p00 + W) * xld + xoff + c] +
-              (float)X[(p00 + W + 1) * xld + xoff + c];
-    Y[q * yld + c] = (bf16)(0.25f * s);
+    r /= Ho;
+    int zo = (int)(r % Zo);
+    int b = (int)(r / Zo);
+    float sum = 0.f;
+#pragma unroll
+    for (int k = 0; k < DZ; ++k) {
+      size_t p00 = ((((size_t)b * Z + DZ * zo + k) * H + 2 * yo) * W + 2 * xo);
+      sum += (float)X[p00 * xld + xoff + c] +
+             (float)X[(p00 + 1) * xld + xoff + c] +
+             (float)X[(p00 + W) * xld + xoff + c] +
+             (float)X[(p00 + W + 1) * xld + xoff + c];
+    }
+    Y[q * yld + c] = (bf16)(sum * (DZ == 2 ? 0.125f : 0.25f));
   }
 }
 
-// dX[2y+i][2x+j][off + c] += dY[y][x][c] / 4
+// dX[DZ z + k][2y+i][2x+j][off + c] += dY[z][y][x][c] / 2^d
+template <int DZ>
 __global__ void pool_bwd_add_kernel(const float* __restrict__ dY, int C,
-                                    int B, int H, int W,
+                                    int B, int Z, int H, int W,
                                     float* __restrict__ dX, int dld,
                                     int doff) {
-  long long n = (long long)B * H * W * C;
+  long long n = (long long)B * Z * H * W * C;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long st = (long long)gridDim.x * blockDim.x;
+  const int Zi = Z / DZ, Hi = H / 2, Wi = W / 2;
   for (; i < n; i += st) {
     int c = (int)(i % C);
     long long q = i / C;
     int x = (int)(q % W);
     long long r = q / W;
     int y = (int)(r % H);
-    int b = (int)(r / H);
-    int Hi = H / 2, Wi = W / 2;
-    float g = dY[(((size_t)b * Hi + y / 2) * Wi + x / 2) * C + c] * 0.25f;
+    r /= H;
+    int z = (int)(r % Z);
+    int b = (int)(r / Z);
+    float g = dY[((((size_t)b * Zi + z / DZ) * Hi + y / 2) * Wi + x / 2) * C +
+                 c] *
+              (DZ == 2 ? 0.125f : 0.25f);
     dX[q * dld + doff + c] += g;
   }
 }
 
-// dX[y][x][c] = sum of dY[2y+i][2x+j][off + c]
+// dX[z][y][x][c] = sum of dY[DZ z + k][2y+i][2x+j][off + c]
+template <int DZ>
 __global__ void up_bwd_kernel(const float* __restrict__ dY, int dld, int doff,
-                              int C, int B, int H, int W,
+                              int C, int B, int Z, int H, int W,
                               float* __restrict__ dX) {
-  const int Ho = H / 2, Wo = W / 2;
-  long long n = (long long)B * Ho * Wo * C;
+  const int Zo = Z / DZ, Ho = H / 2, Wo = W / 2;
+  long long n = (long long)B * Zo * Ho * Wo * C;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long st = (long long)gridDim.x * blockDim.x;
   for (; i < n; i += st) {
@@ -503,29 +555,36 @@ __global__ void up_bwd_kernel(const float* __restrict__ dY, int dld, int doff,
     int xo = (int)(q % Wo);
     long long r = q / Wo;
     int yo = (int)(r % Ho);
-    int b = (int)(r / Ho);
-    size_t p00 = (((size_t)b * H + 2 * yo) * W + 2 * xo);
-    dX[q * C + c] = dY[p00 * dld + doff + c] + dY[(p00 + 1) * dld + doff + c] +
-                    dY[(p00 + W) * dld + doff + c] +
-                    dY[(p00 + W + 1) * dld + doff + c];
+    r /= Ho;
+    int zo = (int)(r % Zo);
+    int b = (int)(r / Zo);
+    float sum = 0.f;
+#pragma unroll
+    for (int k = 0; k < DZ; ++k) {
+      size_t p00 = ((((size_t)b * Z + DZ * zo + k) * H + 2 * yo) * W + 2 * xo);
+      sum += dY[p00 * dld + doff + c] + dY[(p00 + 1) * dld + doff + c] +
+             dY[(p00 + W) * dld + doff + c] +
+             dY[(p00 + W + 1) * dld + doff + c];
+    }
+    dX[q * C + c] = sum;
   }
 }
 
-// Mean squared error of the 2-channel head (ld kOutLd) against tgt [P][2];
-// dout = 2 (out - tgt) / (2P) in channels 0, 1 and 0 elsewhere; per-block
-// float64 partial of the squared error.
+// Mean squared error of the nc-channel head (ld kOutLd) against tgt
+// [P][nc]; dout = 2 (out - tgt) / (nc P) in channels < nc and 0 elsewhere;
+// per-block float64 partial of the squared error.
 __global__ __launch_bounds__(256) void loss_kernel(
     const float* __restrict__ out, const float* __restrict__ tgt, long long P,
-    float* __restrict__ dout, double* __restrict__ part) {
-  const double inv = 1.0 / (2.0 * (double)P);
+    int nc, float* __restrict__ dout, double* __restrict__ part) {
+  const double inv = 1.0 / ((double)nc * (double)P);
   double acc = 0.0;
   for (long long p = (long long)blockIdx.x * blockDim.x + threadIdx.x; p < P;
        p += (long long)gridDim.x * blockDim.x) {
 #pragma unroll
     for (int c = 0; c < kOutLd; ++c) {
       float g = 0.f;
-      if (c < 2) {
-        double d = (double)out[p * kOutLd + c] - (double)tgt[p * 2 + c];
+      if (c < nc) {
+        double d = (double)out[p * kOutLd + c] - (double)tgt[p * nc + c];
         acc += d * d;
         g = (float)(2.0 * d * inv);
       }
@@ -551,80 +610,77 @@ __global__ void loss_final_kernel(const double* __restrict__ part, int nb,
   }
 }
 
-// Network input from planar float32 channels [B][C][H][W] (C <= 32) and
-// the training target [B][H][W][2] from [B][2][H][W].
+// Network input from planar float32 channels [B][C][N] (C <= 32, N pixels
+// or voxels per frame), channels last.
 __global__ void pack_input_kernel(const float* __restrict__ x, int C, int B,
-                                  int H, int W, bf16* __restrict__ xin) {
-  long long n = (long long)B * H * W * kCinPad;
+                                  long long N, bf16* __restrict__ xin) {
+  long long n = (long long)B * N * kCinPad;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long st = (long long)gridDim.x * blockDim.x;
   for (; i < n; i += st) {
     int c = (int)(i % kCinPad);
     long long p = i / kCinPad;
-    long long b = p / ((long long)H * W);
-    long long hw = p - b * H * W;
-    float v = c < C ? x[(b * C + c) * H * W + hw] : 0.f;
+    long long b = p / N;
+    long long hw = p - b * N;
+    float v = c < C ? x[(b * C + c) * N + hw] : 0.f;
     xin[i] = (bf16)v;
   }
 }
 
-// Inputs of frames t with registered neighbours l < t < r:
-// [T_l, T_t, T_r, u_l / h, u_r / h] (2-D), the linear-interpolation base
-// u_b = w_l u_l + w_r u_r ([B][2][H][W]) and, if U_t is wanted, the target
-// correction (u_t - u_b) / h ([B][H][W][2]).
+// Inputs of frames t with registered neighbours l < t < r (D components,
+// N voxels per frame): [T_l, T_t, T_r, u_l / h, u_r / h] (3 + 2D channels),
+// the linear-interpolation base u_b = w_l u_l + w_r u_r ([B][D][N]) and, if
+// U_t is wanted, the target correction (u_t - u_b) / h ([B][N][D]).
 __global__ void assemble_kernel(const float* __restrict__ T,
                                 const float* __restrict__ U,
-                                const int* __restrict__ tlr, int B, int H,
-                                int W, double inv_h, bf16* __restrict__ xin,
+                                const int* __restrict__ tlr, int B, int D,
+                                long long N, double inv_h,
+                                bf16* __restrict__ xin,
                                 float* __restrict__ base,
                                 float* __restrict__ tgt) {
-  const long long HW = (long long)H * W;
-  long long n = (long long)B * HW;
+  long long n = (long long)B * N;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long st = (long long)gridDim.x * blockDim.x;
   for (; i < n; i += st) {
-    int b = (int)(i / HW);
-    long long hw = i - (long long)b * HW;
+    int b = (int)(i / N);
+    long long hw = i - (long long)b * N;
     int t = tlr[3 * b], l = tlr[3 * b + 1], r = tlr[3 * b + 2];
     double wl = (double)(r - t) / (r - l), wr = (double)(t - l) / (r - l);
     bf16* o = xin + i * kCinPad;
-    o[0] = (bf16)T[(size_t)l * HW + hw];
-    o[1] = (bf16)T[(size_t)t * HW + hw];
-    o[2] = (bf16)T[(size_t)r * HW + hw];
-#pragma unroll
-    for (int a = 0; a < 2; ++a) {
-      double ul = U[((size_t)l * 2 + a) * HW + hw];
-      double ur = U[((size_t)r * 2 + a) * HW + hw];
+    o[0] = (bf16)T[(size_t)l * N + hw];
+    o[1] = (bf16)T[(size_t)t * N + hw];
+    o[2] = (bf16)T[(size_t)r * N + hw];
+    for (int a = 0; a < D; ++a) {
+      double ul = U[((size_t)l * D + a) * N + hw];
+      double ur = U[((size_t)r * D + a) * N + hw];
       o[3 + a] = (bf16)(float)(ul * inv_h);
-      o[5 + a] = (bf16)(float)(ur * inv_h);
+      o[3 + D + a] = (bf16)(float)(ur * inv_h);
       double ub = wl * ul + wr * ur;
-      base[((size_t)b * 2 + a) * HW + hw] = (float)ub;
+      base[((size_t)b * D + a) * N + hw] = (float)ub;
       if (tgt) {
-        double ut = U[((size_t)t * 2 + a) * HW + hw];
-        tgt[i * 2 + a] = (float)((ut - ub) * inv_h);
+        double ut = U[((size_t)t * D + a) * N + hw];
+        tgt[i * D + a] = (float)((ut - ub) * inv_h);
       }
     }
-    for (int c = 7; c < kCinPad; ++c) o[c] = (bf16)0.f;
+    for (int c = 3 + 2 * D; c < kCinPad; ++c) o[c] = (bf16)0.f;
   }
 }
 
 // u_t = base + h * correction, written into the all-frame field Uout.
 __global__ void emit_kernel(const float* __restrict__ base,
                             const float* __restrict__ out,
-                            const int* __restrict__ tlr, int B, int H, int W,
-                            double h, float* __restrict__ Uout) {
-  const long long HW = (long long)H * W;
-  long long n = (long long)B * HW;
+                            const int* __restrict__ tlr, int B, int D,
+                            long long N, double h, float* __restrict__ Uout) {
+  long long n = (long long)B * N;
   long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
   long long st = (long long)gridDim.x * blockDim.x;
   for (; i < n; i += st) {
-    int b = (int)(i / HW);
-    long long hw = i - (long long)b * HW;
+    int b = (int)(i / N);
+    long long hw = i - (long long)b * N;
     int t = tlr[3 * b];
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-      Uout[((size_t)t * 2 + a) * HW + hw] =
-          (float)((double)base[((size_t)b * 2 + a) * HW + hw] +
+    for (int a = 0; a < D; ++a)
+      Uout[((size_t)t * D + a) * N + hw] =
+          (float)((double)base[((size_t)b * D + a) * N + hw] +
                   h * (double)out[i * kOutLd + a]);
   }
 }
@@ -659,15 +715,16 @@ struct Buf {
 };
 
 struct Layer {
-  int ci, co, k, ci_p, co_p;
+  int ci, co, k, taps, ci_p, co_p;
   size_t woff, boff;      // offsets into the flat parameter vector
   bf16 *Wt, *Wb;
 };
 
 }  // namespace
 
+// Frames are Z x H x W (Z = 1 for images), channels last.
 struct stml_net {
-  int dim = 2, maxB = 0, maxH = 0, maxW = 0;
+  int dim = 2, maxB = 0, maxZ = 1, maxH = 0, maxW = 0;
   hipStream_t stream = nullptr;
   size_t nparam = 0;
   float *master = nullptr, *m = nullptr, *v = nullptr, *grad = nullptr;
@@ -675,11 +732,10 @@ struct stml_net {
   // activations and gradients
   Buf xin, e1a, c1, p1, e2a, c2, p2, e3a, c3, p3, e4a, e4b, d3a, d3b, d2a,
       d2b, d1a, d1b;
-  float* out = nullptr;     // head output [P][16]
+  float* out = nullptr;     // head output [P][kOutLd]
   float* dout = nullptr;
-  float *g_p1 = nullptr, *g_p2 = nullptr, *g_p3 = nullptr;
-  float* base = nullptr;    // [B][2][H][W]
-  float* tgt = nullptr;     // [B][H][W][2]
+  float* base = nullptr;    // [B][D][N]
+  float* tgt = nullptr;     // [B][N][D]
   int* tlr = nullptr;       // device triples
   int* htlr = nullptr;      // pinned host staging
   float* wpart = nullptr;
@@ -691,7 +747,7 @@ struct stml_net {
   double* dloss = nullptr;
   double* hloss = nullptr;  // pinned
   int step = 0;
-  int curB = 0, curH = 0, curW = 0;
+  int curB = 0, curZ = 1, curH = 0, curW = 0;
 };
 
 namespace {
@@ -713,9 +769,13 @@ struct NetLayout {
 constexpr size_t kWpartCap = (size_t)6 << 20;   // floats of split partials
 constexpr int kBSplit = 1024;
 
-// Frames a batch may hold: every frame has at least 8 x 8 pixels.
+long long max_pixels(const stml_net* n) {
+  return (long long)n->maxB * n->maxZ * n->maxH * n->maxW;
+}
+
+// Frames a batch may hold: every frame has at least 8^d pixels.
 size_t max_frames(const stml_net* n) {
-  return (size_t)n->maxB * n->maxH * n->maxW / 64;
+  return (size_t)(max_pixels(n) / (n->dim == 3 ? 512 : 64));
 }
 
 size_t net_layout(stml_net* n, char* base) {
@@ -723,15 +783,16 @@ size_t net_layout(stml_net* n, char* base) {
   lo.base = base;
   size_t np = 0;
   for (int i = 0; i < kLayers; ++i) {
-    const LayerDef& d = kDefs[i];
+    const LayerDef d = layer_def(n->dim, i);
     Layer& l = n->L[i];
     l.ci = d.ci;
     l.co = d.co;
     l.k = d.k;
+    l.taps = layer_taps(n->dim, d.k);
     l.ci_p = rup(d.ci, 32);
     l.co_p = rup(d.co, 32);
     l.woff = np;
-    np += (size_t)d.k * d.k * d.co * d.ci;
+    np += (size_t)l.taps * d.co * d.ci;
     l.boff = np;
     np += d.co;
   }
@@ -742,13 +803,13 @@ size_t net_layout(stml_net* n, char* base) {
   n->grad = lo.take<float>(np);
   for (int i = 0; i < kLayers; ++i) {
     Layer& l = n->L[i];
-    size_t nw = (size_t)l.k * l.k * l.co_p * l.ci_p;
+    size_t nw = (size_t)l.taps * l.co_p * l.ci_p;
     l.Wt = lo.take<bf16>(nw);
     l.Wb = lo.take<bf16>(nw);
   }
-  const size_t P0 = (size_t)n->maxB * n->maxH * n->maxW;
+  const size_t P0 = (size_t)max_pixels(n);
   auto buf = [&](Buf& b, int ch, int level) {
-    size_t P = P0 >> (2 * level);
+    size_t P = P0 >> (n->dim * level);
     b.a = lo.take<bf16>(P * ch);
     b.g = lo.take<float>(P * ch);
     b.ld = ch;
@@ -774,8 +835,8 @@ size_t net_layout(stml_net* n, char* base) {
   buf(n->d1b, 32, 0);
   n->out = lo.take<float>(P0 * kOutLd);
   n->dout = lo.take<float>(P0 * kOutLd);
-  n->base = lo.take<float>(P0 * 2);
-  n->tgt = lo.take<float>(P0 * 2);
+  n->base = lo.take<float>(P0 * n->dim);
+  n->tgt = lo.take<float>(P0 * n->dim);
   n->tlr = lo.take<int>(3 * max_frames(n));
   n->wpart_cap = kWpartCap;
   n->wpart = lo.take<float>(kWpartCap);
@@ -792,41 +853,57 @@ size_t net_layout(stml_net* n, char* base) {
     if ((call) != hipSuccess) return STML_EDEVICE; \
   } while (0)
 
-// One convolution: K x K taps, input src (cin_p channels), weights
-// Wmat[tap][cout_p][cin_p], output Y (yld, yoff) in float32 or bfloat16.
-// 64-channel blocks (2 x 2 tiles per wave) when cout_p allows, else
-// 32-channel blocks of 512 pixels (4 x 1 tiles per wave).
+// Extents of resolution level lev (0 = full).
+struct Ext {
+  int z, h, w;
+  long long pix() const { return (long long)z * h * w; }
+};
+Ext level_ext(const stml_net* n, int Z, int H, int W, int lev) {
+  return Ext{n->dim == 3 ? Z >> lev : 1, H >> lev, W >> lev};
+}
+
+// One convolution: K x K (x K in 3-D) taps, input src (cin_p channels),
+// weights Wmat[tap][cout_p][cin_p], output Y (yld, yoff) in float32 or
+// bfloat16.  64-channel blocks (2 x 2 tiles per wave) when cout_p allows,
+// else 32-channel blocks of 512 pixels (4 x 1 tiles per wave).
 template <class TX>
 hipError_t conv_launch(stml_net* n, int K, const ConvSrc<TX>& src, int cin_p,
                        const bf16* Wmat, const float* bias, int cout,
                        int cout_p, void* Y, bool y_f32, int yld, int yoff,
-                       bool relu, int B, int H, int W) {
+                       bool relu, int B, Ext e) {
   if ((K != 1 && K != 3) || cin_p % 16 || cout_p % 32 || src.split % 16 ||
-      (K == 3 && W > kMaxConvW))
+      (K == 3 && e.w > kMaxConvW))
     return hipErrorInvalidValue;
+  const bool vol = n->dim == 3 && K == 3;
   const bool wide = cout_p % 64 == 0;
   const int TP = wide ? 256 : 512, COB = wide ? 64 : 32;
-  const int R = K == 3 ? W + 1 : 0;
+  const int R = K == 3 ? e.w + 1 : 0;
   const size_t lds = ((size_t)(TP + 2 * R) + (size_t)K * K * COB) * kRowLd *
                      sizeof(bf16);
-  const long long P = (long long)B * H * W;
+  const long long P = (long long)B * e.pix();
   dim3 grid((unsigned)((P + TP - 1) / TP), cout_p / COB);
   hipStream_t s = n->stream;
   constexpr bool F = std::is_same<TX, float>::value;
-#define CONV_CASE(KK, CSS, PSS, OF, RL)                                      \
-  conv_kernel<KK, CSS, PSS, TX, OF, RL><<<grid, 256, lds, s>>>(             \
-      src, cin_p, Wmat, bias, cout, cout_p, Y, yld, yoff, B, H, W)
+#define CONV_CASE(KK, KZ, CSS, PSS, OF, RL)                                  \
+  conv_kernel<KK, KZ, CSS, PSS, TX, OF, RL><<<grid, 256, lds, s>>>(         \
+      src, cin_p, Wmat, bias, cout, cout_p, Y, yld, yoff, B, e.z, e.h, e.w)
+#define CONV_DIMS(CSS, PSS, OF, RL)          \
+  do {                                       \
+    if (vol) CONV_CASE(3, 3, CSS, PSS, OF, RL); \
+    else CONV_CASE(3, 1, CSS, PSS, OF, RL);  \
+  } while (0)
   if (!F && K == 3 && !y_f32 && relu) {
-    if (wide) CONV_CASE(3, 2, 2, false, true);
-    else CONV_CASE(3, 1, 4, false, true);
+    if (wide) CONV_DIMS(2, 2, false, true);
+    else CONV_DIMS(1, 4, false, true);
   } else if (K == 3 && y_f32 && !relu) {
-    if (wide) CONV_CASE(3, 2, 2, true, false);
-    else CONV_CASE(3, 1, 4, true, false);
+    if (wide) CONV_DIMS(2, 2, true, false);
+    else CONV_DIMS(1, 4, true, false);
   } else if (K == 1 && y_f32 && !relu && !wide) {
-    CONV_CASE(1, 1, 4, true, false);
+    CONV_CASE(1, 1, 1, 4, true, false);
   } else {
     return hipErrorInvalidValue;
   }
+#undef CONV_DIMS
 #undef CONV_CASE
   return hipGetLastError();
 }
@@ -840,21 +917,47 @@ ConvSrc<bf16> cat_src(const Buf& b, int skipC, const Buf& low) {
   return ConvSrc<bf16>{b.a, b.ld, 0, low.a, low.ld, 0, skipC};
 }
 
-// Forward through every layer for B images of H x W (multiples of 8).
-int net_forward(stml_net* n, int B, int H, int W) {
+template <class... A>
+hipError_t pool_launch(int dim, long long nthreads, hipStream_t s, A... a) {
+  if (dim == 3)
+    pool_kernel<2><<<gridsz(nthreads), 256, 0, s>>>(a...);
+  else
+    pool_kernel<1><<<gridsz(nthreads), 256, 0, s>>>(a...);
+  return hipGetLastError();
+}
+template <class... A>
+hipError_t pool_bwd_launch(int dim, long long nthreads, hipStream_t s,
+                           A... a) {
+  if (dim == 3)
+    pool_bwd_add_kernel<2><<<gridsz(nthreads), 256, 0, s>>>(a...);
+  else
+    pool_bwd_add_kernel<1><<<gridsz(nthreads), 256, 0, s>>>(a...);
+  return hipGetLastError();
+}
+template <class... A>
+hipError_t up_bwd_launch(int dim, long long nthreads, hipStream_t s, A... a) {
+  if (dim == 3)
+    up_bwd_kernel<2><<<gridsz(nthreads), 256, 0, s>>>(a...);
+  else
+    up_bwd_kernel<1><<<gridsz(nthreads), 256, 0, s>>>(a...);
+  return hipGetLastError();
+}
+
+// Forward through every layer for B frames of Z x H x W (multiples of 8).
+int net_forward(stml_net* n, int B, int Z, int H, int W) {
   auto conv3 = [&](int li, const ConvSrc<bf16>& in, int lev, Buf& outb,
                    int ooff) {
     const Layer& l = n->L[li];
     return conv_launch(n, 3, in, l.ci_p, l.Wt, n->master + l.boff, l.co,
-                       l.co_p, outb.a, false, outb.ld, ooff, true, B, H >> lev,
-                       W >> lev);
+                       l.co_p, outb.a, false, outb.ld, ooff, true, B,
+                       level_ext(n, Z, H, W, lev));
   };
   auto pool = [&](const Buf& in, int ioff, int C, Buf& outb) {
-    int lev = in.level;
-    int h = H >> lev, w = W >> lev;
-    pool_kernel<<<gridsz((long long)B * h * w * C / 4), 256, 0, n->stream>>>(
-        in.a, in.ld, ioff, C, B, h, w, outb.a, outb.ld);
-    return hipGetLastError();
+    const Ext e = level_ext(n, Z, H, W, in.level);
+    return pool_launch(n->dim, ((long long)B * e.pix() >> n->dim) * C,
+                       n->stream,
+                       (const bf16*)in.a, in.ld, ioff, C, B, e.z, e.h,
+                       e.w, outb.a, outb.ld);
   };
   NET_OK(conv3(E1A, one_src(n->xin, 0, 32), 0, n->e1a, 0));
   NET_OK(conv3(E1B, one_src(n->e1a, 0, 32), 0, n->c1, 0));
@@ -876,17 +979,17 @@ int net_forward(stml_net* n, int B, int H, int W) {
   const Layer& h = n->L[HEAD];
   NET_OK(conv_launch(n, 1, one_src(n->d1b, 0, 32), h.ci_p, h.Wt,
                      n->master + h.boff, h.co, h.co_p, n->out, true, kOutLd,
-                     0, false, B, H, W));
+                     0, false, B, level_ext(n, Z, H, W, 0)));
   return STML_OK;
 }
 
 // Weight and bias gradient of layer li from dPre (ld, off) and its input X.
 int layer_wgrad(stml_net* n, int li, const float* dP, int pld, int poff,
-                const ConvSrc<bf16>& X, int B, int h, int w,
-                const AdamArgs& a, bool copy_grad) {
+                const ConvSrc<bf16>& X, int B, Ext e, const AdamArgs& a,
+                bool copy_grad) {
   const Layer& l = n->L[li];
-  const int K2 = l.k * l.k;
-  const long long P = (long long)B * h * w;
+  const int K2 = l.taps;
+  const long long P = (long long)B * e.pix();
   const long long nchunks = (P + kWChunk - 1) / kWChunk;
   const int nco = (l.co_p + 63) / 64, nci = (l.ci_p + 63) / 64;
   const int gy = K2 * nco * nci;
@@ -899,14 +1002,16 @@ int layer_wgrad(stml_net* n, int li, const float* dP, int pld, int poff,
   const long long cps = (nchunks + ns - 1) / ns;
   ns = (nchunks + cps - 1) / cps;
   dim3 grid((unsigned)ns, gy);
-  if (l.k == 3)
-    wgrad_kernel<3><<<grid, 256, 0, n->stream>>>(dP, pld, poff, l.co_p, X,
-                                                 l.ci_p, B, h, w, (int)cps,
-                                                 n->wpart);
+#define WGRAD(KK, KZ)                                                     \
+  wgrad_kernel<KK, KZ><<<grid, 256, 0, n->stream>>>(                      \
+      dP, pld, poff, l.co_p, X, l.ci_p, B, e.z, e.h, e.w, (int)cps, n->wpart)
+  if (l.k == 3 && n->dim == 3)
+    WGRAD(3, 3);
+  else if (l.k == 3)
+    WGRAD(3, 1);
   else
-    wgrad_kernel<1><<<grid, 256, 0, n->stream>>>(dP, pld, poff, l.co_p, X,
-                                                 l.ci_p, B, h, w, (int)cps,
-                                                 n->wpart);
+    WGRAD(1, 1);
+#undef WGRAD
   NET_OK(hipGetLastError());
   const long long pps = (P + kBSplit - 1) / kBSplit;
   const int bs = (int)((P + pps - 1) / pps);
@@ -929,12 +1034,12 @@ int layer_wgrad(stml_net* n, int li, const float* dP, int pld, int poff,
 // input is in (its first skipC channels) followed, when low is given, by
 // the upsampled channels of low.
 int conv_back(stml_net* n, int li, Buf& outb, int ooff, const Buf& in,
-              float* dX, int dld, int B, int H, int W, const AdamArgs& a,
-              bool copy_grad, const Buf* low = nullptr, int skipC = 0) {
+              float* dX, int dld, int B, int Z, int H, int W,
+              const AdamArgs& a, bool copy_grad, const Buf* low = nullptr,
+              int skipC = 0) {
   const Layer& l = n->L[li];
-  const int lev = in.level;
-  const int h = H >> lev, w = W >> lev;
-  const long long P = (long long)B * h * w;
+  const Ext e = level_ext(n, Z, H, W, in.level);
+  const long long P = (long long)B * e.pix();
   relu_bwd_kernel<<<gridsz(P * l.co), 256, 0, n->stream>>>(
       outb.g, outb.ld, ooff, outb.a, outb.ld, ooff, l.co_p, P);
   NET_OK(hipGetLastError());
@@ -945,10 +1050,10 @@ int conv_back(stml_net* n, int li, Buf& outb, int ooff, const Buf& in,
                        ConvSrc<float>{outb.g + ooff, outb.ld, 0, nullptr, 0,
                                       0, l.co_p},
                        l.co_p, l.Wb, nullptr, l.ci_p, l.ci_p, dX, true, dld, 0,
-                       false, B, h, w));
+                       false, B, e));
   const ConvSrc<bf16> X = low ? cat_src(in, skipC, *low)
                               : one_src(in, 0, l.ci_p);
-  return layer_wgrad(n, li, outb.g, outb.ld, ooff, X, B, h, w, a, copy_grad);
+  return layer_wgrad(n, li, outb.g, outb.ld, ooff, X, B, e, a, copy_grad);
 }
 
 }  // namespace
@@ -956,31 +1061,50 @@ int conv_back(stml_net* n, int li, Buf& outb, int ooff, const Buf& in,
 namespace stml {
 void net_capacity(const stml_net* n, int* max_batch, long long* max_pixels) {
   *max_batch = n->maxB;
-  *max_pixels = (long long)n->maxB * n->maxH * n->maxW;
+  *max_pixels = ::max_pixels(n);
 }
+int net_dim(const stml_net* n) { return n->dim; }
 }  // namespace stml
 
 // ================================================================ C-ABI
 
+namespace {
+
+// Frame extent of a batch: (H, W) in 2-D, (Z, H, W) in 3-D; every extent a
+// multiple of 8 (three poolings), the fastest at most kMaxConvW.
+bool parse_ext(int dim, const int* ext, int* Z, int* H, int* W) {
+  if (!ext || (dim != 2 && dim != 3)) return false;
+  for (int a = 0; a < dim; ++a)
+    if (ext[a] < 8 || ext[a] % 8) return false;
+  *Z = dim == 3 ? ext[0] : 1;
+  *H = ext[dim - 2];
+  *W = ext[dim - 1];
+  return *W <= kMaxConvW;
+}
+
+}  // namespace
+
 extern "C" {
 
 int stml_net_param_count(int dim) {
-  if (dim != 2) return STML_EINVAL;
+  if (dim != 2 && dim != 3) return STML_EINVAL;
   int np = 0;
-  for (int i = 0; i < kLayers; ++i)
-    np += kDefs[i].k * kDefs[i].k * kDefs[i].co * kDefs[i].ci + kDefs[i].co;
+  for (int i = 0; i < kLayers; ++i) {
+    const LayerDef d = layer_def(dim, i);
+    np += layer_taps(dim, d.k) * d.co * d.ci + d.co;
+  }
   return np;
 }
 
 size_t stml_net_workspace_bytes(int dim, int max_batch, const int* ext) {
-  if (dim != 2 || max_batch < 1 || !ext || ext[0] < 8 || ext[1] < 8 ||
-      ext[0] % 8 || ext[1] % 8 || ext[1] > kMaxConvW)
-    return 0;
+  int Z, H, W;
+  if (max_batch < 1 || !parse_ext(dim, ext, &Z, &H, &W)) return 0;
   stml_net tmp;
   tmp.dim = dim;
   tmp.maxB = max_batch;
-  tmp.maxH = ext[0];
-  tmp.maxW = ext[1];
+  tmp.maxZ = Z;
+  tmp.maxH = H;
+  tmp.maxW = W;
   return net_layout(&tmp, nullptr);
 }
 
@@ -994,8 +1118,7 @@ int stml_net_create(int dim, int max_batch, const int* ext, void* stream,
   stml_net* n = new stml_net();
   n->dim = dim;
   n->maxB = max_batch;
-  n->maxH = ext[0];
-  n->maxW = ext[1];
+  parse_ext(dim, ext, &n->maxZ, &n->maxH, &n->maxW);
   n->stream = (hipStream_t)stream;
   net_layout(n, (char*)ws);
   if (hipHostMalloc((void**)&n->htlr, 3 * sizeof(int) * max_frames(n),
@@ -1032,9 +1155,9 @@ int stml_net_set_params(stml_net* n, const float* params) {
   zero_f32_kernel<<<2048, 256, 0, n->stream>>>(n->v, n->nparam);
   for (int i = 0; i < kLayers; ++i) {
     const Layer& l = n->L[i];
-    int ne = l.k * l.k * l.co * l.ci;
+    int ne = l.taps * l.co * l.ci;
     weights_from_master_kernel<<<(ne + 255) / 256, 256, 0, n->stream>>>(
-        n->master + l.woff, l.k * l.k, l.co, l.ci, l.co_p, l.ci_p, l.Wt, l.Wb);
+        n->master + l.woff, l.taps, l.co, l.ci, l.co_p, l.ci_p, l.Wt, l.Wb);
   }
   n->step = 0;
   NET_OK(hipGetLastError());
@@ -1050,10 +1173,10 @@ int stml_net_get_params(const stml_net* n, float* params) {
   return STML_OK;
 }
 
-static int check_shape(const stml_net* n, int B, const int* ext) {
-  if (!ext || B < 1 || ext[0] % 8 || ext[1] % 8 || ext[0] < 8 ||
-      ext[1] < 8 || ext[1] > kMaxConvW ||
-      (long long)B * ext[0] * ext[1] > (long long)n->maxB * n->maxH * n->maxW)
+static int check_shape(const stml_net* n, int B, const int* ext, int* Z,
+                       int* H, int* W) {
+  if (B < 1 || !parse_ext(n->dim, ext, Z, H, W) ||
+      (long long)B * *Z * *H * *W > max_pixels(n))
     return STML_EINVAL;
   return STML_OK;
 }
@@ -1061,16 +1184,17 @@ static int check_shape(const stml_net* n, int B, const int* ext) {
 int stml_net_set_input(stml_net* n, const float* x, int C, const float* tgt,
                        int B, const int* ext) {
   if (!n || !x || C < 1 || C > kCinPad) return STML_EINVAL;
-  if (check_shape(n, B, ext)) return STML_EINVAL;
-  const int H = ext[0], W = ext[1];
-  long long P = (long long)B * H * W;
-  pack_input_kernel<<<gridsz(P * kCinPad), 256, 0, n->stream>>>(x, C, B, H, W,
+  int Z, H, W;
+  if (check_shape(n, B, ext, &Z, &H, &W)) return STML_EINVAL;
+  const long long N = (long long)Z * H * W, P = (long long)B * N;
+  pack_input_kernel<<<gridsz(P * kCinPad), 256, 0, n->stream>>>(x, C, B, N,
                                                                 n->xin.a);
   NET_OK(hipGetLastError());
   if (tgt)
-    NET_OK(hipMemcpyAsync(n->tgt, tgt, P * 2 * sizeof(float),
+    NET_OK(hipMemcpyAsync(n->tgt, tgt, P * n->dim * sizeof(float),
                           hipMemcpyDeviceToDevice, n->stream));
   n->curB = B;
+  n->curZ = Z;
   n->curH = H;
   n->curW = W;
   NET_OK(hipStreamSynchronize(n->stream));
@@ -1082,7 +1206,8 @@ int stml_net_assemble(stml_net* n, const float* T, const float* U,
                       const int* triples, int B, int with_target) {
   if (!n || !T || !U || !triples || !(h > 0) || n_frames < 3)
     return STML_EINVAL;
-  if (check_shape(n, B, ext)) return STML_EINVAL;
+  int Z, H, W;
+  if (check_shape(n, B, ext, &Z, &H, &W)) return STML_EINVAL;
   for (int b = 0; b < B; ++b) {
     const int t = triples[3 * b], l = triples[3 * b + 1],
               r = triples[3 * b + 2];
@@ -1091,12 +1216,13 @@ int stml_net_assemble(stml_net* n, const float* T, const float* U,
   for (int i = 0; i < 3 * B; ++i) n->htlr[i] = triples[i];
   NET_OK(hipMemcpyAsync(n->tlr, n->htlr, 3 * B * sizeof(int),
                         hipMemcpyHostToDevice, n->stream));
-  const int H = ext[0], W = ext[1];
-  assemble_kernel<<<gridsz((long long)B * H * W), 256, 0, n->stream>>>(
-      T, U, n->tlr, B, H, W, 1.0 / h, n->xin.a, n->base,
+  const long long N = (long long)Z * H * W;
+  assemble_kernel<<<gridsz((long long)B * N), 256, 0, n->stream>>>(
+      T, U, n->tlr, B, n->dim, N, 1.0 / h, n->xin.a, n->base,
       with_target ? n->tgt : nullptr);
   NET_OK(hipGetLastError());
   n->curB = B;
+  n->curZ = Z;
   n->curH = H;
   n->curW = W;
   NET_OK(hipStreamSynchronize(n->stream));
@@ -1105,12 +1231,12 @@ int stml_net_assemble(stml_net* n, const float* T, const float* U,
 
 int stml_net_forward(stml_net* n, float* out) {
   if (!n || !n->curB) return STML_ESTATE;
-  int rc = net_forward(n, n->curB, n->curH, n->curW);
+  int rc = net_forward(n, n->curB, n->curZ, n->curH, n->curW);
   if (rc) return rc;
   if (out)
     NET_OK(hipMemcpyAsync(out, n->out,
-                          (size_t)n->curB * n->curH * n->curW * kOutLd *
-                              sizeof(float),
+                          (size_t)n->curB * n->curZ * n->curH * n->curW *
+                              kOutLd * sizeof(float),
                           hipMemcpyDeviceToDevice, n->stream));
   NET_OK(hipStreamSynchronize(n->stream));
   return STML_OK;
@@ -1118,9 +1244,9 @@ int stml_net_forward(stml_net* n, float* out) {
 
 int stml_net_emit(stml_net* n, double h, float* U) {
   if (!n || !n->curB || !U) return STML_ESTATE;
-  emit_kernel<<<gridsz((long long)n->curB * n->curH * n->curW), 256, 0,
-                n->stream>>>(n->base, n->out, n->tlr, n->curB, n->curH,
-                             n->curW, h, U);
+  const long long N = (long long)n->curZ * n->curH * n->curW;
+  emit_kernel<<<gridsz((long long)n->curB * N), 256, 0, n->stream>>>(
+      n->base, n->out, n->tlr, n->curB, n->dim, N, h, U);
   NET_OK(hipGetLastError());
   NET_OK(hipStreamSynchronize(n->stream));
   return STML_OK;
@@ -1129,12 +1255,15 @@ int stml_net_emit(stml_net* n, double h, float* U) {
 // forward + loss + backward; Adam if lr > 0; gradient copy if grad != NULL
 static int net_step(stml_net* n, double lr, float* grad, double* loss) {
   if (!n->curB) return STML_ESTATE;
-  const int B = n->curB, H = n->curH, W = n->curW;
-  int rc = net_forward(n, B, H, W);
+  const int B = n->curB, Z = n->curZ, H = n->curH, W = n->curW;
+  const int dim = n->dim;
+  int rc = net_forward(n, B, Z, H, W);
   if (rc) return rc;
-  const long long P = (long long)B * H * W;
+  const Ext e0 = level_ext(n, Z, H, W, 0), e1 = level_ext(n, Z, H, W, 1),
+            e2 = level_ext(n, Z, H, W, 2), e3 = level_ext(n, Z, H, W, 3);
+  const long long P = (long long)B * e0.pix();
   int lb = gridsz(P);
-  loss_kernel<<<lb, 256, 0, n->stream>>>(n->out, n->tgt, P, n->dout,
+  loss_kernel<<<lb, 256, 0, n->stream>>>(n->out, n->tgt, P, dim, n->dout,
                                          n->lpart);
   loss_final_kernel<<<1, 64, 0, n->stream>>>(n->lpart, lb, n->dloss);
   NET_OK(hipGetLastError());
@@ -1148,6 +1277,7 @@ static int net_step(stml_net* n, double lr, float* grad, double* loss) {
   a.c1 = a.apply ? (float)(1.0 / (1.0 - std::pow(0.9, n->step))) : 1.f;
   a.c2 = a.apply ? (float)(1.0 / (1.0 - std::pow(0.999, n->step))) : 1.f;
   const bool cg = grad != nullptr;
+  hipStream_t s = n->stream;
   // head: dout -> d1b gradient; weight gradient from dout and d1b
   {
     const Layer& l = n->L[HEAD];
@@ -1155,70 +1285,70 @@ static int net_step(stml_net* n, double lr, float* grad, double* loss) {
                        ConvSrc<float>{n->dout, kOutLd, 0, nullptr, 0, 0,
                                       l.co_p},
                        l.co_p, l.Wb, nullptr, l.ci_p, l.ci_p, n->d1b.g, true,
-                       32, 0, false, B, H, W));
+                       32, 0, false, B, e0));
     rc = layer_wgrad(n, HEAD, n->dout, kOutLd, 0, one_src(n->d1b, 0, 32), B,
-                     H, W, a, cg);
+                     e0, a, cg);
     if (rc) return rc;
   }
   // decoder 1
-  if ((rc = conv_back(n, D1B, n->d1b, 0, n->d1a, n->d1a.g, 32, B, H, W, a,
-                      cg)))
+  if ((rc = conv_back(n, D1B, n->d1b, 0, n->d1a, n->d1a.g, 32, B, Z, H, W,
+                      a, cg)))
     return rc;
-  if ((rc = conv_back(n, D1A, n->d1a, 0, n->c1, n->c1.g, 96, B, H, W, a,
+  if ((rc = conv_back(n, D1A, n->d1a, 0, n->c1, n->c1.g, 96, B, Z, H, W, a,
                       cg, &n->d2b, 32)))
     return rc;
-  up_bwd_kernel<<<gridsz(P / 4 * 64), 256, 0, n->stream>>>(
-      n->c1.g, 96, 32, 64, B, H, W, n->d2b.g);
+  NET_OK(up_bwd_launch(dim, B * e1.pix() * 64, s, (const float*)n->c1.g, 96,
+                       32, 64, B, e0.z, e0.h, e0.w, n->d2b.g));
   // decoder 2
-  if ((rc = conv_back(n, D2B, n->d2b, 0, n->d2a, n->d2a.g, 64, B, H, W, a,
-                      cg)))
+  if ((rc = conv_back(n, D2B, n->d2b, 0, n->d2a, n->d2a.g, 64, B, Z, H, W,
+                      a, cg)))
     return rc;
-  if ((rc = conv_back(n, D2A, n->d2a, 0, n->c2, n->c2.g, 192, B, H, W, a,
+  if ((rc = conv_back(n, D2A, n->d2a, 0, n->c2, n->c2.g, 192, B, Z, H, W, a,
                       cg, &n->d3b, 64)))
     return rc;
-  up_bwd_kernel<<<gridsz(P / 16 * 128), 256, 0, n->stream>>>(
-      n->c2.g, 192, 64, 128, B, H / 2, W / 2, n->d3b.g);
+  NET_OK(up_bwd_launch(dim, B * e2.pix() * 128, s, (const float*)n->c2.g,
+                       192, 64, 128, B, e1.z, e1.h, e1.w, n->d3b.g));
   // decoder 3
-  if ((rc = conv_back(n, D3B, n->d3b, 0, n->d3a, n->d3a.g, 128, B, H, W,
+  if ((rc = conv_back(n, D3B, n->d3b, 0, n->d3a, n->d3a.g, 128, B, Z, H, W,
                       a, cg)))
     return rc;
-  if ((rc = conv_back(n, D3A, n->d3a, 0, n->c3, n->c3.g, 256, B, H, W, a,
+  if ((rc = conv_back(n, D3A, n->d3a, 0, n->c3, n->c3.g, 256, B, Z, H, W, a,
                       cg, &n->e4b, 128)))
     return rc;
-  up_bwd_kernel<<<gridsz(P / 64 * 128), 256, 0, n->stream>>>(
-      n->c3.g, 256, 128, 128, B, H / 4, W / 4, n->e4b.g);
+  NET_OK(up_bwd_launch(dim, B * e3.pix() * 128, s, (const float*)n->c3.g,
+                       256, 128, 128, B, e2.z, e2.h, e2.w, n->e4b.g));
   // encoder 4 (bottom)
-  if ((rc = conv_back(n, E4B, n->e4b, 0, n->e4a, n->e4a.g, 128, B, H, W,
+  if ((rc = conv_back(n, E4B, n->e4b, 0, n->e4a, n->e4a.g, 128, B, Z, H, W,
                       a, cg)))
     return rc;
-  if ((rc = conv_back(n, E4A, n->e4a, 0, n->p3, n->p3.g, 128, B, H, W, a,
+  if ((rc = conv_back(n, E4A, n->e4a, 0, n->p3, n->p3.g, 128, B, Z, H, W, a,
                       cg)))
     return rc;
-  pool_bwd_add_kernel<<<gridsz(P / 16 * 128), 256, 0, n->stream>>>(
-      n->p3.g, 128, B, H / 4, W / 4, n->c3.g, 256, 0);
+  NET_OK(pool_bwd_launch(dim, B * e2.pix() * 128, s, (const float*)n->p3.g,
+                         128, B, e2.z, e2.h, e2.w, n->c3.g, 256, 0));
   // encoder 3
-  if ((rc = conv_back(n, E3B, n->c3, 0, n->e3a, n->e3a.g, 128, B, H, W, a,
+  if ((rc = conv_back(n, E3B, n->c3, 0, n->e3a, n->e3a.g, 128, B, Z, H, W,
+                      a, cg)))
+    return rc;
+  if ((rc = conv_back(n, E3A, n->e3a, 0, n->p2, n->p2.g, 64, B, Z, H, W, a,
                       cg)))
     return rc;
-  if ((rc = conv_back(n, E3A, n->e3a, 0, n->p2, n->p2.g, 64, B, H, W, a,
-                      cg)))
-    return rc;
-  pool_bwd_add_kernel<<<gridsz(P / 4 * 64), 256, 0, n->stream>>>(
-      n->p2.g, 64, B, H / 2, W / 2, n->c2.g, 192, 0);
+  NET_OK(pool_bwd_launch(dim, B * e1.pix() * 64, s, (const float*)n->p2.g,
+                         64, B, e1.z, e1.h, e1.w, n->c2.g, 192, 0));
   // encoder 2
-  if ((rc = conv_back(n, E2B, n->c2, 0, n->e2a, n->e2a.g, 64, B, H, W, a,
+  if ((rc = conv_back(n, E2B, n->c2, 0, n->e2a, n->e2a.g, 64, B, Z, H, W, a,
                       cg)))
     return rc;
-  if ((rc = conv_back(n, E2A, n->e2a, 0, n->p1, n->p1.g, 32, B, H, W, a,
+  if ((rc = conv_back(n, E2A, n->e2a, 0, n->p1, n->p1.g, 32, B, Z, H, W, a,
                       cg)))
     return rc;
-  pool_bwd_add_kernel<<<gridsz(P * 32), 256, 0, n->stream>>>(
-      n->p1.g, 32, B, H, W, n->c1.g, 96, 0);
+  NET_OK(pool_bwd_launch(dim, B * e0.pix() * 32, s, (const float*)n->p1.g,
+                         32, B, e0.z, e0.h, e0.w, n->c1.g, 96, 0));
   // encoder 1
-  if ((rc = conv_back(n, E1B, n->c1, 0, n->e1a, n->e1a.g, 32, B, H, W, a,
+  if ((rc = conv_back(n, E1B, n->c1, 0, n->e1a, n->e1a.g, 32, B, Z, H, W, a,
                       cg)))
     return rc;
-  if ((rc = conv_back(n, E1A, n->e1a, 0, n->xin, nullptr, 0, B, H, W, a,
+  if ((rc = conv_back(n, E1A, n->e1a, 0, n->xin, nullptr, 0, B, Z, H, W, a,
                       cg)))
     return rc;
   NET_OK(hipGetLastError());

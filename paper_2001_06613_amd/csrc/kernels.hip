@@ -67,19 +67,18 @@ int tile_blocks(const Geom& g) {
 }
 
 // Waves per block split the frames of K; more waves shorten the per-wave
-// frame loops (latency) at the cost of registers: up to 16 (2D Hessian
-// product), 8 (2D evaluation) or 4.
-static int waves_for(int nK, int maxg) {
-  int G = nK < maxg ? nK : maxg;
-  return G < 1 ? 1 : G;
-}
-// 2-D launches use a fixed block size (waves without frames idle), so that
-// a problem gets the same blocks, and the same rounding, alone and batched.
+// frame loops (latency) at the cost of registers: 8 for the 2-D evaluation,
+// 4 otherwise.  The block size does not depend on |K| (waves without frames
+// idle), so that a problem gets the same blocks, and the same rounding,
+// alone and batched.
 int tile_threads(int dim, int nK) {
-  return (dim == 2 ? 4 : waves_for(nK, 4)) * kWave;
+  (void)dim;
+  (void)nK;
+  return 4 * kWave;
 }
 int eval_threads(int dim, int nK) {
-  return (dim == 2 ? 8 : waves_for(nK, 4)) * kWave;
+  (void)nK;
+  return (dim == 2 ? 8 : 4) * kWave;
 }
 
 #define STML_DIM_DISPATCH(dim, KERNEL, GRID, BLOCK, STREAM, ...)          \
@@ -699,7 +698,7 @@ __global__ __launch_bounds__(64) void ls_predict_kernel(
   }
 }
 
-// ------------------------------------------------- batched 2-D iteration
+// ------------------------------------------------------ batched iteration
 
 // Problem of block b: the j with first[j] <= b < first[j + 1].
 __device__ __forceinline__ int job_index(const int* __restrict__ f, int n,
@@ -723,14 +722,15 @@ __device__ __forceinline__ const Job& job_of(const JobSet& js, int c,
   return js.jobs[j];
 }
 
-template <int REG>
-__global__ __launch_bounds__(512) void eval_batch_kernel(JobSet js) {
+template <int D, int REG>
+__global__ __launch_bounds__(D == 2 ? 512 : 256) void eval_batch_kernel(
+    JobSet js) {
   Blk blk;
   const Job& J = job_of(js, kClsTile, blk);
   const Geom g = J.g;
   const Model md = J.md;
   Scal* sc = J.sc;
-  eval_body<2, REG>(J.T, J.u, J.K, g, md, J.grad, J.dW,
+  eval_body<D, REG>(J.T, J.u, J.K, g, md, J.grad, J.dW,
                     J.rb.region(kRegEval), sc->gn_cur, sc, blk);
 }
 
@@ -743,7 +743,7 @@ __global__ __launch_bounds__(256) void start_batch_kernel(JobSet js) {
                       J.log);
 }
 
-template <int REG>
+template <int D, int REG>
 __global__ __launch_bounds__(256) void trial_batch_kernel(JobSet js, Steps st,
                                                           LSPass ls) {
   Blk blk;
@@ -751,7 +751,7 @@ __global__ __launch_bounds__(256) void trial_batch_kernel(JobSet js, Steps st,
   const Geom g = J.g;
   const Model md = J.md;
   Scal* sc = J.sc;
-  trial_body<2, REG>(J.T, J.u, J.x, J.grad, J.K, g, md, st,
+  trial_body<D, REG>(J.T, J.u, J.x, J.grad, J.K, g, md, st,
                      J.rb.region(kRegTrial), sc->gn_cur, ls, sc, J.log, blk);
 }
 
@@ -771,8 +771,8 @@ __global__ __launch_bounds__(256) void accept_batch_kernel(
   Blk blk;
   const Job& J = job_of(js, kClsElem, blk);
   Scal* sc = J.sc;
-  ls_accept_body(J.u, J.x, J.K, J.md.nK, 2, J.g.N, st, ls, ls_max, c1, fixed,
-                 tol_J, tol_u, sc->gn_cur, sc, J.log, blk);
+  ls_accept_body(J.u, J.x, J.K, J.md.nK, geom_dim(J.g), J.g.N, st, ls,
+                 ls_max, c1, fixed, tol_J, tol_u, sc->gn_cur, sc, J.log, blk);
 }
 
 // Start of a batched registration: per problem, every iteration enabled,
@@ -810,11 +810,10 @@ hipError_t batch_gn_reset(const JobSet& js, int gn_max, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t batch_eval(const JobSet& js, int nblocks, int reg, hipStream_t s) {
-  if (reg == 0)
-    eval_batch_kernel<0><<<nblocks, eval_threads(2, 0), 0, s>>>(js);
-  else
-    eval_batch_kernel<1><<<nblocks, eval_threads(2, 0), 0, s>>>(js);
+hipError_t batch_eval(const JobSet& js, int nblocks, int dim, int reg,
+                      hipStream_t s) {
+  STML_TILE_DISPATCH(dim, reg, eval_batch_kernel, nblocks,
+                     eval_threads(dim, 0), s, js);
   return hipGetLastError();
 }
 
@@ -823,14 +822,12 @@ hipError_t batch_finalize_start(const JobSet& js, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t batch_trial(const JobSet& js, int ntile, int reg, const double* t,
-                       LSPass ls, hipStream_t s) {
+hipError_t batch_trial(const JobSet& js, int ntile, int dim, int reg,
+                       const double* t, LSPass ls, hipStream_t s) {
   Steps st;
   for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
-  if (reg == 0)
-    trial_batch_kernel<0><<<ntile, tile_threads(2, 0), 0, s>>>(js, st, ls);
-  else
-    trial_batch_kernel<1><<<ntile, tile_threads(2, 0), 0, s>>>(js, st, ls);
+  STML_TILE_DISPATCH(dim, reg, trial_batch_kernel, ntile,
+                     tile_threads(dim, 0), s, js, st, ls);
   trial_final_batch_kernel<<<js.n, 256, 0, s>>>(js, st, ls);
   return hipGetLastError();
 }

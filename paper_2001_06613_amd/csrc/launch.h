@@ -132,15 +132,15 @@ hipError_t launch_ls_predict(float* Y, float* Z, ThomasTab tab, int n,
 //
 // One problem of a batched launch: the subset K of one sequence at one
 // level, with that sequence's own solver vectors, reduction slots, scalars
-// and log.  Every kernel of a 2-D Gauss-Newton iteration has a batched
-// form that serves all problems in one launch: the blocks of a launch are
+// and log.  Every kernel of a Gauss-Newton iteration has a batched form that
+// serves all problems (all 2-D or all 3-D) in one launch: the blocks of a launch are
 // dealt to the problems in order (first[c][j] .. first[c][j+1] for kernel
 // class c), each problem getting exactly the blocks (and hence the sums) it
 // gets alone.  The iteration index is read from the problem's scalars
 // (gn_cur), so one captured iteration can be replayed.
 struct Job {
   const float* T;        // level frames [n][N]
-  float* u;              // displacements [n][2][N]
+  float* u;              // displacements [n][D][N]
   const int* K;          // frames of the subset
   Geom g;
   Model md;
@@ -149,7 +149,7 @@ struct Job {
   RedBuf rb;
   Scal* sc;
   GNLog* log;
-  long long count;       // |K| 2 N
+  long long count;       // |K| D N
   int nb_tile, nb_vox, nb_elem;
   CgTiles ct;
 };
@@ -164,13 +164,15 @@ struct JobSet {
 void job_shape(Job* job);
 int elem_grid(long long count);
 hipError_t batch_gn_reset(const JobSet& js, int gn_max, hipStream_t s);
-hipError_t batch_eval(const JobSet& js, int nblocks, int reg, hipStream_t s);
-hipError_t batch_cg_init(const JobSet& js, int nvox, hipStream_t s);
-hipError_t batch_cg_hvp(const JobSet& js, int nhv, int reg, int it,
+hipError_t batch_eval(const JobSet& js, int nblocks, int dim, int reg,
+                      hipStream_t s);
+hipError_t batch_cg_init(const JobSet& js, int nvox, int dim, hipStream_t s);
+hipError_t batch_cg_hvp(const JobSet& js, int nhv, int dim, int reg, int it,
                         int fixed, double rtol, hipStream_t s);
-hipError_t batch_cg_update(const JobSet& js, int nvox, int it, hipStream_t s);
-hipError_t batch_trial(const JobSet& js, int ntile, int reg, const double* t,
-                       LSPass ls, hipStream_t s);
+hipError_t batch_cg_update(const JobSet& js, int nvox, int dim, int it,
+                           hipStream_t s);
+hipError_t batch_trial(const JobSet& js, int ntile, int dim, int reg,
+                       const double* t, LSPass ls, hipStream_t s);
 hipError_t batch_accept(const JobSet& js, int nelem, const double* t,
                         LSPass ls, int ls_max, double c1, int fixed,
                         double tol_J, double tol_u, hipStream_t s);
@@ -179,5 +181,7 @@ hipError_t batch_advance(const JobSet& js, int* stop_out, hipStream_t s);
 // Capacity of a learned-predictor net (cnn.hip): the batch it was created
 // for and the pixels a batch may hold in total (frames x pixels per frame).
 void net_capacity(const stml_net* n, int* max_batch, long long* max_pixels);
+int net_dim(const stml_net* n);
+constexpr int kMaxNetWidth = 256;   // widest frame row the net accepts
 
 }  // namespace stml

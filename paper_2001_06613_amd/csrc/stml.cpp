@@ -585,13 +585,14 @@ int objective_on(stml_ctx* c, int level, int q, const float* U, double* J) {
 }
 
 bool net_fits(const stml_ctx* c, int level) {
-  if (!c->net || !c->ureg || c->d != 2) return false;
+  if (!c->net || !c->ureg || net_dim(c->net) != c->d) return false;
   int maxB = 0;
   long long maxpix = 0;
   net_capacity(c->net, &maxB, &maxpix);
   const std::vector<int>& e = c->ext[level];
-  return e[0] % 8 == 0 && e[1] % 8 == 0 && e[0] >= 8 && e[1] >= 8 &&
-         (long long)e[0] * e[1] <= maxpix;
+  for (int a = 0; a < c->d; ++a)
+    if (e[a] % 8 || e[a] < 8) return false;
+  return e[c->d - 1] <= kMaxNetWidth && c->N[level] <= maxpix;
 }
 
 // Learned start guess for the frames of K_{q_next} \ K_{q_next-1}: the
@@ -623,7 +624,7 @@ int learned_predict(stml_ctx* c, int level, int q_next) {
   net_capacity(c->net, &maxB, &maxpix);
   const int* e = c->ext[level].data();
   const double h = c->h[level];
-  const int per = (int)std::min<long long>(nt, maxpix / ((long long)e[0] * e[1]));
+  const int per = (int)std::min<long long>(nt, maxpix / c->N[level]);
   for (int s = 0; s < nt; s += per) {
     int B = std::min(per, nt - s);
     rc = stml_net_assemble(c->net, b.T, c->ureg, c->n, e, h,
@@ -1062,7 +1063,8 @@ int stml_gn_direction(stml_ctx* c, int level, const int* frames, int nk,
 
 int stml_set_predictor_net(stml_ctx* c, stml_net* net) {
   if (!c) return STML_EINVAL;
-  if (net && c->d != 2) return fail(c, STML_EINVAL, "learned predictor: 2-D");
+  if (net && net_dim(net) != c->d)
+    return fail(c, STML_EINVAL, "learned predictor of another dimension");
   if (net && !c->ureg)
     return fail(c, STML_ESTATE, "create the context with predictor = 1");
   c->net = net;
@@ -1170,19 +1172,21 @@ size_t batch_layout(int count, char* base, stml_batch* b) {
 }
 
 // One Gauss-Newton iteration of every problem of js.
-hipError_t batch_iteration(const JobSet& js, const int* tot, int reg,
-                           const stml_opts& o,
+hipError_t batch_iteration(const JobSet& js, const int* tot, int dim,
+                           int reg, const stml_opts& o,
                            const std::vector<LSPass>& passes,
                            const std::vector<std::vector<double>>& steps,
                            int* dstop, hipStream_t s) {
-  hipError_t e = batch_eval(js, tot[kClsTile], reg, s);
-  if (e == hipSuccess) e = batch_cg_init(js, tot[kClsVox], s);
+  hipError_t e = batch_eval(js, tot[kClsTile], dim, reg, s);
+  if (e == hipSuccess) e = batch_cg_init(js, tot[kClsVox], dim, s);
   for (int it = 0; e == hipSuccess && it < o.cg_max; ++it) {
-    e = batch_cg_hvp(js, tot[kClsHv], reg, it, o.parity_mode, o.cg_rtol, s);
-    if (e == hipSuccess) e = batch_cg_update(js, tot[kClsVox], it, s);
+    e = batch_cg_hvp(js, tot[kClsHv], dim, reg, it, o.parity_mode,
+                     o.cg_rtol, s);
+    if (e == hipSuccess) e = batch_cg_update(js, tot[kClsVox], dim, it, s);
   }
   for (size_t pi = 0; e == hipSuccess && pi < passes.size(); ++pi) {
-    e = batch_trial(js, tot[kClsTile], reg, steps[pi].data(), passes[pi], s);
+    e = batch_trial(js, tot[kClsTile], dim, reg, steps[pi].data(),
+                    passes[pi], s);
     if (e == hipSuccess)
       e = batch_accept(js, tot[kClsElem], steps[pi].data(), passes[pi],
                        o.ls_max, o.c1, o.parity_mode, o.tol_J, o.tol_u, s);
@@ -1234,13 +1238,14 @@ int batch_register(stml_batch* b, int level, int q) {
   std::vector<std::vector<double>> steps;
   ls_passes(o.ls_max, &passes, &steps);
   const int reg = o.regulariser;
+  const int dim = b->c[0]->d;
   BHIP_OK(batch_gn_reset(js, o.gn_max, b->stream));
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
   if (b->graph && o.gn_max > 0) {
     BHIP_OK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = batch_iteration(js, tot, reg, o, passes, steps, b->dstop,
-                                   b->stream);
+    hipError_t e = batch_iteration(js, tot, dim, reg, o, passes, steps,
+                                   b->dstop, b->stream);
     hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -1252,8 +1257,8 @@ int batch_register(stml_batch* b, int level, int q) {
   hipError_t e = hipSuccess;
   for (int it = 0; it < o.gn_max && e == hipSuccess; ++it) {
     e = exec ? hipGraphLaunch(exec, b->stream)
-             : batch_iteration(js, tot, reg, o, passes, steps, b->dstop,
-                               b->stream);
+             : batch_iteration(js, tot, dim, reg, o, passes, steps,
+                               b->dstop, b->stream);
     if (e != hipSuccess || o.parity_mode) continue;
     e = hipMemcpyAsync(b->hstop, b->dstop, S * sizeof(int),
                        hipMemcpyDeviceToHost, b->stream);
@@ -1315,7 +1320,7 @@ int stml_batch_create(stml_ctx* const* ctxs, int count, void* stream,
   if (!a) return STML_EINVAL;
   for (int j = 0; j < count; ++j) {
     const stml_ctx* c = ctxs[j];
-    if (!c || c->d != 2 || c->L != a->L || c->T1 != a->T1 ||
+    if (!c || c->d != a->d || c->L != a->L || c->T1 != a->T1 ||
         c->o.regulariser != a->o.regulariser || c->o.gn_max != a->o.gn_max ||
         c->o.cg_max != a->o.cg_max || c->o.ls_max != a->o.ls_max ||
         c->o.parity_mode != a->o.parity_mode || c->o.c1 != a->o.c1 ||

@@ -95,6 +95,59 @@ def test_batched_sequence_matches_oracle():
     assert np.abs(u - ost.Y[1]).max() <= 1e-3
 
 
+# 3-D: (frames, extent, seed), ragged against the 16 x 4 x 4 tiles
+CASES3 = [(5, (10, 12, 18), 0), (6, (12, 16, 20), 1), (4, (8, 8, 24), 2)]
+
+
+def _opts3(parity):
+    return default_opts(dim=3, n_spatial=2, n_temporal=2, reg="curvature",
+                        alpha=0.1, gn_max=3 if parity else 20,
+                        cg_max=5 if parity else 20, parity_mode=parity)
+
+
+@pytest.mark.parametrize("parity,graph", [(True, True), (False, False)])
+def test_batch_3d_equals_single_runs(parity, graph):
+    singles, batched = [], []
+    for n, ext, seed in CASES3:
+        f = torch.from_numpy(
+            synth.sinusoid_sequence(n, ext, 1.5, 1, 70 + seed)[0]).cuda()
+        for group in (singles, batched):
+            st = STML(n, ext, opts=_opts3(parity))
+            st.set_sequence(f)
+            group.append(st)
+    print(f"batch 3d parity={parity} graph={graph}", flush=True)
+    for a in singles:
+        a.run()
+    Batch(batched, graph=graph).run()
+    torch.cuda.synchronize()
+    for a, b in zip(singles, batched):
+        _assert_same(a, b)
+    if not parity:
+        gns = [g["gn"] for b in batched for g in b.logs()]
+        assert min(gns) < 20
+
+
+def test_batched_3d_sequence_matches_oracle():
+    kw = dict(n_spatial=2, n_temporal=2, reg="curvature", alpha=0.1,
+              gn_max=3, cg_max=5, parity_mode=True)
+    sts, frames0 = [], None
+    for n, ext, seed in CASES3[:2]:
+        f = synth.sinusoid_sequence(n, ext, 1.5, 1, 70 + seed)[0]
+        frames0 = f if frames0 is None else frames0
+        st = STML(n, ext, opts=default_opts(dim=3, **kw))
+        st.set_sequence(torch.from_numpy(f).cuda())
+        sts.append(st)
+    print("batched 3d vs oracle", flush=True)
+    Batch(sts).run()
+    ost = oracle.stml.STMLState(frames0, oracle.STMLOptions(**kw))
+    ost.run()
+    for lg, olg in zip(sts[0].logs(), [x for x in ost.log if "q" in x]):
+        assert lg["steps"] == olg["steps"]
+        assert lg["J"] == pytest.approx(olg["J"], rel=1e-5)
+    u = sts[0].get_displacements(1).cpu().numpy()
+    assert np.abs(u - ost.Y[1]).max() <= 1e-3
+
+
 def test_batch_rejects_mismatched_contexts():
     a = STML(8, (32, 32), opts=default_opts(n_spatial=2, n_temporal=2))
     b = STML(8, (32, 32), opts=default_opts(n_spatial=2, n_temporal=3))
@@ -106,11 +159,14 @@ def test_batch_rejects_mismatched_contexts():
         Batch([a, c])
     with pytest.raises(STMLError):
         Batch([a, a])
+    v = STML(4, (8, 8, 16), opts=default_opts(dim=3, n_spatial=2,
+                                              n_temporal=2))
+    with pytest.raises(STMLError):
+        Batch([a, v])
     # a context without a sequence: the run reports it
     B = Batch([a])
     with pytest.raises(STMLError):
         B.run()
-
 
 
 def test_tuning_changes_only_rounding_and_keeps_batch_identity(tmp_path):

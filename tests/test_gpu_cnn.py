@@ -37,30 +37,37 @@ def _oracle32(fn, *args, **kw):
         cnn.ACCUM = np.float64
 
 
-def _flip_kernels(params):
-    """3x3 kernels turned by 180 degrees (tap t -> 8 - t); biases kept."""
-    P = cnn.unpack(params)
+def _flip_kernels(params, dim=2):
+    """3^d kernels turned by 180 degrees about every axis (tap t ->
+    3^d - 1 - t); biases kept."""
+    P = cnn.unpack(params, dim)
     flat = []
-    for name, ci, co, k in cnn.LAYERS:
+    for name, ci, co, k in cnn.layers(dim):
         W, b = P[name]
         flat += [(W[::-1] if k == 3 else W).ravel(), b]
     return np.concatenate(flat)
 
 
+def _turn(a, dim):
+    """Every spatial axis of a (B, *spatial, C) array reversed."""
+    return a[(slice(None),) + (slice(None, None, -1),) * dim].copy()
+
+
 def _noise(fn, params, x, *rest):
     """Spread of float32 accumulation: the largest distance from the float64
-    result over two summation orders (as given, and on the images turned by
-    180 degrees with turned kernels, which computes the same network in
-    exact arithmetic but sums in another order).  Returns a function of the
-    float64 result and the selection slice."""
+    result over two summation orders (as given, and on the frames turned by
+    180 degrees about every axis with turned kernels, which computes the
+    same network in exact arithmetic but sums in another order).  Returns a
+    function of the float64 result and the selection slice."""
+    dim = x.ndim - 2
     a = _oracle32(fn, params, x, *rest)
-    xf = x[:, ::-1, ::-1].copy()
-    rf = [r[:, ::-1, ::-1].copy() for r in rest]
-    b = _oracle32(fn, _flip_kernels(params).astype(np.float32), xf, *rf)
+    xf = _turn(x, dim)
+    rf = [_turn(r, dim) for r in rest]
+    b = _oracle32(fn, _flip_kernels(params, dim).astype(np.float32), xf, *rf)
     if isinstance(a, tuple) and np.ndim(a[1]) == 1:       # (loss, grad)
-        runs = [a[1], _flip_kernels(b[1])]
+        runs = [a[1], _flip_kernels(b[1], dim)]
     else:                                                  # (out, ...)
-        runs = [a[0], b[0][:, ::-1, ::-1]]
+        runs = [a[0], _turn(b[0], dim)]
     return lambda ref, sl=slice(None): max(_rel(r[sl], ref[sl]) for r in runs)
 
 
@@ -176,4 +183,101 @@ def test_assemble_and_emit():
         expect = base[b] + h * out[b].transpose(2, 0, 1)
         np.testing.assert_allclose(unew[t], expect, rtol=1e-5, atol=1e-5)
     untouched = [k for k in range(n) if k not in (3, 5, 1)]
+    np.testing.assert_array_equal(unew[untouched], u[untouched])
+
+
+# ------------------------------------------------------------------- 3-D
+
+
+def _batch3(B, ext, seed):
+    rng = np.random.default_rng(seed)
+    x = np.empty((B, 9) + ext, np.float32)
+    for b in range(B):
+        img = synth.base_image(rng, ext)
+        x[b, 0:3] = img[None] * (1 + 0.05 * rng.standard_normal((3,) + ext))
+        x[b, 3:9] = rng.uniform(-2, 2, (6,) + ext)
+    tgt = (0.3 * rng.standard_normal((B,) + ext + (3,))).astype(np.float32)
+    return x, tgt
+
+
+@pytest.mark.parametrize("B,ext", [(1, (16, 16, 24)), (2, (8, 16, 16))])
+def test_forward_parity_3d(B, ext):
+    net = Net(2, (16, 16, 24), dim=3)
+    params = cnn.init_params(11, dim=3)
+    params[-3:] = 0.05
+    net.set_params(torch.from_numpy(params))
+    x, _ = _batch3(B, ext, 12)
+    net.set_input(torch.from_numpy(x))
+    print(f"cnn forward 3d {B}x{ext}", flush=True)
+    out = net.forward().cpu().numpy()
+    xn = np.moveaxis(x, 1, -1)
+    ref, _ = cnn.forward(params, xn, bf16=True)
+    noise = _noise(cnn.forward, params, xn)(ref)
+    print(f"gpu {_rel(out, ref):.2e}, f32-accumulation noise {noise:.2e}")
+    assert out.shape == ref.shape
+    assert _rel(out, ref) <= 2 * noise + 1e-4
+
+
+def test_gradient_parity_3d():
+    ext = (8, 16, 16)
+    net = Net(1, ext, dim=3)
+    params = cnn.init_params(13, dim=3)
+    net.set_params(torch.from_numpy(params))
+    x, tgt = _batch3(1, ext, 14)
+    net.set_input(torch.from_numpy(x), torch.from_numpy(tgt))
+    print("cnn gradient 3d", flush=True)
+    loss, g = net.gradient()
+    g = g.cpu().numpy().astype(np.float64)
+    xn = np.moveaxis(x, 1, -1)
+    ref_loss, ref_g = cnn.loss_and_grad(params, xn, tgt, bf16=True)
+    l32, _ = _oracle32(cnn.loss_and_grad, params, xn, tgt, bf16=True)
+    noise = _noise(cnn.loss_and_grad, params, xn, tgt)
+    o = 0
+    bad = []
+    for name, ci, co, k in cnn.layers(3):
+        nw = k ** 3 * co * ci
+        sl = slice(o, o + nw)
+        e, n = _rel(g[sl], ref_g[sl]), noise(ref_g, sl)
+        print(f"{name}: gpu {e:.2e} noise {n:.2e}")
+        if e > 2 * n + 1e-4:
+            bad.append(name)
+        o += nw + co
+    print(f"all: gpu {_rel(g, ref_g):.2e} noise {noise(ref_g):.2e}")
+    assert not bad, bad
+    assert _rel(g, ref_g) <= 2 * noise(ref_g) + 1e-4
+    assert abs(loss - ref_loss) <= 2 * abs(l32 - ref_loss) + 1e-4 * ref_loss
+
+
+def test_assemble_and_emit_3d():
+    n, ext = 7, (8, 16, 24)
+    rng = np.random.default_rng(15)
+    frames = rng.uniform(0.2, 1, (n,) + ext).astype(np.float32)
+    u = rng.uniform(-3, 3, (n, 3) + ext).astype(np.float32)
+    h = 2.0
+    triples = [(3, 0, 4), (5, 4, 6)]
+    net = Net(2, ext, dim=3)
+    params = cnn.init_params(16, dim=3)
+    net.set_params(torch.from_numpy(params))
+    fd = torch.from_numpy(frames).cuda()
+    ud = torch.from_numpy(u).cuda()
+    net.assemble(fd, ud, h, triples, with_target=True)
+    out = net.forward().cpu().numpy()
+    x = np.zeros((2, 9) + ext, np.float32)
+    base = np.zeros((2, 3) + ext)
+    for b, (t, l, r) in enumerate(triples):
+        x[b, 0], x[b, 1], x[b, 2] = frames[l], frames[t], frames[r]
+        x[b, 3:6] = u[l] / h
+        x[b, 6:9] = u[r] / h
+        wl, wr = (r - t) / (r - l), (t - l) / (r - l)
+        base[b] = wl * u[l].astype(np.float64) + wr * u[r]
+    xn = np.moveaxis(x, 1, -1)
+    ref, _ = cnn.forward(params, xn)
+    assert _rel(out, ref) <= 2 * _noise(cnn.forward, params, xn)(ref) + 1e-4
+    unew = ud.clone()
+    net.emit(h, unew)
+    unew = unew.cpu().numpy()
+    for b, (t, l, r) in enumerate(triples):
+        expect = base[b] + h * np.moveaxis(out[b], -1, 0)
+        np.testing.assert_allclose(unew[t], expect, rtol=1e-5, atol=1e-5)
+    untouched = [k for k in range(n) if k not in (3, 5)]
     np.testing.assert_array_equal(unew[untouched], u[untouched])
