@@ -161,6 +161,9 @@ def _gen_volume_sequence(args):
     return synth.sinusoid_sequence(n, VOLUME["extent"], 4.0, 3, seed)[0]
 
 
+LEARNED3D_SEEDS = (21000, 21001)   # held out from the 3-D training seeds
+
+
 def volume_comparison(single, seqs, log):
     """3-D: the 32-frame 128x128x64 volume solved alone (3 spatial x 3
     temporal levels, curvature alpha 0.1, fixed 5 GN x 10 CG), then four
@@ -259,6 +262,24 @@ def learned_comparison(seqs, log):
                for k, v in s.items() if k != "sequences"}}
 
 
+def learned3d_comparison(seqs, log):
+    """Paper's predictor vs the shipped 3-D learned one on held-out
+    32-frame 128x128x64 volumes (convergence-controlled Gauss-Newton)."""
+    from paper_2001_06613_amd import learned
+    from paper_2001_06613_amd.binding import Net
+
+    net = Net(1, VOLUME["extent"], dim=3)
+    net.set_params(learned.load_params(learned.TRAINED_C5))
+    rows = learned.compare(net, seqs, opts=learned.schedule_opts(
+        dim=3, gn_max=40), warmup=0)
+    s = learned.summarise(rows)
+    log("learned 3-D: comparison done")
+    net.close()
+    return {"sequences": len(rows), "seeds": [r["seed"] for r in rows],
+            **{k: (round(v, 4) if isinstance(v, float) else v)
+               for k, v in s.items() if k != "sequences"}}
+
+
 def pmc_probe(st, fr):
     """One solve and a plain copy of known size, for counter runs."""
     import torch
@@ -307,6 +328,8 @@ def main():
         log("batch: sequences generated")
     if not args.pmc_probe and not args.no_volume:
         jobs = [(VOLUME["n"], 3)] + synth.config_volume_batch()
+        if not args.no_learned:
+            jobs += [(VOLUME["n"], s) for s in LEARNED3D_SEEDS]
         with mp.get_context("fork").Pool(len(jobs)) as pool:
             volume_seqs = pool.map(_gen_volume_sequence, jobs, chunksize=1)
         log("volume: sequences generated")
@@ -416,8 +439,12 @@ def main():
     if learned_seqs is not None:
         out["learned"] = learned_comparison(learned_seqs, log)
     if volume_seqs is not None:
-        out["volume"] = volume_comparison(volume_seqs[0], volume_seqs[1:],
-                                          log)
+        nb = len(synth.config_volume_batch())
+        out["volume"] = volume_comparison(volume_seqs[0],
+                                          volume_seqs[1:1 + nb], log)
+        if not args.no_learned:
+            out["learned_3d"] = learned3d_comparison(
+                list(zip(LEARNED3D_SEEDS, volume_seqs[1 + nb:])), log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frames)
     print(json.dumps(out))

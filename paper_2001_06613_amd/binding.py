@@ -159,6 +159,11 @@ def load(path=LIB_PATH):
         raise STMLError(STML_EDEVICE,
                         f"{path} is missing: build it with "
                         "`python -c 'import __graft_entry__ as g; g.build()'`")
+    # torch first: the library then binds to the HIP runtime torch loaded
+    # (one runtime per process, so torch's streams and memory are valid
+    # handles for the library)
+    import torch  # noqa: F401
+
     lib = ctypes.CDLL(path)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)

@@ -182,7 +182,7 @@ __device__ __forceinline__ void cgv_update_body(
 #pragma unroll
     for (int a = 0; a < D; ++a) v[a] = 0.0;
     if (valid) {
-#pragma unroll 2
+#pragma unroll 1
       for (int j = j0; j < j1; ++j) {
         const size_t base = (size_t)j * D * N + pos.idx;
 #pragma unroll
@@ -210,8 +210,10 @@ __device__ __forceinline__ void cgv_update_body(
   block_partials<2>(vals, 0u, part, blk);
 }
 
+// Two blocks per compute unit (at most 64 registers per lane): while one
+// block combines its per-voxel sums, the other streams.
 template <int D>
-__global__ __launch_bounds__(1024) void cgv_update_kernel(
+__global__ __launch_bounds__(1024, 8) void cgv_update_kernel(
     int it, const float* __restrict__ p, const float* __restrict__ q,
     const float* __restrict__ dW, Geom g, Model md, float* __restrict__ x,
     float* __restrict__ r, float* __restrict__ z, double* __restrict__ Sz,
@@ -323,22 +325,49 @@ __device__ __forceinline__ void cgt_hvp2_body(
     }
     const int jbeg = fg * fpg;
     const int jend = jbeg + fpg < md.nK ? jbeg + fpg : md.nK;
-    for (int j = jbeg; j < jend; ++j) {
-      // stage p (replicate padding at the grid edge = clamped loads)
-      for (int i = threadIdx.x; i < kHY * kHX; i += blockDim.x) {
-        int hy = i / kHX, hx = i - (i / kHX) * kHX;
-        int gy = min(max(y0 - 2 + hy, 0), m0 - 1);
-        int gx = min(max(x0 - 2 + hx, 0), m1 - 1);
-        unsigned o = (unsigned)(gy * m1 + gx);
+    // p of the halo tile, staged through registers one frame ahead: the
+    // loads of frame j + 1 are in flight while frame j is computed
+    // (replicate padding at the grid edge = clamped loads)
+    constexpr int kSt = (kHY * kHX + kTX * kTY - 1) / (kTX * kTY);
+    unsigned so[kSt];
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          size_t plane = ((size_t)j * D + a) * N;
-          float pv = it > 0 ? __builtin_fmaf(bf, p_old[plane + o], zv[plane + o])
-                            : zv[plane + o];
-          P[a][hy][hx] = (double)pv;
+    for (int s = 0; s < kSt; ++s) {
+      const int i = threadIdx.x + s * kTX * kTY;
+      const int hy = i / kHX, hx = i - (i / kHX) * kHX;
+      const int gy = min(max(y0 - 2 + hy, 0), m0 - 1);
+      const int gx = min(max(x0 - 2 + hx, 0), m1 - 1);
+      so[s] = (unsigned)(gy * m1 + gx);
+    }
+    float sz[kSt][D], sp[kSt][D];
+    auto fetch = [&](int j) {
+#pragma unroll
+      for (int s = 0; s < kSt; ++s) {
+        if (threadIdx.x + s * kTX * kTY < kHY * kHX) {
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            const size_t plane = ((size_t)j * D + a) * N;
+            sz[s][a] = zv[plane + so[s]];
+            sp[s][a] = it > 0 ? p_old[plane + so[s]] : 0.f;
+          }
+        }
+      }
+    };
+    if (jbeg < jend) fetch(jbeg);
+    for (int j = jbeg; j < jend; ++j) {
+#pragma unroll
+      for (int s = 0; s < kSt; ++s) {
+        const int i = threadIdx.x + s * kTX * kTY;
+        if (i < kHY * kHX) {
+          const int hy = i / kHX, hx = i - (i / kHX) * kHX;
+#pragma unroll
+          for (int a = 0; a < D; ++a)
+            P[a][hy][hx] = (double)(it > 0 ? __builtin_fmaf(bf, sp[s][a],
+                                                            sz[s][a])
+                                           : sz[s][a]);
         }
       }
       __syncthreads();
+      if (j + 1 < jend) fetch(j + 1);
       if (REG) {
         // L p on the 1-cell halo; outside the grid it replicates the edge
         for (int i = threadIdx.x; i < kLY * kLX; i += blockDim.x) {
@@ -398,8 +427,10 @@ __device__ __forceinline__ void cgt_hvp2_body(
   block_partials<1>(vals, 0u, part, blk);
 }
 
+// Eight blocks per compute unit (at most 64 registers per lane) keep enough
+// tile loads in flight (the diffusion form needs more registers: five).
 template <int REG>
-__global__ __launch_bounds__(256) void cgt_hvp2_kernel(
+__global__ __launch_bounds__(256, REG ? 8 : 5) void cgt_hvp2_kernel(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
     Model md, float* __restrict__ q, const double* __restrict__ Sz,
@@ -715,9 +746,8 @@ __global__ __launch_bounds__(1024) void cg_init_batch_kernel(JobSet js) {
 }
 
 template <int D, int REG>
-__global__ __launch_bounds__(256) void cg_hvp_batch_kernel(JobSet js, int it,
-                                                           int fixed,
-                                                           double rtol) {
+__global__ __launch_bounds__(256, D == 3 ? 1 : (REG ? 8 : 5)) void cg_hvp_batch_kernel(
+    JobSet js, int it, int fixed, double rtol) {
   Blk blk;
   const Job& J = cg_job_of(js, kClsHv, blk);
   const Geom g = J.g;
@@ -742,7 +772,7 @@ __global__ __launch_bounds__(256) void cg_hvp_batch_kernel(JobSet js, int it,
 }
 
 template <int D>
-__global__ __launch_bounds__(1024) void cg_update_batch_kernel(JobSet js,
+__global__ __launch_bounds__(1024, 8) void cg_update_batch_kernel(JobSet js,
                                                                int it) {
   Blk blk;
   const Job& J = cg_job_of(js, kClsVox, blk);
