@@ -240,8 +240,15 @@ int stml_set_tuning(stml_ctx* ctx, const stml_tuning* tuning);
 int stml_get_tuning(const stml_ctx* ctx, stml_tuning* tuning);
 
 /* mask != 0: clear the accumulators and time the classes whose bit
- * (1 << STML_K_...) is set; mask = 0: stop timing. */
+ * (1 << STML_K_...) is set; mask = 0: stop timing.  Each timed launch is
+ * bracketed by its dispatch's own start/end timestamps (or an event pair);
+ * the records are resolved when read, never inside a solve. */
 int stml_timing(stml_ctx* ctx, int mask);
+/* As stml_timing, but time only every period-th launch of each class
+ * (period >= 1; counting restarts here): a timestamped dispatch costs a few
+ * microseconds of issue time, so a sample keeps a timed run close to an
+ * untimed one.  Totals then cover the sampled launches only. */
+int stml_timing_every(stml_ctx* ctx, int mask, int period);
 /* Totals of one kernel class at one level (level = -1: all levels):
  * time, launches, voxel-frames, and algorithmic HBM bytes (every input
  * field read once, every output field written once, float32). */

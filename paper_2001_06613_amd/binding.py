@@ -133,6 +133,7 @@ SIGNATURES = {
     "stml_set_tuning": (_I, [_P, ctypes.POINTER(stml_tuning)]),
     "stml_get_tuning": (_I, [_P, ctypes.POINTER(stml_tuning)]),
     "stml_timing": (_I, [_P, _I]),
+    "stml_timing_every": (_I, [_P, _I, _I]),
     "stml_timing_get": (_I, [_P, _I, _I, _DP,
                              ctypes.POINTER(ctypes.c_longlong), _DP, _DP]),
 }
@@ -366,9 +367,10 @@ class STML:
         return {"tile_blocks": t.tile_blocks, "vox_blocks": t.vox_blocks,
                 "hv_blocks": t.hv_blocks}
 
-    def timing(self, kernels):
+    def timing(self, kernels, every=1):
         """Start timing the named kernel classes (True: all), or stop (None,
-        False or an empty list)."""
+        False or an empty list); every > 1 times only every every-th launch
+        of each class."""
         if kernels is True:
             mask = (1 << len(KERNELS)) - 1
         elif not kernels:
@@ -377,7 +379,8 @@ class STML:
             mask = 0
             for k in kernels:
                 mask |= 1 << KERNELS[k]
-        return self._check(self.lib.stml_timing(self.ctx, mask))
+        return self._check(self.lib.stml_timing_every(self.ctx, mask,
+                                                      int(every)))
 
     def timing_get(self, kernel, level=-1):
         ms = ctypes.c_double()

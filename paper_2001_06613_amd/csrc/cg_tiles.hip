@@ -210,10 +210,12 @@ __device__ __forceinline__ void cgv_update_body(
   block_partials<2>(vals, 0u, part, blk);
 }
 
-// Two blocks per compute unit (at most 64 registers per lane): while one
-// block combines its per-voxel sums, the other streams.
-template <int D>
-__global__ __launch_bounds__(1024, 8) void cgv_update_kernel(
+// OCC: two blocks per compute unit (at most 64 registers per lane), so that
+// while one block combines its per-voxel sums the other streams; for grids
+// with more blocks than compute units.  Small grids (latency-bound levels)
+// run faster with the registers unconstrained.  Same arithmetic either way.
+template <int D, bool OCC>
+__global__ __launch_bounds__(1024, OCC ? 8 : 1) void cgv_update_kernel(
     int it, const float* __restrict__ p, const float* __restrict__ q,
     const float* __restrict__ dW, Geom g, Model md, float* __restrict__ x,
     float* __restrict__ r, float* __restrict__ z, double* __restrict__ Sz,
@@ -704,9 +706,13 @@ hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
                              hipEvent_t ev0, hipEvent_t ev1) {
   int nb = cgv_blocks(g), nt = cgv_threads(dim, md.nK);
   int hv_nb = cg_tiles(g, md.nK, dim).grid;
-  hipExtLaunchKernelGGL(dim == 2 ? cgv_update_kernel<2> : cgv_update_kernel<3>,
-                        dim3(nb), dim3(nt), 0, s, ev0, ev1, 0, it, p, q, dW, g,
-                        md, x, r, z, sums.Sz, sums.Vz,
+  const bool occ = nb > kCUs;
+  auto kern = dim == 2 ? (occ ? cgv_update_kernel<2, true>
+                              : cgv_update_kernel<2, false>)
+                       : (occ ? cgv_update_kernel<3, true>
+                              : cgv_update_kernel<3, false>);
+  hipExtLaunchKernelGGL(kern, dim3(nb), dim3(nt), 0, s, ev0, ev1, 0, it, p,
+                        q, dW, g, md, x, r, z, sums.Sz, sums.Vz,
                         (const double*)rb.region(kRegHv), hv_nb,
                         rb.region(kRegUpdate), sc, gn_it);
   return hipGetLastError();

@@ -92,6 +92,8 @@ struct stml_ctx {
     long long n = 0;
   };
   unsigned timing = 0;                  // bit k: time kernel class k
+  int tperiod = 1;                      // time every tperiod-th launch
+  long long tcount[STML_K_COUNT] = {};  // launches seen per class
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
   std::map<std::pair<int, int>, KStat> kstats;
@@ -265,13 +267,28 @@ hipEvent_t pooled_event(stml_ctx* c) {
   return e;
 }
 
-void tbegin(stml_ctx* c, int kernel, int level, double vf, double bytes) {
-  if (!((c->timing >> kernel) & 1u)) return;
+void tresolve(stml_ctx* c);
+
+// Pending records are resolved when read (stml_timing_get), when timing is
+// switched, or when this many accumulate: resolving waits for the events,
+// so it is kept out of the solve.
+constexpr size_t kMaxPending = 1 << 15;
+
+// Whether this launch of class kernel is timed (every tperiod-th one).
+bool timed_now(stml_ctx* c, int kernel) {
+  if (!((c->timing >> kernel) & 1u)) return false;
+  return c->tcount[kernel]++ % c->tperiod == 0;
+}
+
+bool tbegin(stml_ctx* c, int kernel, int level, double vf, double bytes) {
+  if (!timed_now(c, kernel)) return false;
+  if (c->pending.size() >= kMaxPending) tresolve(c);
   stml_ctx::Rec r{kernel, level, vf, bytes, pooled_event(c),
                   pooled_event(c)};
-  if (!r.a || !r.b) return;
+  if (!r.a || !r.b) return false;
   (void)hipEventRecord(r.a, c->stream);
   c->pending.push_back(r);
+  return true;
 }
 
 // Timing by the dispatch itself: a pending record whose events the
@@ -279,7 +296,8 @@ void tbegin(stml_ctx* c, int kernel, int level, double vf, double bytes) {
 void tdispatch(stml_ctx* c, int kernel, int level, double vf, double bytes,
                hipEvent_t* ev0, hipEvent_t* ev1) {
   *ev0 = *ev1 = nullptr;
-  if (!((c->timing >> kernel) & 1u)) return;
+  if (!timed_now(c, kernel)) return;
+  if (c->pending.size() >= kMaxPending) tresolve(c);
   stml_ctx::Rec r{kernel, level, vf, bytes, pooled_event(c),
                   pooled_event(c)};
   if (!r.a || !r.b) return;
@@ -288,9 +306,9 @@ void tdispatch(stml_ctx* c, int kernel, int level, double vf, double bytes,
   c->pending.push_back(r);
 }
 
-void tend(stml_ctx* c, int kernel) {
-  if (!((c->timing >> kernel) & 1u) || c->pending.empty()) return;
-  (void)hipEventRecord(c->pending.back().b, c->stream);
+void tend(stml_ctx* c) {
+  if (!c->pending.empty())
+    (void)hipEventRecord(c->pending.back().b, c->stream);
 }
 
 void tresolve(stml_ctx* c) {
@@ -316,7 +334,6 @@ int read_scal(stml_ctx* c) {
   HIP_OK(hipMemcpyAsync(c->hsc, c->sc, sizeof(Scal), hipMemcpyDeviceToHost,
                         c->stream));
   HIP_OK(hipStreamSynchronize(c->stream));
-  tresolve(c);
   return STML_OK;
 }
 
@@ -349,9 +366,10 @@ double alg_bytes(int kernel, int D, int cg_it) {
   } while (0)
 #define TIMED_IT(KERNEL, LEVEL, VF, CGIT, CALL)                        \
   do {                                                                 \
-    tbegin(c, KERNEL, LEVEL, VF, (VF) * alg_bytes(KERNEL, c->d, CGIT)); \
+    const bool tr_ =                                                   \
+        tbegin(c, KERNEL, LEVEL, VF, (VF) * alg_bytes(KERNEL, c->d, CGIT)); \
     hipError_t te_ = (CALL);           \
-    tend(c, KERNEL);                   \
+    if (tr_) tend(c);                  \
     HIP_OK(te_);                       \
   } while (0)
 
@@ -677,7 +695,6 @@ int do_predict(stml_ctx* c, int level, int q_next) {
                             c->N[level], c->o.beta, c->stream));
   }
   HIP_OK(hipStreamSynchronize(c->stream));
-  tresolve(c);
   if (q_next > 0) c->pick.used = 0;
   if (learned) return learned_predict(c, level, q_next);
   return STML_OK;
@@ -1087,14 +1104,18 @@ int stml_get_tuning(const stml_ctx* c, stml_tuning* t) {
   return STML_OK;
 }
 
-int stml_timing(stml_ctx* c, int mask) {
-  if (!c || mask < 0) return STML_EINVAL;
+int stml_timing_every(stml_ctx* c, int mask, int period) {
+  if (!c || mask < 0 || period < 1) return STML_EINVAL;
   HIP_OK(hipStreamSynchronize(c->stream));
   tresolve(c);
   if (mask) c->kstats.clear();
   c->timing = (unsigned)mask & ((1u << STML_K_COUNT) - 1u);
+  c->tperiod = period;
+  for (long long& n : c->tcount) n = 0;
   return STML_OK;
 }
+
+int stml_timing(stml_ctx* c, int mask) { return stml_timing_every(c, mask, 1); }
 
 int stml_timing_get(stml_ctx* c, int kernel, int level, double* ms,
                     long long* n, double* vf, double* bytes) {

@@ -15,6 +15,7 @@ constexpr int kMaxFPT = 16;        // max frames one thread keeps in registers
 constexpr int kMaxChunks = 16;     // waves per block -> |K| <= 256
 constexpr int kTrialSteps = 5;     // Armijo steps evaluated per pass
 constexpr int kXCD = 8;            // MI355X: 8 accelerator complex dies
+constexpr int kCUs = 256;          // compute units (32 per die)
 constexpr int kMaxTileBlocks = 512;    // default block caps
 constexpr int kHvBlocks = 2048;
 constexpr int kMaxElemBlocks = 1024;

@@ -24,7 +24,8 @@ import os
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL = "cgv_update_kernel<2>"
+KERNEL = "cgv_update_kernel<2,"    # both launch-bound forms match
+LABEL = "cgv_update_kernel<2, *>"
 # every source the kernel is built from
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
            ("cg_tiles.hip", "reduce.h", "stml_dev.h", "launch.h")]
@@ -82,7 +83,7 @@ def summarise(fetch_dir, write_dir):
     per_launch = (f["kernel_kib_mean"] * 1024.0 * scale_f +
                   w["kernel_kib_mean"] * 1024.0 * scale_w)
     sha = source_sha()
-    return {"kernel": KERNEL, "hbm_bytes_per_launch": per_launch,
+    return {"kernel": LABEL, "hbm_bytes_per_launch": per_launch,
             "fetch_kib_per_launch": f["kernel_kib_mean"],
             "write_kib_per_launch": w["kernel_kib_mean"],
             "fetch_scale": scale_f, "write_scale": scale_w,

@@ -176,6 +176,31 @@ def test_repeat_runs_bitwise_identical():
     assert outs[0][1] == outs[1][1]
 
 
+def test_timing_counts_and_leaves_results_unchanged():
+    """Timed runs (all launches, or every 3rd) count the launches the
+    schedule makes and give the untimed run's displacements."""
+    frames = _small()
+    kw = dict(n_spatial=2, n_temporal=2, gn_max=3, cg_max=6,
+              parity_mode=True)
+    st = STML(8, frames.shape[1:], opts=default_opts(**kw))
+    f = torch.from_numpy(frames).cuda()
+    st.set_sequence(f)
+    st.run()
+    ref = st.get_displacements().clone()
+    n_upd = sum(sum(lg["cg"]) for lg in st.logs())
+    print("timing", flush=True)
+    for every in (1, 3):
+        st.timing(["cg_update", "hessvec"], every=every)
+        st.set_sequence(f)
+        st.run()
+        t = st.timing_get("cg_update")
+        st.timing(None)
+        assert torch.equal(st.get_displacements(), ref)
+        assert t["launches"] == -(-n_upd // every)
+        assert t["ms"] > 0 and t["bytes"] > 0
+        assert st.timing_get("eval")["launches"] == 0
+
+
 def test_large_level_parity():
     """64 frames of 256x256 (the benchmark's finest level), all frames."""
     frames, _ = synth.config_large(1)
