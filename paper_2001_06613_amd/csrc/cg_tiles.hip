@@ -25,10 +25,8 @@ constexpr int kHX = kTX + 4;       // with a 2-cell halo
 constexpr int kHY = kTY + 4;
 constexpr int kLX = kTX + 2;       // L p on a 1-cell halo
 constexpr int kLY = kTY + 2;
-// 3-D tiles: 16 (x) x 4 (y) x 4 (z) voxels, 2-cell halo for p, 1 for L p
-constexpr int kT3X = 16, kT3Y = 4, kT3Z = 4;
-constexpr int kH3X = kT3X + 4, kH3Y = kT3Y + 4, kH3Z = kT3Z + 4;
-constexpr int kL3X = kT3X + 2, kL3Y = kT3Y + 2, kL3Z = kT3Z + 2;
+// 3-D columns: 16 (x) x 16 (y) points marched through 16 planes in z
+constexpr int kT3X = kHv3X, kT3Y = kHv3Y, kT3Z = kHv3Z;
 
 // Frames of a voxel-major tile handled by this wave.
 __device__ __forceinline__ void wave_frames(int nK, int& j0, int& j1) {
@@ -447,9 +445,15 @@ __global__ __launch_bounds__(256, REG ? 8 : 5) void cgt_hvp2_kernel(
 }
 
 // 3-D Hessian product on p = z + beta p_old (it > 0) or p = z for one
-// 16 x 4 x 4 tile of a group of frames: the 2-D kernel's scheme with p
-// staged in LDS as float32 (exactly the values the kernel stores) and L p in
-// float64; the voxel sums S, V and the CG scalars as in 2-D.
+// column of a group of frames: a 16 x 16 tile in (x, y) marched through
+// kZ3 planes in z.  For each frame the block keeps a ring of five planes of
+// p (2-cell halo, float32: exactly the values the kernel stores) and three
+// planes of L p (1-cell halo, float64) in LDS; every step stages one new
+// plane of p (its loads issued one step ahead, into registers), forms one
+// plane of L p and finishes one plane of q = H p.  The halo overhead per
+// step is that of a 2-D tile (20 x 20 loads for 16 x 16 outputs) instead of
+// a 3-D one.  Voxel sums S, V and the CG scalars as in 2-D; the per-voxel
+// sums are read per frame (they stay in the L2 across the block's frames).
 template <int REG>
 __device__ __forceinline__ void cgt_hvp3_body(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
@@ -461,9 +465,13 @@ __device__ __forceinline__ void cgt_hvp3_body(
     const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
     double* __restrict__ part, Scal* __restrict__ sc, int gn_it, Blk blk) {
   constexpr int D = 3;
-  __shared__ float P[D][kH3Z][kH3Y][kH3X];
-  __shared__ double L[REG ? D : 1][REG ? kL3Z : 1][REG ? kL3Y : 1]
-                     [REG ? kL3X : 1];
+  constexpr int HX = kT3X + 4, HY = kT3Y + 4;   // p plane with halo
+  constexpr int LX = kT3X + 2, LY = kT3Y + 2;   // L p plane with halo
+  constexpr int NT = kT3X * kT3Y;               // threads = tile points
+  constexpr int kPS = (HX * HY + NT - 1) / NT;  // p points per thread
+  constexpr int kLS = (LX * LY + NT - 1) / NT;  // L points per thread
+  __shared__ float P[D][5][HY][HX];
+  __shared__ double L[REG ? D : 1][REG ? 3 : 1][REG ? LY : 1][REG ? LX : 1];
   if (sc->done || gn_it >= sc->gn_stop) return;
   double beta = 0.0;
   if (it > 0) {
@@ -489,118 +497,168 @@ __device__ __forceinline__ void cgt_hvp3_body(
   if (bb < nreal) {
     const int m0 = g.m[0], m1 = g.m[1], m2 = g.m[2];
     const long long N = g.N;
+    const long long plane_n = (long long)m1 * m2;
     const int tile = bb / nfg, fg = bb - (bb / nfg) * nfg;
     const int ntx = (m2 + kT3X - 1) / kT3X, nty = (m1 + kT3Y - 1) / kT3Y;
     const int x0 = (tile % ntx) * kT3X;
     const int y0 = ((tile / ntx) % nty) * kT3Y;
     const int z0 = (tile / ntx / nty) * kT3Z;
-    const int lx = threadIdx.x % kT3X, ly = (threadIdx.x / kT3X) % kT3Y,
-              lz = threadIdx.x / (kT3X * kT3Y);
-    const int x = x0 + lx, y = y0 + ly, z = z0 + lz;
-    const bool valid = x < m2 && y < m1 && z < m0;
-    const unsigned vox =
-        valid ? (unsigned)(((long long)z * m1 + y) * m2 + x) : 0u;
-    double sbar = 0.0, vbar[D] = {0.0, 0.0, 0.0};
-    if (valid) {
-      double S = Sz[vox], V[D];
+    const int z1 = z0 + kT3Z < m0 ? z0 + kT3Z : m0;
+    const int lx = threadIdx.x % kT3X, ly = threadIdx.x / kT3X;
+    const int x = x0 + lx, y = y0 + ly;
+    const bool inplane = x < m2 && y < m1;
+    const unsigned vxy = inplane ? (unsigned)(y * m2 + x) : 0u;
+    // in-plane offsets of this thread's halo points (clamped: replicate)
+    unsigned po[kPS];
+    int pi[kPS];
 #pragma unroll
-      for (int a = 0; a < D; ++a) V[a] = Vz[(size_t)a * N + vox];
-      if (it > 0) {
-        S += beta * Sp_old[vox];
-#pragma unroll
-        for (int a = 0; a < D; ++a) V[a] += beta * Vp_old[(size_t)a * N + vox];
-      }
-      if (fg == 0) {
-        Sp_new[vox] = S;
-#pragma unroll
-        for (int a = 0; a < D; ++a) Vp_new[(size_t)a * N + vox] = V[a];
-      }
-      sbar = S * md.inv_nK;
-#pragma unroll
-      for (int a = 0; a < D; ++a) vbar[a] = V[a] * md.inv_nK;
+    for (int s = 0; s < kPS; ++s) {
+      const int i = threadIdx.x + s * NT;
+      pi[s] = i < HX * HY ? i : -1;
+      const int hy = i / HX, hx = i - (i / HX) * HX;
+      const int gy = min(max(y0 - 2 + hy, 0), m1 - 1);
+      const int gx = min(max(x0 - 2 + hx, 0), m2 - 1);
+      po[s] = (unsigned)(gy * m2 + gx);
     }
+    const bool hn = y > 0, hs = y < m1 - 1, hw = x > 0, he = x < m2 - 1;
     const int jbeg = fg * fpg;
     const int jend = jbeg + fpg < md.nK ? jbeg + fpg : md.nK;
-    for (int j = jbeg; j < jend; ++j) {
-      // stage p (replicate padding at the grid edge = clamped loads)
-      for (int i = threadIdx.x; i < kH3Z * kH3Y * kH3X; i += blockDim.x) {
-        int hz = i / (kH3Y * kH3X), r = i - hz * (kH3Y * kH3X);
-        int hy = r / kH3X, hx = r - hy * kH3X;
-        int gz = min(max(z0 - 2 + hz, 0), m0 - 1);
-        int gy = min(max(y0 - 2 + hy, 0), m1 - 1);
-        int gx = min(max(x0 - 2 + hx, 0), m2 - 1);
-        unsigned o = (unsigned)(((long long)gz * m1 + gy) * m2 + gx);
+    float rz[kPS][D], rp[kPS][D];
+    // loads of p plane pz (clamped) of frame j into registers
+    auto fetch = [&](int j, int pz) {
+      const int gz = min(max(pz, 0), m0 - 1);
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          size_t plane = ((size_t)j * D + a) * N;
-          P[a][hz][hy][hx] =
-              it > 0 ? __builtin_fmaf(bf, p_old[plane + o], zv[plane + o])
-                     : zv[plane + o];
-        }
-      }
-      __syncthreads();
-      if (REG) {
-        // L p on the 1-cell halo; outside the grid it replicates the edge
-        for (int i = threadIdx.x; i < kL3Z * kL3Y * kL3X; i += blockDim.x) {
-          int qz = i / (kL3Y * kL3X), r = i - qz * (kL3Y * kL3X);
-          int qy = r / kL3X, qx = r - qy * kL3X;
-          int cz = min(max(z0 - 1 + qz, 0), m0 - 1) - z0 + 2;
-          int cy = min(max(y0 - 1 + qy, 0), m1 - 1) - y0 + 2;
-          int cx = min(max(x0 - 1 + qx, 0), m2 - 1) - x0 + 2;
+      for (int s = 0; s < kPS; ++s) {
+        if (pi[s] >= 0) {
 #pragma unroll
           for (int a = 0; a < D; ++a) {
-            double c = P[a][cz][cy][cx];
-            L[a][qz][qy][qx] = ((double)P[a][cz - 1][cy][cx] - c) +
-                               ((double)P[a][cz + 1][cy][cx] - c) +
-                               ((double)P[a][cz][cy - 1][cx] - c) +
-                               ((double)P[a][cz][cy + 1][cx] - c) +
-                               ((double)P[a][cz][cy][cx - 1] - c) +
-                               ((double)P[a][cz][cy][cx + 1] - c);
+            const size_t o =
+                ((size_t)j * D + a) * N + (size_t)gz * plane_n + po[s];
+            rz[s][a] = zv[o];
+            rp[s][a] = it > 0 ? p_old[o] : 0.f;
           }
         }
-        __syncthreads();
       }
-      if (valid) {
-        const int pz = lz + 2, py = ly + 2, px = lx + 2;
-        double pc[D], d[D], s = 0.0;
-        const size_t jb = (size_t)j * D * N + vox;
+    };
+    auto put = [&](int pz) {
+      const int slot = (pz - z0 + 2) % 5;
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          pc[a] = P[a][pz][py][px];
-          d[a] = (double)dW[jb + (size_t)a * N];
-          s += d[a] * pc[a];
+      for (int s = 0; s < kPS; ++s) {
+        if (pi[s] >= 0) {
+          const int hy = pi[s] / HX, hx = pi[s] - (pi[s] / HX) * HX;
+#pragma unroll
+          for (int a = 0; a < D; ++a)
+            P[a][slot][hy][hx] =
+                it > 0 ? __builtin_fmaf(bf, rp[s][a], rz[s][a]) : rz[s][a];
         }
-        const double ds = md.data_c * (s - sbar);
-        // neighbours that leave the grid replicate this voxel: zero terms
-        const bool hd = z > 0, hu = z < m0 - 1, hn = y > 0, hs = y < m1 - 1,
-                   hw = x > 0, he = x < m2 - 1;
+      }
+    };
+    // L p on plane lz (1-cell halo in x, y) from the p planes lz - 1..lz + 1
+    auto lplane = [&](int lz) {
+      const int c = (lz - z0 + 2) % 5, dn = (lz - 1 - z0 + 2) % 5,
+                up = (lz + 1 - z0 + 2) % 5, sl = (lz - z0 + 1) % 3;
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          double btb;
-          if (REG) {
-            const int qz = lz + 1, qy = ly + 1, qx = lx + 1;
-            double c = L[a][qz][qy][qx];
-            btb = (hd ? L[a][qz - 1][qy][qx] - c : 0.0) +
-                  (hu ? L[a][qz + 1][qy][qx] - c : 0.0) +
-                  (hn ? L[a][qz][qy - 1][qx] - c : 0.0) +
-                  (hs ? L[a][qz][qy + 1][qx] - c : 0.0) +
-                  (hw ? L[a][qz][qy][qx - 1] - c : 0.0) +
-                  (he ? L[a][qz][qy][qx + 1] - c : 0.0);
-          } else {
-            double c = pc[a];
-            btb = -(((double)P[a][pz - 1][py][px] - c) +
-                    ((double)P[a][pz + 1][py][px] - c) +
-                    ((double)P[a][pz][py - 1][px] - c) +
-                    ((double)P[a][pz][py + 1][px] - c) +
-                    ((double)P[a][pz][py][px - 1] - c) +
-                    ((double)P[a][pz][py][px + 1] - c));
+      for (int s = 0; s < kLS; ++s) {
+        const int i = threadIdx.x + s * NT;
+        if (i < LX * LY) {
+          const int qy = i / LX, qx = i - (i / LX) * LX;
+          const int cy = qy + 1, cx = qx + 1;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            const double v = P[a][c][cy][cx];
+            L[a][sl][qy][qx] = ((double)P[a][dn][cy][cx] - v) +
+                               ((double)P[a][up][cy][cx] - v) +
+                               ((double)P[a][c][cy - 1][cx] - v) +
+                               ((double)P[a][c][cy + 1][cx] - v) +
+                               ((double)P[a][c][cy][cx - 1] - v) +
+                               ((double)P[a][c][cy][cx + 1] - v);
           }
-          double h = ds * d[a] + md.alpha_hd * md.reg_scale * btb +
-                     md.lam_c * vbar[a];
-          float hf = (float)h;
-          q[jb + (size_t)a * N] = hf;
-          p_new[jb + (size_t)a * N] = (float)pc[a];
-          acc += pc[a] * (double)hf;
+        }
+      }
+    };
+    for (int j = jbeg; j < jend; ++j) {
+      // prologue: p planes z0 - 2 .. z0 + 1, then L planes z0 - 1, z0
+      for (int pz = z0 - 2; pz <= z0 + 1; ++pz) {
+        fetch(j, pz);
+        put(pz);
+      }
+      fetch(j, z0 + 2);
+      __syncthreads();
+      if (REG) {
+        lplane(z0 - 1);
+        lplane(z0);
+      }
+      for (int zz = z0; zz < z1; ++zz) {
+        put(zz + 2);                  // staged one step ahead
+        __syncthreads();
+        if (zz + 3 <= z1 + 1) fetch(j, zz + 3);
+        if (REG) {
+          lplane(zz + 1);
+          __syncthreads();
+        }
+        if (inplane) {
+          const unsigned vox = (unsigned)((size_t)zz * plane_n + vxy);
+          double S = Sz[vox], V[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) V[a] = Vz[(size_t)a * N + vox];
+          if (it > 0) {
+            S += beta * Sp_old[vox];
+#pragma unroll
+            for (int a = 0; a < D; ++a)
+              V[a] += beta * Vp_old[(size_t)a * N + vox];
+          }
+          if (fg == 0 && j == jbeg) {
+            Sp_new[vox] = S;
+#pragma unroll
+            for (int a = 0; a < D; ++a) Vp_new[(size_t)a * N + vox] = V[a];
+          }
+          const double sbar = S * md.inv_nK;
+          double vbar[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) vbar[a] = V[a] * md.inv_nK;
+          const int c = (zz - z0 + 2) % 5, py = ly + 2, px = lx + 2;
+          double pc[D], d[D], sum = 0.0;
+          const size_t jb = (size_t)j * D * N + vox;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            pc[a] = P[a][c][py][px];
+            d[a] = (double)dW[jb + (size_t)a * N];
+            sum += d[a] * pc[a];
+          }
+          const double ds = md.data_c * (sum - sbar);
+          // neighbours that leave the grid replicate this voxel: zero terms
+          const bool hd = zz > 0, hu = zz < m0 - 1;
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            double btb;
+            if (REG) {
+              const int sm = (zz - 1 - z0 + 1) % 3, s0 = (zz - z0 + 1) % 3,
+                        sp = (zz + 1 - z0 + 1) % 3;
+              const int qy = ly + 1, qx = lx + 1;
+              const double cc = L[a][s0][qy][qx];
+              btb = (hd ? L[a][sm][qy][qx] - cc : 0.0) +
+                    (hu ? L[a][sp][qy][qx] - cc : 0.0) +
+                    (hn ? L[a][s0][qy - 1][qx] - cc : 0.0) +
+                    (hs ? L[a][s0][qy + 1][qx] - cc : 0.0) +
+                    (hw ? L[a][s0][qy][qx - 1] - cc : 0.0) +
+                    (he ? L[a][s0][qy][qx + 1] - cc : 0.0);
+            } else {
+              const int dn = (zz - 1 - z0 + 2) % 5, up = (zz + 1 - z0 + 2) % 5;
+              const double cc = pc[a];
+              btb = -(((double)P[a][dn][py][px] - cc) +
+                      ((double)P[a][up][py][px] - cc) +
+                      ((double)P[a][c][py - 1][px] - cc) +
+                      ((double)P[a][c][py + 1][px] - cc) +
+                      ((double)P[a][c][py][px - 1] - cc) +
+                      ((double)P[a][c][py][px + 1] - cc));
+            }
+            const double h = ds * d[a] + md.alpha_hd * md.reg_scale * btb +
+                             md.lam_c * vbar[a];
+            const float hf = (float)h;
+            q[jb + (size_t)a * N] = hf;
+            p_new[jb + (size_t)a * N] = (float)pc[a];
+            acc += pc[a] * (double)hf;
+          }
         }
       }
       __syncthreads();

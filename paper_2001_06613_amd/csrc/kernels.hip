@@ -67,14 +67,13 @@ int tile_blocks(const Geom& g) {
 }
 
 // Waves per block split the frames of K; more waves shorten the per-wave
-// frame loops (latency) at the cost of registers: 8 for the 2-D evaluation,
-// 4 otherwise.  The block size does not depend on |K| (waves without frames
-// idle), so that a problem gets the same blocks, and the same rounding,
-// alone and batched.
+// frame loops (latency) at the cost of registers and LDS: 8 for the 2-D
+// evaluation and trial sweeps, 4 in 3-D.  The block size does not depend on
+// |K| (waves without frames idle), so that a problem gets the same blocks,
+// and the same rounding, alone and batched.
 int tile_threads(int dim, int nK) {
-  (void)dim;
   (void)nK;
-  return 4 * kWave;
+  return (dim == 2 ? 8 : 4) * kWave;
 }
 int eval_threads(int dim, int nK) {
   (void)nK;
@@ -382,7 +381,7 @@ __device__ __forceinline__ void trial_body(
   if (ls.p > 0 && log[gn_it].next_pass != ls.p) return;
   constexpr int NT = kTrialSteps;
   constexpr int NV = 2 * NT + 2 * D;
-  __shared__ double xs[4][kWave][NV];
+  __shared__ double xs[D == 2 ? 8 : 4][kWave][NV];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = wave_id();
   const int G = blockDim.x / kWave;
@@ -483,7 +482,7 @@ __device__ __forceinline__ void trial_body(
 }
 
 template <int D, int REG>
-__global__ __launch_bounds__(256) void trial_kernel(
+__global__ __launch_bounds__(D == 2 ? 512 : 256) void trial_kernel(
     const float* __restrict__ T, const float* __restrict__ u,
     const float* __restrict__ dl, const float* __restrict__ gr,
     const int* __restrict__ K, Geom g, Model md, Steps st,
@@ -744,8 +743,8 @@ __global__ __launch_bounds__(256) void start_batch_kernel(JobSet js) {
 }
 
 template <int D, int REG>
-__global__ __launch_bounds__(256) void trial_batch_kernel(JobSet js, Steps st,
-                                                          LSPass ls) {
+__global__ __launch_bounds__(D == 2 ? 512 : 256) void trial_batch_kernel(
+    JobSet js, Steps st, LSPass ls) {
   Blk blk;
   const Job& J = job_of(js, kClsTile, blk);
   const Geom g = J.g;

@@ -182,6 +182,8 @@ hipError_t batch_advance(const JobSet& js, int* stop_out, hipStream_t s);
 // for and the pixels a batch may hold in total (frames x pixels per frame).
 void net_capacity(const stml_net* n, int* max_batch, long long* max_pixels);
 int net_dim(const stml_net* n);
+// 3-D Hessian-product columns: x, y tile and planes marched in z
+constexpr int kHv3X = 16, kHv3Y = 16, kHv3Z = 16;
 constexpr int kMaxNetWidth = 256;   // widest frame row the net accepts
 
 }  // namespace stml

@@ -228,14 +228,16 @@ bool setup_dims(stml_ctx* c, const stml_opts* o, int n, const int* extent) {
   // compact vectors index elements with 64-bit offsets, but the element
   // kernels decode the frame index from 32-bit rows
   if ((double)n * o->dim * (double)c->N[c->L - 1] > 2.0e9) return false;
-  // the Hessian product runs one block per 64 x 4 (3-D: 16 x 4 x 4) tile
-  // at least, and its partials must fit one reduction region
+  // the Hessian product runs one block per 64 x 4 tile (3-D: per column of
+  // kHv3X x kHv3Y x kHv3Z) at least, and its partials must fit one
+  // reduction region
   {
     const std::vector<int>& e = c->ext[c->L - 1];
     long long tiles =
-        o->dim == 2 ? (long long)((e[1] + 63) / 64) * ((e[0] + 3) / 4)
-                    : (long long)((e[2] + 15) / 16) * ((e[1] + 3) / 4) *
-                          ((e[0] + 3) / 4);
+        o->dim == 2
+            ? (long long)((e[1] + 63) / 64) * ((e[0] + 3) / 4)
+            : (long long)((e[2] + kHv3X - 1) / kHv3X) *
+                  ((e[1] + kHv3Y - 1) / kHv3Y) * ((e[0] + kHv3Z - 1) / kHv3Z);
     if (tiles > (long long)kRegionSlots - 8192 - 8) return false;
   }
   c->K = temporal_sets(n, c->T1);
