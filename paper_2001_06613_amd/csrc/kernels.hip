@@ -492,66 +492,56 @@ __global__ __launch_bounds__(D == 2 ? 512 : 256) void trial_kernel(
                      grid_blk());
 }
 
-// One block: objective at the trial steps, g.delta, max |delta| and
-// sum delta^2.
-__device__ __forceinline__ void finalize_trial_body(
-    const double* __restrict__ part, int nb, const Model& md,
-    const Steps& st, Scal* __restrict__ sc, int gn_it, LSPass ls,
-    GNLog* __restrict__ log) {
-  if (gn_it >= sc->gn_stop) return;
-  if (ls.p > 0 && log[gn_it].next_pass != ls.p) return;
-  constexpr int NT = kTrialSteps;
-  double out[NT + 9];
-  reduce_partials<NT + 9>(part, nb, 1u << (NT + 7), out);
-  if (threadIdx.x == 0) {
-    double sA = md.half_alpha_hd * md.reg_scale;
-    for (int s = 0; s < NT; ++s) {
-      double t = st.t[s];
-      double Dv = md.hd * out[s];
-      double Sv = sA * (out[NT] + 2.0 * t * out[NT + 1] + t * t * out[NT + 2]);
-      double Pv = md.lam_hd *
-                  (out[NT + 3] + 2.0 * t * out[NT + 4] + t * t * out[NT + 5]);
-      sc->Jt[s] = Dv + Sv + Pv;
-    }
-    sc->slope = out[NT + 6];
-    sc->maxd = out[NT + 7];
-    if (ls.p == 0) {
-      GNLog& L = log[gn_it];
-      L.J0t = sc->Jt[0];
-      L.slope = out[NT + 6];
-      L.maxd = out[NT + 7];
-      L.ssqd = out[NT + 8];
-    }
-  }
-}
-
-__global__ __launch_bounds__(256) void finalize_trial_kernel(
-    const double* __restrict__ part, int nb, Model md, Steps st,
-    Scal* __restrict__ sc, int gn_it, LSPass ls, GNLog* __restrict__ log) {
-  finalize_trial_body(part, nb, md, st, sc, gn_it, ls, log);
-}
-
 // Armijo decision of sweep ls and, if a step passes, u[K[j]] += t delta_j.
-// Every block takes the same decision from the same values.  Flags a later
-// block of this kernel might read (next_pass, gn_stop) are only written in
-// ways that leave such a block's work unchanged.
+// Every block first totals the trial sweep's partials itself (the
+// objective at the sweep's steps, g.delta, max |delta|, sum delta^2) and so
+// takes the same decision from the same values; block 0 records them.
+// Flags a later block of this kernel might read (next_pass, gn_stop) are
+// only written in ways that leave such a block's work unchanged; each block
+// reads them once, so that its threads agree.
 __device__ __forceinline__ void ls_accept_body(
     float* __restrict__ u, const float* __restrict__ dl,
     const int* __restrict__ K, int nK, int dim, long long N, const Steps& st,
     LSPass ls, int ls_max, double c1, int fixed, double tol_J, double tol_u,
-    int gn_it, Scal* __restrict__ sc, GNLog* __restrict__ log, Blk blk) {
-  if (gn_it >= sc->gn_stop) return;
+    const double* __restrict__ tpart, int tnb, const Model& md, int gn_it,
+    Scal* __restrict__ sc, GNLog* __restrict__ log, Blk blk) {
+  __shared__ int skip;
   GNLog* L = log + gn_it;
-  if (ls.p > 0 && L->next_pass != ls.p) return;
-  const double J0t = L->J0t, slope = L->slope;
+  if (threadIdx.x == 0)
+    skip = gn_it >= sc->gn_stop || (ls.p > 0 && L->next_pass != ls.p);
+  __syncthreads();
+  if (skip) return;
+  constexpr int NT = kTrialSteps;
+  double out[NT + 9];
+  reduce_partials<NT + 9>(tpart, tnb, 1u << (NT + 7), out);
+  double Jt[NT];
+  const double sA = md.half_alpha_hd * md.reg_scale;
+#pragma unroll
+  for (int s = 0; s < NT; ++s) {
+    const double t = st.t[s];
+    const double Dv = md.hd * out[s];
+    const double Sv =
+        sA * (out[NT] + 2.0 * t * out[NT + 1] + t * t * out[NT + 2]);
+    const double Pv = md.lam_hd * (out[NT + 3] + 2.0 * t * out[NT + 4] +
+                                   t * t * out[NT + 5]);
+    Jt[s] = Dv + Sv + Pv;
+  }
+  const double J0t = ls.p == 0 ? Jt[0] : L->J0t;
+  const double slope = ls.p == 0 ? out[NT + 6] : L->slope;
+  if (ls.p == 0 && blk.id == 0 && threadIdx.x == 0) {
+    L->J0t = Jt[0];
+    L->slope = out[NT + 6];
+    L->maxd = out[NT + 7];
+    L->ssqd = out[NT + 8];
+  }
   double tacc = -1.0, Jacc = 0.0;
-  for (int s = ls.base; s < kTrialSteps; ++s) {
-    int e = ls.e0 + (s - ls.base);
-    if (e > ls_max) break;
-    if (sc->Jt[s] <= J0t + c1 * st.t[s] * slope) {
+#pragma unroll
+  for (int s = 0; s < NT; ++s) {
+    const int e = ls.e0 + (s - ls.base);
+    if (tacc < 0.0 && s >= ls.base && e <= ls_max &&
+        Jt[s] <= J0t + c1 * st.t[s] * slope) {
       tacc = st.t[s];
-      Jacc = sc->Jt[s];
-      break;
+      Jacc = Jt[s];
     }
   }
   if (tacc < 0.0) {
@@ -584,7 +574,7 @@ __device__ __forceinline__ void ls_accept_body(
     L->Jacc = Jacc;
     L->cg = sc->iters;
     L->status = breakdown ? 2 : 0;
-    const double rms = sqrt(L->ssqd / (double)count);
+    const double rms = sqrt(out[NT + 8] / (double)count);
     bool stop = breakdown ||
                 (!fixed && (L->J - Jacc) <= tol_J * fabs(L->J) &&
                  tacc * rms <= tol_u);
@@ -596,9 +586,10 @@ __global__ __launch_bounds__(256) void ls_accept_kernel(
     float* __restrict__ u, const float* __restrict__ dl,
     const int* __restrict__ K, int nK, int dim, long long N, Steps st,
     LSPass ls, int ls_max, double c1, int fixed, double tol_J, double tol_u,
-    int gn_it, Scal* __restrict__ sc, GNLog* __restrict__ log) {
+    const double* __restrict__ tpart, int tnb, Model md, int gn_it,
+    Scal* __restrict__ sc, GNLog* __restrict__ log) {
   ls_accept_body(u, dl, K, nK, dim, N, st, ls, ls_max, c1, fixed, tol_J,
-                 tol_u, gn_it, sc, log, grid_blk());
+                 tol_u, tpart, tnb, md, gn_it, sc, log, grid_blk());
 }
 
 // Start of a registration: every Gauss-Newton iteration enabled, logs
@@ -754,24 +745,16 @@ __global__ __launch_bounds__(D == 2 ? 512 : 256) void trial_batch_kernel(
                      J.rb.region(kRegTrial), sc->gn_cur, ls, sc, J.log, blk);
 }
 
-__global__ __launch_bounds__(256) void trial_final_batch_kernel(JobSet js,
-                                                                Steps st,
-                                                                LSPass ls) {
-  const Job& J = js.jobs[blockIdx.x];
-  const Model md = J.md;
-  Scal* sc = J.sc;
-  finalize_trial_body(J.rb.region(kRegTrial), J.nb_tile, md, st, sc,
-                      sc->gn_cur, ls, J.log);
-}
-
 __global__ __launch_bounds__(256) void accept_batch_kernel(
     JobSet js, Steps st, LSPass ls, int ls_max, double c1, int fixed,
     double tol_J, double tol_u) {
   Blk blk;
   const Job& J = job_of(js, kClsElem, blk);
   Scal* sc = J.sc;
-  ls_accept_body(J.u, J.x, J.K, J.md.nK, geom_dim(J.g), J.g.N, st, ls,
-                 ls_max, c1, fixed, tol_J, tol_u, sc->gn_cur, sc, J.log, blk);
+  const Model md = J.md;
+  ls_accept_body(J.u, J.x, J.K, md.nK, geom_dim(J.g), J.g.N, st, ls, ls_max,
+                 c1, fixed, tol_J, tol_u, J.rb.region(kRegTrial), J.nb_tile,
+                 md, sc->gn_cur, sc, J.log, blk);
 }
 
 // Start of a batched registration: per problem, every iteration enabled,
@@ -827,7 +810,6 @@ hipError_t batch_trial(const JobSet& js, int ntile, int dim, int reg,
   for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
   STML_TILE_DISPATCH(dim, reg, trial_batch_kernel, ntile,
                      tile_threads(dim, 0), s, js, st, ls);
-  trial_final_batch_kernel<<<js.n, 256, 0, s>>>(js, st, ls);
   return hipGetLastError();
 }
 
@@ -929,22 +911,21 @@ hipError_t launch_trial(int dim, const float* T, const float* u,
   double* part = rb.region(kRegTrial);
   STML_TILE_DISPATCH(dim, md.reg, trial_kernel, nb, nt, s, T, u, delta, grad,
                      K, g, md, st, part, gn_it, ls, sc, log);
-  finalize_trial_kernel<<<1, 256, 0, s>>>(part, nb, md, st, sc, gn_it, ls,
-                                          log);
   return hipGetLastError();
 }
 
 hipError_t launch_ls_accept(float* u, const float* delta, const int* K,
-                            int nK, int dim, long long N, const double* t,
+                            const Geom& g, const Model& md, const double* t,
                             LSPass ls, int ls_max, double c1, int fixed,
-                            double tol_J, double tol_u, int gn_it, Scal* sc,
-                            GNLog* log, hipStream_t s) {
+                            double tol_J, double tol_u, RedBuf rb, int gn_it,
+                            Scal* sc, GNLog* log, hipStream_t s) {
   Steps st;
   for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
-  size_t count = (size_t)nK * dim * N;
+  const int dim = geom_dim(g);
+  size_t count = (size_t)md.nK * dim * g.N;
   ls_accept_kernel<<<elem_blocks(count), 256, 0, s>>>(
-      u, delta, K, nK, dim, N, st, ls, ls_max, c1, fixed, tol_J, tol_u, gn_it,
-      sc, log);
+      u, delta, K, md.nK, dim, g.N, st, ls, ls_max, c1, fixed, tol_J, tol_u,
+      rb.region(kRegTrial), tile_blocks(g), md, gn_it, sc, log);
   return hipGetLastError();
 }
 

@@ -67,12 +67,13 @@ hipError_t launch_trial(int dim, const float* T, const float* u,
                         const Geom& g, const Model& md, const double* t,
                         RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
                         LSPass ls, GNLog* log);
-// Armijo decision of sweep ls; u[K[j]] += t delta_j for the accepted t.
+// Armijo decision of sweep ls from the trial sweep's partials; u[K[j]] +=
+// t delta_j for the accepted t.
 hipError_t launch_ls_accept(float* u, const float* delta, const int* K,
-                            int nK, int dim, long long N, const double* t,
+                            const Geom& g, const Model& md, const double* t,
                             LSPass ls, int ls_max, double c1, int fixed,
-                            double tol_J, double tol_u, int gn_it, Scal* sc,
-                            GNLog* log, hipStream_t s);
+                            double tol_J, double tol_u, RedBuf rb, int gn_it,
+                            Scal* sc, GNLog* log, hipStream_t s);
 hipError_t launch_gn_reset(Scal* sc, GNLog* log, int n, hipStream_t s);
 // One block: objective of the evaluation (ev_nb partials) and the CG start
 // scalars (in_nb partials of the CG start kernel).

@@ -536,9 +536,9 @@ int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
             launch_trial(D, T, u, c->x, c->g, Kdev, g, md, steps[pi].data(),
                          c->rb, c->sc, c->stream, it, passes[pi], c->gnlog));
       TIMED(STML_K_ACCEPT, level, vf,
-            launch_ls_accept(u, c->x, Kdev, nK, D, g.N, steps[pi].data(),
+            launch_ls_accept(u, c->x, Kdev, g, md, steps[pi].data(),
                              passes[pi], o.ls_max, o.c1, o.parity_mode,
-                             o.tol_J, o.tol_u, it, c->sc, c->gnlog,
+                             o.tol_J, o.tol_u, c->rb, it, c->sc, c->gnlog,
                              c->stream));
     }
     if (!o.parity_mode) {

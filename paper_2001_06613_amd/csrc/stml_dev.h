@@ -58,9 +58,6 @@ struct Scal {
   double rzh[2];              // r.z of CG iteration it in slot it & 1
   double r0, a, beta;         // CG scalars
   double pq, rr;
-  double Jt[8];               // objective at the trial steps
-  double slope;               // g . delta
-  double maxd;                // max |delta|
   double vHv;
   int done;                   // 0 running, 1 converged, 2 breakdown
   int iters;                  // CG iterations taken
