@@ -27,6 +27,9 @@ constexpr int kLX = kTX + 2;       // L p on a 1-cell halo
 constexpr int kLY = kTY + 2;
 // 3-D columns: 16 (x) x 16 (y) points marched through 16 planes in z
 constexpr int kT3X = kHv3X, kT3Y = kHv3Y, kT3Z = kHv3Z;
+// threads of a Hessian-product block: one per tile point
+constexpr int kHv2Threads = kTX * kTY;
+constexpr int kHv3Threads = kT3X * kT3Y;
 
 // Frames of a voxel-major tile handled by this wave.
 __device__ __forceinline__ void wave_frames(int nK, int& j0, int& j1) {
@@ -430,7 +433,7 @@ __device__ __forceinline__ void cgt_hvp2_body(
 // Eight blocks per compute unit (at most 64 registers per lane) keep enough
 // tile loads in flight (the diffusion form needs more registers: five).
 template <int REG>
-__global__ __launch_bounds__(256, REG ? 8 : 5) void cgt_hvp2_kernel(
+__global__ __launch_bounds__(kHv2Threads, REG ? 8 : 5) void cgt_hvp2_kernel(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
     Model md, float* __restrict__ q, const double* __restrict__ Sz,
@@ -669,7 +672,7 @@ __device__ __forceinline__ void cgt_hvp3_body(
 }
 
 template <int REG>
-__global__ __launch_bounds__(256) void cgt_hvp3_kernel(
+__global__ __launch_bounds__(kHv3Threads) void cgt_hvp3_kernel(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
     Model md, float* __restrict__ q, const double* __restrict__ Sz,
@@ -749,8 +752,9 @@ hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
   // with events: the dispatch records its own start and end
   auto kern = dim == 2 ? (md.reg == 0 ? cgt_hvp2_kernel<0> : cgt_hvp2_kernel<1>)
                        : (md.reg == 0 ? cgt_hvp3_kernel<0> : cgt_hvp3_kernel<1>);
-  hipExtLaunchKernelGGL(kern, dim3(t.grid), dim3(kTX * kTY), 0, s, ev0, ev1,
-                        0, it, z, p_old, p_new, dW, g, md, q, sums.Sz,
+  hipExtLaunchKernelGGL(kern, dim3(t.grid),
+                        dim3(dim == 2 ? kHv2Threads : kHv3Threads), 0, s, ev0,
+                        ev1, 0, it, z, p_old, p_new, dW, g, md, q, sums.Sz,
                         sums.Vz, Sp_old, Vp_old, Sp_new, Vp_new, t.nreal,
                         t.nfg, t.fpg, (const double*)rb.region(kRegUpdate),
                         t.vox_grid, fixed, rtol, rb.region(kRegHv), sc, gn_it);
@@ -810,7 +814,8 @@ __global__ __launch_bounds__(1024) void cg_init_batch_kernel(JobSet js) {
 }
 
 template <int D, int REG>
-__global__ __launch_bounds__(256, D == 3 ? 1 : (REG ? 8 : 5)) void cg_hvp_batch_kernel(
+__global__ __launch_bounds__(D == 2 ? kHv2Threads : kHv3Threads,
+                             D == 3 ? 1 : (REG ? 8 : 5)) void cg_hvp_batch_kernel(
     JobSet js, int it, int fixed, double rtol) {
   Blk blk;
   const Job& J = cg_job_of(js, kClsHv, blk);
@@ -877,7 +882,8 @@ hipError_t batch_cg_hvp(const JobSet& js, int nhv, int dim, int reg, int it,
                               : cg_hvp_batch_kernel<2, 1>)
                   : (reg == 0 ? cg_hvp_batch_kernel<3, 0>
                               : cg_hvp_batch_kernel<3, 1>);
-  kern<<<nhv, kTX * kTY, 0, s>>>(js, it, fixed, rtol);
+  kern<<<nhv, dim == 2 ? kHv2Threads : kHv3Threads, 0, s>>>(js, it, fixed,
+                                                            rtol);
   return hipGetLastError();
 }
 

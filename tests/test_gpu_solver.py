@@ -225,6 +225,31 @@ def test_large_level_parity():
     assert _rel(hv.cpu().numpy(), Hv_ref) <= 1e-5
 
 
+def test_large_volume_level_parity():
+    """8 frames of 128x128x64 (the volume workload's finest extent), all
+    frames, in the launch configuration the benchmark uses."""
+    n, ext = 8, (128, 128, 64)
+    frames = synth.sinusoid_sequence(n, ext, 4.0, 3, 3)[0]
+    o = default_opts(dim=3, n_spatial=3, n_temporal=3, reg="curvature",
+                     alpha=0.1, cg_max=3, parity_mode=True)
+    st = STML(n, ext, opts=o)
+    st.set_sequence(torch.from_numpy(frames).cuda())
+    u = synth.random_displacement(ext, n, 3.0, 12)
+    K = list(range(n))
+    print("large volume eval", flush=True)
+    out = st.eval(2, K, torch.from_numpy(u))
+    par = oracle.ModelParams(alpha=0.1, reg="curvature")
+    ref = oracle.objective(frames, u, K, 1.0, par)
+    assert abs(out["J"] - ref["J"]) <= 1e-5 * abs(ref["J"])
+    assert _rel(out["g"].cpu().numpy(), ref["g"]) <= 1e-5
+    print("large volume hessvec", flush=True)
+    v = np.random.default_rng(2).standard_normal(ref["g"].shape).astype(
+        np.float32)
+    hv, _ = st.hessvec(2, K, torch.from_numpy(u), torch.from_numpy(v))
+    Hv_ref = oracle.hessvec(ref["dW"].astype(np.float32), v, 1.0, par)
+    assert _rel(hv.cpu().numpy(), Hv_ref) <= 1e-5
+
+
 def _volume(n, ext, seed):
     return synth.sinusoid_sequence(n, ext, 1.5, 1, seed)[0]
 
