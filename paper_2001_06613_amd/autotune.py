@@ -24,9 +24,13 @@ DEFAULT = {"tile_blocks": 512, "vox_blocks": 512, "hv_blocks": 2048}
 
 
 def cache_key(stmls, batched):
+    """Device (architecture and compute-unit count: the marketing name is
+    not always resolvable), batched or single, and the problem shapes."""
     import torch
 
-    dev = torch.cuda.get_device_name(stmls[0].device)
+    prop = torch.cuda.get_device_properties(stmls[0].device)
+    arch = getattr(prop, "gcnArchName", "") or prop.name
+    dev = f"{arch.split(':')[0]}x{prop.multi_processor_count}"
     shapes = ";".join(f"{s.n}x" + "x".join(map(str, s.extent)) for s in stmls)
     return f"{dev}|{'batch' if batched else 'single'}|{shapes}"
 
