@@ -74,26 +74,36 @@ def _traffic_record():
     return rec.get("hbm_bytes_per_launch")
 
 
-def cpu_baseline(frames, budget_s=30.0):
-    """Oracle timed on the host: one Gauss-Newton iteration (evaluation,
-    10 CG Hessian products, Armijo search) over all 64 frames at the
-    finest level, from zero displacement."""
+def cpu_baseline(frames, budget_s=10.0):
+    """Oracle timed on the host, one thread: Gauss-Newton iterations
+    (evaluation, 10 CG Hessian products, Armijo search) over all 64 frames
+    at the finest level, from zero displacement, repeated until budget_s
+    seconds have passed."""
+    from threadpoolctl import threadpool_limits
+
     import oracle
 
     w = WORKLOAD
     par = oracle.ModelParams(alpha=w["alpha"], lam=w["lam"], reg=w["reg"])
     n = frames.shape[0]
     u0 = np.zeros((n, 2) + frames.shape[1:])
-    t0 = time.perf_counter()
-    res = oracle.gauss_newton(frames, u0, list(range(n)), 1.0, par, gn_max=1,
-                              cg_max=w["cg_max"], fixed=True)
-    dt = time.perf_counter() - t0
-    units = n * float(np.prod(frames.shape[1:])) * (1 + res.cg_iterations[0])
+    units, reps = 0.0, 0
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            res = oracle.gauss_newton(frames, u0, list(range(n)), 1.0, par,
+                                      gn_max=1, cg_max=w["cg_max"],
+                                      fixed=True)
+            units += n * float(np.prod(frames.shape[1:])) * (
+                1 + res.cg_iterations[0])
+            reps += 1
+        dt = time.perf_counter() - t0
     return {"value": units / dt / 1e9, "unit": "Gvoxel-frames/s", "cores": 1,
             "kind": "oracle",
-            "sample": "one Gauss-Newton iteration (1 evaluation + 10 Hessian "
-                      "products + CG + Armijo) over 64 frames x 256x256 at "
-                      f"the finest level, NumPy float64, {dt:.1f} s"}
+            "sample": f"{reps} x one Gauss-Newton iteration (1 evaluation + "
+                      "10 Hessian products + CG + Armijo) over 64 frames x "
+                      "256x256 at the finest level, NumPy float64, one "
+                      f"thread, {dt:.1f} s"}
 
 
 def _gen_batch_sequence(args):
@@ -263,6 +273,88 @@ def learned_comparison(seqs, log):
                for k, v in s.items() if k != "sequences"}}
 
 
+def copy_ceiling(nbytes=1 << 30, reps=5):
+    """Device-to-device copy of nbytes (read + write), median GB/s."""
+    import torch
+
+    x = torch.ones(nbytes // 4, device="cuda")
+    y = torch.empty_like(x)
+    ts = []
+    for _ in range(reps + 1):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        y.copy_(x)
+        b.record()
+        b.synchronize()
+        ts.append(a.elapsed_time(b))
+    del x, y
+    return 2 * nbytes / (float(np.median(ts[1:])) * 1e-3) / 1e9
+
+
+def small_solve(reps=20):
+    """The 8-frame 64x64 sequence (diffusion alpha 1e-2, 2 spatial x 2
+    temporal levels, fixed 5 GN x 10 CG): launch-bound, reported without a
+    roofline claim."""
+    import torch
+    from paper_2001_06613_amd import synth
+    from paper_2001_06613_amd.binding import STML, default_opts
+
+    frames, _ = synth.config_small(0)
+    opts = default_opts(n_spatial=2, n_temporal=2, reg="diffusion",
+                        alpha=1e-2, gn_max=5, cg_max=10, parity_mode=True)
+    st = STML(8, frames.shape[1:], opts=opts)
+    fr = torch.from_numpy(frames).cuda()
+
+    def solve():
+        st.set_sequence(fr)
+        st.run()
+
+    solve()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        solve()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) / reps * 1e3
+    units = _units(st.logs(), [st.level_extent(l) for l in range(2)])
+    st.close()
+    return {"workload": "8 frames x 64x64, 2 x 2 levels, fixed 5 GN x 10 CG",
+            "solve_ms": round(ms, 2), "value": round(units / ms / 1e6, 3),
+            "unit": "Gvoxel-frames/s"}
+
+
+def oracle_full():
+    """The oracle's whole schedule on the 8-frame 64x64 and the 64-frame
+    256x256 sequences (fixed iterations), on this host's cores."""
+    import oracle
+    from paper_2001_06613_amd import synth
+
+    # BLAS and OpenMP pools limited to one thread; the affinity set is what
+    # the host offers
+    out = {"threads": 1, "available_cores": len(os.sched_getaffinity(0)),
+           "cpu_count": os.cpu_count()}
+    f1, _ = synth.config_small(0)
+    kw1 = dict(n_spatial=2, n_temporal=2, reg="diffusion", alpha=1e-2,
+               gn_max=5, cg_max=10, parity_mode=True)
+    from threadpoolctl import threadpool_limits
+
+    lim = threadpool_limits(1)
+    t0 = time.perf_counter()
+    oracle.stml_run(f1, oracle.STMLOptions(**kw1))
+    out["small_s"] = round(time.perf_counter() - t0, 2)
+    w = WORKLOAD
+    f2, _ = synth.config_large(1)
+    kw2 = dict(n_spatial=w["n_spatial"], n_temporal=w["n_temporal"],
+               reg=w["reg"], alpha=w["alpha"], gn_max=w["gn_max"],
+               cg_max=w["cg_max"], parity_mode=True)
+    t0 = time.perf_counter()
+    oracle.stml_run(f2, oracle.STMLOptions(**kw2))
+    out["large_s"] = round(time.perf_counter() - t0, 2)
+    lim.unregister()
+    print(json.dumps({"oracle_full": out}), flush=True)
+
+
 def learned3d_comparison(seqs, log):
     """Paper's predictor vs the shipped 3-D learned one on held-out
     32-frame 128x128x64 volumes (convergence-controlled Gauss-Newton)."""
@@ -304,9 +396,15 @@ def main():
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-volume", action="store_true")
+    ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--oracle-full", action="store_true",
+                    help="time the oracle's whole schedule (CPU only)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="one solve and a copy of known size (counter runs)")
     args = ap.parse_args()
+    if args.oracle_full:
+        oracle_full()
+        return
     if args.gpus != 1:
         print(f"bench.py: --gpus {args.gpus} is not supported: this build "
               "runs the registration path on one GPU only", file=sys.stderr)
@@ -389,11 +487,29 @@ def main():
     fin = st.timing_get(DOMINANT, w["n_spatial"] - 1)
     fin_gbs = fin["bytes"] / (fin["ms"] * 1e-3) / 1e9 if fin["ms"] > 0 else 0.0
     traffic = _traffic_record()
+    copy_gbs = copy_ceiling()
     # per-kernel breakdown from one extra, separately timed solve (every
     # class bracketed), outside the timed region
     st.timing(True)
     step()
     st.timing(False)
+    # the metric's own kernels alone (evaluation and Hessian products, as
+    # many as the schedule runs) at the finest level, and their roofline
+    lf = w["n_spatial"] - 1
+    ue, uh = st.timing_get("eval", lf), st.timing_get("hessvec", lf)
+    unit_s = (ue["ms"] + uh["ms"]) * 1e-3
+    unit_vf = ue["voxel_frames"] + uh["voxel_frames"]
+    unit_gbs = (ue["bytes"] + uh["bytes"]) / unit_s / 1e9
+    metric_unit = {
+        "what": "evaluation (warp, distance, gradient) and Hessian-product "
+                "kernels alone, finest level",
+        "Gvf_s": round(unit_vf / unit_s / 1e9, 2),
+        "GBs": round(unit_gbs, 1),
+        "frac": round(unit_gbs / HBM_PEAK_GBS, 4),
+        "bytes_per_vf": round((ue["bytes"] + uh["bytes"]) / unit_vf, 2),
+        "roofline_Gvf_s": round(HBM_PEAK_GBS * 1e9 /
+                                ((ue["bytes"] + uh["bytes"]) / unit_vf) /
+                                1e9, 1)}
     kernels = {}
     for k in ("eval", "hessvec", "cg_update", "trial", "cg_init", "accept",
               "predict", "restrict"):
@@ -435,10 +551,14 @@ def main():
             "timed_every": TIME_EVERY,
             "algorithmic_bytes_per_launch": bytes_total / max(dk["launches"], 1),
             "finest_level_GBs": round(fin_gbs, 1),
+            "measured_copy_GBs": round(copy_gbs, 1),
         },
         "kernels_one_solve": kernels,
+        "metric_unit": metric_unit,
     }
     st.close()
+    if not args.no_small:
+        out["small"] = small_solve()
     if batch_seqs is not None:
         out["batched"] = batched_comparison(batch_seqs, log)
     if learned_seqs is not None:

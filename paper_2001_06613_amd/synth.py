@@ -164,11 +164,11 @@ def config_volume(seed=3, n=32, shape=(128, 128, 64), max_disp=4.0):
 def config_volume_batch(master_seed=4, count=4, n_range=(24, 40)):
     """(n, seed) of the 3D batch: n ~ U{24..40} frames of 128x128x64.
 
-    Sequence s is drawn with seed 200 + s by ``sinusoid_sequence`` (3
-    temporal sinusoids, max 4 px).
+    Sequence s is drawn with seed 30 + s by ``sinusoid_sequence`` (3
+    temporal sinusoids, max 4 px); the frame counts by the master seed.
     """
     rng = _rng(master_seed)
-    return [(int(rng.integers(n_range[0], n_range[1] + 1)), 200 + s)
+    return [(int(rng.integers(n_range[0], n_range[1] + 1)), 30 + s)
             for s in range(count)]
 
 
