@@ -1,4 +1,4 @@
-// Conjugate-gradient kernels of the Gauss-Newton step for 2-D sequences.
+// Conjugate-gradient kernels of the Gauss-Newton step (images and volumes).
 //
 // The Gauss-Newton Hessian couples the frames of a voxel only through two
 // per-voxel sums, S = sum_k dW_k . v_k and V = sum_k v_k.  The CG direction
@@ -6,11 +6,13 @@
 // by the kernel that writes z) and of p_old (kept from the previous
 // product): S_p = S_z + beta S_pold.  The Hessian product therefore needs
 // no sweep over frames and runs as a plain stencil kernel, parallel over
-// (frame, spatial tile): each block stages p = z + beta p_old of a 64 x 4
-// tile with a 2-cell halo in LDS, forms L p once per point and L (L p) from
-// LDS.  The vector updates are voxel-major (the waves of a block split the
-// frames of a 64-voxel tile) so that they can sum S_z and V_z per voxel; the
-// Jacobi diagonal is recomputed there from dW/du instead of being stored.
+// (frame, spatial tile): in 2-D each block stages p = z + beta p_old of a
+// 64 x 4 tile with a 2-cell halo in LDS, forms L p once per point and
+// L (L p) from LDS; in 3-D a block marches a 16 x 16 column through the
+// planes with rings of planes in LDS.  The vector updates are voxel-major
+// (the waves of a block split the frames of a 64-voxel tile) so that they
+// can sum S_z and V_z per voxel; the Jacobi diagonal is recomputed there
+// from dW/du instead of being stored.
 #include <hip/hip_ext.h>
 #include <math.h>
 

@@ -700,13 +700,6 @@ using namespace stml::cnn;
 
 namespace {
 
-// A tensor view: NHWC with channel stride ld and channel offset off.
-struct TV {
-  void* p;
-  int ld, off, C;
-  int level;       // resolution level 0 (full) .. 3 (1/8)
-};
-
 struct Buf {
   bf16* a;   // activation (bfloat16)
   float* g;  // gradient (float32)

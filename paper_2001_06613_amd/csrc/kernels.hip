@@ -1,12 +1,11 @@
 // HIP kernels of the STML registration path for gfx950 (CDNA4, wave64).
 //
-// Tile kernels (evaluation, Hessian product, trial steps) give every block
-// one or more 64-voxel tiles; the waves of a block split the frames of the
-// subset K between them, so each voxel's cross-frame means (mean warped
-// image, mean displacement) are combined through LDS without a second HBM
-// pass.  Frames a thread owns stay in registers between the two sweeps.
-// All warp and residual arithmetic is float64 from float32 loads; every
-// reduction is float64 and deterministic.
+// Tile kernels (evaluation, trial steps) give every block one or more
+// 64-voxel tiles; the waves of a block split the frames of the subset K
+// between them, so each voxel's cross-frame means (mean warped image, mean
+// displacement) are combined through LDS; the evaluation's second sweep
+// re-reads its frames from the caches.  All warp and residual arithmetic is
+// float64 from float32 loads; every reduction is float64 and deterministic.
 #include <math.h>
 
 #include "launch.h"

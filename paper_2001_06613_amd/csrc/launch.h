@@ -92,10 +92,11 @@ struct CgSums {
   double* Sp[2];
   double* Vp[2];
 };
-struct CgTiles {             // launch shape of the 2-D Hessian product
+struct CgTiles {             // launch shape of the Hessian product
   int nreal, nfg, fpg, grid, vox_grid;
 };
-// Launch shape of the Hessian product (2-D: 64 x 4 tiles, 3-D: 16 x 4 x 4)
+// Launch shape of the Hessian product (2-D: 64 x 4 tiles, 3-D: columns of
+// kHv3X x kHv3Y x kHv3Z) and of the voxel-major updates
 CgTiles cg_tiles(const Geom& g, int nK, int dim);
 int cg_tile_count(const Geom& g, int dim);
 hipError_t launch_cgv_init(int dim, const float* grad, const float* dW,
