@@ -113,9 +113,10 @@ void stml_default_opts(stml_opts* opts);
 
 /* Bytes of device workspace a context for n frames of the given finest
  * extent (dim entries, slowest first) needs.  0 if the arguments are
- * invalid: n outside 1..STML_MAX_FRAMES, n dim N above 2e9 values, or (2-D)
- * more than 8184 tiles of 64 x 4 pixels at the finest level (about 2 Mpx,
- * e.g. 1448 x 1448). */
+ * invalid: n outside 1..STML_MAX_FRAMES, n dim N above 2e9 values, or
+ * more than 8184 Hessian-product tiles at the finest level (2-D: 64 x 4
+ * pixels, about 2 Mpx, e.g. 1448 x 1448; 3-D: columns of 16 x 16 x 16
+ * voxels, about 33 M voxels). */
 size_t stml_workspace_bytes(const stml_opts* opts, int n, const int* extent);
 
 /* Create a context.  workspace_dev must stay valid, untouched by the caller,
@@ -225,7 +226,7 @@ int stml_gn_direction(stml_ctx* ctx, int level, const int* frames, int nk,
 #define STML_K_COUNT       9
 #define STML_K_ALL       0x1ff  /* mask of every class                     */
 
-/* Launch shape of the 2-D kernels (autotuned by the caller; every value a
+/* Launch shape of the kernels (autotuned by the caller; every value a
  * multiple of 8): blocks per registration for the objective and trial
  * kernels (8..1024, default 512) and for the voxel-major CG updates
  * (8..1024, default 512), and the block target of the Hessian product
@@ -260,21 +261,24 @@ int stml_timing_get(stml_ctx* ctx, int kernel, int level, double* total_ms,
  * A convolutional encoder-decoder that refines the linear interpolation of
  * a frame t between its registered neighbours l < t < r (Sec. 3 predicts
  * such frames by interpolation; the network adds a learned correction).
- * 2-D only.  Input channels: frame_l, frame_t, frame_r, u_l / h, u_r / h
- * (displacements in pixels of the level, h = cell width); output: the
- * 2-channel correction c, u_t = w_l u_l + w_r u_r + h c with the linear
- * weights w_l = (r - t) / (r - l), w_r = (t - l) / (r - l).  Encoder 3x3
- * convolutions 32/64/128/128 with ReLU and 2x2 average pooling, decoder
+ * For images (dim 2) and volumes (dim 3; D = dim components).  Input
+ * channels: frame_l, frame_t, frame_r, u_l / h, u_r / h (3 + 2D channels;
+ * displacements in pixels of the level, h = cell width); output: the
+ * D-channel correction c, u_t = w_l u_l + w_r u_r + h c with the linear
+ * weights w_l = (r - t) / (r - l), w_r = (t - l) / (r - l).  Encoder 3^dim
+ * convolutions 32/64/128/128 with ReLU and 2^dim average pooling, decoder
  * with nearest upsampling and skip concatenation, 1x1 head.  Parameters are
- * one float32 vector (layer by layer W[tap][c_out][c_in] then b[c_out]);
- * kernels use bfloat16 weights and activations with float32 accumulation
- * (MFMA), float32 gradients, Adam on the float32 master copy.  Extents must
- * be multiples of 8, widths at most 256.  The net is sized for max_batch frames of max_extent;
- * a batch may hold any number B of frames of any extent H x W with
- * B H W <= max_batch times the pixels of max_extent.  All buffers:
- * caller-owned device memory; the net keeps the last assembled batch until
- * the next one.  Errors: STML_EINVAL (shapes, null pointers, triples not
- * l < t < r), STML_ESTATE (no batch yet), STML_EDEVICE. */
+ * one float32 vector (layer by layer W[tap][c_out][c_in] then b[c_out], the
+ * taps in row-major order of their offsets); kernels use bfloat16 weights
+ * and activations with float32 accumulation (MFMA), float32 gradients, Adam
+ * on the float32 master copy.  Extents (H, W in 2-D; Z, H, W in 3-D, W
+ * fastest) must be multiples of 8, W at most 256.  The net is sized for
+ * max_batch frames of max_extent; a batch may hold any number B of frames
+ * of any extent with B times its voxels <= max_batch times the voxels of
+ * max_extent.  All buffers: caller-owned device memory; the net keeps the
+ * last assembled batch until the next one.  Errors: STML_EINVAL (shapes,
+ * null pointers, triples not l < t < r), STML_ESTATE (no batch yet),
+ * STML_EDEVICE. */
 typedef struct stml_net stml_net;
 
 int stml_net_param_count(int dim);
@@ -288,22 +292,22 @@ void stml_net_destroy(stml_net* net);
 int stml_net_set_params(stml_net* net, const float* params_dev);
 int stml_net_get_params(const stml_net* net, float* params_dev);
 /* A batch from planar float32 channels x [batch][channels][extent] and,
- * optionally, the target correction [batch][extent][2]. */
+ * optionally, the target correction [batch][extent][D]. */
 int stml_net_set_input(stml_net* net, const float* x_dev, int channels,
                        const float* target_dev, int batch, const int* extent);
 /* A batch of frames (triples[3b] = t, l, r with 0 <= l < t < r < n_frames)
- * from level images [n_frames][extent] and displacements
- * [n_frames][2][extent]; with_target: the target correction
+ * from level frames [n_frames][extent] and displacements
+ * [n_frames][D][extent]; with_target: the target correction
  * (u_t - linear interpolation) / h from the same field. */
 int stml_net_assemble(stml_net* net, const float* frames_dev,
                       const float* u_dev, int n_frames, const int* extent,
                       double h, const int* triples, int batch,
                       int with_target);
 /* Forward pass; out_dev (may be NULL) receives [batch][extent][32] floats
- * whose first 2 channels are the correction. */
+ * whose first D channels are the correction. */
 int stml_net_forward(stml_net* net, float* out_dev);
 /* u_t = linear interpolation + h * correction into u_dev
- * [n_frames][2][extent] (n_frames and extent as last assembled) for the
+ * [n_frames][D][extent] (n_frames and extent as last assembled) for the
  * frames of the last assembled batch (after stml_net_forward). */
 int stml_net_emit(stml_net* net, double h, float* u_dev);
 /* Mean squared error of the correction and its gradient wrt the
@@ -319,7 +323,8 @@ int stml_net_train_step(stml_net* net, double lr, double* loss);
  * K_{q+1} and the one with the lower objective is kept (a tie keeps the
  * paper's); the log of the following registration records the choice.
  * The context must have been created with opts.predictor = 1 (ESTATE
- * otherwise); the net runs on its own stream and must outlive its use. */
+ * otherwise) and have the net's dimension (EINVAL otherwise); the net runs
+ * on its own stream and must outlive its use. */
 int stml_set_predictor_net(stml_ctx* ctx, stml_net* net);
 
 /* --- batching: several sequences in shared launches ----------------------
