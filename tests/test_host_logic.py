@@ -1,0 +1,108 @@
+"""Host-side logic that needs no GPU: prediction triples, parameter files,
+the layer table shared by the library binding and the oracle, the HBM
+traffic reduction of the counter runs, and the benchmark's unit count."""
+
+import csv
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import cnn
+from paper_2001_06613_amd import learned, pmc_traffic
+
+
+@pytest.mark.parametrize("n,T", [(17, 3), (33, 3), (64, 3), (9, 2), (40, 4)])
+def test_prediction_triples_are_the_nearest_registered_neighbours(n, T):
+    K = [list(k) for k in oracle.temporal_sets(n, T)]
+    tri = learned.prediction_triples(K)
+    seen = set()
+    for q in range(T - 1):
+        new = sorted(set(K[q + 1]) - set(K[q]))
+        for t in new:
+            lo = max(k for k in K[q] if k < t)
+            hi = min(k for k in K[q] if k > t)
+            assert (t, lo, hi) in tri
+            seen.add((t, lo, hi))
+    # nothing else, and every triple is ordered
+    assert set(tri) == seen
+    assert all(l < t < r for t, l, r in tri)
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_layer_tables_agree(dim):
+    lib = [(ci, co, k) for ci, co, k in learned.layers(dim)]
+    ref = [(ci, co, k) for _, ci, co, k in cnn.layers(dim)]
+    assert lib == ref
+    assert learned.init_params(0, dim=dim).size == cnn.param_count(dim)
+
+
+def test_parameter_files_round_trip(tmp_path):
+    p2 = learned.init_params(1, dim=2)
+    f = str(tmp_path / "p.npy")
+    learned.save_params(f, p2)
+    np.testing.assert_array_equal(learned.load_params(f), p2)
+    # .npz: weights rounded to bfloat16 (what the kernels use), biases kept
+    p3 = learned.init_params(2, dim=3)
+    p3[-3:] = 0.123456789
+    g = str(tmp_path / "p.npz")
+    learned.save_params(g, p3, dim=3)
+    q3 = learned.load_params(g)
+    o = 0
+    for ci, co, k in learned.layers(3):
+        nw = k ** 3 * co * ci
+        np.testing.assert_array_equal(q3[o:o + nw],
+                                      cnn.to_bf16(p3[o:o + nw]).astype(
+                                          np.float32))
+        np.testing.assert_array_equal(q3[o + nw:o + nw + co],
+                                      p3[o + nw:o + nw + co])
+        o += nw + co
+    assert o == p3.size
+
+
+def _counter_csv(path, rows):
+    fields = ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"]
+    os.makedirs(path, exist_ok=True)
+    with open(os.path.join(path, "run_counter_collection.csv"), "w",
+              newline="") as fh:
+        w = csv.DictWriter(fh, fieldnames=fields)
+        w.writeheader()
+        for r in rows:
+            w.writerow(dict(zip(fields, r)))
+
+
+def test_traffic_record_scales_by_the_copy(tmp_path):
+    kib = pmc_traffic.COPY_BYTES / 1024.0
+    name = "void stml::cgv_update_kernel<2, true>(int, ...)"
+    small = "void stml::cgv_update_kernel<2, false>(int, ...)"
+    # FETCH_SIZE reads half the copy's bytes per copied byte (scale 2);
+    # two counter rows of one dispatch add up
+    _counter_csv(tmp_path / "f", [
+        (1, name, "FETCH_SIZE", 300.0), (1, name, "FETCH_SIZE", 100.0),
+        (2, small, "FETCH_SIZE", 200.0),
+        (3, "__amd_rocclr_copyBuffer", "FETCH_SIZE", kib / 2),
+        (4, "void stml::other_kernel()", "FETCH_SIZE", 1e9)])
+    _counter_csv(tmp_path / "w", [
+        (1, name, "WRITE_SIZE", 50.0), (2, small, "WRITE_SIZE", 150.0),
+        (3, "__amd_rocclr_copyBuffer", "WRITE_SIZE", kib),
+        (4, "void stml::other_kernel()", "WRITE_SIZE", 7.0)])
+    rec = pmc_traffic.summarise(str(tmp_path / "f"), str(tmp_path / "w"))
+    assert rec["launches"] == 2
+    assert rec["fetch_scale"] == pytest.approx(2.0)
+    assert rec["write_scale"] == pytest.approx(1.0)
+    # mean fetch (400 + 200) / 2 KiB x 2, mean write (50 + 150) / 2 KiB
+    assert rec["hbm_bytes_per_launch"] == pytest.approx(
+        (300.0 * 2.0 + 100.0) * 1024.0)
+    assert rec["source_sha256"] == pmc_traffic.source_sha()
+
+
+def test_bench_units_count_every_evaluation_and_product():
+    import bench
+
+    logs = [{"level": 0, "nK": 3, "cg": [2, 1]},
+            {"level": 1, "nK": 5, "cg": [4]}]
+    extents = [(4, 8), (8, 16)]
+    # per GN iteration: one evaluation and cg products over nK N voxels
+    expect = 3 * 32 * (3 + 2) + 5 * 128 * 5
+    assert bench._units(logs, extents) == expect
