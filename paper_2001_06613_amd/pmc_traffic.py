@@ -12,8 +12,8 @@ COPY_BYTES bytes (read once, written once).  The counters report KiB per
 dispatch; each is scaled by what it reads for the copy (bytes known), so
 the result is HBM bytes per launch of the kernel, averaged over its
 launches like the benchmark's achieved bandwidth.  The record carries the
-SHA-256 of the kernel's source files: the benchmark reports it only while
-they are unchanged.
+SHA-256 of the kernel's source code (comments and spacing removed): the
+benchmark reports it only while that code is unchanged.
 """
 
 import csv
@@ -21,6 +21,7 @@ import glob
 import hashlib
 import json
 import os
+import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -59,11 +60,19 @@ def _mean(vals):
     return sum(vals) / len(vals) if vals else float("nan")
 
 
+def _code(text):
+    """Source text without comments and blank space: the hash follows the
+    code, not its commentary."""
+    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+    text = re.sub(r"//[^\n]*", " ", text)
+    return " ".join(text.split())
+
+
 def source_sha():
     h = hashlib.sha256()
     for path in SOURCES:
-        with open(path, "rb") as fh:
-            h.update(fh.read())
+        with open(path, encoding="utf-8") as fh:
+            h.update(_code(fh.read()).encode())
     return h.hexdigest()
 
 
