@@ -451,9 +451,10 @@ __global__ __launch_bounds__(kHv2Threads, REG ? 8 : 5) void cgt_hvp2_kernel(
 
 // 3-D Hessian product on p = z + beta p_old (it > 0) or p = z for one
 // column of a group of frames: a 16 x 16 tile in (x, y) marched through
-// kZ3 planes in z.  For each frame the block keeps a ring of five planes of
+// kT3Z planes in z.  For each frame the block keeps a ring of five planes of
 // p (2-cell halo, float32: exactly the values the kernel stores) and three
-// planes of L p (1-cell halo, float64) in LDS; every step stages one new
+// planes of L p (1-cell halo; formed in float64 and kept as float32, which
+// lets four blocks share a compute unit) in LDS; every step stages one new
 // plane of p (its loads issued one step ahead, into registers), forms one
 // plane of L p and finishes one plane of q = H p.  The halo overhead per
 // step is that of a 2-D tile (20 x 20 loads for 16 x 16 outputs) instead of
@@ -476,7 +477,7 @@ __device__ __forceinline__ void cgt_hvp3_body(
   constexpr int kPS = (HX * HY + NT - 1) / NT;  // p points per thread
   constexpr int kLS = (LX * LY + NT - 1) / NT;  // L points per thread
   __shared__ float P[D][5][HY][HX];
-  __shared__ double L[REG ? D : 1][REG ? 3 : 1][REG ? LY : 1][REG ? LX : 1];
+  __shared__ float L[REG ? D : 1][REG ? 3 : 1][REG ? LY : 1][REG ? LX : 1];
   if (sc->done || gn_it >= sc->gn_stop) return;
   double beta = 0.0;
   if (it > 0) {
@@ -673,8 +674,10 @@ __device__ __forceinline__ void cgt_hvp3_body(
   block_partials<1>(vals, 0u, part, blk);
 }
 
+// Four blocks per compute unit (at most 128 registers per lane; the LDS
+// rings take 40 KB).
 template <int REG>
-__global__ __launch_bounds__(kHv3Threads) void cgt_hvp3_kernel(
+__global__ __launch_bounds__(kHv3Threads, 4) void cgt_hvp3_kernel(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
     Model md, float* __restrict__ q, const double* __restrict__ Sz,
@@ -817,7 +820,7 @@ __global__ __launch_bounds__(1024) void cg_init_batch_kernel(JobSet js) {
 
 template <int D, int REG>
 __global__ __launch_bounds__(D == 2 ? kHv2Threads : kHv3Threads,
-                             D == 3 ? 1 : (REG ? 8 : 5)) void cg_hvp_batch_kernel(
+                             D == 3 ? 4 : (REG ? 8 : 5)) void cg_hvp_batch_kernel(
     JobSet js, int it, int fixed, double rtol) {
   Blk blk;
   const Job& J = cg_job_of(js, kClsHv, blk);

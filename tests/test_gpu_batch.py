@@ -95,7 +95,7 @@ def test_batched_sequence_matches_oracle():
     assert np.abs(u - ost.Y[1]).max() <= 1e-3
 
 
-# 3-D: (frames, extent, seed), ragged against the 16 x 4 x 4 tiles
+# 3-D: (frames, extent, seed), ragged against the 16 x 16 x 16 columns
 CASES3 = [(5, (10, 12, 18), 0), (6, (12, 16, 20), 1), (4, (8, 8, 24), 2)]
 
 

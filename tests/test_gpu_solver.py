@@ -256,7 +256,7 @@ def _volume(n, ext, seed):
 
 @pytest.mark.parametrize("reg", ["diffusion", "curvature"])
 def test_gn_direction_parity_3d(reg):
-    ext = (10, 12, 18)             # ragged against 16 x 4 x 4 tiles
+    ext = (10, 12, 18)             # ragged against 16 x 16 x 16 columns
     n = 4
     frames = _volume(n, ext, 21)
     o = default_opts(dim=3, n_spatial=1, n_temporal=2, reg=reg, cg_max=8,

@@ -1,5 +1,6 @@
 """Host-side logic that needs no GPU: prediction triples, parameter files,
-the layer table shared by the library binding and the oracle, the HBM
+the layer table shared by the library binding and the oracle, the count of
+iterations at equal objective in the predictor comparison, the HBM
 traffic reduction of the counter runs, and the benchmark's unit count."""
 
 import csv
@@ -106,3 +107,33 @@ def test_bench_units_count_every_evaluation_and_product():
     # per GN iteration: one evaluation and cg products over nK N voxels
     expect = 3 * 32 * (3 + 2) + 5 * 128 * 5
     assert bench._units(logs, extents) == expect
+
+
+def _log(level, q, J0, Js):
+    return {"level": level, "q": q, "gn": len(Js), "J0": J0,
+            "J_iter": list(Js), "J": Js[-1] if Js else J0, "predictor": 0}
+
+
+def test_iterations_at_equal_objective():
+    plain = [_log(0, 0, 9.0, [8.0]),            # initial stage: not counted
+             _log(0, 1, 10.0, [6.0, 5.0, 4.0]),
+             _log(1, 1, 7.0, [3.0, 2.5]),
+             _log(1, 2, 5.0, [1.0])]
+    learnt = [_log(0, 0, 9.0, [8.0]),
+              _log(0, 1, 5.5, [4.5, 3.9, 3.8]),   # 4.0 reached after 2
+              _log(1, 1, 2.5, [2.4]),             # already there: 0
+              _log(1, 2, 4.0, [2.0, 1.5])]        # never reaches 1.0
+    got = learned.gn_to_reach(learnt, plain)
+    assert got == [((0, 1, 0), 3, 2), ((1, 1, 0), 2, 0), ((1, 2, 0), 1, None)]
+    rows = [{"seed": 0,
+             "plain": {"logs": plain, "corrector_gn": 6, "wall_s": 1.0,
+                       "J_final": 1.0, "learned_picks": 0,
+                       "prediction_steps": 0},
+             "learned": {"logs": learnt, "corrector_gn": 6, "wall_s": 1.0,
+                         "J_final": 1.5, "learned_picks": 1,
+                         "prediction_steps": 3}}]
+    s = learned.summarise(rows)
+    assert s["corrector_gn_plain_matched"] == 6
+    # 2 + 0 + all 2 of the stage that falls short
+    assert s["corrector_gn_to_plain_J"] == 4
+    assert s["stages_short_of_plain_J"] == 1
