@@ -368,7 +368,10 @@ struct Steps {
 // data term per voxel is sum (W - c)^2 - (sum (W - c))^2 / |K| with c the
 // voxel's value in the first frame of K (a shift against cancellation);
 // S and P are quadratic in t and are expanded exactly.  The per-step sums
-// live in LDS (one slot row per thread), which keeps register use low.
+// live in LDS (one slot row per thread), which keeps register use low.  A
+// frame's loads (u, delta, g and both stencils) issue together, and in 2-D
+// the gathers of three steps at a time, so that an image frame costs three
+// dependent memory round trips instead of nine.
 template <int D, int REG>
 __device__ __forceinline__ void trial_body(
     const float* __restrict__ T, const float* __restrict__ u,
@@ -411,27 +414,39 @@ __device__ __forceinline__ void trial_body(
         dv[a] = (double)dl[o];
         my[2 * NT + a] += uv[a];
         my[2 * NT + D + a] += dv[a];
-        if (valid) {
-          slope += (double)gr[o] * dv[a];
-          mx = fmax(mx, fabs(dv[a]));
-          sq += dv[a] * dv[a];
-          double uu, uw, ww;
-          reg_cross<D, REG>(u + ((size_t)k * D + a) * N,
-                            dl + ((size_t)j * D + a) * N, p, g, uu, uw, ww);
-          rA += uu;
-          rB += uw;
-          rC += ww;
-        }
+        // every lane loads (a lane past the end at the clamped last voxel),
+        // so that the loads issue together; only valid lanes count
+        const double gv = (double)gr[o];
+        double uu, uw, ww;
+        reg_cross<D, REG>(u + ((size_t)k * D + a) * N,
+                          dl + ((size_t)j * D + a) * N, p, g, uu, uw, ww);
+        slope = valid ? slope + gv * dv[a] : slope;
+        mx = valid ? fmax(mx, fabs(dv[a])) : mx;
+        sq = valid ? sq + dv[a] * dv[a] : sq;
+        rA = valid ? rA + uu : rA;
+        rB = valid ? rB + uw : rB;
+        rC = valid ? rC + ww : rC;
       }
       const float* Tk = T + (size_t)k * N;
+      constexpr int TG = D == 2 ? 3 : 1;   // steps whose loads issue together
 #pragma unroll 1
-      for (int s = 0; s < NT; ++s) {
-        double ut[D];
+      for (int s0 = 0; s0 < NT; s0 += TG) {
+        double wvs[TG];
 #pragma unroll
-        for (int a = 0; a < D; ++a) ut[a] = uv[a] + st.t[s] * dv[a];
-        double wv = warp_value<D>(Tk, g, p, ut) - c;
-        my[s] += wv;
-        my[NT + s] += wv * wv;
+        for (int kk = 0; kk < TG; ++kk) {
+          const int s = s0 + kk < NT ? s0 + kk : NT - 1;
+          double ut[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a) ut[a] = uv[a] + st.t[s] * dv[a];
+          wvs[kk] = warp_value<D>(Tk, g, p, ut) - c;
+        }
+#pragma unroll
+        for (int kk = 0; kk < TG; ++kk) {
+          if (s0 + kk < NT) {
+            my[s0 + kk] += wvs[kk];
+            my[NT + s0 + kk] += wvs[kk] * wvs[kk];
+          }
+        }
       }
     }
     __syncthreads();

@@ -230,6 +230,9 @@ __device__ __forceinline__ void reg_terms(const F& f, const Pos<D>& p,
   float v[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) v[i] = f.ld(p.idx + off[i]);
+  // keep the loads together: interleaved with their uses they would wait
+  // for each other one by one
+  __builtin_amdgcn_sched_barrier(0);
   const double c = (double)v[0];
   centre = c;
   double vm[D], vp[D], Lc = 0.0;
@@ -329,16 +332,11 @@ __device__ __forceinline__ void warp_sample(const float* __restrict__ T,
     double q = (double)p.c[a] + uv[a] * g.inv_h;
     inside[a] = (q >= 0.0) && (q <= (double)(m - 1));
     double qc = fmin(fmax(q, 0.0), (double)(m - 1));
-    if (m >= 2) {
-      int fl = (int)floor(qc);
-      i0[a] = fl < m - 2 ? fl : m - 2;
-      f[a] = qc - (double)i0[a];
-      i1[a] = i0[a] + 1;
-    } else {
-      i0[a] = 0;
-      i1[a] = 0;
-      f[a] = 0.0;
-    }
+    // m = 1: qc = 0 gives i0 = i1 = 0, f = 0
+    int fl = (int)floor(qc);
+    i0[a] = max(min(fl, m - 2), 0);
+    i1[a] = min(i0[a] + 1, m - 1);
+    f[a] = qc - (double)i0[a];
   }
   if (D == 2) {
     unsigned r0 = (unsigned)i0[0] * (unsigned)g.s[0];
