@@ -142,8 +142,10 @@ __global__ __launch_bounds__(1024) void cgv_init_kernel(
 }
 
 // CG step, part 2: a = rz / p.q (stop on p.q <= 0); x += a p (x = a p at
-// it = 0), r -= a q, z = M^-1 r; per-voxel S_z, V_z; partials r.z, r.r.
-template <int D>
+// it = 0: FIRST), r -= a q, z = M^-1 r; per-voxel S_z, V_z; partials r.z,
+// r.r.  A frame's loads (both components) issue before its stores, which
+// would otherwise hold the next component's loads back.
+template <int D, bool FIRST>
 __device__ __forceinline__ void cgv_update_body(
     int it, const float* __restrict__ p, const float* __restrict__ q,
     const float* __restrict__ dW, const Geom& g, const Model& md,
@@ -188,14 +190,24 @@ __device__ __forceinline__ void cgv_update_body(
 #pragma unroll 1
       for (int j = j0; j < j1; ++j) {
         const size_t base = (size_t)j * D * N + pos.idx;
+        float pf[D], df[D], xf[D], rf[D], qf[D];
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const size_t o = base + (size_t)a * N;
+          pf[a] = p[o];
+          df[a] = dW[o];
+          xf[a] = FIRST ? 0.f : x[o];
+          rf[a] = r[o];
+          qf[a] = q[o];
+        }
 #pragma unroll
         for (int a = 0; a < D; ++a) {
           size_t o = base + (size_t)a * N;
-          double pe = (double)p[o];
-          double d = (double)dW[o];
-          float xn = it == 0 ? (float)(alpha * pe)
-                             : (float)((double)x[o] + alpha * pe);
-          float rv = (float)((double)r[o] - alpha * (double)q[o]);
+          double pe = (double)pf[a];
+          double d = (double)df[a];
+          float xn = FIRST ? (float)(alpha * pe)
+                           : (float)((double)xf[a] + alpha * pe);
+          float rv = (float)((double)rf[a] - alpha * (double)qf[a]);
           float zv = (float)((double)rv / (md.mdiag_c * d * d + rest));
           x[o] = xn;
           r[o] = rv;
@@ -217,15 +229,15 @@ __device__ __forceinline__ void cgv_update_body(
 // while one block combines its per-voxel sums the other streams; for grids
 // with more blocks than compute units.  Small grids (latency-bound levels)
 // run faster with the registers unconstrained.  Same arithmetic either way.
-template <int D, bool OCC>
+template <int D, bool OCC, bool FIRST>
 __global__ __launch_bounds__(1024, OCC ? 8 : 1) void cgv_update_kernel(
     int it, const float* __restrict__ p, const float* __restrict__ q,
     const float* __restrict__ dW, Geom g, Model md, float* __restrict__ x,
     float* __restrict__ r, float* __restrict__ z, double* __restrict__ Sz,
     double* __restrict__ Vz, const double* __restrict__ hv_part, int hv_nb,
     double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
-  cgv_update_body<D>(it, p, q, dW, g, md, x, r, z, Sz, Vz, hv_part, hv_nb,
-                     part, sc, gn_it, grid_blk());
+  cgv_update_body<D, FIRST>(it, p, q, dW, g, md, x, r, z, Sz, Vz, hv_part,
+                            hv_nb, part, sc, gn_it, grid_blk());
 }
 
 // Per-voxel S and V of a stored field v (Hessian product test entry).
@@ -261,11 +273,12 @@ __global__ __launch_bounds__(1024) void cgv_sums_kernel(
   }
 }
 
-// Hessian product on p = z + beta p_old (it > 0) or p = z (it = 0) for one
+// Hessian product on p = z + beta p_old (it > 0) or p = z (it = 0: FIRST,
+// a form of its own, so that no load waits behind a branch on it) for one
 // 64 x 4 tile of a group of frames; stores p and q = H p, partial p.q.
 // For it > 0 it first finishes the previous update: beta and the
 // convergence test from the update's partials.
-template <int REG>
+template <int REG, bool FIRST>
 __device__ __forceinline__ void cgt_hvp2_body(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, const Geom& g,
@@ -280,7 +293,7 @@ __device__ __forceinline__ void cgt_hvp2_body(
   __shared__ double L[REG ? D : 1][REG ? kLY : 1][REG ? kLX : 1];
   if (sc->done || gn_it >= sc->gn_stop) return;
   double beta = 0.0;
-  if (it > 0) {
+  if (!FIRST) {
     double t[2];
     reduce_partials<2>(up_part, up_nb, 0u, t);
     const double rz_old = sc->rzh[(it - 1) & 1];
@@ -314,7 +327,7 @@ __device__ __forceinline__ void cgt_hvp2_body(
     double sbar = 0.0, vbar[D] = {0.0, 0.0};
     if (valid) {
       double S = Sz[vox], V0 = Vz[vox], V1 = Vz[N + vox];
-      if (it > 0) {
+      if (!FIRST) {
         S += beta * Sp_old[vox];
         V0 += beta * Vp_old[vox];
         V1 += beta * Vp_old[N + vox];
@@ -352,7 +365,7 @@ __device__ __forceinline__ void cgt_hvp2_body(
           for (int a = 0; a < D; ++a) {
             const size_t plane = ((size_t)j * D + a) * N;
             sz[s][a] = zv[plane + so[s]];
-            sp[s][a] = it > 0 ? p_old[plane + so[s]] : 0.f;
+            sp[s][a] = !FIRST ? p_old[plane + so[s]] : 0.f;
           }
         }
       }
@@ -366,7 +379,7 @@ __device__ __forceinline__ void cgt_hvp2_body(
           const int hy = i / kHX, hx = i - (i / kHX) * kHX;
 #pragma unroll
           for (int a = 0; a < D; ++a)
-            P[a][hy][hx] = (double)(it > 0 ? __builtin_fmaf(bf, sp[s][a],
+            P[a][hy][hx] = (double)(!FIRST ? __builtin_fmaf(bf, sp[s][a],
                                                             sz[s][a])
                                            : sz[s][a]);
         }
@@ -434,7 +447,7 @@ __device__ __forceinline__ void cgt_hvp2_body(
 
 // Eight blocks per compute unit (at most 64 registers per lane) keep enough
 // tile loads in flight (the diffusion form needs more registers: five).
-template <int REG>
+template <int REG, bool FIRST>
 __global__ __launch_bounds__(kHv2Threads, REG ? 8 : 5) void cgt_hvp2_kernel(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
@@ -444,7 +457,7 @@ __global__ __launch_bounds__(kHv2Threads, REG ? 8 : 5) void cgt_hvp2_kernel(
     double* __restrict__ Vp_new, int nreal, int nfg, int fpg,
     const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
     double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
-  cgt_hvp2_body<REG>(it, zv, p_old, p_new, dW, g, md, q, Sz, Vz, Sp_old,
+  cgt_hvp2_body<REG, FIRST>(it, zv, p_old, p_new, dW, g, md, q, Sz, Vz, Sp_old,
                      Vp_old, Sp_new, Vp_new, nreal, nfg, fpg, up_part, up_nb,
                      fixed, rtol, part, sc, gn_it, grid_blk());
 }
@@ -460,7 +473,7 @@ __global__ __launch_bounds__(kHv2Threads, REG ? 8 : 5) void cgt_hvp2_kernel(
 // step is that of a 2-D tile (20 x 20 loads for 16 x 16 outputs) instead of
 // a 3-D one.  Voxel sums S, V and the CG scalars as in 2-D; the per-voxel
 // sums are read per frame (they stay in the L2 across the block's frames).
-template <int REG>
+template <int REG, bool FIRST>
 __device__ __forceinline__ void cgt_hvp3_body(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, const Geom& g,
@@ -480,7 +493,7 @@ __device__ __forceinline__ void cgt_hvp3_body(
   __shared__ float L[REG ? D : 1][REG ? 3 : 1][REG ? LY : 1][REG ? LX : 1];
   if (sc->done || gn_it >= sc->gn_stop) return;
   double beta = 0.0;
-  if (it > 0) {
+  if (!FIRST) {
     double t[2];
     reduce_partials<2>(up_part, up_nb, 0u, t);
     const double rz_old = sc->rzh[(it - 1) & 1];
@@ -541,7 +554,7 @@ __device__ __forceinline__ void cgt_hvp3_body(
             const size_t o =
                 ((size_t)j * D + a) * N + (size_t)gz * plane_n + po[s];
             rz[s][a] = zv[o];
-            rp[s][a] = it > 0 ? p_old[o] : 0.f;
+            rp[s][a] = !FIRST ? p_old[o] : 0.f;
           }
         }
       }
@@ -555,7 +568,7 @@ __device__ __forceinline__ void cgt_hvp3_body(
 #pragma unroll
           for (int a = 0; a < D; ++a)
             P[a][slot][hy][hx] =
-                it > 0 ? __builtin_fmaf(bf, rp[s][a], rz[s][a]) : rz[s][a];
+                !FIRST ? __builtin_fmaf(bf, rp[s][a], rz[s][a]) : rz[s][a];
         }
       }
     };
@@ -607,7 +620,7 @@ __device__ __forceinline__ void cgt_hvp3_body(
           double S = Sz[vox], V[D];
 #pragma unroll
           for (int a = 0; a < D; ++a) V[a] = Vz[(size_t)a * N + vox];
-          if (it > 0) {
+          if (!FIRST) {
             S += beta * Sp_old[vox];
 #pragma unroll
             for (int a = 0; a < D; ++a)
@@ -676,7 +689,7 @@ __device__ __forceinline__ void cgt_hvp3_body(
 
 // Four blocks per compute unit (at most 128 registers per lane; the LDS
 // rings take 40 KB).
-template <int REG>
+template <int REG, bool FIRST>
 __global__ __launch_bounds__(kHv3Threads, 4) void cgt_hvp3_kernel(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
@@ -686,7 +699,7 @@ __global__ __launch_bounds__(kHv3Threads, 4) void cgt_hvp3_kernel(
     double* __restrict__ Vp_new, int nreal, int nfg, int fpg,
     const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
     double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
-  cgt_hvp3_body<REG>(it, zv, p_old, p_new, dW, g, md, q, Sz, Vz, Sp_old,
+  cgt_hvp3_body<REG, FIRST>(it, zv, p_old, p_new, dW, g, md, q, Sz, Vz, Sp_old,
                      Vp_old, Sp_new, Vp_new, nreal, nfg, fpg, up_part, up_nb,
                      fixed, rtol, part, sc, gn_it, grid_blk());
 }
@@ -755,8 +768,17 @@ hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
   double* Sp_new = sums.Sp[it & 1];
   double* Vp_new = sums.Vp[it & 1];
   // with events: the dispatch records its own start and end
-  auto kern = dim == 2 ? (md.reg == 0 ? cgt_hvp2_kernel<0> : cgt_hvp2_kernel<1>)
-                       : (md.reg == 0 ? cgt_hvp3_kernel<0> : cgt_hvp3_kernel<1>);
+  decltype(&cgt_hvp2_kernel<0, true>) kern;
+  if (it == 0)
+    kern = dim == 2 ? (md.reg == 0 ? cgt_hvp2_kernel<0, true>
+                                   : cgt_hvp2_kernel<1, true>)
+                    : (md.reg == 0 ? cgt_hvp3_kernel<0, true>
+                                   : cgt_hvp3_kernel<1, true>);
+  else
+    kern = dim == 2 ? (md.reg == 0 ? cgt_hvp2_kernel<0, false>
+                                   : cgt_hvp2_kernel<1, false>)
+                    : (md.reg == 0 ? cgt_hvp3_kernel<0, false>
+                                   : cgt_hvp3_kernel<1, false>);
   hipExtLaunchKernelGGL(kern, dim3(t.grid),
                         dim3(dim == 2 ? kHv2Threads : kHv3Threads), 0, s, ev0,
                         ev1, 0, it, z, p_old, p_new, dW, g, md, q, sums.Sz,
@@ -773,11 +795,18 @@ hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
                              hipEvent_t ev0, hipEvent_t ev1) {
   int nb = cgv_blocks(g), nt = cgv_threads(dim, md.nK);
   int hv_nb = cg_tiles(g, md.nK, dim).grid;
-  const bool occ = nb > kCUs;
-  auto kern = dim == 2 ? (occ ? cgv_update_kernel<2, true>
-                              : cgv_update_kernel<2, false>)
-                       : (occ ? cgv_update_kernel<3, true>
-                              : cgv_update_kernel<3, false>);
+  const bool occ = nb > kCUs, first = it == 0;
+  decltype(&cgv_update_kernel<2, true, true>) kern;
+  if (dim == 2)
+    kern = occ ? (first ? cgv_update_kernel<2, true, true>
+                        : cgv_update_kernel<2, true, false>)
+               : (first ? cgv_update_kernel<2, false, true>
+                        : cgv_update_kernel<2, false, false>);
+  else
+    kern = occ ? (first ? cgv_update_kernel<3, true, true>
+                        : cgv_update_kernel<3, true, false>)
+               : (first ? cgv_update_kernel<3, false, true>
+                        : cgv_update_kernel<3, false, false>);
   hipExtLaunchKernelGGL(kern, dim3(nb), dim3(nt), 0, s, ev0, ev1, 0, it, p,
                         q, dW, g, md, x, r, z, sums.Sz, sums.Vz,
                         (const double*)rb.region(kRegHv), hv_nb,
@@ -818,7 +847,7 @@ __global__ __launch_bounds__(1024) void cg_init_batch_kernel(JobSet js) {
                    J.rb.region(kRegInit), sc->gn_cur, sc, blk);
 }
 
-template <int D, int REG>
+template <int D, int REG, bool FIRST>
 __global__ __launch_bounds__(D == 2 ? kHv2Threads : kHv3Threads,
                              D == 3 ? 4 : (REG ? 8 : 5)) void cg_hvp_batch_kernel(
     JobSet js, int it, int fixed, double rtol) {
@@ -830,14 +859,14 @@ __global__ __launch_bounds__(D == 2 ? kHv2Threads : kHv3Threads,
   float* pn = (it & 1) ? J.P1 : J.P0;
   const float* po = (it & 1) ? J.P0 : J.P1;
   if constexpr (D == 2)
-    cgt_hvp2_body<REG>(it, J.z, po, pn, J.dW, g, md, J.q, J.sums.Sz,
+    cgt_hvp2_body<REG, FIRST>(it, J.z, po, pn, J.dW, g, md, J.q, J.sums.Sz,
                        J.sums.Vz, J.sums.Sp[(it + 1) & 1],
                        J.sums.Vp[(it + 1) & 1], J.sums.Sp[it & 1],
                        J.sums.Vp[it & 1], J.ct.nreal, J.ct.nfg, J.ct.fpg,
                        J.rb.region(kRegUpdate), J.nb_vox, fixed, rtol,
                        J.rb.region(kRegHv), sc, sc->gn_cur, blk);
   else
-    cgt_hvp3_body<REG>(it, J.z, po, pn, J.dW, g, md, J.q, J.sums.Sz,
+    cgt_hvp3_body<REG, FIRST>(it, J.z, po, pn, J.dW, g, md, J.q, J.sums.Sz,
                        J.sums.Vz, J.sums.Sp[(it + 1) & 1],
                        J.sums.Vp[(it + 1) & 1], J.sums.Sp[it & 1],
                        J.sums.Vp[it & 1], J.ct.nreal, J.ct.nfg, J.ct.fpg,
@@ -845,7 +874,7 @@ __global__ __launch_bounds__(D == 2 ? kHv2Threads : kHv3Threads,
                        J.rb.region(kRegHv), sc, sc->gn_cur, blk);
 }
 
-template <int D>
+template <int D, bool FIRST>
 __global__ __launch_bounds__(1024, 8) void cg_update_batch_kernel(JobSet js,
                                                                int it) {
   Blk blk;
@@ -854,9 +883,10 @@ __global__ __launch_bounds__(1024, 8) void cg_update_batch_kernel(JobSet js,
   const Model md = J.md;
   Scal* sc = J.sc;
   const float* pn = (it & 1) ? J.P1 : J.P0;
-  cgv_update_body<D>(it, pn, J.q, J.dW, g, md, J.x, J.r, J.z, J.sums.Sz,
-                     J.sums.Vz, J.rb.region(kRegHv), J.ct.grid,
-                     J.rb.region(kRegUpdate), sc, sc->gn_cur, blk);
+  cgv_update_body<D, FIRST>(it, pn, J.q, J.dW, g, md, J.x, J.r, J.z,
+                            J.sums.Sz, J.sums.Vz, J.rb.region(kRegHv),
+                            J.ct.grid, J.rb.region(kRegUpdate), sc,
+                            sc->gn_cur, blk);
 }
 
 void job_shape(Job* job) {
@@ -882,11 +912,17 @@ hipError_t batch_cg_init(const JobSet& js, int nvox, int dim, hipStream_t s) {
 
 hipError_t batch_cg_hvp(const JobSet& js, int nhv, int dim, int reg, int it,
                         int fixed, double rtol, hipStream_t s) {
-  auto kern = dim == 2
-                  ? (reg == 0 ? cg_hvp_batch_kernel<2, 0>
-                              : cg_hvp_batch_kernel<2, 1>)
-                  : (reg == 0 ? cg_hvp_batch_kernel<3, 0>
-                              : cg_hvp_batch_kernel<3, 1>);
+  decltype(&cg_hvp_batch_kernel<2, 0, true>) kern;
+  if (it == 0)
+    kern = dim == 2 ? (reg == 0 ? cg_hvp_batch_kernel<2, 0, true>
+                                : cg_hvp_batch_kernel<2, 1, true>)
+                    : (reg == 0 ? cg_hvp_batch_kernel<3, 0, true>
+                                : cg_hvp_batch_kernel<3, 1, true>);
+  else
+    kern = dim == 2 ? (reg == 0 ? cg_hvp_batch_kernel<2, 0, false>
+                                : cg_hvp_batch_kernel<2, 1, false>)
+                    : (reg == 0 ? cg_hvp_batch_kernel<3, 0, false>
+                                : cg_hvp_batch_kernel<3, 1, false>);
   kern<<<nhv, dim == 2 ? kHv2Threads : kHv3Threads, 0, s>>>(js, it, fixed,
                                                             rtol);
   return hipGetLastError();
@@ -894,10 +930,11 @@ hipError_t batch_cg_hvp(const JobSet& js, int nhv, int dim, int reg, int it,
 
 hipError_t batch_cg_update(const JobSet& js, int nvox, int dim, int it,
                            hipStream_t s) {
-  if (dim == 2)
-    cg_update_batch_kernel<2><<<nvox, cgv_threads(2, 0), 0, s>>>(js, it);
-  else
-    cg_update_batch_kernel<3><<<nvox, cgv_threads(3, 0), 0, s>>>(js, it);
+  auto kern = dim == 2 ? (it == 0 ? cg_update_batch_kernel<2, true>
+                                   : cg_update_batch_kernel<2, false>)
+                       : (it == 0 ? cg_update_batch_kernel<3, true>
+                                   : cg_update_batch_kernel<3, false>);
+  kern<<<nvox, cgv_threads(dim, 0), 0, s>>>(js, it);
   return hipGetLastError();
 }
 

@@ -25,7 +25,7 @@ import re
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL = "cgv_update_kernel<2,"    # both launch-bound forms match
+KERNEL = "cgv_update_kernel<2,"    # every form (launch bound, first step) matches
 LABEL = "cgv_update_kernel<2, *>"
 # every source the kernel is built from
 SOURCES = [os.path.join(HERE, "csrc", f) for f in
