@@ -3,9 +3,10 @@
 // Tile kernels (evaluation, trial steps) give every block one or more
 // 64-voxel tiles; the waves of a block split the frames of the subset K
 // between them, so each voxel's cross-frame means (mean warped image, mean
-// displacement) are combined through LDS; the evaluation's second sweep
-// re-reads its frames from the caches.  All warp and residual arithmetic is
-// float64 from float32 loads; every reduction is float64 and deterministic.
+// displacement) are combined through LDS; the evaluation keeps W and dW/du
+// of a wave's first frames in LDS for its second sweep.  All warp and residual
+// arithmetic is float64 from float32 loads; every reduction is float64 and
+// deterministic.
 #include <math.h>
 
 #include "launch.h"
@@ -226,9 +227,11 @@ __device__ __forceinline__ Chunk frame_chunk(int nK) {
 
 // Objective (D, S, P), gradient and dW/du at u for the frames K.
 // Sweep 1 over the wave's frames warps every frame, stores dW/du and sums
-// W and u per voxel; after the LDS combine, sweep 2 warps again (the loads
-// hit the caches), forms r = W - mean W and writes the gradient.  Block
-// partials of D, S, P go to `part` (3 x gridDim slots).
+// W and u per voxel; after the LDS combine, sweep 2 forms r = W - mean W and
+// writes the gradient, taking W and dW/du of a wave's first frames from LDS
+// and warping the rest again.  The gradient uses dW/du rounded to float32,
+// the values the Hessian product uses.  Block partials of D, S, P go to
+// `part` (3 x gridDim slots).
 template <int D, int REG>
 __device__ __forceinline__ void eval_body(
     const float* __restrict__ T, const float* __restrict__ u,
@@ -237,7 +240,14 @@ __device__ __forceinline__ void eval_body(
     double* __restrict__ part, int gn_it, const Scal* __restrict__ sc,
     Blk blk) {
   if (sc && gn_it >= sc->gn_stop) return;
-  __shared__ double xs[kMaxChunks][kWave][1 + D];
+  constexpr int G_ = D == 2 ? 8 : 4;   // waves per block (eval_threads)
+  // W and dW/du (rounded to float32, as stored) of a wave's first kWF frames
+  // stay in LDS between the sweeps: the second sweep needs neither the
+  // displacement nor the frame again for them
+  constexpr int kWF = 8;
+  __shared__ double xs[G_][kWave][1 + D];
+  __shared__ double wc[G_][kWF][kWave];
+  __shared__ float dc[G_][kWF][D][kWave];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = wave_id();
   const int G = blockDim.x / kWave;
@@ -262,6 +272,11 @@ __device__ __forceinline__ void eval_body(
       for (int a = 0; a < D; ++a) uv[a] = (double)uk[(size_t)a * N + p.idx];
       warp_sample<D>(T + (size_t)k * N, g, p, uv, W, dw);
       sW += W;
+      if (j - ch.j0 < kWF) {
+        wc[w][j - ch.j0][lane] = W;
+#pragma unroll
+        for (int a = 0; a < D; ++a) dc[w][j - ch.j0][a][lane] = (float)dw[a];
+      }
       float* dj = dWo ? dWo + (size_t)j * D * N : nullptr;
 #pragma unroll
       for (int a = 0; a < D; ++a) {
@@ -289,10 +304,20 @@ __device__ __forceinline__ void eval_body(
       for (int j = ch.j0; j < ch.j1; ++j) {
         int k = K[j];
         const float* uk = u + (size_t)k * D * N;
-        double uv[D], dw[D], W;
+        double dw[D], W;
+        if (j - ch.j0 < kWF) {
+          W = wc[w][j - ch.j0][lane];
 #pragma unroll
-        for (int a = 0; a < D; ++a) uv[a] = (double)uk[(size_t)a * N + p.idx];
-        warp_sample<D>(T + (size_t)k * N, g, p, uv, W, dw);
+          for (int a = 0; a < D; ++a) dw[a] = (double)dc[w][j - ch.j0][a][lane];
+        } else {
+          double uv[D];
+#pragma unroll
+          for (int a = 0; a < D; ++a)
+            uv[a] = (double)uk[(size_t)a * N + p.idx];
+          warp_sample<D>(T + (size_t)k * N, g, p, uv, W, dw);
+#pragma unroll
+          for (int a = 0; a < D; ++a) dw[a] = (double)(float)dw[a];
+        }
         double r = W - Wb;
         accD += r * r;
         float* gj = grad ? grad + (size_t)j * D * N : nullptr;
