@@ -462,6 +462,54 @@ __global__ __launch_bounds__(kHv2Threads, REG ? 8 : 5) void cgt_hvp2_kernel(
                      fixed, rtol, part, sc, gn_it, grid_blk());
 }
 
+// CG step, part 0 for volumes (it > 0): beta = r.z / r.z_old from the
+// update's partials (stop on convergence), and the voxel sums of the new
+// direction, S_p = S_z + beta S_pold and V_p = V_z + beta V_pold, formed once
+// per voxel.  The 3-D Hessian product reads the per-voxel sums once per frame
+// (they do not stay in the L2 across a column's frames), so it reads these
+// four values instead of eight.
+__device__ __forceinline__ void cg_psums_body(
+    int it, const double* __restrict__ Sz, const double* __restrict__ Vz,
+    const double* __restrict__ Sp_old, const double* __restrict__ Vp_old,
+    double* __restrict__ Sp_new, double* __restrict__ Vp_new, long long N,
+    const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
+    Scal* __restrict__ sc, int gn_it, Blk blk) {
+  constexpr int D = 3;
+  if (sc->done || gn_it >= sc->gn_stop) return;
+  double t[2];
+  reduce_partials<2>(up_part, up_nb, 0u, t);
+  const double rz_old = sc->rzh[(it - 1) & 1];
+  bool conv = (!fixed && sqrt(t[1]) <= rtol * sc->r0) || t[0] == 0.0;
+  if (conv) {
+    if (blk.id == 0 && threadIdx.x == 0) sc->done = 1;
+    return;
+  }
+  const double beta = t[0] / rz_old;
+  if (blk.id == 0 && threadIdx.x == 0) {
+    sc->rzh[it & 1] = t[0];
+    sc->rr = t[1];
+    sc->beta = beta;
+  }
+  const long long stride = (long long)blk.n * blockDim.x;
+  for (long long v = (long long)blk.id * blockDim.x + threadIdx.x; v < N;
+       v += stride) {
+    Sp_new[v] = Sz[v] + beta * Sp_old[v];
+#pragma unroll
+    for (int a = 0; a < D; ++a)
+      Vp_new[a * N + v] = Vz[a * N + v] + beta * Vp_old[a * N + v];
+  }
+}
+
+__global__ __launch_bounds__(1024) void cg_psums_kernel(
+    int it, const double* __restrict__ Sz, const double* __restrict__ Vz,
+    const double* __restrict__ Sp_old, const double* __restrict__ Vp_old,
+    double* __restrict__ Sp_new, double* __restrict__ Vp_new, long long N,
+    const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
+    Scal* __restrict__ sc, int gn_it) {
+  cg_psums_body(it, Sz, Vz, Sp_old, Vp_old, Sp_new, Vp_new, N, up_part, up_nb,
+                fixed, rtol, sc, gn_it, grid_blk());
+}
+
 // 3-D Hessian product on p = z + beta p_old (it > 0) or p = z for one
 // column of a group of frames: a 16 x 16 tile in (x, y) marched through
 // kT3Z planes in z.  For each frame the block keeps a ring of five planes of
@@ -491,24 +539,18 @@ __device__ __forceinline__ void cgt_hvp3_body(
   constexpr int kLS = (LX * LY + NT - 1) / NT;  // L points per thread
   __shared__ float P[D][5][HY][HX];
   __shared__ float L[REG ? D : 1][REG ? 3 : 1][REG ? LY : 1][REG ? LX : 1];
+  (void)up_part;
+  (void)up_nb;
+  (void)fixed;
+  (void)rtol;
+  (void)Sp_old;
+  (void)Vp_old;
   if (sc->done || gn_it >= sc->gn_stop) return;
-  double beta = 0.0;
-  if (!FIRST) {
-    double t[2];
-    reduce_partials<2>(up_part, up_nb, 0u, t);
-    const double rz_old = sc->rzh[(it - 1) & 1];
-    bool conv = (!fixed && sqrt(t[1]) <= rtol * sc->r0) || t[0] == 0.0;
-    if (conv) {
-      if (blk.id == 0 && threadIdx.x == 0) sc->done = 1;
-      return;
-    }
-    beta = t[0] / rz_old;
-    if (blk.id == 0 && threadIdx.x == 0) {
-      sc->rzh[it & 1] = t[0];
-      sc->rr = t[1];
-      sc->beta = beta;
-    }
-  }
+  // it > 0: beta and the sums of p come from cg_psums_kernel (launched just
+  // before); it = 0: p = z, whose sums this kernel keeps for the next step
+  const double beta = FIRST ? 0.0 : sc->beta;
+  const double* Sc = FIRST ? Sz : Sp_new;
+  const double* Vc = FIRST ? Vz : Vp_new;
   const float bf = (float)beta;
   const int per_xcd = blk.n / kXCD;
   const int bb = (blk.id % kXCD) * per_xcd + blk.id / kXCD;
@@ -617,16 +659,10 @@ __device__ __forceinline__ void cgt_hvp3_body(
         }
         if (inplane) {
           const unsigned vox = (unsigned)((size_t)zz * plane_n + vxy);
-          double S = Sz[vox], V[D];
+          double S = Sc[vox], V[D];
 #pragma unroll
-          for (int a = 0; a < D; ++a) V[a] = Vz[(size_t)a * N + vox];
-          if (!FIRST) {
-            S += beta * Sp_old[vox];
-#pragma unroll
-            for (int a = 0; a < D; ++a)
-              V[a] += beta * Vp_old[(size_t)a * N + vox];
-          }
-          if (fg == 0 && j == jbeg) {
+          for (int a = 0; a < D; ++a) V[a] = Vc[(size_t)a * N + vox];
+          if (FIRST && fg == 0 && j == jbeg) {
             Sp_new[vox] = S;
 #pragma unroll
             for (int a = 0; a < D; ++a) Vp_new[(size_t)a * N + vox] = V[a];
@@ -779,6 +815,17 @@ hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
                                    : cgt_hvp2_kernel<1, false>)
                     : (md.reg == 0 ? cgt_hvp3_kernel<0, false>
                                    : cgt_hvp3_kernel<1, false>);
+  if (dim == 3 && it > 0) {
+    // the sums of p first (timed with the product: start event here)
+    hipExtLaunchKernelGGL(cg_psums_kernel, dim3(cgv_blocks(g)),
+                          dim3(cgv_threads(dim, md.nK)), 0, s, ev0, nullptr,
+                          0, it, sums.Sz, sums.Vz, Sp_old, Vp_old, Sp_new,
+                          Vp_new, g.N, (const double*)rb.region(kRegUpdate),
+                          t.vox_grid, fixed, rtol, sc, gn_it);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    ev0 = nullptr;
+  }
   hipExtLaunchKernelGGL(kern, dim3(t.grid),
                         dim3(dim == 2 ? kHv2Threads : kHv3Threads), 0, s, ev0,
                         ev1, 0, it, z, p_old, p_new, dW, g, md, q, sums.Sz,
@@ -874,6 +921,18 @@ __global__ __launch_bounds__(D == 2 ? kHv2Threads : kHv3Threads,
                        J.rb.region(kRegHv), sc, sc->gn_cur, blk);
 }
 
+__global__ __launch_bounds__(1024) void cg_psums_batch_kernel(JobSet js, int it,
+                                                             int fixed,
+                                                             double rtol) {
+  Blk blk;
+  const Job& J = cg_job_of(js, kClsVox, blk);
+  Scal* sc = J.sc;
+  cg_psums_body(it, J.sums.Sz, J.sums.Vz, J.sums.Sp[(it + 1) & 1],
+                J.sums.Vp[(it + 1) & 1], J.sums.Sp[it & 1], J.sums.Vp[it & 1],
+                J.g.N, J.rb.region(kRegUpdate), J.nb_vox, fixed, rtol, sc,
+                sc->gn_cur, blk);
+}
+
 template <int D, bool FIRST>
 __global__ __launch_bounds__(1024, 8) void cg_update_batch_kernel(JobSet js,
                                                                int it) {
@@ -910,8 +969,14 @@ hipError_t batch_cg_init(const JobSet& js, int nvox, int dim, hipStream_t s) {
   return batch_finalize_start(js, s);
 }
 
-hipError_t batch_cg_hvp(const JobSet& js, int nhv, int dim, int reg, int it,
-                        int fixed, double rtol, hipStream_t s) {
+hipError_t batch_cg_hvp(const JobSet& js, int nhv, int nvox, int dim, int reg,
+                        int it, int fixed, double rtol, hipStream_t s) {
+  if (dim == 3 && it > 0) {
+    cg_psums_batch_kernel<<<nvox, cgv_threads(3, 0), 0, s>>>(js, it, fixed,
+                                                             rtol);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
   decltype(&cg_hvp_batch_kernel<2, 0, true>) kern;
   if (it == 0)
     kern = dim == 2 ? (reg == 0 ? cg_hvp_batch_kernel<2, 0, true>

@@ -1203,8 +1203,8 @@ hipError_t batch_iteration(const JobSet& js, const int* tot, int dim,
   hipError_t e = batch_eval(js, tot[kClsTile], dim, reg, s);
   if (e == hipSuccess) e = batch_cg_init(js, tot[kClsVox], dim, s);
   for (int it = 0; e == hipSuccess && it < o.cg_max; ++it) {
-    e = batch_cg_hvp(js, tot[kClsHv], dim, reg, it, o.parity_mode,
-                     o.cg_rtol, s);
+    e = batch_cg_hvp(js, tot[kClsHv], tot[kClsVox], dim, reg, it,
+                     o.parity_mode, o.cg_rtol, s);
     if (e == hipSuccess) e = batch_cg_update(js, tot[kClsVox], dim, it, s);
   }
   for (size_t pi = 0; e == hipSuccess && pi < passes.size(); ++pi) {
