@@ -519,8 +519,9 @@ __global__ __launch_bounds__(1024) void cg_psums_kernel(
 // plane of p (its loads issued one step ahead, into registers), forms one
 // plane of L p and finishes one plane of q = H p.  The halo overhead per
 // step is that of a 2-D tile (20 x 20 loads for 16 x 16 outputs) instead of
-// a 3-D one.  Voxel sums S, V and the CG scalars as in 2-D; the per-voxel
-// sums are read per frame (they stay in the L2 across the block's frames).
+// a 3-D one.  The voxel sums of p are read per frame: at CG step 0 those of
+// z (which the product keeps for the next step), later the ones
+// cg_psums_kernel formed together with beta.
 template <int REG, bool FIRST>
 __device__ __forceinline__ void cgt_hvp3_body(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
