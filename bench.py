@@ -15,7 +15,10 @@ voxels counts |K| N voxel-frames.  The Armijo trial sweeps, CG vector
 updates, predictors and host synchronisation are inside the timed region
 but not counted as units.
 
-Prints one JSON line.
+Prints one JSON line.  Besides the contract's fields it carries the
+per-kernel breakdown, a small solve, the 32-sequence batch, the learned
+predictor against the paper's (images and volumes), the volume workload,
+SpML against STML (the paper's comparison) and the CPU oracle's rate.
 """
 
 import argparse
@@ -373,6 +376,89 @@ def learned3d_comparison(seqs, log):
                for k, v in s.items() if k != "sequences"}}
 
 
+def multilevel_comparison(frames, dim, log, reps):
+    """The paper's comparison (Sec. 4, Table 1) in this model: the spatial
+    multilevel strategy (SpML: every frame registered on every spatial
+    level, i.e. one temporal level) against STML with three temporal levels
+    (and STML with the eq. (3) stop, eps 1e-3); same inner solver, the
+    paper's predictors, convergence-controlled Gauss-Newton (gn_max 40).
+    Reported per variant: the wall time of the whole schedule (median of
+    `reps` solves) and, from one more solve driven stage by stage (every
+    entry point returns synchronised), the time and Gauss-Newton iterations
+    of each spatial level, D over all frames relative to the unregistered
+    D, and the relative difference of the finest-level displacements from
+    SpML's.  Because the variants stop at different objectives, STML's time
+    to reach SpML's final objective is estimated too: the stages before the
+    last in full, the last one up to the first Gauss-Newton iteration whose
+    objective is at or below SpML's (its time prorated by iterations)."""
+    import torch
+    from paper_2001_06613_amd import learned
+    from paper_2001_06613_amd.binding import STML
+
+    n, ext = frames.shape[0], frames.shape[1:]
+    fr = torch.from_numpy(frames).cuda()
+    out, ys, final_j = {}, {}, None
+    for name, nt, eps in (("spml", 1, 0.0), ("stml", 3, 0.0),
+                          ("stml_eq3", 3, 1e-3)):
+        st = STML(n, ext, opts=learned.schedule_opts(
+            predictor=0, dim=dim, n_temporal=nt, gn_max=40, eps_stop=eps))
+        L = st.levels
+        ts = []
+        for _ in range(reps):
+            st.set_sequence(fr)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        res = {"wall_ms": round(1e3 * float(np.median(ts)), 2),
+               "stages": len(st.logs())}
+        if name != "stml_eq3":
+            # the same schedule, stage by stage (no eq. (3) stop)
+            st.set_sequence(fr)
+            stage_ms = []
+            for lv in range(L):
+                for q in range(nt):
+                    t0 = time.perf_counter()
+                    st.predict(lv, q)
+                    st.register_level(lv, q)
+                    stage_ms.append(1e3 * (time.perf_counter() - t0))
+            logs = st.logs()
+            res["levels"] = [
+                {"level": lv, "extent": list(st.level_extent(lv)),
+                 "ms": round(sum(stage_ms[lv * nt:(lv + 1) * nt]), 2),
+                 "gn": sum(g["gn"] for g in logs if g["level"] == lv)}
+                for lv in range(L)]
+            last = logs[-1]
+            if name == "spml":
+                final_j = last["J"]
+            else:
+                traj = [last["J0"]] + list(last["J_iter"])
+                k = next((i for i, J in enumerate(traj) if J <= final_j),
+                         None)
+                res["final_stage_gn"] = last["gn"]
+                res["final_stage_gn_to_spml_J"] = k
+                if k is not None:
+                    res["est_ms_to_spml_J"] = round(
+                        sum(stage_ms[:-1]) +
+                        stage_ms[-1] * k / max(last["gn"], 1), 2)
+        u = st.get_displacements(L - 1)
+        allk = list(range(n))
+        d0 = st.eval(L - 1, allk, torch.zeros_like(u), want_grad=False)["D"]
+        d1 = st.eval(L - 1, allk, u, want_grad=False)["D"]
+        res["D_over_D0_pct"] = round(100.0 * d1 / d0, 3)
+        ys[name] = u.double()
+        out[name] = res
+        st.close()
+        log(f"multilevel {dim}-D: {name} done")
+    for name in ("stml", "stml_eq3"):
+        out[name]["rel_diff_y_vs_spml_pct"] = round(
+            100.0 * float((ys[name] - ys["spml"]).norm() /
+                          ys["spml"].norm()), 3)
+        out[name]["speedup_vs_spml"] = round(
+            out["spml"]["wall_ms"] / out[name]["wall_ms"], 3)
+    return out
+
 def pmc_probe(st, fr):
     """One solve and a plain copy of known size, for counter runs."""
     import torch
@@ -397,6 +483,8 @@ def main():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--no-volume", action="store_true")
     ap.add_argument("--no-small", action="store_true")
+    ap.add_argument("--no-multilevel", action="store_true",
+                    help="skip the SpML vs STML comparison")
     ap.add_argument("--oracle-full", action="store_true",
                     help="time the oracle's whole schedule (CPU only)")
     ap.add_argument("--pmc-probe", action="store_true",
@@ -570,6 +658,11 @@ def main():
         if not args.no_learned:
             out["learned_3d"] = learned3d_comparison(
                 list(zip(LEARNED3D_SEEDS, volume_seqs[1 + nb:])), log)
+    if not args.no_multilevel:
+        out["multilevel"] = {"image": multilevel_comparison(frames, 2, log, 3)}
+        if volume_seqs is not None:
+            out["multilevel"]["volume"] = multilevel_comparison(
+                volume_seqs[0], 3, log, 1)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frames)
     print(json.dumps(out))
