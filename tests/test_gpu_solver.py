@@ -301,3 +301,36 @@ def test_register_level_parity_3d(reg):
     assert lg["J"] == pytest.approx(olg["J"], rel=1e-5)
     u = st.get_displacements(0).cpu().numpy()
     assert np.abs(u - ost.Y[0]).max() <= 1e-3
+
+
+def test_spml_run_parity_and_staged_schedule():
+    """SpML (one temporal level: every frame on every spatial level) against
+    the oracle; and the schedule driven stage by stage through the entry
+    points (as the benchmark's SpML/STML comparison times it) equals
+    stml_run bit for bit."""
+    frames = _small()
+    kw = dict(n_spatial=2, n_temporal=1, reg="curvature", gn_max=5,
+              cg_max=10, parity_mode=True)
+    st = STML(8, frames.shape[1:], opts=default_opts(**kw))
+    st.set_sequence(torch.from_numpy(frames).cuda())
+    print("spml run", flush=True)
+    st.run()
+    u_ref, ost = oracle.stml_run(frames, oracle.STMLOptions(**kw))
+    assert [lg["steps"] for lg in st.logs()] == \
+        [lg["steps"] for lg in ost.log]
+    assert len(st.logs()) == 2
+    assert np.abs(st.get_displacements().cpu().numpy() - u_ref).max() <= 1e-3
+    kw3 = dict(kw, n_temporal=2)
+    st3 = STML(8, frames.shape[1:], opts=default_opts(**kw3))
+    st3.set_sequence(torch.from_numpy(frames).cuda())
+    st3.run()
+    whole = st3.get_displacements().cpu().numpy()
+    st3.set_sequence(torch.from_numpy(frames).cuda())
+    print("stml staged", flush=True)
+    for lv in range(2):
+        for q in range(2):
+            st3.predict(lv, q)
+            st3.register_level(lv, q)
+    assert len(st3.logs()) == 4
+    np.testing.assert_array_equal(st3.get_displacements().cpu().numpy(),
+                                  whole)
