@@ -215,7 +215,8 @@ int stml_gn_direction(stml_ctx* ctx, int level, const int* frames, int nk,
  * whole-sequence kernels) accumulate per (class, level).  Timing adds two
  * event records per timed launch. */
 #define STML_K_EVAL        0  /* warp + distance + gradient                 */
-#define STML_K_HESSVEC     1  /* Gauss-Newton Hessian product (CG and test)  */
+#define STML_K_HESSVEC     1  /* Gauss-Newton Hessian product (CG and test;
+                                 volumes: with the direction's voxel sums) */
 #define STML_K_CG_UPDATE   2  /* x, r, z update and r.z                      */
 #define STML_K_CG_PUPDATE  3  /* p = z + beta p                              */
 #define STML_K_TRIAL       4  /* objective at the Armijo trial steps         */
