@@ -255,8 +255,11 @@ def _volume(n, ext, seed):
 
 
 @pytest.mark.parametrize("reg", ["diffusion", "curvature"])
-def test_gn_direction_parity_3d(reg):
-    ext = (10, 12, 18)             # ragged against 16 x 16 x 16 columns
+@pytest.mark.parametrize("ext", [(10, 12, 18), (37, 20, 35)])
+def test_gn_direction_parity_3d(reg, ext):
+    # ragged against 16 x 16 x 16 columns; the second spans several columns
+    # on every axis (CG steps > 0 take beta and the sums of p from the sums
+    # kernel)
     n = 4
     frames = _volume(n, ext, 21)
     o = default_opts(dim=3, n_spatial=1, n_temporal=2, reg=reg, cg_max=8,
@@ -265,7 +268,7 @@ def test_gn_direction_parity_3d(reg):
     st.set_sequence(torch.from_numpy(frames).cuda())
     u = synth.random_displacement(ext, n, 1.2, 4)
     K = [0, 1, 3]
-    print(f"gn_direction 3d {reg}", flush=True)
+    print(f"gn_direction 3d {reg} {ext}", flush=True)
     delta, iters = st.gn_direction(0, K, torch.from_numpy(u))
     par = oracle.ModelParams(reg=reg)
     ref = oracle.objective(frames, u, K, 1.0, par)
