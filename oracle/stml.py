@@ -13,7 +13,10 @@ predictor-corrector loop walks the temporal tree K_0 ... K_T:
   correct by registering K_{q+1} from that prediction.
 * optional stopping rule, eq. (3): after the prediction that follows the
   registration of K_q (q >= 1), stop the level if D over all frames, at the
-  all-frame estimate, changed by at most eps relative to the previous one.
+  all-frame estimate, changed by at most eps from the previous one
+  (|D_q - D_{q-1}| <= eps, as printed; ``stop_relative`` selects the test
+  |D_q - D_{q-1}| <= eps |D_q| instead).  The all-frame estimate is the
+  prediction for every frame, with the frames of K_q as registered.
 
 Reading of eq. (2)'s reference omega: it is the all-frame start guess of the
 current temporal level, z(l, q, all); for q = 0 that is the prolonged
@@ -44,6 +47,7 @@ class STMLOptions:
     lam: float = 1e-2
     beta: float = 1e-5
     eps_stop: float = 0.0          # 0 disables eq. (3)
+    stop_relative: bool = False    # eq. (3) as |dD| <= eps |D|
     gn_max: int = 10
     cg_max: int = 20
     cg_rtol: float = 0.1
@@ -74,6 +78,9 @@ class STMLState:
         self.Y = [None] * opts.n_spatial
         self.Z = [None] * opts.n_spatial
         self.log = []
+        # eq. (3): D over all frames at each q of each level, when enabled
+        self.stop_trace = [[] for _ in range(opts.n_spatial)]
+        self.stop_q = [-1] * opts.n_spatial
 
     def h(self, level):
         return level_spacing(self.opts.n_spatial, level)
@@ -130,9 +137,11 @@ class STMLState:
                     est = self.Y[level].copy()
                     est[Kq] = y_now[Kq]
                     Dq = self.all_frame_D(level, est)
-                    if D_prev is not None and \
-                            abs(Dq - D_prev) <= o.eps_stop * abs(Dq):
+                    self.stop_trace[level].append(Dq)
+                    tol = o.eps_stop * (abs(Dq) if o.stop_relative else 1.0)
+                    if D_prev is not None and abs(Dq - D_prev) <= tol:
                         self.Y[level] = est
+                        self.stop_q[level] = q
                         self.log.append({"level": level, "stop_at_q": q})
                         break
                     D_prev = Dq

@@ -85,3 +85,102 @@ def test_gn_monotone_decrease():
     J_check = objective_value(frames, res.u, [0, 2, 4, 6, 7], 2.0,
                               ModelParams())[0]
     assert J_check == pytest.approx(res.J, rel=1e-12)
+
+
+def test_pcg_jacobi_exact_on_diagonal_in_one_step():
+    # With M = diag(A) = A the preconditioned system is the identity, so the
+    # first Jacobi-PCG step is the exact solution; plain CG (or any other
+    # scaling of r) needs one step per distinct eigenvalue.
+    d = np.array([1.0, 3.0, 10.0, 0.2, 7.5, 42.0])
+    b = np.array([1.0, -2.0, 0.5, 3.0, -1.5, 0.25])
+    x, it, st = pcg(lambda v: d * v, d.copy(), b, cg_max=1, rtol=0.0,
+                    fixed=True)
+    assert it == 1 and st == "ok"
+    np.testing.assert_allclose(x, b / d, rtol=1e-14, atol=0)
+
+
+def _galerkin_krylov(A, Minv, b, k):
+    """A-norm minimiser of the error over span{Minv b, (Minv A) Minv b, ...}
+    (k vectors), built densely; the classical characterisation of the k-th
+    preconditioned CG iterate started at 0."""
+    cols = [Minv @ b]
+    for _ in range(k - 1):
+        cols.append(Minv @ (A @ cols[-1]))
+    Q, _ = np.linalg.qr(np.stack(cols, axis=1))
+    return Q @ np.linalg.solve(Q.T @ A @ Q, Q.T @ b)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 7])
+def test_pcg_iterates_are_preconditioned_krylov_minimisers(k):
+    rng = np.random.default_rng(7)
+    N = 14
+    B = rng.standard_normal((N, N))
+    S = np.diag(np.exp(rng.uniform(-2.0, 2.0, N)))   # strongly uneven scale
+    A = S @ (B @ B.T / N + np.identity(N)) @ S
+    b = rng.standard_normal(N)
+    diag = np.diag(A).copy()
+    x, it, st = pcg(lambda v: A @ v, diag, b, cg_max=k, rtol=0.0, fixed=True)
+    assert it == k and st == "ok"
+    ref = _galerkin_krylov(A, np.diag(1.0 / diag), b, k)
+    np.testing.assert_allclose(x, ref, rtol=1e-9, atol=1e-12)
+    # the test separates Jacobi from no preconditioner and from M = 1/diag
+    for wrong in (np.identity(N), np.diag(diag)):
+        assert np.max(np.abs(_galerkin_krylov(A, wrong, b, k) - ref)) > \
+            1e-3 * np.max(np.abs(ref))
+
+
+class _UnderestimatedQuadratic:
+    """J(x) = (c/2)|x|^2 with a Gauss-Newton Hessian c/rho I (rho > 1).
+
+    The Gauss-Newton direction is delta = -rho x, and
+    J(x + t delta) = J(x) (1 - t rho)^2, so Armijo with constant c1 holds
+    exactly for t <= 2 (1 - c1) / rho: the unit step fails for rho > 2 and
+    the ladder 1, 1/2, 1/4, ... stops at the first power of two below that.
+    """
+
+    def __init__(self, c, rho):
+        self.c, self.rho = c, rho
+
+    def value(self, x):
+        return 0.5 * self.c * float(np.sum(x * x))
+
+    def evaluate(self, x):
+        return self.value(x), self.c * x, None
+
+    def hessvec(self, state, v):
+        return (self.c / self.rho) * v
+
+    def diag(self, state):
+        return np.full(1, self.c / self.rho)
+
+
+@pytest.mark.parametrize("rho,t_expected", [(3.0, 0.5), (5.0, 0.25),
+                                             (10.0, 0.125), (1.5, 1.0)])
+def test_gn_armijo_ladder_closed_form(rho, t_expected):
+    from oracle.solver import gn_minimise
+
+    model = _UnderestimatedQuadratic(2.0, rho)
+    x0 = np.array([0.75])
+    res = gn_minimise(model, x0, gn_max=1, cg_max=1, ls_max=10, c1=1e-4,
+                      fixed=True)
+    assert res.steps == [t_expected]
+    # the accepted point in closed form: x0 (1 - t rho)
+    np.testing.assert_allclose(res.u, x0 * (1.0 - t_expected * rho),
+                               rtol=1e-15)
+    assert res.J == pytest.approx(model.value(x0) *
+                                  (1.0 - t_expected * rho) ** 2, rel=1e-14)
+
+
+def test_gn_armijo_ladder_length():
+    from oracle.solver import gn_minimise
+
+    # t <= 2 (1 - c1) / 4000 ~ 5.0e-4 < 2^-10: ten halvings are not enough,
+    # eleven are (ls_max counts the halvings after t = 1)
+    model = _UnderestimatedQuadratic(1.0, 4000.0)
+    res = gn_minimise(model, np.array([1.0]), gn_max=1, cg_max=1, ls_max=10,
+                      fixed=True)
+    assert res.status == "linesearch" and res.steps == []
+    assert np.all(res.u == 1.0)
+    res = gn_minimise(model, np.array([1.0]), gn_max=1, cg_max=1, ls_max=11,
+                      fixed=True)
+    assert res.steps == [2.0 ** -11]
