@@ -400,8 +400,11 @@ def multilevel_comparison(frames, dim, log, reps):
     out, ys, final_j = {}, {}, None
     for name, nt, eps in (("spml", 1, 0.0), ("stml", 3, 0.0),
                           ("stml_eq3", 3, 1e-3)):
+        # eq. (3) with a relative tolerance (the paper gives no epsilon;
+        # 1e-3 of D is scale-free across the image and volume sequences)
         st = STML(n, ext, opts=learned.schedule_opts(
-            predictor=0, dim=dim, n_temporal=nt, gn_max=40, eps_stop=eps))
+            predictor=0, dim=dim, n_temporal=nt, gn_max=40, eps_stop=eps,
+            stop_relative=eps > 0))
         L = st.levels
         ts = []
         for _ in range(reps):

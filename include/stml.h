@@ -73,7 +73,7 @@ typedef struct stml_opts {
   double alpha;       /* regulariser weight                         (1e-2)   */
   double lambda;      /* penalty weight of Sec. 2                   (1e-2)   */
   double beta;        /* eq. (2) weight                             (1e-5)   */
-  double eps_stop;    /* eq. (3) relative tolerance; 0 = off        (0)      */
+  double eps_stop;    /* eq. (3) tolerance epsilon; 0 = off         (0)      */
   int gn_max;         /* Gauss-Newton iterations per registration   (10)     */
   int cg_max;         /* CG iterations per Gauss-Newton step        (20)     */
   double cg_rtol;     /* CG stops at ||r|| <= cg_rtol ||r_0||       (0.1)    */
@@ -87,6 +87,8 @@ typedef struct stml_opts {
                          (stml_set_predictor_net)                  (0)      */
   int parity_mode;    /* 1: exactly gn_max GN and cg_max CG iterations,
                          no convergence exits, eq. (3) off          (0)      */
+  int stop_relative;  /* 0: eq. (3) as printed, |D_q - D_{q-1}| <= eps;
+                         1: |D_q - D_{q-1}| <= eps |D_q|            (0)      */
 } stml_opts;
 
 /* Statistics of one registration call (GIR on one subset). */
@@ -168,8 +170,20 @@ int stml_register_level(stml_ctx* ctx, int level, int q);
 int stml_correct(stml_ctx* ctx, int level, int q_next);
 
 /* Whole schedule of Sec. 3: levels coarse to fine, predictor-corrector over
- * K_0..K_T, eq. (3) when eps_stop > 0 and not in parity mode. */
+ * K_0..K_T, eq. (3) when eps_stop > 0 and not in parity mode.
+ * Eq. (3) (Sec. 3): after registering K_q and predicting every frame from
+ * it, D is evaluated over all n frames at the estimate (the prediction,
+ * with the frames of K_q as registered); from q = 1 on the level stops
+ * when |D_q - D_{q-1}| <= eps_stop, and that estimate is the level's
+ * result (K_{q+1}, ... are not registered). */
 int stml_run(stml_ctx* ctx);
+
+/* Eq. (3) record of the last stml_run for `level`: the all-frame D_q of
+ * each q evaluated (at most `cap` into D_out, host), and in *stop_q (may be
+ * NULL) the q at which the level stopped, -1 if it did not.  Returns the
+ * number of D values recorded (0 when eq. (3) was off), or EINVAL. */
+int stml_get_stop_trace(const stml_ctx* ctx, int level, double* D_out,
+                        int cap, int* stop_q);
 
 /* Current estimate (y) of `level` into u_dev [n][dim][extent_level...]. */
 int stml_get_displacements(const stml_ctx* ctx, int level, float* u_dev);

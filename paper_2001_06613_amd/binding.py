@@ -45,6 +45,7 @@ class stml_opts(ctypes.Structure):
         ("tol_u", ctypes.c_double),
         ("predictor", ctypes.c_int),
         ("parity_mode", ctypes.c_int),
+        ("stop_relative", ctypes.c_int),
     ]
 
 
@@ -97,6 +98,7 @@ SIGNATURES = {
     "stml_register_level": (_I, [_P, _I, _I]),
     "stml_correct": (_I, [_P, _I, _I]),
     "stml_run": (_I, [_P]),
+    "stml_get_stop_trace": (_I, [_P, _I, _DP, _I, _IP]),
     "stml_get_displacements": (_I, [_P, _I, _P]),
     "stml_set_displacements": (_I, [_P, _I, _P]),
     "stml_get_prediction": (_I, [_P, _I, _P]),
@@ -183,7 +185,7 @@ def default_opts(**kw):
             k = "lambda_"
         if k == "reg":
             k, v = "regulariser", REG[v]
-        if k == "parity_mode":
+        if k in ("parity_mode", "stop_relative"):
             v = int(bool(v))
         if not hasattr(o, k):
             raise KeyError(k)
@@ -207,7 +209,11 @@ class STML:
     correct, run, get/set_displacements, eval, hessvec, gn_direction.
     """
 
-    def __init__(self, n, extent, opts=None, stream=None, **kw):
+    def __init__(self, n, extent, opts=None, stream=None,
+                 workspace_fill=None, **kw):
+        """workspace_fill: byte value written over the fresh workspace
+        before the context is created (tests: state must not depend on
+        what the memory held)."""
         import torch
 
         self.torch = torch
@@ -226,6 +232,8 @@ class STML:
         self.device = torch.device("cuda", torch.cuda.current_device())
         self.workspace = torch.empty(nbytes, dtype=torch.uint8,
                                      device=self.device)
+        if workspace_fill is not None:
+            self.workspace.fill_(int(workspace_fill))
         self.stream = stream if stream is not None else \
             torch.cuda.current_stream(self.device)
         ctx = ctypes.c_void_p()
@@ -333,6 +341,16 @@ class STML:
         self._sync_in()
         return self._check(self.lib.stml_set_prediction(self.ctx, level,
                                                         _ptr(z)))
+
+    def stop_trace(self, level=None):
+        """Eq. (3) record of the last run on `level`: (D_q list, stop q or
+        -1)."""
+        level = self.levels - 1 if level is None else level
+        buf = (ctypes.c_double * 64)()
+        q = ctypes.c_int(-1)
+        cnt = self._check(self.lib.stml_get_stop_trace(self.ctx, level, buf,
+                                                       64, ctypes.byref(q)))
+        return list(buf[:min(cnt, 64)]), q.value
 
     def logs(self):
         out = []

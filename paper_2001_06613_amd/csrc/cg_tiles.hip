@@ -141,10 +141,35 @@ __global__ __launch_bounds__(1024) void cgv_init_kernel(
                    grid_blk());
 }
 
+// x = 0 over this block's tiles: the CG solution when no step is taken
+// (r.z = 0 at the start, or p.q <= 0 at the first step), as CG from x0 = 0
+// leaves it; without this the Gauss-Newton step would read whatever x held.
+template <int D>
+__device__ __forceinline__ void cg_zero_x(float* __restrict__ x,
+                                          const Geom& g, const Model& md,
+                                          Blk blk) {
+  int j0, j1;
+  wave_frames(md.nK, j0, j1);
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long N = g.N;
+  const long long ntiles = (N + kWave - 1) / kWave;
+  for (int tt = 0;; ++tt) {
+    long long tile = xcd_tile(ntiles, tt, blk);
+    if (tile < 0) break;
+    long long xv = tile * kWave + lane;
+    if (xv >= N) continue;
+    for (int j = j0; j < j1; ++j)
+#pragma unroll
+      for (int a = 0; a < D; ++a)
+        x[((size_t)j * D + a) * N + (size_t)xv] = 0.f;
+  }
+}
+
 // CG step, part 2: a = rz / p.q (stop on p.q <= 0); x += a p (x = a p at
 // it = 0: FIRST), r -= a q, z = M^-1 r; per-voxel S_z, V_z; partials r.z,
 // r.r.  A frame's loads (both components) issue before its stores, which
-// would otherwise hold the next component's loads back.
+// would otherwise hold the next component's loads back.  At it = 0 a CG
+// that stops before its first step sets x = 0.
 template <int D, bool FIRST>
 __device__ __forceinline__ void cgv_update_body(
     int it, const float* __restrict__ p, const float* __restrict__ q,
@@ -153,7 +178,11 @@ __device__ __forceinline__ void cgv_update_body(
     double* __restrict__ Sz, double* __restrict__ Vz,
     const double* __restrict__ hv_part, int hv_nb, double* __restrict__ part,
     Scal* __restrict__ sc, int gn_it, Blk blk) {
-  if (sc->done || gn_it >= sc->gn_stop) return;
+  if (gn_it >= sc->gn_stop) return;
+  if (sc->done) {
+    if (FIRST) cg_zero_x<D>(x, g, md, blk);
+    return;
+  }
   double t[1];
   reduce_partials<1>(hv_part, hv_nb, 0u, t);
   const double pq = t[0];
@@ -162,6 +191,7 @@ __device__ __forceinline__ void cgv_update_body(
       sc->pq = pq;
       sc->done = 2;
     }
+    if (FIRST) cg_zero_x<D>(x, g, md, blk);
     return;
   }
   const double alpha = sc->rzh[it & 1] / pq;
@@ -949,6 +979,15 @@ __global__ __launch_bounds__(1024, 8) void cg_update_batch_kernel(JobSet js,
                             sc->gn_cur, blk);
 }
 
+template <int D>
+__global__ __launch_bounds__(1024) void cg_zero_x_batch_kernel(JobSet js) {
+  Blk blk;
+  const Job& J = cg_job_of(js, kClsVox, blk);
+  const Scal* sc = J.sc;
+  if (sc->gn_cur >= sc->gn_stop) return;
+  cg_zero_x<D>(J.x, J.g, J.md, blk);
+}
+
 void job_shape(Job* job) {
   const int dim = geom_dim(job->g);
   job->ct = cg_tiles(job->g, job->md.nK, dim);
@@ -968,6 +1007,14 @@ hipError_t batch_cg_init(const JobSet& js, int nvox, int dim, hipStream_t s) {
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return batch_finalize_start(js, s);
+}
+
+hipError_t batch_zero_x(const JobSet& js, int nvox, int dim, hipStream_t s) {
+  if (dim == 2)
+    cg_zero_x_batch_kernel<2><<<nvox, cgv_threads(2, 0), 0, s>>>(js);
+  else
+    cg_zero_x_batch_kernel<3><<<nvox, cgv_threads(3, 0), 0, s>>>(js);
+  return hipGetLastError();
 }
 
 hipError_t batch_cg_hvp(const JobSet& js, int nhv, int nvox, int dim, int reg,

@@ -169,6 +169,8 @@ hipError_t batch_gn_reset(const JobSet& js, int gn_max, hipStream_t s);
 hipError_t batch_eval(const JobSet& js, int nblocks, int dim, int reg,
                       hipStream_t s);
 hipError_t batch_cg_init(const JobSet& js, int nvox, int dim, hipStream_t s);
+// x = 0 for every running job (CG with no iteration: cg_max = 0)
+hipError_t batch_zero_x(const JobSet& js, int nvox, int dim, hipStream_t s);
 hipError_t batch_cg_hvp(const JobSet& js, int nhv, int nvox, int dim, int reg,
                         int it, int fixed, double rtol, hipStream_t s);
 hipError_t batch_cg_update(const JobSet& js, int nvox, int dim, int it,

@@ -80,6 +80,10 @@ struct stml_ctx {
     double Jp = NAN, Jl = NAN;
   } pick;                                // start guess of the next GIR
   std::vector<stml_gir_log> logs;
+  // eq. (3) of the last stml_run: D over all frames per q, and the q at
+  // which each level stopped (-1: not stopped)
+  std::vector<std::vector<double>> stop_trace;
+  std::vector<int> stop_q;
   std::string err;
   // kernel timing
   struct Rec {
@@ -128,6 +132,7 @@ bool opts_valid(const stml_opts* o) {
          o->alpha >= 0 && o->lambda >= 0 && o->beta >= 0 &&
          o->eps_stop >= 0 && o->gn_max >= 0 && o->cg_max >= 0 &&
          o->ls_max >= 0 && o->ls_max <= 60 &&
+         (o->stop_relative == 0 || o->stop_relative == 1) &&
          (o->predictor == 0 || o->predictor == 1);
 }
 
@@ -466,6 +471,8 @@ int enqueue_pcg(stml_ctx* c, int level, const Geom& g, const Model& md,
   TIMED(STML_K_CG_INIT, level, vf,
         launch_cgv_init(D, c->g, c->dW, g, md, c->r, c->z, c->sums, c->rb,
                         c->sc, c->stream, gn_it, c->gnlog));
+  if (c->o.cg_max == 0)   // no CG step: the direction is x0 = 0
+    HIP_OK(launch_fill(c->x, (size_t)md.nK * D * g.N, 0.0f, c->stream));
   for (int it = 0; it < c->o.cg_max; ++it) {
     float* pn = c->P[it & 1];
     const float* po = c->P[(it + 1) & 1];
@@ -916,6 +923,8 @@ int stml_run(stml_ctx* c) {
   const int T = c->T1 - 1;
   const bool eq3 = c->o.eps_stop > 0 && !c->o.parity_mode;
   int warn = STML_OK;
+  c->stop_trace.assign(c->L, std::vector<double>());
+  c->stop_q.assign(c->L, -1);
   for (int level = 0; level < c->L; ++level) {
     int rc = do_predict(c, level, 0);
     if (rc < 0) return rc;
@@ -946,10 +955,15 @@ int stml_run(stml_ctx* c) {
         double Dq;
         rc = all_frame_D(c, level, c->r, &Dq);
         if (rc) return rc;
-        if (have_prev && std::fabs(Dq - D_prev) <= c->o.eps_stop * std::fabs(Dq)) {
+        c->stop_trace[level].push_back(Dq);
+        // eq. (3) as printed: |D_q - D_{q-1}| <= eps (relative on request)
+        const double tol =
+            c->o.eps_stop * (c->o.stop_relative ? std::fabs(Dq) : 1.0);
+        if (have_prev && std::fabs(Dq - D_prev) <= tol) {
           HIP_OK(hipMemcpyAsync(b.Y, c->r, cnt * sizeof(float),
                                 hipMemcpyDeviceToDevice, c->stream));
           HIP_OK(hipStreamSynchronize(c->stream));
+          c->stop_q[level] = q;
           break;
         }
         D_prev = Dq;
@@ -961,6 +975,24 @@ int stml_run(stml_ctx* c) {
     }
   }
   return warn;
+}
+
+int stml_get_stop_trace(const stml_ctx* cc, int level, double* D_out,
+                        int cap, int* stop_q) {
+  stml_ctx* c = const_cast<stml_ctx*>(cc);
+  if (!c) return STML_EINVAL;
+  int rc = check_level(c, level);
+  if (rc) return rc;
+  if (cap < 0 || (cap > 0 && !D_out))
+    return fail(c, STML_EINVAL, "D_out must hold cap values");
+  if ((int)c->stop_trace.size() != c->L) {
+    if (stop_q) *stop_q = -1;
+    return 0;
+  }
+  const std::vector<double>& tr = c->stop_trace[level];
+  for (int i = 0; i < (int)tr.size() && i < cap; ++i) D_out[i] = tr[i];
+  if (stop_q) *stop_q = c->stop_q[level];
+  return (int)tr.size();
 }
 
 static int copy_field(stml_ctx* c, int level, float* dst, const float* src) {
@@ -1202,6 +1234,7 @@ hipError_t batch_iteration(const JobSet& js, const int* tot, int dim,
                            int* dstop, hipStream_t s) {
   hipError_t e = batch_eval(js, tot[kClsTile], dim, reg, s);
   if (e == hipSuccess) e = batch_cg_init(js, tot[kClsVox], dim, s);
+  if (e == hipSuccess && o.cg_max == 0) e = batch_zero_x(js, tot[kClsVox], dim, s);
   for (int it = 0; e == hipSuccess && it < o.cg_max; ++it) {
     e = batch_cg_hvp(js, tot[kClsHv], tot[kClsVox], dim, reg, it,
                      o.parity_mode, o.cg_rtol, s);

@@ -281,3 +281,76 @@ def test_assemble_and_emit_3d():
         np.testing.assert_allclose(unew[t], expect, rtol=1e-5, atol=1e-5)
     untouched = [k for k in range(n) if k not in (3, 5)]
     np.testing.assert_array_equal(unew[untouched], u[untouched])
+
+
+# ------------------------------------------ workload row widths, 2-D and 3-D
+
+
+def _noise_elementwise(fn, params, x, ref):
+    """Largest element-wise distance of the two float32-accumulation oracle
+    runs (the orders of _noise) from the float64 result."""
+    dim = x.ndim - 2
+    a = _oracle32(fn, params, x)[0]
+    b = _turn(_oracle32(fn, _flip_kernels(params, dim).astype(np.float32),
+                        _turn(x, dim))[0], dim)
+    return max(float(np.max(np.abs(a - ref))), float(np.max(np.abs(b - ref))))
+
+
+def _check_forward(net, params, x, label):
+    net.set_params(torch.from_numpy(params))
+    net.set_input(torch.from_numpy(x))
+    print(f"cnn forward {label}", flush=True)
+    out = net.forward().cpu().numpy()
+    xn = np.moveaxis(x, 1, -1).copy()
+    ref, _ = cnn.forward(params, xn, bf16=True)
+    noise = _noise(cnn.forward, params, xn)(ref)
+    emax = float(np.max(np.abs(out - ref)))
+    nmax = _noise_elementwise(cnn.forward, params, xn, ref)
+    print(f"  norm: gpu {_rel(out, ref):.2e}, noise {noise:.2e}; "
+          f"element-wise: gpu {emax:.2e}, noise {nmax:.2e}, "
+          f"max|ref| {np.max(np.abs(ref)):.2e}", flush=True)
+    assert out.shape == ref.shape
+    assert _rel(out, ref) <= 2 * noise + 1e-4
+    assert emax <= 2 * nmax + 1e-4 * float(np.max(np.abs(ref)))
+
+
+def test_forward_parity_full_width_image():
+    # 256-pixel rows: the widest LDS halo of the 2-D convolution
+    params = cnn.init_params(21)
+    params[-2:] = 0.05
+    x, _ = _batch(1, 256, 256, 22)
+    _check_forward(Net(1, (256, 256)), params, x, "1x256x256")
+
+
+def test_forward_parity_volume_slab():
+    # a 16-plane slab of the 128 x 128 x 64 volume at its row and plane size
+    params = cnn.init_params(23, dim=3)
+    params[-3:] = 0.05
+    x, _ = _batch3(1, (16, 128, 64), 24)
+    _check_forward(Net(1, (16, 128, 64), dim=3), params, x, "1x16x128x64")
+
+
+def test_gradient_parity_full_width():
+    B, H, W = 1, 64, 256
+    net = Net(1, (H, W))
+    params = cnn.init_params(25)
+    net.set_params(torch.from_numpy(params))
+    x, tgt = _batch(B, H, W, 26)
+    net.set_input(torch.from_numpy(x), torch.from_numpy(tgt))
+    print("cnn gradient 1x64x256", flush=True)
+    loss, g = net.gradient()
+    g = g.cpu().numpy().astype(np.float64)
+    xn = x.transpose(0, 2, 3, 1)
+    ref_loss, ref_g = cnn.loss_and_grad(params, xn, tgt, bf16=True)
+    noise = _noise(cnn.loss_and_grad, params, xn, tgt)
+    o, bad = 0, []
+    for name, ci, co, k in cnn.LAYERS:
+        nw = k * k * co * ci
+        sl = slice(o, o + nw)
+        e, n = _rel(g[sl], ref_g[sl]), noise(ref_g, sl)
+        print(f"{name}: gpu {e:.2e} noise {n:.2e}")
+        if e > 2 * n + 1e-4:
+            bad.append(name)
+        o += nw + co
+    assert not bad, bad
+    assert _rel(g, ref_g) <= 2 * noise(ref_g) + 1e-4

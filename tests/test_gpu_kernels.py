@@ -56,6 +56,23 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def _elementwise(got, ref, tol, what):
+    """max |got - ref| <= tol max |ref| over every element; also reports
+    the largest error on the voxels next to a domain face."""
+    err = np.abs(got - ref)
+    scale = float(np.max(np.abs(ref)))
+    d = ref.ndim - 2
+    face = np.zeros(ref.shape[2:], bool)
+    for a in range(d):
+        sl = [slice(None)] * d
+        for idx in (0, -1):
+            sl[a] = idx
+            face[tuple(sl)] = True
+    print(f"  {what}: max err {err.max():.3e} (faces {err[..., face].max():.3e})"
+          f" vs max|ref| {scale:.3e}", flush=True)
+    assert float(err.max()) <= tol * scale, what
+
+
 def _setup(case, seed=0):
     name, n, ext, levels, reg, K = case
     frames = _frames(n, ext, seed)
@@ -73,10 +90,11 @@ def test_eval_parity(case):
     print(f"eval parity {case[0]}", flush=True)
     out = st.eval(level, K, torch.from_numpy(u))
     ref = oracle.objective(frames, u, K, h, _params(reg))
-    for key in ("J", "D", "S", "P"):
-        assert abs(out[key] - ref[key]) <= 1e-5 * abs(ref["J"]) + 1e-12, key
+    for key in ("J", "D", "S", "P"):       # each to its own size
+        assert abs(out[key] - ref[key]) <= 1e-5 * abs(ref[key]) + 1e-12, key
     g = out["g"].cpu().numpy()
     assert _rel(g, ref["g"]) <= 1e-5
+    _elementwise(g, ref["g"], 1e-5, "g")
     dW = out["dW"].cpu().numpy()
     np.testing.assert_allclose(dW, ref["dW"], rtol=1e-6, atol=1e-6)
 
@@ -94,6 +112,7 @@ def test_hessvec_parity(case):
     dW32 = ref["dW"].astype(np.float32)
     Hv_ref = oracle.hessvec(dW32, v, h, _params(reg))
     assert _rel(hv.cpu().numpy(), Hv_ref) <= 1e-5
+    _elementwise(hv.cpu().numpy(), Hv_ref, 1e-5, "Hv")
     assert vhv == pytest.approx(float(np.sum(v * Hv_ref)), rel=1e-5)
 
 

@@ -24,6 +24,13 @@ def _rel(a, b):
     return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
 
 
+def _elementwise(got, ref, tol, what):
+    err = float(np.max(np.abs(got - ref)))
+    scale = float(np.max(np.abs(ref)))
+    print(f"  {what}: max err {err:.3e} vs max|ref| {scale:.3e}", flush=True)
+    assert err <= tol * scale, what
+
+
 def _small():
     frames, g = synth.config_small(0)
     return frames
@@ -215,14 +222,17 @@ def test_large_level_parity():
     out = st.eval(3, K, torch.from_numpy(u))
     par = oracle.ModelParams(alpha=0.1, reg="curvature")
     ref = oracle.objective(frames, u, K, 1.0, par)
-    assert abs(out["J"] - ref["J"]) <= 1e-5 * abs(ref["J"])
+    for key in ("J", "D", "S", "P"):
+        assert abs(out[key] - ref[key]) <= 1e-5 * abs(ref[key]), key
     assert _rel(out["g"].cpu().numpy(), ref["g"]) <= 1e-5
+    _elementwise(out["g"].cpu().numpy(), ref["g"], 1e-5, "g")
     print("large hessvec", flush=True)
     v = np.random.default_rng(1).standard_normal(ref["g"].shape).astype(
         np.float32)
     hv, _ = st.hessvec(3, K, torch.from_numpy(u), torch.from_numpy(v))
     Hv_ref = oracle.hessvec(ref["dW"].astype(np.float32), v, 1.0, par)
     assert _rel(hv.cpu().numpy(), Hv_ref) <= 1e-5
+    _elementwise(hv.cpu().numpy(), Hv_ref, 1e-5, "Hv")
 
 
 def test_large_volume_level_parity():
@@ -240,14 +250,17 @@ def test_large_volume_level_parity():
     out = st.eval(2, K, torch.from_numpy(u))
     par = oracle.ModelParams(alpha=0.1, reg="curvature")
     ref = oracle.objective(frames, u, K, 1.0, par)
-    assert abs(out["J"] - ref["J"]) <= 1e-5 * abs(ref["J"])
+    for key in ("J", "D", "S", "P"):
+        assert abs(out[key] - ref[key]) <= 1e-5 * abs(ref[key]), key
     assert _rel(out["g"].cpu().numpy(), ref["g"]) <= 1e-5
+    _elementwise(out["g"].cpu().numpy(), ref["g"], 1e-5, "g")
     print("large volume hessvec", flush=True)
     v = np.random.default_rng(2).standard_normal(ref["g"].shape).astype(
         np.float32)
     hv, _ = st.hessvec(2, K, torch.from_numpy(u), torch.from_numpy(v))
     Hv_ref = oracle.hessvec(ref["dW"].astype(np.float32), v, 1.0, par)
     assert _rel(hv.cpu().numpy(), Hv_ref) <= 1e-5
+    _elementwise(hv.cpu().numpy(), Hv_ref, 1e-5, "Hv")
 
 
 def _volume(n, ext, seed):
