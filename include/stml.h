@@ -222,6 +222,37 @@ int stml_hessvec(stml_ctx* ctx, int level, const int* frames, int nk,
 int stml_gn_direction(stml_ctx* ctx, int level, const int* frames, int nk,
                       const float* u_dev, float* delta_dev, int* out_cg);
 
+/* --- evaluation without allocation --------------------------------------
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * objective, gradient and dW/du of stml_eval (same kernels, same results)
+ * on frames the caller holds, without a context or workspace.  Its scratch
+ * (the evaluation's float64 partials, the objective scalars and the frame
+ * list) is one static device array of STML_NOALLOC_SCRATCH_BYTES that each
+ * GPU holds from the first call on it until the process ends.  Calls that
+ * overlap on one GPU (two host threads, or two streams in flight) share
+ * that array and race; each call returns with its stream synchronised.
+ *   opts      : dim, regulariser, alpha, lambda are read (host).
+ *   n, extent : frames and their extent (dim ints, slowest first; host).
+ *   h         : grid spacing of this level (finest = 1).
+ *   frames_dev: [n][extent...] float32 images (device).
+ *   frames    : nk ascending frame indices, the subset K (host).
+ *   u_dev     : [n][dim][extent...] displacements (device).
+ *   out_JDSP  : host, {J, D, S, P}.
+ *   grad_dev, dW_dev: [nk][dim][extent...] outputs (device, required).
+ *   hip_stream: hipStream_t (NULL = default).
+ * Errors: EINVAL (null pointer, options, shape, frame list), ENOMEM (n
+ * above STML_MAX_FRAMES, or an evaluation grid above the scratch's 512
+ * blocks: cannot happen for valid shapes), EDEVICE; the message is in
+ * stml_noalloc_last_error() (per host thread).  Calls no hipMalloc,
+ * hipFree or other allocating routine. */
+#define STML_NOALLOC_SCRATCH_BYTES 66816
+int stml_eval_noalloc(const stml_opts* opts, int n, const int* extent,
+                      double h, const float* frames_dev, const int* frames,
+                      int nk, const float* u_dev, double* out_JDSP,
+                      float* grad_dev, float* dW_dev, void* hip_stream);
+const char* stml_noalloc_last_error(void);
+
 /* --- kernel timing (measurement only) -----------------------------------
  * Each launch of a timed kernel class on the context's stream is bracketed
  * by two HIP events; durations, launch counts and the voxel-frames each

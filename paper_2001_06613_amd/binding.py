@@ -134,6 +134,10 @@ SIGNATURES = {
     "stml_batch_run": (_I, [_P]),
     "stml_set_tuning": (_I, [_P, ctypes.POINTER(stml_tuning)]),
     "stml_get_tuning": (_I, [_P, ctypes.POINTER(stml_tuning)]),
+    "stml_eval_noalloc": (_I, [ctypes.POINTER(stml_opts), _I, _IP,
+                               ctypes.c_double, _P, _IP, _I, _P, _DP, _P, _P,
+                               _P]),
+    "stml_noalloc_last_error": (ctypes.c_char_p, []),
     "stml_timing": (_I, [_P, _I]),
     "stml_timing_every": (_I, [_P, _I, _I]),
     "stml_timing_get": (_I, [_P, _I, _I, _DP,
@@ -200,6 +204,41 @@ def _int_array(vals):
 
 def _ptr(t):
     return ctypes.c_void_p(t.data_ptr())
+
+
+def eval_noalloc(frames, u, K, h=1.0, opts=None, grad=None, dW=None,
+                 stream=None, **kw):
+    """stml_eval_noalloc: objective, gradient and dW/du over the frames K
+    of `frames` ([n][extent...] float32, on the device) at u
+    ([n][dim][extent...]), with no context and no library allocation.
+    grad and dW ([|K|][dim][extent...] float32) are allocated by torch here
+    unless given.  Returns (dict J, D, S, P, grad, dW)."""
+    import torch
+
+    lib = load()
+    o = opts if opts is not None else default_opts(**kw)
+    n, ext = frames.shape[0], tuple(frames.shape[1:])
+    shape = (len(K), len(ext)) + ext
+    if grad is None:
+        grad = torch.empty(shape, dtype=torch.float32, device=frames.device)
+    if dW is None:
+        dW = torch.empty(shape, dtype=torch.float32, device=frames.device)
+    for t, want in ((frames, (n,) + ext), (u, (n, len(ext)) + ext),
+                    (grad, shape), (dW, shape)):
+        if tuple(t.shape) != want or t.dtype != torch.float32 or \
+                not t.is_contiguous() or not t.is_cuda:
+            raise STMLError(STML_EINVAL, f"need a contiguous float32 device "
+                                         f"tensor of shape {want}")
+    s = stream if stream is not None else torch.cuda.current_stream()
+    out = (ctypes.c_double * 4)()
+    rc = lib.stml_eval_noalloc(ctypes.byref(o), n, _int_array(ext), float(h),
+                               _ptr(frames), _int_array(K), len(K), _ptr(u),
+                               out, _ptr(grad), _ptr(dW),
+                               ctypes.c_void_p(s.cuda_stream))
+    if rc != STML_OK:
+        raise STMLError(rc, lib.stml_noalloc_last_error().decode())
+    return {"J": out[0], "D": out[1], "S": out[2], "P": out[3],
+            "g": grad, "dW": dW}
 
 
 class STML:
