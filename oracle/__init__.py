@@ -18,6 +18,9 @@ non-parametric groupwise model for the inner registration:
   algorithm (tridiagonal, O(n)).
 * Sec. 3, eq. (3): optional stopping rule on the change of D.
 * Sec. 4: spatial multilevel data, smoothing in space only.
+* Sec. 2 and Sec. 4 (``affine.py``): the paper's experimental model, one
+  affine-linear map per frame, the correlation-based SqN distance and
+  L-BFGS, with the same schedule acting on the parameters.
 
 Every floating-point quantity is computed in float64 from float32 inputs.
 
