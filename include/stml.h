@@ -60,6 +60,23 @@ extern "C" {
 #define STML_REG_DIFFUSION 0
 #define STML_REG_CURVATURE 1
 
+/* Registration model of a context (stml_opts.model).
+ * FIELD : a displacement field per frame, groupwise SSD, diffusion or
+ *         curvature regulariser, Gauss-Newton with Jacobi-PCG (the instance
+ *         described at the top of this header).
+ * AFFINE: the paper's experimental model (Sec. 2, Sec. 4): one affine-linear
+ *         map per frame, u_k(x) = B_k xi(x) + b_k with xi(x) = (x - c) / R,
+ *         c the centre of the finest grid and R half its largest side, so the
+ *         p = dim^2 + dim parameters theta_k = (B_k row-major, b_k) are in
+ *         pixels and mean the same map on every level; D is the pair sum of
+ *         eq. (1) with the correlation-based distance 1 - rho_ij^2 (the SVD
+ *         based SqN measure with q = 4, Sec. 2), no regulariser, the penalty
+ *         P = lambda h^d sum_x |mean_k u_k(x)|^2 (Sec. 2), minimised by
+ *         L-BFGS (Sec. 2) with the Armijo search; the temporal predictors
+ *         and eq. (3) act on the parameters. */
+#define STML_MODEL_FIELD  0
+#define STML_MODEL_AFFINE 1
+
 #define STML_MAX_FRAMES  256  /* frames per sequence supported by kernels   */
 
 typedef struct stml_ctx stml_ctx;
@@ -89,6 +106,10 @@ typedef struct stml_opts {
                          no convergence exits, eq. (3) off          (0)      */
   int stop_relative;  /* 0: eq. (3) as printed, |D_q - D_{q-1}| <= eps;
                          1: |D_q - D_{q-1}| <= eps |D_q|            (0)      */
+  int model;          /* STML_MODEL_FIELD or STML_MODEL_AFFINE      (0)      */
+  int lbfgs_mem;      /* AFFINE: L-BFGS pairs kept, 1..16 (gn_max is
+                         the iteration cap; alpha, regulariser, cg_* and
+                         predictor do not apply)                    (5)      */
 } stml_opts;
 
 /* Statistics of one registration call (GIR on one subset). */
@@ -197,6 +218,27 @@ int stml_set_prediction(stml_ctx* ctx, int level, const float* z_dev);
  * stml_set_sequence, and entry i. */
 int stml_log_count(const stml_ctx* ctx);
 int stml_get_log(const stml_ctx* ctx, int i, stml_gir_log* out);
+
+/* --- affine model (opts.model = STML_MODEL_AFFINE) -----------------------
+ * Parameters are host arrays [n][p], p = dim^2 + dim, float64, rows
+ * theta_k = (B_k row-major, b_k) in pixels (see STML_MODEL_AFFINE).  On an
+ * affine context stml_get_displacements writes u_k(x) of every frame;
+ * stml_set_displacements, stml_get/set_prediction, stml_eval,
+ * stml_hessvec, stml_gn_direction, learned predictors and batches return
+ * EINVAL; the schedule entry points (predict, register_level, correct,
+ * run) act on the parameters. */
+
+/* Current parameters of `level` into theta_out (host, [n][p]). */
+int stml_get_params(const stml_ctx* ctx, int level, double* theta_out);
+/* Overwrite the current parameters of `level` (resume or test). */
+int stml_set_params(stml_ctx* ctx, int level, const double* theta);
+/* Objective of the affine model at theta (host, [n][p]) over the frames K
+ * (nk ascending indices): out_JDP = {J, D, P}; the gradient wrt the
+ * parameters of the frames of K into grad_out (host, [nk][p], may be NULL).
+ * Errors: EINVAL (also a frame without contrast after warping, whose
+ * correlation is undefined). */
+int stml_eval_params(stml_ctx* ctx, int level, const int* frames, int nk,
+                     const double* theta, double* out_JDP, double* grad_out);
 
 /* --- kernel-level entry points (same conventions) ------------------------
  * frames: host array of nk frame indices (distinct, ascending), the subset K.

@@ -24,6 +24,7 @@ STML_WLINESEARCH = 2
 MAX_FRAMES = 256
 
 REG = {"diffusion": 0, "curvature": 1}
+MODEL = {"field": 0, "affine": 1}
 
 
 class stml_opts(ctypes.Structure):
@@ -46,6 +47,8 @@ class stml_opts(ctypes.Structure):
         ("predictor", ctypes.c_int),
         ("parity_mode", ctypes.c_int),
         ("stop_relative", ctypes.c_int),
+        ("model", ctypes.c_int),
+        ("lbfgs_mem", ctypes.c_int),
     ]
 
 
@@ -105,6 +108,9 @@ SIGNATURES = {
     "stml_set_prediction": (_I, [_P, _I, _P]),
     "stml_log_count": (_I, [_P]),
     "stml_get_log": (_I, [_P, _I, ctypes.POINTER(stml_gir_log)]),
+    "stml_get_params": (_I, [_P, _I, _DP]),
+    "stml_set_params": (_I, [_P, _I, _DP]),
+    "stml_eval_params": (_I, [_P, _I, _IP, _I, _DP, _DP, _DP]),
     "stml_eval": (_I, [_P, _I, _IP, _I, _P, _DP, _P, _P]),
     "stml_hessvec": (_I, [_P, _I, _IP, _I, _P, _P, _P, _DP]),
     "stml_gn_direction": (_I, [_P, _I, _IP, _I, _P, _P, _IP]),
@@ -189,6 +195,8 @@ def default_opts(**kw):
             k = "lambda_"
         if k == "reg":
             k, v = "regulariser", REG[v]
+        if k == "model" and isinstance(v, str):
+            v = MODEL[v]
         if k in ("parity_mode", "stop_relative"):
             v = int(bool(v))
         if not hasattr(o, k):
@@ -380,6 +388,41 @@ class STML:
         self._sync_in()
         return self._check(self.lib.stml_set_prediction(self.ctx, level,
                                                         _ptr(z)))
+
+    # -- affine model: parameters [n][p] (host float64 arrays)
+    @property
+    def n_params(self):
+        return self.dim * self.dim + self.dim
+
+    def get_params(self, level=None):
+        level = self.levels - 1 if level is None else level
+        out = np.zeros((self.n, self.n_params), np.float64)
+        self._check(self.lib.stml_get_params(
+            self.ctx, level, out.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+        return out
+
+    def set_params(self, level, theta):
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        if th.shape != (self.n, self.n_params):
+            raise STMLError(STML_EINVAL, f"need ({self.n}, {self.n_params})")
+        return self._check(self.lib.stml_set_params(
+            self.ctx, level, th.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
+
+    def eval_params(self, level, frames, theta, grad=True):
+        """(dict J, D, P) and the gradient [|K|][p] at theta [n][p]."""
+        th = np.ascontiguousarray(theta, dtype=np.float64)
+        if th.shape != (self.n, self.n_params):
+            raise STMLError(STML_EINVAL, f"need ({self.n}, {self.n_params})")
+        out = (ctypes.c_double * 3)()
+        g = np.zeros((len(frames), self.n_params), np.float64) if grad \
+            else None
+        dp = ctypes.POINTER(ctypes.c_double)
+        self._sync_in()
+        self._check(self.lib.stml_eval_params(
+            self.ctx, level, _int_array(frames), len(frames),
+            th.ctypes.data_as(dp), out,
+            g.ctypes.data_as(dp) if grad else None))
+        return {"J": out[0], "D": out[1], "P": out[2]}, g
 
     def stop_trace(self, level=None):
         """Eq. (3) record of the last run on `level`: (D_q list, stop q or

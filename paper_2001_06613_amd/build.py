@@ -18,8 +18,8 @@ ARCH = "gfx950"
 # scalar or float2 code
 DEVICE_FLAGS = ["-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 
-SOURCES = ["kernels.hip", "cg_tiles.hip", "cnn.hip", "noalloc.hip",
-           "stml.cpp"]
+SOURCES = ["kernels.hip", "cg_tiles.hip", "cnn.hip", "affine.hip",
+           "noalloc.hip", "stml.cpp"]
 
 
 def _run(cmd):

@@ -182,6 +182,75 @@ hipError_t batch_accept(const JobSet& js, int nelem, const double* t,
                         double tol_J, double tol_u, hipStream_t s);
 hipError_t batch_advance(const JobSet& js, int* stop_out, hipStream_t s);
 
+// ------------------------------------------------ affine model (affine.hip)
+//
+// Affine-linear maps per frame with the SqN distance (Sec. 2, Sec. 4):
+// u_k(x) = B_k xi(x) + b_k, xi(x) = (x - c) / R on a level's cell centres.
+struct AffGeom {
+  Geom g;
+  double h, hd, inv_R;
+  double c[3];
+  int d;
+};
+// Objective of the last first-pass evaluation (J = D + P) and a flag for a
+// frame without contrast after warping (zero variance).
+struct AffScal {
+  double J, D, P;
+  int bad, pad;
+};
+// L-BFGS state of one registration (device).
+struct AffState {
+  double J, Jt, slope, t;
+  double rho[16];
+  int npairs, head, iters, accepted, stop, bad;
+};
+// Device buffers of one evaluation.
+struct AffBufs {
+  double* part;     // Gram partials [nb][E]
+  double* tot;      // Gram totals [E]
+  double* mu;       // frame means [|K|]
+  double* Rc;       // dD/dW coefficients [|K|][|K|]
+  double* gpen;     // penalty gradient wrt the mean parameters [p]
+  float* r;         // dD/dW_i per voxel [|K|][N]
+  double* gpart;    // parameter-gradient partials [|K|][p][nb]
+  double* gout;     // gradient [|K|][p]
+  AffScal* sc;
+};
+constexpr int kAffGramBlocks = 256;    // Gram partials per evaluation
+constexpr int kAffPgradBlocks = 64;    // gradient partials per frame
+struct AffShape {
+  int split, groups, E, nb_gram, nb_resid, nb_pgrad;
+  size_t lds_gram, lds_resid;
+};
+AffShape aff_shape(const AffGeom& ag, int nk);
+// J (and with grad the gradient into b.gout) at x + t dv (dv may be null:
+// at x) for the frames K; reuse_gram skips the first pass, whose totals
+// (b.tot) are then those of the same point.
+hipError_t launch_aff_objective(const float* T, const int* K, int nk,
+                                const double* x, const double* dv, double t,
+                                const AffGeom& ag, double lam, AffBufs b,
+                                bool grad, bool reuse_gram, hipStream_t s);
+hipError_t launch_aff_state_init(AffState* st, const AffScal* sc,
+                                 hipStream_t s);
+hipError_t launch_aff_direction(AffState* st, const double* g, double* d,
+                                const double* S, const double* Y, int nP,
+                                int mem, hipStream_t s);
+hipError_t launch_aff_accept(AffState* st, const AffScal* sc, double t,
+                             double c1, hipStream_t s);
+hipError_t launch_aff_update(AffState* st, double* x, const double* d,
+                             double* g, const double* gn, double* S,
+                             double* Y, int nP, int mem, double tol_J,
+                             double tol_u, hipStream_t s);
+hipError_t launch_aff_gather(double* x, const double* theta, const int* K,
+                             int nk, int P, bool scatter, hipStream_t s);
+hipError_t launch_aff_linear_predict(double* Y, double* Z, LinTab tab, int n,
+                                     int P, hipStream_t s);
+hipError_t launch_aff_ls_predict(double* Y, double* Z, ThomasTab tab, int n,
+                                 int P, double beta, double* dp,
+                                 hipStream_t s);
+hipError_t launch_aff_field(const double* theta, int n, const AffGeom& ag,
+                            float* u, hipStream_t s);
+
 // Capacity of a learned-predictor net (cnn.hip): the batch it was created
 // for and the pixels a batch may hold in total (frames x pixels per frame).
 void net_capacity(const stml_net* n, int* max_batch, long long* max_pixels);

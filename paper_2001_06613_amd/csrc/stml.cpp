@@ -79,6 +79,21 @@ struct stml_ctx {
     int used = -1;
     double Jp = NAN, Jl = NAN;
   } pick;                                // start guess of the next GIR
+  // affine model: parameters [n][P] per level (estimate Y, start guess Z),
+  // the evaluation's buffers and the L-BFGS state and vectors ([n P])
+  int npar = 0;
+  struct AffLevel {
+    double* Y;
+    double* Z;
+  };
+  std::vector<AffLevel> alv;
+  AffBufs ab{};
+  double *ax = nullptr, *agr = nullptr, *ad = nullptr, *agn = nullptr,
+         *aS = nullptr, *aY = nullptr, *aest = nullptr, *anow = nullptr,
+         *adp = nullptr;
+  AffState* ast = nullptr;
+  AffState* hast = nullptr;             // pinned host mirrors
+  AffScal* hasc = nullptr;
   std::vector<stml_gir_log> logs;
   // eq. (3) of the last stml_run: D over all frames per q, and the q at
   // which each level stopped (-1: not stopped)
@@ -133,6 +148,9 @@ bool opts_valid(const stml_opts* o) {
          o->eps_stop >= 0 && o->gn_max >= 0 && o->cg_max >= 0 &&
          o->ls_max >= 0 && o->ls_max <= 60 &&
          (o->stop_relative == 0 || o->stop_relative == 1) &&
+         (o->model == STML_MODEL_FIELD ||
+          (o->model == STML_MODEL_AFFINE && o->predictor == 0 &&
+           o->lbfgs_mem >= 1 && o->lbfgs_mem <= 16)) &&
          (o->predictor == 0 || o->predictor == 1);
 }
 
@@ -166,11 +184,62 @@ long long voxels(const std::vector<int>& e) {
 }
 
 // Walk the workspace: returns the byte size; assigns pointers if base.
+size_t layout_affine(stml_ctx* c, Layout& lo) {
+  const int n = c->n, P = c->npar;
+  const size_t nP = (size_t)n * P;
+  c->alv.resize(c->L);
+  for (int l = 0; l < c->L; ++l) {
+    c->lv[l].T = lo.take<float>((size_t)n * c->N[l]);
+    c->lv[l].Y = c->lv[l].Z = nullptr;
+    c->alv[l].Y = lo.take<double>(nP);
+    c->alv[l].Z = lo.take<double>(nP);
+  }
+  const size_t E = (size_t)(n + 1) * (n + 2) / 2;
+  c->ab.part = lo.take<double>((size_t)kAffGramBlocks * E);
+  c->ab.tot = lo.take<double>(E);
+  c->ab.mu = lo.take<double>(n);
+  c->ab.Rc = lo.take<double>((size_t)n * n);
+  c->ab.gpen = lo.take<double>(16);
+  c->ab.r = lo.take<float>((size_t)n * c->N[c->L - 1]);
+  c->ab.gpart = lo.take<double>(nP * kAffPgradBlocks);
+  c->ab.gout = nullptr;                      // set per evaluation
+  c->ab.sc = lo.take<AffScal>(1);
+  c->ax = lo.take<double>(nP);
+  c->agr = lo.take<double>(nP);
+  c->ad = lo.take<double>(nP);
+  c->agn = lo.take<double>(nP);
+  c->aest = lo.take<double>(nP);
+  c->anow = lo.take<double>(nP);
+  c->adp = lo.take<double>(nP);
+  c->aS = lo.take<double>(nP * c->o.lbfgs_mem);
+  c->aY = lo.take<double>(nP * c->o.lbfgs_mem);
+  c->ast = lo.take<AffState>(1);
+  return lo.off;
+}
+
 size_t layout(stml_ctx* c, char* base) {
   Layout lo;
   lo.base = base;
   const int n = c->n, D = c->d;
   c->lv.resize(c->L);
+  if (c->o.model == STML_MODEL_AFFINE) {
+    layout_affine(c, lo);
+    c->sc = lo.take<Scal>(1);
+    c->gnlog = lo.take<GNLog>(1);
+    c->kbuf = lo.take<int>(STML_MAX_FRAMES);
+    c->qt.resize(c->T1);
+    for (int q = 0; q < c->T1; ++q) {
+      c->qt[q].K = lo.take<int>(n);
+      c->qt[q].lin.left = lo.take<int>(n);
+      c->qt[q].lin.right = lo.take<int>(n);
+      c->qt[q].lin.wl = lo.take<double>(n);
+      c->qt[q].lin.wr = lo.take<double>(n);
+      c->qt[q].thomas.invp = lo.take<double>(n);
+      c->qt[q].thomas.cp = lo.take<double>(n);
+      c->qt[q].thomas.mask = lo.take<int>(n);
+    }
+    return lo.off;
+  }
   for (int l = 0; l < c->L; ++l) {
     size_t NL = (size_t)c->N[l];
     c->lv[l].T = lo.take<float>((size_t)n * NL);
@@ -233,10 +302,11 @@ bool setup_dims(stml_ctx* c, const stml_opts* o, int n, const int* extent) {
   // compact vectors index elements with 64-bit offsets, but the element
   // kernels decode the frame index from 32-bit rows
   if ((double)n * o->dim * (double)c->N[c->L - 1] > 2.0e9) return false;
+  c->npar = o->dim * o->dim + o->dim;
   // the Hessian product runs one block per 64 x 4 tile (3-D: per column of
   // kHv3X x kHv3Y x kHv3Z) at least, and its partials must fit one
   // reduction region
-  {
+  if (o->model == STML_MODEL_FIELD) {
     const std::vector<int>& e = c->ext[c->L - 1];
     long long tiles =
         o->dim == 2
@@ -673,7 +743,153 @@ int learned_predict(stml_ctx* c, int level, int q_next) {
   return STML_OK;
 }
 
+// ------------------------------------------------------------ affine model
+
+AffGeom aff_geom(const stml_ctx* c, int level) {
+  AffGeom ag;
+  ag.g = geom_of(c, level);
+  ag.h = c->h[level];
+  ag.d = c->d;
+  ag.hd = c->d == 3 ? ag.h * ag.h * ag.h : ag.h * ag.h;
+  const std::vector<int>& ef = c->ext[c->L - 1];
+  int mx = 0;
+  for (int a = 0; a < 3; ++a) ag.c[a] = 0.0;
+  for (int a = 0; a < c->d; ++a) {
+    ag.c[a] = ef[a] / 2.0;
+    mx = std::max(mx, ef[a]);
+  }
+  ag.inv_R = 1.0 / (mx / 2.0);
+  return ag;
+}
+
+int read_aff(stml_ctx* c) {
+  HIP_OK(hipMemcpyAsync(c->hast, c->ast, sizeof(AffState),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(hipMemcpyAsync(c->hasc, c->ab.sc, sizeof(AffScal),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  return STML_OK;
+}
+
+// Objective (and gradient into gout) of the frames Kdev at x + t dv.
+int aff_objective(stml_ctx* c, int level, const int* Kdev, int nk,
+                  const double* x, const double* dv, double t, double* gout,
+                  bool reuse_gram) {
+  AffBufs b = c->ab;
+  b.gout = gout;
+  HIP_OK(launch_aff_objective(c->lv[level].T, Kdev, nk, x, dv, t,
+                              aff_geom(c, level), c->o.lambda, b,
+                              gout != nullptr, reuse_gram, c->stream));
+  return STML_OK;
+}
+
+// GIR(level, K_q) of the affine model: L-BFGS on the parameters of K_q,
+// every decision on the device; the host waits once per trial step.
+int aff_register(stml_ctx* c, int level, int q, stml_gir_log* log) {
+  const stml_opts& o = c->o;
+  const int nk = (int)c->K[q].size(), P = c->npar, nP = nk * P;
+  const int* Kd = c->qt[q].K;
+  const int mem = o.lbfgs_mem;
+  double* theta = c->alv[level].Y;
+  std::memset(log, 0, sizeof *log);
+  log->n_frames = nk;
+  HIP_OK(launch_aff_gather(c->ax, theta, Kd, nk, P, false, c->stream));
+  int rc = aff_objective(c, level, Kd, nk, c->ax, nullptr, 0.0, c->agr,
+                         false);
+  if (rc) return rc;
+  HIP_OK(launch_aff_state_init(c->ast, c->ab.sc, c->stream));
+  rc = read_aff(c);
+  if (rc) return rc;
+  if (c->hast->bad)
+    return fail(c, STML_EINVAL, "a frame has no contrast after warping");
+  log->J0 = log->J = c->hast->J;
+  int status = STML_OK;
+  for (int it = 0; it < o.gn_max; ++it) {
+    HIP_OK(launch_aff_direction(c->ast, c->agr, c->ad, c->aS, c->aY, nP, mem,
+                                c->stream));
+    bool accepted = false;
+    double t = 1.0;
+    for (int ti = 0; ti <= o.ls_max; ++ti) {
+      t = std::ldexp(1.0, -ti);
+      rc = aff_objective(c, level, Kd, nk, c->ax, c->ad, t, nullptr, false);
+      if (rc) return rc;
+      HIP_OK(launch_aff_accept(c->ast, c->ab.sc, t, o.c1, c->stream));
+      rc = read_aff(c);
+      if (rc) return rc;
+      if (c->hast->bad)
+        return fail(c, STML_EINVAL, "a frame has no contrast after warping");
+      if (c->hast->accepted) {
+        accepted = true;
+        break;
+      }
+    }
+    if (!accepted) {
+      status = STML_WLINESEARCH;
+      break;
+    }
+    rc = aff_objective(c, level, Kd, nk, c->ax, c->ad, t, c->agn, true);
+    if (rc) return rc;
+    HIP_OK(launch_aff_update(c->ast, c->ax, c->ad, c->agr, c->agn, c->aS,
+                             c->aY, nP, mem, o.tol_J, o.tol_u, c->stream));
+    rc = read_aff(c);
+    if (rc) return rc;
+    if (it < 64) {
+      log->step[it] = t;
+      log->J_iter[it] = c->hast->J;
+    }
+    log->gn_iterations += 1;
+    log->J = c->hast->J;
+    if (!o.parity_mode && c->hast->stop) break;
+  }
+  HIP_OK(launch_aff_gather(c->ax, theta, Kd, nk, P, true, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  log->D = c->hasc->D;
+  log->P = c->hasc->P;
+  log->S = 0.0;
+  log->status = status;
+  log->predictor = q > 0 ? 0 : -1;
+  return status;
+}
+
+int aff_predict(stml_ctx* c, int level, int q_next) {
+  const int n = c->n, P = c->npar;
+  const size_t bytes = (size_t)n * P * sizeof(double);
+  stml_ctx::AffLevel& a = c->alv[level];
+  if (q_next == 0) {
+    if (level == 0)
+      HIP_OK(hipMemsetAsync(a.Z, 0, bytes, c->stream));
+    else   // the same parameters mean the same map on every level
+      HIP_OK(hipMemcpyAsync(a.Z, c->alv[level - 1].Y, bytes,
+                            hipMemcpyDeviceToDevice, c->stream));
+    HIP_OK(hipMemcpyAsync(a.Y, a.Z, bytes, hipMemcpyDeviceToDevice,
+                          c->stream));
+  } else if (level == 0) {
+    HIP_OK(launch_aff_linear_predict(a.Y, a.Z, c->qt[q_next - 1].lin, n, P,
+                                     c->stream));
+  } else {
+    HIP_OK(launch_aff_ls_predict(a.Y, a.Z, c->qt[q_next - 1].thomas, n, P,
+                                 c->o.beta, c->adp, c->stream));
+  }
+  HIP_OK(hipStreamSynchronize(c->stream));
+  return STML_OK;
+}
+
+// D over all frames at the parameters U ([n][P], device).
+int aff_all_frame_D(stml_ctx* c, int level, const double* U, double* out) {
+  const int T = c->T1 - 1;
+  int rc = aff_objective(c, level, c->qt[T].K, c->n, U, nullptr, 0.0,
+                         nullptr, false);
+  if (rc) return rc;
+  rc = read_aff(c);
+  if (rc) return rc;
+  if (c->hasc->bad)
+    return fail(c, STML_EINVAL, "a frame has no contrast after warping");
+  *out = c->hasc->D;
+  return STML_OK;
+}
+
 int do_predict(stml_ctx* c, int level, int q_next) {
+  if (c->o.model == STML_MODEL_AFFINE) return aff_predict(c, level, q_next);
   const int n = c->n, D = c->d;
   LevelBufs& b = c->lv[level];
   const size_t cnt = (size_t)n * D * c->N[level];
@@ -713,6 +929,10 @@ int record_gir(stml_ctx* c, int level, int q, int rc, stml_gir_log& log);
 
 int do_register(stml_ctx* c, int level, int q) {
   stml_gir_log log;
+  if (c->o.model == STML_MODEL_AFFINE) {
+    int rc = aff_register(c, level, q, &log);
+    return record_gir(c, level, q, rc, log);
+  }
   int rc = gauss_newton(c, level, c->qt[q].K, (int)c->K[q].size(),
                         c->lv[level].Y, &log);
   return record_gir(c, level, q, rc, log);
@@ -774,6 +994,9 @@ void stml_default_opts(stml_opts* o) {
   o->tol_u = 1e-2;
   o->predictor = 0;
   o->parity_mode = 0;
+  o->stop_relative = 0;
+  o->model = STML_MODEL_FIELD;
+  o->lbfgs_mem = 5;
 }
 
 size_t stml_workspace_bytes(const stml_opts* o, int n, const int* extent) {
@@ -804,7 +1027,12 @@ int stml_create(const stml_opts* o, int n, const int* extent, void* stream,
                     hipHostMallocDefault) != hipSuccess ||
       hipHostMalloc((void**)&c->hlog,
                     (o->gn_max > 0 ? o->gn_max : 1) * sizeof(GNLog),
-                    hipHostMallocDefault) != hipSuccess) {
+                    hipHostMallocDefault) != hipSuccess ||
+      (o->model == STML_MODEL_AFFINE &&
+       (hipHostMalloc((void**)&c->hast, sizeof(AffState),
+                      hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc((void**)&c->hasc, sizeof(AffScal),
+                      hipHostMallocDefault) != hipSuccess))) {
     stml_destroy(c);
     return STML_EDEVICE;
   }
@@ -825,6 +1053,8 @@ void stml_destroy(stml_ctx* c) {
   if (c->hsc) (void)hipHostFree(c->hsc);
   if (c->hk) (void)hipHostFree(c->hk);
   if (c->hlog) (void)hipHostFree(c->hlog);
+  if (c->hast) (void)hipHostFree(c->hast);
+  if (c->hasc) (void)hipHostFree(c->hasc);
   delete c;
 }
 
@@ -848,6 +1078,12 @@ int stml_set_sequence(stml_ctx* c, const float* frames_dev) {
                           c->stream));
   }
   for (int l = 0; l < L; ++l) {
+    if (c->o.model == STML_MODEL_AFFINE) {
+      size_t pc = (size_t)n * c->npar * sizeof(double);
+      HIP_OK(hipMemsetAsync(c->alv[l].Y, 0, pc, c->stream));
+      HIP_OK(hipMemsetAsync(c->alv[l].Z, 0, pc, c->stream));
+      continue;
+    }
     size_t vc = (size_t)n * D * c->N[l];
     HIP_OK(launch_fill(c->lv[l].Y, vc, 0.0f, c->stream));
     HIP_OK(launch_fill(c->lv[l].Z, vc, 0.0f, c->stream));
@@ -935,6 +1171,44 @@ int stml_run(stml_ctx* c) {
     double D_prev = 0.0;
     const size_t cnt = (size_t)c->n * c->d * c->N[level];
     for (int q = 0; q < T; ++q) {
+      if (c->o.model == STML_MODEL_AFFINE) {
+        stml_ctx::AffLevel& a = c->alv[level];
+        const size_t pb = (size_t)c->n * c->npar * sizeof(double);
+        if (eq3)
+          HIP_OK(hipMemcpyAsync(c->anow, a.Y, pb, hipMemcpyDeviceToDevice,
+                                c->stream));
+        rc = do_predict(c, level, q + 1);
+        if (rc < 0) return rc;
+        if (eq3) {
+          // estimate = prediction, with the frames of K_q as registered
+          const int nq = (int)c->K[q].size();
+          HIP_OK(hipMemcpyAsync(c->aest, a.Y, pb, hipMemcpyDeviceToDevice,
+                                c->stream));
+          HIP_OK(launch_aff_gather(c->ax, c->anow, c->qt[q].K, nq, c->npar,
+                                   false, c->stream));
+          HIP_OK(launch_aff_gather(c->ax, c->aest, c->qt[q].K, nq, c->npar,
+                                   true, c->stream));
+          double Dq;
+          rc = aff_all_frame_D(c, level, c->aest, &Dq);
+          if (rc) return rc;
+          c->stop_trace[level].push_back(Dq);
+          const double tol =
+              c->o.eps_stop * (c->o.stop_relative ? std::fabs(Dq) : 1.0);
+          if (have_prev && std::fabs(Dq - D_prev) <= tol) {
+            HIP_OK(hipMemcpyAsync(a.Y, c->aest, pb, hipMemcpyDeviceToDevice,
+                                  c->stream));
+            HIP_OK(hipStreamSynchronize(c->stream));
+            c->stop_q[level] = q;
+            break;
+          }
+          D_prev = Dq;
+          have_prev = true;
+        }
+        rc = do_register(c, level, q + 1);
+        if (rc < 0) return rc;
+        if (rc > 0) warn = rc;
+        continue;
+      }
       LevelBufs& b = c->lv[level];
       if (eq3) {
         // keep the registered frames of K_q for the all-frame estimate
@@ -1006,16 +1280,30 @@ static int copy_field(stml_ctx* c, int level, float* dst, const float* src) {
   return STML_OK;
 }
 
+static int field_only(stml_ctx* c) {
+  if (c->o.model != STML_MODEL_FIELD)
+    return fail(c, STML_EINVAL, "not available for the affine model");
+  return STML_OK;
+}
+
 int stml_get_displacements(const stml_ctx* cc, int level, float* u) {
   stml_ctx* c = const_cast<stml_ctx*>(cc);
   if (!c) return STML_EINVAL;
   if (check_level(c, level)) return STML_EINVAL;
+  if (c->o.model == STML_MODEL_AFFINE) {
+    if (!u) return fail(c, STML_EINVAL, "null pointer");
+    HIP_OK(launch_aff_field(c->alv[level].Y, c->n, aff_geom(c, level), u,
+                            c->stream));
+    HIP_OK(hipStreamSynchronize(c->stream));
+    return STML_OK;
+  }
   return copy_field(c, level, u, c->lv[level].Y);
 }
 
 int stml_set_displacements(stml_ctx* c, int level, const float* u) {
   if (!c) return STML_EINVAL;
   if (check_level(c, level)) return STML_EINVAL;
+  if (field_only(c)) return STML_EINVAL;
   return copy_field(c, level, c->lv[level].Y, u);
 }
 
@@ -1023,13 +1311,83 @@ int stml_get_prediction(const stml_ctx* cc, int level, float* z) {
   stml_ctx* c = const_cast<stml_ctx*>(cc);
   if (!c) return STML_EINVAL;
   if (check_level(c, level)) return STML_EINVAL;
+  if (field_only(c)) return STML_EINVAL;
   return copy_field(c, level, z, c->lv[level].Z);
 }
 
 int stml_set_prediction(stml_ctx* c, int level, const float* z) {
   if (!c) return STML_EINVAL;
   if (check_level(c, level)) return STML_EINVAL;
+  if (field_only(c)) return STML_EINVAL;
   return copy_field(c, level, c->lv[level].Z, z);
+}
+
+int stml_get_params(const stml_ctx* cc, int level, double* theta) {
+  stml_ctx* c = const_cast<stml_ctx*>(cc);
+  if (!c) return STML_EINVAL;
+  if (check_level(c, level)) return STML_EINVAL;
+  if (c->o.model != STML_MODEL_AFFINE)
+    return fail(c, STML_EINVAL, "parameters exist for the affine model only");
+  if (!theta) return fail(c, STML_EINVAL, "null pointer");
+  HIP_OK(hipMemcpyAsync(theta, c->alv[level].Y,
+                        (size_t)c->n * c->npar * sizeof(double),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  return STML_OK;
+}
+
+int stml_set_params(stml_ctx* c, int level, const double* theta) {
+  if (!c) return STML_EINVAL;
+  if (check_level(c, level)) return STML_EINVAL;
+  if (c->o.model != STML_MODEL_AFFINE)
+    return fail(c, STML_EINVAL, "parameters exist for the affine model only");
+  if (!theta) return fail(c, STML_EINVAL, "null pointer");
+  for (size_t i = 0; i < (size_t)c->n * c->npar; ++i)
+    if (!std::isfinite(theta[i]))
+      return fail(c, STML_EINVAL, "non-finite parameter");
+  HIP_OK(hipMemcpyAsync(c->alv[level].Y, theta,
+                        (size_t)c->n * c->npar * sizeof(double),
+                        hipMemcpyHostToDevice, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  return STML_OK;
+}
+
+int stml_eval_params(stml_ctx* c, int level, const int* frames, int nk,
+                     const double* theta, double* out, double* grad) {
+  if (!c) return STML_EINVAL;
+  int rc = check_level(c, level);
+  if (rc) return rc;
+  if (c->o.model != STML_MODEL_AFFINE)
+    return fail(c, STML_EINVAL, "parameters exist for the affine model only");
+  if (!c->have_seq) return fail(c, STML_ESTATE, "no sequence");
+  if (!theta || !out) return fail(c, STML_EINVAL, "null pointer");
+  rc = stage_frames(c, frames, nk);
+  if (rc) return rc;
+  const int P = c->npar;
+  std::vector<double> xk((size_t)nk * P);
+  for (int j = 0; j < nk; ++j)
+    for (int i = 0; i < P; ++i) {
+      const double v = theta[(size_t)frames[j] * P + i];
+      if (!std::isfinite(v)) return fail(c, STML_EINVAL, "non-finite parameter");
+      xk[(size_t)j * P + i] = v;
+    }
+  HIP_OK(hipMemcpyAsync(c->ax, xk.data(), xk.size() * sizeof(double),
+                        hipMemcpyHostToDevice, c->stream));
+  rc = aff_objective(c, level, c->kbuf, nk, c->ax, nullptr, 0.0,
+                     grad ? c->agr : nullptr, false);
+  if (rc) return rc;
+  if (grad)
+    HIP_OK(hipMemcpyAsync(grad, c->agr, xk.size() * sizeof(double),
+                          hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(hipMemcpyAsync(c->hasc, c->ab.sc, sizeof(AffScal),
+                        hipMemcpyDeviceToHost, c->stream));
+  HIP_OK(hipStreamSynchronize(c->stream));
+  if (c->hasc->bad)
+    return fail(c, STML_EINVAL, "a frame has no contrast after warping");
+  out[0] = c->hasc->J;
+  out[1] = c->hasc->D;
+  out[2] = c->hasc->P;
+  return STML_OK;
 }
 
 int stml_log_count(const stml_ctx* c) {
@@ -1045,6 +1403,7 @@ int stml_get_log(const stml_ctx* c, int i, stml_gir_log* out) {
 int stml_eval(stml_ctx* c, int level, const int* frames, int nk,
               const float* u, double* out, float* grad, float* dW) {
   if (!c) return STML_EINVAL;
+  if (field_only(c)) return STML_EINVAL;
   int rc = check_level(c, level);
   if (rc) return rc;
   if (!c->have_seq) return fail(c, STML_ESTATE, "no sequence");
@@ -1068,6 +1427,7 @@ int stml_eval(stml_ctx* c, int level, const int* frames, int nk,
 int stml_hessvec(stml_ctx* c, int level, const int* frames, int nk,
                  const float* u, const float* v, float* hv, double* vHv) {
   if (!c) return STML_EINVAL;
+  if (field_only(c)) return STML_EINVAL;
   int rc = check_level(c, level);
   if (rc) return rc;
   if (!c->have_seq) return fail(c, STML_ESTATE, "no sequence");
@@ -1090,6 +1450,7 @@ int stml_hessvec(stml_ctx* c, int level, const int* frames, int nk,
 int stml_gn_direction(stml_ctx* c, int level, const int* frames, int nk,
                       const float* u, float* delta, int* out_cg) {
   if (!c) return STML_EINVAL;
+  if (field_only(c)) return STML_EINVAL;
   int rc = check_level(c, level);
   if (rc) return rc;
   if (!c->have_seq) return fail(c, STML_ESTATE, "no sequence");
@@ -1114,6 +1475,7 @@ int stml_gn_direction(stml_ctx* c, int level, const int* frames, int nk,
 
 int stml_set_predictor_net(stml_ctx* c, stml_net* net) {
   if (!c) return STML_EINVAL;
+  if (field_only(c)) return STML_EINVAL;
   if (net && net_dim(net) != c->d)
     return fail(c, STML_EINVAL, "learned predictor of another dimension");
   if (net && !c->ureg)
@@ -1376,7 +1738,8 @@ int stml_batch_create(stml_ctx* const* ctxs, int count, void* stream,
   if (!a) return STML_EINVAL;
   for (int j = 0; j < count; ++j) {
     const stml_ctx* c = ctxs[j];
-    if (!c || c->d != a->d || c->L != a->L || c->T1 != a->T1 ||
+    if (!c || c->o.model != STML_MODEL_FIELD || c->d != a->d ||
+        c->L != a->L || c->T1 != a->T1 ||
         c->o.regulariser != a->o.regulariser || c->o.gn_max != a->o.gn_max ||
         c->o.cg_max != a->o.cg_max || c->o.ls_max != a->o.ls_max ||
         c->o.parity_mode != a->o.parity_mode || c->o.c1 != a->o.c1 ||
