@@ -476,6 +476,148 @@ def pmc_probe(st, fr):
     print(json.dumps({"pmc_probe": True, "copy_bytes": COPY_BYTES}))
 
 
+FP64_PEAK_TFS = 78.6           # MI355X float64 vector (and matrix) peak
+AFFINE = dict(n=129, extent=(225, 80, 40), n_spatial=3, n_temporal=4,
+              lam=1e-3, beta=1e-5, gn_max=20, max_disp=4.0, seed=60)
+
+
+def _affine_frames():
+    from paper_2001_06613_amd import synth
+
+    a = AFFINE
+    return synth.affine_sequence(a["n"], a["extent"], a["max_disp"],
+                                 a["seed"], workers=16)[0]
+
+
+def _affine_opts(n_temporal, eps=0.0):
+    from paper_2001_06613_amd.binding import default_opts
+
+    a = AFFINE
+    return default_opts(dim=3, model="affine", n_spatial=a["n_spatial"],
+                        n_temporal=n_temporal, lam=a["lam"], beta=a["beta"],
+                        gn_max=a["gn_max"], eps_stop=eps,
+                        stop_relative=eps > 0)
+
+
+def affine_eval_rate(st, reps=20):
+    """Objective passes (warp + Gram matrix + SqN) over all 129 frames of the
+    finest level: time per pass, voxel-frames per second, and the Gram
+    kernel's float64 rate (2 E N flops per pass, E = (|K|+1)(|K|+2)/2
+    entries of the Gram matrix of the frames and a row of ones) against the
+    float64 peak; the same with the gradient (two more passes)."""
+    import torch
+
+    a = AFFINE
+    n = a["n"]
+    lf = a["n_spatial"] - 1
+    K = list(range(n))
+    theta = st.get_params(lf)
+    N = float(np.prod(a["extent"]))
+    out = {}
+    for grad in (False, True):
+        st.eval_params(lf, K, theta, grad=grad)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            st.eval_params(lf, K, theta, grad=grad)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out["with_gradient" if grad else "objective"] = {
+            "ms": round(1e3 * dt, 3),
+            "Gvf_s": round(n * N / dt / 1e9, 2)}
+    E = (n + 1) * (n + 2) / 2
+    flops = 2.0 * E * N
+    tf = flops / (out["objective"]["ms"] * 1e-3) / 1e12
+    out["gram"] = {"flops_per_pass": flops, "TFLOPs": round(tf, 2),
+                   "peak": FP64_PEAK_TFS, "frac_upper_bound": round(
+                       tf / FP64_PEAK_TFS, 4),
+                   "note": "objective pass time (warp, Gram, totals, "
+                           "finalize, parameter copies) taken as the Gram "
+                           "kernel's: a lower bound of its rate"}
+    return out
+
+
+def affine_comparison(frames, log):
+    """The paper's experimental model (affine maps per frame, the SqN
+    distance, L-BFGS) on the grid sizes of its Table 1 dataset D2: 129
+    frames of 225x80x40 volumes, 3 spatial levels (57x20x10, 113x40x20,
+    225x80x40), |K_0| = 17, |K_1| = 33 (4 temporal levels), synthetic affine
+    motion of at most 4 px.  SpML (one temporal level) against STML (eq. (2)
+    on finer levels) and STML with eq. (3) (relative 1e-3); L-BFGS with at
+    most 20 iterations and the convergence test per registration.  Columns
+    as in Table 1: run time, reduction of D from the unregistered frames
+    (all frames, finest level), relative difference of the displacements
+    (STML vs SpML)."""
+    import torch
+    from paper_2001_06613_amd.binding import STML
+
+    a = AFFINE
+    n, ext = a["n"], a["extent"]
+    fr = torch.from_numpy(frames).cuda()
+    lf = a["n_spatial"] - 1
+    res, disp = {}, {}
+    D0 = None
+    for name, nt, eps in (("spml", 1, 0.0), ("stml", a["n_temporal"], 0.0),
+                          ("stml_eq3", a["n_temporal"], 1e-3)):
+        st = STML(n, ext, opts=_affine_opts(nt, eps))
+        ts = []
+        for _ in range(2):
+            st.set_sequence(fr)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st.run()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        logs = st.logs()
+        theta = st.get_params(lf)
+        if D0 is None:
+            D0 = st.eval_params(lf, list(range(n)),
+                                np.zeros_like(theta), grad=False)[0]["D"]
+        D = st.eval_params(lf, list(range(n)), theta, grad=False)[0]["D"]
+        disp[name] = st.get_displacements(lf).cpu().numpy()
+        res[name] = {"wall_ms": round(1e3 * min(ts), 1),
+                     "registrations": len(logs),
+                     "lbfgs_iterations": sum(lg["gn"] for lg in logs),
+                     "D_reduction_pct": round(100.0 * (D0 - D) / D0, 2)}
+        if name == "stml":
+            res["eval_rate"] = affine_eval_rate(st)
+        st.close()
+        log(f"affine: {name} done")
+    ref = disp["spml"]
+    for name in ("stml", "stml_eq3"):
+        res[name]["rel_diff_y_vs_spml_pct"] = round(
+            100.0 * float(np.linalg.norm(disp[name] - ref) /
+                          np.linalg.norm(ref)), 2)
+        res[name]["speedup_vs_spml"] = round(
+            res["spml"]["wall_ms"] / res[name]["wall_ms"], 3)
+    res["workload"] = ("129 frames x 225x80x40 (Table 1 D2 grid sizes), "
+                       "affine motion <= 4 px, 3 spatial x 4 temporal "
+                       "levels, SqN distance, lambda 1e-3, L-BFGS <= 20")
+    res["paper"] = ("Table 1 D2 (affine, SqN, L-BFGS on private 4D-OCT "
+                    "data, hardware not stated): SpML 7681 s, STML 3035 s "
+                    "(2.5x)")
+    return res
+
+
+def affine_probe():
+    """A few objective and gradient passes of the affine model at full size
+    (129 x 225x80x40), for profiler runs."""
+    import torch
+    from paper_2001_06613_amd.binding import STML
+
+    a = AFFINE
+    frames = _affine_frames()
+    st = STML(a["n"], a["extent"], opts=_affine_opts(1))
+    st.set_sequence(torch.from_numpy(frames).cuda())
+    lf = a["n_spatial"] - 1
+    K = list(range(a["n"]))
+    theta = np.zeros((a["n"], 12))
+    for grad in (False, True, False, True):
+        st.eval_params(lf, K, theta, grad=grad)
+    torch.cuda.synchronize()
+    print(json.dumps({"affine_probe": True}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -492,7 +634,14 @@ def main():
                     help="time the oracle's whole schedule (CPU only)")
     ap.add_argument("--pmc-probe", action="store_true",
                     help="one solve and a copy of known size (counter runs)")
+    ap.add_argument("--no-affine", action="store_true",
+                    help="skip the paper's affine SqN / L-BFGS model block")
+    ap.add_argument("--affine-probe", action="store_true",
+                    help="a few affine evaluations at full size (profiler)")
     args = ap.parse_args()
+    if args.affine_probe:
+        affine_probe()
+        return
     if args.oracle_full:
         oracle_full()
         return
@@ -525,6 +674,10 @@ def main():
         log("volume: sequences generated")
     if not args.pmc_probe and not args.no_learned:
         learned_seqs = list(learned.generate(range(20000, 20004), workers=4))
+    affine_frames = None
+    if not args.pmc_probe and not args.no_affine:
+        affine_frames = _affine_frames()
+        log("affine: sequence generated")
 
     import torch
     from paper_2001_06613_amd.binding import STML, default_opts
@@ -620,7 +773,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32 storage / f64 accumulate",
         "data": "synthetic",
         "config": {
             "workload": "STML solve, 64 frames x 256x256 OCT-like phantom, "
@@ -666,6 +819,8 @@ def main():
         if volume_seqs is not None:
             out["multilevel"]["volume"] = multilevel_comparison(
                 volume_seqs[0], 3, log, 1)
+    if affine_frames is not None:
+        out["affine"] = affine_comparison(affine_frames, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frames)
     print(json.dumps(out))

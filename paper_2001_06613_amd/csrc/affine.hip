@@ -78,13 +78,39 @@ __device__ __forceinline__ void aff_stage_params(const double* __restrict__ x,
     th[i] = dv ? x[i] + t * dv[i] : x[i];
 }
 
+// Voxel geometry of one tile (cell indices and xi), once per tile in LDS,
+// so that the warps of the tile's frames do not redo the index division.
+template <int D>
+struct AffTileGeo {
+  int c[D][kAffV];
+  double xi[D][kAffV];
+};
+
+template <int D>
+__device__ __forceinline__ void aff_tile_geo(const AffGeom& ag, long long v0,
+                                             AffTileGeo<D>& tg) {
+  if (threadIdx.x < kAffV) {
+    const long long vox = v0 + threadIdx.x;
+    Pos<D> pos = make_pos<D>(ag.g, vox < ag.g.N ? vox : ag.g.N - 1);
+    double xi[D];
+    aff_xi<D>(ag, pos, xi);
+#pragma unroll
+    for (int e = 0; e < D; ++e) {
+      tg.c[e][threadIdx.x] = pos.c[e];
+      tg.xi[e][threadIdx.x] = xi[e];
+    }
+  }
+}
+
 // Warped frames of one tile into Ws[row][kAffV + 1] (float64): rows of K,
 // then (ones) a row of ones over the valid voxels; invalid voxels hold 0.
+// The tile's geometry must be in tg (and visible: after a barrier).
 template <int D>
 __device__ __forceinline__ void aff_stage_tile(
     const float* __restrict__ T, const int* __restrict__ K, int nk,
     bool ones, const AffGeom& ag, const double* th, const double* mu,
-    long long v0, double* Ws) {
+    long long v0, const AffTileGeo<D>& tg, double* Ws) {
+  constexpr int P = D * D + D;
   const int rows = nk + (ones ? 1 : 0);
   const long long N = ag.g.N;
   for (int idx = threadIdx.x; idx < rows * kAffV; idx += blockDim.x) {
@@ -93,10 +119,22 @@ __device__ __forceinline__ void aff_stage_tile(
     double val = 0.0;
     if (vox < N) {
       if (k < nk) {
-        Pos<D> pos = make_pos<D>(ag.g, vox);
-        double dW[D];
-        aff_warp<D>(T + (size_t)K[k] * N, ag, pos,
-                    th + (size_t)k * (D * D + D), val, dW);
+        Pos<D> pos;
+        double xi[D], uv[D], dW[D];
+#pragma unroll
+        for (int e = 0; e < D; ++e) {
+          pos.c[e] = tg.c[e][v];
+          xi[e] = tg.xi[e][v];
+        }
+        const double* t = th + (size_t)k * P;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          double s = 0.0;
+#pragma unroll
+          for (int e = 0; e < D; ++e) s += t[a * D + e] * xi[e];
+          uv[a] = s + t[D * D + a];
+        }
+        warp_sample<D>(T + (size_t)K[k] * N, ag.g, pos, uv, val, dW);
         if (mu) val -= mu[k];
       } else {
         val = 1.0;
@@ -116,13 +154,20 @@ __device__ __forceinline__ void aff_tile_of(int tau, int TI, int& I, int& J) {
   J = I + tau;
 }
 
-// Pass 1: raw Gram matrix of [W_K; 1] over this block's tiles.
-template <int D>
+// Pass 1: raw Gram matrix of [W_K; 1] over this block's tiles.  The rows
+// are dealt into TI groups {g, g + TI, g + 2 TI, g + 3 TI}; a thread owns
+// MT tiles (I, J), I <= J, of 4 x 4 entries of such groups (split threads
+// share one tile when there are fewer tiles than threads; blockIdx.y
+// selects a group of tiles when MT per thread do not cover them).
+// Neighbouring threads read neighbouring rows, which lie in distinct LDS
+// banks (rows 4 apart would share 8 banks).
+template <int D, int MT>
 __global__ __launch_bounds__(kAffThreads) void aff_gram_kernel(
     const float* __restrict__ T, const int* __restrict__ K, int nk,
     const double* __restrict__ x, const double* __restrict__ dv, double t,
     AffGeom ag, int split, double* __restrict__ part, int E) {
   extern __shared__ double lds[];
+  __shared__ AffTileGeo<D> tg;
   constexpr int P = D * D + D;
   const int K1 = nk + 1;
   const int TI = (K1 + 3) / 4;
@@ -133,55 +178,78 @@ __global__ __launch_bounds__(kAffThreads) void aff_gram_kernel(
   for (int i = threadIdx.x + K1 * (kAffV + 1); i < 4 * TI * (kAffV + 1);
        i += blockDim.x)
     Ws[i] = 0.0;                                      // padding rows
-  // thread -> (tile, voxel sub-lane); split threads share a tile and take
+  // thread -> (tiles, voxel sub-lane); split threads share a tile and take
   // every split-th voxel, then add up by shuffles within their group
   const int tl = threadIdx.x / split, sub = threadIdx.x - tl * split;
-  const int tau = blockIdx.y * (kAffThreads / split) + tl;
-  const bool act = tau < NT;
-  int I = 0, J = 0;
-  if (act) aff_tile_of(tau, TI, I, J);
-  double acc[4][4];
+  const int per = kAffThreads / split;
+  int I[MT], J[MT];
+  bool act[MT];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int m = 0; m < MT; ++m) {
+    const int tau = (blockIdx.y * MT + m) * per + tl;
+    act[m] = tau < NT;
+    I[m] = J[m] = 0;
+    if (act[m]) aff_tile_of(tau, TI, I[m], J[m]);
+  }
+  double acc[MT][4][4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
+  for (int m = 0; m < MT; ++m)
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) acc[m][a][b] = 0.0;
   const long long nch = (ag.g.N + kAffV - 1) / kAffV;
-  __syncthreads();
   for (long long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
-    aff_stage_tile<D>(T, K, nk, true, ag, th, nullptr, ch * kAffV, Ws);
+    aff_tile_geo<D>(ag, ch * kAffV, tg);
     __syncthreads();
-    if (act) {
-      const double* ra = Ws + 4 * I * (kAffV + 1);
-      const double* rb = Ws + 4 * J * (kAffV + 1);
+    aff_stage_tile<D>(T, K, nk, true, ag, th, nullptr, ch * kAffV, tg, Ws);
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < MT; ++m) {
+      if (!act[m]) continue;
+      const double* ra = Ws + I[m] * (kAffV + 1);
+      const double* rb = Ws + J[m] * (kAffV + 1);
+      const int rs = TI * (kAffV + 1);
       for (int v = sub; v < kAffV; v += split) {
         double av[4], bv[4];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          av[a] = ra[a * (kAffV + 1) + v];
-          bv[a] = rb[a * (kAffV + 1) + v];
+          av[a] = ra[a * rs + v];
+          bv[a] = rb[a * rs + v];
         }
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
-          for (int b = 0; b < 4; ++b) acc[a][b] += av[a] * bv[b];
+          for (int b = 0; b < 4; ++b) acc[m][a][b] += av[a] * bv[b];
       }
     }
     __syncthreads();
   }
   for (int o = split >> 1; o >= 1; o >>= 1)
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int m = 0; m < MT; ++m)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) acc[a][b] += __shfl_xor(acc[a][b], o, kWave);
-  if (act && sub == 0) {
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b)
+          acc[m][a][b] += __shfl_xor(acc[m][a][b], o, kWave);
+  if (sub == 0) {
     double* out = part + (size_t)blockIdx.x * E;
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int m = 0; m < MT; ++m) {
+      if (!act[m]) continue;
 #pragma unroll
-      for (int b = 0; b < 4; ++b) {
-        const int r = 4 * I + a, c = 4 * J + b;
-        if (r < K1 && c < K1 && r <= c) out[aff_tri_index(r, c, K1)] = acc[a][b];
-      }
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) {
+          // tile (I, J), I <= J, holds rows I + a TI and J + b TI: every
+          // unordered pair once (both orders on the diagonal tiles)
+          const int r = I[m] + a * TI, c = J[m] + b * TI;
+          if (r >= K1 || c >= K1) continue;
+          if (r <= c) out[aff_tri_index(r, c, K1)] = acc[m][a][b];
+          else if (I[m] != J[m]) out[aff_tri_index(c, r, K1)] = acc[m][a][b];
+        }
+    }
   }
 }
 
@@ -347,6 +415,7 @@ __global__ __launch_bounds__(kAffThreads) void aff_resid_kernel(
     AffGeom ag, const double* __restrict__ mu, const double* __restrict__ Rc,
     float* __restrict__ r) {
   extern __shared__ double lds[];
+  __shared__ AffTileGeo<D> tg;
   constexpr int P = D * D + D;
   const int TI = (nk + 3) / 4;
   double* th = lds;
@@ -360,7 +429,9 @@ __global__ __launch_bounds__(kAffThreads) void aff_resid_kernel(
   const int ntile = TI * (kAffV / 4);
   __syncthreads();
   for (long long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
-    aff_stage_tile<D>(T, K, nk, false, ag, th, mu, ch * kAffV, Ws);
+    aff_tile_geo<D>(ag, ch * kAffV, tg);
+    __syncthreads();
+    aff_stage_tile<D>(T, K, nk, false, ag, th, mu, ch * kAffV, tg, Ws);
     __syncthreads();
     for (int tau = threadIdx.x; tau < ntile; tau += blockDim.x) {
       const int I = tau / (kAffV / 4), V = tau - I * (kAffV / 4);
@@ -675,7 +746,10 @@ AffShape aff_shape(const AffGeom& ag, int nk) {
   int split = 1;
   while (split < 32 && NT * split * 2 <= kAffThreads) split *= 2;
   sh.split = split;
-  sh.groups = (NT * split + kAffThreads - 1) / kAffThreads;
+  // up to three tiles per thread (48 float64 accumulators) before the
+  // tiles are spread over groups that each warp the frames again
+  sh.mt = 1;   // more blocks per compute unit beat fewer warps (measured)
+  sh.groups = (NT * split + sh.mt * kAffThreads - 1) / (sh.mt * kAffThreads);
   sh.E = K1 * (K1 + 1) / 2;
   sh.nb_gram = (int)(nch < kAffGramBlocks ? nch : kAffGramBlocks);
   sh.nb_resid = (int)(nch < 1024 ? nch : 1024);
@@ -693,10 +767,14 @@ AffShape aff_shape(const AffGeom& ag, int nk) {
 // Dynamic LDS above 64 KiB has to be allowed per kernel.
 static hipError_t aff_allow_lds() {
   static hipError_t e = [] {
-    const int cap = 160 * 1024;
+    const int cap = 156 * 1024;    // 160 KiB per CU, less static LDS
     hipError_t r = hipSuccess;
-    const void* ks[] = {(const void*)aff_gram_kernel<2>,
-                        (const void*)aff_gram_kernel<3>,
+    const void* ks[] = {(const void*)aff_gram_kernel<2, 1>,
+                        (const void*)aff_gram_kernel<2, 2>,
+                        (const void*)aff_gram_kernel<2, 3>,
+                        (const void*)aff_gram_kernel<3, 1>,
+                        (const void*)aff_gram_kernel<3, 2>,
+                        (const void*)aff_gram_kernel<3, 3>,
                         (const void*)aff_resid_kernel<2>,
                         (const void*)aff_resid_kernel<3>};
     for (const void* k : ks) {
@@ -718,12 +796,15 @@ hipError_t launch_aff_objective(const float* T, const int* K, int nk,
   if (e != hipSuccess) return e;
   if (!reuse_gram) {
     dim3 grid(sh.nb_gram, sh.groups);
+    decltype(&aff_gram_kernel<2, 1>) kern;
     if (ag.d == 2)
-      aff_gram_kernel<2><<<grid, kAffThreads, sh.lds_gram, s>>>(
-          T, K, nk, x, dv, t, ag, sh.split, b.part, sh.E);
+      kern = sh.mt == 1 ? aff_gram_kernel<2, 1>
+           : sh.mt == 2 ? aff_gram_kernel<2, 2> : aff_gram_kernel<2, 3>;
     else
-      aff_gram_kernel<3><<<grid, kAffThreads, sh.lds_gram, s>>>(
-          T, K, nk, x, dv, t, ag, sh.split, b.part, sh.E);
+      kern = sh.mt == 1 ? aff_gram_kernel<3, 1>
+           : sh.mt == 2 ? aff_gram_kernel<3, 2> : aff_gram_kernel<3, 3>;
+    kern<<<grid, kAffThreads, sh.lds_gram, s>>>(T, K, nk, x, dv, t, ag,
+                                                sh.split, b.part, sh.E);
     aff_sum_kernel<<<(sh.E + 255) / 256, 256, 0, s>>>(b.part, sh.nb_gram,
                                                        sh.E, b.tot);
   }

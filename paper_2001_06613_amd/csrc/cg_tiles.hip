@@ -170,7 +170,7 @@ __device__ __forceinline__ void cg_zero_x(float* __restrict__ x,
 // r.r.  A frame's loads (both components) issue before its stores, which
 // would otherwise hold the next component's loads back.  At it = 0 a CG
 // that stops before its first step sets x = 0.
-template <int D, bool FIRST>
+template <int D, bool FIRST, bool PRE>
 __device__ __forceinline__ void cgv_update_body(
     int it, const float* __restrict__ p, const float* __restrict__ q,
     const float* __restrict__ dW, const Geom& g, const Model& md,
@@ -178,8 +178,42 @@ __device__ __forceinline__ void cgv_update_body(
     double* __restrict__ Sz, double* __restrict__ Vz,
     const double* __restrict__ hv_part, int hv_nb, double* __restrict__ part,
     Scal* __restrict__ sc, int gn_it, Blk blk) {
-  if (gn_it >= sc->gn_stop) return;
-  if (sc->done) {
+  const int stop = sc->gn_stop, done = sc->done;
+  const double rz_it = sc->rzh[it & 1];
+  int j0, j1;
+  wave_frames(md.nK, j0, j1);
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long N = g.N;
+  const long long ntiles = (N + kWave - 1) / kWave;
+  // PRE (grids of at most one block per compute unit, latency-bound): the
+  // first frame of the first tile is requested together with the control
+  // scalars and the product's partials (four frames ahead measured slower:
+  // the registers they hold cost more than the round trips they save)
+  constexpr int kPreF = 1;
+  float pf0[kPreF][D], df0[kPreF][D], xf0[kPreF][D], rf0[kPreF][D],
+      qf0[kPreF][D];
+  const long long tile0 = xcd_tile(ntiles, 0, blk);
+  const long long xv0 = tile0 * kWave + lane;
+  const bool pre = PRE && tile0 >= 0 && xv0 < N;
+  if (pre) {
+#pragma unroll
+    for (int f = 0; f < kPreF; ++f) {
+      if (j0 + f < j1) {
+        const size_t base = (size_t)(j0 + f) * D * N + (size_t)xv0;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const size_t o = base + (size_t)a * N;
+          pf0[f][a] = p[o];
+          df0[f][a] = dW[o];
+          xf0[f][a] = FIRST ? 0.f : x[o];
+          rf0[f][a] = r[o];
+          qf0[f][a] = q[o];
+        }
+      }
+    }
+  }
+  if (gn_it >= stop) return;
+  if (done) {
     if (FIRST) cg_zero_x<D>(x, g, md, blk);
     return;
   }
@@ -194,17 +228,12 @@ __device__ __forceinline__ void cgv_update_body(
     if (FIRST) cg_zero_x<D>(x, g, md, blk);
     return;
   }
-  const double alpha = sc->rzh[it & 1] / pq;
+  const double alpha = rz_it / pq;
   if (blk.id == 0 && threadIdx.x == 0) {
     sc->pq = pq;
     sc->a = alpha;
     sc->iters = it + 1;
   }
-  int j0, j1;
-  wave_frames(md.nK, j0, j1);
-  const int lane = threadIdx.x & (kWave - 1);
-  const long long N = g.N;
-  const long long ntiles = (N + kWave - 1) / kWave;
   double rz = 0.0, rr = 0.0;
   for (int tt = 0;; ++tt) {
     long long tile = xcd_tile(ntiles, tt, blk);
@@ -221,14 +250,26 @@ __device__ __forceinline__ void cgv_update_body(
       for (int j = j0; j < j1; ++j) {
         const size_t base = (size_t)j * D * N + pos.idx;
         float pf[D], df[D], xf[D], rf[D], qf[D];
+        if (PRE && tt == 0 && j - j0 < kPreF) {
+          const int f = j - j0;
 #pragma unroll
-        for (int a = 0; a < D; ++a) {
-          const size_t o = base + (size_t)a * N;
-          pf[a] = p[o];
-          df[a] = dW[o];
-          xf[a] = FIRST ? 0.f : x[o];
-          rf[a] = r[o];
-          qf[a] = q[o];
+          for (int a = 0; a < D; ++a) {
+            pf[a] = pf0[f][a];
+            df[a] = df0[f][a];
+            xf[a] = xf0[f][a];
+            rf[a] = rf0[f][a];
+            qf[a] = qf0[f][a];
+          }
+        } else {
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            const size_t o = base + (size_t)a * N;
+            pf[a] = p[o];
+            df[a] = dW[o];
+            xf[a] = FIRST ? 0.f : x[o];
+            rf[a] = r[o];
+            qf[a] = q[o];
+          }
         }
 #pragma unroll
         for (int a = 0; a < D; ++a) {
@@ -266,8 +307,9 @@ __global__ __launch_bounds__(1024, OCC ? 8 : 1) void cgv_update_kernel(
     float* __restrict__ r, float* __restrict__ z, double* __restrict__ Sz,
     double* __restrict__ Vz, const double* __restrict__ hv_part, int hv_nb,
     double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
-  cgv_update_body<D, FIRST>(it, p, q, dW, g, md, x, r, z, Sz, Vz, hv_part,
-                            hv_nb, part, sc, gn_it, grid_blk());
+  cgv_update_body<D, FIRST, !OCC>(it, p, q, dW, g, md, x, r, z, Sz, Vz,
+                                  hv_part, hv_nb, part, sc, gn_it,
+                                  grid_blk());
 }
 
 // Per-voxel S and V of a stored field v (Hessian product test entry).
@@ -321,13 +363,73 @@ __device__ __forceinline__ void cgt_hvp2_body(
   constexpr int D = 2;
   __shared__ double P[D][kHY][kHX];
   __shared__ double L[REG ? D : 1][REG ? kLY : 1][REG ? kLX : 1];
-  if (sc->done || gn_it >= sc->gn_stop) return;
+  // Everything this block reads is requested before it waits for the
+  // control scalars and the update's partials: the per-voxel sums and the
+  // first frame's halo tile are in flight meanwhile (on the coarse levels
+  // these round trips are most of a launch's time).
+  const int done = sc->done, stop = sc->gn_stop;
+  const double rz_old = FIRST ? 0.0 : sc->rzh[(it - 1) & 1];
+  const double r0 = sc->r0;
+  // block -> (tile, frame group), XCD-chunked
+  const int per_xcd = blk.n / kXCD;
+  const int bb = (blk.id % kXCD) * per_xcd + blk.id / kXCD;
+  const int m0 = g.m[0], m1 = g.m[1];
+  const long long N = g.N;
+  const bool has = bb < nreal;
+  const int tile = has ? bb / nfg : 0, fg = has ? bb - (bb / nfg) * nfg : 0;
+  const int ntx = (m1 + kTX - 1) / kTX;
+  const int y0 = (tile / ntx) * kTY, x0 = (tile % ntx) * kTX;
+  const int ty = threadIdx.x / kTX, tx = threadIdx.x % kTX;
+  const int y = y0 + ty, xx = x0 + tx;
+  const bool valid = has && y < m0 && xx < m1;
+  const unsigned vox = valid ? (unsigned)(y * m1 + xx) : 0u;
+  const int jbeg = fg * fpg;
+  const int jend = !has ? jbeg : (jbeg + fpg < md.nK ? jbeg + fpg : md.nK);
+  double S = 0.0, V0 = 0.0, V1 = 0.0, So = 0.0, Vo0 = 0.0, Vo1 = 0.0;
+  if (valid) {
+    S = Sz[vox];
+    V0 = Vz[vox];
+    V1 = Vz[N + vox];
+    if (!FIRST) {
+      So = Sp_old[vox];
+      Vo0 = Vp_old[vox];
+      Vo1 = Vp_old[N + vox];
+    }
+  }
+  // p of the halo tile, staged through registers one frame ahead: the
+  // loads of frame j + 1 are in flight while frame j is computed
+  // (replicate padding at the grid edge = clamped loads)
+  constexpr int kSt = (kHY * kHX + kTX * kTY - 1) / (kTX * kTY);
+  unsigned so[kSt];
+#pragma unroll
+  for (int s = 0; s < kSt; ++s) {
+    const int i = threadIdx.x + s * kTX * kTY;
+    const int hy = i / kHX, hx = i - (i / kHX) * kHX;
+    const int gy = min(max(y0 - 2 + hy, 0), m0 - 1);
+    const int gx = min(max(x0 - 2 + hx, 0), m1 - 1);
+    so[s] = (unsigned)(gy * m1 + gx);
+  }
+  float sz[kSt][D], sp[kSt][D];
+  auto fetch = [&](int j) {
+#pragma unroll
+    for (int s = 0; s < kSt; ++s) {
+      if (threadIdx.x + s * kTX * kTY < kHY * kHX) {
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const size_t plane = ((size_t)j * D + a) * N;
+          sz[s][a] = zv[plane + so[s]];
+          sp[s][a] = !FIRST ? p_old[plane + so[s]] : 0.f;
+        }
+      }
+    }
+  };
+  if (jbeg < jend) fetch(jbeg);
+  if (done || gn_it >= stop) return;
   double beta = 0.0;
   if (!FIRST) {
     double t[2];
     reduce_partials<2>(up_part, up_nb, 0u, t);
-    const double rz_old = sc->rzh[(it - 1) & 1];
-    bool conv = (!fixed && sqrt(t[1]) <= rtol * sc->r0) || t[0] == 0.0;
+    bool conv = (!fixed && sqrt(t[1]) <= rtol * r0) || t[0] == 0.0;
     if (conv) {
       if (blk.id == 0 && threadIdx.x == 0) sc->done = 1;
       return;
@@ -340,27 +442,14 @@ __device__ __forceinline__ void cgt_hvp2_body(
     }
   }
   const float bf = (float)beta;
-  // block -> (tile, frame group), XCD-chunked
-  const int per_xcd = blk.n / kXCD;
-  const int bb = (blk.id % kXCD) * per_xcd + blk.id / kXCD;
   double acc = 0.0;
-  if (bb < nreal) {
-    const int m0 = g.m[0], m1 = g.m[1];
-    const long long N = g.N;
-    const int tile = bb / nfg, fg = bb - (bb / nfg) * nfg;
-    const int ntx = (m1 + kTX - 1) / kTX;
-    const int y0 = (tile / ntx) * kTY, x0 = (tile % ntx) * kTX;
-    const int ty = threadIdx.x / kTX, tx = threadIdx.x % kTX;
-    const int y = y0 + ty, xx = x0 + tx;
-    const bool valid = y < m0 && xx < m1;
-    const unsigned vox = valid ? (unsigned)(y * m1 + xx) : 0u;
+  if (has) {
     double sbar = 0.0, vbar[D] = {0.0, 0.0};
     if (valid) {
-      double S = Sz[vox], V0 = Vz[vox], V1 = Vz[N + vox];
       if (!FIRST) {
-        S += beta * Sp_old[vox];
-        V0 += beta * Vp_old[vox];
-        V1 += beta * Vp_old[N + vox];
+        S += beta * So;
+        V0 += beta * Vo0;
+        V1 += beta * Vo1;
       }
       if (fg == 0) {
         Sp_new[vox] = S;
@@ -371,36 +460,6 @@ __device__ __forceinline__ void cgt_hvp2_body(
       vbar[0] = V0 * md.inv_nK;
       vbar[1] = V1 * md.inv_nK;
     }
-    const int jbeg = fg * fpg;
-    const int jend = jbeg + fpg < md.nK ? jbeg + fpg : md.nK;
-    // p of the halo tile, staged through registers one frame ahead: the
-    // loads of frame j + 1 are in flight while frame j is computed
-    // (replicate padding at the grid edge = clamped loads)
-    constexpr int kSt = (kHY * kHX + kTX * kTY - 1) / (kTX * kTY);
-    unsigned so[kSt];
-#pragma unroll
-    for (int s = 0; s < kSt; ++s) {
-      const int i = threadIdx.x + s * kTX * kTY;
-      const int hy = i / kHX, hx = i - (i / kHX) * kHX;
-      const int gy = min(max(y0 - 2 + hy, 0), m0 - 1);
-      const int gx = min(max(x0 - 2 + hx, 0), m1 - 1);
-      so[s] = (unsigned)(gy * m1 + gx);
-    }
-    float sz[kSt][D], sp[kSt][D];
-    auto fetch = [&](int j) {
-#pragma unroll
-      for (int s = 0; s < kSt; ++s) {
-        if (threadIdx.x + s * kTX * kTY < kHY * kHX) {
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            const size_t plane = ((size_t)j * D + a) * N;
-            sz[s][a] = zv[plane + so[s]];
-            sp[s][a] = !FIRST ? p_old[plane + so[s]] : 0.f;
-          }
-        }
-      }
-    };
-    if (jbeg < jend) fetch(jbeg);
     for (int j = jbeg; j < jend; ++j) {
 #pragma unroll
       for (int s = 0; s < kSt; ++s) {
@@ -973,7 +1032,7 @@ __global__ __launch_bounds__(1024, 8) void cg_update_batch_kernel(JobSet js,
   const Model md = J.md;
   Scal* sc = J.sc;
   const float* pn = (it & 1) ? J.P1 : J.P0;
-  cgv_update_body<D, FIRST>(it, pn, J.q, J.dW, g, md, J.x, J.r, J.z,
+  cgv_update_body<D, FIRST, false>(it, pn, J.q, J.dW, g, md, J.x, J.r, J.z,
                             J.sums.Sz, J.sums.Vz, J.rb.region(kRegHv),
                             J.ct.grid, J.rb.region(kRegUpdate), sc,
                             sc->gn_cur, blk);

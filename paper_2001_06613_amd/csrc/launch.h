@@ -219,7 +219,7 @@ struct AffBufs {
 constexpr int kAffGramBlocks = 256;    // Gram partials per evaluation
 constexpr int kAffPgradBlocks = 64;    // gradient partials per frame
 struct AffShape {
-  int split, groups, E, nb_gram, nb_resid, nb_pgrad;
+  int split, mt, groups, E, nb_gram, nb_resid, nb_pgrad;
   size_t lds_gram, lds_resid;
 };
 AffShape aff_shape(const AffGeom& ag, int nk);

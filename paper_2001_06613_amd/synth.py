@@ -208,3 +208,58 @@ def random_displacement(shape_nd, n, max_px, seed, smooth=True):
     else:
         u = rng.uniform(-max_px, max_px, (n, d) + tuple(shape_nd))
     return u.astype(np.float32)
+
+
+def affine_motion(n, d, max_disp, extent, seed, n_sin=2):
+    """Per-frame affine motions (n, d, d + 1): row a of frame t maps a voxel
+    centre x to the displacement sum_e M[a, e] (x_e - m_e / 2) / (m_e / 2)
+    + M[a, d], a sum of n_sin temporal sinusoids of random matrices, scaled
+    so that the largest displacement over the grid corners and frames is
+    max_disp pixels."""
+    rng = _rng(seed)
+    mats = rng.standard_normal((n_sin, d, d + 1))
+    mats[:, :, :d] *= 0.5                      # strain smaller than shift
+    phase = rng.uniform(0, 2 * math.pi, n_sin)
+    t = np.arange(n, dtype=np.float64)
+    M = np.zeros((n, d, d + 1))
+    for j in range(n_sin):
+        M += np.sin(2 * math.pi * (j + 1) * t / n + phase[j])[:, None, None] \
+            * mats[j][None]
+    corners = np.array(np.meshgrid(*[[-1.0, 1.0]] * d, indexing="ij")) \
+        .reshape(d, -1)
+    disp = np.einsum("tae,ec->tac", M[:, :, :d], corners) + M[:, :, d:]
+    mx = np.sqrt(np.sum(disp * disp, axis=1)).max()
+    return M * (max_disp / mx)
+
+
+def affine_frame(B, M):
+    """One frame B(x - g(x)) for an affine motion M (d, d + 1) of
+    ``affine_motion`` (linear sampling, edge clamp)."""
+    shape = B.shape
+    d = len(shape)
+    grids = np.meshgrid(*[np.arange(m, dtype=np.float64) for m in shape],
+                        indexing="ij")
+    rel = [(grids[e] + 0.5 - shape[e] / 2.0) / (shape[e] / 2.0)
+           for e in range(d)]
+    coords = np.stack([grids[a] - (sum(M[a, e] * rel[e] for e in range(d))
+                                   + M[a, d]) for a in range(d)])
+    return ndimage.map_coordinates(B, coords, order=1,
+                                   mode="nearest").astype(np.float32)
+
+
+def affine_sequence(n, shape, max_disp, seed, workers=None):
+    """OCT-like phantom moved by temporally smooth affine motions: the
+    stand-in for the paper's affine experiments (Sec. 4).  Returns (frames
+    float32 (n, *shape), motions (n, d, d + 1)).  With ``workers`` > 1 the
+    frames are sampled by forked processes."""
+    rng = _rng(seed)
+    B = base_image(rng, shape)
+    M = affine_motion(n, len(shape), max_disp, shape, seed + 1)
+    if workers and workers > 1:
+        import multiprocessing as mp
+        with mp.get_context("fork").Pool(workers) as pool:
+            frames = pool.starmap(affine_frame, [(B, M[t]) for t in range(n)],
+                                  chunksize=4)
+    else:
+        frames = [affine_frame(B, M[t]) for t in range(n)]
+    return np.stack(frames), M
