@@ -109,6 +109,105 @@ def cpu_baseline(frames, budget_s=10.0):
                       f"thread, {dt:.1f} s"}
 
 
+HALO_ROWS = 8    # slab halo: Armijo trial steps move up to a few pixels
+
+
+def _slab_worker(args):
+    """One row slab (with halo rows) of the 64-frame 256x256 level: the
+    oracle's Gauss-Newton iteration repeated for budget_s seconds on one
+    thread; returns (voxel-frame units of its own rows, seconds)."""
+    frames, r0, r1, budget_s = args
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+
+    w = WORKLOAD
+    par = oracle.ModelParams(alpha=w["alpha"], lam=w["lam"], reg=w["reg"])
+    lo, hi = max(r0 - HALO_ROWS, 0), min(r1 + HALO_ROWS, frames.shape[1])
+    sl = np.ascontiguousarray(frames[:, lo:hi])
+    n = sl.shape[0]
+    u0 = np.zeros((n, 2) + sl.shape[1:])
+    own = n * (r1 - r0) * sl.shape[2]
+    units = 0.0
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < budget_s:
+            res = oracle.gauss_newton(sl, u0, list(range(n)), 1.0, par,
+                                      gn_max=1, cg_max=w["cg_max"],
+                                      fixed=True)
+            units += own * (1 + res.cg_iterations[0])
+        dt = time.perf_counter() - t0
+    return units, dt
+
+
+def cpu_baseline_slabs(frames, budget_s=10.0):
+    """The same oracle iteration on row slabs in parallel processes (one
+    thread each), each slab holding all frames of its rows plus halo rows:
+    the oracle on this host's cores."""
+    import multiprocessing as mp
+
+    cores = min(16, len(os.sched_getaffinity(0)))
+    H = frames.shape[1]
+    edges = [round(H * i / cores) for i in range(cores + 1)]
+    jobs = [(frames, edges[i], edges[i + 1], budget_s) for i in range(cores)]
+    with mp.get_context("fork").Pool(cores) as pool:
+        out = pool.map(_slab_worker, jobs, chunksize=1)
+    units = sum(u for u, _ in out)
+    span = max(dt for _, dt in out)
+    return {"value": units / span / 1e9, "unit": "Gvoxel-frames/s",
+            "cores": cores, "kind": "oracle",
+            "sample": f"{cores} row slabs of 64 frames x 256x256 ({HALO_ROWS} "
+                      "halo rows each), one process and thread per slab, "
+                      "each repeating one Gauss-Newton iteration (1 "
+                      "evaluation + 10 Hessian products + CG + Armijo) for "
+                      f"{budget_s:.0f} s; rate over the slowest worker's "
+                      "timed span"}
+
+
+def _oracle_schedule_worker(args):
+    """Seconds of the oracle's whole schedule on one batch sequence, one
+    thread."""
+    (n, side, seed), kw = args
+    from threadpoolctl import threadpool_limits
+
+    import oracle
+
+    f = _gen_batch_sequence((n, side, seed))
+    with threadpool_limits(1):
+        t0 = time.perf_counter()
+        oracle.stml_run(f, oracle.STMLOptions(**kw))
+        return time.perf_counter() - t0
+
+
+def oracle_batch_extrapolation():
+    """The oracle's whole schedule (fixed 5 GN x 10 CG) on the two smallest
+    of the 32 batch sequences, one thread each (two processes); seconds per
+    voxel-frame times the batch's voxel-frames gives the extrapolated oracle
+    time of the batch."""
+    from paper_2001_06613_amd import synth
+
+    w = WORKLOAD
+    cfg = synth.config_batch()
+    total_vf = float(sum(n * side * side for n, side, _ in cfg))
+    small = sorted(cfg, key=lambda c: c[0] * c[1] ** 2)[:2]
+    kw = dict(n_spatial=w["n_spatial"], n_temporal=w["n_temporal"],
+              reg=w["reg"], alpha=w["alpha"], gn_max=w["gn_max"],
+              cg_max=w["cg_max"], parity_mode=True)
+    import multiprocessing as mp
+
+    with mp.get_context("fork").Pool(2) as pool:
+        res = pool.map(_oracle_schedule_worker, [(c, kw) for c in small],
+                       chunksize=1)
+    secs = sum(r for r in res)
+    vf = float(sum(n * side * side for n, side, _ in small))
+    return {"sequences": [[n, side] for n, side, _ in small],
+            "oracle_s": round(secs, 2), "voxel_frames": vf,
+            "s_per_voxel_frame": secs / vf,
+            "batch_voxel_frames": total_vf,
+            "batch_oracle_s_extrapolated": round(secs / vf * total_vf, 1),
+            "cores": 1}
+
+
 def _gen_batch_sequence(args):
     from paper_2001_06613_amd import synth
 
@@ -674,6 +773,15 @@ def main():
         log("volume: sequences generated")
     if not args.pmc_probe and not args.no_learned:
         learned_seqs = list(learned.generate(range(20000, 20004), workers=4))
+    cpu_multi, cpu_batch = None, None
+    if not args.pmc_probe and not args.no_cpu_baseline:
+        # the host measurements run before the GPU is touched (forked
+        # workers)
+        frames_c2, _ = synth.config_large(1)
+        cpu_multi = cpu_baseline_slabs(frames_c2)
+        log("cpu: row slabs done")
+        cpu_batch = oracle_batch_extrapolation()
+        log("cpu: batch extrapolation done")
     affine_frames = None
     if not args.pmc_probe and not args.no_affine:
         affine_frames = _affine_frames()
@@ -823,6 +931,12 @@ def main():
         out["affine"] = affine_comparison(affine_frames, log)
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(frames)
+        out["cpu_baseline_cores"] = cpu_multi
+        out["cpu_batch_extrapolation"] = cpu_batch
+        if batch_seqs is not None:
+            cpu_batch["gpu_batched_s"] = out["batched"]["batched_ms"] / 1e3
+            cpu_batch["ratio"] = round(cpu_batch[
+                "batch_oracle_s_extrapolated"] / cpu_batch["gpu_batched_s"], 1)
     print(json.dumps(out))
 
 
