@@ -358,6 +358,14 @@ def _set_all(sts, dev):
     return True
 
 
+def _round4(v):
+    if isinstance(v, float):
+        return round(v, 4)
+    if isinstance(v, dict):
+        return {k: _round4(x) for k, x in v.items()}
+    return v
+
+
 def learned_comparison(seqs, log):
     """Paper's predictor vs the shipped learned one on held-out 64-frame
     256x256 sequences (convergence-controlled Gauss-Newton)."""
@@ -371,8 +379,7 @@ def learned_comparison(seqs, log):
     log("learned: comparison done")
     net.close()
     return {"sequences": len(rows), "seeds": [r["seed"] for r in rows],
-            **{k: (round(v, 4) if isinstance(v, float) else v)
-               for k, v in s.items() if k != "sequences"}}
+            **{k: _round4(v) for k, v in s.items() if k != "sequences"}}
 
 
 def copy_ceiling(nbytes=1 << 30, reps=5):
@@ -471,8 +478,7 @@ def learned3d_comparison(seqs, log):
     log("learned 3-D: comparison done")
     net.close()
     return {"sequences": len(rows), "seeds": [r["seed"] for r in rows],
-            **{k: (round(v, 4) if isinstance(v, float) else v)
-               for k, v in s.items() if k != "sequences"}}
+            **{k: _round4(v) for k, v in s.items() if k != "sequences"}}
 
 
 def multilevel_comparison(frames, dim, log, reps):

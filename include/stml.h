@@ -206,6 +206,15 @@ int stml_run(stml_ctx* ctx);
 int stml_get_stop_trace(const stml_ctx* ctx, int level, double* D_out,
                         int cap, int* stop_q);
 
+/* Objective targets for the registrations of the schedule (host array
+ * J_targets[level * n_temporal + q], float64; -INFINITY for none; NULL
+ * clears them): outside parity mode, GIR(level, K_q) also stops as soon as
+ * its objective is at or below the target (before its first step if the
+ * start already is).  Used to run a schedule to the objectives another run
+ * reached (equal-objective comparisons).  Field model only; EINVAL for a
+ * NaN. */
+int stml_set_targets(stml_ctx* ctx, const double* J_targets);
+
 /* Current estimate (y) of `level` into u_dev [n][dim][extent_level...]. */
 int stml_get_displacements(const stml_ctx* ctx, int level, float* u_dev);
 /* Overwrite the current estimate of `level` (resume or test). */

@@ -101,6 +101,7 @@ SIGNATURES = {
     "stml_register_level": (_I, [_P, _I, _I]),
     "stml_correct": (_I, [_P, _I, _I]),
     "stml_run": (_I, [_P]),
+    "stml_set_targets": (_I, [_P, _DP]),
     "stml_get_stop_trace": (_I, [_P, _I, _DP, _I, _IP]),
     "stml_get_displacements": (_I, [_P, _I, _P]),
     "stml_set_displacements": (_I, [_P, _I, _P]),
@@ -423,6 +424,17 @@ class STML:
             th.ctypes.data_as(dp), out,
             g.ctypes.data_as(dp) if grad else None))
         return {"J": out[0], "D": out[1], "P": out[2]}, g
+
+    def set_targets(self, targets):
+        """Objective targets [levels][n_temporal] (NaN-free; -inf for
+        none), or None to clear."""
+        if targets is None:
+            return self._check(self.lib.stml_set_targets(self.ctx, None))
+        t = np.ascontiguousarray(targets, dtype=np.float64)
+        if t.shape != (self.levels, self.opts.n_temporal):
+            raise STMLError(STML_EINVAL, "need (levels, n_temporal) targets")
+        return self._check(self.lib.stml_set_targets(
+            self.ctx, t.ctypes.data_as(ctypes.POINTER(ctypes.c_double))))
 
     def stop_trace(self, level=None):
         """Eq. (3) record of the last run on `level`: (D_q list, stop q or

@@ -375,6 +375,9 @@ __device__ __forceinline__ void finalize_start_body(
     sc->iters = 0;
     sc->done = i2[0] == 0.0 ? 1 : 0;
     if (log) log[gn_it].J = Dv + Sv + Pv;
+    // a start at or below the target takes no step (the stop tests of the
+    // accept kernel run only where a step was taken)
+    if (gn_it == 0 && Dv + Sv + Pv <= sc->J_target) sc->gn_stop = 0;
   }
 }
 
@@ -615,8 +618,9 @@ __device__ __forceinline__ void ls_accept_body(
     L->status = breakdown ? 2 : 0;
     const double rms = sqrt(out[NT + 8] / (double)count);
     bool stop = breakdown ||
-                (!fixed && (L->J - Jacc) <= tol_J * fabs(L->J) &&
-                 tacc * rms <= tol_u);
+                (!fixed && (((L->J - Jacc) <= tol_J * fabs(L->J) &&
+                             tacc * rms <= tol_u) ||
+                            Jacc <= sc->J_target));
     if (stop) sc->gn_stop = gn_it + 1;
   }
 }
@@ -634,7 +638,8 @@ __global__ __launch_bounds__(256) void ls_accept_kernel(
 // Start of a registration: every Gauss-Newton iteration enabled, logs
 // cleared.
 __global__ void gn_reset_kernel(Scal* __restrict__ sc,
-                                GNLog* __restrict__ log, int n) {
+                                GNLog* __restrict__ log, int n,
+                                double J_target) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) {
     GNLog L = {};
@@ -646,6 +651,7 @@ __global__ void gn_reset_kernel(Scal* __restrict__ sc,
     sc->gn_stop = 0x7fffffff;
     sc->done = 0;
     sc->gn_cur = 0;
+    sc->J_target = J_target;
   }
 }
 
@@ -811,6 +817,7 @@ __global__ __launch_bounds__(256) void reset_batch_kernel(JobSet js,
     J.sc->gn_stop = 0x7fffffff;
     J.sc->done = 0;
     J.sc->gn_cur = 0;
+    J.sc->J_target = -INFINITY;
   }
 }
 
@@ -983,9 +990,10 @@ hipError_t launch_finalize_vhv(const double* part, int nb, Scal* sc,
   return hipGetLastError();
 }
 
-hipError_t launch_gn_reset(Scal* sc, GNLog* log, int n, hipStream_t s) {
+hipError_t launch_gn_reset(Scal* sc, GNLog* log, int n, hipStream_t s,
+                           double J_target) {
   int nb = (n + 255) / 256;
-  gn_reset_kernel<<<nb < 1 ? 1 : nb, 256, 0, s>>>(sc, log, n);
+  gn_reset_kernel<<<nb < 1 ? 1 : nb, 256, 0, s>>>(sc, log, n, J_target);
   return hipGetLastError();
 }
 

@@ -74,7 +74,10 @@ hipError_t launch_ls_accept(float* u, const float* delta, const int* K,
                             LSPass ls, int ls_max, double c1, int fixed,
                             double tol_J, double tol_u, RedBuf rb, int gn_it,
                             Scal* sc, GNLog* log, hipStream_t s);
-hipError_t launch_gn_reset(Scal* sc, GNLog* log, int n, hipStream_t s);
+// J_target: the registration stops once J <= J_target (not in parity
+// mode); -inf for none.
+hipError_t launch_gn_reset(Scal* sc, GNLog* log, int n, hipStream_t s,
+                           double J_target = -INFINITY);
 // One block: objective of the evaluation (ev_nb partials) and the CG start
 // scalars (in_nb partials of the CG start kernel).
 hipError_t launch_finalize_start(RedBuf rb, int ev_nb, int in_nb,

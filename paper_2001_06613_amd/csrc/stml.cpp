@@ -95,6 +95,8 @@ struct stml_ctx {
   AffState* hast = nullptr;             // pinned host mirrors
   AffScal* hasc = nullptr;
   std::vector<stml_gir_log> logs;
+  // objective targets per (level, q) (-inf: none), see stml_set_targets
+  std::vector<double> targets;
   // eq. (3) of the last stml_run: D over all frames per q, and the q at
   // which each level stopped (-1: not stopped)
   std::vector<std::vector<double>> stop_trace;
@@ -591,7 +593,7 @@ int gn_log(stml_ctx* c, int nK, long long N, stml_gir_log* log);
 // host synchronises once at the end, otherwise after every iteration so
 // that no launches are spent after the stopping rule fired.
 int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
-                 stml_gir_log* log) {
+                 stml_gir_log* log, double J_target = -INFINITY) {
   const stml_opts& o = c->o;
   const int D = c->d;
   const Geom g = geom_of(c, level);
@@ -601,7 +603,8 @@ int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
   std::vector<LSPass> passes;
   std::vector<std::vector<double>> steps;
   ls_passes(o.ls_max, &passes, &steps);
-  HIP_OK(launch_gn_reset(c->sc, c->gnlog, o.gn_max, c->stream));
+  HIP_OK(launch_gn_reset(c->sc, c->gnlog, o.gn_max, c->stream,
+                         o.parity_mode ? -INFINITY : J_target));
   for (int it = 0; it < o.gn_max; ++it) {
     TIMED(STML_K_EVAL, level, vf,
           launch_eval(D, T, u, Kdev, g, md, c->g, c->dW, c->rb, c->sc,
@@ -640,6 +643,8 @@ int gn_log(stml_ctx* c, int nK, long long N, stml_gir_log* log) {
   std::memset(log, 0, sizeof *log);
   log->n_frames = nK;
   log->J0 = log->J = NAN;
+  // the start's objective, also when no step was taken (a target met)
+  if (o.gn_max > 0) log->J0 = log->J = c->hlog[0].J;
   for (int it = 0; it < o.gn_max; ++it) {
     const GNLog& L = c->hlog[it];
     if (L.status < 0) break;
@@ -933,8 +938,11 @@ int do_register(stml_ctx* c, int level, int q) {
     int rc = aff_register(c, level, q, &log);
     return record_gir(c, level, q, rc, log);
   }
+  const double target = c->targets.empty()
+                            ? -INFINITY
+                            : c->targets[(size_t)level * c->T1 + q];
   int rc = gauss_newton(c, level, c->qt[q].K, (int)c->K[q].size(),
-                        c->lv[level].Y, &log);
+                        c->lv[level].Y, &log, target);
   return record_gir(c, level, q, rc, log);
 }
 
@@ -1320,6 +1328,22 @@ int stml_set_prediction(stml_ctx* c, int level, const float* z) {
   if (check_level(c, level)) return STML_EINVAL;
   if (field_only(c)) return STML_EINVAL;
   return copy_field(c, level, c->lv[level].Z, z);
+}
+
+int stml_set_targets(stml_ctx* c, const double* J_targets) {
+  if (!c) return STML_EINVAL;
+  if (!J_targets) {
+    c->targets.clear();
+    return STML_OK;
+  }
+  if (c->o.model != STML_MODEL_FIELD)
+    return fail(c, STML_EINVAL, "targets apply to the field model");
+  const size_t cnt = (size_t)c->L * c->T1;
+  for (size_t i = 0; i < cnt; ++i)
+    if (std::isnan(J_targets[i]))
+      return fail(c, STML_EINVAL, "target %zu is NaN", i);
+  c->targets.assign(J_targets, J_targets + cnt);
+  return STML_OK;
 }
 
 int stml_get_params(const stml_ctx* cc, int level, double* theta) {

@@ -64,6 +64,7 @@ struct Scal {
   int bad;                    // non-finite input count
   int gn_stop;                // Gauss-Newton iterations >= gn_stop do nothing
   int gn_cur;                 // iteration of batched (graph) launches
+  double J_target;            // stop once J <= J_target (-inf: no target)
 };
 
 // One Gauss-Newton iteration as decided on the device.

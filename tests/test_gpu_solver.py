@@ -350,3 +350,37 @@ def test_spml_run_parity_and_staged_schedule():
     assert len(st3.logs()) == 4
     np.testing.assert_array_equal(st3.get_displacements().cpu().numpy(),
                                   whole)
+
+
+def test_objective_target_stops_registration():
+    """stml_set_targets: GIR stops at the first accepted step whose
+    objective is at or below the target, and takes no step when the start
+    already is; the steps before are those of the run without a target."""
+    frames = _small()
+    kw = dict(n_spatial=1, n_temporal=2, reg="curvature", alpha=0.1,
+              gn_max=8, cg_max=10, tol_J=0.0, tol_u=0.0)
+    st = STML(8, frames.shape[1:], opts=default_opts(**kw))
+    fr = torch.from_numpy(frames).cuda()
+    st.set_sequence(fr)
+    st.predict(0, 0)
+    st.register_level(0, 0)
+    free = st.logs()[0]
+    assert free["gn"] == 8
+    targets = np.full((1, 2), -np.inf)
+    targets[0, 0] = free["J_iter"][2]
+    st.set_targets(targets)
+    st.set_sequence(fr)
+    st.predict(0, 0)
+    st.register_level(0, 0)
+    lg = st.logs()[0]
+    assert lg["gn"] == 3 and lg["J"] == free["J_iter"][2]
+    assert lg["steps"] == free["steps"][:3]
+    targets[0, 0] = free["J0"]                  # the start meets it
+    st.set_targets(targets)
+    st.set_sequence(fr)
+    st.predict(0, 0)
+    st.register_level(0, 0)
+    lg = st.logs()[0]
+    assert lg["gn"] == 0 and lg["J"] == free["J0"]
+    assert torch.count_nonzero(st.get_displacements(0)).item() == 0
+    st.set_targets(None)
