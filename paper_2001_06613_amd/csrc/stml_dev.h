@@ -404,17 +404,52 @@ __device__ __forceinline__ int wave_id() {
   return __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
 }
 
-// Wave-level sum (butterfly, fixed order -> deterministic).
+// Wave-level reductions by DPP lane moves (register-only, a few cycles
+// each; a shuffle goes through the LDS crossbar): inclusive scan within
+// 16-lane rows (shifts by 1, 2, 4, 8), then row 0's total into row 1 and
+// rows 0-1's into rows 2-3 (row broadcasts of lanes 15 and 31), so lane 63
+// ends with the total, which every lane reads back.  Lanes a move cannot
+// reach contribute the identity.  The order of the float64 operations is
+// fixed, so results are deterministic.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ double dpp_f64(double v, double identity) {
+  const long long b = __double_as_longlong(v);
+  const long long id = __double_as_longlong(identity);
+  const int lo = __builtin_amdgcn_update_dpp((int)id, (int)b, CTRL, ROW_MASK,
+                                             0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp((int)(id >> 32), (int)(b >> 32),
+                                             CTRL, ROW_MASK, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) |
+                              (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_lane63(double v) {
+  const long long b = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_readlane((int)b, 63);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), 63);
+  return __longlong_as_double(((long long)hi << 32) |
+                              (long long)(unsigned)lo);
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += dpp_f64<0x111, 0xf>(v, 0.0);     // row_shr:1
+  v += dpp_f64<0x112, 0xf>(v, 0.0);     // row_shr:2
+  v += dpp_f64<0x114, 0xf>(v, 0.0);     // row_shr:4
+  v += dpp_f64<0x118, 0xf>(v, 0.0);     // row_shr:8
+  v += dpp_f64<0x142, 0xa>(v, 0.0);     // row_bcast:15 into rows 1, 3
+  v += dpp_f64<0x143, 0xc>(v, 0.0);     // row_bcast:31 into rows 2, 3
+  return wave_lane63(v);
 }
 
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int o = 32; o >= 1; o >>= 1) v = fmax(v, __shfl_xor(v, o, kWave));
-  return v;
+  const double ninf = -__builtin_inf();
+  v = fmax(v, dpp_f64<0x111, 0xf>(v, ninf));
+  v = fmax(v, dpp_f64<0x112, 0xf>(v, ninf));
+  v = fmax(v, dpp_f64<0x114, 0xf>(v, ninf));
+  v = fmax(v, dpp_f64<0x118, 0xf>(v, ninf));
+  v = fmax(v, dpp_f64<0x142, 0xa>(v, ninf));
+  v = fmax(v, dpp_f64<0x143, 0xc>(v, ninf));
+  return wave_lane63(v);
 }
 
 // A block's index and the block count within its own problem: the grid of
