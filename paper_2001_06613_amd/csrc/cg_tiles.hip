@@ -66,18 +66,12 @@ __device__ __forceinline__ void store_voxel_sums(double s, const double* v,
 #pragma unroll
   for (int a = 0; a < D; ++a) xs[w][lane][1 + a] = v[a];
   __syncthreads();
-  if (w == 0 && valid) {
-    double ts = 0.0, tv[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) tv[a] = 0.0;
-    for (int c = 0; c < G; ++c) {
-      ts += xs[c][lane][0];
-#pragma unroll
-      for (int a = 0; a < D; ++a) tv[a] += xs[c][lane][1 + a];
-    }
-    S[x] = ts;
-#pragma unroll
-    for (int a = 0; a < D; ++a) V[(size_t)a * N + x] = tv[a];
+  // wave k sums value k (S, then the D components of V) over the waves
+  if (w <= D && valid) {
+    double t = 0.0;
+    for (int c = 0; c < G; ++c) t += xs[c][lane][w];
+    if (w == 0) S[x] = t;
+    else V[(size_t)(w - 1) * N + x] = t;
   }
   __syncthreads();
 }

@@ -29,7 +29,20 @@ __device__ void block_partials(const double (&vals)[NV], unsigned maxmask,
     if (lane == 0) red[w][v] = x;
   }
   __syncthreads();
-  if (threadIdx.x < NV) {
+  if (NV <= 4) {
+    // wave 0 combines the waves' values: lane i holds wave i's
+    if (w == 0) {
+#pragma unroll
+      for (int v = 0; v < NV; ++v) {
+        const bool mx = (maxmask >> v) & 1u;
+        const double id = mx ? -__builtin_inf() : 0.0;
+        const double x = lane < nw ? red[lane][v] : id;
+        const double s = mx ? wave_max(x) : wave_sum(x);
+        if (lane == 0) part[(size_t)v * blk.n + blk.id] = s;
+      }
+    }
+  } else if (threadIdx.x < NV) {
+    // many values: one thread per value, in parallel
     int v = threadIdx.x;
     bool mx = (maxmask >> v) & 1u;
     double s = red[0][v];
@@ -44,12 +57,36 @@ __device__ void block_partials(const double (&vals)[NV], unsigned maxmask,
 }
 
 // Totals of NV values from nb partial slots each; every thread of the block
-// receives them.  Slots are summed in 256 fixed strands (strand v: slots
-// v, v + 256, ...), whichever threads compute them, and the strands then in
-// a fixed tree, so the order depends on nb only, not on the block size.
+// receives them.  Up to 64 slots, every wave sums them by a wave reduction
+// (lane l holds slot l); more slots are summed in 256
+// fixed strands (strand v: slots v, v + 256, ...), whichever threads
+// compute them, and the strands then in a fixed tree.  Either way the order
+// depends on nb only, not on the block size.
 template <int NV>
 __device__ void reduce_partials(const double* __restrict__ part, int nb,
                                 unsigned maxmask, double (&out)[NV]) {
+  if (nb <= kWave) {
+    // few slots: every wave sums them itself (lane l takes slot l), without
+    // LDS or barriers; the order depends on nb only (more slots would be
+    // read again by every wave of every block)
+    const int lane = threadIdx.x & (kWave - 1);
+    double acc[NV];
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      acc[v] = ((maxmask >> v) & 1u) ? -1.0e300 : 0.0;
+    for (int i = lane; i < nb; i += kWave) {
+      double x[NV];
+#pragma unroll
+      for (int v = 0; v < NV; ++v) x[v] = part[(size_t)v * nb + i];
+#pragma unroll
+      for (int v = 0; v < NV; ++v)
+        acc[v] = ((maxmask >> v) & 1u) ? fmax(acc[v], x[v]) : acc[v] + x[v];
+    }
+#pragma unroll
+    for (int v = 0; v < NV; ++v)
+      out[v] = ((maxmask >> v) & 1u) ? wave_max(acc[v]) : wave_sum(acc[v]);
+    return;
+  }
   constexpr int kStrands = 4 * kWave;
   __shared__ double red[NV][kStrands];
   __shared__ double tot[NV];
