@@ -871,6 +871,8 @@ def main():
     kernels = {}
     for k in ("eval", "hessvec", "cg_update", "trial", "cg_init", "accept",
               "predict", "restrict"):
+        # cg_init: the one-block kernel of the CG start scalars (r and z
+        # are formed by the evaluation)
         t = st.timing_get(k)
         gbs = t["bytes"] / (t["ms"] * 1e-3) / 1e9 if t["ms"] > 0 else 0.0
         kernels[k] = {"ms": round(t["ms"], 4), "launches": t["launches"],

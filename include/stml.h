@@ -316,7 +316,7 @@ const char* stml_noalloc_last_error(void);
 #define STML_K_CG_UPDATE   2  /* x, r, z update and r.z                      */
 #define STML_K_CG_PUPDATE  3  /* p = z + beta p                              */
 #define STML_K_TRIAL       4  /* objective at the Armijo trial steps         */
-#define STML_K_CG_INIT     5  /* CG start                                    */
+#define STML_K_CG_INIT     5  /* CG start scalars (r, z: by the evaluation)  */
 #define STML_K_ACCEPT      6  /* u += t delta                                */
 #define STML_K_PREDICT     7  /* prolongation and temporal predictors        */
 #define STML_K_RESTRICT    8  /* spatial restriction                         */

@@ -42,14 +42,6 @@ __device__ __forceinline__ void wave_frames(int nK, int& j0, int& j1) {
   j1 = j0 + per < nK ? j0 + per : nK;
 }
 
-// Jacobi diagonal factor of voxel p without the data term.
-template <int D>
-__device__ __forceinline__ double jacobi_rest(const Pos<D>& p, const Geom& g,
-                                              const Model& md) {
-  return md.alpha_hd * md.reg_scale * reg_diag_at<D>(p, g, md.reg) +
-         md.pen_diag;
-}
-
 // Combine the per-wave sums of S (1) and V (D) of every voxel of the tile
 // and store them (float64).
 template <int D>
@@ -74,65 +66,6 @@ __device__ __forceinline__ void store_voxel_sums(double s, const double* v,
     else V[(size_t)(w - 1) * N + x] = t;
   }
   __syncthreads();
-}
-
-// CG start: r = -g, z = M^-1 r; per-voxel S_z, V_z; partials of r.z, r.r.
-template <int D>
-__device__ __forceinline__ void cgv_init_body(
-    const float* __restrict__ grad, const float* __restrict__ dW,
-    const Geom& g, const Model& md, float* __restrict__ r,
-    float* __restrict__ z, double* __restrict__ Sz, double* __restrict__ Vz,
-    double* __restrict__ part, int gn_it, const Scal* __restrict__ sc,
-    Blk blk) {
-  if (gn_it >= sc->gn_stop) return;
-  int j0, j1;
-  wave_frames(md.nK, j0, j1);
-  const int lane = threadIdx.x & (kWave - 1);
-  const long long N = g.N;
-  const long long ntiles = (N + kWave - 1) / kWave;
-  double rz = 0.0, rr = 0.0;
-  for (int it = 0;; ++it) {
-    long long tile = xcd_tile(ntiles, it, blk);
-    if (tile < 0) break;
-    long long x = tile * kWave + lane;
-    bool valid = x < N;
-    Pos<D> pos = make_pos<D>(g, valid ? x : N - 1);
-    const double rest = jacobi_rest<D>(pos, g, md);
-    double s = 0.0, v[D];
-#pragma unroll
-    for (int a = 0; a < D; ++a) v[a] = 0.0;
-    if (valid) {
-      for (int j = j0; j < j1; ++j) {
-        const size_t base = (size_t)j * D * N + pos.idx;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          size_t o = base + (size_t)a * N;
-          double d = (double)dW[o];
-          float rv = -grad[o];
-          float zv = (float)((double)rv / (md.mdiag_c * d * d + rest));
-          r[o] = rv;
-          z[o] = zv;
-          rz += (double)rv * (double)zv;
-          rr += (double)rv * (double)rv;
-          s += d * (double)zv;
-          v[a] += (double)zv;
-        }
-      }
-    }
-    store_voxel_sums<D>(s, v, x, valid, N, Sz, Vz);
-  }
-  double vals[2] = {rz, rr};
-  block_partials<2>(vals, 0u, part, blk);
-}
-
-template <int D>
-__global__ __launch_bounds__(1024) void cgv_init_kernel(
-    const float* __restrict__ grad, const float* __restrict__ dW, Geom g,
-    Model md, float* __restrict__ r, float* __restrict__ z,
-    double* __restrict__ Sz, double* __restrict__ Vz,
-    double* __restrict__ part, int gn_it, const Scal* __restrict__ sc) {
-  cgv_init_body<D>(grad, dW, g, md, r, z, Sz, Vz, part, gn_it, sc,
-                   grid_blk());
 }
 
 // x = 0 over this block's tiles: the CG solution when no step is taken
@@ -861,21 +794,6 @@ CgTiles cg_tiles(const Geom& g, int nK, int dim) {
   return t;
 }
 
-hipError_t launch_cgv_init(int dim, const float* grad, const float* dW,
-                           const Geom& g, const Model& md, float* r, float* z,
-                           CgSums sums, RedBuf rb, Scal* sc, hipStream_t s,
-                           int gn_it, GNLog* log) {
-  int nb = cgv_blocks(g), nt = cgv_threads(dim, md.nK);
-  double* part = rb.region(kRegInit);
-  if (dim == 2)
-    cgv_init_kernel<2><<<nb, nt, 0, s>>>(grad, dW, g, md, r, z, sums.Sz,
-                                         sums.Vz, part, gn_it, sc);
-  else
-    cgv_init_kernel<3><<<nb, nt, 0, s>>>(grad, dW, g, md, r, z, sums.Sz,
-                                         sums.Vz, part, gn_it, sc);
-  return launch_finalize_start(rb, tile_blocks(g), nb, md, sc, gn_it, log, s);
-}
-
 hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
                           float* p_new, const float* dW, const Geom& g,
                           const Model& md, float* q, CgSums sums, int fixed,
@@ -967,17 +885,6 @@ __device__ __forceinline__ const Job& cg_job_of(const JobSet& js, int c,
   return js.jobs[j];
 }
 
-template <int D>
-__global__ __launch_bounds__(1024) void cg_init_batch_kernel(JobSet js) {
-  Blk blk;
-  const Job& J = cg_job_of(js, kClsVox, blk);
-  const Geom g = J.g;
-  const Model md = J.md;
-  Scal* sc = J.sc;
-  cgv_init_body<D>(J.grad, J.dW, g, md, J.r, J.z, J.sums.Sz, J.sums.Vz,
-                   J.rb.region(kRegInit), sc->gn_cur, sc, blk);
-}
-
 template <int D, int REG, bool FIRST>
 __global__ __launch_bounds__(D == 2 ? kHv2Threads : kHv3Threads,
                              D == 3 ? 4 : (REG ? 8 : 5)) void cg_hvp_batch_kernel(
@@ -1048,18 +955,6 @@ void job_shape(Job* job) {
   job->nb_vox = job->ct.vox_grid;
   job->count = (long long)job->md.nK * dim * job->g.N;
   job->nb_elem = elem_grid(job->count);
-}
-
-hipError_t batch_finalize_start(const JobSet& js, hipStream_t s);
-
-hipError_t batch_cg_init(const JobSet& js, int nvox, int dim, hipStream_t s) {
-  if (dim == 2)
-    cg_init_batch_kernel<2><<<nvox, cgv_threads(2, 0), 0, s>>>(js);
-  else
-    cg_init_batch_kernel<3><<<nvox, cgv_threads(3, 0), 0, s>>>(js);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  return batch_finalize_start(js, s);
 }
 
 hipError_t batch_zero_x(const JobSet& js, int nvox, int dim, hipStream_t s) {

@@ -232,13 +232,18 @@ __device__ __forceinline__ Chunk frame_chunk(int nK) {
 // and warping the rest again.  The gradient uses dW/du rounded to float32,
 // the values the Hessian product uses.  Block partials of D, S, P go to
 // `part` (3 x gridDim slots).
-template <int D, int REG>
+// INIT: sweep 2 also starts the Jacobi-PCG of the Gauss-Newton step from
+// the float32 gradient just written: r = -g, z = r / M with M recomputed
+// from the float32 dW/du, per-voxel S_z = sum_k dW_k . z_k and V_z =
+// sum_k z_k (combined over the waves in LDS), and partials of r.z and r.r
+// after those of D, S, P (5 x gridDim slots).
+template <int D, int REG, bool INIT>
 __device__ __forceinline__ void eval_body(
     const float* __restrict__ T, const float* __restrict__ u,
     const int* __restrict__ K, const Geom& g, const Model& md,
     float* __restrict__ grad, float* __restrict__ dWo,
     double* __restrict__ part, int gn_it, const Scal* __restrict__ sc,
-    Blk blk) {
+    CgStart cs, Blk blk) {
   if (sc && gn_it >= sc->gn_stop) return;
   constexpr int G_ = D == 2 ? 8 : 4;   // waves per block (eval_threads)
   // W and dW/du (rounded to float32, as stored) of a wave's first kWF frames
@@ -254,13 +259,16 @@ __device__ __forceinline__ void eval_body(
   const Chunk ch = frame_chunk(md.nK);
   const long long N = g.N;
   const long long ntiles = (N + kWave - 1) / kWave;
-  double accD = 0.0, accS = 0.0, accP = 0.0;
+  double accD = 0.0, accS = 0.0, accP = 0.0, rz = 0.0, rr = 0.0;
   for (int it = 0;; ++it) {
     long long tile = xcd_tile(ntiles, it, blk);
     if (tile < 0) break;
     long long x = tile * kWave + lane;
     bool valid = x < N;
     Pos<D> p = make_pos<D>(g, valid ? x : N - 1);
+    double sz = 0.0, vz[D];
+#pragma unroll
+    for (int a = 0; a < D; ++a) vz[a] = 0.0;
     double sW = 0.0, sU[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) sU[a] = 0.0;
@@ -301,6 +309,7 @@ __device__ __forceinline__ void eval_body(
 #pragma unroll
     for (int a = 0; a < D; ++a) ub[a] *= md.inv_nK;
     if (valid) {
+      const double rest = INIT ? jacobi_rest<D>(p, g, md) : 0.0;
       for (int j = ch.j0; j < ch.j1; ++j) {
         int k = K[j];
         const float* uk = u + (size_t)k * D * N;
@@ -329,7 +338,20 @@ __device__ __forceinline__ void eval_body(
           if (gj) {
             double gv = md.data_c * r * dw[a] +
                         md.alpha_hd * md.reg_scale * btb + md.lam_c * ub[a];
-            gj[(size_t)a * N + p.idx] = (float)gv;
+            const float gf = (float)gv;
+            gj[(size_t)a * N + p.idx] = gf;
+            if (INIT) {
+              const size_t o = ((size_t)j * D + a) * N + p.idx;
+              const float rv = -gf;
+              const float zv =
+                  (float)((double)rv / (md.mdiag_c * dw[a] * dw[a] + rest));
+              cs.r[o] = rv;
+              cs.z[o] = zv;
+              rz += (double)rv * (double)zv;
+              rr += (double)rv * (double)rv;
+              sz += dw[a] * (double)zv;
+              vz[a] += (double)zv;
+            }
           }
         }
       }
@@ -338,29 +360,51 @@ __device__ __forceinline__ void eval_body(
         for (int a = 0; a < D; ++a) accP += ub[a] * ub[a];
       }
     }
+    if (INIT) {
+      // per-voxel S_z and V_z over the waves' frames: wave c sums value c
+      xs[w][lane][0] = sz;
+#pragma unroll
+      for (int a = 0; a < D; ++a) xs[w][lane][1 + a] = vz[a];
+      __syncthreads();
+      if (w <= D && valid) {
+        double t = 0.0;
+        for (int c = 0; c < G; ++c) t += xs[c][lane][w];
+        if (w == 0) cs.Sz[x] = t;
+        else cs.Vz[(size_t)(w - 1) * N + x] = t;
+      }
+      __syncthreads();
+    }
   }
-  double vals[3] = {accD, accS, accP};
-  block_partials<3>(vals, 0u, part, blk);
+  if (INIT) {
+    double vals[5] = {accD, accS, accP, rz, rr};
+    block_partials<5>(vals, 0u, part, blk);
+  } else {
+    double vals[3] = {accD, accS, accP};
+    block_partials<3>(vals, 0u, part, blk);
+  }
 }
 
-template <int D, int REG>
-__global__ __launch_bounds__(D == 2 ? 512 : 256) void eval_kernel(
+// Two 8-wave blocks per compute unit in 2-D (LDS allows two): at most 128
+// registers per lane.
+template <int D, int REG, bool INIT>
+__global__ __launch_bounds__(D == 2 ? 512 : 256, D == 2 ? 4 : 1) void eval_kernel(
     const float* __restrict__ T, const float* __restrict__ u,
     const int* __restrict__ K, Geom g, Model md, float* __restrict__ grad,
     float* __restrict__ dWo, double* __restrict__ part, int gn_it,
-    const Scal* __restrict__ sc) {
-  eval_body<D, REG>(T, u, K, g, md, grad, dWo, part, gn_it, sc, grid_blk());
+    const Scal* __restrict__ sc, CgStart cs) {
+  eval_body<D, REG, INIT>(T, u, K, g, md, grad, dWo, part, gn_it, sc, cs,
+                          grid_blk());
 }
 
-// One block: the objective of the evaluation and the CG start scalars.
+// One block: the objective of the evaluation and the CG start scalars (the
+// five partials of an evaluation that formed the CG start).
 __device__ __forceinline__ void finalize_start_body(
-    const double* __restrict__ ev_part, int ev_nb,
-    const double* __restrict__ in_part, int in_nb, const Model& md,
+    const double* __restrict__ ev_part, int ev_nb, const Model& md,
     Scal* __restrict__ sc, int gn_it, GNLog* __restrict__ log) {
   if (gn_it >= sc->gn_stop) return;
-  double e[3], i2[2];
-  reduce_partials<3>(ev_part, ev_nb, 0u, e);
-  reduce_partials<2>(in_part, in_nb, 0u, i2);
+  double e[5];
+  reduce_partials<5>(ev_part, ev_nb, 0u, e);
+  const double i2[2] = {e[3], e[4]};
   if (threadIdx.x == 0) {
     double Dv = md.hd * e[0];
     double Sv = md.half_alpha_hd * md.reg_scale * e[1];
@@ -382,10 +426,9 @@ __device__ __forceinline__ void finalize_start_body(
 }
 
 __global__ __launch_bounds__(256) void finalize_start_kernel(
-    const double* __restrict__ ev_part, int ev_nb,
-    const double* __restrict__ in_part, int in_nb, Model md,
+    const double* __restrict__ ev_part, int ev_nb, Model md,
     Scal* __restrict__ sc, int gn_it, GNLog* __restrict__ log) {
-  finalize_start_body(ev_part, ev_nb, in_part, in_nb, md, sc, gn_it, log);
+  finalize_start_body(ev_part, ev_nb, md, sc, gn_it, log);
 }
 
 struct Steps {
@@ -758,23 +801,23 @@ __device__ __forceinline__ const Job& job_of(const JobSet& js, int c,
 }
 
 template <int D, int REG>
-__global__ __launch_bounds__(D == 2 ? 512 : 256) void eval_batch_kernel(
+__global__ __launch_bounds__(D == 2 ? 512 : 256, D == 2 ? 4 : 1) void eval_batch_kernel(
     JobSet js) {
   Blk blk;
   const Job& J = job_of(js, kClsTile, blk);
   const Geom g = J.g;
   const Model md = J.md;
   Scal* sc = J.sc;
-  eval_body<D, REG>(J.T, J.u, J.K, g, md, J.grad, J.dW,
-                    J.rb.region(kRegEval), sc->gn_cur, sc, blk);
+  eval_body<D, REG, true>(J.T, J.u, J.K, g, md, J.grad, J.dW,
+                          J.rb.region(kRegEval), sc->gn_cur, sc,
+                          CgStart{J.r, J.z, J.sums.Sz, J.sums.Vz}, blk);
 }
 
 __global__ __launch_bounds__(256) void start_batch_kernel(JobSet js) {
   const Job& J = js.jobs[blockIdx.x];
   const Model md = J.md;
   Scal* sc = J.sc;
-  finalize_start_body(J.rb.region(kRegEval), J.nb_tile,
-                      J.rb.region(kRegInit), J.nb_vox, md, sc, sc->gn_cur,
+  finalize_start_body(J.rb.region(kRegEval), J.nb_tile, md, sc, sc->gn_cur,
                       J.log);
 }
 
@@ -934,12 +977,21 @@ hipError_t launch_ls_predict(float* Y, float* Z, ThomasTab tab, int n,
 hipError_t launch_eval(int dim, const float* T, const float* u, const int* K,
                        const Geom& g, const Model& md, float* grad,
                        float* dW, RedBuf rb, Scal* sc, hipStream_t s,
-                       bool finalize, int gn_it) {
+                       bool finalize, int gn_it, const CgStart* cs) {
   int nb = tile_blocks(g), nt = eval_threads(dim, md.nK);
   double* part = rb.region(kRegEval);
   const Scal* gate = finalize ? nullptr : sc;
-  STML_TILE_DISPATCH(dim, md.reg, eval_kernel, nb, nt, s, T, u, K, g, md,
-                     grad, dW, part, gn_it, gate);
+  if (cs && !grad) return hipErrorInvalidValue;
+  const CgStart none{nullptr, nullptr, nullptr, nullptr};
+  const CgStart c0 = cs ? *cs : none;
+  decltype(&eval_kernel<2, 0, false>) kern;
+  if (dim == 2)
+    kern = md.reg == 0 ? (cs ? eval_kernel<2, 0, true> : eval_kernel<2, 0, false>)
+                       : (cs ? eval_kernel<2, 1, true> : eval_kernel<2, 1, false>);
+  else
+    kern = md.reg == 0 ? (cs ? eval_kernel<3, 0, true> : eval_kernel<3, 0, false>)
+                       : (cs ? eval_kernel<3, 1, true> : eval_kernel<3, 1, false>);
+  kern<<<nb, nt, 0, s>>>(T, u, K, g, md, grad, dW, part, gn_it, gate, c0);
   if (finalize)
     finalize_eval_kernel<<<1, 256, 0, s>>>(part, nb, md, sc);
   return hipGetLastError();
@@ -975,11 +1027,10 @@ hipError_t launch_ls_accept(float* u, const float* delta, const int* K,
   return hipGetLastError();
 }
 
-hipError_t launch_finalize_start(RedBuf rb, int ev_nb, int in_nb,
-                                 const Model& md, Scal* sc, int gn_it,
-                                 GNLog* log, hipStream_t s) {
-  finalize_start_kernel<<<1, 256, 0, s>>>(rb.region(kRegEval), ev_nb,
-                                          rb.region(kRegInit), in_nb, md, sc,
+hipError_t launch_finalize_start(RedBuf rb, int ev_nb, const Model& md,
+                                 Scal* sc, int gn_it, GNLog* log,
+                                 hipStream_t s) {
+  finalize_start_kernel<<<1, 256, 0, s>>>(rb.region(kRegEval), ev_nb, md, sc,
                                           gn_it, log);
   return hipGetLastError();
 }

@@ -13,7 +13,7 @@ namespace stml {
 // a consumer can read its producer's slots after the next kernel wrote its
 // own.  A region holds up to 16 values x 1024 blocks.
 constexpr size_t kRegionSlots = (size_t)16 * 1024;
-enum { kRegEval, kRegInit, kRegHv, kRegUpdate, kRegTrial, kRegTest, kRegCount };
+enum { kRegEval, kRegHv, kRegUpdate, kRegTrial, kRegTest, kRegCount };
 constexpr size_t kRedSlots = kRegionSlots * kRegCount;
 struct RedBuf {
   double* part;         // kRedSlots doubles
@@ -52,13 +52,25 @@ hipError_t launch_prolong(int dim, const float* coarse, float* fine,
                           int fields, const Geom& gc, const Geom& gf,
                           hipStream_t s);
 
+// Start of the Jacobi-PCG, formed by the evaluation from the gradient it
+// writes: r = -g, z = M^-1 r and the per-voxel sums S_z ([N]) and V_z
+// ([D][N]).
+struct CgStart {
+  float* r;
+  float* z;
+  double* Sz;
+  double* Vz;
+};
 // finalize = false leaves the partials for the CG start to reduce.
 // gn_it: Gauss-Newton iteration this launch belongs to (ignored when
 // finalize is set); the kernel does nothing if gn_it >= sc->gn_stop.
+// cs (needs grad): the evaluation also forms the CG start; its partials
+// then hold r.z and r.r after D, S, P.
 hipError_t launch_eval(int dim, const float* T, const float* u, const int* K,
                        const Geom& g, const Model& md, float* grad,
                        float* dW, RedBuf rb, Scal* sc, hipStream_t s,
-                       bool finalize, int gn_it);
+                       bool finalize, int gn_it,
+                       const CgStart* cs = nullptr);
 
 // Objective at u + t_i delta for kTrialSteps values of t (t = 0 allowed),
 // g.delta and max |delta|, for line-search sweep ls of iteration gn_it.
@@ -78,11 +90,11 @@ hipError_t launch_ls_accept(float* u, const float* delta, const int* K,
 // mode); -inf for none.
 hipError_t launch_gn_reset(Scal* sc, GNLog* log, int n, hipStream_t s,
                            double J_target = -INFINITY);
-// One block: objective of the evaluation (ev_nb partials) and the CG start
-// scalars (in_nb partials of the CG start kernel).
-hipError_t launch_finalize_start(RedBuf rb, int ev_nb, int in_nb,
-                                 const Model& md, Scal* sc, int gn_it,
-                                 GNLog* log, hipStream_t s);
+// One block: objective and CG start scalars from the partials of an
+// evaluation that formed the CG start (ev_nb blocks).
+hipError_t launch_finalize_start(RedBuf rb, int ev_nb, const Model& md,
+                                 Scal* sc, int gn_it, GNLog* log,
+                                 hipStream_t s);
 hipError_t launch_finalize_vhv(const double* part, int nb, Scal* sc,
                                hipStream_t s);
 
@@ -102,10 +114,6 @@ struct CgTiles {             // launch shape of the Hessian product
 // kHv3X x kHv3Y x kHv3Z) and of the voxel-major updates
 CgTiles cg_tiles(const Geom& g, int nK, int dim);
 int cg_tile_count(const Geom& g, int dim);
-hipError_t launch_cgv_init(int dim, const float* grad, const float* dW,
-                           const Geom& g, const Model& md, float* r, float* z,
-                           CgSums sums, RedBuf rb, Scal* sc, hipStream_t s,
-                           int gn_it, GNLog* log);
 // ev0/ev1 (optional): timed by the dispatch's own start/end timestamps
 hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
                           float* p_new, const float* dW, const Geom& g,
@@ -171,7 +179,8 @@ int elem_grid(long long count);
 hipError_t batch_gn_reset(const JobSet& js, int gn_max, hipStream_t s);
 hipError_t batch_eval(const JobSet& js, int nblocks, int dim, int reg,
                       hipStream_t s);
-hipError_t batch_cg_init(const JobSet& js, int nvox, int dim, hipStream_t s);
+// objective and CG start scalars of every running job (one block each)
+hipError_t batch_finalize_start(const JobSet& js, hipStream_t s);
 // x = 0 for every running job (CG with no iteration: cg_max = 0)
 hipError_t batch_zero_x(const JobSet& js, int nvox, int dim, hipStream_t s);
 hipError_t batch_cg_hvp(const JobSet& js, int nhv, int nvox, int dim, int reg,

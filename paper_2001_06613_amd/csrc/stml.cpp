@@ -420,12 +420,12 @@ int read_scal(stml_ctx* c) {
 // fields of D components): what the kernel must read and write once.
 double alg_bytes(int kernel, int D, int cg_it) {
   switch (kernel) {
-    case STML_K_EVAL: return 4.0 + 12.0 * D;      // T; u; dW, g
+    case STML_K_EVAL: return 4.0 + 20.0 * D;      // T; u; dW, g, r, z
     case STML_K_HESSVEC:                          // z (+p_old), dW; p, q
       return cg_it > 0 ? 20.0 * D : 16.0 * D;
     case STML_K_CG_UPDATE:                        // p, q, dW, r (+x); x, r, z
       return cg_it > 0 ? 32.0 * D : 28.0 * D;
-    case STML_K_CG_INIT: return 16.0 * D;         // g, dW; r, z
+    case STML_K_CG_INIT: return 0.0;              // scalars only
     case STML_K_TRIAL: return 4.0 + 12.0 * D;     // T; u, delta, g
     case STML_K_ACCEPT: return 12.0 * D;          // u, delta; u
     case STML_K_PREDICT: return 16.0 * D;         // read y, z; write z, y
@@ -533,16 +533,22 @@ int stage_frames(stml_ctx* c, const int* frames, int nk) {
   return STML_OK;
 }
 
-// Jacobi-PCG for H delta = -g at the evaluation just made (g, dW in
-// scratch), as part of Gauss-Newton iteration gn_it.  Enqueued only; the
-// scalars stay on the device.
+// The CG start the evaluation forms along with the gradient (r, z and the
+// per-voxel sums of z).
+CgStart cg_start(stml_ctx* c) {
+  return CgStart{c->r, c->z, c->sums.Sz, c->sums.Vz};
+}
+
+// Jacobi-PCG for H delta = -g at the evaluation just made (g, dW, and the
+// CG start r, z in scratch), as part of Gauss-Newton iteration gn_it.
+// Enqueued only; the scalars stay on the device.
 int enqueue_pcg(stml_ctx* c, int level, const Geom& g, const Model& md,
                 int gn_it) {
   const int D = c->d;
   const double vf = (double)md.nK * g.N;
   TIMED(STML_K_CG_INIT, level, vf,
-        launch_cgv_init(D, c->g, c->dW, g, md, c->r, c->z, c->sums, c->rb,
-                        c->sc, c->stream, gn_it, c->gnlog));
+        launch_finalize_start(c->rb, tile_blocks(g), md, c->sc, gn_it,
+                              c->gnlog, c->stream));
   if (c->o.cg_max == 0)   // no CG step: the direction is x0 = 0
     HIP_OK(launch_fill(c->x, (size_t)md.nK * D * g.N, 0.0f, c->stream));
   for (int it = 0; it < c->o.cg_max; ++it) {
@@ -605,10 +611,11 @@ int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
   ls_passes(o.ls_max, &passes, &steps);
   HIP_OK(launch_gn_reset(c->sc, c->gnlog, o.gn_max, c->stream,
                          o.parity_mode ? -INFINITY : J_target));
+  const CgStart cs = cg_start(c);
   for (int it = 0; it < o.gn_max; ++it) {
     TIMED(STML_K_EVAL, level, vf,
           launch_eval(D, T, u, Kdev, g, md, c->g, c->dW, c->rb, c->sc,
-                      c->stream, false, it));
+                      c->stream, false, it, &cs));
     int rc = enqueue_pcg(c, level, g, md, it);
     if (rc) return rc;
     for (size_t pi = 0; pi < passes.size(); ++pi) {
@@ -1484,8 +1491,9 @@ int stml_gn_direction(stml_ctx* c, int level, const int* frames, int nk,
   Geom g = geom_of(c, level);
   Model md = model_of(c, level, nk);
   HIP_OK(launch_gn_reset(c->sc, c->gnlog, 1, c->stream));
+  const CgStart cs = cg_start(c);
   HIP_OK(launch_eval(c->d, c->lv[level].T, u, c->kbuf, g, md, c->g, c->dW,
-                     c->rb, c->sc, c->stream, false, 0));
+                     c->rb, c->sc, c->stream, false, 0, &cs));
   rc = enqueue_pcg(c, level, g, md, 0);
   if (rc) return rc;
   HIP_OK(hipMemcpyAsync(delta, c->x, (size_t)nk * c->d * g.N * sizeof(float),
@@ -1618,8 +1626,9 @@ hipError_t batch_iteration(const JobSet& js, const int* tot, int dim,
                            const std::vector<LSPass>& passes,
                            const std::vector<std::vector<double>>& steps,
                            int* dstop, hipStream_t s) {
+  // the evaluation also forms the CG start (r, z, sums of z)
   hipError_t e = batch_eval(js, tot[kClsTile], dim, reg, s);
-  if (e == hipSuccess) e = batch_cg_init(js, tot[kClsVox], dim, s);
+  if (e == hipSuccess) e = batch_finalize_start(js, s);
   if (e == hipSuccess && o.cg_max == 0) e = batch_zero_x(js, tot[kClsVox], dim, s);
   for (int it = 0; e == hipSuccess && it < o.cg_max; ++it) {
     e = batch_cg_hvp(js, tot[kClsHv], tot[kClsVox], dim, reg, it,

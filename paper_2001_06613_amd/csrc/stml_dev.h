@@ -318,6 +318,14 @@ __device__ __forceinline__ double reg_diag_at(const Pos<D>& p, const Geom& g,
   return reg == 0 ? dd : dd * dd + dd;
 }
 
+// Jacobi diagonal factor of voxel p without the data term.
+template <int D>
+__device__ __forceinline__ double jacobi_rest(const Pos<D>& p, const Geom& g,
+                                              const Model& md) {
+  return md.alpha_hd * md.reg_scale * reg_diag_at<D>(p, g, md.reg) +
+         md.pen_diag;
+}
+
 // Bi/trilinear sample of one frame at x + u(x) with d/du, float64.
 template <int D>
 __device__ __forceinline__ void warp_sample(const float* __restrict__ T,
