@@ -431,30 +431,119 @@ __global__ __launch_bounds__(256) void finalize_start_kernel(
   finalize_start_body(ev_part, ev_nb, md, sc, gn_it, log);
 }
 
-struct Steps {
-  double t[kTrialSteps];
+// Totals of line-search sweep q (its objective values Jt at its steps, by
+// the exact quadratic expansion of S and P) and of sweep 0 (the reference
+// J0t = J(t = 0), the slope g.delta, max |delta| and sum delta^2).
+struct SweepTotals {
+  double Jt[kTrialSteps];
+  double J0t, slope, maxd, ssqd;
 };
 
-// Objective at u + t delta for kTrialSteps values of t in one sweep.  The
-// data term per voxel is sum (W - c)^2 - (sum (W - c))^2 / |K| with c the
-// voxel's value in the first frame of K (a shift against cancellation);
-// S and P are quadratic in t and are expanded exactly.  The per-step sums
-// live in LDS (one slot row per thread), which keeps register use low.  A
-// frame's loads (u, delta, g and both stencils) issue together, and in 2-D
-// the gathers of three steps at a time, so that an image frame costs three
-// dependent memory round trips instead of nine.
-template <int D, int REG>
+template <int NT>
+__device__ __forceinline__ void sweep_objectives(const double (&out)[NT + 9],
+                                                 int q, int ls_max,
+                                                 const Model& md,
+                                                 double (&Jt)[kTrialSteps]) {
+  const double sA = md.half_alpha_hd * md.reg_scale;
+#pragma unroll
+  for (int s = 0; s < NT; ++s) {
+    const double t = sweep_t(q, s, ls_max);
+    const double Dv = md.hd * out[s];
+    const double Sv =
+        sA * (out[NT] + 2.0 * t * out[NT + 1] + t * t * out[NT + 2]);
+    const double Pv = md.lam_hd * (out[NT + 3] + 2.0 * t * out[NT + 4] +
+                                   t * t * out[NT + 5]);
+    Jt[s] = Dv + Sv + Pv;
+  }
+}
+
+// LDS of sweep_totals (reused by the two reductions in turn)
+constexpr int kSweepLds = reduce_lds_doubles<kTrialSteps + 9>();
+
+__device__ SweepTotals sweep_totals(RedBuf rb, int nb, int q, int ls_max,
+                                    const Model& md, double* lds) {
+  constexpr int N0 = kSweep0Steps, N1 = kTrialSteps;
+  SweepTotals st;
+  double o0[N0 + 9];
+  reduce_partials_in<N0 + 9>(rb.region(kRegTrial), nb, 1u << (N0 + 7), o0,
+                             lds);
+  double J0[kTrialSteps];
+  sweep_objectives<N0>(o0, 0, ls_max, md, J0);
+  st.J0t = J0[0];
+  st.slope = o0[N0 + 6];
+  st.maxd = o0[N0 + 7];
+  st.ssqd = o0[N0 + 8];
+  if (q == 0) {
+#pragma unroll
+    for (int s = 0; s < kTrialSteps; ++s) st.Jt[s] = s < N0 ? J0[s] : 0.0;
+  } else {
+    double o1[N1 + 9];
+    reduce_partials_in<N1 + 9>(rb.region(trial_region(q)), nb,
+                               1u << (N1 + 7), o1, lds);
+    sweep_objectives<N1>(o1, q, ls_max, md, st.Jt);
+  }
+  return st;
+}
+
+// Armijo test J(t) <= J(0) + c1 t g.delta over the steps of sweep q in
+// order: the first accepted step's index (and its objective), or -1.
+__device__ __forceinline__ int sweep_decision(const SweepTotals& st, int q,
+                                              int ls_max, double c1,
+                                              double& Jacc) {
+  const int ns = sweep_steps(q);
+  int acc = -1;
+  // unrolled with constant indices: the totals stay in registers
+#pragma unroll
+  for (int s = 0; s < kTrialSteps; ++s) {
+    const double t = sweep_t(q, s, ls_max);
+    if (acc < 0 && s < ns && sweep_tests(q, s, ls_max) &&
+        st.Jt[s] <= st.J0t + c1 * t * st.slope) {
+      acc = s;
+      Jacc = st.Jt[s];
+    }
+  }
+  return acc;
+}
+
+__device__ __forceinline__ int sweep_accepts(RedBuf rb, int nb, int q,
+                                             int ls_max, double c1,
+                                             const Model& md, double& Jacc,
+                                             double* lds) {
+  const SweepTotals st = sweep_totals(rb, nb, q, ls_max, md, lds);
+  return sweep_decision(st, q, ls_max, c1, Jacc);
+}
+
+// Objective at u + t delta for the NT steps of line-search sweep `sweep`
+// (sweep 0: t = 0 and t = 1, one dependent round of gathers per image
+// frame).  The data term per voxel is sum (W - c)^2 - (sum (W - c))^2 / |K|
+// with c the voxel's value in the first frame of K (a shift against
+// cancellation); S and P are quadratic in t and are expanded exactly.  The
+// per-step sums live in LDS (one slot row per thread), which keeps register
+// use low.  A frame's loads (u, delta, g and both stencils) issue together,
+// and in 2-D the gathers of up to three steps at a time, so that an image
+// frame of a five-step sweep costs three dependent memory round trips
+// instead of nine.
+template <int D, int REG, int NT>
 __device__ __forceinline__ void trial_body(
     const float* __restrict__ T, const float* __restrict__ u,
     const float* __restrict__ dl, const float* __restrict__ gr,
-    const int* __restrict__ K, const Geom& g, const Model& md,
-    const Steps& st, double* __restrict__ part, int gn_it, LSPass ls,
-    const Scal* __restrict__ sc, const GNLog* __restrict__ log, Blk blk) {
-  if (gn_it >= sc->gn_stop) return;
-  if (ls.p > 0 && log[gn_it].next_pass != ls.p) return;
-  constexpr int NT = kTrialSteps;
+    const int* __restrict__ K, const Geom& g, const Model& md, int sweep,
+    int ls_max, double c1, RedBuf rb, int nb, int gn_it,
+    const Scal* __restrict__ sc, GNLog* __restrict__ log, Blk blk) {
   constexpr int NV = 2 * NT + 2 * D;
   __shared__ double xs[D == 2 ? 8 : 4][kWave][NV];
+  if (gn_it >= sc->gn_stop) return;
+  if constexpr (NT == kTrialSteps) {
+    // a sweep >= 1 runs only after its predecessor ran and accepted no step
+    static_assert(sizeof(xs) / sizeof(double) >= kSweepLds, "LDS");
+    if (sweep >= 2 && log[gn_it].next_pass < sweep - 1) return;
+    double Jacc;
+    if (sweep_accepts(rb, nb, sweep - 1, ls_max, c1, md, Jacc,
+                      &xs[0][0][0]) >= 0)
+      return;
+    if (blk.id == 0 && threadIdx.x == 0) log[gn_it].next_pass = sweep;
+  }
+  double* __restrict__ part = rb.region(trial_region(sweep));
   const int lane = threadIdx.x & (kWave - 1);
   const int w = wave_id();
   const int G = blockDim.x / kWave;
@@ -499,16 +588,20 @@ __device__ __forceinline__ void trial_body(
         rC = valid ? rC + ww : rC;
       }
       const float* Tk = T + (size_t)k * N;
-      constexpr int TG = D == 2 ? 3 : 1;   // steps whose loads issue together
+      // steps whose loads issue together: three in a five-step image sweep;
+      // one at a time in the two-step sweep (two in flight measured
+      // slower under the register cap)
+      constexpr int TG = D == 2 ? (NT < 3 ? 1 : 3) : 1;
 #pragma unroll 1
       for (int s0 = 0; s0 < NT; s0 += TG) {
         double wvs[TG];
 #pragma unroll
         for (int kk = 0; kk < TG; ++kk) {
           const int s = s0 + kk < NT ? s0 + kk : NT - 1;
+          const double ts = sweep_t(sweep, s, ls_max);
           double ut[D];
 #pragma unroll
-          for (int a = 0; a < D; ++a) ut[a] = uv[a] + st.t[s] * dv[a];
+          for (int a = 0; a < D; ++a) ut[a] = uv[a] + ts * dv[a];
           wvs[kk] = warp_value<D>(Tk, g, p, ut) - c;
         }
 #pragma unroll
@@ -566,82 +659,61 @@ __device__ __forceinline__ void trial_body(
   block_partials<NT + 9>(vals, 1u << (NT + 7), part, blk);
 }
 
-template <int D, int REG>
-__global__ __launch_bounds__(D == 2 ? 512 : 256) void trial_kernel(
+// Two 8-wave blocks per compute unit in 2-D: at most 128 registers.
+template <int D, int REG, int NT>
+__global__ __launch_bounds__(D == 2 ? 512 : 256, D == 2 ? 4 : 1) void trial_kernel(
     const float* __restrict__ T, const float* __restrict__ u,
     const float* __restrict__ dl, const float* __restrict__ gr,
-    const int* __restrict__ K, Geom g, Model md, Steps st,
-    double* __restrict__ part, int gn_it, LSPass ls,
-    const Scal* __restrict__ sc, const GNLog* __restrict__ log) {
-  trial_body<D, REG>(T, u, dl, gr, K, g, md, st, part, gn_it, ls, sc, log,
-                     grid_blk());
+    const int* __restrict__ K, Geom g, Model md, int p, int ls_max, double c1,
+    RedBuf rb, int nb, int gn_it, const Scal* __restrict__ sc,
+    GNLog* __restrict__ log) {
+  trial_body<D, REG, NT>(T, u, dl, gr, K, g, md, p, ls_max, c1, rb, nb, gn_it,
+                         sc, log, grid_blk());
 }
 
-// Armijo decision of sweep ls and, if a step passes, u[K[j]] += t delta_j.
-// Every block first totals the trial sweep's partials itself (the
-// objective at the sweep's steps, g.delta, max |delta|, sum delta^2) and so
-// takes the same decision from the same values; block 0 records them.
-// Flags a later block of this kernel might read (next_pass, gn_stop) are
-// only written in ways that leave such a block's work unchanged; each block
-// reads them once, so that its threads agree.
+// Armijo decision after the sweeps and, if a step passes, u[K[j]] +=
+// t delta_j.  The last sweep that ran is the one whose predecessors all
+// failed; every block totals its partials (and those of sweep 0) itself
+// and so takes the same decision from the same values; block 0 records
+// them.  The flag a later block of this kernel might read (gn_stop) is only
+// written in a way that leaves such a block's work unchanged; each block
+// reads it once, so that its threads agree.
 __device__ __forceinline__ void ls_accept_body(
     float* __restrict__ u, const float* __restrict__ dl,
-    const int* __restrict__ K, int nK, int dim, long long N, const Steps& st,
-    LSPass ls, int ls_max, double c1, int fixed, double tol_J, double tol_u,
-    const double* __restrict__ tpart, int tnb, const Model& md, int gn_it,
-    Scal* __restrict__ sc, GNLog* __restrict__ log, Blk blk) {
-  __shared__ int skip;
+    const int* __restrict__ K, int nK, int dim, long long N, int ls_max,
+    double c1, int fixed, double tol_J, double tol_u, RedBuf rb, int tnb,
+    const Model& md, int gn_it, Scal* __restrict__ sc,
+    GNLog* __restrict__ log, Blk blk) {
+  __shared__ int skip, q;
+  __shared__ double lds[kSweepLds];
   GNLog* L = log + gn_it;
-  if (threadIdx.x == 0)
-    skip = gn_it >= sc->gn_stop || (ls.p > 0 && L->next_pass != ls.p);
+  if (threadIdx.x == 0) {
+    skip = gn_it >= sc->gn_stop;
+    q = L->next_pass;
+  }
   __syncthreads();
   if (skip) return;
-  constexpr int NT = kTrialSteps;
-  double out[NT + 9];
-  reduce_partials<NT + 9>(tpart, tnb, 1u << (NT + 7), out);
-  double Jt[NT];
-  const double sA = md.half_alpha_hd * md.reg_scale;
-#pragma unroll
-  for (int s = 0; s < NT; ++s) {
-    const double t = st.t[s];
-    const double Dv = md.hd * out[s];
-    const double Sv =
-        sA * (out[NT] + 2.0 * t * out[NT + 1] + t * t * out[NT + 2]);
-    const double Pv = md.lam_hd * (out[NT + 3] + 2.0 * t * out[NT + 4] +
-                                   t * t * out[NT + 5]);
-    Jt[s] = Dv + Sv + Pv;
+  const int qs = q;
+  const SweepTotals st = sweep_totals(rb, tnb, qs, ls_max, md, lds);
+  double Jacc = 0.0;
+  const int sacc = sweep_decision(st, qs, ls_max, c1, Jacc);
+  if (blk.id == 0 && threadIdx.x == 0) {
+    L->J0t = st.J0t;
+    L->slope = st.slope;
+    L->maxd = st.maxd;
+    L->ssqd = st.ssqd;
   }
-  const double J0t = ls.p == 0 ? Jt[0] : L->J0t;
-  const double slope = ls.p == 0 ? out[NT + 6] : L->slope;
-  if (ls.p == 0 && blk.id == 0 && threadIdx.x == 0) {
-    L->J0t = Jt[0];
-    L->slope = out[NT + 6];
-    L->maxd = out[NT + 7];
-    L->ssqd = out[NT + 8];
-  }
-  double tacc = -1.0, Jacc = 0.0;
-#pragma unroll
-  for (int s = 0; s < NT; ++s) {
-    const int e = ls.e0 + (s - ls.base);
-    if (tacc < 0.0 && s >= ls.base && e <= ls_max &&
-        Jt[s] <= J0t + c1 * st.t[s] * slope) {
-      tacc = st.t[s];
-      Jacc = Jt[s];
-    }
-  }
-  if (tacc < 0.0) {
+  if (sacc < 0) {
+    // the last sweep failed too: no step
     if (blk.id == 0 && threadIdx.x == 0) {
-      if (ls.last) {
-        L->status = 1;
-        L->t = 0.0;
-        L->cg = sc->iters;
-        sc->gn_stop = gn_it;
-      } else {
-        L->next_pass = ls.p + 1;
-      }
+      L->status = 1;
+      L->t = 0.0;
+      L->cg = sc->iters;
+      sc->gn_stop = gn_it;
     }
     return;
   }
+  const double tacc = sweep_t(qs, sacc, ls_max);
   size_t count = (size_t)nK * dim * N;
   size_t stride = (size_t)blk.n * blockDim.x;
   for (size_t e = (size_t)blk.id * blockDim.x + threadIdx.x; e < count;
@@ -659,7 +731,7 @@ __device__ __forceinline__ void ls_accept_body(
     L->Jacc = Jacc;
     L->cg = sc->iters;
     L->status = breakdown ? 2 : 0;
-    const double rms = sqrt(out[NT + 8] / (double)count);
+    const double rms = sqrt(st.ssqd / (double)count);
     bool stop = breakdown ||
                 (!fixed && (((L->J - Jacc) <= tol_J * fabs(L->J) &&
                              tacc * rms <= tol_u) ||
@@ -670,12 +742,11 @@ __device__ __forceinline__ void ls_accept_body(
 
 __global__ __launch_bounds__(256) void ls_accept_kernel(
     float* __restrict__ u, const float* __restrict__ dl,
-    const int* __restrict__ K, int nK, int dim, long long N, Steps st,
-    LSPass ls, int ls_max, double c1, int fixed, double tol_J, double tol_u,
-    const double* __restrict__ tpart, int tnb, Model md, int gn_it,
-    Scal* __restrict__ sc, GNLog* __restrict__ log) {
-  ls_accept_body(u, dl, K, nK, dim, N, st, ls, ls_max, c1, fixed, tol_J,
-                 tol_u, tpart, tnb, md, gn_it, sc, log, grid_blk());
+    const int* __restrict__ K, int nK, int dim, long long N, int ls_max,
+    double c1, int fixed, double tol_J, double tol_u, RedBuf rb, int tnb,
+    Model md, int gn_it, Scal* __restrict__ sc, GNLog* __restrict__ log) {
+  ls_accept_body(u, dl, K, nK, dim, N, ls_max, c1, fixed, tol_J, tol_u, rb,
+                 tnb, md, gn_it, sc, log, grid_blk());
 }
 
 // Start of a registration: every Gauss-Newton iteration enabled, logs
@@ -821,28 +892,27 @@ __global__ __launch_bounds__(256) void start_batch_kernel(JobSet js) {
                       J.log);
 }
 
-template <int D, int REG>
-__global__ __launch_bounds__(D == 2 ? 512 : 256) void trial_batch_kernel(
-    JobSet js, Steps st, LSPass ls) {
+template <int D, int REG, int NT>
+__global__ __launch_bounds__(D == 2 ? 512 : 256, D == 2 ? 4 : 1) void trial_batch_kernel(
+    JobSet js, int p, int ls_max, double c1) {
   Blk blk;
   const Job& J = job_of(js, kClsTile, blk);
   const Geom g = J.g;
   const Model md = J.md;
   Scal* sc = J.sc;
-  trial_body<D, REG>(J.T, J.u, J.x, J.grad, J.K, g, md, st,
-                     J.rb.region(kRegTrial), sc->gn_cur, ls, sc, J.log, blk);
+  trial_body<D, REG, NT>(J.T, J.u, J.x, J.grad, J.K, g, md, p, ls_max, c1,
+                         J.rb, J.nb_tile, sc->gn_cur, sc, J.log, blk);
 }
 
 __global__ __launch_bounds__(256) void accept_batch_kernel(
-    JobSet js, Steps st, LSPass ls, int ls_max, double c1, int fixed,
-    double tol_J, double tol_u) {
+    JobSet js, int ls_max, double c1, int fixed, double tol_J, double tol_u) {
   Blk blk;
   const Job& J = job_of(js, kClsElem, blk);
   Scal* sc = J.sc;
   const Model md = J.md;
-  ls_accept_body(J.u, J.x, J.K, md.nK, geom_dim(J.g), J.g.N, st, ls, ls_max,
-                 c1, fixed, tol_J, tol_u, J.rb.region(kRegTrial), J.nb_tile,
-                 md, sc->gn_cur, sc, J.log, blk);
+  ls_accept_body(J.u, J.x, J.K, md.nK, geom_dim(J.g), J.g.N, ls_max, c1,
+                 fixed, tol_J, tol_u, J.rb, J.nb_tile, md, sc->gn_cur, sc,
+                 J.log, blk);
 }
 
 // Start of a batched registration: per problem, every iteration enabled,
@@ -893,22 +963,41 @@ hipError_t batch_finalize_start(const JobSet& js, hipStream_t s) {
   return hipGetLastError();
 }
 
-hipError_t batch_trial(const JobSet& js, int ntile, int dim, int reg,
-                       const double* t, LSPass ls, hipStream_t s) {
-  Steps st;
-  for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
-  STML_TILE_DISPATCH(dim, reg, trial_batch_kernel, ntile,
-                     tile_threads(dim, 0), s, js, st, ls);
+// (dimension, regulariser, steps of the sweep) specialisations of the
+// trial sweep kernels.
+#define STML_TRIAL_DISPATCH(dim, reg, p, KERNEL, GRID, BLOCK, STREAM, ...)   \
+  do {                                                                    \
+    if ((p) == 0)                                                         \
+      STML_TRIAL_DISPATCH_NT(dim, reg, kSweep0Steps, KERNEL, GRID, BLOCK, \
+                             STREAM, __VA_ARGS__);                        \
+    else                                                                  \
+      STML_TRIAL_DISPATCH_NT(dim, reg, kTrialSteps, KERNEL, GRID, BLOCK,  \
+                             STREAM, __VA_ARGS__);                        \
+  } while (0)
+#define STML_TRIAL_DISPATCH_NT(dim, reg, NT, KERNEL, GRID, BLOCK, STREAM, ...) \
+  do {                                                                    \
+    if ((dim) == 2 && (reg) == 0)                                         \
+      KERNEL<2, 0, NT><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);          \
+    else if ((dim) == 2)                                                  \
+      KERNEL<2, 1, NT><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);          \
+    else if ((reg) == 0)                                                  \
+      KERNEL<3, 0, NT><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);          \
+    else                                                                  \
+      KERNEL<3, 1, NT><<<GRID, BLOCK, 0, STREAM>>>(__VA_ARGS__);          \
+  } while (0)
+
+hipError_t batch_trial(const JobSet& js, int ntile, int dim, int reg, int p,
+                       int ls_max, double c1, hipStream_t s) {
+  STML_TRIAL_DISPATCH(dim, reg, p, trial_batch_kernel, ntile,
+                      tile_threads(dim, 0), s, js, p, ls_max, c1);
   return hipGetLastError();
 }
 
-hipError_t batch_accept(const JobSet& js, int nelem, const double* t,
-                        LSPass ls, int ls_max, double c1, int fixed,
-                        double tol_J, double tol_u, hipStream_t s) {
-  Steps st;
-  for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
-  accept_batch_kernel<<<nelem, 256, 0, s>>>(js, st, ls, ls_max, c1, fixed,
-                                            tol_J, tol_u);
+hipError_t batch_accept(const JobSet& js, int nelem, int ls_max, double c1,
+                        int fixed, double tol_J, double tol_u,
+                        hipStream_t s) {
+  accept_batch_kernel<<<nelem, 256, 0, s>>>(js, ls_max, c1, fixed, tol_J,
+                                            tol_u);
   return hipGetLastError();
 }
 
@@ -999,31 +1088,26 @@ hipError_t launch_eval(int dim, const float* T, const float* u, const int* K,
 
 hipError_t launch_trial(int dim, const float* T, const float* u,
                         const float* delta, const float* grad, const int* K,
-                        const Geom& g, const Model& md, const double* t,
-                        RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
-                        LSPass ls, GNLog* log) {
-  Steps st;
-  for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
+                        const Geom& g, const Model& md, int p, int ls_max,
+                        double c1, RedBuf rb, Scal* sc, hipStream_t s,
+                        int gn_it, GNLog* log) {
   int nb = tile_blocks(g);
   int nt = tile_threads(dim, md.nK);
-  double* part = rb.region(kRegTrial);
-  STML_TILE_DISPATCH(dim, md.reg, trial_kernel, nb, nt, s, T, u, delta, grad,
-                     K, g, md, st, part, gn_it, ls, sc, log);
+  STML_TRIAL_DISPATCH(dim, md.reg, p, trial_kernel, nb, nt, s, T, u, delta,
+                      grad, K, g, md, p, ls_max, c1, rb, nb, gn_it, sc, log);
   return hipGetLastError();
 }
 
 hipError_t launch_ls_accept(float* u, const float* delta, const int* K,
-                            const Geom& g, const Model& md, const double* t,
-                            LSPass ls, int ls_max, double c1, int fixed,
-                            double tol_J, double tol_u, RedBuf rb, int gn_it,
-                            Scal* sc, GNLog* log, hipStream_t s) {
-  Steps st;
-  for (int i = 0; i < kTrialSteps; ++i) st.t[i] = t[i];
+                            const Geom& g, const Model& md, int ls_max,
+                            double c1, int fixed, double tol_J, double tol_u,
+                            RedBuf rb, int gn_it, Scal* sc, GNLog* log,
+                            hipStream_t s) {
   const int dim = geom_dim(g);
   size_t count = (size_t)md.nK * dim * g.N;
   ls_accept_kernel<<<elem_blocks(count), 256, 0, s>>>(
-      u, delta, K, md.nK, dim, g.N, st, ls, ls_max, c1, fixed, tol_J, tol_u,
-      rb.region(kRegTrial), tile_blocks(g), md, gn_it, sc, log);
+      u, delta, K, md.nK, dim, g.N, ls_max, c1, fixed, tol_J, tol_u, rb,
+      tile_blocks(g), md, gn_it, sc, log);
   return hipGetLastError();
 }
 

@@ -13,7 +13,22 @@ namespace stml {
 // a consumer can read its producer's slots after the next kernel wrote its
 // own.  A region holds up to 16 values x 1024 blocks.
 constexpr size_t kRegionSlots = (size_t)16 * 1024;
-enum { kRegEval, kRegHv, kRegUpdate, kRegTrial, kRegTest, kRegCount };
+// Line-search sweeps: sweep 0 in kRegTrial, later sweeps alternate between
+// kRegTrialOdd and kRegTrialEven, so that a sweep can read its
+// predecessor's slots while it writes its own.
+enum {
+  kRegEval,
+  kRegHv,
+  kRegUpdate,
+  kRegTrial,
+  kRegTrialOdd,
+  kRegTrialEven,
+  kRegTest,
+  kRegCount
+};
+__host__ __device__ inline int trial_region(int p) {
+  return p == 0 ? kRegTrial : (p & 1) ? kRegTrialOdd : kRegTrialEven;
+}
 constexpr size_t kRedSlots = kRegionSlots * kRegCount;
 struct RedBuf {
   double* part;         // kRedSlots doubles
@@ -72,20 +87,23 @@ hipError_t launch_eval(int dim, const float* T, const float* u, const int* K,
                        bool finalize, int gn_it,
                        const CgStart* cs = nullptr);
 
-// Objective at u + t_i delta for kTrialSteps values of t (t = 0 allowed),
-// g.delta and max |delta|, for line-search sweep ls of iteration gn_it.
+// Line-search sweep p of iteration gn_it (see sweep_t): objective at
+// u + t delta for the sweep's steps, g.delta, max |delta| and sum delta^2.
+// A sweep p >= 1 runs only if sweep p - 1 ran and accepted no step (every
+// block decides that from the partials itself).
 hipError_t launch_trial(int dim, const float* T, const float* u,
                         const float* delta, const float* grad, const int* K,
-                        const Geom& g, const Model& md, const double* t,
-                        RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
-                        LSPass ls, GNLog* log);
-// Armijo decision of sweep ls from the trial sweep's partials; u[K[j]] +=
-// t delta_j for the accepted t.
+                        const Geom& g, const Model& md, int p, int ls_max,
+                        double c1, RedBuf rb, Scal* sc, hipStream_t s,
+                        int gn_it, GNLog* log);
+// Armijo decision after the sweeps: the first accepted step of the last
+// sweep that ran; u[K[j]] += t delta_j, the log entry and the Gauss-Newton
+// stop tests.  No step: status 1 and the iteration ends the registration.
 hipError_t launch_ls_accept(float* u, const float* delta, const int* K,
-                            const Geom& g, const Model& md, const double* t,
-                            LSPass ls, int ls_max, double c1, int fixed,
-                            double tol_J, double tol_u, RedBuf rb, int gn_it,
-                            Scal* sc, GNLog* log, hipStream_t s);
+                            const Geom& g, const Model& md, int ls_max,
+                            double c1, int fixed, double tol_J, double tol_u,
+                            RedBuf rb, int gn_it, Scal* sc, GNLog* log,
+                            hipStream_t s);
 // J_target: the registration stops once J <= J_target (not in parity
 // mode); -inf for none.
 hipError_t launch_gn_reset(Scal* sc, GNLog* log, int n, hipStream_t s,
@@ -187,11 +205,10 @@ hipError_t batch_cg_hvp(const JobSet& js, int nhv, int nvox, int dim, int reg,
                         int it, int fixed, double rtol, hipStream_t s);
 hipError_t batch_cg_update(const JobSet& js, int nvox, int dim, int it,
                            hipStream_t s);
-hipError_t batch_trial(const JobSet& js, int ntile, int dim, int reg,
-                       const double* t, LSPass ls, hipStream_t s);
-hipError_t batch_accept(const JobSet& js, int nelem, const double* t,
-                        LSPass ls, int ls_max, double c1, int fixed,
-                        double tol_J, double tol_u, hipStream_t s);
+hipError_t batch_trial(const JobSet& js, int ntile, int dim, int reg, int p,
+                       int ls_max, double c1, hipStream_t s);
+hipError_t batch_accept(const JobSet& js, int nelem, int ls_max, double c1,
+                        int fixed, double tol_J, double tol_u, hipStream_t s);
 hipError_t batch_advance(const JobSet& js, int* stop_out, hipStream_t s);
 
 // ------------------------------------------------ affine model (affine.hip)

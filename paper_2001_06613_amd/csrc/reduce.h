@@ -62,9 +62,30 @@ __device__ void block_partials(const double (&vals)[NV], unsigned maxmask,
 // fixed strands (strand v: slots v, v + 256, ...), whichever threads
 // compute them, and the strands then in a fixed tree.  Either way the order
 // depends on nb only, not on the block size.
+// LDS a reduction of NV values needs beyond 64 slots (reduce_partials_in).
+template <int NV>
+constexpr int reduce_lds_doubles() {
+  return NV * 4 * kWave + NV;
+}
+
+template <int NV>
+__device__ void reduce_partials_in(const double* __restrict__ part, int nb,
+                                   unsigned maxmask, double (&out)[NV],
+                                   double* lds);
+
 template <int NV>
 __device__ void reduce_partials(const double* __restrict__ part, int nb,
                                 unsigned maxmask, double (&out)[NV]) {
+  __shared__ double lds[reduce_lds_doubles<NV>()];
+  reduce_partials_in<NV>(part, nb, maxmask, out, lds);
+}
+
+// The same with the caller's LDS (reduce_lds_doubles<NV>() doubles), which
+// it may reuse once this returns.
+template <int NV>
+__device__ void reduce_partials_in(const double* __restrict__ part, int nb,
+                                   unsigned maxmask, double (&out)[NV],
+                                   double* lds) {
   if (nb <= kWave) {
     // few slots: every wave sums them itself (lane l takes slot l), without
     // LDS or barriers; the order depends on nb only (more slots would be
@@ -88,8 +109,8 @@ __device__ void reduce_partials(const double* __restrict__ part, int nb,
     return;
   }
   constexpr int kStrands = 4 * kWave;
-  __shared__ double red[NV][kStrands];
-  __shared__ double tot[NV];
+  double(*red)[kStrands] = reinterpret_cast<double(*)[kStrands]>(lds);
+  double* tot = lds + NV * kStrands;
   for (int v0 = threadIdx.x; v0 < kStrands; v0 += blockDim.x) {
     double acc[NV];
 #pragma unroll

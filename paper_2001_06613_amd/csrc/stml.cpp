@@ -567,29 +567,6 @@ int enqueue_pcg(stml_ctx* c, int level, const Geom& g, const Model& md,
   return STML_OK;
 }
 
-// Armijo sweeps of one Gauss-Newton iteration: t = 1, 1/2, ..., 2^-ls_max,
-// kTrialSteps per sweep; the first sweep also evaluates t = 0 so that the
-// comparison uses one formula on both sides.
-int ls_passes(int ls_max, std::vector<LSPass>* passes,
-              std::vector<std::vector<double>>* steps) {
-  int next = 0;
-  for (int p = 0; next <= ls_max; ++p) {
-    LSPass ls{p, p == 0 ? 1 : 0, next, 0};
-    std::vector<double> ts(kTrialSteps);
-    int cnt = 0;
-    if (p == 0) ts[cnt++] = 0.0;
-    while (cnt < kTrialSteps) {
-      int e = next <= ls_max ? next : ls_max;
-      ts[cnt++] = std::ldexp(1.0, -e);
-      if (next <= ls_max) ++next;
-    }
-    ls.last = next > ls_max;
-    passes->push_back(ls);
-    steps->push_back(ts);
-  }
-  return (int)passes->size();
-}
-
 int gn_log(stml_ctx* c, int nK, long long N, stml_gir_log* log);
 
 // Gauss-Newton on the frames Kdev (nK of them) of `level`, updating u in
@@ -606,9 +583,9 @@ int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
   const Model md = model_of(c, level, nK);
   const float* T = c->lv[level].T;
   const double vf = (double)nK * g.N;
-  std::vector<LSPass> passes;
-  std::vector<std::vector<double>> steps;
-  ls_passes(o.ls_max, &passes, &steps);
+  // Armijo: every sweep is enqueued (a sweep whose predecessor accepted a
+  // step exits at once), then one decision
+  const int sweeps = sweep_count(o.ls_max);
   HIP_OK(launch_gn_reset(c->sc, c->gnlog, o.gn_max, c->stream,
                          o.parity_mode ? -INFINITY : J_target));
   const CgStart cs = cg_start(c);
@@ -618,16 +595,14 @@ int gauss_newton(stml_ctx* c, int level, const int* Kdev, int nK, float* u,
                       c->stream, false, it, &cs));
     int rc = enqueue_pcg(c, level, g, md, it);
     if (rc) return rc;
-    for (size_t pi = 0; pi < passes.size(); ++pi) {
+    for (int p = 0; p < sweeps; ++p)
       TIMED(STML_K_TRIAL, level, vf,
-            launch_trial(D, T, u, c->x, c->g, Kdev, g, md, steps[pi].data(),
-                         c->rb, c->sc, c->stream, it, passes[pi], c->gnlog));
-      TIMED(STML_K_ACCEPT, level, vf,
-            launch_ls_accept(u, c->x, Kdev, g, md, steps[pi].data(),
-                             passes[pi], o.ls_max, o.c1, o.parity_mode,
-                             o.tol_J, o.tol_u, c->rb, it, c->sc, c->gnlog,
-                             c->stream));
-    }
+            launch_trial(D, T, u, c->x, c->g, Kdev, g, md, p, o.ls_max, o.c1,
+                         c->rb, c->sc, c->stream, it, c->gnlog));
+    TIMED(STML_K_ACCEPT, level, vf,
+          launch_ls_accept(u, c->x, Kdev, g, md, o.ls_max, o.c1,
+                           o.parity_mode, o.tol_J, o.tol_u, c->rb, it, c->sc,
+                           c->gnlog, c->stream));
     if (!o.parity_mode) {
       rc = read_scal(c);
       if (rc) return rc;
@@ -1622,10 +1597,8 @@ size_t batch_layout(int count, char* base, stml_batch* b) {
 
 // One Gauss-Newton iteration of every problem of js.
 hipError_t batch_iteration(const JobSet& js, const int* tot, int dim,
-                           int reg, const stml_opts& o,
-                           const std::vector<LSPass>& passes,
-                           const std::vector<std::vector<double>>& steps,
-                           int* dstop, hipStream_t s) {
+                           int reg, const stml_opts& o, int* dstop,
+                           hipStream_t s) {
   // the evaluation also forms the CG start (r, z, sums of z)
   hipError_t e = batch_eval(js, tot[kClsTile], dim, reg, s);
   if (e == hipSuccess) e = batch_finalize_start(js, s);
@@ -1635,13 +1608,12 @@ hipError_t batch_iteration(const JobSet& js, const int* tot, int dim,
                      o.parity_mode, o.cg_rtol, s);
     if (e == hipSuccess) e = batch_cg_update(js, tot[kClsVox], dim, it, s);
   }
-  for (size_t pi = 0; e == hipSuccess && pi < passes.size(); ++pi) {
-    e = batch_trial(js, tot[kClsTile], dim, reg, steps[pi].data(),
-                    passes[pi], s);
-    if (e == hipSuccess)
-      e = batch_accept(js, tot[kClsElem], steps[pi].data(), passes[pi],
-                       o.ls_max, o.c1, o.parity_mode, o.tol_J, o.tol_u, s);
-  }
+  const int sweeps = sweep_count(o.ls_max);
+  for (int p = 0; e == hipSuccess && p < sweeps; ++p)
+    e = batch_trial(js, tot[kClsTile], dim, reg, p, o.ls_max, o.c1, s);
+  if (e == hipSuccess)
+    e = batch_accept(js, tot[kClsElem], o.ls_max, o.c1, o.parity_mode,
+                     o.tol_J, o.tol_u, s);
   if (e == hipSuccess) e = batch_advance(js, dstop, s);
   return e;
 }
@@ -1685,9 +1657,6 @@ int batch_register(stml_batch* b, int level, int q) {
                          (size_t)kClsCount * (S + 1) * sizeof(int),
                          hipMemcpyHostToDevice, b->stream));
   const JobSet js{b->djobs, b->dfirst, S};
-  std::vector<LSPass> passes;
-  std::vector<std::vector<double>> steps;
-  ls_passes(o.ls_max, &passes, &steps);
   const int reg = o.regulariser;
   const int dim = b->c[0]->d;
   BHIP_OK(batch_gn_reset(js, o.gn_max, b->stream));
@@ -1695,8 +1664,8 @@ int batch_register(stml_batch* b, int level, int q) {
   hipGraphExec_t exec = nullptr;
   if (b->graph && o.gn_max > 0) {
     BHIP_OK(hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal));
-    hipError_t e = batch_iteration(js, tot, dim, reg, o, passes, steps,
-                                   b->dstop, b->stream);
+    hipError_t e = batch_iteration(js, tot, dim, reg, o, b->dstop,
+                                   b->stream);
     hipError_t e2 = hipStreamEndCapture(b->stream, &graph);
     if (e == hipSuccess) e = e2;
     if (e == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
@@ -1708,8 +1677,7 @@ int batch_register(stml_batch* b, int level, int q) {
   hipError_t e = hipSuccess;
   for (int it = 0; it < o.gn_max && e == hipSuccess; ++it) {
     e = exec ? hipGraphLaunch(exec, b->stream)
-             : batch_iteration(js, tot, dim, reg, o, passes, steps,
-                               b->dstop, b->stream);
+             : batch_iteration(js, tot, dim, reg, o, b->dstop, b->stream);
     if (e != hipSuccess || o.parity_mode) continue;
     e = hipMemcpyAsync(b->hstop, b->dstop, S * sizeof(int),
                        hipMemcpyDeviceToHost, b->stream);

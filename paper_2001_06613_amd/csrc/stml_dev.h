@@ -78,15 +78,34 @@ struct GNLog {
   int cg;                     // CG iterations
   int status;                 // -1 not run, 0 accepted, 1 no step found,
                               // 2 accepted after a CG breakdown
-  int next_pass;              // line-search pass that still has to run
+  int next_pass;              // last line-search sweep that ran
   int pad;
 };
 
-// Armijo sweep p: steps t[0..kTrialSteps) with exponents e0 + (s - base)
-// for s >= base (slot 0 of the first sweep holds t = 0).
-struct LSPass {
-  int p, base, e0, last;      // last: no further sweep after this one
-};
+// Armijo schedule of one Gauss-Newton iteration, t = 2^-e for e = 0, 1,
+// ..., ls_max, in sweeps: sweep 0 evaluates t = 0 (the reference value,
+// taken by the same formula as the steps) and t = 1; sweep p >= 1
+// evaluates kTrialSteps steps, e = 1 + kTrialSteps (p - 1) + s (entries
+// past ls_max repeat 2^-ls_max and are not tested).
+constexpr int kSweep0Steps = 2;
+__host__ __device__ inline int sweep_steps(int p) {
+  return p == 0 ? kSweep0Steps : kTrialSteps;
+}
+__host__ __device__ inline int sweep_count(int ls_max) {
+  return 1 + (ls_max + kTrialSteps - 1) / kTrialSteps;
+}
+// exponent of step s of sweep p; -1 for t = 0
+__host__ __device__ inline int sweep_exp(int p, int s) {
+  return p == 0 ? s - 1 : 1 + kTrialSteps * (p - 1) + s;
+}
+__host__ __device__ inline bool sweep_tests(int p, int s, int ls_max) {
+  const int e = sweep_exp(p, s);
+  return e >= 0 && e <= ls_max;
+}
+__host__ __device__ inline double sweep_t(int p, int s, int ls_max) {
+  const int e = sweep_exp(p, s);
+  return e < 0 ? 0.0 : ldexp(1.0, -(e <= ls_max ? e : ls_max));
+}
 
 // ---------------------------------------------------------------- helpers
 
