@@ -521,8 +521,8 @@ __device__ __forceinline__ int sweep_accepts(RedBuf rb, int nb, int q,
 // per-step sums live in LDS (one slot row per thread), which keeps register
 // use low.  A frame's loads (u, delta, g and both stencils) issue together,
 // and in 2-D the gathers of up to three steps at a time, so that an image
-// frame of a five-step sweep costs three dependent memory round trips
-// instead of nine.
+// frame of a later sweep costs four dependent memory round trips instead of
+// ten.
 template <int D, int REG, int NT>
 __device__ __forceinline__ void trial_body(
     const float* __restrict__ T, const float* __restrict__ u,
@@ -588,7 +588,7 @@ __device__ __forceinline__ void trial_body(
         rC = valid ? rC + ww : rC;
       }
       const float* Tk = T + (size_t)k * N;
-      // steps whose loads issue together: three in a five-step image sweep;
+      // steps whose loads issue together: three in a later image sweep;
       // one at a time in the two-step sweep (two in flight measured
       // slower under the register cap)
       constexpr int TG = D == 2 ? (NT < 3 ? 1 : 3) : 1;

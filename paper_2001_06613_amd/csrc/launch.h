@@ -11,8 +11,10 @@ namespace stml {
 
 // Partial-sum slots of the reductions: one region per producing kernel, so
 // a consumer can read its producer's slots after the next kernel wrote its
-// own.  A region holds up to 16 values x 1024 blocks.
-constexpr size_t kRegionSlots = (size_t)16 * 1024;
+// own.  A region holds up to 20 values x 1024 blocks (a trial sweep of
+// kTrialSteps steps writes kTrialSteps + 9 values per block).
+constexpr size_t kRegionSlots = (size_t)20 * 1024;
+static_assert(kTrialSteps + 9 <= 20, "trial partials exceed a region");
 // Line-search sweeps: sweep 0 in kRegTrial, later sweeps alternate between
 // kRegTrialOdd and kRegTrialEven, so that a sweep can read its
 // predecessor's slots while it writes its own.
