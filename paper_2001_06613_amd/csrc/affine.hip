@@ -14,12 +14,13 @@
 // One evaluation is three passes over the voxels:
 //   gram   : warp every frame of K, stage the warped values of 32 voxels
 //            (and a row of ones) in LDS, and accumulate the raw Gram matrix
-//            sum_x W_i W_j (its ones row gives sum_x W_i and N) in 4 x 4
-//            float64 register tiles; one partial per block;
+//            sum_x W_i W_j (its ones row gives sum_x W_i and N) in 16 x 16
+//            float64 tiles on the matrix cores; one partial per block;
 //   (sum, finalize: totals in block order; covariance, rho, D, P, and the
 //            coefficients Rc of dD/dW_i = sum_b Rc_ib (W_b - mu_b))
-//   resid  : warp again, r_i(x) = sum_b Rc_ib (W_b(x) - mu_b) as a small
-//            GEMM per 32-voxel tile, stored float32 [|K|][N];
+//   resid  : r_i(x) = sum_b Rc_ib (W_b(x) - mu_b) from the warped frames
+//            pass 1 kept (float32), as a GEMM on the matrix cores, stored
+//            float32 [|K|][N];
 //   pgrad  : per frame, sum_x r_i(x) dW_i/du(x) (xi(x), 1) -> the p
 //            parameter partials per block; summed in block order together
 //            with the penalty's gradient.
@@ -104,12 +105,14 @@ __device__ __forceinline__ void aff_tile_geo(const AffGeom& ag, long long v0,
 
 // Warped frames of one tile into Ws[row][kAffV + 1] (float64): rows of K,
 // then (ones) a row of ones over the valid voxels; invalid voxels hold 0.
-// The tile's geometry must be in tg (and visible: after a barrier).
+// Wout (optional) receives the warped values as float32 [|K|][N].  The
+// tile's geometry must be in tg (and visible: after a barrier).
 template <int D>
 __device__ __forceinline__ void aff_stage_tile(
     const float* __restrict__ T, const int* __restrict__ K, int nk,
     bool ones, const AffGeom& ag, const double* th, const double* mu,
-    long long v0, const AffTileGeo<D>& tg, double* Ws) {
+    long long v0, const AffTileGeo<D>& tg, double* Ws,
+    float* __restrict__ Wout) {
   constexpr int P = D * D + D;
   const int rows = nk + (ones ? 1 : 0);
   const long long N = ag.g.N;
@@ -135,6 +138,7 @@ __device__ __forceinline__ void aff_stage_tile(
           uv[a] = s + t[D * D + a];
         }
         warp_sample<D>(T + (size_t)K[k] * N, ag.g, pos, uv, val, dW);
+        if (Wout) Wout[(size_t)k * N + vox] = (float)val;
         if (mu) val -= mu[k];
       } else {
         val = 1.0;
@@ -144,7 +148,7 @@ __device__ __forceinline__ void aff_stage_tile(
   }
 }
 
-// Upper-triangle 4 x 4 tile tau of a TI x TI tile grid -> (I, J), I <= J.
+// Upper-triangle tile tau of a TI x TI tile grid -> (I, J), I <= J.
 __device__ __forceinline__ void aff_tile_of(int tau, int TI, int& I, int& J) {
   I = 0;
   while (tau >= TI - I) {
@@ -154,101 +158,86 @@ __device__ __forceinline__ void aff_tile_of(int tau, int TI, int& I, int& J) {
   J = I + tau;
 }
 
-// Pass 1: raw Gram matrix of [W_K; 1] over this block's tiles.  The rows
-// are dealt into TI groups {g, g + TI, g + 2 TI, g + 3 TI}; a thread owns
-// MT tiles (I, J), I <= J, of 4 x 4 entries of such groups (split threads
-// share one tile when there are fewer tiles than threads; blockIdx.y
-// selects a group of tiles when MT per thread do not cover them).
-// Neighbouring threads read neighbouring rows, which lie in distinct LDS
-// banks (rows 4 apart would share 8 banks).
-template <int D, int MT>
+typedef double aff_d4 __attribute__((ext_vector_type(4)));
+
+// Pass 1: raw Gram matrix G = A A^T of A = [W_K; 1] (rows padded with zeros
+// to a multiple of 16) over this block's voxels, on the float64 matrix
+// cores.  Per 32-voxel tile the warped rows are staged in LDS; the upper
+// triangle of 16 x 16 output tiles is dealt round-robin to the block's
+// four waves (blockIdx.y selects a group of kAffGramTiles tiles per wave
+// when there are more), and each wave accumulates its tiles with
+// v_mfma_f64_16x16x4f64 over the tile's voxels in steps of four: lane l
+// supplies A[16 I + l % 16][v + l / 16] and A[16 J + l % 16][v + l / 16]
+// and holds G[16 I + l / 16 + 4 r][16 J + l % 16] in register r.  The
+// voxels are summed in a fixed order, so repeated runs agree bit for bit.
+template <int D>
 __global__ __launch_bounds__(kAffThreads) void aff_gram_kernel(
     const float* __restrict__ T, const int* __restrict__ K, int nk,
     const double* __restrict__ x, const double* __restrict__ dv, double t,
-    AffGeom ag, int split, double* __restrict__ part, int E) {
+    AffGeom ag, double* __restrict__ part, int E, float* __restrict__ Wout) {
   extern __shared__ double lds[];
   __shared__ AffTileGeo<D> tg;
   constexpr int P = D * D + D;
+  constexpr int MT = kAffGramTiles;
   const int K1 = nk + 1;
-  const int TI = (K1 + 3) / 4;
-  const int NT = TI * (TI + 1) / 2;
+  const int Kt = (K1 + 15) / 16;
+  const int NTt = Kt * (Kt + 1) / 2;
   double* th = lds;                                   // [nk][P]
-  double* Ws = lds + ((nk * P + 1) & ~1);             // [4 TI][kAffV + 1]
+  double* Ws = lds + ((nk * P + 1) & ~1);             // [16 Kt][kAffV + 1]
   aff_stage_params(x, dv, t, nk * P, th);
-  for (int i = threadIdx.x + K1 * (kAffV + 1); i < 4 * TI * (kAffV + 1);
+  for (int i = threadIdx.x + K1 * (kAffV + 1); i < 16 * Kt * (kAffV + 1);
        i += blockDim.x)
     Ws[i] = 0.0;                                      // padding rows
-  // thread -> (tiles, voxel sub-lane); split threads share a tile and take
-  // every split-th voxel, then add up by shuffles within their group
-  const int tl = threadIdx.x / split, sub = threadIdx.x - tl * split;
-  const int per = kAffThreads / split;
-  int I[MT], J[MT];
+  const int w = wave_id();
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r16 = lane & 15, k4 = lane >> 4;
+  int ra[MT], rb[MT];                                 // LDS row offsets
   bool act[MT];
 #pragma unroll
   for (int m = 0; m < MT; ++m) {
-    const int tau = (blockIdx.y * MT + m) * per + tl;
-    act[m] = tau < NT;
-    I[m] = J[m] = 0;
-    if (act[m]) aff_tile_of(tau, TI, I[m], J[m]);
+    const int tau = (blockIdx.y * MT + m) * (kAffThreads / kWave) + w;
+    act[m] = tau < NTt;
+    int I = 0, J = 0;
+    if (act[m]) aff_tile_of(tau, Kt, I, J);
+    ra[m] = (16 * I + r16) * (kAffV + 1) + k4;
+    rb[m] = (16 * J + r16) * (kAffV + 1) + k4;
   }
-  double acc[MT][4][4];
+  aff_d4 acc[MT];
 #pragma unroll
-  for (int m = 0; m < MT; ++m)
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 4; ++b) acc[m][a][b] = 0.0;
+  for (int m = 0; m < MT; ++m) acc[m] = aff_d4{0.0, 0.0, 0.0, 0.0};
   const long long nch = (ag.g.N + kAffV - 1) / kAffV;
   for (long long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
     aff_tile_geo<D>(ag, ch * kAffV, tg);
     __syncthreads();
-    aff_stage_tile<D>(T, K, nk, true, ag, th, nullptr, ch * kAffV, tg, Ws);
+    // the first tile group also keeps the warped frames for pass 2
+    aff_stage_tile<D>(T, K, nk, true, ag, th, nullptr, ch * kAffV, tg, Ws,
+                      blockIdx.y == 0 ? Wout : nullptr);
     __syncthreads();
 #pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      if (!act[m]) continue;
-      const double* ra = Ws + I[m] * (kAffV + 1);
-      const double* rb = Ws + J[m] * (kAffV + 1);
-      const int rs = TI * (kAffV + 1);
-      for (int v = sub; v < kAffV; v += split) {
-        double av[4], bv[4];
+    for (int ks = 0; ks < kAffV; ks += 4) {
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          av[a] = ra[a * rs + v];
-          bv[a] = rb[a * rs + v];
-        }
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 4; ++b) acc[m][a][b] += av[a] * bv[b];
+      for (int m = 0; m < MT; ++m) {
+        if (!act[m]) continue;          // wave-uniform
+        const double a = Ws[ra[m] + ks];
+        const double b = Ws[rb[m] + ks];
+        acc[m] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[m], 0, 0, 0);
       }
     }
     __syncthreads();
   }
-  for (int o = split >> 1; o >= 1; o >>= 1)
+  double* out = part + (size_t)blockIdx.x * E;
 #pragma unroll
-    for (int m = 0; m < MT; ++m)
+  for (int m = 0; m < MT; ++m) {
+    if (!act[m]) continue;
+    const int I = (ra[m] / (kAffV + 1) - r16) / 16;
+    const int J = (rb[m] / (kAffV + 1) - r16) / 16;
+    const int c = 16 * J + r16;
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b)
-          acc[m][a][b] += __shfl_xor(acc[m][a][b], o, kWave);
-  if (sub == 0) {
-    double* out = part + (size_t)blockIdx.x * E;
-#pragma unroll
-    for (int m = 0; m < MT; ++m) {
-      if (!act[m]) continue;
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) {
-          // tile (I, J), I <= J, holds rows I + a TI and J + b TI: every
-          // unordered pair once (both orders on the diagonal tiles)
-          const int r = I[m] + a * TI, c = J[m] + b * TI;
-          if (r >= K1 || c >= K1) continue;
-          if (r <= c) out[aff_tri_index(r, c, K1)] = acc[m][a][b];
-          else if (I[m] != J[m]) out[aff_tri_index(c, r, K1)] = acc[m][a][b];
-        }
+    for (int q = 0; q < 4; ++q) {
+      // tiles with I < J lie above the diagonal; a diagonal tile keeps its
+      // upper triangle (its mirror entries are the same sums)
+      const int r = 16 * I + k4 + 4 * q;
+      if (r < K1 && c < K1 && r <= c) out[aff_tri_index(r, c, K1)] = acc[m][q];
     }
   }
 }
@@ -406,65 +395,74 @@ __global__ __launch_bounds__(kAffThreads) void aff_finalize_kernel(
   }
 }
 
-// Pass 2: r_i(x) = sum_b Rc_ib (W_b(x) - mu_b) for the frames of K, as a
-// GEMM per 32-voxel tile: 4 (frames) x 4 (voxels) register tiles.
-template <int D>
-__global__ __launch_bounds__(kAffThreads) void aff_resid_kernel(
-    const float* __restrict__ T, const int* __restrict__ K, int nk,
-    const double* __restrict__ x, const double* __restrict__ dv, double t,
-    AffGeom ag, const double* __restrict__ mu, const double* __restrict__ Rc,
+// Pass 2: r_i(x) = sum_b Rc_ib (W_b(x) - mu_b) for the frames of K from the
+// warped frames pass 1 stored (float32), as a GEMM on the float64 matrix
+// cores.  A wave owns one 16-row tile I = blockIdx.y * (waves per block) +
+// wave of the output and keeps its rows of Rc as MFMA operands in
+// registers for the whole kernel (KS steps of four columns: lane l holds
+// Rc[16 I + l % 16][4 s + l / 16] in a[s]); blocks of up to MAXT threads.
+// Per 32-voxel tile the centred values are staged in LDS (rows padded with
+// zeros to a multiple of 16) and each wave forms its two 16 x 16 output
+// tiles (register q of lane l: r[16 I + l / 16 + 4 q][16 V + l % 16]).
+template <int KS, int MAXT>
+__global__ __launch_bounds__(MAXT) void aff_resid_kernel(
+    const float* __restrict__ W, int nk, long long N,
+    const double* __restrict__ mu, const double* __restrict__ Rc,
     float* __restrict__ r) {
-  extern __shared__ double lds[];
-  __shared__ AffTileGeo<D> tg;
-  constexpr int P = D * D + D;
-  const int TI = (nk + 3) / 4;
-  double* th = lds;
-  double* Ws = lds + ((nk * P + 1) & ~1);
-  aff_stage_params(x, dv, t, nk * P, th);
-  for (int i = threadIdx.x + nk * (kAffV + 1); i < 4 * TI * (kAffV + 1);
+  extern __shared__ double Ws[];                      // [16 Kt][kAffV + 1]
+  constexpr int NV = kAffV / 16;
+  const int Kt = (nk + 15) / 16;
+  const int nks = 4 * Kt;                             // steps used (<= KS)
+  const int I = blockIdx.y * (blockDim.x / kWave) + wave_id();
+  const bool act = I < Kt;                            // wave-uniform
+  const int lane = threadIdx.x & (kWave - 1);
+  const int r16 = lane & 15, k4 = lane >> 4;
+  for (int i = threadIdx.x + nk * (kAffV + 1); i < 16 * Kt * (kAffV + 1);
        i += blockDim.x)
-    Ws[i] = 0.0;
-  const long long N = ag.g.N;
+    Ws[i] = 0.0;                                      // padding rows
+  // rows past nk read row nk - 1 (their outputs are dropped); columns past
+  // nk are zero
+  const int row = min(16 * (act ? I : 0) + r16, nk - 1);
+  double a[KS];
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int b = 4 * s + k4;
+    a[s] = (s < nks && b < nk) ? Rc[(size_t)row * nk + b] : 0.0;
+  }
   const long long nch = (N + kAffV - 1) / kAffV;
-  const int ntile = TI * (kAffV / 4);
-  __syncthreads();
   for (long long ch = blockIdx.x; ch < nch; ch += gridDim.x) {
-    aff_tile_geo<D>(ag, ch * kAffV, tg);
     __syncthreads();
-    aff_stage_tile<D>(T, K, nk, false, ag, th, mu, ch * kAffV, tg, Ws);
+    for (int idx = threadIdx.x; idx < nk * kAffV; idx += blockDim.x) {
+      const int b = idx / kAffV, v = idx - b * kAffV;
+      const long long vox = ch * kAffV + v;
+      Ws[b * (kAffV + 1) + v] =
+          vox < N ? (double)W[(size_t)b * N + vox] - mu[b] : 0.0;
+    }
     __syncthreads();
-    for (int tau = threadIdx.x; tau < ntile; tau += blockDim.x) {
-      const int I = tau / (kAffV / 4), V = tau - I * (kAffV / 4);
-      double acc[4][4];
+    aff_d4 acc[NV];
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+    for (int v = 0; v < NV; ++v) acc[v] = aff_d4{0.0, 0.0, 0.0, 0.0};
+    if (!act) continue;                 // after the barriers of this tile
 #pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = 0.0;
-      int rows[4];
+    for (int s = 0; s < KS; ++s) {
+      if (s < nks) {                    // block-uniform
 #pragma unroll
-      for (int a = 0; a < 4; ++a) rows[a] = min(4 * I + a, nk - 1);
-      for (int b = 0; b < nk; ++b) {
-        double rc[4], w[4];
-#pragma unroll
-        for (int a = 0; a < 4; ++a) rc[a] = Rc[(size_t)rows[a] * nk + b];
-#pragma unroll
-        for (int v = 0; v < 4; ++v) w[v] = Ws[b * (kAffV + 1) + 4 * V + v];
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int v = 0; v < 4; ++v) acc[a][v] += rc[a] * w[v];
-      }
-#pragma unroll
-      for (int a = 0; a < 4; ++a) {
-        const int i = 4 * I + a;
-#pragma unroll
-        for (int v = 0; v < 4; ++v) {
-          const long long vox = ch * kAffV + 4 * V + v;
-          if (i < nk && vox < N) r[(size_t)i * N + vox] = (float)acc[a][v];
+        for (int v = 0; v < NV; ++v) {
+          const double bv = Ws[(4 * s + k4) * (kAffV + 1) + 16 * v + r16];
+          acc[v] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[s], bv, acc[v], 0,
+                                                        0, 0);
         }
       }
     }
-    __syncthreads();
+#pragma unroll
+    for (int v = 0; v < NV; ++v) {
+      const long long vox = ch * kAffV + 16 * v + r16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int i = 16 * I + k4 + 4 * q;
+        if (i < nk && vox < N) r[(size_t)i * N + vox] = (float)acc[v][q];
+      }
+    }
   }
 }
 
@@ -740,27 +738,23 @@ __global__ void aff_field_kernel(const double* __restrict__ theta, int n,
 AffShape aff_shape(const AffGeom& ag, int nk) {
   AffShape sh;
   const int K1 = nk + 1;
-  const int TI = (K1 + 3) / 4;
-  const int NT = TI * (TI + 1) / 2;
+  const int Kt = (K1 + 15) / 16;
+  const int NTt = Kt * (Kt + 1) / 2;
   const long long nch = (ag.g.N + kAffV - 1) / kAffV;
-  int split = 1;
-  while (split < 32 && NT * split * 2 <= kAffThreads) split *= 2;
-  sh.split = split;
-  // up to three tiles per thread (48 float64 accumulators) before the
-  // tiles are spread over groups that each warp the frames again
-  sh.mt = 1;   // more blocks per compute unit beat fewer warps (measured)
-  sh.groups = (NT * split + sh.mt * kAffThreads - 1) / (sh.mt * kAffThreads);
+  // kAffGramTiles 16 x 16 tiles per wave before the tiles are spread over
+  // groups that each warp the frames again
+  const int per_group = kAffGramTiles * (kAffThreads / kWave);
+  sh.groups = (NTt + per_group - 1) / per_group;
   sh.E = K1 * (K1 + 1) / 2;
   sh.nb_gram = (int)(nch < kAffGramBlocks ? nch : kAffGramBlocks);
-  sh.nb_resid = (int)(nch < 1024 ? nch : 1024);
+  sh.nb_resid = (int)(nch < 2 * kCUs ? nch : 2 * kCUs);
   const long long per = (ag.g.N + kAffThreads - 1) / kAffThreads;
   sh.nb_pgrad = (int)(per < kAffPgradBlocks ? per : kAffPgradBlocks);
   const int P = ag.d * ag.d + ag.d;
-  sh.lds_gram = (size_t)(((nk * P + 1) & ~1) + 4 * TI * (kAffV + 1)) *
+  sh.lds_gram = (size_t)(((nk * P + 1) & ~1) + 16 * Kt * (kAffV + 1)) *
                 sizeof(double);
-  const int TIr = (nk + 3) / 4;
-  sh.lds_resid = (size_t)(((nk * P + 1) & ~1) + 4 * TIr * (kAffV + 1)) *
-                 sizeof(double);
+  const int Ktr = (nk + 15) / 16;
+  sh.lds_resid = (size_t)(16 * Ktr * (kAffV + 1)) * sizeof(double);
   return sh;
 }
 
@@ -769,14 +763,11 @@ static hipError_t aff_allow_lds() {
   static hipError_t e = [] {
     const int cap = 156 * 1024;    // 160 KiB per CU, less static LDS
     hipError_t r = hipSuccess;
-    const void* ks[] = {(const void*)aff_gram_kernel<2, 1>,
-                        (const void*)aff_gram_kernel<2, 2>,
-                        (const void*)aff_gram_kernel<2, 3>,
-                        (const void*)aff_gram_kernel<3, 1>,
-                        (const void*)aff_gram_kernel<3, 2>,
-                        (const void*)aff_gram_kernel<3, 3>,
-                        (const void*)aff_resid_kernel<2>,
-                        (const void*)aff_resid_kernel<3>};
+    const void* ks[] = {(const void*)aff_gram_kernel<2>,
+                        (const void*)aff_gram_kernel<3>,
+                        (const void*)aff_resid_kernel<16, 256>,
+                        (const void*)aff_resid_kernel<40, 640>,
+                        (const void*)aff_resid_kernel<64, 512>};
     for (const void* k : ks) {
       hipError_t q = hipFuncSetAttribute(
           k, hipFuncAttributeMaxDynamicSharedMemorySize, cap);
@@ -796,15 +787,12 @@ hipError_t launch_aff_objective(const float* T, const int* K, int nk,
   if (e != hipSuccess) return e;
   if (!reuse_gram) {
     dim3 grid(sh.nb_gram, sh.groups);
-    decltype(&aff_gram_kernel<2, 1>) kern;
     if (ag.d == 2)
-      kern = sh.mt == 1 ? aff_gram_kernel<2, 1>
-           : sh.mt == 2 ? aff_gram_kernel<2, 2> : aff_gram_kernel<2, 3>;
+      aff_gram_kernel<2><<<grid, kAffThreads, sh.lds_gram, s>>>(
+          T, K, nk, x, dv, t, ag, b.part, sh.E, b.W);
     else
-      kern = sh.mt == 1 ? aff_gram_kernel<3, 1>
-           : sh.mt == 2 ? aff_gram_kernel<3, 2> : aff_gram_kernel<3, 3>;
-    kern<<<grid, kAffThreads, sh.lds_gram, s>>>(T, K, nk, x, dv, t, ag,
-                                                sh.split, b.part, sh.E);
+      aff_gram_kernel<3><<<grid, kAffThreads, sh.lds_gram, s>>>(
+          T, K, nk, x, dv, t, ag, b.part, sh.E, b.W);
     aff_sum_kernel<<<(sh.E + 255) / 256, 256, 0, s>>>(b.part, sh.nb_gram,
                                                        sh.E, b.tot);
   }
@@ -812,12 +800,24 @@ hipError_t launch_aff_objective(const float* T, const int* K, int nk,
                                                 b.sc, b.mu, b.Rc, b.gpen,
                                                 grad ? 1 : 0);
   if (!grad) return hipGetLastError();
-  if (ag.d == 2)
-    aff_resid_kernel<2><<<sh.nb_resid, kAffThreads, sh.lds_resid, s>>>(
-        T, K, nk, x, dv, t, ag, b.mu, b.Rc, b.r);
-  else
-    aff_resid_kernel<3><<<sh.nb_resid, kAffThreads, sh.lds_resid, s>>>(
-        T, K, nk, x, dv, t, ag, b.mu, b.Rc, b.r);
+  {
+    // one wave per 16-row tile: up to 10 tiles in one block (KS = 40,
+    // 640 threads), else two block rows of at most 8 waves (|K| <= 256)
+    const int Kt = (nk + 15) / 16;
+    decltype(&aff_resid_kernel<16, 256>) rk;
+    int rows = 1, waves = Kt;
+    if (Kt <= 4) {
+      rk = aff_resid_kernel<16, 256>;
+    } else if (Kt <= 10) {
+      rk = aff_resid_kernel<40, 640>;
+    } else {
+      rk = aff_resid_kernel<64, 512>;
+      rows = 2;
+      waves = (Kt + 1) / 2;
+    }
+    rk<<<dim3(sh.nb_resid, rows), waves * kWave, sh.lds_resid, s>>>(
+        b.W, nk, ag.g.N, b.mu, b.Rc, b.r);
+  }
   dim3 gp(sh.nb_pgrad, nk);
   if (ag.d == 2)
     aff_pgrad_kernel<2><<<gp, kAffThreads, 0, s>>>(T, K, x, dv, t, ag, b.r,

@@ -243,14 +243,17 @@ struct AffBufs {
   double* Rc;       // dD/dW coefficients [|K|][|K|]
   double* gpen;     // penalty gradient wrt the mean parameters [p]
   float* r;         // dD/dW_i per voxel [|K|][N]
+  float* W;         // warped frames of the last Gram pass [|K|][N]
   double* gpart;    // parameter-gradient partials [|K|][p][nb]
   double* gout;     // gradient [|K|][p]
   AffScal* sc;
 };
-constexpr int kAffGramBlocks = 256;    // Gram partials per evaluation
+constexpr int kAffGramBlocks = 512;    // Gram partials per evaluation
+constexpr int kAffGramTiles = 12;      // 16 x 16 Gram tiles per wave
+constexpr int kAffResidRows = 3;       // 16-row tiles of dD/dW per wave
 constexpr int kAffPgradBlocks = 64;    // gradient partials per frame
 struct AffShape {
-  int split, mt, groups, E, nb_gram, nb_resid, nb_pgrad;
+  int groups, E, nb_gram, nb_resid, nb_pgrad;
   size_t lds_gram, lds_resid;
 };
 AffShape aff_shape(const AffGeom& ag, int nk);

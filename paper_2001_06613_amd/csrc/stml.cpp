@@ -203,6 +203,7 @@ size_t layout_affine(stml_ctx* c, Layout& lo) {
   c->ab.Rc = lo.take<double>((size_t)n * n);
   c->ab.gpen = lo.take<double>(16);
   c->ab.r = lo.take<float>((size_t)n * c->N[c->L - 1]);
+  c->ab.W = lo.take<float>((size_t)n * c->N[c->L - 1]);
   c->ab.gpart = lo.take<double>(nP * kAffPgradBlocks);
   c->ab.gout = nullptr;                      // set per evaluation
   c->ab.sc = lo.take<AffScal>(1);

@@ -53,8 +53,13 @@ CASES = [
     ("2d_single", 3, (20, 70), 1, 0, [1]),
     ("3d_ragged", 4, (9, 10, 11), 1, 0, [0, 1, 3]),
     ("3d_coarse", 3, (17, 12, 21), 2, 0, [0, 1, 2]),
-    # more frames than one 4 x 4 Gram tile row, several tile groups
+    # more frames than one 16-row tile of the Gram matrix
     ("2d_many", 40, (24, 20), 1, 0, list(range(0, 40, 1))),
+    # more Gram tiles than the waves of a block hold (several tile groups,
+    # each warping the frames again) and more than one group of row tiles
+    # of dD/dW per wave
+    ("2d_groups", 210, (12, 10), 1, 0, list(range(0, 210, 1))),
+    ("3d_groups", 150, (5, 6, 7), 1, 0, list(range(0, 150, 1))),
 ]
 
 
