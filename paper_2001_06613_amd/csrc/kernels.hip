@@ -714,15 +714,15 @@ __device__ __forceinline__ void ls_accept_body(
     return;
   }
   const double tacc = sweep_t(qs, sacc, ls_max);
-  size_t count = (size_t)nK * dim * N;
-  size_t stride = (size_t)blk.n * blockDim.x;
-  for (size_t e = (size_t)blk.id * blockDim.x + threadIdx.x; e < count;
+  // |K| D N < 2^31 (a context checks it): 32-bit index arithmetic, whose
+  // divisions cost a fraction of 64-bit ones
+  const unsigned DN = (unsigned)dim * (unsigned)N;
+  const size_t count = (size_t)nK * DN;
+  const unsigned stride = (unsigned)blk.n * blockDim.x;
+  for (unsigned e = (unsigned)blk.id * blockDim.x + threadIdx.x; e < count;
        e += stride) {
-    size_t row = e / (size_t)N;
-    size_t x = e - row * (size_t)N;
-    int j = (int)(row / dim);
-    int a = (int)(row - (size_t)j * dim);
-    size_t o = ((size_t)K[j] * dim + a) * N + x;
+    const unsigned j = e / DN;
+    const size_t o = (size_t)K[j] * DN + (e - j * DN);
     u[o] = (float)((double)u[o] + tacc * (double)dl[e]);
   }
   if (blk.id == 0 && threadIdx.x == 0) {
