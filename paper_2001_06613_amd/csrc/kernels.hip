@@ -164,7 +164,8 @@ __global__ void restrict_kernel(const float* __restrict__ fine,
 
 // Prolongation: the coarse cell-centred linear interpolant (edge clamp)
 // sampled at fine cell centres; fine index i sits at coarse coordinate
-// i/2 - 1/4.
+// i/2 - 1/4.  Blocks in y split the fields (frames x components), so that a
+// thread interpolates a few fields of its voxel rather than all of them.
 template <int D>
 __global__ void prolong_kernel(const float* __restrict__ coarse,
                                float* __restrict__ fine, int fields, Geom gc,
@@ -190,7 +191,7 @@ __global__ void prolong_kernel(const float* __restrict__ coarse,
         f[a] = 0.0;
       }
     }
-    for (int fi = 0; fi < fields; ++fi) {
+    for (int fi = blockIdx.y; fi < fields; fi += gridDim.y) {
       const float* c = coarse + (size_t)fi * gc.N;
       double v = 0.0;
 #pragma unroll
@@ -825,6 +826,9 @@ __global__ __launch_bounds__(64) void ls_predict_kernel(
   const size_t sys = (size_t)blockIdx.x * B + threadIdx.x;
   const bool valid = sys < per;
   double prev = 0.0;
+  // unrolled, so that the loads of several frames are in flight (only the
+  // recurrence is sequential)
+#pragma unroll 8
   for (int k = 0; k < n; ++k) {
     double rhs = 0.0;
     if (valid && tab.mask[k]) {
@@ -835,6 +839,7 @@ __global__ __launch_bounds__(64) void ls_predict_kernel(
     dp[k * B + threadIdx.x] = prev;
   }
   double xi = 0.0;
+#pragma unroll 8
   for (int k = n - 1; k >= 0; --k) {
     xi = (k == n - 1) ? dp[k * B + threadIdx.x]
                       : dp[k * B + threadIdx.x] - tab.cp[k] * xi;
@@ -1033,14 +1038,18 @@ hipError_t launch_restrict(int dim, const float* fine, float* coarse, int n,
 hipError_t launch_prolong(int dim, const float* coarse, float* fine,
                           int fields, const Geom& gc, const Geom& gf,
                           hipStream_t s) {
-  int nb = elem_blocks((size_t)gf.N, 1);
+  const int nb = elem_blocks((size_t)gf.N, 1);
+  // about 4096 blocks in all, each field group at least one
+  int fy = (4096 + nb - 1) / nb;
+  if (fy > fields) fy = fields;
+  if (fy < 1) fy = 1;
+  const dim3 grid(nb, fy);
   if (dim == 2)
-    prolong_kernel<2><<<nb, 256, 0, s>>>(coarse, fine, fields, gc, gf);
+    prolong_kernel<2><<<grid, 256, 0, s>>>(coarse, fine, fields, gc, gf);
   else
-    prolong_kernel<3><<<nb, 256, 0, s>>>(coarse, fine, fields, gc, gf);
+    prolong_kernel<3><<<grid, 256, 0, s>>>(coarse, fine, fields, gc, gf);
   return hipGetLastError();
 }
-
 
 hipError_t launch_linear_predict(const float* Y, float* Z, float* Yout,
                                  LinTab tab, int n, int dim, long long N,
