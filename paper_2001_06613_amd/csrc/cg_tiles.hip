@@ -97,6 +97,10 @@ __device__ __forceinline__ void cg_zero_x(float* __restrict__ x,
 // r.r.  A frame's loads (both components) issue before its stores, which
 // would otherwise hold the next component's loads back.  At it = 0 a CG
 // that stops before its first step sets x = 0.
+// FIRST with ev_part: the step also forms the start scalars of the
+// Gauss-Newton iteration from the evaluation's five partials (J = D + S +
+// P, r.z, r.r; the log's J) and takes their decisions: r.z = 0 ends the CG
+// with x = 0, and a start at or below the objective target takes no step.
 template <int D, bool FIRST, bool PRE>
 __device__ __forceinline__ void cgv_update_body(
     int it, const float* __restrict__ p, const float* __restrict__ q,
@@ -104,9 +108,11 @@ __device__ __forceinline__ void cgv_update_body(
     float* __restrict__ x, float* __restrict__ r, float* __restrict__ z,
     double* __restrict__ Sz, double* __restrict__ Vz,
     const double* __restrict__ hv_part, int hv_nb, double* __restrict__ part,
-    Scal* __restrict__ sc, int gn_it, Blk blk) {
-  const int stop = sc->gn_stop, done = sc->done;
-  const double rz_it = sc->rzh[it & 1];
+    Scal* __restrict__ sc, int gn_it, const double* __restrict__ ev_part,
+    int ev_nb, GNLog* __restrict__ log, Blk blk) {
+  const int stop = sc->gn_stop;
+  int done = sc->done;
+  double rz_it = sc->rzh[it & 1];
   int j0, j1;
   wave_frames(md.nK, j0, j1);
   const int lane = threadIdx.x & (kWave - 1);
@@ -140,6 +146,33 @@ __device__ __forceinline__ void cgv_update_body(
     }
   }
   if (gn_it >= stop) return;
+  if (FIRST && ev_part) {
+    // (the flags other blocks read at their start, done and gn_stop, are
+    // only written in ways that leave such a block's work unchanged)
+    double e[5];
+    reduce_partials<5>(ev_part, ev_nb, 0u, e);
+    const double Dv = md.hd * e[0];
+    const double Sv = md.half_alpha_hd * md.reg_scale * e[1];
+    const double Pv = md.lam_hd * e[2];
+    const double Jv = Dv + Sv + Pv;
+    rz_it = e[3];
+    done = e[3] == 0.0 ? 1 : 0;
+    const bool no_step = gn_it == 0 && Jv <= sc->J_target;
+    if (blk.id == 0 && threadIdx.x == 0) {
+      sc->D = Dv;
+      sc->S = Sv;
+      sc->P = Pv;
+      sc->J = Jv;
+      sc->rzh[0] = e[3];
+      sc->r0 = sqrt(e[4]);
+      sc->rr = e[4];
+      sc->iters = 0;
+      sc->done = done;
+      if (log) log[gn_it].J = Jv;
+      if (no_step) sc->gn_stop = 0;
+    }
+    if (no_step) return;
+  }
   if (done) {
     if (FIRST) cg_zero_x<D>(x, g, md, blk);
     return;
@@ -257,10 +290,11 @@ __global__ __launch_bounds__(1024, OCC ? 8 : 1) void cgv_update_kernel(
     const float* __restrict__ dW, Geom g, Model md, float* __restrict__ x,
     float* __restrict__ r, float* __restrict__ z, double* __restrict__ Sz,
     double* __restrict__ Vz, const double* __restrict__ hv_part, int hv_nb,
-    double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
+    double* __restrict__ part, Scal* __restrict__ sc, int gn_it,
+    const double* __restrict__ ev_part, int ev_nb, GNLog* __restrict__ log) {
   cgv_update_body<D, FIRST, !OCC>(it, p, q, dW, g, md, x, r, z, Sz, Vz,
-                                  hv_part, hv_nb, part, sc, gn_it,
-                                  grid_blk());
+                                  hv_part, hv_nb, part, sc, gn_it, ev_part,
+                                  ev_nb, log, grid_blk());
 }
 
 // Per-voxel S and V of a stored field v (Hessian product test entry).
@@ -375,7 +409,9 @@ __device__ __forceinline__ void cgt_hvp2_body(
     }
   };
   if (jbeg < jend) fetch(jbeg);
-  if (done || gn_it >= stop) return;
+  // at CG step 0 the done flag is the previous iteration's (the update of
+  // this step forms the new one)
+  if ((!FIRST && done) || gn_it >= stop) return;
   double beta = 0.0;
   if (!FIRST) {
     double t[2];
@@ -586,7 +622,9 @@ __device__ __forceinline__ void cgt_hvp3_body(
   (void)rtol;
   (void)Sp_old;
   (void)Vp_old;
-  if (sc->done || gn_it >= sc->gn_stop) return;
+  // at CG step 0 the done flag is the previous iteration's (the update of
+  // this step forms the new one)
+  if ((!FIRST && sc->done) || gn_it >= sc->gn_stop) return;
   // it > 0: beta and the sums of p come from cg_psums_kernel (launched just
   // before); it = 0: p = z, whose sums this kernel keeps for the next step
   const double beta = FIRST ? 0.0 : sc->beta;
@@ -865,7 +903,7 @@ hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
                              const float* dW, const Geom& g, const Model& md,
                              float* x, float* r, float* z, CgSums sums,
                              RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
-                             hipEvent_t ev0, hipEvent_t ev1) {
+                             GNLog* log, hipEvent_t ev0, hipEvent_t ev1) {
   int nb = cgv_blocks(g), nt = cgv_threads(dim, md.nK);
   int hv_nb = cg_tiles(g, md.nK, dim).grid;
   const bool occ = nb > kCUs, first = it == 0;
@@ -883,7 +921,9 @@ hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
   hipExtLaunchKernelGGL(kern, dim3(nb), dim3(nt), 0, s, ev0, ev1, 0, it, p,
                         q, dW, g, md, x, r, z, sums.Sz, sums.Vz,
                         (const double*)rb.region(kRegHv), hv_nb,
-                        rb.region(kRegUpdate), sc, gn_it);
+                        rb.region(kRegUpdate), sc, gn_it,
+                        (const double*)rb.region(kRegEval), tile_blocks(g),
+                        log);
   return hipGetLastError();
 }
 
@@ -960,7 +1000,8 @@ __global__ __launch_bounds__(1024, 8) void cg_update_batch_kernel(JobSet js,
   cgv_update_body<D, FIRST, false>(it, pn, J.q, J.dW, g, md, J.x, J.r, J.z,
                             J.sums.Sz, J.sums.Vz, J.rb.region(kRegHv),
                             J.ct.grid, J.rb.region(kRegUpdate), sc,
-                            sc->gn_cur, blk);
+                            sc->gn_cur, J.rb.region(kRegEval), J.nb_tile,
+                            J.log, blk);
 }
 
 template <int D>

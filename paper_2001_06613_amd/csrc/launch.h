@@ -141,11 +141,13 @@ hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
                           double rtol, RedBuf rb, Scal* sc, hipStream_t s,
                           int gn_it, hipEvent_t ev0 = nullptr,
                           hipEvent_t ev1 = nullptr);
+// At it = 0 it also forms the Gauss-Newton iteration's start scalars from
+// the evaluation's partials (and writes log[gn_it].J).
 hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
                              const float* dW, const Geom& g, const Model& md,
                              float* x, float* r, float* z, CgSums sums,
                              RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
-                             hipEvent_t ev0 = nullptr,
+                             GNLog* log, hipEvent_t ev0 = nullptr,
                              hipEvent_t ev1 = nullptr);
 // Test entry: H v for a stored v through the tiled Hessian product;
 // v is copied to vcopy on the way.

@@ -542,16 +542,18 @@ CgStart cg_start(stml_ctx* c) {
 
 // Jacobi-PCG for H delta = -g at the evaluation just made (g, dW, and the
 // CG start r, z in scratch), as part of Gauss-Newton iteration gn_it.
-// Enqueued only; the scalars stay on the device.
+// Enqueued only; the scalars stay on the device.  The first CG update forms
+// the iteration's start scalars; without CG steps a one-block kernel does.
 int enqueue_pcg(stml_ctx* c, int level, const Geom& g, const Model& md,
                 int gn_it) {
   const int D = c->d;
   const double vf = (double)md.nK * g.N;
-  TIMED(STML_K_CG_INIT, level, vf,
-        launch_finalize_start(c->rb, tile_blocks(g), md, c->sc, gn_it,
-                              c->gnlog, c->stream));
-  if (c->o.cg_max == 0)   // no CG step: the direction is x0 = 0
+  if (c->o.cg_max == 0) {   // no CG step: the direction is x0 = 0
+    TIMED(STML_K_CG_INIT, level, vf,
+          launch_finalize_start(c->rb, tile_blocks(g), md, c->sc, gn_it,
+                                c->gnlog, c->stream));
     HIP_OK(launch_fill(c->x, (size_t)md.nK * D * g.N, 0.0f, c->stream));
+  }
   for (int it = 0; it < c->o.cg_max; ++it) {
     float* pn = c->P[it & 1];
     const float* po = c->P[(it + 1) & 1];
@@ -563,7 +565,8 @@ int enqueue_pcg(stml_ctx* c, int level, const Geom& g, const Model& md,
     TIMED_DISPATCH(STML_K_CG_UPDATE, level, vf, it,
                    launch_cgv_update(D, it, pn, c->q, c->dW, g, md, c->x,
                                      c->r, c->z, c->sums, c->rb, c->sc,
-                                     c->stream, gn_it, ev0_, ev1_));
+                                     c->stream, gn_it, c->gnlog, ev0_,
+                                     ev1_));
   }
   return STML_OK;
 }
@@ -1600,9 +1603,10 @@ size_t batch_layout(int count, char* base, stml_batch* b) {
 hipError_t batch_iteration(const JobSet& js, const int* tot, int dim,
                            int reg, const stml_opts& o, int* dstop,
                            hipStream_t s) {
-  // the evaluation also forms the CG start (r, z, sums of z)
+  // the evaluation also forms the CG start (r, z, sums of z); the first CG
+  // update its scalars (without CG steps a one-block kernel per job does)
   hipError_t e = batch_eval(js, tot[kClsTile], dim, reg, s);
-  if (e == hipSuccess) e = batch_finalize_start(js, s);
+  if (e == hipSuccess && o.cg_max == 0) e = batch_finalize_start(js, s);
   if (e == hipSuccess && o.cg_max == 0) e = batch_zero_x(js, tot[kClsVox], dim, s);
   for (int it = 0; e == hipSuccess && it < o.cg_max; ++it) {
     e = batch_cg_hvp(js, tot[kClsHv], tot[kClsVox], dim, reg, it,
