@@ -49,7 +49,7 @@ __device__ __forceinline__ void store_voxel_sums(double s, const double* v,
                                                  long long x, bool valid,
                                                  long long N,
                                                  double* __restrict__ S,
-                                                 double* __restrict__ V) {
+                                                 float* __restrict__ V) {
   __shared__ double xs[kMaxChunks][kWave][1 + D];
   const int lane = threadIdx.x & (kWave - 1);
   const int w = wave_id();
@@ -106,7 +106,7 @@ __device__ __forceinline__ void cgv_update_body(
     int it, const float* __restrict__ p, const float* __restrict__ q,
     const float* __restrict__ dW, const Geom& g, const Model& md,
     float* __restrict__ x, float* __restrict__ r, float* __restrict__ z,
-    double* __restrict__ Sz, double* __restrict__ Vz,
+    double* __restrict__ Sz, float* __restrict__ Vz,
     const double* __restrict__ hv_part, int hv_nb, double* __restrict__ part,
     Scal* __restrict__ sc, int gn_it, const double* __restrict__ ev_part,
     int ev_nb, GNLog* __restrict__ log, Blk blk) {
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(1024, OCC ? 8 : 1) void cgv_update_kernel(
     int it, const float* __restrict__ p, const float* __restrict__ q,
     const float* __restrict__ dW, Geom g, Model md, float* __restrict__ x,
     float* __restrict__ r, float* __restrict__ z, double* __restrict__ Sz,
-    double* __restrict__ Vz, const double* __restrict__ hv_part, int hv_nb,
+    float* __restrict__ Vz, const double* __restrict__ hv_part, int hv_nb,
     double* __restrict__ part, Scal* __restrict__ sc, int gn_it,
     const double* __restrict__ ev_part, int ev_nb, GNLog* __restrict__ log) {
   cgv_update_body<D, FIRST, !OCC>(it, p, q, dW, g, md, x, r, z, Sz, Vz,
@@ -301,7 +301,7 @@ __global__ __launch_bounds__(1024, OCC ? 8 : 1) void cgv_update_kernel(
 template <int D>
 __global__ __launch_bounds__(1024) void cgv_sums_kernel(
     const float* __restrict__ v, const float* __restrict__ dW, Geom g,
-    Model md, double* __restrict__ S, double* __restrict__ V) {
+    Model md, double* __restrict__ S, float* __restrict__ V) {
   int j0, j1;
   wave_frames(md.nK, j0, j1);
   const int lane = threadIdx.x & (kWave - 1);
@@ -340,9 +340,9 @@ __device__ __forceinline__ void cgt_hvp2_body(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, const Geom& g,
     const Model& md, float* __restrict__ q, const double* __restrict__ Sz,
-    const double* __restrict__ Vz, const double* __restrict__ Sp_old,
-    const double* __restrict__ Vp_old, double* __restrict__ Sp_new,
-    double* __restrict__ Vp_new, int nreal, int nfg, int fpg,
+    const float* __restrict__ Vz, const double* __restrict__ Sp_old,
+    const float* __restrict__ Vp_old, double* __restrict__ Sp_new,
+    float* __restrict__ Vp_new, int nreal, int nfg, int fpg,
     const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
     double* __restrict__ part, Scal* __restrict__ sc, int gn_it, Blk blk) {
   constexpr int D = 2;
@@ -528,9 +528,9 @@ __global__ __launch_bounds__(kHv2Threads, REG ? 8 : 5) void cgt_hvp2_kernel(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
     Model md, float* __restrict__ q, const double* __restrict__ Sz,
-    const double* __restrict__ Vz, const double* __restrict__ Sp_old,
-    const double* __restrict__ Vp_old, double* __restrict__ Sp_new,
-    double* __restrict__ Vp_new, int nreal, int nfg, int fpg,
+    const float* __restrict__ Vz, const double* __restrict__ Sp_old,
+    const float* __restrict__ Vp_old, double* __restrict__ Sp_new,
+    float* __restrict__ Vp_new, int nreal, int nfg, int fpg,
     const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
     double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
   cgt_hvp2_body<REG, FIRST>(it, zv, p_old, p_new, dW, g, md, q, Sz, Vz, Sp_old,
@@ -545,9 +545,9 @@ __global__ __launch_bounds__(kHv2Threads, REG ? 8 : 5) void cgt_hvp2_kernel(
 // (they do not stay in the L2 across a column's frames), so it reads these
 // four values instead of eight.
 __device__ __forceinline__ void cg_psums_body(
-    int it, const double* __restrict__ Sz, const double* __restrict__ Vz,
-    const double* __restrict__ Sp_old, const double* __restrict__ Vp_old,
-    double* __restrict__ Sp_new, double* __restrict__ Vp_new, long long N,
+    int it, const double* __restrict__ Sz, const float* __restrict__ Vz,
+    const double* __restrict__ Sp_old, const float* __restrict__ Vp_old,
+    double* __restrict__ Sp_new, float* __restrict__ Vp_new, long long N,
     const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
     Scal* __restrict__ sc, int gn_it, Blk blk) {
   constexpr int D = 3;
@@ -577,9 +577,9 @@ __device__ __forceinline__ void cg_psums_body(
 }
 
 __global__ __launch_bounds__(1024) void cg_psums_kernel(
-    int it, const double* __restrict__ Sz, const double* __restrict__ Vz,
-    const double* __restrict__ Sp_old, const double* __restrict__ Vp_old,
-    double* __restrict__ Sp_new, double* __restrict__ Vp_new, long long N,
+    int it, const double* __restrict__ Sz, const float* __restrict__ Vz,
+    const double* __restrict__ Sp_old, const float* __restrict__ Vp_old,
+    double* __restrict__ Sp_new, float* __restrict__ Vp_new, long long N,
     const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
     Scal* __restrict__ sc, int gn_it) {
   cg_psums_body(it, Sz, Vz, Sp_old, Vp_old, Sp_new, Vp_new, N, up_part, up_nb,
@@ -603,9 +603,9 @@ __device__ __forceinline__ void cgt_hvp3_body(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, const Geom& g,
     const Model& md, float* __restrict__ q, const double* __restrict__ Sz,
-    const double* __restrict__ Vz, const double* __restrict__ Sp_old,
-    const double* __restrict__ Vp_old, double* __restrict__ Sp_new,
-    double* __restrict__ Vp_new, int nreal, int nfg, int fpg,
+    const float* __restrict__ Vz, const double* __restrict__ Sp_old,
+    const float* __restrict__ Vp_old, double* __restrict__ Sp_new,
+    float* __restrict__ Vp_new, int nreal, int nfg, int fpg,
     const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
     double* __restrict__ part, Scal* __restrict__ sc, int gn_it, Blk blk) {
   constexpr int D = 3;
@@ -629,7 +629,7 @@ __device__ __forceinline__ void cgt_hvp3_body(
   // before); it = 0: p = z, whose sums this kernel keeps for the next step
   const double beta = FIRST ? 0.0 : sc->beta;
   const double* Sc = FIRST ? Sz : Sp_new;
-  const double* Vc = FIRST ? Vz : Vp_new;
+  const float* Vc = FIRST ? Vz : Vp_new;
   const float bf = (float)beta;
   const int per_xcd = blk.n / kXCD;
   const int bb = (blk.id % kXCD) * per_xcd + blk.id / kXCD;
@@ -809,9 +809,9 @@ __global__ __launch_bounds__(kHv3Threads, 4) void cgt_hvp3_kernel(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
     Model md, float* __restrict__ q, const double* __restrict__ Sz,
-    const double* __restrict__ Vz, const double* __restrict__ Sp_old,
-    const double* __restrict__ Vp_old, double* __restrict__ Sp_new,
-    double* __restrict__ Vp_new, int nreal, int nfg, int fpg,
+    const float* __restrict__ Vz, const double* __restrict__ Sp_old,
+    const float* __restrict__ Vp_old, double* __restrict__ Sp_new,
+    float* __restrict__ Vp_new, int nreal, int nfg, int fpg,
     const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
     double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
   cgt_hvp3_body<REG, FIRST>(it, zv, p_old, p_new, dW, g, md, q, Sz, Vz, Sp_old,
@@ -864,9 +864,9 @@ hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
   const int dim = geom_dim(g);
   CgTiles t = cg_tiles(g, md.nK, dim);
   const double* Sp_old = sums.Sp[(it + 1) & 1];
-  const double* Vp_old = sums.Vp[(it + 1) & 1];
+  const float* Vp_old = sums.Vp[(it + 1) & 1];
   double* Sp_new = sums.Sp[it & 1];
-  double* Vp_new = sums.Vp[it & 1];
+  float* Vp_new = sums.Vp[it & 1];
   // with events: the dispatch records its own start and end
   decltype(&cgt_hvp2_kernel<0, true>) kern;
   if (it == 0)

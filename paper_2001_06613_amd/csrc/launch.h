@@ -76,7 +76,7 @@ struct CgStart {
   float* r;
   float* z;
   double* Sz;
-  double* Vz;
+  float* Vz;
 };
 // finalize = false leaves the partials for the CG start to reduce.
 // gn_it: Gauss-Newton iteration this launch belongs to (ignored when
@@ -119,13 +119,15 @@ hipError_t launch_finalize_vhv(const double* part, int nb, Scal* sc,
                                hipStream_t s);
 
 // --- CG with per-voxel cross-frame sums (cg_tiles.hip) -------------------
-// Float64 per-voxel sums: S = sum_k dW_k . v_k ([N]) and V = sum_k v_k
-// ([D][N]) of z, and of the CG directions (ping-pong by CG iteration).
+// Per-voxel sums, accumulated in float64: S = sum_k dW_k . v_k ([N],
+// stored float64: the data term subtracts its mean from each s_k) and
+// V = sum_k v_k ([D][N], stored float32: it only feeds the penalty term) of
+// z, and of the CG directions (ping-pong by CG iteration).
 struct CgSums {
   double* Sz;
-  double* Vz;
+  float* Vz;
   double* Sp[2];
-  double* Vp[2];
+  float* Vp[2];
 };
 struct CgTiles {             // launch shape of the Hessian product
   int nreal, nfg, fpg, grid, vox_grid;

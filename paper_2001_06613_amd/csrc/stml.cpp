@@ -262,10 +262,10 @@ size_t layout(stml_ctx* c, char* base) {
   {
     size_t NF = (size_t)c->N[c->L - 1];
     c->sums.Sz = lo.take<double>(NF);
-    c->sums.Vz = lo.take<double>(NF * D);
+    c->sums.Vz = lo.take<float>(NF * D);
     for (int i = 0; i < 2; ++i) {
       c->sums.Sp[i] = lo.take<double>(NF);
-      c->sums.Vp[i] = lo.take<double>(NF * D);
+      c->sums.Vp[i] = lo.take<float>(NF * D);
     }
   }
   c->rb.part = lo.take<double>(kRedSlots);
