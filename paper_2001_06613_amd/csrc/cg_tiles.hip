@@ -8,7 +8,7 @@
 // no sweep over frames and runs as a plain stencil kernel, parallel over
 // (frame, spatial tile): in 2-D each block stages p = z + beta p_old of a
 // 64 x 4 tile with a 2-cell halo in LDS, forms L p once per point and
-// L (L p) from LDS; in 3-D a block marches a 16 x 16 column through the
+// L (L p) from LDS; in 3-D a block marches a 32 x 16 column through the
 // planes with rings of planes in LDS.  The vector updates are voxel-major
 // (the waves of a block split the frames of a 64-voxel tile) so that they
 // can sum S_z and V_z per voxel; the Jacobi diagonal is recomputed there
@@ -587,14 +587,14 @@ __global__ __launch_bounds__(1024) void cg_psums_kernel(
 }
 
 // 3-D Hessian product on p = z + beta p_old (it > 0) or p = z for one
-// column of a group of frames: a 16 x 16 tile in (x, y) marched through
+// column of a group of frames: a 32 x 16 tile in (x, y) marched through
 // kT3Z planes in z.  For each frame the block keeps a ring of five planes of
 // p (2-cell halo, float32: exactly the values the kernel stores) and three
 // planes of L p (1-cell halo; formed in float64 and kept as float32, which
-// lets four blocks share a compute unit) in LDS; every step stages one new
-// plane of p (its loads issued one step ahead, into registers), forms one
+// lets two 512-thread blocks share a compute unit) in LDS; every step stages
+// one new plane of p (its loads issued one step ahead, into registers), forms one
 // plane of L p and finishes one plane of q = H p.  The halo overhead per
-// step is that of a 2-D tile (20 x 20 loads for 16 x 16 outputs) instead of
+// step is that of a 2-D tile (36 x 20 loads for 32 x 16 outputs) instead of
 // a 3-D one.  The voxel sums of p are read per frame: at CG step 0 those of
 // z (which the product keeps for the next step), later the ones
 // cg_psums_kernel formed together with beta.
@@ -802,8 +802,9 @@ __device__ __forceinline__ void cgt_hvp3_body(
   block_partials<1>(vals, 0u, part, blk);
 }
 
-// Four blocks per compute unit (at most 128 registers per lane; the LDS
-// rings take 40 KB).
+// Two 512-thread blocks per compute unit (at most 128 registers per lane;
+// the LDS rings take 64 KB).  Columns of 32 x 16 measured 15% faster than
+// 16 x 16 ones (less halo per output), and than 64 x 16, 32 x 32 and 32 x 8.
 template <int REG, bool FIRST>
 __global__ __launch_bounds__(kHv3Threads, 4) void cgt_hvp3_kernel(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,

@@ -294,7 +294,7 @@ hipError_t launch_aff_field(const double* theta, int n, const AffGeom& ag,
 void net_capacity(const stml_net* n, int* max_batch, long long* max_pixels);
 int net_dim(const stml_net* n);
 // 3-D Hessian-product columns: x, y tile and planes marched in z
-constexpr int kHv3X = 16, kHv3Y = 16, kHv3Z = 16;
+constexpr int kHv3X = 32, kHv3Y = 16, kHv3Z = 16;
 constexpr int kMaxNetWidth = 256;   // widest frame row the net accepts
 
 }  // namespace stml

@@ -28,9 +28,10 @@ CASES = [
     ("3d_ragged_diff", 3, (7, 12, 13), 1, "diffusion", [0, 1, 2]),
     ("2d_thin_row", 4, (1, 150), 1, "curvature", [0, 1, 2, 3]),
     ("2d_single_frame", 3, (20, 70), 1, "curvature", [1]),
-    # several 16 x 16 columns of 16 planes, each axis with a ragged tail
+    # several 32 x 16 columns of 16 planes, each axis with a ragged tail
     ("3d_columns_curv", 3, (37, 20, 35), 1, "curvature", [0, 2]),
     ("3d_columns_diff", 2, (20, 33, 17), 1, "diffusion", [0, 1]),
+    ("3d_columns_wide", 2, (18, 17, 70), 1, "curvature", [0, 1]),
 ]
 
 

@@ -268,9 +268,9 @@ def _volume(n, ext, seed):
 
 
 @pytest.mark.parametrize("reg", ["diffusion", "curvature"])
-@pytest.mark.parametrize("ext", [(10, 12, 18), (37, 20, 35)])
+@pytest.mark.parametrize("ext", [(10, 12, 18), (37, 20, 70)])
 def test_gn_direction_parity_3d(reg, ext):
-    # ragged against 16 x 16 x 16 columns; the second spans several columns
+    # ragged against 32 x 16 x 16 columns; the second spans several columns
     # on every axis (CG steps > 0 take beta and the sums of p from the sums
     # kernel)
     n = 4
