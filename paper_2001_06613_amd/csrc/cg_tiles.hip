@@ -521,10 +521,11 @@ __device__ __forceinline__ void cgt_hvp2_body(
   block_partials<1>(vals, 0u, part, blk);
 }
 
-// Eight blocks per compute unit (at most 64 registers per lane) keep enough
-// tile loads in flight (the diffusion form needs more registers: five).
+// Seven blocks per compute unit (at most 72 registers per lane) keep enough
+// tile loads in flight without the spill that eight (64 registers) cost
+// (the diffusion form needs more registers: five).
 template <int REG, bool FIRST>
-__global__ __launch_bounds__(kHv2Threads, REG ? 8 : 5) void cgt_hvp2_kernel(
+__global__ __launch_bounds__(kHv2Threads, REG ? 7 : 5) void cgt_hvp2_kernel(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
     Model md, float* __restrict__ q, const double* __restrict__ Sz,
@@ -952,7 +953,7 @@ __device__ __forceinline__ const Job& cg_job_of(const JobSet& js, int c,
 
 template <int D, int REG, bool FIRST>
 __global__ __launch_bounds__(D == 2 ? kHv2Threads : kHv3Threads,
-                             D == 3 ? 4 : (REG ? 8 : 5)) void cg_hvp_batch_kernel(
+                             D == 3 ? 4 : (REG ? 7 : 5)) void cg_hvp_batch_kernel(
     JobSet js, int it, int fixed, double rtol) {
   Blk blk;
   const Job& J = cg_job_of(js, kClsHv, blk);
