@@ -264,6 +264,7 @@ __device__ __forceinline__ void eval_body(
   for (int it = 0;; ++it) {
     long long tile = xcd_tile(ntiles, it, blk);
     if (tile < 0) break;
+    tile = stencil_tile<D>(g, tile);
     long long x = tile * kWave + lane;
     bool valid = x < N;
     Pos<D> p = make_pos<D>(g, valid ? x : N - 1);
@@ -560,6 +561,7 @@ __device__ __forceinline__ void trial_body(
   for (int it = 0;; ++it) {
     long long tile = xcd_tile(ntiles, it, blk);
     if (tile < 0) break;
+    tile = stencil_tile<D>(g, tile);
     long long x = tile * kWave + lane;
     bool valid = x < N;
     Pos<D> p = make_pos<D>(g, valid ? x : N - 1);

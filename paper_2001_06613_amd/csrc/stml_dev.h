@@ -508,4 +508,30 @@ __device__ __forceinline__ long long xcd_tile(long long ntiles, int i) {
   return xcd_tile(ntiles, i, grid_blk());
 }
 
+// Tile order of the volume sweeps whose regulariser stencils reach the
+// neighbouring z-lines (evaluation and trial steps).  A tile is 64 voxels
+// of one z-line when the z-extent is a multiple of 64; in index order the
+// lines at x +- 1 and x +- 2 come m1 and 2 m1 tiles later and have left the
+// L2 by then.  Ordered instead in bands of kLineBand y-lines (x slower
+// within a band), they come kLineBand and 2 kLineBand tiles later, in the
+// same round of a die's blocks; with m1 = 8 kLineBand every die's range of
+// tiles (xcd_tile) is one band.  t: position in the order; returns the
+// index of the tile.  Other shapes keep index order.
+constexpr unsigned kLineBand = 16;
+template <int D>
+__device__ __forceinline__ long long stencil_tile(const Geom& g, long long t) {
+  if (D != 3 || g.m[2] % kWave != 0) return t;
+  const unsigned nz = (unsigned)g.m[2] / kWave;
+  const unsigned m0 = (unsigned)g.m[0], m1 = (unsigned)g.m[1];
+  const unsigned tt = (unsigned)t;
+  const unsigned band = kLineBand * m0 * nz;  // tiles of a full band
+  const unsigned b = tt / band;
+  const unsigned r = tt - b * band;
+  const unsigned y0 = b * kLineBand;
+  const unsigned bw = (m1 - y0 < kLineBand ? m1 - y0 : kLineBand) * nz;
+  const unsigned i0 = r / bw;  // x of the line
+  // the rest, r - i0 bw, is (y - y0) nz + the tile within the line
+  return ((long long)i0 * m1 + y0) * nz + (r - i0 * bw);
+}
+
 }  // namespace stml
