@@ -722,11 +722,46 @@ __device__ __forceinline__ void ls_accept_body(
   const unsigned DN = (unsigned)dim * (unsigned)N;
   const size_t count = (size_t)nK * DN;
   const unsigned stride = (unsigned)blk.n * blockDim.x;
-  for (unsigned e = (unsigned)blk.id * blockDim.x + threadIdx.x; e < count;
-       e += stride) {
-    const unsigned j = e / DN;
-    const size_t o = (size_t)K[j] * DN + (e - j * DN);
+  // element e = j DN + i of delta (frame j of K), (j, i) advanced by the
+  // stride without a division.  K is read from LDS, and in the passes where
+  // all four of a thread's elements exist their loads issue together with
+  // no branch between them; the rest go one at a time.
+  __shared__ int Ks[kMaxFrames];
+  for (int t = threadIdx.x; t < nK; t += blockDim.x) Ks[t] = K[t];
+  __syncthreads();
+  unsigned e = (unsigned)blk.id * blockDim.x + threadIdx.x;
+  unsigned j = e / DN, i = e - (e / DN) * DN;
+  constexpr int kU = 4;
+  auto advance = [&]() {
+    e += stride;
+    i += stride;
+    while (i >= DN && j < (unsigned)nK) {
+      i -= DN;
+      ++j;
+    }
+  };
+  while (e + (kU - 1) * stride < count) {
+    size_t o[kU], d[kU];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      o[k] = (size_t)Ks[j] * DN + i;
+      d[k] = e;
+      advance();
+    }
+    float uv[kU], dv[kU];
+#pragma unroll
+    for (int k = 0; k < kU; ++k) {
+      uv[k] = u[o[k]];
+      dv[k] = dl[d[k]];
+    }
+#pragma unroll
+    for (int k = 0; k < kU; ++k)
+      u[o[k]] = (float)((double)uv[k] + tacc * (double)dv[k]);
+  }
+  while (e < count) {
+    const size_t o = (size_t)Ks[j] * DN + i;
     u[o] = (float)((double)u[o] + tacc * (double)dl[e]);
+    advance();
   }
   if (blk.id == 0 && threadIdx.x == 0) {
     bool breakdown = sc->done == 2;

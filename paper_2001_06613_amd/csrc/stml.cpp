@@ -17,6 +17,9 @@
 
 using namespace stml;
 
+static_assert(STML_MAX_FRAMES == kMaxFrames,
+              "the kernels size per-frame LDS tables by kMaxFrames");
+
 namespace {
 
 constexpr size_t kAlign = 256;

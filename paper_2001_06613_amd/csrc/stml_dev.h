@@ -13,6 +13,7 @@ namespace stml {
 constexpr int kWave = 64;          // CDNA wavefront
 constexpr int kMaxFPT = 16;        // max frames one thread keeps in registers
 constexpr int kMaxChunks = 16;     // waves per block -> |K| <= 256
+constexpr int kMaxFrames = 256;    // frames of a sequence (the C-ABI maximum)
 constexpr int kTrialSteps = 10;    // Armijo steps of a sweep after the first
 constexpr int kXCD = 8;            // MI355X: 8 accelerator complex dies
 constexpr int kCUs = 256;          // compute units (32 per die)
