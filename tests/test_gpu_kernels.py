@@ -32,6 +32,11 @@ CASES = [
     ("3d_columns_curv", 3, (37, 20, 35), 1, "curvature", [0, 2]),
     ("3d_columns_diff", 2, (20, 33, 17), 1, "diffusion", [0, 1]),
     ("3d_columns_wide", 2, (18, 17, 70), 1, "curvature", [0, 1]),
+    # z-extents that are multiples of the 64-voxel tile: the evaluation
+    # takes its tiles in bands of 16 y-lines; two tiles per z-line and a
+    # ragged last band (16, 16, 5 lines), and a single short band
+    ("3d_line_bands", 3, (5, 37, 128), 1, "curvature", [0, 2]),
+    ("3d_line_short", 2, (9, 7, 64), 1, "diffusion", [0, 1]),
 ]
 
 

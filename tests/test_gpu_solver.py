@@ -268,11 +268,12 @@ def _volume(n, ext, seed):
 
 
 @pytest.mark.parametrize("reg", ["diffusion", "curvature"])
-@pytest.mark.parametrize("ext", [(10, 12, 18), (37, 20, 70)])
+@pytest.mark.parametrize("ext", [(10, 12, 18), (37, 20, 70), (5, 37, 128)])
 def test_gn_direction_parity_3d(reg, ext):
     # ragged against 32 x 16 x 16 columns; the second spans several columns
     # on every axis (CG steps > 0 take beta and the sums of p from the sums
-    # kernel)
+    # kernel); the third has whole 64-voxel z-line tiles, which the
+    # evaluation takes in bands of 16 y-lines (the last band ragged)
     n = 4
     frames = _volume(n, ext, 21)
     o = default_opts(dim=3, n_spatial=1, n_temporal=2, reg=reg, cg_max=8,
@@ -296,8 +297,10 @@ def test_gn_direction_parity_3d(reg, ext):
 
 
 @pytest.mark.parametrize("reg", ["diffusion", "curvature"])
-def test_register_level_parity_3d(reg):
-    ext = (10, 12, 18)
+@pytest.mark.parametrize("ext", [(10, 12, 18), (4, 21, 64)])
+def test_register_level_parity_3d(reg, ext):
+    # the second: evaluation and trial sweeps in bands of 16 y-lines of
+    # whole z-line tiles (16 and 5 lines)
     n = 4
     frames = _volume(n, ext, 22)
     kw = dict(dim=3, n_spatial=1, n_temporal=2, reg=reg, gn_max=3, cg_max=6,
