@@ -205,7 +205,62 @@ __device__ __forceinline__ void cgv_update_body(
     double s = 0.0, v[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) v[a] = 0.0;
-    if (valid) {
+    // one frame from its loaded values: x, r, z stored, sums accumulated
+    auto frame = [&](size_t base, const float* pf, const float* df,
+                     const float* xf, const float* rf, const float* qf) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        size_t o = base + (size_t)a * N;
+        double pe = (double)pf[a];
+        double d = (double)df[a];
+        float xn = FIRST ? (float)(alpha * pe)
+                         : (float)((double)xf[a] + alpha * pe);
+        float rv = (float)((double)rf[a] - alpha * (double)qf[a]);
+        float zv = (float)((double)rv / (md.mdiag_c * d * d + rest));
+        x[o] = xn;
+        r[o] = rv;
+        z[o] = zv;
+        rz += (double)rv * (double)zv;
+        rr += (double)rv * (double)rv;
+        s += d * (double)zv;
+        v[a] += (double)zv;
+      }
+    };
+    auto load = [&](size_t base, float* pf, float* df, float* xf, float* rf,
+                    float* qf) {
+#pragma unroll
+      for (int a = 0; a < D; ++a) {
+        const size_t o = base + (size_t)a * N;
+        pf[a] = p[o];
+        df[a] = dW[o];
+        xf[a] = FIRST ? 0.f : x[o];
+        rf[a] = r[o];
+        qf[a] = q[o];
+      }
+    };
+    if (valid && PRE) {
+      // small grids (a wave's frames in turn are the latency): after the
+      // frame requested ahead, two frames per pass, whose loads issue
+      // together (an odd last frame loads its own values twice); frames
+      // are accumulated in order, as one at a time
+      int j = j0;
+      if (tt == 0 && j < j1) {
+        frame((size_t)j * D * N + pos.idx, pf0[0], df0[0], xf0[0], rf0[0],
+              qf0[0]);
+        ++j;
+      }
+#pragma unroll 1
+      for (; j < j1; j += 2) {
+        const int jb = j + 1 < j1 ? j + 1 : j;
+        const size_t b0 = (size_t)j * D * N + pos.idx;
+        const size_t b1 = (size_t)jb * D * N + pos.idx;
+        float pf[2][D], df[2][D], xf[2][D], rf[2][D], qf[2][D];
+        load(b0, pf[0], df[0], xf[0], rf[0], qf[0]);
+        load(b1, pf[1], df[1], xf[1], rf[1], qf[1]);
+        frame(b0, pf[0], df[0], xf[0], rf[0], qf[0]);
+        if (jb != j) frame(b1, pf[1], df[1], xf[1], rf[1], qf[1]);
+      }
+    } else if (valid) {
 #pragma unroll 1
       for (int j = j0; j < j1; ++j) {
         const size_t base = (size_t)j * D * N + pos.idx;
@@ -245,33 +300,9 @@ __device__ __forceinline__ void cgv_update_body(
           }
           continue;
         } else {
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            const size_t o = base + (size_t)a * N;
-            pf[a] = p[o];
-            df[a] = dW[o];
-            xf[a] = FIRST ? 0.f : x[o];
-            rf[a] = r[o];
-            qf[a] = q[o];
-          }
+          load(base, pf, df, xf, rf, qf);
         }
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          size_t o = base + (size_t)a * N;
-          double pe = (double)pf[a];
-          double d = (double)df[a];
-          float xn = FIRST ? (float)(alpha * pe)
-                           : (float)((double)xf[a] + alpha * pe);
-          float rv = (float)((double)rf[a] - alpha * (double)qf[a]);
-          float zv = (float)((double)rv / (md.mdiag_c * d * d + rest));
-          x[o] = xn;
-          r[o] = rv;
-          z[o] = zv;
-          rz += (double)rv * (double)zv;
-          rr += (double)rv * (double)rv;
-          s += d * (double)zv;
-          v[a] += (double)zv;
-        }
+        frame(base, pf, df, xf, rf, qf);
       }
     }
     store_voxel_sums<D>(s, v, xv, valid, N, Sz, Vz);
