@@ -238,7 +238,12 @@ __device__ __forceinline__ Chunk frame_chunk(int nK) {
 // from the float32 dW/du, per-voxel S_z = sum_k dW_k . z_k and V_z =
 // sum_k z_k (combined over the waves in LDS), and partials of r.z and r.r
 // after those of D, S, P (5 x gridDim slots).
-template <int D, int REG, bool INIT>
+// PAIR (grids of at most one block per compute unit, where a wave's frames
+// in turn are the latency): both sweeps take two frames per pass, whose
+// loads issue together (in sweep 2 all stencils of both frames before any
+// arithmetic); every value is formed and accumulated as one frame at a time,
+// in the same order, so the results are bitwise those of the plain form.
+template <int D, int REG, bool INIT, bool PAIR = false>
 __device__ __forceinline__ void eval_body(
     const float* __restrict__ T, const float* __restrict__ u,
     const int* __restrict__ K, const Geom& g, const Model& md,
@@ -274,13 +279,13 @@ __device__ __forceinline__ void eval_body(
     double sW = 0.0, sU[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) sU[a] = 0.0;
-    for (int j = ch.j0; j < ch.j1; ++j) {
-      int k = K[j];
-      const float* uk = u + (size_t)k * D * N;
-      double uv[D], dw[D], W;
+    // sweep 1, one frame: displacement, then the warp's gathers
+    auto s1_load = [&](int j, double* uv) {
+      const float* uk = u + (size_t)K[j] * D * N;
 #pragma unroll
       for (int a = 0; a < D; ++a) uv[a] = (double)uk[(size_t)a * N + p.idx];
-      warp_sample<D>(T + (size_t)k * N, g, p, uv, W, dw);
+    };
+    auto s1_frame = [&](int j, const double* uv, double W, const double* dw) {
       sW += W;
       if (j - ch.j0 < kWF) {
         wc[w][j - ch.j0][lane] = W;
@@ -292,6 +297,25 @@ __device__ __forceinline__ void eval_body(
       for (int a = 0; a < D; ++a) {
         sU[a] += uv[a];
         if (valid && dj) dj[(size_t)a * N + p.idx] = (float)dw[a];
+      }
+    };
+    if (PAIR) {
+      for (int j = ch.j0; j < ch.j1; j += 2) {
+        const int jb = j + 1 < ch.j1 ? j + 1 : j;
+        double u0[D], u1[D], dw0[D], dw1[D], W0, W1;
+        s1_load(j, u0);
+        s1_load(jb, u1);
+        warp_sample<D>(T + (size_t)K[j] * N, g, p, u0, W0, dw0);
+        warp_sample<D>(T + (size_t)K[jb] * N, g, p, u1, W1, dw1);
+        s1_frame(j, u0, W0, dw0);
+        if (jb != j) s1_frame(jb, u1, W1, dw1);
+      }
+    } else {
+      for (int j = ch.j0; j < ch.j1; ++j) {
+        double uv[D], dw[D], W;
+        s1_load(j, uv);
+        warp_sample<D>(T + (size_t)K[j] * N, g, p, uv, W, dw);
+        s1_frame(j, uv, W, dw);
       }
     }
     xs[w][lane][0] = sW;
@@ -312,30 +336,33 @@ __device__ __forceinline__ void eval_body(
     for (int a = 0; a < D; ++a) ub[a] *= md.inv_nK;
     if (valid) {
       const double rest = INIT ? jacobi_rest<D>(p, g, md) : 0.0;
-      for (int j = ch.j0; j < ch.j1; ++j) {
-        int k = K[j];
-        const float* uk = u + (size_t)k * D * N;
-        double dw[D], W;
+      const Nbr<D> nbr = neighbours<D>(p, g);
+      constexpr int NP = RegPts<D, REG>::kN;
+      // sweep 2, one frame: W and dW/du (from LDS, or warped again)
+      auto s2_wd = [&](int j, double& W, double* dw) {
         if (j - ch.j0 < kWF) {
           W = wc[w][j - ch.j0][lane];
 #pragma unroll
           for (int a = 0; a < D; ++a) dw[a] = (double)dc[w][j - ch.j0][a][lane];
         } else {
+          const float* uk = u + (size_t)K[j] * D * N;
           double uv[D];
 #pragma unroll
           for (int a = 0; a < D; ++a)
             uv[a] = (double)uk[(size_t)a * N + p.idx];
-          warp_sample<D>(T + (size_t)k * N, g, p, uv, W, dw);
+          warp_sample<D>(T + (size_t)K[j] * N, g, p, uv, W, dw);
 #pragma unroll
           for (int a = 0; a < D; ++a) dw[a] = (double)(float)dw[a];
         }
-        double r = W - Wb;
-        accD += r * r;
+      };
+      // ... then the residual, the regulariser terms from the loaded
+      // stencils of its components, the gradient and the PCG start
+      auto s2_comp = [&](int j, int a, double r, const double* dw,
+                         const float (&va)[NP]) {
         float* gj = grad ? grad + (size_t)j * D * N : nullptr;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
+        {
           double btb, e, cen;
-          reg_terms<D, REG>(Src1{uk + (size_t)a * N}, p, g, btb, e, cen);
+          reg_eval<D, REG>(va, nbr, btb, e, cen);
           accS += e;
           if (gj) {
             double gv = md.data_c * r * dw[a] +
@@ -354,6 +381,50 @@ __device__ __forceinline__ void eval_body(
               sz += dw[a] * (double)zv;
               vz[a] += (double)zv;
             }
+          }
+        }
+      };
+      auto s2_frame = [&](int j, double W, const double* dw,
+                          const float (*v)[NP]) {
+        const double r = W - Wb;
+        accD += r * r;
+#pragma unroll
+        for (int a = 0; a < D; ++a) s2_comp(j, a, r, dw, v[a]);
+      };
+      auto s2_load = [&](int j, float (*v)[NP]) {
+        const float* uk = u + (size_t)K[j] * D * N;
+#pragma unroll
+        for (int a = 0; a < D; ++a)
+          reg_load<D, REG>(Src1{uk + (size_t)a * N}, p, nbr, v[a]);
+      };
+      if (PAIR) {
+        for (int j = ch.j0; j < ch.j1; j += 2) {
+          const int jb = j + 1 < ch.j1 ? j + 1 : j;
+          double W0, W1, dw0[D], dw1[D];
+          float v0[D][NP], v1[D][NP];
+          s2_wd(j, W0, dw0);
+          s2_wd(jb, W1, dw1);
+          s2_load(j, v0);
+          s2_load(jb, v1);
+          // keep the stencil loads of both frames together
+          __builtin_amdgcn_sched_barrier(0);
+          s2_frame(j, W0, dw0, v0);
+          if (jb != j) s2_frame(jb, W1, dw1, v1);
+        }
+      } else {
+        for (int j = ch.j0; j < ch.j1; ++j) {
+          double W, dw[D];
+          s2_wd(j, W, dw);
+          const double r = W - Wb;
+          accD += r * r;
+          // one component's stencil at a time: its loads, then its terms
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            float va[NP];
+            reg_load<D, REG>(Src1{u + ((size_t)K[j] * D + a) * N}, p, nbr,
+                             va);
+            __builtin_amdgcn_sched_barrier(0);
+            s2_comp(j, a, r, dw, va);
           }
         }
       }
@@ -387,15 +458,17 @@ __device__ __forceinline__ void eval_body(
 }
 
 // Two 8-wave blocks per compute unit in 2-D (LDS allows two): at most 128
-// registers per lane.
-template <int D, int REG, bool INIT>
-__global__ __launch_bounds__(D == 2 ? 512 : 256, D == 2 ? 4 : 1) void eval_kernel(
+// registers per lane.  The paired form runs on grids of at most one block
+// per compute unit: at most 256.
+template <int D, int REG, bool INIT, bool PAIR = false>
+__global__ __launch_bounds__(D == 2 ? 512 : 256,
+                             D == 2 ? (PAIR ? 2 : 4) : 1) void eval_kernel(
     const float* __restrict__ T, const float* __restrict__ u,
     const int* __restrict__ K, Geom g, Model md, float* __restrict__ grad,
     float* __restrict__ dWo, double* __restrict__ part, int gn_it,
     const Scal* __restrict__ sc, CgStart cs) {
-  eval_body<D, REG, INIT>(T, u, K, g, md, grad, dWo, part, gn_it, sc, cs,
-                          grid_blk());
+  eval_body<D, REG, INIT, PAIR>(T, u, K, g, md, grad, dWo, part, gn_it, sc,
+                                cs, grid_blk());
 }
 
 // One block: the objective of the evaluation and the CG start scalars (the
@@ -1120,7 +1193,15 @@ hipError_t launch_eval(int dim, const float* T, const float* u, const int* K,
   const CgStart none{nullptr, nullptr, nullptr, nullptr};
   const CgStart c0 = cs ? *cs : none;
   decltype(&eval_kernel<2, 0, false>) kern;
-  if (dim == 2)
+  // images on grids of at most one block per compute unit: the paired form
+  // (the same results)
+  if (dim == 2 && nb <= kCUs)
+    kern = md.reg == 0
+               ? (cs ? eval_kernel<2, 0, true, true>
+                     : eval_kernel<2, 0, false, true>)
+               : (cs ? eval_kernel<2, 1, true, true>
+                     : eval_kernel<2, 1, false, true>);
+  else if (dim == 2)
     kern = md.reg == 0 ? (cs ? eval_kernel<2, 0, true> : eval_kernel<2, 0, false>)
                        : (cs ? eval_kernel<2, 1, true> : eval_kernel<2, 1, false>);
   else

@@ -238,22 +238,28 @@ __device__ __forceinline__ constexpr int diag_index(int a, int sa, int b,
 
 // B^T B v at p (without the 1/h^2 or 1/h^4 factor), this voxel's share of
 // ||B v||^2 and v at p: diffusion (REG 0) -> (-L v, forward-face
-// differences squared); curvature (REG 1) -> (L (L v), (L v)^2).  All the
-// stencil's loads are issued first, then the float64 arithmetic.
+// differences squared); curvature (REG 1) -> (L (L v), (L v)^2).  In two
+// parts, so that a caller can issue the loads of several stencils before
+// the arithmetic of any: reg_load issues the stencil's loads, reg_eval does
+// the float64 arithmetic on them.
+template <int D, int REG>
+struct RegPts {
+  static constexpr int kN = REG ? StencilPts<D>::kAll : StencilPts<D>::kFace;
+};
 template <int D, int REG, class F>
-__device__ __forceinline__ void reg_terms(const F& f, const Pos<D>& p,
-                                          const Geom& g, double& btb,
-                                          double& energy, double& centre) {
-  constexpr int NP = REG ? StencilPts<D>::kAll : StencilPts<D>::kFace;
-  const Nbr<D> nb = neighbours<D>(p, g);
+__device__ __forceinline__ void reg_load(const F& f, const Pos<D>& p,
+                                         const Nbr<D>& nb,
+                                         float (&v)[RegPts<D, REG>::kN]) {
+  constexpr int NP = RegPts<D, REG>::kN;
   int off[NP];
   stencil_offsets<D, NP>(nb, off);
-  float v[NP];
 #pragma unroll
   for (int i = 0; i < NP; ++i) v[i] = f.ld(p.idx + off[i]);
-  // keep the loads together: interleaved with their uses they would wait
-  // for each other one by one
-  __builtin_amdgcn_sched_barrier(0);
+}
+template <int D, int REG>
+__device__ __forceinline__ void reg_eval(const float (&v)[RegPts<D, REG>::kN],
+                                         const Nbr<D>& nb, double& btb,
+                                         double& energy, double& centre) {
   const double c = (double)v[0];
   centre = c;
   double vm[D], vp[D], Lc = 0.0;
@@ -290,6 +296,19 @@ __device__ __forceinline__ void reg_terms(const F& f, const Pos<D>& p,
     }
   btb = LL;
   energy = Lc * Lc;
+}
+// Both parts for one stencil; all its loads are issued first.
+template <int D, int REG, class F>
+__device__ __forceinline__ void reg_terms(const F& f, const Pos<D>& p,
+                                          const Geom& g, double& btb,
+                                          double& energy, double& centre) {
+  const Nbr<D> nb = neighbours<D>(p, g);
+  float v[RegPts<D, REG>::kN];
+  reg_load<D, REG>(f, p, nb, v);
+  // keep the loads together: interleaved with their uses they would wait
+  // for each other one by one
+  __builtin_amdgcn_sched_barrier(0);
+  reg_eval<D, REG>(v, nb, btb, energy, centre);
 }
 
 // Shares of ||B u||^2, <B u, B w>, ||B w||^2 at p (quadratic expansion of S).
