@@ -415,6 +415,15 @@ __device__ __forceinline__ void eval_body(
         for (int j = ch.j0; j < ch.j1; ++j) {
           double W, dw[D];
           s2_wd(j, W, dw);
+          if (D == 3) {
+            // volumes (no register cap): the stencils of all components
+            // before any arithmetic
+            float v[D][NP];
+            s2_load(j, v);
+            __builtin_amdgcn_sched_barrier(0);
+            s2_frame(j, W, dw, v);
+            continue;
+          }
           const double r = W - Wb;
           accD += r * r;
           // one component's stencil at a time: its loads, then its terms
