@@ -674,9 +674,10 @@ __device__ __forceinline__ void trial_body(
       }
       const float* Tk = T + (size_t)k * N;
       // steps whose loads issue together: three in a later image sweep;
-      // one at a time in the two-step sweep (two in flight measured
-      // slower under the register cap)
-      constexpr int TG = D == 2 ? (NT < 3 ? 1 : 3) : 1;
+      // one at a time in the two-step image sweep (two in flight measured
+      // slower under the register cap); both steps of the two-step volume
+      // sweep (no register cap), one at a time in a later one
+      constexpr int TG = D == 2 ? (NT < 3 ? 1 : 3) : (NT < 3 ? NT : 1);
 #pragma unroll 1
       for (int s0 = 0; s0 < NT; s0 += TG) {
         double wvs[TG];
