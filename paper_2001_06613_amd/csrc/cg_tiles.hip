@@ -92,59 +92,91 @@ __device__ __forceinline__ void cg_zero_x(float* __restrict__ x,
   }
 }
 
-// CG step, part 2: a = rz / p.q (stop on p.q <= 0); x += a p (x = a p at
-// it = 0: FIRST), r -= a q, z = M^-1 r; per-voxel S_z, V_z; partials r.z,
-// r.r.  A frame's loads (both components) issue before its stores, which
-// would otherwise hold the next component's loads back.  At it = 0 a CG
-// that stops before its first step sets x = 0.
-// FIRST with ev_part: the step also forms the start scalars of the
-// Gauss-Newton iteration from the evaluation's five partials (J = D + S +
-// P, r.z, r.r; the log's J) and takes their decisions: r.z = 0 ends the CG
-// with x = 0, and a start at or below the objective target takes no step.
-template <int D, bool FIRST, bool PRE>
-__device__ __forceinline__ void cgv_update_body(
-    int it, const float* __restrict__ p, const float* __restrict__ q,
-    const float* __restrict__ dW, const Geom& g, const Model& md,
-    float* __restrict__ x, float* __restrict__ r, float* __restrict__ z,
-    double* __restrict__ Sz, float* __restrict__ Vz,
-    const double* __restrict__ hv_part, int hv_nb, double* __restrict__ part,
-    Scal* __restrict__ sc, int gn_it, const double* __restrict__ ev_part,
-    int ev_nb, GNLog* __restrict__ log, Blk blk) {
-  const int stop = sc->gn_stop;
-  int done = sc->done;
-  double rz_it = sc->rzh[it & 1];
+// x = (zero ? 0 : x) + a p over this block's tiles (voxel-major, every
+// frame): the pending term of a CG that stopped after an even step.
+template <int D>
+__device__ __forceinline__ void cg_fold_x(float* __restrict__ x,
+                                          const float* __restrict__ p,
+                                          double a, bool zero, const Geom& g,
+                                          const Model& md, Blk blk) {
   int j0, j1;
   wave_frames(md.nK, j0, j1);
   const int lane = threadIdx.x & (kWave - 1);
   const long long N = g.N;
   const long long ntiles = (N + kWave - 1) / kWave;
+  for (int tt = 0;; ++tt) {
+    long long tile = xcd_tile(ntiles, tt, blk);
+    if (tile < 0) break;
+    long long xv = tile * kWave + lane;
+    if (xv >= N) continue;
+    for (int j = j0; j < j1; ++j)
+#pragma unroll
+      for (int a2 = 0; a2 < D; ++a2) {
+        const size_t o = ((size_t)j * D + a2) * N + (size_t)xv;
+        x[o] = (float)((zero ? 0.0 : (double)x[o]) + a * (double)p[o]);
+      }
+  }
+}
+
+// CG step, part 2: a = rz / p.q (stop on p.q <= 0); r -= a q, z = M^-1 r;
+// per-voxel S_z, V_z; partials r.z, r.r; x by XM (cg_x_mode): nothing at an
+// even step other than the last, x += a' p' + a p at an odd one (p' and a'
+// of the previous step: the other buffer of the direction pair and the step
+// length history), x += a p at a last even step.  A frame's loads (both
+// components) issue before its stores, which would otherwise hold the next
+// component's loads back.  At it = 0 a CG that stops before its first step
+// sets x = 0; a breakdown at an odd step adds the previous step's term.
+// FIRST with ev_part: the step also forms the start scalars of the
+// Gauss-Newton iteration from the evaluation's five partials (J = D + S +
+// P, r.z, r.r; the log's J) and takes their decisions: r.z = 0 ends the CG
+// with x = 0, and a start at or below the objective target takes no step.
+template <int D, bool FIRST, bool PRE, int XM>
+__device__ __forceinline__ void cgv_update_body(
+    int it, const float* __restrict__ p, const float* __restrict__ p_prev,
+    const float* __restrict__ q, const float* __restrict__ dW, const Geom& g,
+    const Model& md, float* __restrict__ x, float* __restrict__ r,
+    float* __restrict__ z, double* __restrict__ Sz, float* __restrict__ Vz,
+    const double* __restrict__ hv_part, int hv_nb, double* __restrict__ part,
+    Scal* __restrict__ sc, int gn_it, const double* __restrict__ ev_part,
+    int ev_nb, GNLog* __restrict__ log, Blk blk) {
+  static_assert(!FIRST || XM == kXNone || XM == kXOne, "x mode");
+  constexpr bool kP = XM != kXNone;                    // reads p
+  constexpr bool kPP = XM == kXTwo || XM == kXTwoFirst; // reads p'
+  constexpr bool kXR = (XM == kXOne && !FIRST) || XM == kXTwo;  // reads x
+  const int stop = sc->gn_stop;
+  int done = sc->done;
+  double rz_it = sc->rzh[it & 1];
+  const double a_prev = (!FIRST && (it & 1)) ? sc->ah[(it - 1) & 1] : 0.0;
+  int j0, j1;
+  wave_frames(md.nK, j0, j1);
+  const int lane = threadIdx.x & (kWave - 1);
+  const long long N = g.N;
+  const long long ntiles = (N + kWave - 1) / kWave;
+  // one frame's loads and its update (x, r, z stored, sums accumulated)
+  struct Fr {
+    float p[D], pp[D], d[D], x[D], r[D], q[D];
+  };
+  auto load = [&](size_t base, Fr& f) {
+#pragma unroll
+    for (int a = 0; a < D; ++a) {
+      const size_t o = base + (size_t)a * N;
+      f.p[a] = kP ? p[o] : 0.f;
+      f.pp[a] = kPP ? p_prev[o] : 0.f;
+      f.d[a] = dW[o];
+      f.x[a] = kXR ? x[o] : 0.f;
+      f.r[a] = r[o];
+      f.q[a] = q[o];
+    }
+  };
   // PRE (grids of at most one block per compute unit, latency-bound): the
   // first frame of the first tile is requested together with the control
   // scalars and the product's partials (four frames ahead measured slower:
   // the registers they hold cost more than the round trips they save)
-  constexpr int kPreF = 1;
-  float pf0[kPreF][D], df0[kPreF][D], xf0[kPreF][D], rf0[kPreF][D],
-      qf0[kPreF][D];
   const long long tile0 = xcd_tile(ntiles, 0, blk);
   const long long xv0 = tile0 * kWave + lane;
   const bool pre = PRE && tile0 >= 0 && xv0 < N;
-  if (pre) {
-#pragma unroll
-    for (int f = 0; f < kPreF; ++f) {
-      if (j0 + f < j1) {
-        const size_t base = (size_t)(j0 + f) * D * N + (size_t)xv0;
-#pragma unroll
-        for (int a = 0; a < D; ++a) {
-          const size_t o = base + (size_t)a * N;
-          pf0[f][a] = p[o];
-          df0[f][a] = dW[o];
-          xf0[f][a] = FIRST ? 0.f : x[o];
-          rf0[f][a] = r[o];
-          qf0[f][a] = q[o];
-        }
-      }
-    }
-  }
+  Fr f0;
+  if (pre && j0 < j1) load((size_t)j0 * D * N + (size_t)xv0, f0);
   if (gn_it >= stop) return;
   if (FIRST && ev_part) {
     // (the flags other blocks read at their start, done and gn_stop, are
@@ -186,12 +218,15 @@ __device__ __forceinline__ void cgv_update_body(
       sc->done = 2;
     }
     if (FIRST) cg_zero_x<D>(x, g, md, blk);
+    // the previous (even) step left its term to this one
+    else if (it & 1) cg_fold_x<D>(x, p_prev, a_prev, it == 1, g, md, blk);
     return;
   }
   const double alpha = rz_it / pq;
   if (blk.id == 0 && threadIdx.x == 0) {
     sc->pq = pq;
     sc->a = alpha;
+    sc->ah[it & 1] = alpha;
     sc->iters = it + 1;
   }
   double rz = 0.0, rr = 0.0;
@@ -205,37 +240,27 @@ __device__ __forceinline__ void cgv_update_body(
     double s = 0.0, v[D];
 #pragma unroll
     for (int a = 0; a < D; ++a) v[a] = 0.0;
-    // one frame from its loaded values: x, r, z stored, sums accumulated
-    auto frame = [&](size_t base, const float* pf, const float* df,
-                     const float* xf, const float* rf, const float* qf) {
+    auto frame = [&](size_t base, const Fr& f) {
 #pragma unroll
       for (int a = 0; a < D; ++a) {
         size_t o = base + (size_t)a * N;
-        double pe = (double)pf[a];
-        double d = (double)df[a];
-        float xn = FIRST ? (float)(alpha * pe)
-                         : (float)((double)xf[a] + alpha * pe);
-        float rv = (float)((double)rf[a] - alpha * (double)qf[a]);
+        const double d = (double)f.d[a];
+        if (XM == kXOne)
+          x[o] = FIRST ? (float)(alpha * (double)f.p[a])
+                       : (float)((double)f.x[a] + alpha * (double)f.p[a]);
+        else if (XM == kXTwo)
+          x[o] = (float)(((double)f.x[a] + a_prev * (double)f.pp[a]) +
+                         alpha * (double)f.p[a]);
+        else if (XM == kXTwoFirst)
+          x[o] = (float)(a_prev * (double)f.pp[a] + alpha * (double)f.p[a]);
+        float rv = (float)((double)f.r[a] - alpha * (double)f.q[a]);
         float zv = (float)((double)rv / (md.mdiag_c * d * d + rest));
-        x[o] = xn;
         r[o] = rv;
         z[o] = zv;
         rz += (double)rv * (double)zv;
         rr += (double)rv * (double)rv;
         s += d * (double)zv;
         v[a] += (double)zv;
-      }
-    };
-    auto load = [&](size_t base, float* pf, float* df, float* xf, float* rf,
-                    float* qf) {
-#pragma unroll
-      for (int a = 0; a < D; ++a) {
-        const size_t o = base + (size_t)a * N;
-        pf[a] = p[o];
-        df[a] = dW[o];
-        xf[a] = FIRST ? 0.f : x[o];
-        rf[a] = r[o];
-        qf[a] = q[o];
       }
     };
     if (valid && PRE) {
@@ -245,8 +270,7 @@ __device__ __forceinline__ void cgv_update_body(
       // are accumulated in order, as one at a time
       int j = j0;
       if (tt == 0 && j < j1) {
-        frame((size_t)j * D * N + pos.idx, pf0[0], df0[0], xf0[0], rf0[0],
-              qf0[0]);
+        frame((size_t)j * D * N + pos.idx, f0);
         ++j;
       }
 #pragma unroll 1
@@ -254,55 +278,51 @@ __device__ __forceinline__ void cgv_update_body(
         const int jb = j + 1 < j1 ? j + 1 : j;
         const size_t b0 = (size_t)j * D * N + pos.idx;
         const size_t b1 = (size_t)jb * D * N + pos.idx;
-        float pf[2][D], df[2][D], xf[2][D], rf[2][D], qf[2][D];
-        load(b0, pf[0], df[0], xf[0], rf[0], qf[0]);
-        load(b1, pf[1], df[1], xf[1], rf[1], qf[1]);
-        frame(b0, pf[0], df[0], xf[0], rf[0], qf[0]);
-        if (jb != j) frame(b1, pf[1], df[1], xf[1], rf[1], qf[1]);
+        Fr fa, fb;
+        load(b0, fa);
+        load(b1, fb);
+        frame(b0, fa);
+        if (jb != j) frame(b1, fb);
+      }
+    } else if (valid && D == 3) {
+      // volumes on large grids: one component at a time, which keeps the
+      // form limited to 64 registers free of spills (issuing all 15 loads
+      // of a frame first spilled 52 B per lane and streamed 8% slower)
+#pragma unroll 1
+      for (int j = j0; j < j1; ++j) {
+        const size_t base = (size_t)j * D * N + pos.idx;
+#pragma unroll
+        for (int a = 0; a < D; ++a) {
+          const size_t o = base + (size_t)a * N;
+          const float pv = kP ? p[o] : 0.f, ppv = kPP ? p_prev[o] : 0.f,
+                      dv = dW[o], xv2 = kXR ? x[o] : 0.f, rv0 = r[o],
+                      qv = q[o];
+          const double d = (double)dv;
+          if (XM == kXOne)
+            x[o] = FIRST ? (float)(alpha * (double)pv)
+                         : (float)((double)xv2 + alpha * (double)pv);
+          else if (XM == kXTwo)
+            x[o] = (float)(((double)xv2 + a_prev * (double)ppv) +
+                           alpha * (double)pv);
+          else if (XM == kXTwoFirst)
+            x[o] = (float)(a_prev * (double)ppv + alpha * (double)pv);
+          float rv = (float)((double)rv0 - alpha * (double)qv);
+          float zv = (float)((double)rv / (md.mdiag_c * d * d + rest));
+          r[o] = rv;
+          z[o] = zv;
+          rz += (double)rv * (double)zv;
+          rr += (double)rv * (double)rv;
+          s += d * (double)zv;
+          v[a] += (double)zv;
+        }
       }
     } else if (valid) {
 #pragma unroll 1
       for (int j = j0; j < j1; ++j) {
         const size_t base = (size_t)j * D * N + pos.idx;
-        float pf[D], df[D], xf[D], rf[D], qf[D];
-        if (PRE && tt == 0 && j - j0 < kPreF) {
-          const int f = j - j0;
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            pf[a] = pf0[f][a];
-            df[a] = df0[f][a];
-            xf[a] = xf0[f][a];
-            rf[a] = rf0[f][a];
-            qf[a] = qf0[f][a];
-          }
-        } else if (D == 3 && !PRE) {
-          // volumes: one component at a time, which keeps the form limited
-          // to 64 registers free of spills (issuing all 15 loads of a frame
-          // first spilled 52 B per lane and streamed 8% slower)
-#pragma unroll
-          for (int a = 0; a < D; ++a) {
-            const size_t o = base + (size_t)a * N;
-            const float pv = p[o], dv = dW[o], xv = FIRST ? 0.f : x[o],
-                        rv0 = r[o], qv = q[o];
-            double pe = (double)pv;
-            double d = (double)dv;
-            float xn = FIRST ? (float)(alpha * pe)
-                             : (float)((double)xv + alpha * pe);
-            float rv = (float)((double)rv0 - alpha * (double)qv);
-            float zv = (float)((double)rv / (md.mdiag_c * d * d + rest));
-            x[o] = xn;
-            r[o] = rv;
-            z[o] = zv;
-            rz += (double)rv * (double)zv;
-            rr += (double)rv * (double)rv;
-            s += d * (double)zv;
-            v[a] += (double)zv;
-          }
-          continue;
-        } else {
-          load(base, pf, df, xf, rf, qf);
-        }
-        frame(base, pf, df, xf, rf, qf);
+        Fr f;
+        load(base, f);
+        frame(base, f);
       }
     }
     store_voxel_sums<D>(s, v, xv, valid, N, Sz, Vz);
@@ -315,17 +335,18 @@ __device__ __forceinline__ void cgv_update_body(
 // while one block combines its per-voxel sums the other streams; for grids
 // with more blocks than compute units.  Small grids (latency-bound levels)
 // run faster with the registers unconstrained.  Same arithmetic either way.
-template <int D, bool OCC, bool FIRST>
+template <int D, bool OCC, bool FIRST, int XM>
 __global__ __launch_bounds__(1024, OCC ? 8 : 1) void cgv_update_kernel(
-    int it, const float* __restrict__ p, const float* __restrict__ q,
-    const float* __restrict__ dW, Geom g, Model md, float* __restrict__ x,
-    float* __restrict__ r, float* __restrict__ z, double* __restrict__ Sz,
-    float* __restrict__ Vz, const double* __restrict__ hv_part, int hv_nb,
-    double* __restrict__ part, Scal* __restrict__ sc, int gn_it,
-    const double* __restrict__ ev_part, int ev_nb, GNLog* __restrict__ log) {
-  cgv_update_body<D, FIRST, !OCC>(it, p, q, dW, g, md, x, r, z, Sz, Vz,
-                                  hv_part, hv_nb, part, sc, gn_it, ev_part,
-                                  ev_nb, log, grid_blk());
+    int it, const float* __restrict__ p, const float* __restrict__ p_prev,
+    const float* __restrict__ q, const float* __restrict__ dW, Geom g,
+    Model md, float* __restrict__ x, float* __restrict__ r,
+    float* __restrict__ z, double* __restrict__ Sz, float* __restrict__ Vz,
+    const double* __restrict__ hv_part, int hv_nb, double* __restrict__ part,
+    Scal* __restrict__ sc, int gn_it, const double* __restrict__ ev_part,
+    int ev_nb, GNLog* __restrict__ log) {
+  cgv_update_body<D, FIRST, !OCC, XM>(it, p, p_prev, q, dW, g, md, x, r, z,
+                                      Sz, Vz, hv_part, hv_nb, part, sc, gn_it,
+                                      ev_part, ev_nb, log, grid_blk());
 }
 
 // Per-voxel S and V of a stored field v (Hessian product test entry).
@@ -370,7 +391,8 @@ template <int REG, bool FIRST>
 __device__ __forceinline__ void cgt_hvp2_body(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, const Geom& g,
-    const Model& md, float* __restrict__ q, const double* __restrict__ Sz,
+    const Model& md, float* __restrict__ q, float* __restrict__ x,
+    const double* __restrict__ Sz,
     const float* __restrict__ Vz, const double* __restrict__ Sp_old,
     const float* __restrict__ Vp_old, double* __restrict__ Sp_new,
     float* __restrict__ Vp_new, int nreal, int nfg, int fpg,
@@ -450,6 +472,17 @@ __device__ __forceinline__ void cgt_hvp2_body(
     bool conv = (!fixed && sqrt(t[1]) <= rtol * r0) || t[0] == 0.0;
     if (conv) {
       if (blk.id == 0 && threadIdx.x == 0) sc->done = 1;
+      // converged after an even step: its term of x is still pending
+      if ((it & 1) && valid) {
+        const double a_prev = sc->ah[(it - 1) & 1];
+        for (int j = jbeg; j < jend; ++j)
+#pragma unroll
+          for (int a = 0; a < D; ++a) {
+            const size_t o = ((size_t)j * D + a) * N + vox;
+            x[o] = (float)((it == 1 ? 0.0 : (double)x[o]) +
+                           a_prev * (double)p_old[o]);
+          }
+      }
       return;
     }
     beta = t[0] / rz_old;
@@ -559,15 +592,17 @@ template <int REG, bool FIRST>
 __global__ __launch_bounds__(kHv2Threads, REG ? 7 : 5) void cgt_hvp2_kernel(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
-    Model md, float* __restrict__ q, const double* __restrict__ Sz,
+    Model md, float* __restrict__ q, float* __restrict__ x,
+    const double* __restrict__ Sz,
     const float* __restrict__ Vz, const double* __restrict__ Sp_old,
     const float* __restrict__ Vp_old, double* __restrict__ Sp_new,
     float* __restrict__ Vp_new, int nreal, int nfg, int fpg,
     const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
     double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
-  cgt_hvp2_body<REG, FIRST>(it, zv, p_old, p_new, dW, g, md, q, Sz, Vz, Sp_old,
-                     Vp_old, Sp_new, Vp_new, nreal, nfg, fpg, up_part, up_nb,
-                     fixed, rtol, part, sc, gn_it, grid_blk());
+  cgt_hvp2_body<REG, FIRST>(it, zv, p_old, p_new, dW, g, md, q, x, Sz, Vz,
+                            Sp_old, Vp_old, Sp_new, Vp_new, nreal, nfg, fpg,
+                            up_part, up_nb, fixed, rtol, part, sc, gn_it,
+                            grid_blk());
 }
 
 // CG step, part 0 for volumes (it > 0): beta = r.z / r.z_old from the
@@ -634,7 +669,8 @@ template <int REG, bool FIRST>
 __device__ __forceinline__ void cgt_hvp3_body(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, const Geom& g,
-    const Model& md, float* __restrict__ q, const double* __restrict__ Sz,
+    const Model& md, float* __restrict__ q, float* __restrict__ x,
+    const double* __restrict__ Sz,
     const float* __restrict__ Vz, const double* __restrict__ Sp_old,
     const float* __restrict__ Vp_old, double* __restrict__ Sp_new,
     float* __restrict__ Vp_new, int nreal, int nfg, int fpg,
@@ -656,15 +692,44 @@ __device__ __forceinline__ void cgt_hvp3_body(
   (void)Vp_old;
   // at CG step 0 the done flag is the previous iteration's (the update of
   // this step forms the new one)
-  if ((!FIRST && sc->done) || gn_it >= sc->gn_stop) return;
+  if (gn_it >= sc->gn_stop) return;
+  const int per_xcd = blk.n / kXCD;
+  const int bb = (blk.id % kXCD) * per_xcd + blk.id / kXCD;
+  if (!FIRST && sc->done) {
+    // converged at this step (the sums kernel found it) after an even step:
+    // that step's term of x is still pending
+    if ((it & 1) && sc->iters == it && bb < nreal) {
+      const double a_prev = sc->ah[(it - 1) & 1];
+      const int m0 = g.m[0], m1 = g.m[1], m2 = g.m[2];
+      const long long N = g.N;
+      const long long plane_n = (long long)m1 * m2;
+      const int tile = bb / nfg, fg = bb - (bb / nfg) * nfg;
+      const int ntx = (m2 + kT3X - 1) / kT3X, nty = (m1 + kT3Y - 1) / kT3Y;
+      const int xx = (tile % ntx) * kT3X + (int)threadIdx.x % kT3X;
+      const int yy = ((tile / ntx) % nty) * kT3Y + (int)threadIdx.x / kT3X;
+      const int z0 = (tile / ntx / nty) * kT3Z;
+      const int z1 = z0 + kT3Z < m0 ? z0 + kT3Z : m0;
+      const int jbeg = fg * fpg;
+      const int jend = jbeg + fpg < md.nK ? jbeg + fpg : md.nK;
+      if (xx < m2 && yy < m1)
+        for (int j = jbeg; j < jend; ++j)
+          for (int zz = z0; zz < z1; ++zz)
+#pragma unroll
+            for (int a = 0; a < D; ++a) {
+              const size_t o = ((size_t)j * D + a) * N +
+                               (size_t)zz * plane_n + (size_t)(yy * m2 + xx);
+              x[o] = (float)((it == 1 ? 0.0 : (double)x[o]) +
+                             a_prev * (double)p_old[o]);
+            }
+    }
+    return;
+  }
   // it > 0: beta and the sums of p come from cg_psums_kernel (launched just
   // before); it = 0: p = z, whose sums this kernel keeps for the next step
   const double beta = FIRST ? 0.0 : sc->beta;
   const double* Sc = FIRST ? Sz : Sp_new;
   const float* Vc = FIRST ? Vz : Vp_new;
   const float bf = (float)beta;
-  const int per_xcd = blk.n / kXCD;
-  const int bb = (blk.id % kXCD) * per_xcd + blk.id / kXCD;
   double acc = 0.0;
   if (bb < nreal) {
     const int m0 = g.m[0], m1 = g.m[1], m2 = g.m[2];
@@ -841,15 +906,17 @@ template <int REG, bool FIRST>
 __global__ __launch_bounds__(kHv3Threads, 4) void cgt_hvp3_kernel(
     int it, const float* __restrict__ zv, const float* __restrict__ p_old,
     float* __restrict__ p_new, const float* __restrict__ dW, Geom g,
-    Model md, float* __restrict__ q, const double* __restrict__ Sz,
+    Model md, float* __restrict__ q, float* __restrict__ x,
+    const double* __restrict__ Sz,
     const float* __restrict__ Vz, const double* __restrict__ Sp_old,
     const float* __restrict__ Vp_old, double* __restrict__ Sp_new,
     float* __restrict__ Vp_new, int nreal, int nfg, int fpg,
     const double* __restrict__ up_part, int up_nb, int fixed, double rtol,
     double* __restrict__ part, Scal* __restrict__ sc, int gn_it) {
-  cgt_hvp3_body<REG, FIRST>(it, zv, p_old, p_new, dW, g, md, q, Sz, Vz, Sp_old,
-                     Vp_old, Sp_new, Vp_new, nreal, nfg, fpg, up_part, up_nb,
-                     fixed, rtol, part, sc, gn_it, grid_blk());
+  cgt_hvp3_body<REG, FIRST>(it, zv, p_old, p_new, dW, g, md, q, x, Sz, Vz,
+                            Sp_old, Vp_old, Sp_new, Vp_new, nreal, nfg, fpg,
+                            up_part, up_nb, fixed, rtol, part, sc, gn_it,
+                            grid_blk());
 }
 
 // ------------------------------------------------------------ launchers
@@ -891,7 +958,8 @@ CgTiles cg_tiles(const Geom& g, int nK, int dim) {
 
 hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
                           float* p_new, const float* dW, const Geom& g,
-                          const Model& md, float* q, CgSums sums, int fixed,
+                          const Model& md, float* q, float* x, CgSums sums,
+                          int fixed,
                           double rtol, RedBuf rb, Scal* sc, hipStream_t s,
                           int gn_it, hipEvent_t ev0, hipEvent_t ev1) {
   const int dim = geom_dim(g);
@@ -925,34 +993,46 @@ hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
   }
   hipExtLaunchKernelGGL(kern, dim3(t.grid),
                         dim3(dim == 2 ? kHv2Threads : kHv3Threads), 0, s, ev0,
-                        ev1, 0, it, z, p_old, p_new, dW, g, md, q, sums.Sz,
+                        ev1, 0, it, z, p_old, p_new, dW, g, md, q, x, sums.Sz,
                         sums.Vz, Sp_old, Vp_old, Sp_new, Vp_new, t.nreal,
                         t.nfg, t.fpg, (const double*)rb.region(kRegUpdate),
                         t.vox_grid, fixed, rtol, rb.region(kRegHv), sc, gn_it);
   return hipGetLastError();
 }
 
-hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
+// The update's forms: (dimension, two blocks per compute unit, CG step 0,
+// x mode).
+#define STML_CGV_FORMS(D, OCC)                                              \
+  {cgv_update_kernel<D, OCC, true, kXNone>,                                 \
+   cgv_update_kernel<D, OCC, true, kXOne>,                                  \
+   cgv_update_kernel<D, OCC, false, kXNone>,                                \
+   cgv_update_kernel<D, OCC, false, kXOne>,                                 \
+   cgv_update_kernel<D, OCC, false, kXTwo>,                                 \
+   cgv_update_kernel<D, OCC, false, kXTwoFirst>}
+
+// index of the form for step it of cg_max: step 0 (x untouched or x = a p),
+// then the four modes of later steps
+static int cgv_form(int it, int cg_max) {
+  const int xm = cg_x_mode(it, cg_max);
+  return it == 0 ? (xm == kXOne ? 1 : 0) : 2 + xm;
+}
+
+hipError_t launch_cgv_update(int dim, int it, int cg_max, const float* p,
+                             const float* p_prev, const float* q,
                              const float* dW, const Geom& g, const Model& md,
                              float* x, float* r, float* z, CgSums sums,
                              RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
                              GNLog* log, hipEvent_t ev0, hipEvent_t ev1) {
   int nb = cgv_blocks(g), nt = cgv_threads(dim, md.nK);
   int hv_nb = cg_tiles(g, md.nK, dim).grid;
-  const bool occ = nb > kCUs, first = it == 0;
-  decltype(&cgv_update_kernel<2, true, true>) kern;
-  if (dim == 2)
-    kern = occ ? (first ? cgv_update_kernel<2, true, true>
-                        : cgv_update_kernel<2, true, false>)
-               : (first ? cgv_update_kernel<2, false, true>
-                        : cgv_update_kernel<2, false, false>);
-  else
-    kern = occ ? (first ? cgv_update_kernel<3, true, true>
-                        : cgv_update_kernel<3, true, false>)
-               : (first ? cgv_update_kernel<3, false, true>
-                        : cgv_update_kernel<3, false, false>);
+  const bool occ = nb > kCUs;
+  using Kern = decltype(&cgv_update_kernel<2, true, true, kXNone>);
+  static const Kern forms[2][2][6] = {
+      {STML_CGV_FORMS(2, false), STML_CGV_FORMS(2, true)},
+      {STML_CGV_FORMS(3, false), STML_CGV_FORMS(3, true)}};
+  const Kern kern = forms[dim == 3][occ][cgv_form(it, cg_max)];
   hipExtLaunchKernelGGL(kern, dim3(nb), dim3(nt), 0, s, ev0, ev1, 0, it, p,
-                        q, dW, g, md, x, r, z, sums.Sz, sums.Vz,
+                        p_prev, q, dW, g, md, x, r, z, sums.Sz, sums.Vz,
                         (const double*)rb.region(kRegHv), hv_nb,
                         rb.region(kRegUpdate), sc, gn_it,
                         (const double*)rb.region(kRegEval), tile_blocks(g),
@@ -994,14 +1074,14 @@ __global__ __launch_bounds__(D == 2 ? kHv2Threads : kHv3Threads,
   float* pn = (it & 1) ? J.P1 : J.P0;
   const float* po = (it & 1) ? J.P0 : J.P1;
   if constexpr (D == 2)
-    cgt_hvp2_body<REG, FIRST>(it, J.z, po, pn, J.dW, g, md, J.q, J.sums.Sz,
+    cgt_hvp2_body<REG, FIRST>(it, J.z, po, pn, J.dW, g, md, J.q, J.x, J.sums.Sz,
                        J.sums.Vz, J.sums.Sp[(it + 1) & 1],
                        J.sums.Vp[(it + 1) & 1], J.sums.Sp[it & 1],
                        J.sums.Vp[it & 1], J.ct.nreal, J.ct.nfg, J.ct.fpg,
                        J.rb.region(kRegUpdate), J.nb_vox, fixed, rtol,
                        J.rb.region(kRegHv), sc, sc->gn_cur, blk);
   else
-    cgt_hvp3_body<REG, FIRST>(it, J.z, po, pn, J.dW, g, md, J.q, J.sums.Sz,
+    cgt_hvp3_body<REG, FIRST>(it, J.z, po, pn, J.dW, g, md, J.q, J.x, J.sums.Sz,
                        J.sums.Vz, J.sums.Sp[(it + 1) & 1],
                        J.sums.Vp[(it + 1) & 1], J.sums.Sp[it & 1],
                        J.sums.Vp[it & 1], J.ct.nreal, J.ct.nfg, J.ct.fpg,
@@ -1021,7 +1101,7 @@ __global__ __launch_bounds__(1024) void cg_psums_batch_kernel(JobSet js, int it,
                 sc->gn_cur, blk);
 }
 
-template <int D, bool FIRST>
+template <int D, bool FIRST, int XM>
 __global__ __launch_bounds__(1024, 8) void cg_update_batch_kernel(JobSet js,
                                                                int it) {
   Blk blk;
@@ -1030,11 +1110,11 @@ __global__ __launch_bounds__(1024, 8) void cg_update_batch_kernel(JobSet js,
   const Model md = J.md;
   Scal* sc = J.sc;
   const float* pn = (it & 1) ? J.P1 : J.P0;
-  cgv_update_body<D, FIRST, false>(it, pn, J.q, J.dW, g, md, J.x, J.r, J.z,
-                            J.sums.Sz, J.sums.Vz, J.rb.region(kRegHv),
-                            J.ct.grid, J.rb.region(kRegUpdate), sc,
-                            sc->gn_cur, J.rb.region(kRegEval), J.nb_tile,
-                            J.log, blk);
+  const float* po = (it & 1) ? J.P0 : J.P1;
+  cgv_update_body<D, FIRST, false, XM>(
+      it, pn, po, J.q, J.dW, g, md, J.x, J.r, J.z, J.sums.Sz, J.sums.Vz,
+      J.rb.region(kRegHv), J.ct.grid, J.rb.region(kRegUpdate), sc,
+      sc->gn_cur, J.rb.region(kRegEval), J.nb_tile, J.log, blk);
 }
 
 template <int D>
@@ -1087,13 +1167,21 @@ hipError_t batch_cg_hvp(const JobSet& js, int nhv, int nvox, int dim, int reg,
   return hipGetLastError();
 }
 
+#define STML_CGV_BATCH_FORMS(D)                                             \
+  {cg_update_batch_kernel<D, true, kXNone>,                                 \
+   cg_update_batch_kernel<D, true, kXOne>,                                  \
+   cg_update_batch_kernel<D, false, kXNone>,                                \
+   cg_update_batch_kernel<D, false, kXOne>,                                 \
+   cg_update_batch_kernel<D, false, kXTwo>,                                 \
+   cg_update_batch_kernel<D, false, kXTwoFirst>}
+
 hipError_t batch_cg_update(const JobSet& js, int nvox, int dim, int it,
-                           hipStream_t s) {
-  auto kern = dim == 2 ? (it == 0 ? cg_update_batch_kernel<2, true>
-                                   : cg_update_batch_kernel<2, false>)
-                       : (it == 0 ? cg_update_batch_kernel<3, true>
-                                   : cg_update_batch_kernel<3, false>);
-  kern<<<nvox, cgv_threads(dim, 0), 0, s>>>(js, it);
+                           int cg_max, hipStream_t s) {
+  using Kern = decltype(&cg_update_batch_kernel<2, true, kXNone>);
+  static const Kern forms[2][6] = {STML_CGV_BATCH_FORMS(2),
+                                   STML_CGV_BATCH_FORMS(3)};
+  forms[dim == 3][cgv_form(it, cg_max)]<<<nvox, cgv_threads(dim, 0), 0, s>>>(
+      js, it);
   return hipGetLastError();
 }
 
@@ -1109,8 +1197,8 @@ hipError_t launch_hessvec_tiled(const float* v, const float* dW,
     cgv_sums_kernel<3><<<nb, nt, 0, s>>>(v, dW, g, md, sums.Sz, sums.Vz);
   hipError_t e = launch_gn_reset(sc, nullptr, 0, s);
   if (e != hipSuccess) return e;
-  e = launch_cgt_hvp(0, v, nullptr, vcopy, dW, g, md, hv, sums, 1, 0.0, rb,
-                     sc, s, 0);
+  e = launch_cgt_hvp(0, v, nullptr, vcopy, dW, g, md, hv, nullptr, sums, 1,
+                     0.0, rb, sc, s, 0);
   if (e != hipSuccess) return e;
   return launch_finalize_vhv(rb.region(kRegHv), cg_tiles(g, md.nK, dim).grid,
                              sc, s);

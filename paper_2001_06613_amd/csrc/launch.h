@@ -137,15 +137,20 @@ struct CgTiles {             // launch shape of the Hessian product
 CgTiles cg_tiles(const Geom& g, int nK, int dim);
 int cg_tile_count(const Geom& g, int dim);
 // ev0/ev1 (optional): timed by the dispatch's own start/end timestamps
+// x: the CG solution, to which a step that finds convergence after an even
+// step adds that step's term (unused at it = 0).
 hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
                           float* p_new, const float* dW, const Geom& g,
-                          const Model& md, float* q, CgSums sums, int fixed,
-                          double rtol, RedBuf rb, Scal* sc, hipStream_t s,
-                          int gn_it, hipEvent_t ev0 = nullptr,
+                          const Model& md, float* q, float* x, CgSums sums,
+                          int fixed, double rtol, RedBuf rb, Scal* sc,
+                          hipStream_t s, int gn_it, hipEvent_t ev0 = nullptr,
                           hipEvent_t ev1 = nullptr);
 // At it = 0 it also forms the Gauss-Newton iteration's start scalars from
-// the evaluation's partials (and writes log[gn_it].J).
-hipError_t launch_cgv_update(int dim, int it, const float* p, const float* q,
+// the evaluation's partials (and writes log[gn_it].J).  p_prev: the
+// direction of step it - 1 (the other buffer of the pair); x is written by
+// cg_x_mode(it, cg_max).
+hipError_t launch_cgv_update(int dim, int it, int cg_max, const float* p,
+                             const float* p_prev, const float* q,
                              const float* dW, const Geom& g, const Model& md,
                              float* x, float* r, float* z, CgSums sums,
                              RedBuf rb, Scal* sc, hipStream_t s, int gn_it,
@@ -210,7 +215,7 @@ hipError_t batch_zero_x(const JobSet& js, int nvox, int dim, hipStream_t s);
 hipError_t batch_cg_hvp(const JobSet& js, int nhv, int nvox, int dim, int reg,
                         int it, int fixed, double rtol, hipStream_t s);
 hipError_t batch_cg_update(const JobSet& js, int nvox, int dim, int it,
-                           hipStream_t s);
+                           int cg_max, hipStream_t s);
 hipError_t batch_trial(const JobSet& js, int ntile, int dim, int reg, int p,
                        int ls_max, double c1, hipStream_t s);
 hipError_t batch_accept(const JobSet& js, int nelem, int ls_max, double c1,

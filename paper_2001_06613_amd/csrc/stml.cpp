@@ -422,13 +422,20 @@ int read_scal(stml_ctx* c) {
 
 // Algorithmic HBM bytes per voxel-frame of each kernel class (float32
 // fields of D components): what the kernel must read and write once.
-double alg_bytes(int kernel, int D, int cg_it) {
+double alg_bytes(int kernel, int D, int cg_it, int cg_max) {
   switch (kernel) {
     case STML_K_EVAL: return 4.0 + 20.0 * D;      // T; u; dW, g, r, z
     case STML_K_HESSVEC:                          // z (+p_old), dW; p, q
       return cg_it > 0 ? 20.0 * D : 16.0 * D;
-    case STML_K_CG_UPDATE:                        // p, q, dW, r (+x); x, r, z
-      return cg_it > 0 ? 32.0 * D : 28.0 * D;
+    case STML_K_CG_UPDATE: {                      // q, dW, r; r, z; x terms
+      // x by cg_x_mode: none; x (+)= a p; x += a' p' + a p; x = a' p' + a p
+      const int xm = cg_x_mode(cg_it, cg_max);
+      const double xb = xm == kXNone  ? 0.0
+                        : xm == kXOne ? (cg_it > 0 ? 12.0 : 8.0)
+                        : xm == kXTwo ? 16.0
+                                      : 12.0;
+      return (20.0 + xb) * D;
+    }
     case STML_K_CG_INIT: return 0.0;              // scalars only
     case STML_K_TRIAL: return 4.0 + 12.0 * D;     // T; u, delta, g
     case STML_K_ACCEPT: return 12.0 * D;          // u, delta; u
@@ -444,13 +451,15 @@ double alg_bytes(int kernel, int D, int cg_it) {
   do {                                                                  \
     hipEvent_t ev0_, ev1_;                                              \
     tdispatch(c, KERNEL, LEVEL, VF,                                     \
-              (VF) * alg_bytes(KERNEL, c->d, CGIT), &ev0_, &ev1_);      \
+              (VF) * alg_bytes(KERNEL, c->d, CGIT, c->o.cg_max), &ev0_, \
+              &ev1_);                                                   \
     HIP_OK(CALL);                                                       \
   } while (0)
 #define TIMED_IT(KERNEL, LEVEL, VF, CGIT, CALL)                        \
   do {                                                                 \
     const bool tr_ =                                                   \
-        tbegin(c, KERNEL, LEVEL, VF, (VF) * alg_bytes(KERNEL, c->d, CGIT)); \
+        tbegin(c, KERNEL, LEVEL, VF,                                    \
+               (VF) * alg_bytes(KERNEL, c->d, CGIT, c->o.cg_max));     \
     hipError_t te_ = (CALL);           \
     if (tr_) tend(c);                  \
     HIP_OK(te_);                       \
@@ -562,11 +571,13 @@ int enqueue_pcg(stml_ctx* c, int level, const Geom& g, const Model& md,
     const float* po = c->P[(it + 1) & 1];
     TIMED_DISPATCH(STML_K_HESSVEC, level, vf, it,
                    launch_cgt_hvp(it, c->z, po, pn, c->dW, g, md, c->q,
-                                  c->sums, c->o.parity_mode, c->o.cg_rtol,
+                                  c->x, c->sums, c->o.parity_mode,
+                                  c->o.cg_rtol,
                                   c->rb, c->sc, c->stream, gn_it, ev0_,
                                   ev1_));
     TIMED_DISPATCH(STML_K_CG_UPDATE, level, vf, it,
-                   launch_cgv_update(D, it, pn, c->q, c->dW, g, md, c->x,
+                   launch_cgv_update(D, it, c->o.cg_max, pn, po, c->q,
+                                     c->dW, g, md, c->x,
                                      c->r, c->z, c->sums, c->rb, c->sc,
                                      c->stream, gn_it, c->gnlog, ev0_,
                                      ev1_));
@@ -1614,7 +1625,8 @@ hipError_t batch_iteration(const JobSet& js, const int* tot, int dim,
   for (int it = 0; e == hipSuccess && it < o.cg_max; ++it) {
     e = batch_cg_hvp(js, tot[kClsHv], tot[kClsVox], dim, reg, it,
                      o.parity_mode, o.cg_rtol, s);
-    if (e == hipSuccess) e = batch_cg_update(js, tot[kClsVox], dim, it, s);
+    if (e == hipSuccess)
+      e = batch_cg_update(js, tot[kClsVox], dim, it, o.cg_max, s);
   }
   const int sweeps = sweep_count(o.ls_max);
   for (int p = 0; e == hipSuccess && p < sweeps; ++p)

@@ -66,6 +66,7 @@ struct Scal {
   int gn_stop;                // Gauss-Newton iterations >= gn_stop do nothing
   int gn_cur;                 // iteration of batched (graph) launches
   double J_target;            // stop once J <= J_target (-inf: no target)
+  double ah[2];               // CG step length of iteration it in slot it & 1
 };
 
 // One Gauss-Newton iteration as decided on the device.
@@ -82,6 +83,24 @@ struct GNLog {
   int next_pass;              // last line-search sweep that ran
   int pad;
 };
+
+// Terms of the CG solution x = sum_i a_i p_i that the update of CG step it
+// (of cg_max) writes.  An even step other than the last leaves x alone; the
+// odd step after it adds both steps' terms, p of the previous step being
+// still in the other buffer of the direction pair, so x is read and written
+// every second step only; the last step completes x.  A CG that stops after
+// an even step (convergence found by the next step's first kernel, or a
+// breakdown at the next update) has that kernel add the pending term.
+enum CgXMode {
+  kXNone = 0,      // x untouched
+  kXOne = 1,       // x += a p (x = a p at step 0)
+  kXTwo = 2,       // x += a' p' + a p
+  kXTwoFirst = 3,  // x = a' p' + a p (step 1)
+};
+__host__ __device__ inline int cg_x_mode(int it, int cg_max) {
+  if (it & 1) return it == 1 ? kXTwoFirst : kXTwo;
+  return it == cg_max - 1 ? kXOne : kXNone;
+}
 
 // Armijo schedule of one Gauss-Newton iteration, t = 2^-e for e = 0, 1,
 // ..., ls_max, in sweeps: sweep 0 evaluates t = 0 (the reference value,

@@ -37,8 +37,11 @@ def _small():
 
 
 @pytest.mark.parametrize("reg,cg", [("diffusion", 10), ("curvature", 10),
-                                    ("curvature", 1)])
+                                    ("curvature", 1), ("curvature", 2),
+                                    ("diffusion", 5)])
 def test_gn_direction_parity(reg, cg):
+    # x is written every second CG step: cg = 1 and 5 end on a step that
+    # completes x alone, 2 and 10 on one that adds two steps' terms
     frames = _small()
     n, ext = 8, frames.shape[1:]
     o = default_opts(n_spatial=1, n_temporal=2, reg=reg, cg_max=cg,
@@ -267,33 +270,63 @@ def _volume(n, ext, seed):
     return synth.sinusoid_sequence(n, ext, 1.5, 1, seed)[0]
 
 
-@pytest.mark.parametrize("reg", ["diffusion", "curvature"])
+@pytest.mark.parametrize("reg,cg", [("diffusion", 8), ("curvature", 8),
+                                    ("curvature", 5)])
 @pytest.mark.parametrize("ext", [(10, 12, 18), (37, 20, 70), (5, 37, 128)])
-def test_gn_direction_parity_3d(reg, ext):
+def test_gn_direction_parity_3d(reg, cg, ext):
     # ragged against 32 x 16 x 16 columns; the second spans several columns
     # on every axis (CG steps > 0 take beta and the sums of p from the sums
     # kernel); the third has whole 64-voxel z-line tiles, which the
     # evaluation takes in bands of 16 y-lines (the last band ragged)
     n = 4
     frames = _volume(n, ext, 21)
-    o = default_opts(dim=3, n_spatial=1, n_temporal=2, reg=reg, cg_max=8,
+    o = default_opts(dim=3, n_spatial=1, n_temporal=2, reg=reg, cg_max=cg,
                      parity_mode=True)
     st = STML(n, ext, opts=o)
     st.set_sequence(torch.from_numpy(frames).cuda())
     u = synth.random_displacement(ext, n, 1.2, 4)
     K = [0, 1, 3]
-    print(f"gn_direction 3d {reg} {ext}", flush=True)
+    print(f"gn_direction 3d {reg} cg={cg} {ext}", flush=True)
     delta, iters = st.gn_direction(0, K, torch.from_numpy(u))
     par = oracle.ModelParams(reg=reg)
     ref = oracle.objective(frames, u, K, 1.0, par)
     diag = oracle.jacobi_diag(ref["dW"], 1.0, par)
     d_ref, it_ref, _ = oracle.pcg(
-        lambda v: oracle.hessvec(ref["dW"], v, 1.0, par), diag, -ref["g"], 8,
+        lambda v: oracle.hessvec(ref["dW"], v, 1.0, par), diag, -ref["g"], cg,
         fixed=True)
-    assert iters == it_ref == 8
+    assert iters == it_ref == cg
     d = delta.cpu().numpy()
     assert _rel(d, d_ref) <= 1e-4
     assert np.abs(d - d_ref).max() <= 1e-3
+
+
+@pytest.mark.parametrize("reg", ["diffusion", "curvature"])
+def test_register_level_convergence_stop_3d(reg):
+    """Volumes outside parity mode: CG stops at cg_rtol after odd and even
+    steps (after an even one the first kernel of the next step, which finds
+    the convergence, completes x), Gauss-Newton at tol_J / tol_u; counts,
+    steps and result match the oracle."""
+    ext = (10, 12, 18)
+    n = 4
+    frames = _volume(n, ext, 25)
+    kw = dict(dim=3, n_spatial=1, n_temporal=2, reg=reg, gn_max=20,
+              cg_max=20, tol_J=1e-3, tol_u=2e-2, parity_mode=False)
+    st = STML(n, ext, opts=default_opts(**kw))
+    st.set_sequence(torch.from_numpy(frames).cuda())
+    st.predict(0, 0)
+    st.register_level(0, 0)
+    ost = oracle.stml.STMLState(frames, oracle.STMLOptions(
+        **{k: v for k, v in kw.items() if k != "dim"}))
+    ost.predict(0, 0)
+    ost.register_level(0, 0)
+    lg, olg = st.logs()[0], ost.log[0]
+    print("3d gn", lg["gn"], olg["gn"], "cg", lg["cg"], olg["cg"], flush=True)
+    assert lg["gn"] == olg["gn"]
+    assert lg["cg"] == olg["cg"]
+    assert lg["steps"] == olg["steps"]
+    assert lg["J"] == pytest.approx(olg["J"], rel=1e-5)
+    u = st.get_displacements(0).cpu().numpy()
+    assert np.abs(u - ost.Y[0]).max() <= 1e-3
 
 
 @pytest.mark.parametrize("reg", ["diffusion", "curvature"])
