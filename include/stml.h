@@ -313,7 +313,7 @@ const char* stml_noalloc_last_error(void);
 #define STML_K_EVAL        0  /* warp + distance + gradient                 */
 #define STML_K_HESSVEC     1  /* Gauss-Newton Hessian product (CG and test;
                                  volumes: with the direction's voxel sums) */
-#define STML_K_CG_UPDATE   2  /* x, r, z update and r.z                      */
+#define STML_K_CG_UPDATE   2  /* r, z update, x every second step, r.z       */
 #define STML_K_CG_PUPDATE  3  /* p = z + beta p                              */
 #define STML_K_TRIAL       4  /* objective at the Armijo trial steps         */
 #define STML_K_CG_INIT     5  /* CG start scalars (r, z: by the evaluation)  */
