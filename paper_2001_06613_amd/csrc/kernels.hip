@@ -972,6 +972,42 @@ __global__ __launch_bounds__(64) void ls_predict_kernel(
   }
 }
 
+// The same sweep for a sequence of exactly NF frames with d' in registers
+// (fully unrolled): the LDS form holds n doubles per system and so admits
+// few waves per compute unit; this one is limited by registers only.  Same
+// arithmetic in the same order.
+template <int NF>
+__global__ __launch_bounds__(64) void ls_predict_reg_kernel(
+    float* __restrict__ Y, float* __restrict__ Z, ThomasTab tab, int dim,
+    long long N, double beta) {
+  const size_t per = (size_t)dim * N;
+  const size_t sys = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool valid = sys < per;
+  double dp[NF];
+  double prev = 0.0;
+#pragma unroll
+  for (int k = 0; k < NF; ++k) {
+    double rhs = 0.0;
+    if (valid && tab.mask[k]) {
+      size_t o = (size_t)k * per + sys;
+      rhs = (double)Y[o] - (double)Z[o];
+    }
+    prev = (rhs + beta * prev) * tab.invp[k];
+    dp[k] = prev;
+  }
+  double xi = 0.0;
+#pragma unroll
+  for (int k = NF - 1; k >= 0; --k) {
+    xi = (k == NF - 1) ? dp[k] : dp[k] - tab.cp[k] * xi;
+    if (valid) {
+      size_t o = (size_t)k * per + sys;
+      float zv = (float)((double)Z[o] + xi);
+      Z[o] = zv;
+      Y[o] = zv;
+    }
+  }
+}
+
 // ------------------------------------------------------ batched iteration
 
 // Problem of block b: the j with first[j] <= b < first[j + 1].
@@ -1183,8 +1219,17 @@ hipError_t launch_linear_predict(const float* Y, float* Z, float* Yout,
 hipError_t launch_ls_predict(float* Y, float* Z, ThomasTab tab, int n,
                              int dim, long long N, double beta,
                              hipStream_t s) {
-  // d' of every system stays in LDS: n * B doubles <= 64 KiB.
   size_t systems = (size_t)dim * N;
+  if (n == 64 || n == 32) {
+    // d' in registers (the frame counts of the image and volume workloads)
+    const int nb = (int)((systems + 63) / 64);
+    if (n == 64)
+      ls_predict_reg_kernel<64><<<nb, 64, 0, s>>>(Y, Z, tab, dim, N, beta);
+    else
+      ls_predict_reg_kernel<32><<<nb, 64, 0, s>>>(Y, Z, tab, dim, N, beta);
+    return hipGetLastError();
+  }
+  // d' of every system stays in LDS: n * B doubles <= 64 KiB.
   int B = n <= 128 ? 64 : 32;
   int nb = (int)((systems + B - 1) / B);
   size_t lds = (size_t)n * B * sizeof(double);

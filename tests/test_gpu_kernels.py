@@ -184,8 +184,9 @@ def test_linear_predictor_parity(n):
                                    rtol=1e-6, atol=1e-6)
 
 
-@pytest.mark.parametrize("n,beta", [(9, 1e-5), (17, 0.5), (64, 1e-5),
-                                    (129, 1e-5), (200, 3.0)])
+# 32 and 64 frames take the form with the sweep's pivots in registers
+@pytest.mark.parametrize("n,beta", [(9, 1e-5), (17, 0.5), (32, 0.5),
+                                    (64, 1e-5), (129, 1e-5), (200, 3.0)])
 def test_ls_predictor_parity(n, beta):
     ext = (11, 19)
     o = default_opts(dim=2, n_spatial=2, n_temporal=3, beta=beta)
