@@ -272,6 +272,13 @@ int stml_hessvec(stml_ctx* ctx, int level, const int* frames, int nk,
  * (delta = last iterate). */
 int stml_gn_direction(stml_ctx* ctx, int level, const int* frames, int nk,
                       const float* u_dev, float* delta_dev, int* out_cg);
+/* Test of the CG breakdown branch (p.Hp <= 0 never occurs with valid
+ * options, Sec. 2's Gauss-Newton matrix being SPD): from now on CG step it
+ * of every Gauss-Newton iteration of this context (single runs, not
+ * batches) stops as if p.Hp <= 0, keeping the iterate of the steps before
+ * it (x = 0 at it = 0) and reporting STML_EBREAKDOWN where a breakdown is
+ * reported.  it = -1 turns this off.  EINVAL for it < -1. */
+int stml_force_cg_breakdown(stml_ctx* ctx, int it);
 
 /* --- evaluation without allocation --------------------------------------
  * For callers that cannot allocate device memory (code under HIP graph

@@ -115,6 +115,7 @@ SIGNATURES = {
     "stml_eval": (_I, [_P, _I, _IP, _I, _P, _DP, _P, _P]),
     "stml_hessvec": (_I, [_P, _I, _IP, _I, _P, _P, _P, _DP]),
     "stml_gn_direction": (_I, [_P, _I, _IP, _I, _P, _P, _IP]),
+    "stml_force_cg_breakdown": (_I, [_P, _I]),
     "stml_net_param_count": (_I, [_I]),
     "stml_net_workspace_bytes": (ctypes.c_size_t, [_I, _I, _IP]),
     "stml_net_create": (_I, [_I, _I, _IP, _P, _P, ctypes.c_size_t,
@@ -534,16 +535,24 @@ class STML:
                                           ctypes.byref(vhv)))
         return hv, vhv.value
 
-    def gn_direction(self, level, frames, u):
+    def gn_direction(self, level, frames, u, allow_breakdown=False):
+        """(delta, CG iterations); with allow_breakdown a CG breakdown
+        returns (delta, iterations, STML_EBREAKDOWN) instead of raising."""
         u = self._dev(u, (self.n, self.dim) + self.level_extent(level))
         delta = self._field(level, len(frames))
         cg = ctypes.c_int()
         self._sync_in()
-        self._check(self.lib.stml_gn_direction(self.ctx, level,
-                                               _int_array(frames), len(frames),
-                                               _ptr(u), _ptr(delta),
-                                               ctypes.byref(cg)))
-        return delta, cg.value
+        rc = self.lib.stml_gn_direction(self.ctx, level, _int_array(frames),
+                                        len(frames), _ptr(u), _ptr(delta),
+                                        ctypes.byref(cg))
+        if allow_breakdown and rc == STML_EBREAKDOWN:
+            return delta, cg.value, rc
+        self._check(rc)
+        return (delta, cg.value, rc) if allow_breakdown else (delta, cg.value)
+
+    def force_cg_breakdown(self, it):
+        """Make CG step it break down as if p.Hp <= 0 (-1: off)."""
+        self._check(self.lib.stml_force_cg_breakdown(self.ctx, it))
 
 
 class Batch:

@@ -138,7 +138,7 @@ __device__ __forceinline__ void cgv_update_body(
     float* __restrict__ z, double* __restrict__ Sz, float* __restrict__ Vz,
     const double* __restrict__ hv_part, int hv_nb, double* __restrict__ part,
     Scal* __restrict__ sc, int gn_it, const double* __restrict__ ev_part,
-    int ev_nb, GNLog* __restrict__ log, Blk blk) {
+    int ev_nb, GNLog* __restrict__ log, int brk, Blk blk) {
   static_assert(!FIRST || XM == kXNone || XM == kXOne, "x mode");
   constexpr bool kP = XM != kXNone;                    // reads p
   constexpr bool kPP = XM == kXTwo || XM == kXTwoFirst; // reads p'
@@ -212,7 +212,9 @@ __device__ __forceinline__ void cgv_update_body(
   double t[1];
   reduce_partials<1>(hv_part, hv_nb, 0u, t);
   const double pq = t[0];
-  if (!(pq > 0.0)) {
+  // (brk: this step breaks down as if p.Hp <= 0, a host-forced test of the
+  // branch; -1 otherwise)
+  if (!(pq > 0.0) || it == brk) {
     if (blk.id == 0 && threadIdx.x == 0) {
       sc->pq = pq;
       sc->done = 2;
@@ -343,10 +345,10 @@ __global__ __launch_bounds__(1024, OCC ? 8 : 1) void cgv_update_kernel(
     float* __restrict__ z, double* __restrict__ Sz, float* __restrict__ Vz,
     const double* __restrict__ hv_part, int hv_nb, double* __restrict__ part,
     Scal* __restrict__ sc, int gn_it, const double* __restrict__ ev_part,
-    int ev_nb, GNLog* __restrict__ log) {
+    int ev_nb, GNLog* __restrict__ log, int brk) {
   cgv_update_body<D, FIRST, !OCC, XM>(it, p, p_prev, q, dW, g, md, x, r, z,
                                       Sz, Vz, hv_part, hv_nb, part, sc, gn_it,
-                                      ev_part, ev_nb, log, grid_blk());
+                                      ev_part, ev_nb, log, brk, grid_blk());
 }
 
 // Per-voxel S and V of a stored field v (Hessian product test entry).
@@ -1017,7 +1019,8 @@ static int cgv_form(int it, int cg_max) {
   return it == 0 ? (xm == kXOne ? 1 : 0) : 2 + xm;
 }
 
-hipError_t launch_cgv_update(int dim, int it, int cg_max, const float* p,
+hipError_t launch_cgv_update(int dim, int it, int cg_max, int brk,
+                             const float* p,
                              const float* p_prev, const float* q,
                              const float* dW, const Geom& g, const Model& md,
                              float* x, float* r, float* z, CgSums sums,
@@ -1036,7 +1039,7 @@ hipError_t launch_cgv_update(int dim, int it, int cg_max, const float* p,
                         (const double*)rb.region(kRegHv), hv_nb,
                         rb.region(kRegUpdate), sc, gn_it,
                         (const double*)rb.region(kRegEval), tile_blocks(g),
-                        log);
+                        log, brk);
   return hipGetLastError();
 }
 
@@ -1114,7 +1117,7 @@ __global__ __launch_bounds__(1024, 8) void cg_update_batch_kernel(JobSet js,
   cgv_update_body<D, FIRST, false, XM>(
       it, pn, po, J.q, J.dW, g, md, J.x, J.r, J.z, J.sums.Sz, J.sums.Vz,
       J.rb.region(kRegHv), J.ct.grid, J.rb.region(kRegUpdate), sc,
-      sc->gn_cur, J.rb.region(kRegEval), J.nb_tile, J.log, blk);
+      sc->gn_cur, J.rb.region(kRegEval), J.nb_tile, J.log, -1, blk);
 }
 
 template <int D>

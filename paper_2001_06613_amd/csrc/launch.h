@@ -148,8 +148,10 @@ hipError_t launch_cgt_hvp(int it, const float* z, const float* p_old,
 // At it = 0 it also forms the Gauss-Newton iteration's start scalars from
 // the evaluation's partials (and writes log[gn_it].J).  p_prev: the
 // direction of step it - 1 (the other buffer of the pair); x is written by
-// cg_x_mode(it, cg_max).
-hipError_t launch_cgv_update(int dim, int it, int cg_max, const float* p,
+// cg_x_mode(it, cg_max).  brk: a step that takes the breakdown branch as if
+// p.Hp <= 0 (-1: none).
+hipError_t launch_cgv_update(int dim, int it, int cg_max, int brk,
+                             const float* p,
                              const float* p_prev, const float* q,
                              const float* dW, const Geom& g, const Model& md,
                              float* x, float* r, float* z, CgSums sums,

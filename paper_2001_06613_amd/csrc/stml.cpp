@@ -66,6 +66,7 @@ struct stml_ctx {
   float *g = nullptr, *dW = nullptr, *x = nullptr, *r = nullptr,
         *z = nullptr, *q = nullptr;
   float* P[2] = {nullptr, nullptr};      // CG directions, ping-pong
+  int cg_break = -1;                     // CG step forced to break down
   CgSums sums{};                         // per-voxel cross-frame sums
   RedBuf rb{};
   Scal* sc = nullptr;
@@ -576,8 +577,8 @@ int enqueue_pcg(stml_ctx* c, int level, const Geom& g, const Model& md,
                                   c->rb, c->sc, c->stream, gn_it, ev0_,
                                   ev1_));
     TIMED_DISPATCH(STML_K_CG_UPDATE, level, vf, it,
-                   launch_cgv_update(D, it, c->o.cg_max, pn, po, c->q,
-                                     c->dW, g, md, c->x,
+                   launch_cgv_update(D, it, c->o.cg_max, c->cg_break, pn, po,
+                                     c->q, c->dW, g, md, c->x,
                                      c->r, c->z, c->sums, c->rb, c->sc,
                                      c->stream, gn_it, c->gnlog, ev0_,
                                      ev1_));
@@ -1495,6 +1496,12 @@ int stml_gn_direction(stml_ctx* c, int level, const int* frames, int nk,
   if (rc) return rc;
   if (out_cg) *out_cg = c->hsc->iters;
   if (c->hsc->done == 2) return fail(c, STML_EBREAKDOWN, "CG breakdown");
+  return STML_OK;
+}
+
+int stml_force_cg_breakdown(stml_ctx* c, int it) {
+  if (!c || it < -1) return STML_EINVAL;
+  c->cg_break = it;
   return STML_OK;
 }
 

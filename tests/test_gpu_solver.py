@@ -15,7 +15,7 @@ import torch
 
 import oracle
 from paper_2001_06613_amd import synth
-from paper_2001_06613_amd.binding import STML, default_opts
+from paper_2001_06613_amd.binding import STML, STML_EBREAKDOWN, default_opts
 
 pytestmark = pytest.mark.gpu
 
@@ -298,6 +298,49 @@ def test_gn_direction_parity_3d(reg, cg, ext):
     d = delta.cpu().numpy()
     assert _rel(d, d_ref) <= 1e-4
     assert np.abs(d - d_ref).max() <= 1e-3
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+@pytest.mark.parametrize("brk", [0, 1, 2, 3])
+def test_forced_cg_breakdown(dim, brk):
+    """A CG that breaks down (p.Hp <= 0, forced from the host at step brk)
+    keeps the iterate of the steps before it and reports EBREAKDOWN; a
+    breakdown right after an even step adds that step's pending term of x
+    (brk = 1, 3)."""
+    if dim == 2:
+        frames = _small()
+        n, ext, K = 8, frames.shape[1:], [0, 2, 4, 6, 7]
+        u = synth.random_displacement(ext, n, 1.5, 2)
+    else:
+        n, ext, K = 4, (10, 12, 18), [0, 1, 3]
+        frames = _volume(n, ext, 21)
+        u = synth.random_displacement(ext, n, 1.2, 4)
+    o = default_opts(dim=dim, n_spatial=1, n_temporal=2, reg="curvature",
+                     cg_max=8, parity_mode=True)
+    st = STML(n, ext, opts=o)
+    st.set_sequence(torch.from_numpy(frames).cuda())
+    st.force_cg_breakdown(brk)
+    print(f"forced breakdown {dim}-D at CG step {brk}", flush=True)
+    delta, iters, rc = st.gn_direction(0, K, torch.from_numpy(u),
+                                       allow_breakdown=True)
+    assert rc == STML_EBREAKDOWN
+    assert iters == brk
+    d = delta.cpu().numpy()
+    if brk == 0:
+        assert not np.any(d)
+    else:
+        par = oracle.ModelParams(reg="curvature")
+        ref = oracle.objective(frames, u, K, 1.0, par)
+        diag = oracle.jacobi_diag(ref["dW"], 1.0, par)
+        d_ref, it_ref, _ = oracle.pcg(
+            lambda v: oracle.hessvec(ref["dW"], v, 1.0, par), diag, -ref["g"],
+            brk, fixed=True)
+        assert it_ref == brk
+        assert _rel(d, d_ref) <= 1e-4
+        assert np.abs(d - d_ref).max() <= 1e-3
+    st.force_cg_breakdown(-1)
+    _, iters2 = st.gn_direction(0, K, torch.from_numpy(u))
+    assert iters2 == 8
 
 
 @pytest.mark.parametrize("reg", ["diffusion", "curvature"])
